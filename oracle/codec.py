@@ -1,0 +1,212 @@
+"""End-to-end compression and decompression to the self-describing format (oracle).
+
+The paper's high-level calls compress an array under a tolerance and error
+bound type, and decompress from the buffer alone, whose self-describing
+header carries the version, error bound, topology and coder (Sec. 2.1 and
+Sec. 3, first listing); compression ratio is input bytes over output bytes.
+
+Wire format (little-endian; offsets in bytes):
+
+    0  'MGHP'             magic
+    4  u16 version = 1
+    6  u8  dtype           0 = float32, 1 = float64
+    7  u8  ndim            1..4
+    8  u8  eb              0 = absolute, 1 = relative to max |u|
+    9  u8  alloc           0 = plain, 1 = learned, 2 = count-weighted
+   10  u8  coord_flags     bit d set: dimension d stores its coordinates
+   11  u8  fallback        1 when a learned allocation fell back to plain
+   12  u32 L               number of levels
+   16  u32 dict_size
+   20  u32 chunk_symbols
+   24  f64 tol
+   32  f64 tau_abs
+   40  f64 maxabs          max |u|
+   48  u64 n_symbols
+   56  u64 n_chunks
+   64  u64 n_outliers
+   72  u64 payload_words
+   80  u64 shape[ndim]
+       f64 coords          for each flagged dimension, its n_d coordinates
+       f64 bins[L+1]
+       u8  code_len[dict_size]
+       u32 chunk_bits[n_chunks]
+       u32 chunk_esc[n_chunks]   escape symbols per chunk
+       u32 payload[payload_words]
+       (zero padding to a multiple of 8 bytes)
+       i64 outliers[n_outliers]
+"""
+from __future__ import annotations
+
+import struct
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import alloc as A
+from . import huffman as H
+from . import quant as Q
+from . import transform as X
+from .grid import Hierarchy
+
+MAGIC = b"MGHP"
+VERSION = 1
+ALLOC_PLAIN, ALLOC_LEARNED, ALLOC_COUNT = 0, 1, 2
+
+
+@dataclass
+class Parts:
+    """Everything the compressor computes, for stage-by-stage comparisons."""
+
+    hier: Hierarchy
+    T: type
+    maxabs: float
+    tau_abs: float
+    tau_eff: float
+    bins: list
+    stream: np.ndarray
+    q: np.ndarray
+    symbols: np.ndarray
+    outliers: np.ndarray
+    hist: np.ndarray
+    lengths: np.ndarray
+    codes: np.ndarray
+    chunk_bits: list
+    chunk_esc: list
+    words: list
+
+
+def compress_parts(u, tol, rel=True, coords=None, dict_size=8192, chunk=4096, bins=None,
+                   alloc="plain"):
+    u = np.asarray(u)
+    T = u.dtype.type
+    if T not in (np.float32, np.float64):
+        raise TypeError("float32 or float64 input")
+    if not np.all(np.isfinite(u)):
+        raise ValueError("non-finite input")
+    if not tol > 0:
+        raise ValueError("tolerance must be positive")
+    hier = Hierarchy(u.shape, coords)
+    maxabs = float(np.max(np.abs(u))) if u.size else 0.0
+    tau = A.tau_abs(tol, maxabs, rel)
+    tau_eff = A.tau_effective(tau, maxabs, hier.L, T)
+    if bins is None:
+        bins = A.plain_bins(hier, tau_eff) if alloc == "plain" else A.count_weighted_bins(hier, tau_eff)
+    coarsest, cbars = X.decompose(u, hier, T)
+    stream = Q.to_stream(coarsest, cbars, hier)
+    q = Q.quantize_stream(stream, hier, bins)
+    sym, outl = Q.to_symbols(q, dict_size)
+    hist = H.histogram(sym, dict_size)
+    lengths = H.code_lengths(hist)
+    codes = H.canonical_codes(lengths)
+    cbits, words = H.encode(sym, lengths, codes, chunk)
+    esc = [int(np.count_nonzero(sym[k:k + chunk] == 0)) for k in range(0, len(sym), chunk)]
+    return Parts(hier, T, maxabs, tau, tau_eff, list(map(float, bins)), stream, q, sym, outl, hist,
+                 lengths, codes, cbits, esc, words)
+
+
+def serialize(p: Parts, tol, rel, coords, dict_size, chunk, alloc_code=ALLOC_PLAIN, fallback=0) -> bytes:
+    hier = p.hier
+    D = hier.D
+    flags = 0
+    coord_blob = b""
+    if coords is not None:
+        for d in range(D):
+            if coords[d] is not None:
+                flags |= 1 << d
+                coord_blob += np.asarray(coords[d], dtype="<f8").tobytes()
+    n = len(p.symbols)
+    nch = len(p.chunk_bits)
+    head = struct.pack("<4sHBBBBBBIIIdddQQQQ", MAGIC, VERSION, 0 if p.T is np.float32 else 1, D,
+                       1 if rel else 0, alloc_code, flags, fallback, hier.L, dict_size, chunk,
+                       float(tol), float(p.tau_abs), float(p.maxabs), n, nch, len(p.outliers),
+                       len(p.words))
+    assert len(head) == 80
+    out = [head, np.asarray(hier.shape, dtype="<u8").tobytes(), coord_blob,
+           np.asarray(p.bins, dtype="<f8").tobytes(),
+           np.asarray(p.lengths, dtype=np.uint8).tobytes(),
+           np.asarray(p.chunk_bits, dtype="<u4").tobytes(),
+           np.asarray(p.chunk_esc, dtype="<u4").tobytes(),
+           np.asarray(p.words, dtype="<u4").tobytes()]
+    blob = b"".join(out)
+    blob += b"\0" * ((-len(blob)) % 8)
+    blob += np.asarray(p.outliers, dtype="<i8").tobytes()
+    return blob
+
+
+def compress(u, tol, rel=True, coords=None, dict_size=8192, chunk=4096, bins=None, alloc="plain"):
+    p = compress_parts(u, tol, rel, coords, dict_size, chunk, bins, alloc)
+    code = ALLOC_PLAIN if (alloc == "plain" and bins is None) else (ALLOC_COUNT if alloc == "count" else ALLOC_LEARNED)
+    return serialize(p, tol, rel, coords, dict_size, chunk, code)
+
+
+@dataclass
+class Header:
+    dtype: type
+    ndim: int
+    rel: bool
+    alloc: int
+    fallback: int
+    L: int
+    dict_size: int
+    chunk: int
+    tol: float
+    tau_abs: float
+    maxabs: float
+    n: int
+    n_chunks: int
+    n_outliers: int
+    payload_words: int
+    shape: tuple
+    coords: list
+    bins: list
+    offsets: dict
+
+
+def parse(buf: bytes) -> Header:
+    if len(buf) < 80 or buf[:4] != MAGIC:
+        raise ValueError("not a compressed buffer")
+    (_, ver, dt, D, rel, al, flags, fb, L, dsz, ch, tol, tau, mx, n, nch, nout,
+     nw) = struct.unpack_from("<4sHBBBBBBIIIdddQQQQ", buf, 0)
+    if ver != VERSION or dt > 1 or not 1 <= D <= 4:
+        raise ValueError("unsupported header")
+    pos = 80
+    shape = tuple(int(v) for v in np.frombuffer(buf, "<u8", D, pos))
+    pos += 8 * D
+    coords = [None] * D
+    for d in range(D):
+        if (flags >> d) & 1:
+            coords[d] = np.frombuffer(buf, "<f8", shape[d], pos).copy()
+            pos += 8 * shape[d]
+    bins = [float(v) for v in np.frombuffer(buf, "<f8", L + 1, pos)]
+    pos += 8 * (L + 1)
+    off = {"code_len": pos}
+    pos += dsz
+    off["chunk_bits"] = pos
+    pos += 4 * nch
+    off["chunk_esc"] = pos
+    pos += 4 * nch
+    off["payload"] = pos
+    pos += 4 * nw
+    pos += (-pos) % 8
+    off["outliers"] = pos
+    pos += 8 * nout
+    off["end"] = pos
+    if pos > len(buf):
+        raise ValueError("truncated buffer")
+    return Header(np.float32 if dt == 0 else np.float64, D, bool(rel), al, fb, L, dsz, ch, tol, tau,
+                  mx, n, nch, nout, nw, shape, coords, bins, off)
+
+
+def decompress(buf: bytes):
+    h = parse(buf)
+    hier = Hierarchy(h.shape, h.coords)
+    lengths = np.frombuffer(buf, np.uint8, h.dict_size, h.offsets["code_len"]).astype(np.int64)
+    codes = H.canonical_codes(lengths)
+    cbits = [int(v) for v in np.frombuffer(buf, "<u4", h.n_chunks, h.offsets["chunk_bits"])]
+    words = [int(v) for v in np.frombuffer(buf, "<u4", h.payload_words, h.offsets["payload"])]
+    outl = np.frombuffer(buf, "<i8", h.n_outliers, h.offsets["outliers"])
+    sym = H.decode(words, cbits, lengths, codes, h.n, h.chunk)
+    q = Q.from_symbols(sym, outl, h.dict_size)
+    stream = Q.dequantize_stream(q, hier, h.bins, h.dtype)
+    coarsest, cbars = Q.from_stream(stream, hier, h.dtype)
+    return X.recompose(coarsest, cbars, hier, h.dtype)
