@@ -144,6 +144,35 @@ def recompose_level(cbar, ucoarse, hier: Hierarchy, l: int, T):
     return u
 
 
+def coefficient_at(u, hier: Hierarchy, p, T):
+    """Finest-level coefficient at one node p of the input grid (0 at coarse nodes).
+
+    The interpolant is evaluated at p alone, with the same nesting as
+    ``interpolant``: the highest odd dimension innermost.
+    """
+    l = hier.L
+    odd = [d for d in range(hier.D)
+           if hier.ops[l][d] is not None and p[d] % 2 == 1 and p[d] < hier.sizes[l][d] - 1]
+
+    def nest(q, k):
+        if k == len(odd):
+            return T(u[tuple(q)])
+        d = odd[k]
+        op = hier.ops[l][d]
+        j = (q[d] - 1) // 2
+        left = list(q)
+        right = list(q)
+        left[d] -= 1
+        right[d] += 1
+        a = nest(left, k + 1)
+        b = nest(right, k + 1)
+        return T(T(op.wl[j]) * a) + T(T(op.wr[j]) * b)
+
+    if not odd:
+        return T(0)
+    return T(T(u[tuple(p)]) - nest(list(p), 0))
+
+
 def decompose(u, hier: Hierarchy, T=None):
     """Full decomposition; returns (coarsest grid, [cbar_1, ..., cbar_L])."""
     T = np.dtype(T or u.dtype).type

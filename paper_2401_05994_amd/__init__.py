@@ -1,0 +1,364 @@
+"""Python binding of libmgard_hip.so (MI355X / gfx950 multilevel lossy compressor).
+
+Argument marshalling only: every step runs in the HIP library.  Device
+buffers are torch CUDA tensors; work is enqueued on torch's current stream.
+The functions carry the C names of include/mgard_hip.h.  Importing this module
+does not need a GPU; calling into it does.  If the shared library has not
+been built, loading fails with an error naming the build command -- there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgard_hip.so")
+
+MGARD_OK = 0
+STATUS = {
+    0: "MGARD_OK", -1: "MGARD_ERR_ARG", -2: "MGARD_ERR_SHAPE", -3: "MGARD_ERR_DTYPE", -4: "MGARD_ERR_TOL",
+    -5: "MGARD_ERR_NONFINITE", -6: "MGARD_ERR_CAPACITY", -7: "MGARD_ERR_FORMAT", -8: "MGARD_ERR_DEVICE",
+    -9: "MGARD_ERR_OOM",
+}
+F32, F64 = 0, 1
+ABS, REL = 0, 1
+ALLOC = {"plain": 0, "learned": 1, "count": 2}
+
+
+class MgardError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class mgard_opts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("eb", C.c_uint32), ("alloc", C.c_uint32),
+                ("dict_size", C.c_uint32), ("chunk_symbols", C.c_uint32), ("reserved", C.c_uint32),
+                ("stream", C.c_void_p), ("model", C.c_void_p)]
+
+
+class mgard_info(C.Structure):
+    _fields_ = [("tol", C.c_double), ("tau_abs", C.c_double), ("maxabs", C.c_double),
+                ("bin_width", C.c_double * 40), ("linf_err", C.c_double),
+                ("n_symbols", C.c_uint64), ("n_outliers", C.c_uint64), ("payload_words", C.c_uint64),
+                ("out_bytes", C.c_uint64), ("levels", C.c_uint32), ("fallback_used", C.c_uint32)]
+
+
+class mgard_header(C.Structure):
+    _fields_ = [("version", C.c_uint32), ("dtype", C.c_uint32), ("ndim", C.c_uint32), ("eb", C.c_uint32),
+                ("alloc", C.c_uint32), ("fallback", C.c_uint32), ("coord_flags", C.c_uint32),
+                ("levels", C.c_uint32), ("dict_size", C.c_uint32), ("chunk_symbols", C.c_uint32),
+                ("shape", C.c_uint64 * 4), ("tol", C.c_double), ("tau_abs", C.c_double),
+                ("maxabs", C.c_double), ("n_symbols", C.c_uint64), ("n_chunks", C.c_uint64),
+                ("n_outliers", C.c_uint64), ("payload_words", C.c_uint64), ("total_bytes", C.c_uint64)]
+
+
+_lib = None
+
+
+def load_library():
+    """Loads libmgard_hip.so; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python {os.path.join(_HERE, 'build.py')}`")
+    lib = C.CDLL(LIB_PATH)
+    P, U32, U64, D = C.c_void_p, C.c_uint32, C.c_uint64, C.c_double
+    PU64, PD = C.POINTER(C.c_uint64), C.POINTER(C.c_double)
+    sig = {
+        "mgard_default_opts": (None, [P]),
+        "mgard_last_error": (C.c_char_p, []),
+        "mgard_version": (C.c_char_p, []),
+        "mgard_release_workspace": (C.c_int, []),
+        "mgard_compress_bound": (U64, [U32, PU64, P, C.c_int, P]),
+        "mgard_compress": (C.c_int, [U32, PU64, P, C.c_int, D, P, P, U64, PU64, P, P]),
+        "mgard_decompress": (C.c_int, [P, U64, P, U64, P, P]),
+        "mgard_inspect": (C.c_int, [P, U64, P]),
+        "mgard_stream_layout": (C.c_int, [U32, PU64, C.POINTER(U32), PU64, U32]),
+        "mgard_decompose": (C.c_int, [U32, PU64, P, C.c_int, P, P, P]),
+        "mgard_recompose": (C.c_int, [U32, PU64, P, C.c_int, P, P, P]),
+        "mgard_quantize": (C.c_int, [U32, PU64, C.c_int, P, PD, U32, P, P, P]),
+        "mgard_dequantize": (C.c_int, [U32, PU64, C.c_int, P, P, PD, U32, P, P]),
+        "mgard_histogram": (C.c_int, [P, U64, U32, U32, P, P, P]),
+        "mgard_huffman_codebook": (C.c_int, [P, U32, P, P, P]),
+        "mgard_huffman_encode": (C.c_int, [P, U64, U32, U32, P, P, P, P, U64, PU64, P]),
+        "mgard_huffman_decode": (C.c_int, [P, U64, P, U64, U32, U32, P, P, P]),
+        "mgard_maxabs": (C.c_int, [C.c_int, P, U64, PD, P]),
+        "mgard_plain_constant": (C.c_int, [U32, PU64, P, PD, PD, U32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != MGARD_OK:
+        msg = load_library().mgard_last_error().decode(errors="replace")
+        raise MgardError(code, msg)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _shape(shape):
+    return (C.c_uint64 * len(shape))(*[int(s) for s in shape])
+
+
+class _Coords:
+    """Keeps host coordinate arrays alive for the duration of a call."""
+
+    def __init__(self, coords, ndim):
+        self.arrays = []
+        if coords is None:
+            self.ptr = None
+            return
+        if len(coords) != ndim:
+            raise ValueError("one coordinate entry per dimension")
+        arr = (C.c_void_p * ndim)()
+        for d, x in enumerate(coords):
+            if x is None:
+                arr[d] = None
+            else:
+                a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+                self.arrays.append(a)
+                arr[d] = a.ctypes.data
+        self.arr = arr
+        self.ptr = C.cast(arr, C.c_void_p)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("float32 or float64 tensor expected")
+
+
+def make_opts(eb="rel", alloc="plain", dict_size=8192, chunk=4096, stream=None):
+    o = mgard_opts()
+    load_library().mgard_default_opts(C.byref(o))
+    o.eb = REL if eb == "rel" else ABS
+    o.alloc = ALLOC[alloc]
+    o.dict_size = dict_size
+    o.chunk_symbols = chunk
+    if stream is None:
+        stream = _torch().cuda.current_stream().cuda_stream
+    o.stream = stream
+    return o
+
+
+def mgard_compress_bound(shape, dtype=F32, coords=None, dict_size=8192, chunk=4096):
+    lib = load_library()
+    cc = _Coords(coords, len(shape))
+    o = mgard_opts()
+    lib.mgard_default_opts(C.byref(o))
+    o.dict_size, o.chunk_symbols = dict_size, chunk
+    b = lib.mgard_compress_bound(len(shape), _shape(shape), cc.ptr, dtype, C.byref(o))
+    if b == 0:
+        _check(-1)
+    return int(b)
+
+
+def mgard_compress(u, tol, coords=None, eb="rel", alloc="plain", dict_size=8192, chunk=4096, out=None):
+    """Compresses a CUDA float tensor.  Returns (uint8 CUDA buffer, nbytes, info dict)."""
+    torch = _torch()
+    lib = load_library()
+    u = u.contiguous()
+    dt = _dtype_code(u)
+    shape = tuple(u.shape)
+    cc = _Coords(coords, len(shape))
+    o = make_opts(eb, alloc, dict_size, chunk)
+    bound = mgard_compress_bound(shape, dt, coords, dict_size, chunk)
+    if out is None:
+        out = torch.empty(bound, dtype=torch.uint8, device=u.device)
+    nbytes = C.c_uint64(0)
+    info = mgard_info()
+    _check(lib.mgard_compress(len(shape), _shape(shape), cc.ptr, dt, float(tol), _ptr(u), _ptr(out),
+                              out.numel(), C.byref(nbytes), C.byref(o), C.byref(info)))
+    L = info.levels
+    d = {
+        "tol": info.tol, "tau_abs": info.tau_abs, "maxabs": info.maxabs,
+        "bins": [info.bin_width[i] for i in range(L + 1)], "levels": L,
+        "n_outliers": info.n_outliers, "payload_words": info.payload_words, "out_bytes": info.out_bytes,
+        "fallback_used": info.fallback_used, "linf_err": info.linf_err,
+    }
+    return out, int(nbytes.value), d
+
+
+def mgard_decompress(buf, nbytes, out=None):
+    """Decompresses a uint8 CUDA buffer; returns the field as a CUDA tensor."""
+    torch = _torch()
+    lib = load_library()
+    head = buf[: min(int(nbytes), 1 << 16)].cpu().numpy().tobytes()
+    hd = mgard_inspect(head)
+    shape = tuple(hd["shape"])
+    dtype = torch.float32 if hd["dtype"] == 0 else torch.float64
+    if out is None:
+        out = torch.empty(shape, dtype=dtype, device=buf.device)
+    o = make_opts()
+    h = mgard_header()
+    _check(lib.mgard_decompress(_ptr(buf), int(nbytes), _ptr(out), out.numel() * out.element_size(),
+                                C.byref(o), C.byref(h)))
+    return out
+
+
+def mgard_inspect(host_bytes: bytes):
+    lib = load_library()
+    h = mgard_header()
+    b = C.create_string_buffer(host_bytes, len(host_bytes))
+    code = lib.mgard_inspect(b, len(host_bytes), C.byref(h))
+    if code == -6:  # needs more bytes for the full header: still report the fixed fields
+        pass
+    else:
+        _check(code)
+    return {
+        "version": h.version, "dtype": h.dtype, "ndim": h.ndim, "eb": h.eb, "alloc": h.alloc,
+        "fallback": h.fallback, "coord_flags": h.coord_flags, "levels": h.levels, "dict_size": h.dict_size,
+        "chunk_symbols": h.chunk_symbols, "shape": [h.shape[i] for i in range(h.ndim)], "tol": h.tol,
+        "tau_abs": h.tau_abs, "maxabs": h.maxabs, "n_symbols": h.n_symbols, "n_chunks": h.n_chunks,
+        "n_outliers": h.n_outliers, "payload_words": h.payload_words, "total_bytes": h.total_bytes,
+        "complete": code == 0,
+    }
+
+
+def mgard_stream_layout(shape):
+    lib = load_library()
+    L = C.c_uint32(0)
+    offs = (C.c_uint64 * 42)()
+    _check(lib.mgard_stream_layout(len(shape), _shape(shape), C.byref(L), offs, 42))
+    return int(L.value), [int(offs[i]) for i in range(L.value + 2)]
+
+
+def mgard_decompose(u, coords=None):
+    torch = _torch()
+    lib = load_library()
+    u = u.contiguous()
+    cc = _Coords(coords, u.dim())
+    out = torch.empty(u.numel(), dtype=u.dtype, device=u.device)
+    o = make_opts()
+    _check(lib.mgard_decompose(u.dim(), _shape(u.shape), cc.ptr, _dtype_code(u), _ptr(u), _ptr(out), C.byref(o)))
+    return out
+
+
+def mgard_recompose(coeff, shape, coords=None):
+    torch = _torch()
+    lib = load_library()
+    coeff = coeff.contiguous()
+    cc = _Coords(coords, len(shape))
+    out = torch.empty(tuple(shape), dtype=coeff.dtype, device=coeff.device)
+    o = make_opts()
+    _check(lib.mgard_recompose(len(shape), _shape(shape), cc.ptr, _dtype_code(coeff), _ptr(coeff), _ptr(out),
+                               C.byref(o)))
+    return out
+
+
+def mgard_quantize(coeff, shape, bins, dict_size=8192):
+    torch = _torch()
+    lib = load_library()
+    coeff = coeff.contiguous()
+    n = coeff.numel()
+    sym = torch.empty(n, dtype=torch.int16, device=coeff.device)
+    qside = torch.zeros(n, dtype=torch.int64, device=coeff.device)
+    hb = (C.c_double * len(bins))(*bins)
+    o = make_opts()
+    _check(lib.mgard_quantize(len(shape), _shape(shape), _dtype_code(coeff), _ptr(coeff), hb, dict_size,
+                              _ptr(sym), _ptr(qside), C.byref(o)))
+    return sym, qside
+
+
+def mgard_dequantize(sym, qside, shape, bins, dtype, dict_size=8192):
+    torch = _torch()
+    lib = load_library()
+    out = torch.empty(sym.numel(), dtype=dtype, device=sym.device)
+    hb = (C.c_double * len(bins))(*bins)
+    o = make_opts()
+    _check(lib.mgard_dequantize(len(shape), _shape(shape), _dtype_code(out), _ptr(sym), _ptr(qside), hb,
+                                dict_size, _ptr(out), C.byref(o)))
+    return out
+
+
+def mgard_histogram(sym, dict_size=8192, chunk=4096):
+    torch = _torch()
+    lib = load_library()
+    n = sym.numel()
+    hist = torch.empty(dict_size, dtype=torch.int64, device=sym.device)
+    esc = torch.empty(max((n + chunk - 1) // chunk, 1), dtype=torch.int32, device=sym.device)
+    o = make_opts()
+    _check(lib.mgard_histogram(_ptr(sym), n, dict_size, chunk, _ptr(hist), _ptr(esc), C.byref(o)))
+    return hist, esc
+
+
+def mgard_huffman_codebook(hist, dict_size=8192):
+    torch = _torch()
+    lib = load_library()
+    lens = torch.empty(dict_size, dtype=torch.uint8, device=hist.device)
+    codes = torch.empty(dict_size, dtype=torch.int64, device=hist.device)
+    o = make_opts()
+    _check(lib.mgard_huffman_codebook(_ptr(hist), dict_size, _ptr(lens), _ptr(codes), C.byref(o)))
+    return lens, codes
+
+
+def mgard_huffman_encode(sym, lens, codes, dict_size=8192, chunk=4096):
+    torch = _torch()
+    lib = load_library()
+    n = sym.numel()
+    nch = (n + chunk - 1) // chunk
+    bits = torch.empty(max(nch, 1), dtype=torch.int32, device=sym.device)
+    cap = (n * 64 + 31) // 32 + nch + 1
+    payload = torch.empty(cap, dtype=torch.int32, device=sym.device)
+    words = C.c_uint64(0)
+    o = make_opts()
+    _check(lib.mgard_huffman_encode(_ptr(sym), n, dict_size, chunk, _ptr(lens), _ptr(codes), _ptr(bits),
+                                    _ptr(payload), cap, C.byref(words), C.byref(o)))
+    return bits[:nch], payload[: words.value]
+
+
+def mgard_huffman_decode(payload, bits, n, lens, dict_size=8192, chunk=4096):
+    torch = _torch()
+    lib = load_library()
+    sym = torch.empty(n, dtype=torch.int16, device=payload.device)
+    o = make_opts()
+    _check(lib.mgard_huffman_decode(_ptr(payload), payload.numel(), _ptr(bits), n, dict_size, chunk, _ptr(lens),
+                                    _ptr(sym), C.byref(o)))
+    return sym
+
+
+def mgard_maxabs(u):
+    lib = load_library()
+    m = C.c_double(0)
+    o = make_opts()
+    _check(lib.mgard_maxabs(_dtype_code(u), _ptr(u), u.numel(), C.byref(m), C.byref(o)))
+    return m.value
+
+
+def mgard_plain_constant(shape, coords=None):
+    lib = load_library()
+    cc = _Coords(coords, len(shape))
+    S = C.c_double(0)
+    K = (C.c_double * 41)()
+    _check(lib.mgard_plain_constant(len(shape), _shape(shape), cc.ptr, C.byref(S), K, 41))
+    return S.value, list(K)
+
+
+def mgard_release_workspace():
+    _check(load_library().mgard_release_workspace())
+
+
+def u16(t):
+    """uint16 view (numpy) of an int16 symbol tensor."""
+    return t.cpu().numpy().view(np.uint16)

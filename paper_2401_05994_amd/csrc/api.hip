@@ -1,0 +1,785 @@
+// C interface: argument checks, scratch layout, pipelines and the wire format.
+//
+// Compression (paper Sec. 2 and the first listing of Sec. 3): max|u| ->
+// bin widths on the device -> decomposition with fused quantization ->
+// histogram -> codebook -> chunk sizes -> encode, every table written
+// straight into the caller's output buffer; one readback returns the size.
+// Decompression reads the self-describing header (Sec. 2.1) back to the host,
+// validates it, then decodes and recomposes on the device.
+//
+// Wire format (little-endian, byte offsets):
+//    0 'MGHP'  4 u16 version  6 u8 dtype  7 u8 ndim  8 u8 eb  9 u8 alloc
+//   10 u8 coord_flags  11 u8 fallback  12 u32 L  16 u32 dict  20 u32 chunk
+//   24 f64 tol  32 f64 tau_abs  40 f64 maxabs  48 u64 n_symbols
+//   56 u64 n_chunks  64 u64 n_outliers  72 u64 payload_words
+//   80 u64 shape[ndim], f64 coordinates of flagged dimensions, f64 bins[L+1],
+//   u8 code_len[dict], u32 chunk_bits[n_chunks], u32 chunk_esc[n_chunks],
+//   u32 payload[payload_words], zero padding to 8 bytes, i64 outliers[].
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+
+namespace mg {
+
+void fail(mgard_status code, const std::string& msg) { throw Failure{code, msg}; }
+
+namespace {
+
+thread_local std::string g_err;
+
+template <typename F>
+mgard_status guard(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return MGARD_OK;
+  } catch (const Failure& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return MGARD_ERR_OOM;
+  } catch (...) {
+    g_err = "unexpected exception";
+    return MGARD_ERR_ARG;
+  }
+}
+
+constexpr uint16_t kVersion = 1;
+constexpr uint64_t kFixed = 80;
+
+struct Opts {
+  int eb = MGARD_REL;
+  int alloc = MGARD_ALLOC_PLAIN;
+  int dict = 8192;
+  int chunk = 4096;
+  hipStream_t st = nullptr;
+  const mgard_model* model = nullptr;
+};
+
+Opts read_opts(const mgard_opts* o) {
+  Opts r;
+  if (!o) return r;
+  if (o->struct_size != sizeof(mgard_opts)) fail(MGARD_ERR_ARG, "opts->struct_size mismatch");
+  if (o->eb > 1) fail(MGARD_ERR_ARG, "opts->eb");
+  if (o->alloc > 2) fail(MGARD_ERR_ARG, "opts->alloc");
+  r.eb = (int)o->eb;
+  r.alloc = (int)o->alloc;
+  if (o->dict_size) {
+    const uint32_t d = o->dict_size;
+    if (d < 256 || d > 8192 || (d & (d - 1))) fail(MGARD_ERR_ARG, "dict_size must be a power of two in [256, 8192]");
+    r.dict = (int)d;
+  }
+  if (o->chunk_symbols) {
+    const uint32_t c = o->chunk_symbols;
+    if (c < 256 || c > 8192 || (c % 256)) fail(MGARD_ERR_ARG, "chunk_symbols must be a multiple of 256 in [256, 8192]");
+    r.chunk = (int)c;
+  }
+  r.st = static_cast<hipStream_t>(o->stream);
+  r.model = o->model;
+  return r;
+}
+
+int dtype_size(mgard_dtype t) {
+  if (t == MGARD_F32) return 4;
+  if (t == MGARD_F64) return 8;
+  fail(MGARD_ERR_DTYPE, "dtype must be MGARD_F32 or MGARD_F64");
+}
+
+uint64_t align8(uint64_t v) { return (v + 7) & ~uint64_t(7); }
+
+struct Layout {
+  uint64_t bins, code_len, chunk_bits, chunk_esc, payload;  // byte offsets
+  uint64_t nch;
+};
+
+Layout layout(const Hierarchy& h, const double* const* coords, int dict, int chunk, uint64_t n) {
+  Layout y{};
+  uint64_t p = kFixed + 8ull * h.D;
+  for (int d = 0; d < h.D; ++d)
+    if (coords && coords[d]) p += 8ull * h.shape[d + (MAXD - h.D)];
+  y.bins = p;
+  p += 8ull * (h.L + 1);
+  y.code_len = p;
+  p += (uint64_t)dict;
+  y.nch = (n + chunk - 1) / chunk;
+  y.chunk_bits = p;
+  p += 4 * y.nch;
+  y.chunk_esc = p;
+  p += 4 * y.nch;
+  y.payload = p;
+  return y;
+}
+
+// worst case: every symbol escapes (8 B + 1 bit), or log2(dict)+1 bits per symbol
+uint64_t bound_of(const Hierarchy& h, const double* const* coords, int dict, int chunk) {
+  const uint64_t n = h.count(h.L);
+  Layout y = layout(h, coords, dict, chunk, n);
+  int lg = 0;
+  while ((1 << lg) < dict) ++lg;
+  const uint64_t words = (n * (uint64_t)(lg + 1) + 31) / 32 + y.nch;
+  return align8(y.payload + 4 * words) + 8 * n + 64;
+}
+
+struct Finale {  // device results read back by the host at the end
+  uint64_t total_bytes, n_outliers, payload_words, pad;
+  double scalars[8];  // tau_abs, maxabs, nonfinite, tau_eff
+  double bins[MAXL + 1];
+};
+
+__global__ void k_outlier_offset(const uint64_t* word_off, uint64_t nch, uint64_t payload_off,
+                                 uint64_t* ooff) {
+  if (threadIdx.x == 0) *ooff = (payload_off + 4 * word_off[nch] + 7) & ~7ull;
+}
+
+__global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* esc_off, uint64_t nch,
+                           const uint64_t* ooff, const double* scalars, const double* bins, int L,
+                           uint64_t bins_off, int fallback, Finale* fin) {
+  if (threadIdx.x != 0) return;
+  const uint64_t pw = word_off[nch], no = esc_off[nch];
+  double* hd = reinterpret_cast<double*>(out);
+  hd[4] = scalars[0];  // tau_abs at 32
+  hd[5] = scalars[1];  // maxabs at 40
+  uint64_t* hu = reinterpret_cast<uint64_t*>(out);
+  hu[8] = no;  // 64
+  hu[9] = pw;  // 72
+  out[11] = (char)fallback;
+  double* bo = reinterpret_cast<double*>(out + bins_off);
+  for (int l = 0; l <= L; ++l) bo[l] = bins[l];
+  fin->total_bytes = *ooff + 8 * no;
+  fin->n_outliers = no;
+  fin->payload_words = pw;
+  for (int i = 0; i < 4; ++i) fin->scalars[i] = scalars[i];
+  for (int l = 0; l <= L; ++l) fin->bins[l] = bins[l];
+}
+
+__global__ void k_zero_pad(char* out, const uint64_t* word_off, uint64_t nch, uint64_t payload_off) {
+  if (threadIdx.x != 0) return;
+  const uint64_t e = payload_off + 4 * word_off[nch];
+  for (uint64_t b = e; b % 8; ++b) out[b] = 0;
+}
+
+std::vector<uint8_t> header_bytes(const Hierarchy& h, const double* const* coords, int dtype, int eb,
+                                  int alloc, double tol, int dict, int chunk, uint64_t n,
+                                  uint64_t nch) {
+  std::vector<uint8_t> b(kFixed, 0);
+  auto w16 = [&](size_t o, uint16_t v) { std::memcpy(&b[o], &v, 2); };
+  auto w32 = [&](size_t o, uint32_t v) { std::memcpy(&b[o], &v, 4); };
+  auto w64 = [&](size_t o, uint64_t v) { std::memcpy(&b[o], &v, 8); };
+  auto wd = [&](size_t o, double v) { std::memcpy(&b[o], &v, 8); };
+  std::memcpy(&b[0], "MGHP", 4);
+  w16(4, kVersion);
+  b[6] = (uint8_t)dtype;
+  b[7] = (uint8_t)h.D;
+  b[8] = (uint8_t)eb;
+  b[9] = (uint8_t)alloc;
+  uint8_t flags = 0;
+  for (int d = 0; d < h.D; ++d)
+    if (coords && coords[d]) flags |= (uint8_t)(1u << d);
+  b[10] = flags;
+  b[11] = 0;
+  w32(12, (uint32_t)h.L);
+  w32(16, (uint32_t)dict);
+  w32(20, (uint32_t)chunk);
+  wd(24, tol);
+  wd(32, 0.0);
+  wd(40, 0.0);
+  w64(48, n);
+  w64(56, nch);
+  w64(64, 0);
+  w64(72, 0);
+  const int pad = MAXD - h.D;
+  for (int d = 0; d < h.D; ++d) {
+    uint64_t s = (uint64_t)h.shape[d + pad];
+    const uint8_t* p = reinterpret_cast<const uint8_t*>(&s);
+    b.insert(b.end(), p, p + 8);
+  }
+  for (int d = 0; d < h.D; ++d)
+    if (coords && coords[d]) {
+      const uint8_t* p = reinterpret_cast<const uint8_t*>(coords[d]);
+      b.insert(b.end(), p, p + 8 * h.shape[d + pad]);
+    }
+  return b;
+}
+
+// Parses a header held on the host; fills hdr and, optionally, coordinates.
+struct Parsed {
+  mgard_header hd{};
+  std::vector<std::vector<double>> coords;
+  uint64_t bins_off = 0, code_len = 0, chunk_bits = 0, chunk_esc = 0, payload = 0, outliers = 0;
+  uint64_t need = 0;  // bytes of header needed up to the end of bins
+};
+
+// returns false when more bytes are needed (need is set)
+bool parse_header(const uint8_t* b, uint64_t bytes, Parsed& P) {
+  if (bytes < kFixed) {
+    P.need = kFixed;
+    return false;
+  }
+  if (std::memcmp(b, "MGHP", 4) != 0) fail(MGARD_ERR_FORMAT, "bad magic");
+  mgard_header& h = P.hd;
+  uint16_t ver;
+  std::memcpy(&ver, b + 4, 2);
+  h.version = ver;
+  if (ver != kVersion) fail(MGARD_ERR_FORMAT, "unsupported version");
+  h.dtype = b[6];
+  h.ndim = b[7];
+  h.eb = b[8];
+  h.alloc = b[9];
+  h.coord_flags = b[10];
+  h.fallback = b[11];
+  if (h.dtype > 1 || h.ndim < 1 || h.ndim > 4 || h.eb > 1 || h.alloc > 2 || (h.coord_flags >> h.ndim))
+    fail(MGARD_ERR_FORMAT, "bad header fields");
+  std::memcpy(&h.levels, b + 12, 4);
+  std::memcpy(&h.dict_size, b + 16, 4);
+  std::memcpy(&h.chunk_symbols, b + 20, 4);
+  std::memcpy(&h.tol, b + 24, 8);
+  std::memcpy(&h.tau_abs, b + 32, 8);
+  std::memcpy(&h.maxabs, b + 40, 8);
+  std::memcpy(&h.n_symbols, b + 48, 8);
+  std::memcpy(&h.n_chunks, b + 56, 8);
+  std::memcpy(&h.n_outliers, b + 64, 8);
+  std::memcpy(&h.payload_words, b + 72, 8);
+  const uint32_t d = h.dict_size, c = h.chunk_symbols;
+  if (d < 256 || d > 8192 || (d & (d - 1)) || c < 256 || c > 8192 || (c % 256))
+    fail(MGARD_ERR_FORMAT, "bad dictionary or chunk size");
+  if (h.levels > MAXL - 1) fail(MGARD_ERR_FORMAT, "bad level count");
+  uint64_t p = kFixed + 8ull * h.ndim;
+  if (bytes < p) {
+    P.need = p;
+    return false;
+  }
+  uint64_t n = 1;
+  for (uint32_t i = 0; i < h.ndim; ++i) {
+    std::memcpy(&h.shape[i], b + kFixed + 8 * i, 8);
+    if (h.shape[i] == 0 || h.shape[i] > (1ull << 31)) fail(MGARD_ERR_FORMAT, "bad shape");
+    n *= h.shape[i];
+    if (n > (1ull << 40)) fail(MGARD_ERR_FORMAT, "bad shape");
+  }
+  if (n != h.n_symbols) fail(MGARD_ERR_FORMAT, "symbol count does not match shape");
+  if (h.n_chunks != (n + c - 1) / c) fail(MGARD_ERR_FORMAT, "chunk count does not match");
+  if (h.n_outliers > n) fail(MGARD_ERR_FORMAT, "outlier count");
+  if (h.payload_words > (n * 64 + 31) / 32 + h.n_chunks) fail(MGARD_ERR_FORMAT, "payload size");
+  for (uint32_t i = 0; i < h.ndim; ++i)
+    if ((h.coord_flags >> i) & 1) p += 8 * h.shape[i];
+  P.bins_off = p;
+  p += 8ull * (h.levels + 1);
+  P.need = p;
+  if (bytes < p) return false;
+  P.coords.assign(h.ndim, {});
+  uint64_t q = kFixed + 8ull * h.ndim;
+  for (uint32_t i = 0; i < h.ndim; ++i)
+    if ((h.coord_flags >> i) & 1) {
+      P.coords[i].resize(h.shape[i]);
+      std::memcpy(P.coords[i].data(), b + q, 8 * h.shape[i]);
+      q += 8 * h.shape[i];
+    }
+  P.code_len = p;
+  p += d;
+  P.chunk_bits = p;
+  p += 4 * h.n_chunks;
+  P.chunk_esc = p;
+  p += 4 * h.n_chunks;
+  P.payload = p;
+  p += 4 * h.payload_words;
+  p = align8(p);
+  P.outliers = p;
+  p += 8 * h.n_outliers;
+  h.total_bytes = p;
+  return true;
+}
+
+void check_bins(const Parsed& P, const uint8_t* b) {
+  for (uint32_t l = 0; l <= P.hd.levels; ++l) {
+    double v;
+    std::memcpy(&v, b + P.bins_off + 8 * l, 8);
+    if (!(v > 0.0) || !std::isfinite(v)) fail(MGARD_ERR_FORMAT, "bad bin width");
+  }
+}
+
+template <typename T>
+void compress_impl(Hierarchy& h, const double* const* coords, double tol, const T* d_in, char* d_out,
+                   uint64_t* out_bytes, const Opts& o, mgard_info* info) {
+  const bool f64 = sizeof(T) == 8;
+  hipStream_t st = o.st;
+  const T* table = static_cast<const T*>(device_table(h, f64, st));
+  const uint64_t n = h.count(h.L);
+  Layout y = layout(h, coords, o.dict, o.chunk, n);
+  const uint64_t nch = y.nch;
+  // scratch
+  const uint64_t dbytes = decompose_scratch_bytes<T>(h);
+  uint64_t need = dbytes + carve_size<uint16_t>(n) + carve_size<int64_t>(n) +
+                  carve_size<double>(MAXL + 1) + carve_size<double>(8) + carve_size<uint64_t>(4) +
+                  2 * carve_size<uint64_t>((uint64_t)o.dict) + 2 * carve_size<uint64_t>(nch + 1) +
+                  carve_size<Finale>(1) + 4096;
+  Workspace& ws = workspace();
+  ws.reserve(need);
+  Carver cv(ws.base());
+  void* dscratch = cv.take<char>(dbytes);
+  uint16_t* sym = cv.take<uint16_t>(n);
+  int64_t* qside = cv.take<int64_t>(n);
+  double* bins = cv.take<double>(MAXL + 1);
+  double* scalars = cv.take<double>(8);
+  uint64_t* misc = cv.take<uint64_t>(4);  // [0] max bits, [1] outlier byte offset
+  uint64_t* hist = cv.take<uint64_t>((uint64_t)o.dict);
+  uint64_t* codes = cv.take<uint64_t>((uint64_t)o.dict);
+  uint64_t* word_off = cv.take<uint64_t>(nch + 1);
+  uint64_t* esc_off = cv.take<uint64_t>(nch + 1);
+  Finale* fin = cv.take<Finale>(1);
+
+  std::vector<uint8_t> hb = header_bytes(h, coords, f64 ? 1 : 0, o.eb, o.alloc, tol, o.dict, o.chunk, n, nch);
+  MG_HIP(hipMemcpyAsync(d_out, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
+
+  // tolerance and bin widths
+  launch_maxabs<T>(d_in, n, &misc[0], st);
+  BinArgs ba{};
+  for (int l = 0; l <= h.L; ++l) {
+    ba.K[l] = h.K[l];
+    ba.counts[l] = (double)h.level_count[l];
+  }
+  const int alloc = o.alloc == MGARD_ALLOC_COUNT ? MGARD_ALLOC_COUNT : MGARD_ALLOC_PLAIN;
+  launch_bins(f64 ? 1 : 0, &misc[0], tol, o.eb, h.S, h.L, alloc, ba, bins, scalars, st);
+
+  // decomposition with fused quantization
+  QuantOut q;
+  q.sym = sym;
+  q.qside = qside;
+  q.bins = bins;
+  q.R = o.dict / 2;
+  decompose<T>(h, table, d_in, nullptr, &q, dscratch, st);
+
+  // lossless stage, tables written in place
+  uint32_t* chunk_esc = reinterpret_cast<uint32_t*>(d_out + y.chunk_esc);
+  uint32_t* chunk_bits = reinterpret_cast<uint32_t*>(d_out + y.chunk_bits);
+  uint8_t* code_len = reinterpret_cast<uint8_t*>(d_out + y.code_len);
+  launch_histogram(sym, n, o.dict, o.chunk, hist, chunk_esc, st);
+  launch_codebook(hist, o.dict, code_len, codes, st);
+  launch_chunk_bits(sym, n, o.chunk, code_len, chunk_bits, st);
+  launch_scan_words(chunk_bits, nch, word_off, st);
+  launch_scan_u32(chunk_esc, nch, esc_off, st);
+  hipLaunchKernelGGL(k_outlier_offset, dim3(1), dim3(1), 0, st, word_off, nch, y.payload, &misc[1]);
+  launch_encode(sym, n, o.chunk, code_len, codes, word_off, reinterpret_cast<uint32_t*>(d_out + y.payload),
+                esc_off, qside, d_out, &misc[1], st);
+  hipLaunchKernelGGL(k_zero_pad, dim3(1), dim3(1), 0, st, d_out, word_off, nch, y.payload);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, d_out, word_off, esc_off, nch, &misc[1], scalars, bins,
+                     h.L, y.bins, 0, fin);
+  MG_HIP(hipGetLastError());
+  Finale hf;
+  MG_HIP(hipMemcpyAsync(&hf, fin, sizeof(Finale), hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  if (hf.scalars[2] != 0.0) fail(MGARD_ERR_NONFINITE, "input holds NaN or infinity");
+  *out_bytes = hf.total_bytes;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->tol = tol;
+    info->tau_abs = hf.scalars[0];
+    info->maxabs = hf.scalars[1];
+    for (int l = 0; l <= h.L; ++l) info->bin_width[l] = hf.bins[l];
+    info->linf_err = -1.0;
+    info->n_symbols = n;
+    info->n_outliers = hf.n_outliers;
+    info->payload_words = hf.payload_words;
+    info->out_bytes = hf.total_bytes;
+    info->levels = (uint32_t)h.L;
+    info->fallback_used = 0;
+  }
+}
+
+template <typename T>
+void decompress_impl(Hierarchy& h, const Parsed& P, const char* d_in, T* d_out, const Opts& o) {
+  const bool f64 = sizeof(T) == 8;
+  hipStream_t st = o.st;
+  const T* table = static_cast<const T*>(device_table(h, f64, st));
+  const uint64_t n = P.hd.n_symbols, nch = P.hd.n_chunks;
+  const int dict = (int)P.hd.dict_size, chunk = (int)P.hd.chunk_symbols;
+  const uint64_t rbytes = recompose_scratch_bytes<T>(h);
+  uint64_t need = rbytes + carve_size<uint16_t>(n) + carve_size<int64_t>(n) + 2 * carve_size<uint64_t>(nch + 1) +
+                  decode_table_bytes(dict) + carve_size<uint32_t>(4) + 4096;
+  Workspace& ws = workspace();
+  ws.reserve(need);
+  Carver cv(ws.base());
+  void* rscratch = cv.take<char>(rbytes);
+  uint16_t* sym = cv.take<uint16_t>(n);
+  int64_t* qside = cv.take<int64_t>(n);
+  uint64_t* word_off = cv.take<uint64_t>(nch + 1);
+  uint64_t* esc_off = cv.take<uint64_t>(nch + 1);
+  void* tabs = cv.take<char>(decode_table_bytes(dict));
+  uint32_t* status = cv.take<uint32_t>(4);
+  MG_HIP(hipMemsetAsync(status, 0, 16, st));
+  const uint32_t* chunk_bits = reinterpret_cast<const uint32_t*>(d_in + P.chunk_bits);
+  const uint32_t* chunk_esc = reinterpret_cast<const uint32_t*>(d_in + P.chunk_esc);
+  launch_scan_words(chunk_bits, nch, word_off, st);
+  launch_scan_u32(chunk_esc, nch, esc_off, st);
+  launch_decode_full(reinterpret_cast<const uint32_t*>(d_in + P.payload), P.hd.payload_words, word_off,
+                     chunk_bits, n, dict, chunk, reinterpret_cast<const uint8_t*>(d_in + P.code_len), sym,
+                     esc_off, P.hd.n_outliers, reinterpret_cast<const int64_t*>(d_in + P.outliers), qside, tabs,
+                     status, st);
+  QuantOut q;
+  q.sym = sym;
+  q.qside = qside;
+  q.bins = reinterpret_cast<const double*>(d_in + P.bins_off);
+  q.R = dict / 2;
+  recompose<T>(h, table, nullptr, &q, d_out, rscratch, st);
+  uint32_t hs[4];
+  MG_HIP(hipMemcpyAsync(hs, status, 16, hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  if (hs[0]) fail(MGARD_ERR_FORMAT, "payload does not decode");
+}
+
+struct CoordPtrs {
+  const double* p[MAXD] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+void mgard_default_opts(mgard_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(mgard_opts);
+  o->eb = MGARD_REL;
+  o->alloc = MGARD_ALLOC_PLAIN;
+  o->dict_size = 8192;
+  o->chunk_symbols = 4096;
+}
+
+const char* mgard_last_error(void) { return g_err.c_str(); }
+
+const char* mgard_version(void) { return "mgard-hip 1 (gfx950)"; }
+
+mgard_status mgard_release_workspace(void) {
+  return guard([&] { workspace().release(); });
+}
+
+uint64_t mgard_compress_bound(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                              mgard_dtype dtype, const mgard_opts* opts) {
+  uint64_t r = 0;
+  mgard_status s = guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    auto h = get_hierarchy(ndim, shape, coords);
+    r = bound_of(*h, coords, o.dict, o.chunk);
+  });
+  return s == MGARD_OK ? r : 0;
+}
+
+mgard_status mgard_compress(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                            mgard_dtype dtype, double tol, const void* d_in, void* d_out,
+                            uint64_t out_capacity, uint64_t* out_bytes, const mgard_opts* opts,
+                            mgard_info* info) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    const int ts = dtype_size(dtype);
+    (void)ts;
+    if (!d_in || !d_out || !out_bytes) fail(MGARD_ERR_ARG, "null buffer");
+    if (!(tol > 0.0) || !std::isfinite(tol)) fail(MGARD_ERR_TOL, "tolerance must be positive and finite");
+    if (o.alloc == MGARD_ALLOC_LEARNED) fail(MGARD_ERR_ARG, "learned allocation needs mgard_compress_learned");
+    auto h = get_hierarchy(ndim, shape, coords);
+    const uint64_t bound = bound_of(*h, coords, o.dict, o.chunk);
+    if (out_capacity < bound) {
+      *out_bytes = bound;
+      fail(MGARD_ERR_CAPACITY, "output capacity below mgard_compress_bound");
+    }
+    if (dtype == MGARD_F32)
+      compress_impl<float>(*h, coords, tol, static_cast<const float*>(d_in), static_cast<char*>(d_out), out_bytes,
+                           o, info);
+    else
+      compress_impl<double>(*h, coords, tol, static_cast<const double*>(d_in), static_cast<char*>(d_out),
+                            out_bytes, o, info);
+  });
+}
+
+mgard_status mgard_inspect(const void* h_buf, uint64_t bytes, mgard_header* hdr) {
+  return guard([&] {
+    if (!h_buf || !hdr) fail(MGARD_ERR_ARG, "null pointer");
+    Parsed P;
+    if (!parse_header(static_cast<const uint8_t*>(h_buf), bytes, P)) {
+      *hdr = P.hd;
+      hdr->total_bytes = P.need;
+      fail(MGARD_ERR_CAPACITY, "more header bytes needed");
+    }
+    check_bins(P, static_cast<const uint8_t*>(h_buf));
+    *hdr = P.hd;
+  });
+}
+
+mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out, uint64_t out_capacity,
+                              const mgard_opts* opts, mgard_header* hdr) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_in || !d_out) fail(MGARD_ERR_ARG, "null buffer");
+    std::vector<uint8_t> hb(std::min<uint64_t>(in_bytes, kFixed));
+    if (in_bytes < kFixed) fail(MGARD_ERR_FORMAT, "buffer shorter than a header");
+    MG_HIP(hipMemcpyAsync(hb.data(), d_in, kFixed, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+    Parsed P;
+    if (!parse_header(hb.data(), hb.size(), P)) {
+      if (P.need > in_bytes) fail(MGARD_ERR_FORMAT, "truncated header");
+      hb.resize(P.need);
+      MG_HIP(hipMemcpyAsync(hb.data(), d_in, P.need, hipMemcpyDeviceToHost, o.st));
+      MG_HIP(hipStreamSynchronize(o.st));
+      if (!parse_header(hb.data(), hb.size(), P)) fail(MGARD_ERR_FORMAT, "truncated header");
+    }
+    check_bins(P, hb.data());
+    if (P.hd.total_bytes > in_bytes) fail(MGARD_ERR_FORMAT, "buffer shorter than its header says");
+    const int ts = P.hd.dtype ? 8 : 4;
+    if (out_capacity < P.hd.n_symbols * (uint64_t)ts) fail(MGARD_ERR_CAPACITY, "output buffer too small");
+    CoordPtrs cp;
+    for (uint32_t d = 0; d < P.hd.ndim; ++d) cp.p[d] = P.coords[d].empty() ? nullptr : P.coords[d].data();
+    auto h = get_hierarchy(P.hd.ndim, P.hd.shape, cp.p);
+    if ((uint32_t)h->L != P.hd.levels) fail(MGARD_ERR_FORMAT, "level count does not match shape");
+    if (P.hd.dtype)
+      decompress_impl<double>(*h, P, static_cast<const char*>(d_in), static_cast<double*>(d_out), o);
+    else
+      decompress_impl<float>(*h, P, static_cast<const char*>(d_in), static_cast<float*>(d_out), o);
+    if (hdr) *hdr = P.hd;
+  });
+}
+
+mgard_status mgard_stream_layout(uint32_t ndim, const uint64_t* shape, uint32_t* levels,
+                                 uint64_t* level_offsets, uint32_t max_offsets) {
+  return guard([&] {
+    if (!levels) fail(MGARD_ERR_ARG, "null pointer");
+    auto h = get_hierarchy(ndim, shape, nullptr);
+    *levels = (uint32_t)h->L;
+    if (level_offsets) {
+      if (max_offsets < (uint32_t)h->L + 2) fail(MGARD_ERR_CAPACITY, "level_offsets too short");
+      for (int l = 0; l <= h->L + 1; ++l) level_offsets[l] = h->level_off[l];
+    }
+  });
+}
+
+mgard_status mgard_decompose(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                             mgard_dtype dtype, const void* d_in, void* d_coeff, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_in || !d_coeff) fail(MGARD_ERR_ARG, "null buffer");
+    auto h = get_hierarchy(ndim, shape, coords);
+    const bool f64 = dtype == MGARD_F64;
+    const void* table = device_table(*h, f64, o.st);
+    Workspace& ws = workspace();
+    if (f64) {
+      ws.reserve(decompose_scratch_bytes<double>(*h));
+      decompose<double>(*h, static_cast<const double*>(table), static_cast<const double*>(d_in),
+                        static_cast<double*>(d_coeff), nullptr, ws.base(), o.st);
+    } else {
+      ws.reserve(decompose_scratch_bytes<float>(*h));
+      decompose<float>(*h, static_cast<const float*>(table), static_cast<const float*>(d_in),
+                       static_cast<float*>(d_coeff), nullptr, ws.base(), o.st);
+    }
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_recompose(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                             mgard_dtype dtype, const void* d_coeff, void* d_out, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_coeff || !d_out) fail(MGARD_ERR_ARG, "null buffer");
+    auto h = get_hierarchy(ndim, shape, coords);
+    const bool f64 = dtype == MGARD_F64;
+    const void* table = device_table(*h, f64, o.st);
+    Workspace& ws = workspace();
+    if (f64) {
+      ws.reserve(recompose_scratch_bytes<double>(*h));
+      recompose<double>(*h, static_cast<const double*>(table), static_cast<const double*>(d_coeff), nullptr,
+                        static_cast<double*>(d_out), ws.base(), o.st);
+    } else {
+      ws.reserve(recompose_scratch_bytes<float>(*h));
+      recompose<float>(*h, static_cast<const float*>(table), static_cast<const float*>(d_coeff), nullptr,
+                       static_cast<float*>(d_out), ws.base(), o.st);
+    }
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+// small device copies of level offsets and bin widths for the stage calls
+static void stage_tables(const Hierarchy& h, const double* h_bins, hipStream_t st, uint64_t** d_off,
+                         double** d_bins) {
+  Workspace& ws = workspace();
+  ws.reserve(carve_size<uint64_t>(MAXL + 2) + carve_size<double>(MAXL + 1) + 1024);
+  Carver cv(ws.base());
+  *d_off = cv.take<uint64_t>(MAXL + 2);
+  *d_bins = cv.take<double>(MAXL + 1);
+  MG_HIP(hipMemcpyAsync(*d_off, h.level_off.data(), 8 * (h.L + 2), hipMemcpyHostToDevice, st));
+  MG_HIP(hipMemcpyAsync(*d_bins, h_bins, 8 * (h.L + 1), hipMemcpyHostToDevice, st));
+}
+
+mgard_status mgard_quantize(uint32_t ndim, const uint64_t* shape, mgard_dtype dtype, const void* d_coeff,
+                            const double* h_bins, uint32_t dict_size, uint16_t* d_symbols, int64_t* d_qside,
+                            const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_coeff || !h_bins || !d_symbols || !d_qside) fail(MGARD_ERR_ARG, "null buffer");
+    if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
+    auto h = get_hierarchy(ndim, shape, nullptr);
+    for (int l = 0; l <= h->L; ++l)
+      if (!(h_bins[l] > 0.0) || !std::isfinite(h_bins[l])) fail(MGARD_ERR_ARG, "bin widths must be positive");
+    uint64_t* off;
+    double* bins;
+    stage_tables(*h, h_bins, o.st, &off, &bins);
+    const uint64_t n = h->count(h->L);
+    if (dtype == MGARD_F64)
+      launch_quantize<double>(static_cast<const double*>(d_coeff), n, off, h->L + 1, bins, (int)dict_size / 2,
+                              d_symbols, d_qside, o.st);
+    else
+      launch_quantize<float>(static_cast<const float*>(d_coeff), n, off, h->L + 1, bins, (int)dict_size / 2,
+                             d_symbols, d_qside, o.st);
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_dequantize(uint32_t ndim, const uint64_t* shape, mgard_dtype dtype,
+                              const uint16_t* d_symbols, const int64_t* d_qside, const double* h_bins,
+                              uint32_t dict_size, void* d_coeff, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_coeff || !h_bins || !d_symbols || !d_qside) fail(MGARD_ERR_ARG, "null buffer");
+    if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
+    auto h = get_hierarchy(ndim, shape, nullptr);
+    uint64_t* off;
+    double* bins;
+    stage_tables(*h, h_bins, o.st, &off, &bins);
+    const uint64_t n = h->count(h->L);
+    if (dtype == MGARD_F64)
+      launch_dequantize<double>(d_symbols, d_qside, n, off, h->L + 1, bins, (int)dict_size / 2,
+                                static_cast<double*>(d_coeff), o.st);
+    else
+      launch_dequantize<float>(d_symbols, d_qside, n, off, h->L + 1, bins, (int)dict_size / 2,
+                               static_cast<float*>(d_coeff), o.st);
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_histogram(const uint16_t* d_symbols, uint64_t n, uint32_t dict_size, uint32_t chunk,
+                             uint64_t* d_hist, uint32_t* d_chunk_esc, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_symbols || !d_hist || !d_chunk_esc) fail(MGARD_ERR_ARG, "null buffer");
+    if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
+    if (chunk < 256 || chunk > 8192 || chunk % 256) fail(MGARD_ERR_ARG, "chunk");
+    launch_histogram(d_symbols, n, (int)dict_size, (int)chunk, d_hist, d_chunk_esc, o.st);
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_huffman_codebook(const uint64_t* d_hist, uint32_t dict_size, uint8_t* d_code_len,
+                                    uint64_t* d_codes, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_hist || !d_code_len || !d_codes) fail(MGARD_ERR_ARG, "null buffer");
+    if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
+    launch_codebook(d_hist, (int)dict_size, d_code_len, d_codes, o.st);
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_huffman_encode(const uint16_t* d_symbols, uint64_t n, uint32_t dict_size, uint32_t chunk,
+                                  const uint8_t* d_code_len, const uint64_t* d_codes, uint32_t* d_chunk_bits,
+                                  uint32_t* d_payload, uint64_t payload_capacity, uint64_t* payload_words,
+                                  const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_symbols || !d_code_len || !d_codes || !d_chunk_bits || !d_payload || !payload_words)
+      fail(MGARD_ERR_ARG, "null buffer");
+    if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
+    if (chunk < 256 || chunk > 8192 || chunk % 256) fail(MGARD_ERR_ARG, "chunk");
+    const uint64_t nch = (n + chunk - 1) / chunk;
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<uint64_t>(nch + 1) + 1024);
+    uint64_t* word_off = static_cast<uint64_t*>(ws.base());
+    launch_chunk_bits(d_symbols, n, (int)chunk, d_code_len, d_chunk_bits, o.st);
+    launch_scan_words(d_chunk_bits, nch, word_off, o.st);
+    uint64_t total = 0;
+    MG_HIP(hipMemcpyAsync(&total, word_off + nch, 8, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+    *payload_words = total;
+    if (total > payload_capacity) fail(MGARD_ERR_CAPACITY, "payload capacity");
+    launch_encode(d_symbols, n, (int)chunk, d_code_len, d_codes, word_off, d_payload, nullptr, nullptr, nullptr,
+                  nullptr, o.st);
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_huffman_decode(const uint32_t* d_payload, uint64_t payload_words, const uint32_t* d_chunk_bits,
+                                  uint64_t n, uint32_t dict_size, uint32_t chunk, const uint8_t* d_code_len,
+                                  uint16_t* d_symbols, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_payload || !d_chunk_bits || !d_code_len || !d_symbols) fail(MGARD_ERR_ARG, "null buffer");
+    if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
+    if (chunk < 256 || chunk > 8192 || chunk % 256) fail(MGARD_ERR_ARG, "chunk");
+    const uint64_t nch = (n + chunk - 1) / chunk;
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<uint64_t>(nch + 1) + decode_table_bytes((int)dict_size) + carve_size<uint32_t>(4) +
+               1024);
+    Carver cv(ws.base());
+    uint64_t* word_off = cv.take<uint64_t>(nch + 1);
+    void* tabs = cv.take<char>(decode_table_bytes((int)dict_size));
+    uint32_t* status = cv.take<uint32_t>(4);
+    MG_HIP(hipMemsetAsync(status, 0, 16, o.st));
+    launch_scan_words(d_chunk_bits, nch, word_off, o.st);
+    launch_decode_full(d_payload, payload_words, word_off, d_chunk_bits, n, (int)dict_size, (int)chunk,
+                       d_code_len, d_symbols, nullptr, 0, nullptr, nullptr, tabs, status, o.st);
+    uint32_t hs[4];
+    MG_HIP(hipMemcpyAsync(hs, status, 16, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+    if (hs[0]) fail(MGARD_ERR_FORMAT, "payload does not decode");
+  });
+}
+
+mgard_status mgard_maxabs(mgard_dtype dtype, const void* d_in, uint64_t n, double* h_maxabs,
+                          const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_in || !h_maxabs) fail(MGARD_ERR_ARG, "null pointer");
+    Workspace& ws = workspace();
+    ws.reserve(1024);
+    uint64_t* bits = static_cast<uint64_t*>(ws.base());
+    if (dtype == MGARD_F64)
+      launch_maxabs<double>(static_cast<const double*>(d_in), n, bits, o.st);
+    else
+      launch_maxabs<float>(static_cast<const float*>(d_in), n, bits, o.st);
+    uint64_t hb = 0;
+    MG_HIP(hipMemcpyAsync(&hb, bits, 8, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+    double m;
+    if (dtype == MGARD_F64) {
+      if (hb >= 0x7ff0000000000000ull) fail(MGARD_ERR_NONFINITE, "NaN or infinity");
+      std::memcpy(&m, &hb, 8);
+    } else {
+      if (hb >= 0x7f800000ull) fail(MGARD_ERR_NONFINITE, "NaN or infinity");
+      uint32_t b32 = (uint32_t)hb;
+      float f;
+      std::memcpy(&f, &b32, 4);
+      m = f;
+    }
+    *h_maxabs = m;
+  });
+}
+
+mgard_status mgard_plain_constant(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                                  double* h_S, double* h_K, uint32_t max_levels) {
+  return guard([&] {
+    if (!h_S) fail(MGARD_ERR_ARG, "null pointer");
+    auto h = get_hierarchy(ndim, shape, coords);
+    *h_S = h->S;
+    if (h_K) {
+      if (max_levels < (uint32_t)h->L + 1) fail(MGARD_ERR_CAPACITY, "h_K too short");
+      for (int l = 0; l <= h->L; ++l) h_K[l] = h->K[l];
+    }
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,471 @@
+// Lossless stage: histogram, canonical Huffman codebook, chunked encode and
+// decode (gfx950).
+//
+// Paper Sec. 2: the quantized integers are losslessly encoded before being
+// written.  The code is a canonical Huffman code over a fixed dictionary:
+//   * lengths from the two-queue merge of leaves sorted by (count, symbol),
+//     the leaf queue winning ties (computed in place on the sorted weights,
+//     which gives the same tree as the explicit two queues);
+//   * canonical codes in (length, symbol) order;
+//   * the symbol stream is cut into chunks; each chunk is packed MSB-first into
+//     32-bit words starting word-aligned, so chunks decode independently.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace mg {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int MAXLEN = 64;
+
+// ------------------------------------------------------------------ histogram
+__global__ void __launch_bounds__(TPB) k_histogram(const uint16_t* __restrict__ sym, uint64_t n, int dict,
+                                                   int chunk, uint64_t nch, unsigned long long* __restrict__ hist,
+                                                   uint32_t* __restrict__ chunk_esc) {
+  extern __shared__ uint32_t sh[];
+  __shared__ uint32_t esc;
+  for (int b = threadIdx.x; b < dict; b += TPB) sh[b] = 0;
+  __syncthreads();
+  for (uint64_t k = blockIdx.x; k < nch; k += gridDim.x) {
+    if (threadIdx.x == 0) esc = 0;
+    __syncthreads();
+    const uint64_t beg = k * (uint64_t)chunk;
+    const uint64_t end = min(beg + (uint64_t)chunk, n);
+    uint32_t e = 0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += TPB) {
+      const uint32_t s = sym[i];
+      atomicAdd(&sh[s], 1u);
+      e += (s == 0);
+    }
+    if (e) atomicAdd(&esc, e);
+    __syncthreads();
+    if (threadIdx.x == 0) chunk_esc[k] = esc;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < dict; b += TPB)
+    if (sh[b]) atomicAdd(&hist[b], (unsigned long long)sh[b]);
+}
+
+// ------------------------------------------------------------------ codebook
+// One workgroup.  keys: (count << 16 | symbol), empty bins sort last.
+__global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ hist, int dict,
+                                                   uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
+  extern __shared__ uint64_t keys[];  // dict entries, then dict uint16 symbols
+  uint16_t* syms = reinterpret_cast<uint16_t*>(keys + dict);
+  __shared__ int nleaf;
+  __shared__ uint32_t bl_count[MAXLEN + 1];
+  const int t = threadIdx.x;
+  const int nt = blockDim.x;
+  if (t == 0) nleaf = 0;
+  for (int i = t; i <= MAXLEN; i += nt) bl_count[i] = 0;
+  __syncthreads();
+  for (int s = t; s < dict; s += nt) {
+    const uint64_t c = hist[s];
+    keys[s] = c ? ((c << 16) | (uint64_t)s) : ~0ull;
+    if (c) atomicAdd(&nleaf, 1);
+  }
+  __syncthreads();
+  // bitonic sort, ascending
+  for (int k = 2; k <= dict; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < dict; i += nt) {
+        const int p = i ^ j;
+        if (p > i) {
+          const uint64_t a = keys[i], b = keys[p];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            keys[i] = b;
+            keys[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int s = t; s < dict; s += nt) len_out[s] = 0;
+  __syncthreads();
+  if (t == 0) {
+    const int n = nleaf;
+    uint64_t* A = keys;  // weights, in place
+    for (int i = 0; i < n; ++i) {
+      syms[i] = (uint16_t)(A[i] & 0xffff);
+      A[i] >>= 16;
+    }
+    if (n == 1) {
+      len_out[syms[0]] = 1;
+    } else if (n > 1) {
+      // phase 1: merge; internal node weights replace consumed entries by their parent index
+      int leaf = 0, root = 0;
+      for (int next = 0; next < n - 1; ++next) {
+        if (leaf >= n || (root < next && A[root] < A[leaf])) {
+          A[next] = A[root];
+          A[root++] = (uint64_t)next;
+        } else {
+          A[next] = A[leaf++];
+        }
+        if (leaf >= n || (root < next && A[root] < A[leaf])) {
+          A[next] += A[root];
+          A[root++] = (uint64_t)next;
+        } else {
+          A[next] += A[leaf++];
+        }
+      }
+      // phase 2: internal node depths
+      A[n - 2] = 0;
+      for (int next = n - 3; next >= 0; --next) A[next] = A[A[next]] + 1;
+      // phase 3: leaf depths, deepest for the smallest weights
+      int avbl = 1, used = 0, depth = 0, rt = n - 2, nx = n - 1;
+      while (avbl > 0) {
+        while (rt >= 0 && (int)A[rt] == depth) {
+          ++used;
+          --rt;
+        }
+        while (avbl > used) {
+          A[nx--] = (uint64_t)depth;
+          --avbl;
+        }
+        avbl = 2 * used;
+        ++depth;
+        used = 0;
+      }
+      for (int i = 0; i < n; ++i) len_out[syms[i]] = (uint8_t)A[i];
+    }
+    // canonical codes: first code per length, then consecutive by symbol
+    for (int s = 0; s < dict; ++s) bl_count[len_out[s]]++;
+    uint64_t first[MAXLEN + 1];
+    uint64_t code = 0;
+    bl_count[0] = 0;
+    first[0] = 0;
+    for (int b = 1; b <= MAXLEN; ++b) {
+      code = (code + bl_count[b - 1]) << 1;
+      first[b] = code;
+    }
+    for (int s = 0; s < dict; ++s) {
+      const int L = len_out[s];
+      codes[s] = L ? first[L]++ : 0ull;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ chunk sizes
+__global__ void __launch_bounds__(TPB) k_chunk_bits(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+                                                    uint64_t nch, const uint8_t* __restrict__ len,
+                                                    uint32_t* __restrict__ chunk_bits) {
+  __shared__ uint32_t acc;
+  for (uint64_t k = blockIdx.x; k < nch; k += gridDim.x) {
+    if (threadIdx.x == 0) acc = 0;
+    __syncthreads();
+    const uint64_t beg = k * (uint64_t)chunk;
+    const uint64_t end = min(beg + (uint64_t)chunk, n);
+    uint32_t b = 0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += TPB) b += len[sym[i]];
+    atomicAdd(&acc, b);
+    __syncthreads();
+    if (threadIdx.x == 0) chunk_bits[k] = acc;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ scans
+// Exclusive scan over n values (words of chunk bit counts when WORDS), one
+// workgroup; off has n+1 entries, off[n] the total.
+template <bool WORDS>
+__global__ void __launch_bounds__(1024) k_scan(const uint32_t* __restrict__ v, uint64_t n,
+                                               uint64_t* __restrict__ off) {
+  __shared__ uint64_t part[1024];
+  const int t = threadIdx.x;
+  const uint64_t per = (n + 1023) / 1024;
+  const uint64_t beg = min((uint64_t)t * per, n), end = min(beg + per, n);
+  uint64_t s = 0;
+  for (uint64_t i = beg; i < end; ++i) s += WORDS ? (uint64_t)((v[i] + 31u) >> 5) : (uint64_t)v[i];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    uint64_t add = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  uint64_t run = part[t] - s;
+  for (uint64_t i = beg; i < end; ++i) {
+    off[i] = run;
+    run += WORDS ? (uint64_t)((v[i] + 31u) >> 5) : (uint64_t)v[i];
+  }
+  if (t == 1023) off[n] = part[1023];
+}
+
+// ------------------------------------------------------------------ encode
+__device__ inline void put_code(uint32_t* words, uint64_t b, int L, uint64_t code) {
+  // code occupies chunk bits [b, b+L), MSB-first
+  const uint64_t e = b + (uint64_t)L;
+  for (uint64_t w = b >> 5; (w << 5) < e; ++w) {
+    const uint64_t ws = w << 5, we = ws + 32;
+    const uint64_t s0 = b > ws ? b : ws;
+    const uint64_t s1 = e < we ? e : we;
+    const int nb = (int)(s1 - s0);
+    uint64_t part = code >> (e - s1);
+    part &= (nb >= 64) ? ~0ull : ((1ull << nb) - 1ull);
+    atomicOr(&words[w], (uint32_t)(part << (we - s1)));
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+                                                uint64_t nch, const uint8_t* __restrict__ len,
+                                                const uint64_t* __restrict__ codes,
+                                                const uint64_t* __restrict__ word_off,
+                                                uint32_t* __restrict__ payload,
+                                                const uint64_t* __restrict__ esc_off,
+                                                const int64_t* __restrict__ qside, char* obase,
+                                                const uint64_t* __restrict__ ooff) {
+  extern __shared__ uint32_t words[];
+  int64_t* outliers = obase ? reinterpret_cast<int64_t*>(obase + *ooff) : nullptr;  // chunk * MAXLEN / 32 words
+  __shared__ uint64_t scan[TPB];
+  __shared__ uint32_t escan[TPB];
+  const int t = threadIdx.x;
+  const int per = chunk / TPB;
+  for (uint64_t k = blockIdx.x; k < nch; k += gridDim.x) {
+    const uint64_t beg = k * (uint64_t)chunk;
+    const uint64_t w0 = word_off[k], nw = word_off[k + 1] - w0;
+    for (uint64_t i = t; i < nw; i += TPB) words[i] = 0;
+    const uint64_t mine = beg + (uint64_t)t * per;
+    uint64_t bits = 0;
+    uint32_t esc = 0;
+    for (int j = 0; j < per; ++j) {
+      const uint64_t i = mine + j;
+      if (i < n) {
+        const uint16_t s = sym[i];
+        bits += len[s];
+        esc += (s == 0);
+      }
+    }
+    scan[t] = bits;
+    escan[t] = esc;
+    __syncthreads();
+    for (int d = 1; d < TPB; d <<= 1) {
+      uint64_t a = t >= d ? scan[t - d] : 0;
+      uint32_t b = t >= d ? escan[t - d] : 0;
+      __syncthreads();
+      scan[t] += a;
+      escan[t] += b;
+      __syncthreads();
+    }
+    uint64_t pos = scan[t] - bits;
+    uint64_t eo = (outliers ? esc_off[k] : 0) + (escan[t] - esc);
+    for (int j = 0; j < per; ++j) {
+      const uint64_t i = mine + j;
+      if (i < n) {
+        const uint16_t s = sym[i];
+        const int L = len[s];
+        put_code(words, pos, L, codes[s]);
+        pos += L;
+        if (s == 0 && outliers) outliers[eo++] = qside[i];
+      }
+    }
+    __syncthreads();
+    for (uint64_t i = t; i < nw; i += TPB) payload[w0 + i] = words[i];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ decode
+// tables: count[65] u32, first[65] u64, offset[65] u32, then dict uint16 symbols
+struct DecTables {
+  uint32_t count[MAXLEN + 1];
+  uint32_t offset[MAXLEN + 1];
+  uint64_t first[MAXLEN + 1];
+  uint32_t minlen, maxlen, bad;
+};
+
+__global__ void k_decode_tables(const uint8_t* __restrict__ len, int dict, DecTables* tab,
+                                uint16_t* __restrict__ sorted) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t cnt[MAXLEN + 1];
+  for (int b = 0; b <= MAXLEN; ++b) cnt[b] = 0;
+  uint32_t bad = 0;
+  for (int s = 0; s < dict; ++s) {
+    if (len[s] > MAXLEN) bad = 1;
+    else cnt[len[s]]++;
+  }
+  cnt[0] = 0;
+  uint64_t code = 0;
+  uint32_t off = 0, minlen = 0, maxlen = 0;
+  for (int b = 1; b <= MAXLEN; ++b) {
+    code = (code + cnt[b - 1]) << 1;
+    tab->first[b] = code;
+    tab->count[b] = cnt[b];
+    tab->offset[b] = off;
+    off += cnt[b];
+    if (cnt[b]) {
+      if (!minlen) minlen = b;
+      maxlen = b;
+    }
+  }
+  tab->first[0] = 0;
+  tab->count[0] = 0;
+  tab->offset[0] = 0;
+  // Kraft check: a canonical prefix code must not overflow its last length
+  if (maxlen && (tab->first[maxlen] + cnt[maxlen]) > (1ull << maxlen) && maxlen < 64) bad = 1;
+  uint32_t fill[MAXLEN + 1];
+  for (int b = 0; b <= MAXLEN; ++b) fill[b] = tab->offset[b];
+  for (int s = 0; s < dict; ++s)
+    if (len[s] && len[s] <= MAXLEN) sorted[fill[len[s]]++] = (uint16_t)s;
+  tab->minlen = minlen;
+  tab->maxlen = maxlen;
+  tab->bad = bad;
+}
+
+// One thread per chunk.  status[0] is set to 1 on malformed input.
+__global__ void __launch_bounds__(TPB) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
+                                                const uint64_t* __restrict__ word_off,
+                                                const uint32_t* __restrict__ chunk_bits, uint64_t n, int chunk,
+                                                uint64_t nch, const DecTables* __restrict__ tab,
+                                                const uint16_t* __restrict__ sorted, uint16_t* __restrict__ sym,
+                                                const uint64_t* __restrict__ esc_off, uint64_t n_out,
+                                                const int64_t* __restrict__ outliers, int64_t* __restrict__ qside,
+                                                uint32_t* __restrict__ status) {
+  __shared__ uint32_t cnt[MAXLEN + 1], offs[MAXLEN + 1];
+  __shared__ uint64_t first[MAXLEN + 1];
+  for (int b = threadIdx.x; b <= MAXLEN; b += blockDim.x) {
+    cnt[b] = tab->count[b];
+    offs[b] = tab->offset[b];
+    first[b] = tab->first[b];
+  }
+  __syncthreads();
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nch) return;
+  if (tab->bad || tab->maxlen == 0) {
+    atomicOr(status, 1u);
+    return;
+  }
+  const uint64_t w0 = word_off[k], w1 = word_off[k + 1];
+  const uint64_t nbits = chunk_bits[k];
+  if (w1 > payload_words || w1 < w0) {
+    atomicOr(status, 1u);
+    return;
+  }
+  const uint64_t beg = k * (uint64_t)chunk;
+  const uint64_t cntk = min((uint64_t)chunk, n - beg);
+  const int minlen = (int)tab->minlen, maxlen = (int)tab->maxlen;
+  const uint32_t* src = payload + w0;
+  uint64_t buf = 0;  // left-aligned bit buffer
+  int have = 0;
+  uint64_t next_word = 0, consumed = 0;
+  uint64_t eo = esc_off[k];
+  for (uint64_t i = 0; i < cntk; ++i) {
+    uint64_t code = 0;
+    int L = 0;
+    int s = -1;
+    while (L < maxlen) {
+      if (have == 0) {
+        if (next_word >= w1 - w0) break;
+        buf = (uint64_t)src[next_word++] << 32;
+        have = 32;
+      }
+      code = (code << 1) | (buf >> 63);
+      buf <<= 1;
+      --have;
+      ++consumed;
+      ++L;
+      if (L >= minlen) {
+        const uint64_t d = code - first[L];
+        if (code >= first[L] && d < cnt[L]) {
+          s = sorted[offs[L] + (uint32_t)d];
+          break;
+        }
+      }
+    }
+    if (s < 0 || consumed > nbits) {
+      atomicOr(status, 1u);
+      return;
+    }
+    sym[beg + i] = (uint16_t)s;
+    if (s == 0 && qside) {
+      if (eo >= n_out) {
+        atomicOr(status, 1u);
+        return;
+      }
+      qside[beg + i] = outliers[eo++];
+    }
+  }
+  if (consumed != nbits) atomicOr(status, 1u);
+}
+
+inline unsigned blocks_for(uint64_t nch, unsigned cap) {
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nch, cap));
+}
+
+}  // namespace
+
+void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
+                      uint32_t* chunk_esc, hipStream_t st) {
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  MG_HIP(hipMemsetAsync(hist, 0, sizeof(uint64_t) * dict, st));
+  if (nch == 0) return;
+  hipLaunchKernelGGL(k_histogram, dim3(blocks_for(nch, 2048)), dim3(TPB), dict * sizeof(uint32_t), st, sym, n,
+                     dict, chunk, nch, (unsigned long long*)hist, chunk_esc);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes, hipStream_t st) {
+  const size_t shmem = (size_t)dict * (sizeof(uint64_t) + sizeof(uint16_t));
+  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), shmem, st, hist, dict, len, codes);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_chunk_bits(const uint16_t* sym, uint64_t n, int chunk, const uint8_t* len,
+                       uint32_t* chunk_bits, hipStream_t st) {
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  if (nch == 0) return;
+  hipLaunchKernelGGL(k_chunk_bits, dim3(blocks_for(nch, 8192)), dim3(TPB), 0, st, sym, n, chunk, nch, len,
+                     chunk_bits);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_scan_words(const uint32_t* chunk_bits, uint64_t nch, uint64_t* word_off, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan<true>, dim3(1), dim3(1024), 0, st, chunk_bits, nch, word_off);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_scan_u32(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan<false>, dim3(1), dim3(1024), 0, st, v, n, off);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_encode(const uint16_t* sym, uint64_t n, int chunk, const uint8_t* len,
+                   const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
+                   const uint64_t* esc_off, const int64_t* qside, char* obase,
+                   const uint64_t* ooff, hipStream_t st) {
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  if (nch == 0) return;
+  const size_t shmem = (size_t)chunk * MAXLEN / 32 * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_encode, dim3(blocks_for(nch, 4096)), dim3(TPB), shmem, st, sym, n, chunk, nch, len,
+                     codes, word_off, payload, esc_off, qside, obase, ooff);
+  MG_HIP(hipGetLastError());
+}
+
+uint64_t decode_table_bytes(int dict) {
+  return carve_size<DecTables>(1) + carve_size<uint16_t>((uint64_t)dict) + carve_size<uint32_t>(4);
+}
+
+// Full decode entry used by the API: builds the tables, then decodes.
+void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const uint64_t* word_off,
+                        const uint32_t* chunk_bits, uint64_t n, int dict, int chunk,
+                        const uint8_t* len, uint16_t* sym, const uint64_t* esc_off, uint64_t n_out,
+                        const int64_t* outliers, int64_t* qside, void* table_scratch,
+                        uint32_t* d_status, hipStream_t st) {
+  Carver cv(table_scratch);
+  DecTables* tab = cv.take<DecTables>(1);
+  uint16_t* sorted = cv.take<uint16_t>((uint64_t)dict);
+  hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(64), 0, st, len, dict, tab, sorted);
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  if (nch) {
+    const unsigned blocks = (unsigned)((nch + 63) / 64);
+    hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(64), 0, st, payload, payload_words, word_off, chunk_bits, n,
+                       chunk, nch, tab, sorted, sym, esc_off, n_out, outliers, qside, d_status);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+}  // namespace mg

@@ -1,0 +1,190 @@
+// Internal declarations shared by the host orchestration and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mgard_hip.h"
+
+namespace mg {
+
+constexpr int MAXD = 4;    // dimensions handled by the kernels (leading slots padded)
+constexpr int MAXL = 39;   // levels that fit in mgard_info::bin_width
+
+struct Failure {
+  mgard_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(mgard_status code, const std::string& msg);
+
+#define MG_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) ::mg::fail(MGARD_ERR_DEVICE, std::string(#call) + ": " +        \
+                                                        hipGetErrorString(e_));           \
+  } while (0)
+
+// ----------------------------------------------------------------- hierarchy
+// Per level l (1..L) and decomposed dimension d, the FP64 operator constants
+// that take grid l to grid l-1 along d (see hierarchy.cpp for the formulas).
+struct DimOps {
+  int nf = 0, nc = 0;
+  std::vector<double> wl, wr;      // interpolation weights, indexed by fine index (0 at coarse)
+  std::vector<double> ma, mb, mc;  // fine mass matrix bands
+  std::vector<double> rl, rr;      // restriction weights per coarse node
+  std::vector<double> ta, tr, tcp; // Thomas factors of the coarse mass matrix
+  double norm_inf = 0.0;           // || T^-1 P^T M ||_inf
+};
+
+// Offsets (in elements) of one (level, dim)'s arrays inside the device table.
+struct DevDim {
+  uint64_t wl, wr, ma, mb, mc, rl, rr, ta, tr, tcp;
+};
+
+struct Hierarchy {
+  int D = 0;                          // user dimensions
+  std::array<int64_t, MAXD> shape{};  // slot layout: user dim d sits in slot d + (MAXD - D)
+  std::array<bool, MAXD> active{};    // decomposed slots
+  int L = 0;
+  std::vector<std::array<int64_t, MAXD>> sizes;     // sizes[l][slot], l = 0..L
+  std::vector<std::array<DimOps, MAXD>> ops;        // ops[l][slot], l = 1..L
+  std::vector<std::array<DevDim, MAXD>> devoff;     // device-table offsets
+  std::vector<double> K;                            // K[l], K[0] = 0
+  double S = 1.0;                                   // 1 + sum_l (1 + K_l)
+  std::vector<uint64_t> level_count;                // stream entries per level
+  std::vector<uint64_t> level_off;                  // L + 2 entries
+  std::vector<double> table;                        // concatenated FP64 constants
+  void* dev_table[2] = {nullptr, nullptr};          // table cast to float / double
+  int dev_id[2] = {-1, -1};
+  uint64_t count(int l) const {
+    uint64_t n = 1;
+    for (int s = 0; s < MAXD; ++s) n *= (uint64_t)sizes[l][s];
+    return n;
+  }
+  ~Hierarchy();
+};
+
+// Builds (or returns a cached) hierarchy.  Throws Failure on bad arguments.
+std::shared_ptr<Hierarchy> get_hierarchy(uint32_t ndim, const uint64_t* shape,
+                                         const double* const* coords);
+// Device copy of the constants in precision T (uploaded on first use).
+const void* device_table(Hierarchy& h, bool f64, hipStream_t stream);
+
+// ----------------------------------------------------------------- workspace
+// One growable device allocation per device, carved into aligned pieces.
+class Workspace {
+ public:
+  void reserve(uint64_t bytes);
+  void* base() const { return base_; }
+  uint64_t size() const { return size_; }
+  void release();
+
+ private:
+  void* base_ = nullptr;
+  uint64_t size_ = 0;
+};
+Workspace& workspace();
+
+struct Carver {
+  char* p;
+  uint64_t used = 0;
+  explicit Carver(void* base) : p(static_cast<char*>(base)) {}
+  template <typename X>
+  X* take(uint64_t n) {
+    uint64_t off = (used + 255) & ~uint64_t(255);
+    used = off + n * sizeof(X);
+    return reinterpret_cast<X*>(p + off);
+  }
+};
+template <typename X>
+inline uint64_t carve_size(uint64_t n) {
+  return ((n * sizeof(X)) + 255) & ~uint64_t(255);
+}
+
+// --------------------------------------------------------- kernel launchers
+// Geometry of one level as the kernels see it (slot layout, 4 slots).
+template <typename T>
+struct LevelGeom {
+  int32_t nf[MAXD], nc[MAXD], act[MAXD];
+  int32_t pad_slots;                 // MAXD - D
+  const T* wl[MAXD];
+  const T* wr[MAXD];
+  uint64_t level_off;                // stream offset of this level
+  uint64_t sub_off[16];              // sub-grid offsets inside the level (by user mask)
+  uint64_t sub_stride[16][MAXD];     // C-order strides of each sub-grid (slot layout)
+};
+
+template <typename T>
+struct DimConsts {
+  const T *wl, *wr, *ma, *mb, *mc, *rl, *rr, *ta, *tr, *tcp;
+};
+
+template <typename T>
+LevelGeom<T> level_geom(const Hierarchy& h, int l, const T* table);
+template <typename T>
+DimConsts<T> dim_consts(const Hierarchy& h, int l, int slot, const T* table);
+
+// Decomposition / recomposition of a whole hierarchy (transform.hip).
+// mode 0: float coefficient stream; mode 1: quantized symbols + qside.
+struct QuantOut {
+  uint16_t* sym = nullptr;
+  int64_t* qside = nullptr;
+  const double* bins = nullptr;  // device, L+1 entries
+  int R = 0;
+};
+template <typename T>
+uint64_t decompose_scratch_bytes(const Hierarchy& h);
+template <typename T>
+void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, const QuantOut* q,
+               void* scratch, hipStream_t st);
+template <typename T>
+uint64_t recompose_scratch_bytes(const Hierarchy& h);
+template <typename T>
+void recompose(const Hierarchy& h, const T* table, const T* d_stream, const QuantOut* q, T* d_out,
+               void* scratch, hipStream_t st);
+
+// Quantization helpers (quant.hip).
+template <typename T>
+void launch_maxabs(const T* d, uint64_t n, uint64_t* d_bits, hipStream_t st);
+struct BinArgs {
+  double K[MAXL + 1];
+  double counts[MAXL + 1];
+};
+void launch_bins(int f64, const uint64_t* d_maxbits, double tol, int rel, double S, int L,
+                 int alloc, const BinArgs& a, double* d_bins, double* d_scalars, hipStream_t st);
+template <typename T>
+void launch_quantize(const T* c, uint64_t n, const uint64_t* d_level_off, int nlev,
+                     const double* d_bins, int R, uint16_t* sym, int64_t* qside, hipStream_t st);
+template <typename T>
+void launch_dequantize(const uint16_t* sym, const int64_t* qside, uint64_t n,
+                       const uint64_t* d_level_off, int nlev, const double* d_bins, int R, T* c,
+                       hipStream_t st);
+
+// Huffman (huffman.hip).
+void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
+                      uint32_t* chunk_esc, hipStream_t st);
+void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes,
+                     hipStream_t st);
+void launch_chunk_bits(const uint16_t* sym, uint64_t n, int chunk, const uint8_t* len,
+                       uint32_t* chunk_bits, hipStream_t st);
+// exclusive scan of per-chunk words (ceil(bits/32)) -> offsets (n+1 entries, last = total)
+void launch_scan_words(const uint32_t* chunk_bits, uint64_t nch, uint64_t* word_off,
+                       hipStream_t st);
+void launch_scan_u32(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st);
+void launch_encode(const uint16_t* sym, uint64_t n, int chunk, const uint8_t* len,
+                   const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
+                   const uint64_t* esc_off, const int64_t* qside, char* obase,
+                   const uint64_t* ooff, hipStream_t st);
+uint64_t decode_table_bytes(int dict);
+void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const uint64_t* word_off,
+                        const uint32_t* chunk_bits, uint64_t n, int dict, int chunk,
+                        const uint8_t* len, uint16_t* sym, const uint64_t* esc_off, uint64_t n_out,
+                        const int64_t* outliers, int64_t* qside, void* table_scratch,
+                        uint32_t* d_status, hipStream_t st);
+
+}  // namespace mg

@@ -1,0 +1,535 @@
+// Multilevel decomposition and recomposition kernels (gfx950).
+//
+// One level of the decomposition (paper Sec. 2, recursive multilevel
+// decomposition; P1 finite-element reading):
+//   1. coefficients c = u - Pi u at the new nodes, Pi the multilinear
+//      interpolant from the coarse nodes, evaluated as nested 1D
+//      interpolations with the highest dimension innermost, each step
+//      (wl*a) + (wr*b) rounded to T;
+//   2. load vector f = (P^T M) cbar along dimensions D-1 .. 0 (mass stencil
+//      ((a*g[i-1] + b*g[i]) + c*g[i+1]), restriction ((rl*g[c-1] + g[c]) +
+//      rr*g[c+1]));
+//   3. Thomas solves with the coarse mass matrix along dimensions 0 .. D-1;
+//   4. u_{l-1} = u_l|coarse + z.
+// Recomposition inverts it: z from c, u_l|coarse = u_{l-1} - z,
+// u_l = c + Pi(u_l|coarse) at new nodes.
+//
+// The order of every rounding is fixed above so that results are
+// reproducible; the library is built with floating-point contraction off.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace mg {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned grid_for(uint64_t n, unsigned cap = 1u << 20) {
+  uint64_t g = (n + TPB - 1) / TPB;
+  if (g < 1) g = 1;
+  return (unsigned)std::min<uint64_t>(g, cap);
+}
+
+// slot coordinates of a fine-grid linear index
+struct Coord {
+  int32_t i[MAXD];
+};
+
+template <typename T>
+__device__ inline Coord unflatten(uint64_t p, const LevelGeom<T>& g) {
+  Coord c;
+#pragma unroll
+  for (int s = MAXD - 1; s >= 0; --s) {
+    uint64_t n = (uint64_t)g.nf[s];
+    c.i[s] = (int32_t)(p % n);
+    p /= n;
+  }
+  return c;
+}
+
+// mask of slots whose index is a new node of this level
+template <typename T>
+__device__ inline int new_mask(const Coord& c, const LevelGeom<T>& g) {
+  int m = 0;
+#pragma unroll
+  for (int s = 0; s < MAXD; ++s)
+    if (g.act[s] && (c.i[s] & 1) && c.i[s] < g.nf[s] - 1) m |= 1 << s;
+  return m;
+}
+
+template <typename T>
+__device__ inline int coarse_idx(int i, int s, const LevelGeom<T>& g) {
+  return g.act[s] ? ((i + 1) >> 1) : i;
+}
+
+// stream position of a new node
+template <typename T>
+__device__ inline uint64_t stream_pos(const Coord& c, int mslot, const LevelGeom<T>& g) {
+  const int m = mslot >> g.pad_slots;
+  uint64_t pos = g.level_off + g.sub_off[m];
+#pragma unroll
+  for (int s = 0; s < MAXD; ++s) {
+    int idx = ((mslot >> s) & 1) ? (c.i[s] >> 1) : coarse_idx(c.i[s], s, g);
+    pos += (uint64_t)idx * g.sub_stride[m][s];
+  }
+  return pos;
+}
+
+template <class X>
+__device__ inline X sel4(const X* a, int s) {
+  return s == 0 ? a[0] : (s == 1 ? a[1] : (s == 2 ? a[2] : a[3]));
+}
+
+// Pi at a new node.  FINE: corners read from the fine grid `src` (coarse
+// positions of grid l); otherwise from the dense coarse grid `src` (grid l-1).
+template <typename T, bool FINE>
+__device__ inline T interpolate(const T* __restrict__ src, const Coord& c, int mslot,
+                                const LevelGeom<T>& g) {
+  uint64_t st[MAXD];  // strides of the grid we read
+  uint64_t acc = 1;
+#pragma unroll
+  for (int s = MAXD - 1; s >= 0; --s) {
+    st[s] = acc;
+    acc *= (uint64_t)(FINE ? g.nf[s] : g.nc[s]);
+  }
+  uint64_t base = 0;
+#pragma unroll
+  for (int s = 0; s < MAXD; ++s) {
+    int id;
+    if ((mslot >> s) & 1)
+      id = FINE ? c.i[s] - 1 : (c.i[s] >> 1);
+    else
+      id = FINE ? c.i[s] : coarse_idx(c.i[s], s, g);
+    base += (uint64_t)id * st[s];
+  }
+  // odd slots in increasing order: their corner step and weights
+  uint64_t ost[MAXD];
+  T owl[MAXD], owr[MAXD];
+  int mm = mslot;
+#pragma unroll
+  for (int j = 0; j < MAXD; ++j) {
+    const int s = mm ? __builtin_ctz(mm) : 0;
+    const bool live = mm != 0;
+    mm &= mm - 1;
+    ost[j] = (uint64_t)(FINE ? 2 : 1) * sel4(st, s);
+    const int is = sel4(c.i, s);
+    owl[j] = live ? sel4(g.wl, s)[is] : T(0);
+    owr[j] = live ? sel4(g.wr, s)[is] : T(0);
+  }
+  const int k = __builtin_popcount(mslot);
+  T v[16];
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) {
+    if (cc < (1 << k)) {
+      uint64_t off = base;
+#pragma unroll
+      for (int j = 0; j < MAXD; ++j)
+        if ((cc >> j) & 1) off += ost[j];
+      v[cc] = src[off];
+    }
+  }
+  // reduce the highest odd dimension first (innermost interpolation)
+#pragma unroll
+  for (int j = MAXD - 1; j >= 0; --j) {
+    if (j < k) {
+      const int half = 1 << j;
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+        if (cc < half) v[cc] = owl[j] * v[cc] + owr[j] * v[cc + half];
+    }
+  }
+  return v[0];
+}
+
+template <typename T>
+__device__ inline void quantize_one(T c, double inv_b, int R, uint64_t pos, uint16_t* __restrict__ sym,
+                                    int64_t* __restrict__ qside) {
+  double y = (double)c * inv_b;
+  double a = floor(fabs(y) + 0.5);
+  int64_t q = (int64_t)(y < 0.0 ? -a : a);
+  if (q > -R && q < R) {
+    sym[pos] = (uint16_t)(q + R);
+  } else {
+    sym[pos] = 0;
+    qside[pos] = q;
+  }
+}
+
+template <typename T>
+__device__ inline T dequantize_one(const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside,
+                                   uint64_t pos, double b, int R) {
+  uint16_t s = sym[pos];
+  int64_t q = s ? (int64_t)s - R : qside[pos];
+  return static_cast<T>((double)q * b);
+}
+
+// Step 1 (+ fused quantization when MODE == 1).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPB) k_coeff(const T* __restrict__ u, T* __restrict__ cbar,
+                                               T* __restrict__ ucoarse, T* __restrict__ cstream,
+                                               uint16_t* __restrict__ sym, int64_t* __restrict__ qside,
+                                               const double* __restrict__ bins, int level, int R,
+                                               LevelGeom<T> g, uint64_t nfine) {
+  double inv_b = 0.0;
+  if (MODE == 1) inv_b = 1.0 / bins[level];
+  for (uint64_t p = (uint64_t)blockIdx.x * TPB + threadIdx.x; p < nfine;
+       p += (uint64_t)gridDim.x * TPB) {
+    Coord c = unflatten(p, g);
+    const int m = new_mask(c, g);
+    const T up = u[p];
+    if (m == 0) {
+      uint64_t q = 0;
+#pragma unroll
+      for (int s = 0; s < MAXD; ++s) q = q * (uint64_t)g.nc[s] + (uint64_t)coarse_idx(c.i[s], s, g);
+      ucoarse[q] = up;
+      cbar[p] = T(0);
+      continue;
+    }
+    const T cv = up - interpolate<T, true>(u, c, m, g);
+    cbar[p] = cv;
+    const uint64_t pos = stream_pos(c, m, g);
+    if (MODE == 0)
+      cstream[pos] = cv;
+    else
+      quantize_one(cv, inv_b, R, pos, sym, qside);
+  }
+}
+
+// Step 2 along one dimension: (outer, nf, inner) -> (outer, nc, inner).
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_mass_restrict(const T* __restrict__ in, T* __restrict__ out,
+                                                       uint64_t outer, int nf, int nc, uint64_t inner,
+                                                       DimConsts<T> w) {
+  const uint64_t total = outer * (uint64_t)nc * inner;
+  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < total;
+       t += (uint64_t)gridDim.x * TPB) {
+    const uint64_t k = t % inner;
+    const uint64_t r = t / inner;
+    const int j = (int)(r % (uint64_t)nc);
+    const uint64_t o = r / (uint64_t)nc;
+    const T* line = in + o * (uint64_t)nf * inner + k;
+    auto G = [&](int i) { return line[(uint64_t)i * inner]; };
+    auto Mg = [&](int i) {
+      T s = w.mb[i] * G(i);
+      if (i > 0) s = w.ma[i] * G(i - 1) + s;
+      if (i < nf - 1) s = s + w.mc[i] * G(i + 1);
+      return s;
+    };
+    const int c = (j == nc - 1) ? nf - 1 : 2 * j;
+    T f = Mg(c);
+    if (c >= 2 && !(c & 1)) f = w.rl[j] * Mg(c - 1) + f;
+    if (!(c & 1) && c < nf - 2) f = f + w.rr[j] * Mg(c + 1);
+    out[(o * (uint64_t)nc + j) * inner + k] = f;
+  }
+}
+
+// Step 3 along one dimension, in place, one thread per line.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t outer, int n,
+                                                uint64_t inner, DimConsts<T> w) {
+  const uint64_t lines = outer * inner;
+  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < lines;
+       t += (uint64_t)gridDim.x * TPB) {
+    const uint64_t k = t % inner;
+    const uint64_t o = t / inner;
+    T* line = data + o * (uint64_t)n * inner + k;
+    T prev = line[0] * w.tr[0];
+    line[0] = prev;
+    for (int i = 1; i < n; ++i) {
+      prev = (line[(uint64_t)i * inner] - w.ta[i] * prev) * w.tr[i];
+      line[(uint64_t)i * inner] = prev;
+    }
+    T x = prev;
+    for (int i = n - 2; i >= 0; --i) {
+      x = line[(uint64_t)i * inner] - w.tcp[i] * x;
+      line[(uint64_t)i * inner] = x;
+    }
+  }
+}
+
+template <typename T, bool ADD>
+__global__ void __launch_bounds__(TPB) k_axpy(T* __restrict__ dst, const T* __restrict__ a,
+                                              const T* __restrict__ b, uint64_t n) {
+  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < n; t += (uint64_t)gridDim.x * TPB)
+    dst[t] = ADD ? a[t] + b[t] : a[t] - b[t];
+}
+
+// coarsest grid <-> stream[0, n0)
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPB) k_coarsest_out(const T* __restrict__ src, T* __restrict__ cstream,
+                                                      uint16_t* __restrict__ sym,
+                                                      int64_t* __restrict__ qside,
+                                                      const double* __restrict__ bins, int R, uint64_t n) {
+  double inv_b = 0.0;
+  if (MODE == 1) inv_b = 1.0 / bins[0];
+  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < n; t += (uint64_t)gridDim.x * TPB) {
+    if (MODE == 0)
+      cstream[t] = src[t];
+    else
+      quantize_one(src[t], inv_b, R, t, sym, qside);
+  }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPB) k_coarsest_in(T* __restrict__ dst, const T* __restrict__ cstream,
+                                                     const uint16_t* __restrict__ sym,
+                                                     const int64_t* __restrict__ qside,
+                                                     const double* __restrict__ bins, int R, uint64_t n) {
+  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < n; t += (uint64_t)gridDim.x * TPB)
+    dst[t] = MODE == 0 ? cstream[t] : dequantize_one<T>(sym, qside, t, bins[0], R);
+}
+
+// Recomposition: scatter the level's coefficients to the fine grid (zeros at coarse nodes).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPB) k_scatter(T* __restrict__ cbar, const T* __restrict__ cstream,
+                                                 const uint16_t* __restrict__ sym,
+                                                 const int64_t* __restrict__ qside,
+                                                 const double* __restrict__ bins, int level, int R,
+                                                 LevelGeom<T> g, uint64_t nfine) {
+  double b = MODE == 1 ? bins[level] : 0.0;
+  for (uint64_t p = (uint64_t)blockIdx.x * TPB + threadIdx.x; p < nfine;
+       p += (uint64_t)gridDim.x * TPB) {
+    Coord c = unflatten(p, g);
+    const int m = new_mask(c, g);
+    if (m == 0) {
+      cbar[p] = T(0);
+      continue;
+    }
+    const uint64_t pos = stream_pos(c, m, g);
+    cbar[p] = MODE == 0 ? cstream[pos] : dequantize_one<T>(sym, qside, pos, b, R);
+  }
+}
+
+// Recomposition: u_l = c + Pi(uc) at new nodes, uc at coarse nodes.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_interp_add(T* __restrict__ out, const T* __restrict__ cbar,
+                                                    const T* __restrict__ uc, LevelGeom<T> g,
+                                                    uint64_t nfine) {
+  for (uint64_t p = (uint64_t)blockIdx.x * TPB + threadIdx.x; p < nfine;
+       p += (uint64_t)gridDim.x * TPB) {
+    Coord c = unflatten(p, g);
+    const int m = new_mask(c, g);
+    if (m == 0) {
+      uint64_t q = 0;
+#pragma unroll
+      for (int s = 0; s < MAXD; ++s) q = q * (uint64_t)g.nc[s] + (uint64_t)coarse_idx(c.i[s], s, g);
+      out[p] = uc[q];
+      continue;
+    }
+    out[p] = cbar[p] + interpolate<T, false>(uc, c, m, g);
+  }
+}
+
+// Load vector + solves on cbar (grid l) -> z on grid l-1, written to `zout`.
+// Uses two ping-pong buffers of at least count(l)/2 ... count(l) elements.
+template <typename T>
+void correction(const Hierarchy& h, int l, const T* table, const T* cbar, T* bufA, T* bufB,
+                T** zout, hipStream_t st) {
+  std::array<int64_t, MAXD> shp = h.sizes[l];
+  const T* src = cbar;
+  T* dst = bufA;
+  for (int s = MAXD - 1; s >= 0; --s) {
+    if (!h.active[s]) continue;
+    uint64_t outer = 1, inner = 1;
+    for (int q = 0; q < s; ++q) outer *= (uint64_t)shp[q];
+    for (int q = s + 1; q < MAXD; ++q) inner *= (uint64_t)shp[q];
+    const int nf = (int)shp[s], nc = (int)h.sizes[l - 1][s];
+    const uint64_t total = outer * (uint64_t)nc * inner;
+    hipLaunchKernelGGL(k_mass_restrict<T>, dim3(grid_for(total)), dim3(TPB), 0, st, src, dst, outer, nf,
+                       nc, inner, dim_consts<T>(h, l, s, table));
+    shp[s] = nc;
+    src = dst;
+    dst = (dst == bufA) ? bufB : bufA;
+  }
+  T* z = const_cast<T*>(src);
+  for (int s = 0; s < MAXD; ++s) {
+    if (!h.active[s]) continue;
+    uint64_t outer = 1, inner = 1;
+    for (int q = 0; q < s; ++q) outer *= (uint64_t)shp[q];
+    for (int q = s + 1; q < MAXD; ++q) inner *= (uint64_t)shp[q];
+    hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, z, outer, (int)shp[s],
+                       inner, dim_consts<T>(h, l, s, table));
+  }
+  *zout = z;
+}
+
+struct Scratch {
+  uint64_t cbar, pa, pb, ga, gb;  // element counts
+};
+
+Scratch scratch_counts(const Hierarchy& h) {
+  Scratch s{};
+  const int L = h.L;
+  s.cbar = L >= 1 ? h.count(L) : 0;
+  // restriction ping-pong: the first restriction halves (roughly) the finest grid
+  uint64_t g = 0;
+  for (int l = 1; l <= L; ++l) {
+    std::array<int64_t, MAXD> shp = h.sizes[l];
+    for (int q = MAXD - 1; q >= 0; --q) {
+      if (!h.active[q]) continue;
+      shp[q] = h.sizes[l - 1][q];
+      uint64_t n = 1;
+      for (int r = 0; r < MAXD; ++r) n *= (uint64_t)shp[r];
+      g = std::max(g, n);
+    }
+  }
+  s.ga = s.gb = g;
+  s.pa = L >= 1 ? h.count(L - 1) : h.count(0);
+  s.pb = L >= 2 ? h.count(L - 2) : h.count(0);
+  return s;
+}
+
+}  // namespace
+
+template <typename T>
+LevelGeom<T> level_geom(const Hierarchy& h, int l, const T* table) {
+  LevelGeom<T> g{};
+  g.pad_slots = MAXD - h.D;
+  for (int s = 0; s < MAXD; ++s) {
+    g.nf[s] = (int32_t)h.sizes[l][s];
+    g.nc[s] = (int32_t)h.sizes[l - 1][s];
+    g.act[s] = h.active[s] ? 1 : 0;
+    g.wl[s] = h.active[s] ? table + h.devoff[l][s].wl : nullptr;
+    g.wr[s] = h.active[s] ? table + h.devoff[l][s].wr : nullptr;
+  }
+  g.level_off = h.level_off[l];
+  uint64_t off = 0;
+  const int D = h.D;
+  for (int m = 1; m < (1 << D); ++m) {
+    int64_t ext[MAXD];
+    for (int s = 0; s < MAXD; ++s) {
+      int d = s - g.pad_slots;
+      bool bit = d >= 0 && ((m >> d) & 1);
+      ext[s] = bit ? (h.sizes[l][s] - h.sizes[l - 1][s]) : h.sizes[l - 1][s];
+    }
+    uint64_t acc = 1;
+    for (int s = MAXD - 1; s >= 0; --s) {
+      g.sub_stride[m][s] = acc;
+      acc *= (uint64_t)ext[s];
+    }
+    g.sub_off[m] = off;
+    off += acc;
+  }
+  return g;
+}
+
+template <typename T>
+DimConsts<T> dim_consts(const Hierarchy& h, int l, int s, const T* t) {
+  const DevDim& o = h.devoff[l][s];
+  return DimConsts<T>{t + o.wl, t + o.wr, t + o.ma, t + o.mb, t + o.mc,
+                      t + o.rl, t + o.rr, t + o.ta, t + o.tr, t + o.tcp};
+}
+
+template <typename T>
+uint64_t decompose_scratch_bytes(const Hierarchy& h) {
+  Scratch s = scratch_counts(h);
+  return carve_size<T>(s.cbar) + carve_size<T>(s.pa) + carve_size<T>(s.pb) + carve_size<T>(s.ga) +
+         carve_size<T>(s.gb) + 1024;
+}
+
+template <typename T>
+uint64_t recompose_scratch_bytes(const Hierarchy& h) {
+  return decompose_scratch_bytes<T>(h);
+}
+
+template <typename T>
+void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, const QuantOut* q,
+               void* scratch, hipStream_t st) {
+  Scratch sc = scratch_counts(h);
+  Carver cv(scratch);
+  T* cbar = cv.take<T>(sc.cbar);
+  T* pa = cv.take<T>(sc.pa);
+  T* pb = cv.take<T>(sc.pb);
+  T* ga = cv.take<T>(sc.ga);
+  T* gb = cv.take<T>(sc.gb);
+  const T* cur = d_in;
+  T* nxt = pa;
+  const int mode = q ? 1 : 0;
+  for (int l = h.L; l >= 1; --l) {
+    LevelGeom<T> g = level_geom<T>(h, l, table);
+    const uint64_t nfine = h.count(l);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_coeff<T, 0>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cur, cbar, nxt, d_stream,
+                         nullptr, nullptr, nullptr, l, 0, g, nfine);
+    else
+      hipLaunchKernelGGL((k_coeff<T, 1>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cur, cbar, nxt, nullptr,
+                         q->sym, q->qside, q->bins, l, q->R, g, nfine);
+    T* z = nullptr;
+    correction<T>(h, l, table, cbar, ga, gb, &z, st);
+    const uint64_t nc = h.count(l - 1);
+    hipLaunchKernelGGL((k_axpy<T, true>), dim3(grid_for(nc)), dim3(TPB), 0, st, nxt, nxt, z, nc);
+    cur = nxt;
+    nxt = (nxt == pa) ? pb : pa;
+  }
+  const uint64_t n0 = h.count(0);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_coarsest_out<T, 0>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, d_stream, nullptr,
+                       nullptr, nullptr, 0, n0);
+  else
+    hipLaunchKernelGGL((k_coarsest_out<T, 1>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, nullptr, q->sym,
+                       q->qside, q->bins, q->R, n0);
+  MG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void recompose(const Hierarchy& h, const T* table, const T* d_stream, const QuantOut* q, T* d_out,
+               void* scratch, hipStream_t st) {
+  Scratch sc = scratch_counts(h);
+  Carver cv(scratch);
+  T* cbar = cv.take<T>(sc.cbar);
+  T* pa = cv.take<T>(sc.pa);
+  T* pb = cv.take<T>(sc.pb);
+  T* ga = cv.take<T>(sc.ga);
+  T* gb = cv.take<T>(sc.gb);
+  const int mode = q ? 1 : 0;
+  const uint64_t n0 = h.count(0);
+  // grid 0 goes where level 1 reads it; the last level writes d_out
+  auto level_buf = [&](int l) -> T* {
+    if (l == h.L) return d_out;
+    return ((h.L - l) % 2 == 1) ? pa : pb;
+  };
+  T* cur = level_buf(0);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_coarsest_in<T, 0>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, d_stream, nullptr,
+                       nullptr, nullptr, 0, n0);
+  else
+    hipLaunchKernelGGL((k_coarsest_in<T, 1>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, nullptr, q->sym,
+                       q->qside, q->bins, q->R, n0);
+  for (int l = 1; l <= h.L; ++l) {
+    LevelGeom<T> g = level_geom<T>(h, l, table);
+    const uint64_t nfine = h.count(l);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_scatter<T, 0>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cbar, d_stream, nullptr,
+                         nullptr, nullptr, l, 0, g, nfine);
+    else
+      hipLaunchKernelGGL((k_scatter<T, 1>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cbar, nullptr, q->sym,
+                         q->qside, q->bins, l, q->R, g, nfine);
+    T* z = nullptr;
+    correction<T>(h, l, table, cbar, ga, gb, &z, st);
+    const uint64_t nc = h.count(l - 1);
+    // uc = u_{l-1} - z, in place in z
+    hipLaunchKernelGGL((k_axpy<T, false>), dim3(grid_for(nc)), dim3(TPB), 0, st, z, cur, z, nc);
+    T* out = level_buf(l);
+    hipLaunchKernelGGL(k_interp_add<T>, dim3(grid_for(nfine)), dim3(TPB), 0, st, out, cbar, z, g, nfine);
+    cur = out;
+  }
+  if (h.L == 0 && cur != d_out) MG_HIP(hipMemcpyAsync(d_out, cur, n0 * sizeof(T), hipMemcpyDeviceToDevice, st));
+  MG_HIP(hipGetLastError());
+}
+
+#define MG_INST(T)                                                                                    \
+  template LevelGeom<T> level_geom<T>(const Hierarchy&, int, const T*);                             \
+  template DimConsts<T> dim_consts<T>(const Hierarchy&, int, int, const T*);                        \
+  template uint64_t decompose_scratch_bytes<T>(const Hierarchy&);                                   \
+  template uint64_t recompose_scratch_bytes<T>(const Hierarchy&);                                   \
+  template void decompose<T>(const Hierarchy&, const T*, const T*, T*, const QuantOut*, void*,      \
+                             hipStream_t);                                                          \
+  template void recompose<T>(const Hierarchy&, const T*, const T*, const QuantOut*, T*, void*,      \
+                             hipStream_t);
+MG_INST(float)
+MG_INST(double)
+#undef MG_INST
+
+}  // namespace mg

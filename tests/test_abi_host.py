@@ -1,0 +1,109 @@
+"""The C-ABI library on the CPU: it loads, exports every declared entry point,
+and its host-only calls agree with the oracle (no GPU work is issued)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import fieldgen
+import paper_2401_05994_amd as m
+from oracle import alloc as A
+from oracle import codec, grid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mgard_hip.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(mgard_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = m.load_library()
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert b"gfx950" in lib.mgard_version()
+
+
+@pytest.mark.parametrize("shape,coords", [
+    ((129, 129), None),
+    ((513, 513, 513), None),
+    ((257, 257, 257), None),
+    ((500, 500, 500), "geo"),
+    ((65, 2049), None),
+    ((9, 10, 11, 12), "rand"),
+])
+def test_plain_constant_matches_oracle(shape, coords):
+    if coords == "geo":
+        x = fieldgen.geometric_coords(shape[0])
+        cs = [x] * len(shape)
+    elif coords == "rand":
+        rng = np.random.default_rng(1)
+        cs = [fieldgen.random_coords(n, rng) for n in shape]
+    else:
+        cs = None
+    S, K = m.mgard_plain_constant(shape, cs)
+    h = grid.Hierarchy(shape, cs)
+    assert abs(S - A.S_constant(h)) <= 1e-13 * S
+    Ko = A.level_K(h)
+    for l in range(1, h.L + 1):
+        assert abs(K[l] - Ko[l]) <= 1e-13 * Ko[l]
+
+
+@pytest.mark.parametrize("shape", [(129, 129), (17, 9, 6), (2, 33), (1, 9, 1), (5, 6, 5, 6), (3,), (1,)])
+def test_stream_layout_matches_oracle(shape):
+    L, offs = m.mgard_stream_layout(shape)
+    h = grid.Hierarchy(shape)
+    assert L == h.L
+    assert offs == [0] + list(np.cumsum(h.level_counts()))
+
+
+def test_inspect_parses_oracle_buffer():
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal((17, 20)).astype(np.float32)
+    xs = [None, fieldgen.random_coords(20, rng)]
+    buf = codec.compress(u, 1e-2, coords=xs, dict_size=512, chunk=256)
+    hd = m.mgard_inspect(buf)
+    ho = codec.parse(buf)
+    assert hd["complete"]
+    assert hd["shape"] == [17, 20] and hd["dtype"] == 0 and hd["coord_flags"] == 2
+    assert hd["levels"] == ho.L and hd["n_outliers"] == ho.n_outliers
+    assert hd["payload_words"] == ho.payload_words and hd["total_bytes"] == len(buf)
+    assert hd["tau_abs"] == ho.tau_abs and hd["dict_size"] == 512
+
+
+def test_inspect_rejects_bad_buffers():
+    u = fieldgen.bumps2d(33)
+    buf = codec.compress(u, 1e-3)
+    with pytest.raises(m.MgardError) as e:
+        m.mgard_inspect(b"XXXX" + buf[4:])
+    assert e.value.code == -7
+    bad = bytearray(buf)
+    bad[16:20] = (1000).to_bytes(4, "little")  # dictionary not a power of two
+    with pytest.raises(m.MgardError):
+        m.mgard_inspect(bytes(bad))
+    bad = bytearray(buf)
+    bad[48:56] = (12345).to_bytes(8, "little")  # symbol count disagrees with the shape
+    with pytest.raises(m.MgardError):
+        m.mgard_inspect(bytes(bad))
+    hd = m.mgard_inspect(buf[:60])  # short: fixed part only
+    assert not hd["complete"]
+
+
+def test_compress_bound_and_argument_errors():
+    b = m.mgard_compress_bound((513, 513, 513), m.F32)
+    assert b > 513 ** 3 * 2
+    with pytest.raises(m.MgardError):
+        m.mgard_compress_bound((0, 5), m.F32)
+    with pytest.raises(m.MgardError):
+        m.mgard_compress_bound((5, 5, 5, 5, 5), m.F32)
+    with pytest.raises(m.MgardError):
+        m.mgard_compress_bound((9, 9), m.F32, dict_size=1000)
+    with pytest.raises(m.MgardError):
+        m.mgard_compress_bound((9, 9), m.F32, coords=[np.arange(9.0), np.arange(9.0)[::-1].copy()])

@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Bars: floating-point stages agree with the oracle in the same working
+precision (same rounding order, so the expected result is bit-identical; the
+normwise tolerance 1e-6 max|u| for float32 and 1e-13 max|u| for float64 is
+asserted first), and float32 results stay within 1e-6 max|u| of the float64
+oracle.  Integer stages (quantized symbols, histogram, code lengths, codes,
+payload words) must be bit-exact.  Inputs are seeded and synthetic.
+"""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import fieldgen
+from oracle import alloc as A
+from oracle import codec, grid, huffman as H, quant as Q
+from oracle import transform as X
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def tol_for(T):
+    return 1e-6 if T == np.float32 else 1e-13
+
+
+CASES = {
+    "c1-129x129-f64": ((129, 129), np.float64, None),
+    "3d-33x20x17-f32-nonuniform": ((33, 20, 17), np.float32, "rand"),
+    "3d-17x18x19-f64-nonuniform": ((17, 18, 19), np.float64, "rand"),
+    "1d-1000-f32": ((1000,), np.float32, None),
+    "4d-9x10x7x6-f64": ((9, 10, 7, 6), np.float64, "rand"),
+    "batchdims-2x65x1x33-f32": ((2, 65, 1, 33), np.float32, None),
+    "even-64x50-f32": ((64, 50), np.float32, None),
+    "3d-65x65x65-f32": ((65, 65, 65), np.float32, None),
+}
+
+
+def make_case(name):
+    shape, T, cmode = CASES[name]
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    if name.startswith("c1"):
+        u = fieldgen.bumps2d(129, seed=1)
+    elif name.startswith("3d-65"):
+        u = fieldgen.spectral(shape, -5.0 / 3.0, 2)
+    else:
+        u = fieldgen.random_field(shape, rng)
+    u = u.astype(T)
+    coords = [fieldgen.random_coords(n, rng) for n in shape] if cmode == "rand" else None
+    return u, coords
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_decompose_matches_oracle(lib, name):
+    u, coords = make_case(name)
+    T = u.dtype.type
+    say("decompose", name)
+    h = grid.Hierarchy(u.shape, coords)
+    ref = Q.to_stream(*X.decompose(u, h, T), h)
+    got = host(lib.mgard_decompose(dev(u), coords))
+    scale = float(np.abs(u).max())
+    assert np.abs(got.astype(np.float64) - ref).max() <= tol_for(T) * scale
+    mism = int(np.count_nonzero(got != ref))
+    assert mism == 0, f"{mism} of {ref.size} coefficients differ in the last bits"
+
+
+@pytest.mark.parametrize("name", ["3d-33x20x17-f32-nonuniform", "3d-65x65x65-f32", "batchdims-2x65x1x33-f32"])
+def test_f32_decompose_close_to_f64_oracle(lib, name):
+    u, coords = make_case(name)
+    say("f32 vs f64 oracle", name)
+    h = grid.Hierarchy(u.shape, coords)
+    ref = Q.to_stream(*X.decompose(u.astype(np.float64), h, np.float64), h)
+    got = host(lib.mgard_decompose(dev(u), coords)).astype(np.float64)
+    off = Q.level_offsets(h)
+    scale = float(np.abs(u).max())
+    for l in range(h.L + 1):
+        d = np.abs(got[off[l]:off[l + 1]] - ref[off[l]:off[l + 1]]).max()
+        assert d <= 1e-6 * scale, (l, d / scale)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_recompose_matches_oracle(lib, name):
+    u, coords = make_case(name)
+    T = u.dtype.type
+    say("recompose", name)
+    h = grid.Hierarchy(u.shape, coords)
+    c0, cb = X.decompose(u, h, T)
+    stream = Q.to_stream(c0, cb, h)
+    ref = X.recompose(*Q.from_stream(stream, h, T), h, T)
+    got = host(lib.mgard_recompose(dev(stream), u.shape, coords))
+    assert got.dtype == T
+    assert np.abs(got.astype(np.float64) - ref).max() <= tol_for(T) * float(np.abs(u).max())
+    assert int(np.count_nonzero(got != ref)) == 0
+    if T == np.float64:
+        assert np.abs(got - u).max() <= 1e-12 * np.abs(u).max()
+
+
+def test_gpu_roundtrip_f64_nonuniform(lib):
+    rng = np.random.default_rng(7)
+    shape = (40, 33, 27)
+    xs = [fieldgen.random_coords(n, rng) for n in shape]
+    u = fieldgen.random_field(shape, rng)
+    say("roundtrip f64", shape)
+    c = lib.mgard_decompose(dev(u), xs)
+    r = host(lib.mgard_recompose(c, shape, xs))
+    assert np.abs(r - u).max() <= 1e-12 * np.abs(u).max()
+
+
+@pytest.mark.parametrize("name", ["c1-129x129-f64", "3d-33x20x17-f32-nonuniform"])
+@pytest.mark.parametrize("dict_size", [256, 8192])
+def test_quantize_dequantize_stage(lib, name, dict_size):
+    u, coords = make_case(name)
+    T = u.dtype.type
+    say("quantize stage", name, dict_size)
+    h = grid.Hierarchy(u.shape, coords)
+    stream = Q.to_stream(*X.decompose(u, h, T), h)
+    bins = [1e-3 * (1.0 + 0.1 * l) for l in range(h.L + 1)]
+    q = Q.quantize_stream(stream, h, bins)
+    sym_ref, out_ref = Q.to_symbols(q, dict_size)
+    sym, qside = lib.mgard_quantize(dev(stream), u.shape, bins, dict_size)
+    s = lib.u16(sym).astype(np.int64)
+    assert np.array_equal(s, sym_ref)
+    esc = sym_ref == 0
+    assert np.array_equal(host(qside)[esc], out_ref)
+    deq = host(lib.mgard_dequantize(sym, qside, u.shape, bins, torch.float32 if T == np.float32 else torch.float64,
+                                    dict_size))
+    assert np.array_equal(deq, Q.dequantize_stream(q, h, bins, T))
+
+
+def _symbol_streams():
+    rng = np.random.default_rng(12)
+    u = fieldgen.bumps2d()
+    p = codec.compress_parts(u, 1e-4, dict_size=8192)
+    yield "c1-1e-4", p.symbols, 8192, 4096
+    lap = np.clip(np.round(rng.laplace(512, 30, size=200_003)), 0, 1023).astype(np.int64)
+    yield "laplace-1024", lap, 1024, 512
+    yield "single-symbol", np.full(5000, 77, dtype=np.int64), 256, 256
+    wide = rng.integers(0, 8192, size=100_000)
+    yield "uniform-8192", wide, 8192, 8192
+    geo = np.minimum(rng.geometric(0.02, size=300_000), 4095).astype(np.int64)
+    yield "geometric-4096", geo, 4096, 1024
+
+
+@pytest.mark.parametrize("case", list(range(5)))
+def test_huffman_stages_bitexact(lib, case):
+    name, sym, dict_size, chunk = list(_symbol_streams())[case]
+    say("huffman", name)
+    dsym = dev(sym.astype(np.int16) if sym.max() < 32768 else sym.astype(np.uint16).view(np.int16))
+    hist, esc = lib.mgard_histogram(dsym, dict_size, chunk)
+    href = H.histogram(sym, dict_size)
+    assert np.array_equal(host(hist), href)
+    eref = [int(np.count_nonzero(sym[k:k + chunk] == 0)) for k in range(0, len(sym), chunk)]
+    assert list(host(esc)[:len(eref)]) == eref
+    lens, codes = lib.mgard_huffman_codebook(hist, dict_size)
+    lref = H.code_lengths(href)
+    cref = H.canonical_codes(lref)
+    assert np.array_equal(host(lens).astype(np.int64), lref)
+    assert np.array_equal(host(codes).view(np.uint64)[lref > 0], cref[lref > 0])
+    bits, payload = lib.mgard_huffman_encode(dsym, lens, codes, dict_size, chunk)
+    bref, wref = H.encode(sym, lref, cref, chunk)
+    assert list(host(bits).astype(np.int64)) == bref
+    assert np.array_equal(host(payload).view(np.uint32).astype(np.int64), np.asarray(wref, dtype=np.int64))
+    # decode the oracle's payload on the GPU
+    dec = lib.mgard_huffman_decode(dev(np.asarray(wref, dtype=np.uint32).view(np.int32)),
+                                   dev(np.asarray(bref, dtype=np.uint32).view(np.int32)), len(sym), lens,
+                                   dict_size, chunk)
+    assert np.array_equal(lib.u16(dec).astype(np.int64), sym)
+
+
+@pytest.mark.parametrize("name,tol", [("c1-129x129-f64", 1e-3), ("c1-129x129-f64", 1e-5),
+                                      ("3d-33x20x17-f32-nonuniform", 1e-2), ("3d-65x65x65-f32", 1e-3),
+                                      ("even-64x50-f32", 1e-4), ("4d-9x10x7x6-f64", 1e-3)])
+def test_compressed_bytes_equal_oracle(lib, name, tol):
+    u, coords = make_case(name)
+    say("compress bytes", name, tol)
+    ref = codec.compress(u, tol, coords=coords)
+    buf, nbytes, info = lib.mgard_compress(dev(u), tol, coords)
+    got = host(buf[:nbytes]).tobytes()
+    assert nbytes == len(ref)
+    assert got == ref
+    # GPU decompression of the oracle's buffer equals the oracle's decompression
+    r = host(lib.mgard_decompress(dev(np.frombuffer(ref, dtype=np.uint8)), len(ref)))
+    rref = codec.decompress(ref)
+    assert np.array_equal(r, rref)
+    assert np.abs(r.astype(np.float64) - u.astype(np.float64)).max() <= tol * np.abs(u).max()
+
+
+def test_error_paths(lib):
+    say("error paths")
+    u = np.ones((33, 33), dtype=np.float32)
+    u[3, 4] = np.nan
+    with pytest.raises(lib.MgardError) as e:
+        lib.mgard_compress(dev(u), 1e-3)
+    assert e.value.code == -5
+    u[3, 4] = np.inf
+    with pytest.raises(lib.MgardError) as e:
+        lib.mgard_compress(dev(u), 1e-3)
+    assert e.value.code == -5
+    v = fieldgen.bumps2d(65).astype(np.float32)
+    with pytest.raises(lib.MgardError) as e:
+        lib.mgard_compress(dev(v), 0.0)
+    assert e.value.code == -4
+    with pytest.raises(lib.MgardError) as e:
+        lib.mgard_compress(dev(v), 1e-3, out=torch.empty(100, dtype=torch.uint8, device=DEV))
+    assert e.value.code == -6
+    buf, nbytes, _ = lib.mgard_compress(dev(v), 1e-3)
+    with pytest.raises(lib.MgardError) as e:
+        lib.mgard_decompress(buf, nbytes - 8)
+    assert e.value.code == -7
+    # corrupt one chunk bit count: the payload no longer decodes
+    hd = codec.parse(host(buf[:nbytes]).tobytes())
+    bad = buf[:nbytes].clone()
+    o = hd.offsets["chunk_bits"]
+    bad[o] = (int(bad[o]) + 1) % 256
+    with pytest.raises(lib.MgardError) as e:
+        lib.mgard_decompress(bad, nbytes)
+    assert e.value.code == -7
+    # zero field: all coefficients quantize to zero
+    z = torch.zeros((17, 17), dtype=torch.float64, device=DEV)
+    b2, n2, _ = lib.mgard_compress(z, 1e-3)
+    assert torch.equal(lib.mgard_decompress(b2, n2), z)
