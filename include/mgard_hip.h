@@ -77,9 +77,9 @@ typedef struct {
   uint32_t struct_size;   /* sizeof(mgard_opts) */
   uint32_t eb;            /* mgard_eb, default MGARD_REL */
   uint32_t alloc;         /* mgard_alloc, default MGARD_ALLOC_PLAIN */
-  uint32_t dict_size;     /* Huffman dictionary: power of two in [256, 16384]; 0 = 8192 */
+  uint32_t dict_size;     /* Huffman dictionary: power of two in [256, 8192]; 0 = 8192 */
   uint32_t chunk_symbols; /* symbols per independently decodable chunk, multiple of 256
-                             in [256, 65536]; 0 = 4096 */
+                             in [256, 8192]; 0 = 4096 */
   uint32_t reserved;
   void* stream;              /* hipStream_t */
   const mgard_model* model;  /* required for MGARD_ALLOC_LEARNED */
@@ -209,6 +209,15 @@ mgard_status mgard_maxabs(mgard_dtype dtype, const void* d_in, uint64_t n, doubl
 mgard_status mgard_plain_constant(uint32_t ndim, const uint64_t* shape,
                                   const double* const* coords, double* h_S, double* h_K,
                                   uint32_t max_levels);
+
+/* ----------------------------------------------------------- measurement
+ * Kernel timing with HIP events recorded on each launch's stream.
+ * mgard_timing(1) clears earlier records and starts recording; (0) clears and
+ * stops.  mgard_timing_report waits for the recorded events and writes one
+ * line per kernel name, "name launches total_milliseconds", into h_buf
+ * (capacity bytes, NUL-terminated); *needed receives the size required. */
+mgard_status mgard_timing(int enable);
+mgard_status mgard_timing_report(char* h_buf, uint64_t capacity, uint64_t* needed);
 
 /* ----------------------------------------------------------- miscellaneous */
 const char* mgard_last_error(void);

@@ -50,7 +50,7 @@ def prolongation_dense(op: DimOp):
 
 
 def correction_matrix(op: DimOp):
-    """Dense A = T^{-1} P^T M for one dimension and level."""
+    """Dense A = T^{-1} P^T M for one dimension and level (LAPACK solve; used to pin below)."""
     M = tridiag_dense(op.ma, op.mb, op.mc)
     Tm = tridiag_dense(*op.coarse_mass)
     P = prolongation_dense(op)
@@ -61,6 +61,22 @@ def norm_inf(A) -> float:
     return float(np.abs(A).sum(axis=1).max())
 
 
+def correction_norm(op: DimOp) -> float:
+    """||T^{-1} P^T M||_inf as the method applies the operator: column k of A is the
+    1D mass, restriction and Thomas steps applied to the unit vector e_k (float64),
+    and the row sums of |A| accumulate over k = 0, 1, ... in order."""
+    from .transform import mass_axis, restrict_axis, thomas_axis
+
+    rows = np.zeros(op.nc)
+    for k in range(op.nf):
+        e = np.zeros(op.nf)
+        e[k] = 1.0
+        col = thomas_axis(restrict_axis(mass_axis(e, 0, op, np.float64), 0, op, np.float64), 0, op,
+                          np.float64)
+        rows = rows + np.abs(col)
+    return float(rows.max())
+
+
 def level_K(hier: Hierarchy):
     """K_l for l = 1..L (index 0 unused, set to 0)."""
     K = [0.0]
@@ -68,7 +84,7 @@ def level_K(hier: Hierarchy):
         k = 1.0
         for op in hier.ops[l]:
             if op is not None:
-                k *= norm_inf(correction_matrix(op))
+                k *= correction_norm(op)
         K.append(k)
     return K
 

@@ -89,6 +89,8 @@ def load_library():
         "mgard_huffman_decode": (C.c_int, [P, U64, P, U64, U32, U32, P, P, P]),
         "mgard_maxabs": (C.c_int, [C.c_int, P, U64, PD, P]),
         "mgard_plain_constant": (C.c_int, [U32, PU64, P, PD, PD, U32]),
+        "mgard_timing": (C.c_int, [C.c_int]),
+        "mgard_timing_report": (C.c_int, [C.c_char_p, U64, PU64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -362,3 +364,21 @@ def mgard_release_workspace():
 def u16(t):
     """uint16 view (numpy) of an int16 symbol tensor."""
     return t.cpu().numpy().view(np.uint16)
+
+
+def mgard_timing(enable: bool):
+    _check(load_library().mgard_timing(1 if enable else 0))
+
+
+def mgard_timing_report():
+    """{kernel name: (launches, total ms)} recorded since mgard_timing(True)."""
+    lib = load_library()
+    need = C.c_uint64(0)
+    lib.mgard_timing_report(None, 0, C.byref(need))
+    buf = C.create_string_buffer(int(need.value) + 1)
+    _check(lib.mgard_timing_report(buf, len(buf), C.byref(need)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms = line.split()
+        out[name] = (int(n), float(ms))
+    return out

@@ -322,7 +322,7 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
   int64_t* qside = cv.take<int64_t>(n);
   double* bins = cv.take<double>(MAXL + 1);
   double* scalars = cv.take<double>(8);
-  uint64_t* misc = cv.take<uint64_t>(4);  // [0] max bits, [1] outlier byte offset
+  uint64_t* misc = cv.take<uint64_t>(4);  // [0] max bits, [1] outlier byte offset, [2] status
   uint64_t* hist = cv.take<uint64_t>((uint64_t)o.dict);
   uint64_t* codes = cv.take<uint64_t>((uint64_t)o.dict);
   uint64_t* word_off = cv.take<uint64_t>(nch + 1);
@@ -354,13 +354,13 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
   uint32_t* chunk_esc = reinterpret_cast<uint32_t*>(d_out + y.chunk_esc);
   uint32_t* chunk_bits = reinterpret_cast<uint32_t*>(d_out + y.chunk_bits);
   uint8_t* code_len = reinterpret_cast<uint8_t*>(d_out + y.code_len);
-  launch_histogram(sym, n, o.dict, o.chunk, hist, chunk_esc, st);
+  launch_histogram(sym, n, o.dict, o.chunk, hist, chunk_esc, reinterpret_cast<uint32_t*>(&misc[2]), st);
   launch_codebook(hist, o.dict, code_len, codes, st);
-  launch_chunk_bits(sym, n, o.chunk, code_len, chunk_bits, st);
+  launch_chunk_bits(sym, n, o.dict, o.chunk, code_len, chunk_bits, st);
   launch_scan_words(chunk_bits, nch, word_off, st);
   launch_scan_u32(chunk_esc, nch, esc_off, st);
   hipLaunchKernelGGL(k_outlier_offset, dim3(1), dim3(1), 0, st, word_off, nch, y.payload, &misc[1]);
-  launch_encode(sym, n, o.chunk, code_len, codes, word_off, reinterpret_cast<uint32_t*>(d_out + y.payload),
+  launch_encode(sym, n, o.dict, o.chunk, code_len, codes, word_off, reinterpret_cast<uint32_t*>(d_out + y.payload),
                 esc_off, qside, d_out, &misc[1], st);
   hipLaunchKernelGGL(k_zero_pad, dim3(1), dim3(1), 0, st, d_out, word_off, nch, y.payload);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, d_out, word_off, esc_off, nch, &misc[1], scalars, bins,
@@ -668,8 +668,15 @@ mgard_status mgard_histogram(const uint16_t* d_symbols, uint64_t n, uint32_t dic
     if (!d_symbols || !d_hist || !d_chunk_esc) fail(MGARD_ERR_ARG, "null buffer");
     if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
     if (chunk < 256 || chunk > 8192 || chunk % 256) fail(MGARD_ERR_ARG, "chunk");
-    launch_histogram(d_symbols, n, (int)dict_size, (int)chunk, d_hist, d_chunk_esc, o.st);
+    Workspace& ws = workspace();
+    ws.reserve(1024);
+    uint32_t* status = static_cast<uint32_t*>(ws.base());
+    MG_HIP(hipMemsetAsync(status, 0, 4, o.st));
+    launch_histogram(d_symbols, n, (int)dict_size, (int)chunk, d_hist, d_chunk_esc, status, o.st);
+    uint32_t hs = 0;
+    MG_HIP(hipMemcpyAsync(&hs, status, 4, hipMemcpyDeviceToHost, o.st));
     MG_HIP(hipStreamSynchronize(o.st));
+    if (hs) fail(MGARD_ERR_ARG, "a symbol lies outside the dictionary");
   });
 }
 
@@ -698,14 +705,14 @@ mgard_status mgard_huffman_encode(const uint16_t* d_symbols, uint64_t n, uint32_
     Workspace& ws = workspace();
     ws.reserve(carve_size<uint64_t>(nch + 1) + 1024);
     uint64_t* word_off = static_cast<uint64_t*>(ws.base());
-    launch_chunk_bits(d_symbols, n, (int)chunk, d_code_len, d_chunk_bits, o.st);
+    launch_chunk_bits(d_symbols, n, (int)dict_size, (int)chunk, d_code_len, d_chunk_bits, o.st);
     launch_scan_words(d_chunk_bits, nch, word_off, o.st);
     uint64_t total = 0;
     MG_HIP(hipMemcpyAsync(&total, word_off + nch, 8, hipMemcpyDeviceToHost, o.st));
     MG_HIP(hipStreamSynchronize(o.st));
     *payload_words = total;
     if (total > payload_capacity) fail(MGARD_ERR_CAPACITY, "payload capacity");
-    launch_encode(d_symbols, n, (int)chunk, d_code_len, d_codes, word_off, d_payload, nullptr, nullptr, nullptr,
+    launch_encode(d_symbols, n, (int)dict_size, (int)chunk, d_code_len, d_codes, word_off, d_payload, nullptr, nullptr, nullptr,
                   nullptr, o.st);
     MG_HIP(hipStreamSynchronize(o.st));
   });
@@ -766,6 +773,19 @@ mgard_status mgard_maxabs(mgard_dtype dtype, const void* d_in, uint64_t n, doubl
       m = f;
     }
     *h_maxabs = m;
+  });
+}
+
+mgard_status mgard_timing(int enable) {
+  return guard([&] { timing_set(enable); });
+}
+
+mgard_status mgard_timing_report(char* h_buf, uint64_t capacity, uint64_t* needed) {
+  return guard([&] {
+    std::string r = timing_report();
+    if (needed) *needed = r.size() + 1;
+    if (!h_buf || capacity < r.size() + 1) fail(MGARD_ERR_CAPACITY, "report buffer too small");
+    std::memcpy(h_buf, r.c_str(), r.size() + 1);
   });
 }
 

@@ -19,12 +19,13 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int MAXLEN = 64;
+constexpr int MAXDICT = 8192;  // largest dictionary; all LDS below is static
 
 // ------------------------------------------------------------------ histogram
 __global__ void __launch_bounds__(TPB) k_histogram(const uint16_t* __restrict__ sym, uint64_t n, int dict,
                                                    int chunk, uint64_t nch, unsigned long long* __restrict__ hist,
-                                                   uint32_t* __restrict__ chunk_esc) {
-  extern __shared__ uint32_t sh[];
+                                                   uint32_t* __restrict__ chunk_esc, uint32_t* __restrict__ status) {
+  __shared__ uint32_t sh[MAXDICT];
   __shared__ uint32_t esc;
   for (int b = threadIdx.x; b < dict; b += TPB) sh[b] = 0;
   __syncthreads();
@@ -36,7 +37,10 @@ __global__ void __launch_bounds__(TPB) k_histogram(const uint16_t* __restrict__ 
     uint32_t e = 0;
     for (uint64_t i = beg + threadIdx.x; i < end; i += TPB) {
       const uint32_t s = sym[i];
-      atomicAdd(&sh[s], 1u);
+      if (s < (uint32_t)dict)
+        atomicAdd(&sh[s], 1u);
+      else
+        atomicOr(status, 1u);  // symbol outside the dictionary
       e += (s == 0);
     }
     if (e) atomicAdd(&esc, e);
@@ -52,8 +56,8 @@ __global__ void __launch_bounds__(TPB) k_histogram(const uint16_t* __restrict__ 
 // One workgroup.  keys: (count << 16 | symbol), empty bins sort last.
 __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ hist, int dict,
                                                    uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
-  extern __shared__ uint64_t keys[];  // dict entries, then dict uint16 symbols
-  uint16_t* syms = reinterpret_cast<uint16_t*>(keys + dict);
+  __shared__ uint64_t keys[MAXDICT];
+  __shared__ uint16_t syms[MAXDICT];
   __shared__ int nleaf;
   __shared__ uint32_t bl_count[MAXLEN + 1];
   const int t = threadIdx.x;
@@ -151,7 +155,7 @@ __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ 
 
 // ------------------------------------------------------------------ chunk sizes
 __global__ void __launch_bounds__(TPB) k_chunk_bits(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
-                                                    uint64_t nch, const uint8_t* __restrict__ len,
+                                                    uint64_t nch, uint32_t mask, const uint8_t* __restrict__ len,
                                                     uint32_t* __restrict__ chunk_bits) {
   __shared__ uint32_t acc;
   for (uint64_t k = blockIdx.x; k < nch; k += gridDim.x) {
@@ -160,7 +164,7 @@ __global__ void __launch_bounds__(TPB) k_chunk_bits(const uint16_t* __restrict__
     const uint64_t beg = k * (uint64_t)chunk;
     const uint64_t end = min(beg + (uint64_t)chunk, n);
     uint32_t b = 0;
-    for (uint64_t i = beg + threadIdx.x; i < end; i += TPB) b += len[sym[i]];
+    for (uint64_t i = beg + threadIdx.x; i < end; i += TPB) b += len[sym[i] & mask];
     atomicAdd(&acc, b);
     __syncthreads();
     if (threadIdx.x == 0) chunk_bits[k] = acc;
@@ -211,15 +215,17 @@ __device__ inline void put_code(uint32_t* words, uint64_t b, int L, uint64_t cod
   }
 }
 
+// MAXW: LDS words of one chunk, chunk * MAXLEN / 32 for the largest chunk of the instantiation.
+template <int MAXW>
 __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
-                                                uint64_t nch, const uint8_t* __restrict__ len,
+                                                uint64_t nch, uint32_t mask, const uint8_t* __restrict__ len,
                                                 const uint64_t* __restrict__ codes,
                                                 const uint64_t* __restrict__ word_off,
                                                 uint32_t* __restrict__ payload,
                                                 const uint64_t* __restrict__ esc_off,
                                                 const int64_t* __restrict__ qside, char* obase,
                                                 const uint64_t* __restrict__ ooff) {
-  extern __shared__ uint32_t words[];
+  __shared__ uint32_t words[MAXW];
   int64_t* outliers = obase ? reinterpret_cast<int64_t*>(obase + *ooff) : nullptr;  // chunk * MAXLEN / 32 words
   __shared__ uint64_t scan[TPB];
   __shared__ uint32_t escan[TPB];
@@ -235,7 +241,7 @@ __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym
     for (int j = 0; j < per; ++j) {
       const uint64_t i = mine + j;
       if (i < n) {
-        const uint16_t s = sym[i];
+        const uint32_t s = sym[i] & mask;
         bits += len[s];
         esc += (s == 0);
       }
@@ -256,7 +262,7 @@ __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym
     for (int j = 0; j < per; ++j) {
       const uint64_t i = mine + j;
       if (i < n) {
-        const uint16_t s = sym[i];
+        const uint32_t s = sym[i] & mask;
         const int L = len[s];
         put_code(words, pos, L, codes[s]);
         pos += L;
@@ -352,7 +358,7 @@ __global__ void __launch_bounds__(TPB) k_decode(const uint32_t* __restrict__ pay
   uint64_t buf = 0;  // left-aligned bit buffer
   int have = 0;
   uint64_t next_word = 0, consumed = 0;
-  uint64_t eo = esc_off[k];
+  uint64_t eo = esc_off ? esc_off[k] : 0;  // escapes are resolved only when outliers are given
   for (uint64_t i = 0; i < cntk; ++i) {
     uint64_t code = 0;
     int L = 0;
@@ -399,27 +405,29 @@ inline unsigned blocks_for(uint64_t nch, unsigned cap) {
 }  // namespace
 
 void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
-                      uint32_t* chunk_esc, hipStream_t st) {
+                      uint32_t* chunk_esc, uint32_t* status, hipStream_t st) {
   const uint64_t nch = (n + chunk - 1) / chunk;
   MG_HIP(hipMemsetAsync(hist, 0, sizeof(uint64_t) * dict, st));
   if (nch == 0) return;
-  hipLaunchKernelGGL(k_histogram, dim3(blocks_for(nch, 2048)), dim3(TPB), dict * sizeof(uint32_t), st, sym, n,
-                     dict, chunk, nch, (unsigned long long*)hist, chunk_esc);
+  KernelTimer kt("histogram", st);
+  hipLaunchKernelGGL(k_histogram, dim3(blocks_for(nch, 2048)), dim3(TPB), 0, st, sym, n,
+                     dict, chunk, nch, (unsigned long long*)hist, chunk_esc, status);
   MG_HIP(hipGetLastError());
 }
 
 void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes, hipStream_t st) {
-  const size_t shmem = (size_t)dict * (sizeof(uint64_t) + sizeof(uint16_t));
-  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), shmem, st, hist, dict, len, codes);
+  KernelTimer kt("codebook", st);
+  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, dict, len, codes);
   MG_HIP(hipGetLastError());
 }
 
-void launch_chunk_bits(const uint16_t* sym, uint64_t n, int chunk, const uint8_t* len,
+void launch_chunk_bits(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                        uint32_t* chunk_bits, hipStream_t st) {
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return;
-  hipLaunchKernelGGL(k_chunk_bits, dim3(blocks_for(nch, 8192)), dim3(TPB), 0, st, sym, n, chunk, nch, len,
-                     chunk_bits);
+  KernelTimer kt("chunk_bits", st);
+  hipLaunchKernelGGL(k_chunk_bits, dim3(blocks_for(nch, 8192)), dim3(TPB), 0, st, sym, n, chunk, nch,
+                     (uint32_t)(dict - 1), len, chunk_bits);
   MG_HIP(hipGetLastError());
 }
 
@@ -433,15 +441,19 @@ void launch_scan_u32(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t s
   MG_HIP(hipGetLastError());
 }
 
-void launch_encode(const uint16_t* sym, uint64_t n, int chunk, const uint8_t* len,
+void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                    const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
                    const uint64_t* esc_off, const int64_t* qside, char* obase,
                    const uint64_t* ooff, hipStream_t st) {
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return;
-  const size_t shmem = (size_t)chunk * MAXLEN / 32 * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_encode, dim3(blocks_for(nch, 4096)), dim3(TPB), shmem, st, sym, n, chunk, nch, len,
-                     codes, word_off, payload, esc_off, qside, obase, ooff);
+  KernelTimer kt("encode", st);
+  if (chunk <= 4096)
+    hipLaunchKernelGGL(k_encode<4096 * MAXLEN / 32>, dim3(blocks_for(nch, 4096)), dim3(TPB), 0, st, sym, n, chunk,
+                       nch, (uint32_t)(dict - 1), len, codes, word_off, payload, esc_off, qside, obase, ooff);
+  else
+    hipLaunchKernelGGL(k_encode<8192 * MAXLEN / 32>, dim3(blocks_for(nch, 4096)), dim3(TPB), 0, st, sym, n, chunk,
+                       nch, (uint32_t)(dict - 1), len, codes, word_off, payload, esc_off, qside, obase, ooff);
   MG_HIP(hipGetLastError());
 }
 
@@ -462,6 +474,7 @@ void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const u
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch) {
     const unsigned blocks = (unsigned)((nch + 63) / 64);
+    KernelTimer kt("decode", st);
     hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(64), 0, st, payload, payload_words, word_off, chunk_bits, n,
                        chunk, nch, tab, sorted, sym, esc_off, n_out, outliers, qside, d_status);
   }

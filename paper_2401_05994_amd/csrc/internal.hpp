@@ -29,6 +29,23 @@ struct Failure {
                                                         hipGetErrorString(e_));           \
   } while (0)
 
+// ----------------------------------------------------------------- timing
+// Scoped HIP-event timer around one launch (active only after mgard_timing(1)).
+class KernelTimer {
+ public:
+  KernelTimer(const char* name, hipStream_t st);
+  ~KernelTimer();
+  KernelTimer(const KernelTimer&) = delete;
+  KernelTimer& operator=(const KernelTimer&) = delete;
+
+ private:
+  hipStream_t st_;
+  int idx_;
+};
+bool timing_enabled();
+void timing_set(int on);
+std::string timing_report();
+
 // ----------------------------------------------------------------- hierarchy
 // Per level l (1..L) and decomposed dimension d, the FP64 operator constants
 // that take grid l to grid l-1 along d (see hierarchy.cpp for the formulas).
@@ -167,16 +184,16 @@ void launch_dequantize(const uint16_t* sym, const int64_t* qside, uint64_t n,
 
 // Huffman (huffman.hip).
 void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
-                      uint32_t* chunk_esc, hipStream_t st);
+                      uint32_t* chunk_esc, uint32_t* status, hipStream_t st);
 void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes,
                      hipStream_t st);
-void launch_chunk_bits(const uint16_t* sym, uint64_t n, int chunk, const uint8_t* len,
+void launch_chunk_bits(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                        uint32_t* chunk_bits, hipStream_t st);
 // exclusive scan of per-chunk words (ceil(bits/32)) -> offsets (n+1 entries, last = total)
 void launch_scan_words(const uint32_t* chunk_bits, uint64_t nch, uint64_t* word_off,
                        hipStream_t st);
 void launch_scan_u32(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st);
-void launch_encode(const uint16_t* sym, uint64_t n, int chunk, const uint8_t* len,
+void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                    const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
                    const uint64_t* esc_off, const int64_t* qside, char* obase,
                    const uint64_t* ooff, hipStream_t st);

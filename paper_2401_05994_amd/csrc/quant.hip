@@ -135,6 +135,7 @@ __global__ void __launch_bounds__(TPB) k_dequantize(const uint16_t* __restrict__
 template <typename T>
 void launch_maxabs(const T* d, uint64_t n, uint64_t* d_bits, hipStream_t st) {
   MG_HIP(hipMemsetAsync(d_bits, 0, sizeof(uint64_t), st));
+  KernelTimer kt("maxabs", st);
   hipLaunchKernelGGL(k_maxabs<T>, dim3(grid_for(n, 4096)), dim3(TPB), 0, st, d, n, d_bits);
   MG_HIP(hipGetLastError());
 }
@@ -150,6 +151,7 @@ template <typename T>
 void launch_quantize(const T* c, uint64_t n, const uint64_t* d_level_off, int nlev,
                      const double* d_bins, int R, uint16_t* sym, int64_t* qside, hipStream_t st) {
   if (n == 0) return;
+  KernelTimer kt("quantize", st);
   hipLaunchKernelGGL(k_quantize<T>, dim3(grid_for(n, 1u << 20)), dim3(TPB), 0, st, c, n, d_level_off, nlev,
                      d_bins, R, sym, qside);
   MG_HIP(hipGetLastError());
@@ -160,6 +162,7 @@ void launch_dequantize(const uint16_t* sym, const int64_t* qside, uint64_t n,
                        const uint64_t* d_level_off, int nlev, const double* d_bins, int R, T* c,
                        hipStream_t st) {
   if (n == 0) return;
+  KernelTimer kt("dequantize", st);
   hipLaunchKernelGGL(k_dequantize<T>, dim3(grid_for(n, 1u << 20)), dim3(TPB), 0, st, sym, qside, n,
                      d_level_off, nlev, d_bins, R, c);
   MG_HIP(hipGetLastError());

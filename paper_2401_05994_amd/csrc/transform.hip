@@ -337,6 +337,7 @@ void correction(const Hierarchy& h, int l, const T* table, const T* cbar, T* buf
     for (int q = s + 1; q < MAXD; ++q) inner *= (uint64_t)shp[q];
     const int nf = (int)shp[s], nc = (int)h.sizes[l - 1][s];
     const uint64_t total = outer * (uint64_t)nc * inner;
+    KernelTimer kt(l == h.L ? "mass_restrict_fine" : "mass_restrict_coarse", st);
     hipLaunchKernelGGL(k_mass_restrict<T>, dim3(grid_for(total)), dim3(TPB), 0, st, src, dst, outer, nf,
                        nc, inner, dim_consts<T>(h, l, s, table));
     shp[s] = nc;
@@ -349,6 +350,7 @@ void correction(const Hierarchy& h, int l, const T* table, const T* cbar, T* buf
     uint64_t outer = 1, inner = 1;
     for (int q = 0; q < s; ++q) outer *= (uint64_t)shp[q];
     for (int q = s + 1; q < MAXD; ++q) inner *= (uint64_t)shp[q];
+    KernelTimer kt(l == h.L ? "thomas_fine" : "thomas_coarse", st);
     hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, z, outer, (int)shp[s],
                        inner, dim_consts<T>(h, l, s, table));
   }
@@ -450,15 +452,19 @@ void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, c
   for (int l = h.L; l >= 1; --l) {
     LevelGeom<T> g = level_geom<T>(h, l, table);
     const uint64_t nfine = h.count(l);
+    {
+    KernelTimer kt(l == h.L ? "coeff_fine" : "coeff_coarse", st);
     if (mode == 0)
       hipLaunchKernelGGL((k_coeff<T, 0>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cur, cbar, nxt, d_stream,
                          nullptr, nullptr, nullptr, l, 0, g, nfine);
     else
       hipLaunchKernelGGL((k_coeff<T, 1>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cur, cbar, nxt, nullptr,
                          q->sym, q->qside, q->bins, l, q->R, g, nfine);
+    }
     T* z = nullptr;
     correction<T>(h, l, table, cbar, ga, gb, &z, st);
     const uint64_t nc = h.count(l - 1);
+    KernelTimer kt(l == h.L ? "add_fine" : "add_coarse", st);
     hipLaunchKernelGGL((k_axpy<T, true>), dim3(grid_for(nc)), dim3(TPB), 0, st, nxt, nxt, z, nc);
     cur = nxt;
     nxt = (nxt == pa) ? pb : pa;
@@ -500,18 +506,25 @@ void recompose(const Hierarchy& h, const T* table, const T* d_stream, const Quan
   for (int l = 1; l <= h.L; ++l) {
     LevelGeom<T> g = level_geom<T>(h, l, table);
     const uint64_t nfine = h.count(l);
+    {
+    KernelTimer kt(l == h.L ? "scatter_fine" : "scatter_coarse", st);
     if (mode == 0)
       hipLaunchKernelGGL((k_scatter<T, 0>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cbar, d_stream, nullptr,
                          nullptr, nullptr, l, 0, g, nfine);
     else
       hipLaunchKernelGGL((k_scatter<T, 1>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cbar, nullptr, q->sym,
                          q->qside, q->bins, l, q->R, g, nfine);
+    }
     T* z = nullptr;
     correction<T>(h, l, table, cbar, ga, gb, &z, st);
     const uint64_t nc = h.count(l - 1);
     // uc = u_{l-1} - z, in place in z
-    hipLaunchKernelGGL((k_axpy<T, false>), dim3(grid_for(nc)), dim3(TPB), 0, st, z, cur, z, nc);
+    {
+      KernelTimer kt(l == h.L ? "sub_fine" : "sub_coarse", st);
+      hipLaunchKernelGGL((k_axpy<T, false>), dim3(grid_for(nc)), dim3(TPB), 0, st, z, cur, z, nc);
+    }
     T* out = level_buf(l);
+    KernelTimer kt(l == h.L ? "interp_add_fine" : "interp_add_coarse", st);
     hipLaunchKernelGGL(k_interp_add<T>, dim3(grid_for(nfine)), dim3(TPB), 0, st, out, cbar, z, g, nfine);
     cur = out;
   }

@@ -176,7 +176,17 @@ def test_huffman_stages_bitexact(lib, case):
     bits, payload = lib.mgard_huffman_encode(dsym, lens, codes, dict_size, chunk)
     bref, wref = H.encode(sym, lref, cref, chunk)
     assert list(host(bits).astype(np.int64)) == bref
-    assert np.array_equal(host(payload).view(np.uint32).astype(np.int64), np.asarray(wref, dtype=np.int64))
+    got_w = host(payload).view(np.uint32).astype(np.int64)
+    ref_w = np.asarray(wref, dtype=np.int64)
+    bad = np.nonzero(got_w != ref_w)[0]
+    if len(bad):
+        woff = np.concatenate([[0], np.cumsum((np.asarray(bref) + 31) // 32)])
+        ks = np.searchsorted(woff, bad[:8], side="right") - 1
+        say("payload mismatches", len(bad), "first", list(bad[:8]), "chunks", list(ks),
+            "gpu", [hex(int(v)) for v in got_w[bad[:8]]], "ref", [hex(int(v)) for v in ref_w[bad[:8]]])
+        _, payload2 = lib.mgard_huffman_encode(dsym, lens, codes, dict_size, chunk)
+        say("repeat run identical:", bool(np.array_equal(host(payload2), host(payload))))
+    assert len(bad) == 0
     # decode the oracle's payload on the GPU
     dec = lib.mgard_huffman_decode(dev(np.asarray(wref, dtype=np.uint32).view(np.int32)),
                                    dev(np.asarray(bref, dtype=np.uint32).view(np.int32)), len(sym), lens,

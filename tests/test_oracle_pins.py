@@ -205,6 +205,16 @@ def test_correction_norm_closed_form_limit():
     assert abs(Am[64, 128] - g["centre_entry"]) <= 1e-12
 
 
+@pytest.mark.parametrize("n", [3, 4, 5, 8, 17, 64, 129])
+def test_column_norm_equals_dense_lapack_norm(n):
+    """The column-by-column operator norm used by the allocation equals the dense LAPACK one."""
+    rng = np.random.default_rng(n)
+    for x in (np.arange(float(n)), fieldgen.random_coords(n, rng, jitter=0.5)):
+        op = grid.make_dimop(x)
+        dense_norm = A.norm_inf(A.correction_matrix(op))
+        assert abs(A.correction_norm(op) - dense_norm) <= 1e-14 * dense_norm
+
+
 def test_norm_invariant_to_uniform_scale():
     a = A.norm_inf(A.correction_matrix(grid.make_dimop(np.arange(9.0))))
     b = A.norm_inf(A.correction_matrix(grid.make_dimop(0.01 * np.arange(9.0) - 4.0)))
