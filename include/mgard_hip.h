@@ -79,13 +79,13 @@ typedef struct {
   uint32_t alloc;         /* mgard_alloc, default MGARD_ALLOC_PLAIN */
   uint32_t dict_size;     /* Huffman dictionary: power of two in [256, 8192]; 0 = 8192 */
   uint32_t chunk_symbols; /* symbols per independently decodable chunk, multiple of 256
-                             in [256, 8192]; 0 = 4096 */
+                             in [256, 8192]; 0 = 1024 */
   uint32_t reserved;
   void* stream;              /* hipStream_t */
   const mgard_model* model;  /* required for MGARD_ALLOC_LEARNED */
 } mgard_opts;
 
-/* Fills *opts with the defaults (REL, PLAIN, 8192, 4096, default stream). */
+/* Fills *opts with the defaults (REL, PLAIN, 8192, 1024, default stream). */
 void mgard_default_opts(mgard_opts* opts);
 
 typedef struct {

@@ -75,7 +75,7 @@ class Parts:
     words: list
 
 
-def compress_parts(u, tol, rel=True, coords=None, dict_size=8192, chunk=4096, bins=None,
+def compress_parts(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bins=None,
                    alloc="plain"):
     u = np.asarray(u)
     T = u.dtype.type
@@ -133,7 +133,7 @@ def serialize(p: Parts, tol, rel, coords, dict_size, chunk, alloc_code=ALLOC_PLA
     return blob
 
 
-def compress(u, tol, rel=True, coords=None, dict_size=8192, chunk=4096, bins=None, alloc="plain"):
+def compress(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bins=None, alloc="plain"):
     p = compress_parts(u, tol, rel, coords, dict_size, chunk, bins, alloc)
     code = ALLOC_PLAIN if (alloc == "plain" and bins is None) else (ALLOC_COUNT if alloc == "count" else ALLOC_LEARNED)
     return serialize(p, tol, rel, coords, dict_size, chunk, code)

@@ -151,7 +151,7 @@ def _dtype_code(t):
     raise TypeError("float32 or float64 tensor expected")
 
 
-def make_opts(eb="rel", alloc="plain", dict_size=8192, chunk=4096, stream=None):
+def make_opts(eb="rel", alloc="plain", dict_size=8192, chunk=1024, stream=None):
     o = mgard_opts()
     load_library().mgard_default_opts(C.byref(o))
     o.eb = REL if eb == "rel" else ABS
@@ -164,7 +164,7 @@ def make_opts(eb="rel", alloc="plain", dict_size=8192, chunk=4096, stream=None):
     return o
 
 
-def mgard_compress_bound(shape, dtype=F32, coords=None, dict_size=8192, chunk=4096):
+def mgard_compress_bound(shape, dtype=F32, coords=None, dict_size=8192, chunk=1024):
     lib = load_library()
     cc = _Coords(coords, len(shape))
     o = mgard_opts()
@@ -176,7 +176,7 @@ def mgard_compress_bound(shape, dtype=F32, coords=None, dict_size=8192, chunk=40
     return int(b)
 
 
-def mgard_compress(u, tol, coords=None, eb="rel", alloc="plain", dict_size=8192, chunk=4096, out=None):
+def mgard_compress(u, tol, coords=None, eb="rel", alloc="plain", dict_size=8192, chunk=1024, out=None):
     """Compresses a CUDA float tensor.  Returns (uint8 CUDA buffer, nbytes, info dict)."""
     torch = _torch()
     lib = load_library()
@@ -294,7 +294,7 @@ def mgard_dequantize(sym, qside, shape, bins, dtype, dict_size=8192):
     return out
 
 
-def mgard_histogram(sym, dict_size=8192, chunk=4096):
+def mgard_histogram(sym, dict_size=8192, chunk=1024):
     torch = _torch()
     lib = load_library()
     n = sym.numel()
@@ -315,7 +315,7 @@ def mgard_huffman_codebook(hist, dict_size=8192):
     return lens, codes
 
 
-def mgard_huffman_encode(sym, lens, codes, dict_size=8192, chunk=4096):
+def mgard_huffman_encode(sym, lens, codes, dict_size=8192, chunk=1024):
     torch = _torch()
     lib = load_library()
     n = sym.numel()
@@ -330,7 +330,7 @@ def mgard_huffman_encode(sym, lens, codes, dict_size=8192, chunk=4096):
     return bits[:nch], payload[: words.value]
 
 
-def mgard_huffman_decode(payload, bits, n, lens, dict_size=8192, chunk=4096):
+def mgard_huffman_decode(payload, bits, n, lens, dict_size=8192, chunk=1024):
     torch = _torch()
     lib = load_library()
     sym = torch.empty(n, dtype=torch.int16, device=payload.device)

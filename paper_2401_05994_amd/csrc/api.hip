@@ -54,7 +54,7 @@ struct Opts {
   int eb = MGARD_REL;
   int alloc = MGARD_ALLOC_PLAIN;
   int dict = 8192;
-  int chunk = 4096;
+  int chunk = 1024;
   hipStream_t st = nullptr;
   const mgard_model* model = nullptr;
 };
@@ -446,7 +446,7 @@ void mgard_default_opts(mgard_opts* o) {
   o->eb = MGARD_REL;
   o->alloc = MGARD_ALLOC_PLAIN;
   o->dict_size = 8192;
-  o->chunk_symbols = 4096;
+  o->chunk_symbols = 1024;
 }
 
 const char* mgard_last_error(void) { return g_err.c_str(); }
@@ -519,12 +519,13 @@ mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
     MG_HIP(hipMemcpyAsync(hb.data(), d_in, kFixed, hipMemcpyDeviceToHost, o.st));
     MG_HIP(hipStreamSynchronize(o.st));
     Parsed P;
-    if (!parse_header(hb.data(), hb.size(), P)) {
-      if (P.need > in_bytes) fail(MGARD_ERR_FORMAT, "truncated header");
+    // the header grows in three parts (fixed, shape, coordinates + bins): read each as it is known
+    for (int part = 0; !parse_header(hb.data(), hb.size(), P); ++part) {
+      if (part == 3 || P.need <= hb.size() || P.need > in_bytes) fail(MGARD_ERR_FORMAT, "truncated header");
       hb.resize(P.need);
       MG_HIP(hipMemcpyAsync(hb.data(), d_in, P.need, hipMemcpyDeviceToHost, o.st));
       MG_HIP(hipStreamSynchronize(o.st));
-      if (!parse_header(hb.data(), hb.size(), P)) fail(MGARD_ERR_FORMAT, "truncated header");
+      P = Parsed();
     }
     check_bins(P, hb.data());
     if (P.hd.total_bytes > in_bytes) fail(MGARD_ERR_FORMAT, "buffer shorter than its header says");

@@ -124,6 +124,7 @@ std::map<std::string, std::shared_ptr<Hierarchy>> g_cache;
 Hierarchy::~Hierarchy() {
   for (int k = 0; k < 2; ++k)
     if (dev_table[k]) (void)hipFree(dev_table[k]);
+  if (dev_itab) (void)hipFree(dev_itab);
 }
 
 std::shared_ptr<Hierarchy> get_hierarchy(uint32_t ndim, const uint64_t* shape,
@@ -205,6 +206,27 @@ std::shared_ptr<Hierarchy> get_hierarchy(uint32_t ndim, const uint64_t* shape,
   h->level_count[0] = h->count(0);
   for (int l = 1; l <= L; ++l) h->level_count[l] = h->count(l) - h->count(l - 1);
   for (int l = 0; l <= L; ++l) h->level_off[l + 1] = h->level_off[l] + h->level_count[l];
+  // sub-grid offsets and strides per level (stream positions of new nodes)
+  h->itab.assign((uint64_t)(L + 1) * 80, 0);
+  for (int l = 1; l <= L; ++l) {
+    uint64_t* it = h->itab.data() + 80 * (uint64_t)l;
+    uint64_t off = 0;
+    for (int m = 1; m < (1 << ndim); ++m) {
+      int64_t ext[MAXD];
+      for (int s = 0; s < MAXD; ++s) {
+        const int d = s - pad;
+        const bool bit = d >= 0 && ((m >> d) & 1);
+        ext[s] = bit ? (h->sizes[l][s] - h->sizes[l - 1][s]) : h->sizes[l - 1][s];
+      }
+      uint64_t acc = 1;
+      for (int s = MAXD - 1; s >= 0; --s) {
+        it[16 + 4 * m + s] = acc;
+        acc *= (uint64_t)ext[s];
+      }
+      it[m] = off;
+      off += acc;
+    }
+  }
   // constant table
   auto& t = h->table;
   auto put = [&](const std::vector<double>& v) {
@@ -243,6 +265,14 @@ const void* device_table(Hierarchy& h, bool f64, hipStream_t stream) {
   MG_HIP(hipGetDevice(&dev));
   const int k = f64 ? 1 : 0;
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!h.dev_itab || h.dev_itab_id != dev) {
+    if (h.dev_itab) (void)hipFree(h.dev_itab);
+    h.dev_itab = nullptr;
+    if (hipMalloc(&h.dev_itab, h.itab.size() * 8) != hipSuccess) fail(MGARD_ERR_OOM, "sub-grid table");
+    MG_HIP(hipMemcpyAsync(h.dev_itab, h.itab.data(), h.itab.size() * 8, hipMemcpyHostToDevice, stream));
+    MG_HIP(hipStreamSynchronize(stream));
+    h.dev_itab_id = dev;
+  }
   if (h.dev_table[k] && h.dev_id[k] == dev) return h.dev_table[k];
   if (h.dev_table[k]) {
     (void)hipFree(h.dev_table[k]);

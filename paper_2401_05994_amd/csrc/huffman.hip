@@ -53,13 +53,17 @@ __global__ void __launch_bounds__(TPB) k_histogram(const uint16_t* __restrict__ 
 }
 
 // ------------------------------------------------------------------ codebook
-// One workgroup.  keys: (count << 16 | symbol), empty bins sort last.
+// One workgroup; everything stays in LDS.  keys: (count << 16 | symbol),
+// empty bins sort last.  After the sort the keys array holds the leaf
+// weights, then (in place) the two-queue merge, then the leaf depths.
 __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ hist, int dict,
                                                    uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
   __shared__ uint64_t keys[MAXDICT];
   __shared__ uint16_t syms[MAXDICT];
+  __shared__ uint8_t lens[MAXDICT];
   __shared__ int nleaf;
   __shared__ uint32_t bl_count[MAXLEN + 1];
+  __shared__ uint64_t next_code[MAXLEN + 1];
   const int t = threadIdx.x;
   const int nt = blockDim.x;
   if (t == 0) nleaf = 0;
@@ -68,6 +72,7 @@ __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ 
   for (int s = t; s < dict; s += nt) {
     const uint64_t c = hist[s];
     keys[s] = c ? ((c << 16) | (uint64_t)s) : ~0ull;
+    lens[s] = 0;
     if (c) atomicAdd(&nleaf, 1);
   }
   __syncthreads();
@@ -88,68 +93,78 @@ __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ 
       __syncthreads();
     }
   }
-  for (int s = t; s < dict; s += nt) len_out[s] = 0;
+  const int n = nleaf;
+  for (int i = t; i < n; i += nt) {
+    syms[i] = (uint16_t)(keys[i] & 0xffff);
+    keys[i] >>= 16;
+  }
+  __syncthreads();
+  if (t == 0 && n > 1) {
+    uint64_t* A = keys;
+    // phase 1: two-queue merge; a consumed internal node's slot takes its parent's index
+    int leaf = 0, root = 0;
+    for (int next = 0; next < n - 1; ++next) {
+      uint64_t w;
+      if (leaf >= n || (root < next && A[root] < A[leaf])) {
+        w = A[root];
+        A[root++] = (uint64_t)next;
+      } else {
+        w = A[leaf++];
+      }
+      if (leaf >= n || (root < next && A[root] < A[leaf])) {
+        w += A[root];
+        A[root++] = (uint64_t)next;
+      } else {
+        w += A[leaf++];
+      }
+      A[next] = w;
+    }
+    // phase 2: internal node depths
+    A[n - 2] = 0;
+    for (int next = n - 3; next >= 0; --next) A[next] = A[A[next]] + 1;
+    // phase 3: leaf depths, deepest for the smallest weights
+    int avbl = 1, used = 0, depth = 0, rt = n - 2, nx = n - 1;
+    while (avbl > 0) {
+      while (rt >= 0 && (int)A[rt] == depth) {
+        ++used;
+        --rt;
+      }
+      while (avbl > used) {
+        A[nx--] = (uint64_t)depth;
+        --avbl;
+      }
+      avbl = 2 * used;
+      ++depth;
+      used = 0;
+    }
+  }
+  __syncthreads();
+  if (n == 1) {
+    if (t == 0) lens[syms[0]] = 1;
+  } else {
+    for (int i = t; i < n; i += nt) lens[syms[i]] = (uint8_t)keys[i];
+  }
+  __syncthreads();
+  for (int s = t; s < dict; s += nt)
+    if (lens[s]) atomicAdd(&bl_count[lens[s]], 1u);
   __syncthreads();
   if (t == 0) {
-    const int n = nleaf;
-    uint64_t* A = keys;  // weights, in place
-    for (int i = 0; i < n; ++i) {
-      syms[i] = (uint16_t)(A[i] & 0xffff);
-      A[i] >>= 16;
-    }
-    if (n == 1) {
-      len_out[syms[0]] = 1;
-    } else if (n > 1) {
-      // phase 1: merge; internal node weights replace consumed entries by their parent index
-      int leaf = 0, root = 0;
-      for (int next = 0; next < n - 1; ++next) {
-        if (leaf >= n || (root < next && A[root] < A[leaf])) {
-          A[next] = A[root];
-          A[root++] = (uint64_t)next;
-        } else {
-          A[next] = A[leaf++];
-        }
-        if (leaf >= n || (root < next && A[root] < A[leaf])) {
-          A[next] += A[root];
-          A[root++] = (uint64_t)next;
-        } else {
-          A[next] += A[leaf++];
-        }
-      }
-      // phase 2: internal node depths
-      A[n - 2] = 0;
-      for (int next = n - 3; next >= 0; --next) A[next] = A[A[next]] + 1;
-      // phase 3: leaf depths, deepest for the smallest weights
-      int avbl = 1, used = 0, depth = 0, rt = n - 2, nx = n - 1;
-      while (avbl > 0) {
-        while (rt >= 0 && (int)A[rt] == depth) {
-          ++used;
-          --rt;
-        }
-        while (avbl > used) {
-          A[nx--] = (uint64_t)depth;
-          --avbl;
-        }
-        avbl = 2 * used;
-        ++depth;
-        used = 0;
-      }
-      for (int i = 0; i < n; ++i) len_out[syms[i]] = (uint8_t)A[i];
-    }
-    // canonical codes: first code per length, then consecutive by symbol
-    for (int s = 0; s < dict; ++s) bl_count[len_out[s]]++;
-    uint64_t first[MAXLEN + 1];
+    // canonical codes: first code per length, then consecutive in symbol order
     uint64_t code = 0;
-    bl_count[0] = 0;
-    first[0] = 0;
+    next_code[0] = 0;
     for (int b = 1; b <= MAXLEN; ++b) {
-      code = (code + bl_count[b - 1]) << 1;
-      first[b] = code;
+      code = (code + (b > 1 ? bl_count[b - 1] : 0)) << 1;
+      next_code[b] = code;
     }
     for (int s = 0; s < dict; ++s) {
-      const int L = len_out[s];
-      codes[s] = L ? first[L]++ : 0ull;
+      const int L = lens[s];
+      keys[s] = L ? next_code[L]++ : 0ull;
     }
+  }
+  __syncthreads();
+  for (int s = t; s < dict; s += nt) {
+    len_out[s] = lens[s];
+    codes[s] = keys[s];
   }
 }
 
@@ -276,68 +291,98 @@ __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym
 }
 
 // ------------------------------------------------------------------ decode
-// tables: count[65] u32, first[65] u64, offset[65] u32, then dict uint16 symbols
+// Canonical decoding tables: per length L, the first code, the count and the
+// offset into the symbols sorted by (length, symbol); lim1[L] is the
+// left-aligned (64-bit) end of the codes of length <= L, minus one, so the
+// length of the next code is the smallest L with window <= lim1[L].
 struct DecTables {
+  uint64_t first[MAXLEN + 1];
+  uint64_t lim1[MAXLEN + 1];
   uint32_t count[MAXLEN + 1];
   uint32_t offset[MAXLEN + 1];
-  uint64_t first[MAXLEN + 1];
-  uint32_t minlen, maxlen, bad;
+  uint32_t minlen, maxlen, bad, pad;
 };
 
-__global__ void k_decode_tables(const uint8_t* __restrict__ len, int dict, DecTables* tab,
-                                uint16_t* __restrict__ sorted) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t cnt[MAXLEN + 1];
-  for (int b = 0; b <= MAXLEN; ++b) cnt[b] = 0;
-  uint32_t bad = 0;
-  for (int s = 0; s < dict; ++s) {
-    if (len[s] > MAXLEN) bad = 1;
-    else cnt[len[s]]++;
+__global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restrict__ len, int dict, DecTables* tab,
+                                                        uint16_t* __restrict__ sorted) {
+  __shared__ uint8_t lens[MAXDICT];
+  __shared__ uint32_t cnt[MAXLEN + 1];
+  __shared__ uint32_t fill[MAXLEN + 1];
+  __shared__ uint32_t bad;
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (t == 0) bad = 0;
+  for (int b = t; b <= MAXLEN; b += nt) cnt[b] = 0;
+  __syncthreads();
+  for (int s = t; s < dict; s += nt) {
+    const uint8_t L = len[s];
+    lens[s] = L;
+    if (L > MAXLEN)
+      atomicOr(&bad, 1u);
+    else if (L)
+      atomicAdd(&cnt[L], 1u);
   }
-  cnt[0] = 0;
-  uint64_t code = 0;
-  uint32_t off = 0, minlen = 0, maxlen = 0;
-  for (int b = 1; b <= MAXLEN; ++b) {
-    code = (code + cnt[b - 1]) << 1;
-    tab->first[b] = code;
-    tab->count[b] = cnt[b];
-    tab->offset[b] = off;
-    off += cnt[b];
-    if (cnt[b]) {
-      if (!minlen) minlen = b;
-      maxlen = b;
+  __syncthreads();
+  if (t == 0) {
+    uint64_t code = 0;
+    uint32_t off = 0, minlen = 0, maxlen = 0;
+    for (int b = 1; b <= MAXLEN; ++b) {
+      code = (code + (b > 1 ? cnt[b - 1] : 0)) << 1;
+      tab->first[b] = code;
+      tab->count[b] = cnt[b];
+      tab->offset[b] = off;
+      fill[b] = off;
+      off += cnt[b];
+      if (cnt[b]) {
+        if (!minlen) minlen = b;
+        maxlen = b;
+      }
+    }
+    // Kraft: the codes of the longest length must fit in that length
+    if (maxlen && maxlen < 64 && tab->first[maxlen] + cnt[maxlen] > (1ull << maxlen)) bad = 1;
+    // left-aligned limits, saturating at 2^64 - 1
+    for (int b = 1; b <= MAXLEN; ++b) {
+      const uint64_t e = tab->first[b] + tab->count[b];
+      uint64_t lim;
+      if (b == 64)
+        lim = e ? e - 1 : 0;
+      else if (e >= (1ull << b))
+        lim = ~0ull;
+      else
+        lim = e ? (e << (64 - b)) - 1 : 0;
+      tab->lim1[b] = lim;
+    }
+    tab->first[0] = 0;
+    tab->count[0] = 0;
+    tab->offset[0] = 0;
+    tab->lim1[0] = 0;
+    tab->minlen = minlen;
+    tab->maxlen = maxlen;
+    tab->bad = bad;
+    for (int s = 0; s < dict; ++s) {
+      const int L = lens[s];
+      if (L && L <= MAXLEN) sorted[fill[L]++] = (uint16_t)s;
     }
   }
-  tab->first[0] = 0;
-  tab->count[0] = 0;
-  tab->offset[0] = 0;
-  // Kraft check: a canonical prefix code must not overflow its last length
-  if (maxlen && (tab->first[maxlen] + cnt[maxlen]) > (1ull << maxlen) && maxlen < 64) bad = 1;
-  uint32_t fill[MAXLEN + 1];
-  for (int b = 0; b <= MAXLEN; ++b) fill[b] = tab->offset[b];
-  for (int s = 0; s < dict; ++s)
-    if (len[s] && len[s] <= MAXLEN) sorted[fill[len[s]]++] = (uint16_t)s;
-  tab->minlen = minlen;
-  tab->maxlen = maxlen;
-  tab->bad = bad;
 }
 
 // One thread per chunk.  status[0] is set to 1 on malformed input.
-__global__ void __launch_bounds__(TPB) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
-                                                const uint64_t* __restrict__ word_off,
-                                                const uint32_t* __restrict__ chunk_bits, uint64_t n, int chunk,
-                                                uint64_t nch, const DecTables* __restrict__ tab,
-                                                const uint16_t* __restrict__ sorted, uint16_t* __restrict__ sym,
-                                                const uint64_t* __restrict__ esc_off, uint64_t n_out,
-                                                const int64_t* __restrict__ outliers, int64_t* __restrict__ qside,
-                                                uint32_t* __restrict__ status) {
-  __shared__ uint32_t cnt[MAXLEN + 1], offs[MAXLEN + 1];
-  __shared__ uint64_t first[MAXLEN + 1];
+__global__ void __launch_bounds__(64) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
+                                               const uint64_t* __restrict__ word_off,
+                                               const uint32_t* __restrict__ chunk_bits, uint64_t n, int chunk,
+                                               uint64_t nch, const DecTables* __restrict__ tab,
+                                               const uint16_t* __restrict__ sorted_g, int dict,
+                                               uint16_t* __restrict__ sym, const uint64_t* __restrict__ esc_off,
+                                               uint64_t n_out, const int64_t* __restrict__ outliers,
+                                               int64_t* __restrict__ qside, uint32_t* __restrict__ status) {
+  __shared__ uint64_t first[MAXLEN + 1], lim1[MAXLEN + 1];
+  __shared__ uint32_t offs[MAXLEN + 1];
+  __shared__ uint16_t sorted[MAXDICT];
   for (int b = threadIdx.x; b <= MAXLEN; b += blockDim.x) {
-    cnt[b] = tab->count[b];
-    offs[b] = tab->offset[b];
     first[b] = tab->first[b];
+    lim1[b] = tab->lim1[b];
+    offs[b] = tab->offset[b];
   }
+  for (int s = threadIdx.x; s < dict; s += blockDim.x) sorted[s] = sorted_g[s];
   __syncthreads();
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nch) return;
@@ -347,7 +392,7 @@ __global__ void __launch_bounds__(TPB) k_decode(const uint32_t* __restrict__ pay
   }
   const uint64_t w0 = word_off[k], w1 = word_off[k + 1];
   const uint64_t nbits = chunk_bits[k];
-  if (w1 > payload_words || w1 < w0) {
+  if (w1 > payload_words || w1 < w0 || nbits > 32 * (w1 - w0)) {
     atomicOr(status, 1u);
     return;
   }
@@ -355,38 +400,75 @@ __global__ void __launch_bounds__(TPB) k_decode(const uint32_t* __restrict__ pay
   const uint64_t cntk = min((uint64_t)chunk, n - beg);
   const int minlen = (int)tab->minlen, maxlen = (int)tab->maxlen;
   const uint32_t* src = payload + w0;
-  uint64_t buf = 0;  // left-aligned bit buffer
+  const uint64_t nw = w1 - w0;
+  uint64_t buf = 0;  // left-aligned bits
   int have = 0;
   uint64_t next_word = 0, consumed = 0;
   uint64_t eo = esc_off ? esc_off[k] : 0;  // escapes are resolved only when outliers are given
+  uint64_t pack = 0;
+  const bool fast = maxlen <= 32;
   for (uint64_t i = 0; i < cntk; ++i) {
-    uint64_t code = 0;
-    int L = 0;
-    int s = -1;
-    while (L < maxlen) {
-      if (have == 0) {
-        if (next_word >= w1 - w0) break;
-        buf = (uint64_t)src[next_word++] << 32;
-        have = 32;
+    // keep at least 33 valid bits at the top of the buffer
+    while (have <= 32) {
+      const uint64_t w = next_word < nw ? (uint64_t)src[next_word] : 0ull;
+      ++next_word;
+      buf |= w << (32 - have);
+      have += 32;
+    }
+    int s;
+    if (fast) {
+      // code length: the smallest L in [minlen, maxlen] with buf <= lim1[L]
+      int lo = minlen, hi = maxlen;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (buf <= lim1[mid])
+          hi = mid;
+        else
+          lo = mid + 1;
       }
-      code = (code << 1) | (buf >> 63);
-      buf <<= 1;
-      --have;
-      ++consumed;
-      ++L;
-      if (L >= minlen) {
-        const uint64_t d = code - first[L];
-        if (code >= first[L] && d < cnt[L]) {
-          s = sorted[offs[L] + (uint32_t)d];
+      const int L = lo;
+      const uint64_t v = buf >> (64 - L);
+      if (buf > lim1[L] || v < first[L]) {
+        atomicOr(status, 1u);
+        return;
+      }
+      s = sorted[offs[L] + (uint32_t)(v - first[L])];
+      buf <<= L;
+      have -= L;
+      consumed += L;
+    } else {
+      // codes longer than 32 bits exist: decode one bit at a time
+      uint64_t code = 0;
+      s = -1;
+      for (int L = 1; L <= maxlen; ++L) {
+        if (have == 0) {
+          buf = (next_word < nw ? (uint64_t)src[next_word] : 0ull) << 32;
+          ++next_word;
+          have = 32;
+        }
+        code = (code << 1) | (buf >> 63);
+        buf <<= 1;
+        --have;
+        ++consumed;
+        if (L >= minlen && code >= first[L] && code - first[L] < tab->count[L]) {
+          s = sorted[offs[L] + (uint32_t)(code - first[L])];
           break;
         }
       }
+      if (s < 0) {
+        atomicOr(status, 1u);
+        return;
+      }
     }
-    if (s < 0 || consumed > nbits) {
+    if (consumed > nbits) {
       atomicOr(status, 1u);
       return;
     }
-    sym[beg + i] = (uint16_t)s;
+    pack |= (uint64_t)(uint16_t)s << (16 * (i & 3));
+    if ((i & 3) == 3) {
+      *reinterpret_cast<uint64_t*>(sym + beg + i - 3) = pack;
+      pack = 0;
+    }
     if (s == 0 && qside) {
       if (eo >= n_out) {
         atomicOr(status, 1u);
@@ -395,6 +477,7 @@ __global__ void __launch_bounds__(TPB) k_decode(const uint32_t* __restrict__ pay
       qside[beg + i] = outliers[eo++];
     }
   }
+  for (uint64_t i = cntk & ~3ull; i < cntk; ++i) sym[beg + i] = (uint16_t)(pack >> (16 * (i & 3)));
   if (consumed != nbits) atomicOr(status, 1u);
 }
 
@@ -470,13 +553,13 @@ void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const u
   Carver cv(table_scratch);
   DecTables* tab = cv.take<DecTables>(1);
   uint16_t* sorted = cv.take<uint16_t>((uint64_t)dict);
-  hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(64), 0, st, len, dict, tab, sorted);
+  hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(1024), 0, st, len, dict, tab, sorted);
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch) {
     const unsigned blocks = (unsigned)((nch + 63) / 64);
     KernelTimer kt("decode", st);
     hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(64), 0, st, payload, payload_words, word_off, chunk_bits, n,
-                       chunk, nch, tab, sorted, sym, esc_off, n_out, outliers, qside, d_status);
+                       chunk, nch, tab, sorted, dict, sym, esc_off, n_out, outliers, qside, d_status);
   }
   MG_HIP(hipGetLastError());
 }

@@ -78,6 +78,10 @@ struct Hierarchy {
   std::vector<double> table;                        // concatenated FP64 constants
   void* dev_table[2] = {nullptr, nullptr};          // table cast to float / double
   int dev_id[2] = {-1, -1};
+  // per level l, 80 entries at l*80: sub-grid offsets [16], then C-order strides [16][4]
+  std::vector<uint64_t> itab;
+  void* dev_itab = nullptr;
+  int dev_itab_id = -1;
   uint64_t count(int l) const {
     uint64_t n = 1;
     for (int s = 0; s < MAXD; ++s) n *= (uint64_t)sizes[l][s];
@@ -132,8 +136,7 @@ struct LevelGeom {
   const T* wl[MAXD];
   const T* wr[MAXD];
   uint64_t level_off;                // stream offset of this level
-  uint64_t sub_off[16];              // sub-grid offsets inside the level (by user mask)
-  uint64_t sub_stride[16][MAXD];     // C-order strides of each sub-grid (slot layout)
+  const uint64_t* sub;               // device: sub-grid offsets [16] then strides [16][4] of this level
 };
 
 template <typename T>

@@ -68,11 +68,11 @@ __device__ inline int coarse_idx(int i, int s, const LevelGeom<T>& g) {
 template <typename T>
 __device__ inline uint64_t stream_pos(const Coord& c, int mslot, const LevelGeom<T>& g) {
   const int m = mslot >> g.pad_slots;
-  uint64_t pos = g.level_off + g.sub_off[m];
+  uint64_t pos = g.level_off + g.sub[m];
 #pragma unroll
   for (int s = 0; s < MAXD; ++s) {
     int idx = ((mslot >> s) & 1) ? (c.i[s] >> 1) : coarse_idx(c.i[s], s, g);
-    pos += (uint64_t)idx * g.sub_stride[m][s];
+    pos += (uint64_t)idx * g.sub[16 + 4 * m + s];
   }
   return pos;
 }
@@ -397,23 +397,7 @@ LevelGeom<T> level_geom(const Hierarchy& h, int l, const T* table) {
     g.wr[s] = h.active[s] ? table + h.devoff[l][s].wr : nullptr;
   }
   g.level_off = h.level_off[l];
-  uint64_t off = 0;
-  const int D = h.D;
-  for (int m = 1; m < (1 << D); ++m) {
-    int64_t ext[MAXD];
-    for (int s = 0; s < MAXD; ++s) {
-      int d = s - g.pad_slots;
-      bool bit = d >= 0 && ((m >> d) & 1);
-      ext[s] = bit ? (h.sizes[l][s] - h.sizes[l - 1][s]) : h.sizes[l - 1][s];
-    }
-    uint64_t acc = 1;
-    for (int s = MAXD - 1; s >= 0; --s) {
-      g.sub_stride[m][s] = acc;
-      acc *= (uint64_t)ext[s];
-    }
-    g.sub_off[m] = off;
-    off += acc;
-  }
+  g.sub = static_cast<const uint64_t*>(h.dev_itab) + 80 * (uint64_t)l;
   return g;
 }
 

@@ -194,6 +194,27 @@ def test_huffman_stages_bitexact(lib, case):
     assert np.array_equal(lib.u16(dec).astype(np.int64), sym)
 
 
+def test_huffman_long_codes_bitexact(lib):
+    """A complete prefix code with lengths 1..40 (codes longer than 32 bits) through encode and decode."""
+    say("huffman long codes")
+    dict_size, chunk = 256, 256
+    lens = np.zeros(dict_size, dtype=np.int64)
+    lens[:41] = list(range(1, 41)) + [40]
+    codes = H.canonical_codes(lens)
+    rng = np.random.default_rng(3)
+    sym = rng.integers(0, 41, size=5001)
+    bref, wref = H.encode(sym, lens, codes, chunk)
+    dlens = dev(lens.astype(np.uint8))
+    dcodes = dev(codes.view(np.int64))
+    bits, payload = lib.mgard_huffman_encode(dev(sym.astype(np.int16)), dlens, dcodes, dict_size, chunk)
+    assert list(host(bits).astype(np.int64)) == bref
+    assert np.array_equal(host(payload).view(np.uint32).astype(np.int64), np.asarray(wref, dtype=np.int64))
+    dec = lib.mgard_huffman_decode(dev(np.asarray(wref, dtype=np.uint32).view(np.int32)),
+                                   dev(np.asarray(bref, dtype=np.uint32).view(np.int32)), len(sym), dlens,
+                                   dict_size, chunk)
+    assert np.array_equal(lib.u16(dec).astype(np.int64), sym)
+
+
 @pytest.mark.parametrize("name,tol", [("c1-129x129-f64", 1e-3), ("c1-129x129-f64", 1e-5),
                                       ("3d-33x20x17-f32-nonuniform", 1e-2), ("3d-65x65x65-f32", 1e-3),
                                       ("even-64x50-f32", 1e-4), ("4d-9x10x7x6-f64", 1e-3)])
