@@ -67,19 +67,27 @@ def _periodic_side(n: int) -> int:
     return n - 1 if (n % 2 == 1 and n > 1) else n
 
 
-def spectral(shape, beta: float, seed: int, device: str = "cpu"):
-    """Spectral synthesis with E(k) ~ k^beta; returns float64 (numpy on cpu, torch on cuda)."""
+def spectral(shape, beta: float, seed: int, device: str = "cpu", noise: str = "numpy"):
+    """Spectral synthesis with E(k) ~ k^beta; returns float64 (numpy on cpu, torch on cuda).
+
+    noise="numpy" draws the white noise with numpy's PCG64 (default_rng(seed));
+    noise="torch" draws it on `device` with torch's generator seeded by `seed`
+    (used for the large training and evaluation sets, where host generation
+    would dominate).
+    """
     import torch
 
     shape = tuple(int(s) for s in shape)
     D = len(shape)
     m = tuple(_periodic_side(s) for s in shape)
-    rng = np.random.default_rng(seed)
-    noise = rng.standard_normal(size=m)
-    w = torch.from_numpy(noise)
-    del noise
-    if device != "cpu":
-        w = w.to(device)
+    if noise == "torch":
+        g = torch.Generator(device=device).manual_seed(int(seed))
+        w = torch.randn(m, generator=g, device=device, dtype=torch.float64)
+    else:
+        rng = np.random.default_rng(seed)
+        w = torch.from_numpy(rng.standard_normal(size=m))
+        if device != "cpu":
+            w = w.to(device)
     W = torch.fft.rfftn(w)
     del w
     mag = W.abs()

@@ -210,6 +210,64 @@ mgard_status mgard_plain_constant(uint32_t ndim, const uint64_t* shape,
                                   const double* const* coords, double* h_S, double* h_K,
                                   uint32_t max_levels);
 
+/* ----------------------------------------------------- learned allocation
+ * A project addition (the paper defines no learned component; it motivates
+ * higher-ratio compression for AI workloads, Sec. 1).  A small network maps
+ * four features of a level's coefficients -- log(rms/tau), log(max|c|/tau),
+ * log(count), l/L, normalised by a stored mean and standard deviation -- to
+ * theta_l; the level's bin width is b_plain * exp(clamp(theta_l, -3, 5)).
+ * With opts->alloc = MGARD_ALLOC_LEARNED and opts->model set, mgard_compress
+ * decomposes, evaluates the network, quantizes, recomposes on the device and
+ * measures max|u - u~|; when it exceeds tau the plain widths are used instead
+ * (mgard_info.fallback_used = 1, header fallback byte set).  No extra host
+ * synchronisation is added.
+ *
+ * Parameters: MGARD_MLP_NPARAM float32 values, layout mean[4], std[4],
+ * W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3[1] (y = x W^T + b,
+ * Linear(4,64)-ReLU-Linear(64,64)-ReLU-Linear(64,1)). */
+#define MGARD_MLP_NPARAM 4553
+#define MGARD_MLP_IN 4
+#define MGARD_MLP_HID 64
+#define MGARD_MLP_CACHE_PER_ROW 260 /* floats of d_cache per batch row */
+
+/* Copies h_params (n_params == MGARD_MLP_NPARAM) to the current device.
+ * MGARD_ERR_ARG for non-finite values or non-positive feature scales. */
+mgard_status mgard_model_create(const float* h_params, uint64_t n_params, mgard_model** out);
+void mgard_model_free(mgard_model* model);
+
+/* Per level of a coefficient stream (stream order as above): h_stats[3l] =
+ * count, h_stats[3l+1] = sum of squares (float64), h_stats[3l+2] = max |c|. */
+mgard_status mgard_level_stats(uint32_t ndim, const uint64_t* shape, mgard_dtype dtype,
+                               const void* d_coeff, double* h_stats, const mgard_opts* opts);
+
+/* max |a_i - b_i| over n values of dtype, evaluated in float64, into *h_err. */
+mgard_status mgard_linf_error(mgard_dtype dtype, const void* d_a, const void* d_b, uint64_t n,
+                              double* h_err, const mgard_opts* opts);
+
+/* Network forward over `batch` rows of raw features d_x (batch x 4, float32)
+ * into d_out (batch).  d_cache (nullable, batch x MGARD_MLP_CACHE_PER_ROW)
+ * keeps the normalised input and the activations for mgard_mlp_backward.
+ * Sums run in a fixed order; the results are reproducible. */
+mgard_status mgard_mlp_forward(const float* d_params, const float* d_x, uint32_t batch,
+                               float* d_out, float* d_cache, const mgard_opts* opts);
+
+/* Gradients of the loss with respect to the weights (same layout as the
+ * parameters; the mean/std entries are set to 0) from d_dout = dLoss/dout. */
+mgard_status mgard_mlp_backward(const float* d_params, const float* d_cache, const float* d_dout,
+                                uint32_t batch, float* d_grads, const mgard_opts* opts);
+
+/* Mean squared error 1/B sum (pred - target)^2 into *h_loss and its gradient
+ * 2/B (pred - target) into d_dout. */
+mgard_status mgard_mlp_mse(const float* d_pred, const float* d_target, uint32_t batch,
+                           float* d_dout, double* h_loss, const mgard_opts* opts);
+
+/* One Adam step (bias-corrected, step counts from 1) on the weights; the
+ * feature normalisation entries are left unchanged.  d_m, d_v: moment
+ * buffers of MGARD_MLP_NPARAM floats, zero before the first step. */
+mgard_status mgard_mlp_adam(float* d_params, const float* d_grads, float* d_m, float* d_v,
+                            uint32_t step, float lr, float beta1, float beta2, float eps,
+                            const mgard_opts* opts);
+
 /* ----------------------------------------------------------- measurement
  * Kernel timing with HIP events recorded on each launch's stream.
  * mgard_timing(1) clears earlier records and starts recording; (0) clears and

@@ -77,3 +77,56 @@ def adam_step(params, grads, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=
             vh = v[k][j] / (1.0 - beta2 ** t)
             params[k][j] = params[k][j] - lr * mh / (np.sqrt(vh) + eps)
     return params, m, v
+
+
+# Features of a level (float64): log(rms/tau), log(max|c|/tau), log(count), l/L.
+def level_features(stats, tau):
+    """stats: (L+1, 3) rows of (count, sum of squares, max |c|)."""
+    stats = np.asarray(stats, dtype=np.float64)
+    nlev = stats.shape[0]
+    tau = tau if tau > 0 else 1.0
+    out = np.zeros((nlev, 4))
+    for l in range(nlev):
+        cnt, ss, mx = stats[l]
+        rms = np.sqrt(ss / (cnt if cnt > 0 else 1.0))
+        out[l] = [np.log(rms / tau + 1e-30), np.log(mx / tau + 1e-30), np.log(cnt if cnt > 0 else 1.0),
+                  l / (nlev - 1) if nlev > 1 else 0.0]
+    return out
+
+
+def level_stats(stream, offsets):
+    """(count, sum of squares, max |c|) per level of a coefficient stream (float64)."""
+    rows = []
+    for l in range(len(offsets) - 1):
+        c = np.asarray(stream[offsets[l]:offsets[l + 1]], dtype=np.float64)
+        rows.append([len(c), float(np.sum(c * c)), float(np.max(np.abs(c))) if len(c) else 0.0])
+    return np.asarray(rows)
+
+
+def pack(params, mean, std):
+    """Flat parameter vector: mean[4], std[4], W1, b1, W2, b2, W3, b3 (row-major)."""
+    parts = [np.asarray(mean, dtype=np.float64).ravel(), np.asarray(std, dtype=np.float64).ravel()]
+    for W, b in params:
+        parts += [np.asarray(W).ravel(), np.asarray(b).ravel()]
+    return np.concatenate(parts)
+
+
+def unpack(flat, sizes=(4, 64, 64, 1)):
+    flat = np.asarray(flat, dtype=np.float64)
+    F = sizes[0]
+    mean, std = flat[:F], flat[F:2 * F]
+    pos = 2 * F
+    params = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        W = flat[pos:pos + fo * fi].reshape(fo, fi)
+        pos += fo * fi
+        b = flat[pos:pos + fo]
+        pos += fo
+        params.append([W, b])
+    return params, mean, std
+
+
+def learned_bins(plain_bins, theta):
+    """b_l = b_plain * exp(clamp(theta_l, -3, 5))."""
+    t = np.clip(np.asarray(theta, dtype=np.float64).ravel(), -3.0, 5.0)
+    return [float(b) * float(np.exp(x)) for b, x in zip(plain_bins, t)]

@@ -382,3 +382,126 @@ def mgard_timing_report():
         name, n, ms = line.split()
         out[name] = (int(n), float(ms))
     return out
+
+
+# ------------------------------------------------------------- learned allocation
+MLP_NPARAM, MLP_IN, MLP_HID, MLP_CACHE_PER_ROW = 4553, 4, 64, 260
+
+
+def _learned_sigs(lib):
+    P, U32, U64 = C.c_void_p, C.c_uint32, C.c_uint64
+    sig = {
+        "mgard_model_create": (C.c_int, [P, U64, C.POINTER(C.c_void_p)]),
+        "mgard_model_free": (None, [P]),
+        "mgard_level_stats": (C.c_int, [U32, C.POINTER(U64), C.c_int, P, C.POINTER(C.c_double), P]),
+        "mgard_linf_error": (C.c_int, [C.c_int, P, P, U64, C.POINTER(C.c_double), P]),
+        "mgard_mlp_forward": (C.c_int, [P, P, U32, P, P, P]),
+        "mgard_mlp_backward": (C.c_int, [P, P, P, U32, P, P]),
+        "mgard_mlp_mse": (C.c_int, [P, P, U32, P, C.POINTER(C.c_double), P]),
+        "mgard_mlp_adam": (C.c_int, [P, P, P, P, U32, C.c_float, C.c_float, C.c_float, C.c_float, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        if f.argtypes is None:
+            f.restype = res
+            f.argtypes = args
+    return lib
+
+
+class Model:
+    """Device copy of the network parameters (mgard_model*)."""
+
+    def __init__(self, params):
+        lib = _learned_sigs(load_library())
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.size != MLP_NPARAM:
+            raise ValueError(f"{MLP_NPARAM} parameters expected")
+        h = C.c_void_p(0)
+        _check(lib.mgard_model_create(p.ctypes.data, p.size, C.byref(h)))
+        self.handle = h
+        self.params = p
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mgard_model_free(self.handle)
+            self.handle = None
+
+
+def mgard_compress_learned(u, tol, model: Model, coords=None, eb="rel", dict_size=8192, chunk=1024, out=None):
+    """Compression with the learned per-level bin widths (plain widths when the check fails)."""
+    torch = _torch()
+    lib = load_library()
+    u = u.contiguous()
+    dt = _dtype_code(u)
+    shape = tuple(u.shape)
+    cc = _Coords(coords, len(shape))
+    o = make_opts(eb, "learned", dict_size, chunk)
+    o.model = model.handle
+    bound = mgard_compress_bound(shape, dt, coords, dict_size, chunk)
+    if out is None:
+        out = torch.empty(bound, dtype=torch.uint8, device=u.device)
+    nbytes = C.c_uint64(0)
+    info = mgard_info()
+    _check(lib.mgard_compress(len(shape), _shape(shape), cc.ptr, dt, float(tol), _ptr(u), _ptr(out),
+                              out.numel(), C.byref(nbytes), C.byref(o), C.byref(info)))
+    L = info.levels
+    return out, int(nbytes.value), {
+        "tau_abs": info.tau_abs, "bins": [info.bin_width[i] for i in range(L + 1)], "levels": L,
+        "linf_err": info.linf_err, "fallback_used": info.fallback_used, "out_bytes": info.out_bytes,
+        "n_outliers": info.n_outliers,
+    }
+
+
+def mgard_level_stats(coeff, shape):
+    lib = _learned_sigs(load_library())
+    L, _ = mgard_stream_layout(shape)
+    st = (C.c_double * (3 * (L + 1)))()
+    o = make_opts()
+    _check(lib.mgard_level_stats(len(shape), _shape(shape), _dtype_code(coeff), _ptr(coeff), st, C.byref(o)))
+    return np.array(list(st)).reshape(L + 1, 3)
+
+
+def mgard_linf_error(a, b):
+    lib = _learned_sigs(load_library())
+    e = C.c_double(0)
+    o = make_opts()
+    _check(lib.mgard_linf_error(_dtype_code(a), _ptr(a), _ptr(b), a.numel(), C.byref(e), C.byref(o)))
+    return e.value
+
+
+def mgard_mlp_forward(params, x, cache=True):
+    """params: float32 CUDA (MLP_NPARAM); x: float32 CUDA (B, 4) raw features."""
+    torch = _torch()
+    lib = _learned_sigs(load_library())
+    B = x.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=x.device)
+    cch = torch.empty(B * MLP_CACHE_PER_ROW, dtype=torch.float32, device=x.device) if cache else None
+    o = make_opts()
+    _check(lib.mgard_mlp_forward(_ptr(params), _ptr(x.contiguous()), B, _ptr(out), _ptr(cch), C.byref(o)))
+    return out, cch
+
+
+def mgard_mlp_backward(params, cache, dout, batch):
+    torch = _torch()
+    lib = _learned_sigs(load_library())
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=params.device)
+    o = make_opts()
+    _check(lib.mgard_mlp_backward(_ptr(params), _ptr(cache), _ptr(dout), batch, _ptr(g), C.byref(o)))
+    return g
+
+
+def mgard_mlp_mse(pred, target):
+    torch = _torch()
+    lib = _learned_sigs(load_library())
+    d = torch.empty_like(pred)
+    loss = C.c_double(0)
+    o = make_opts()
+    _check(lib.mgard_mlp_mse(_ptr(pred), _ptr(target), pred.numel(), _ptr(d), C.byref(loss), C.byref(o)))
+    return d, loss.value
+
+
+def mgard_mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    lib = _learned_sigs(load_library())
+    o = make_opts()
+    _check(lib.mgard_mlp_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(step), lr, beta1, beta2, eps,
+                              C.byref(o)))

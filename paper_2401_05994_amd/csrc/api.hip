@@ -21,9 +21,22 @@
 
 #include "internal.hpp"
 
+// Device-resident network parameters (MLP layout of internal.hpp).
+struct mgard_model {
+  float* d_params = nullptr;
+  int device = -1;
+};
+
 namespace mg {
 
 void fail(mgard_status code, const std::string& msg) { throw Failure{code, msg}; }
+
+static const float* model_params(const mgard_model* m) {
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev));
+  if (!m->d_params || m->device != dev) fail(MGARD_ERR_ARG, "model lives on another device");
+  return m->d_params;
+}
 
 namespace {
 
@@ -57,6 +70,7 @@ struct Opts {
   int chunk = 1024;
   hipStream_t st = nullptr;
   const mgard_model* model = nullptr;
+  const float* model_params = nullptr;  // device parameters of the model
 };
 
 Opts read_opts(const mgard_opts* o) {
@@ -125,7 +139,7 @@ uint64_t bound_of(const Hierarchy& h, const double* const* coords, int dict, int
 
 struct Finale {  // device results read back by the host at the end
   uint64_t total_bytes, n_outliers, payload_words, pad;
-  double scalars[8];  // tau_abs, maxabs, nonfinite, tau_eff
+  double scalars[8];  // tau_abs, maxabs, nonfinite, tau_eff, measured Linf, fallback used
   double bins[MAXL + 1];
 };
 
@@ -136,7 +150,8 @@ __global__ void k_outlier_offset(const uint64_t* word_off, uint64_t nch, uint64_
 
 __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* esc_off, uint64_t nch,
                            const uint64_t* ooff, const double* scalars, const double* bins, int L,
-                           uint64_t bins_off, int fallback, Finale* fin) {
+                           uint64_t bins_off, int learned, Finale* fin) {
+  const int fallback = learned && scalars[5] != 0.0 ? 1 : 0;
   if (threadIdx.x != 0) return;
   const uint64_t pw = word_off[nch], no = esc_off[nch];
   double* hd = reinterpret_cast<double*>(out);
@@ -151,7 +166,11 @@ __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* 
   fin->total_bytes = *ooff + 8 * no;
   fin->n_outliers = no;
   fin->payload_words = pw;
-  for (int i = 0; i < 4; ++i) fin->scalars[i] = scalars[i];
+  for (int i = 0; i < 6; ++i) fin->scalars[i] = scalars[i];
+  if (!learned) {
+    fin->scalars[4] = -1.0;
+    fin->scalars[5] = 0.0;
+  }
   for (int l = 0; l <= L; ++l) fin->bins[l] = bins[l];
 }
 
@@ -314,10 +333,20 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
                   carve_size<double>(MAXL + 1) + carve_size<double>(8) + carve_size<uint64_t>(4) +
                   2 * carve_size<uint64_t>((uint64_t)o.dict) + 2 * carve_size<uint64_t>(nch + 1) +
                   carve_size<Finale>(1) + 4096;
+  const int nl = h.L + 1;
+  const uint64_t lbytes =
+      o.alloc == MGARD_ALLOC_LEARNED
+          ? 2 * carve_size<T>(n) + carve_size<uint64_t>(MAXL + 2) + carve_size<double>((uint64_t)2 * nl * STATS_BLOCKS) +
+                carve_size<double>(3 * (MAXL + 1)) + carve_size<float>((uint64_t)MLP_IN * (MAXL + 1)) +
+                carve_size<float>(MAXL + 1) + carve_size<float>((uint64_t)2 * MLP_HID * (MAXL + 1)) +
+                carve_size<double>(MAXL + 1) + carve_size<unsigned long long>(1) + 1024
+          : 0;
+  need += lbytes;
   Workspace& ws = workspace();
   ws.reserve(need);
   Carver cv(ws.base());
   void* dscratch = cv.take<char>(dbytes);
+  void* learned_scratch = lbytes ? cv.take<char>(lbytes) : nullptr;
   uint16_t* sym = cv.take<uint16_t>(n);
   int64_t* qside = cv.take<int64_t>(n);
   double* bins = cv.take<double>(MAXL + 1);
@@ -342,13 +371,44 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
   const int alloc = o.alloc == MGARD_ALLOC_COUNT ? MGARD_ALLOC_COUNT : MGARD_ALLOC_PLAIN;
   launch_bins(f64 ? 1 : 0, &misc[0], tol, o.eb, h.S, h.L, alloc, ba, bins, scalars, st);
 
-  // decomposition with fused quantization
   QuantOut q;
   q.sym = sym;
   q.qside = qside;
   q.bins = bins;
   q.R = o.dict / 2;
-  decompose<T>(h, table, d_in, nullptr, &q, dscratch, st);
+  const int nlev = h.L + 1;
+  if (o.alloc == MGARD_ALLOC_LEARNED) {
+    // float coefficients -> level statistics -> network -> bin widths; the
+    // recomposed result is checked on the device and the plain widths are
+    // kept when the L-infinity error exceeds tau
+    Carver lv(learned_scratch);
+    T* cstream = lv.take<T>(n);
+    T* recon = lv.take<T>(n);
+    uint64_t* d_off = lv.take<uint64_t>(MAXL + 2);
+    double* part = lv.take<double>((uint64_t)2 * nlev * STATS_BLOCKS);
+    double* stats = lv.take<double>(3 * (MAXL + 1));
+    float* x = lv.take<float>((uint64_t)MLP_IN * (MAXL + 1));
+    float* theta = lv.take<float>(MAXL + 1);
+    float* tmp = lv.take<float>((uint64_t)2 * MLP_HID * (MAXL + 1));
+    double* learned = lv.take<double>(MAXL + 1);
+    unsigned long long* err = lv.take<unsigned long long>(1);
+    MG_HIP(hipMemcpyAsync(d_off, h.level_off.data(), 8 * (h.L + 2), hipMemcpyHostToDevice, st));
+    decompose<T>(h, table, d_in, cstream, nullptr, dscratch, st);
+    launch_level_stats<T>(cstream, d_off, nlev, part, stats, st);
+    launch_features(stats, scalars, nlev, o.model_params, x, st);
+    mlp_forward(o.model_params, x, nlev, theta, nullptr, tmp, st);
+    launch_apply_theta(bins, theta, nlev, learned, st);
+    launch_quantize<T>(cstream, n, d_off, nlev, learned, q.R, sym, qside, st);
+    QuantOut ql = q;
+    ql.bins = learned;
+    recompose<T>(h, table, nullptr, &ql, recon, dscratch, st);
+    launch_linf<T>(recon, d_in, n, err, st);
+    launch_select_bins(err, scalars, bins, learned, nlev, st);
+    launch_quantize<T>(cstream, n, d_off, nlev, bins, q.R, sym, qside, st);
+  } else {
+    // decomposition with fused quantization
+    decompose<T>(h, table, d_in, nullptr, &q, dscratch, st);
+  }
 
   // lossless stage, tables written in place
   uint32_t* chunk_esc = reinterpret_cast<uint32_t*>(d_out + y.chunk_esc);
@@ -364,7 +424,7 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
                 esc_off, qside, d_out, &misc[1], st);
   hipLaunchKernelGGL(k_zero_pad, dim3(1), dim3(1), 0, st, d_out, word_off, nch, y.payload);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, d_out, word_off, esc_off, nch, &misc[1], scalars, bins,
-                     h.L, y.bins, 0, fin);
+                     h.L, y.bins, o.alloc == MGARD_ALLOC_LEARNED ? 1 : 0, fin);
   MG_HIP(hipGetLastError());
   Finale hf;
   MG_HIP(hipMemcpyAsync(&hf, fin, sizeof(Finale), hipMemcpyDeviceToHost, st));
@@ -377,13 +437,13 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
     info->tau_abs = hf.scalars[0];
     info->maxabs = hf.scalars[1];
     for (int l = 0; l <= h.L; ++l) info->bin_width[l] = hf.bins[l];
-    info->linf_err = -1.0;
+    info->linf_err = hf.scalars[4];
     info->n_symbols = n;
     info->n_outliers = hf.n_outliers;
     info->payload_words = hf.payload_words;
     info->out_bytes = hf.total_bytes;
     info->levels = (uint32_t)h.L;
-    info->fallback_used = 0;
+    info->fallback_used = hf.scalars[5] != 0.0 ? 1u : 0u;
   }
 }
 
@@ -479,7 +539,10 @@ mgard_status mgard_compress(uint32_t ndim, const uint64_t* shape, const double* 
     (void)ts;
     if (!d_in || !d_out || !out_bytes) fail(MGARD_ERR_ARG, "null buffer");
     if (!(tol > 0.0) || !std::isfinite(tol)) fail(MGARD_ERR_TOL, "tolerance must be positive and finite");
-    if (o.alloc == MGARD_ALLOC_LEARNED) fail(MGARD_ERR_ARG, "learned allocation needs mgard_compress_learned");
+    if (o.alloc == MGARD_ALLOC_LEARNED) {
+      if (!o.model) fail(MGARD_ERR_ARG, "learned allocation needs opts->model");
+      o.model_params = model_params(o.model);
+    }
     auto h = get_hierarchy(ndim, shape, coords);
     const uint64_t bound = bound_of(*h, coords, o.dict, o.chunk);
     if (out_capacity < bound) {
@@ -800,6 +863,141 @@ mgard_status mgard_plain_constant(uint32_t ndim, const uint64_t* shape, const do
       if (max_levels < (uint32_t)h->L + 1) fail(MGARD_ERR_CAPACITY, "h_K too short");
       for (int l = 0; l <= h->L; ++l) h_K[l] = h->K[l];
     }
+  });
+}
+
+// ------------------------------------------------------------ learned allocation
+mgard_status mgard_model_create(const float* h_params, uint64_t n_params, mgard_model** out) {
+  return guard([&] {
+    if (!h_params || !out) fail(MGARD_ERR_ARG, "null pointer");
+    if (n_params != (uint64_t)MLP_NPARAM) fail(MGARD_ERR_ARG, "parameter count must be MGARD_MLP_NPARAM");
+    for (uint64_t i = 0; i < n_params; ++i)
+      if (!std::isfinite(h_params[i])) fail(MGARD_ERR_ARG, "non-finite parameter");
+    for (int i = 0; i < MLP_IN; ++i)
+      if (!(h_params[MLP_IN + i] > 0.0f)) fail(MGARD_ERR_ARG, "feature scales must be positive");
+    auto* m = new mgard_model();
+    MG_HIP(hipGetDevice(&m->device));
+    if (hipMalloc(&m->d_params, n_params * sizeof(float)) != hipSuccess) {
+      delete m;
+      fail(MGARD_ERR_OOM, "model parameters");
+    }
+    MG_HIP(hipMemcpy(m->d_params, h_params, n_params * sizeof(float), hipMemcpyHostToDevice));
+    *out = m;
+  });
+}
+
+void mgard_model_free(mgard_model* model) {
+  if (!model) return;
+  if (model->d_params) (void)hipFree(model->d_params);
+  delete model;
+}
+
+mgard_status mgard_level_stats(uint32_t ndim, const uint64_t* shape, mgard_dtype dtype, const void* d_coeff,
+                               double* h_stats, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_coeff || !h_stats) fail(MGARD_ERR_ARG, "null pointer");
+    auto h = get_hierarchy(ndim, shape, nullptr);
+    const int nl = h->L + 1;
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<uint64_t>(MAXL + 2) + carve_size<double>((uint64_t)2 * nl * STATS_BLOCKS) +
+               carve_size<double>(3 * (MAXL + 1)) + 1024);
+    Carver cv(ws.base());
+    uint64_t* d_off = cv.take<uint64_t>(MAXL + 2);
+    double* part = cv.take<double>((uint64_t)2 * nl * STATS_BLOCKS);
+    double* stats = cv.take<double>(3 * (MAXL + 1));
+    MG_HIP(hipMemcpyAsync(d_off, h->level_off.data(), 8 * (h->L + 2), hipMemcpyHostToDevice, o.st));
+    if (dtype == MGARD_F64)
+      launch_level_stats<double>(static_cast<const double*>(d_coeff), d_off, nl, part, stats, o.st);
+    else
+      launch_level_stats<float>(static_cast<const float*>(d_coeff), d_off, nl, part, stats, o.st);
+    MG_HIP(hipMemcpyAsync(h_stats, stats, 8 * 3 * nl, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_linf_error(mgard_dtype dtype, const void* d_a, const void* d_b, uint64_t n, double* h_err,
+                              const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_a || !d_b || !h_err) fail(MGARD_ERR_ARG, "null pointer");
+    Workspace& ws = workspace();
+    ws.reserve(1024);
+    auto* e = static_cast<unsigned long long*>(ws.base());
+    if (dtype == MGARD_F64)
+      launch_linf<double>(static_cast<const double*>(d_a), static_cast<const double*>(d_b), n, e, o.st);
+    else
+      launch_linf<float>(static_cast<const float*>(d_a), static_cast<const float*>(d_b), n, e, o.st);
+    unsigned long long bits = 0;
+    MG_HIP(hipMemcpyAsync(&bits, e, 8, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+    std::memcpy(h_err, &bits, 8);
+  });
+}
+
+mgard_status mgard_mlp_forward(const float* d_params, const float* d_x, uint32_t batch, float* d_out,
+                               float* d_cache, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_params || !d_x || !d_out) fail(MGARD_ERR_ARG, "null pointer");
+    if (batch == 0 || batch > (1u << 24)) fail(MGARD_ERR_ARG, "batch");
+    const uint64_t B = batch;
+    float* xn = d_cache;
+    float* acts = d_cache ? d_cache + B * MLP_IN : nullptr;
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<float>(B * MLP_IN) + carve_size<float>(2 * B * MLP_HID) + 1024);
+    Carver cv(ws.base());
+    if (!xn) xn = cv.take<float>(B * MLP_IN);
+    float* tmp = cv.take<float>(2 * B * MLP_HID);
+    mlp_normalize(d_x, d_params, (int)B, xn, o.st);
+    mlp_forward(d_params, xn, (int)B, d_out, acts, tmp, o.st);
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_mlp_backward(const float* d_params, const float* d_cache, const float* d_dout, uint32_t batch,
+                                float* d_grads, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_params || !d_cache || !d_dout || !d_grads) fail(MGARD_ERR_ARG, "null pointer");
+    if (batch == 0 || batch > (1u << 24)) fail(MGARD_ERR_ARG, "batch");
+    const uint64_t B = batch;
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<float>(2 * B * MLP_HID) + 1024);
+    float* tmp = static_cast<float*>(ws.base());
+    MG_HIP(hipMemsetAsync(d_grads, 0, 2 * MLP_IN * sizeof(float), o.st));
+    mlp_backward(d_params, d_cache, d_cache + B * MLP_IN, d_dout, (int)B, d_grads, tmp, o.st);
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_mlp_mse(const float* d_pred, const float* d_target, uint32_t batch, float* d_dout,
+                           double* h_loss, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_pred || !d_target || !d_dout || !h_loss) fail(MGARD_ERR_ARG, "null pointer");
+    if (batch == 0) fail(MGARD_ERR_ARG, "batch");
+    Workspace& ws = workspace();
+    ws.reserve(1024);
+    double* dl = static_cast<double*>(ws.base());
+    mlp_mse(d_pred, d_target, (int)batch, d_dout, dl, o.st);
+    MG_HIP(hipMemcpyAsync(h_loss, dl, 8, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_mlp_adam(float* d_params, const float* d_grads, float* d_m, float* d_v, uint32_t step, float lr,
+                            float beta1, float beta2, float eps, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_params || !d_grads || !d_m || !d_v) fail(MGARD_ERR_ARG, "null pointer");
+    if (step == 0) fail(MGARD_ERR_ARG, "Adam steps count from 1");
+    const int off = 2 * MLP_IN;  // feature normalisation is not trained
+    mlp_adam(d_params + off, d_grads + off, d_m + off, d_v + off, MLP_NPARAM - off, lr, beta1, beta2, eps,
+             (int)step, o.st);
+    MG_HIP(hipStreamSynchronize(o.st));
   });
 }
 

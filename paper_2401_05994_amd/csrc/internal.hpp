@@ -207,4 +207,36 @@ void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const u
                         const int64_t* outliers, int64_t* qside, void* table_scratch,
                         uint32_t* d_status, hipStream_t st);
 
+// Learned allocation (mlp.hip).  Parameter layout (float32): mean[4], std[4],
+// W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3[1].
+constexpr int MLP_IN = 4, MLP_HID = 64;
+constexpr int MLP_W1 = 2 * MLP_IN;
+constexpr int MLP_B1 = MLP_W1 + MLP_HID * MLP_IN;
+constexpr int MLP_W2 = MLP_B1 + MLP_HID;
+constexpr int MLP_B2 = MLP_W2 + MLP_HID * MLP_HID;
+constexpr int MLP_W3 = MLP_B2 + MLP_HID;
+constexpr int MLP_B3 = MLP_W3 + MLP_HID;
+constexpr int MLP_NPARAM = MLP_B3 + 1;
+constexpr int STATS_BLOCKS = 256;  // partial-sum blocks per level
+template <typename T>
+void launch_level_stats(const T* c, const uint64_t* d_off, int nlev, double* d_part, double* d_stats,
+                        hipStream_t st);
+void launch_features(const double* d_stats, const double* d_scalars, int nlev, const float* d_params,
+                     float* d_x, hipStream_t st);
+void launch_apply_theta(const double* d_bins, const float* d_theta, int nlev, double* d_learned,
+                        hipStream_t st);
+template <typename T>
+void launch_linf(const T* a, const T* b, uint64_t n, unsigned long long* d_err, hipStream_t st);
+void launch_select_bins(const unsigned long long* d_err, double* d_scalars, double* d_bins,
+                        const double* d_learned, int nlev, hipStream_t st);
+void mlp_forward(const float* params, const float* x, int B, float* out, float* cache, float* tmp,
+                 hipStream_t st);
+void mlp_backward(const float* params, const float* x, const float* cache, const float* dout, int B,
+                  float* grads, float* tmp, hipStream_t st);
+void mlp_normalize(const float* x, const float* params, int B, float* xn, hipStream_t st);
+void mlp_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+              float eps, int step, hipStream_t st);
+void mlp_mse(const float* pred, const float* target, int B, float* dout, double* loss,
+             hipStream_t st);
+
 }  // namespace mg

@@ -1,0 +1,187 @@
+"""GPU tests of the learned bin-width allocation: statistics, network kernels
+(forward, backward, Adam) against the float64 oracle, and the check that
+falls back to the plain allocation."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import fieldgen
+from oracle import alloc as A
+from oracle import codec, grid, mlp as M, quant as Q
+from oracle import transform as X
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+def _random_model(seed, mean=None, std=None):
+    params = M.init(seed)
+    mean = np.zeros(4) if mean is None else mean
+    std = np.ones(4) if std is None else std
+    return params, mean, std
+
+
+def test_mlp_kernels_match_oracle(lib):
+    say("mlp kernels")
+    rng = np.random.default_rng(5)
+    params, mean, std = _random_model(11, mean=rng.normal(size=4), std=rng.uniform(0.5, 2.0, size=4))
+    flat = M.pack(params, mean, std).astype(np.float32)
+    B = 37
+    x = rng.normal(size=(B, 4)).astype(np.float32)
+    y = rng.normal(size=B).astype(np.float32)
+    p64 = [[W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)] for W, b in params]
+    xn = (x.astype(np.float64) - flat[:4].astype(np.float64)) / flat[4:8].astype(np.float64)
+    out_ref, cache_ref = M.forward(p64, xn)
+    loss_ref, dout_ref = M.mse(out_ref, y)
+    grads_ref = M.backward(p64, cache_ref, dout_ref)
+    dp = dev(flat)
+    out, cache = lib.mgard_mlp_forward(dp, dev(x))
+    assert rel(host(out), out_ref.ravel()) <= 1e-5
+    dout, loss = lib.mgard_mlp_mse(out, dev(y))
+    assert abs(loss - loss_ref) <= 1e-5 * loss_ref
+    assert rel(host(dout), dout_ref.ravel()) <= 1e-5
+    g = host(lib.mgard_mlp_backward(dp, cache, dout, B))
+    gref = M.pack(grads_ref, np.zeros(4), np.zeros(4))
+    names = ["W1", "b1", "W2", "b2", "W3", "b3"]
+    pos = 8
+    for k, (W, b) in enumerate(grads_ref):
+        for name, arr in ((names[2 * k], W), (names[2 * k + 1], b)):
+            seg = g[pos:pos + arr.size]
+            assert rel(seg, arr.ravel()) <= 1e-4, name
+            pos += arr.size
+    assert np.all(g[:8] == 0)
+    # one Adam step against the oracle's
+    m = torch.zeros(lib.MLP_NPARAM, dtype=torch.float32, device=DEV)
+    v = torch.zeros_like(m)
+    gd = dev(gref.astype(np.float32))
+    lib.mgard_mlp_adam(dp, gd, m, v, 1, lr=1e-2)
+    pref = [[W.copy(), b.copy()] for W, b in p64]
+    gr = [[W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)] for W, b in grads_ref]
+    M.adam_step(pref, gr, M.adam_init(pref), M.adam_init(pref), 1, lr=1e-2)
+    new = host(dp)
+    assert rel(new[8:], M.pack(pref, np.zeros(4), np.zeros(4))[8:]) <= 1e-5
+    assert np.array_equal(new[:8], flat[:8])
+
+
+def test_training_loss_decreases(lib):
+    """A few hundred Adam steps on a smooth target with the project's kernels."""
+    say("mlp training")
+    rng = np.random.default_rng(8)
+    params, mean, std = _random_model(2)
+    flat = dev(M.pack(params, mean, std).astype(np.float32))
+    x = rng.normal(size=(256, 4)).astype(np.float32)
+    y = (np.sin(x[:, 0]) + 0.5 * x[:, 1] * x[:, 2]).astype(np.float32)
+    dx, dy = dev(x), dev(y)
+    m = torch.zeros(lib.MLP_NPARAM, dtype=torch.float32, device=DEV)
+    v = torch.zeros_like(m)
+    losses = []
+    for step in range(1, 301):
+        out, cache = lib.mgard_mlp_forward(flat, dx)
+        dout, loss = lib.mgard_mlp_mse(out, dy)
+        g = lib.mgard_mlp_backward(flat, cache, dout, 256)
+        lib.mgard_mlp_adam(flat, g, m, v, step, lr=3e-3)
+        losses.append(loss)
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_level_stats_and_linf(lib):
+    say("level stats")
+    u = fieldgen.spectral((33, 40, 20), -2.5, 7).astype(np.float32)
+    h = grid.Hierarchy(u.shape)
+    stream = Q.to_stream(*X.decompose(u, h, np.float32), h)
+    st = lib.mgard_level_stats(dev(stream), u.shape)
+    ref = M.level_stats(stream, Q.level_offsets(h))
+    assert np.array_equal(st[:, 0], ref[:, 0])
+    assert rel(st[:, 1], ref[:, 1]) <= 1e-12
+    assert np.array_equal(st[:, 2], ref[:, 2])
+    a = dev(u)
+    b = dev((u + np.float32(1e-3) * np.random.default_rng(1).standard_normal(u.shape)).astype(np.float32))
+    ref_e = float(np.abs(host(a).astype(np.float64) - host(b).astype(np.float64)).max())
+    assert lib.mgard_linf_error(a, b) == ref_e
+
+
+def _model_with_theta(theta_const):
+    params, mean, std = _random_model(3)
+    params[2][0][:] = 0.0
+    params[2][1][:] = theta_const
+    return M.pack(params, mean, std).astype(np.float32)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_zero_theta_model_reproduces_plain_bytes(lib, dtype):
+    say("learned zero theta", dtype)
+    u = fieldgen.spectral((33, 33, 33), -5.0 / 3.0, 4).astype(dtype)
+    model = lib.Model(_model_with_theta(0.0))
+    buf, nb, info = lib.mgard_compress_learned(dev(u), 1e-3, model)
+    assert info["fallback_used"] == 0 and 0 <= info["linf_err"] <= info["tau_abs"]
+    ref = bytearray(codec.compress(u, 1e-3))
+    ref[9] = 1  # the allocation byte says "learned"
+    assert host(buf[:nb]).tobytes() == bytes(ref)
+    r = codec.decompress(host(buf[:nb]).tobytes())
+    assert float(np.abs(r.astype(np.float64) - u.astype(np.float64)).max()) == info["linf_err"]
+
+
+def test_bad_model_falls_back_to_plain(lib):
+    say("learned fallback")
+    u = fieldgen.spectral((33, 33, 33), -5.0 / 3.0, 5).astype(np.float32)
+    model = lib.Model(_model_with_theta(5.0))  # every bin exp(5) ~ 148 times too wide
+    buf, nb, info = lib.mgard_compress_learned(dev(u), 1e-3, model)
+    assert info["fallback_used"] == 1 and info["linf_err"] > info["tau_abs"]
+    got = host(buf[:nb]).tobytes()
+    hd = codec.parse(got)
+    assert hd.fallback == 1 and hd.alloc == codec.ALLOC_LEARNED
+    ref = codec.compress_parts(u, 1e-3)
+    assert hd.bins == ref.bins
+    r = codec.decompress(got)
+    assert np.abs(r.astype(np.float64) - u.astype(np.float64)).max() <= info["tau_abs"]
+
+
+def test_learned_bins_follow_oracle_network(lib):
+    """Header bin widths equal plain * exp(theta) with theta from the float64 oracle network on the
+    oracle's own level statistics (float32 network on the device: 1e-5 relative)."""
+    say("learned bins vs oracle network")
+    rng = np.random.default_rng(9)
+    u = fieldgen.spectral((65, 33, 40), -3.0, 6).astype(np.float32)
+    params, _, _ = _random_model(21)
+    params[2][0] *= 0.05  # small theta: the device check should pass
+    mean = np.array([2.0, 4.0, 8.0, 0.5])
+    std = np.array([2.0, 2.0, 3.0, 0.3])
+    flat = M.pack(params, mean, std).astype(np.float32)
+    model = lib.Model(flat)
+    buf, nb, info = lib.mgard_compress_learned(dev(u), 1e-3, model)
+    h = grid.Hierarchy(u.shape)
+    stream = Q.to_stream(*X.decompose(u, h, np.float32), h)
+    p = codec.compress_parts(u, 1e-3)
+    feats = M.level_features(M.level_stats(stream, Q.level_offsets(h)), p.tau_abs)
+    f32 = [[W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)] for W, b in params]
+    xn = (feats.astype(np.float32).astype(np.float64) - flat[:4].astype(np.float64)) / flat[4:8].astype(np.float64)
+    theta, _ = M.forward(f32, xn)
+    want = M.learned_bins(p.bins, theta)
+    hd = codec.parse(host(buf[:nb]).tobytes())
+    if info["fallback_used"]:
+        assert hd.bins == p.bins
+    else:
+        assert rel(hd.bins, want) <= 1e-5
+    r = codec.decompress(host(buf[:nb]).tobytes())
+    assert np.abs(r.astype(np.float64) - u.astype(np.float64)).max() <= info["tau_abs"]
