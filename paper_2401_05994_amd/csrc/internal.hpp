@@ -168,6 +168,19 @@ template <typename T>
 void recompose(const Hierarchy& h, const T* table, const T* d_stream, const QuantOut* q, T* d_out,
                void* scratch, hipStream_t st);
 
+template <typename T>
+void launch_thomas_strided(T* data, uint64_t outer, int n, uint64_t inner, DimConsts<T> w, hipStream_t st);
+
+// Fused 3D level kernels (transform3d.hip), used when all three sides are decomposed.
+template <typename T>
+bool fused3d_ok(const Hierarchy& h);
+template <typename T>
+void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T* u, T* ucoarse, T* g1, T* z,
+                             const QuantOut* q, T* cstream, hipStream_t st);
+template <typename T>
+void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* g1, T* z,
+                             const QuantOut* q, const T* cstream, hipStream_t st);
+
 // Quantization helpers (quant.hip).
 template <typename T>
 void launch_maxabs(const T* d, uint64_t n, uint64_t* d_bits, hipStream_t st);

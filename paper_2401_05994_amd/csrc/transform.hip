@@ -386,6 +386,11 @@ Scratch scratch_counts(const Hierarchy& h) {
 }  // namespace
 
 template <typename T>
+void launch_thomas_strided(T* data, uint64_t outer, int n, uint64_t inner, DimConsts<T> w, hipStream_t st) {
+  hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, data, outer, n, inner, w);
+}
+
+template <typename T>
 LevelGeom<T> level_geom(const Hierarchy& h, int l, const T* table) {
   LevelGeom<T> g{};
   g.pad_slots = MAXD - h.D;
@@ -433,7 +438,13 @@ void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, c
   const T* cur = d_in;
   T* nxt = pa;
   const int mode = q ? 1 : 0;
-  for (int l = h.L; l >= 1; --l) {
+  const bool f3 = fused3d_ok<T>(h);
+  for (int l = h.L; l >= 1 && f3; --l) {
+    fused3d_decompose_level<T>(h, l, table, cur, nxt, ga, gb, q, d_stream, st);
+    cur = nxt;
+    nxt = (nxt == pa) ? pb : pa;
+  }
+  for (int l = f3 ? 0 : h.L; l >= 1; --l) {
     LevelGeom<T> g = level_geom<T>(h, l, table);
     const uint64_t nfine = h.count(l);
     {
@@ -487,7 +498,13 @@ void recompose(const Hierarchy& h, const T* table, const T* d_stream, const Quan
   else
     hipLaunchKernelGGL((k_coarsest_in<T, 1>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, nullptr, q->sym,
                        q->qside, q->bins, q->R, n0);
-  for (int l = 1; l <= h.L; ++l) {
+  const bool f3 = fused3d_ok<T>(h);
+  for (int l = 1; l <= h.L && f3; ++l) {
+    T* out = level_buf(l);
+    fused3d_recompose_level<T>(h, l, table, cur, out, ga, gb, q, d_stream, st);
+    cur = out;
+  }
+  for (int l = f3 ? h.L + 1 : 1; l <= h.L; ++l) {
     LevelGeom<T> g = level_geom<T>(h, l, table);
     const uint64_t nfine = h.count(l);
     {
@@ -519,6 +536,7 @@ void recompose(const Hierarchy& h, const T* table, const T* d_stream, const Quan
 #define MG_INST(T)                                                                                    \
   template LevelGeom<T> level_geom<T>(const Hierarchy&, int, const T*);                             \
   template DimConsts<T> dim_consts<T>(const Hierarchy&, int, int, const T*);                        \
+  template void launch_thomas_strided<T>(T*, uint64_t, int, uint64_t, DimConsts<T>, hipStream_t);   \
   template uint64_t decompose_scratch_bytes<T>(const Hierarchy&);                                   \
   template uint64_t recompose_scratch_bytes<T>(const Hierarchy&);                                   \
   template void decompose<T>(const Hierarchy&, const T*, const T*, T*, const QuantOut*, void*,      \

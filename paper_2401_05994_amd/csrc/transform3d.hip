@@ -1,0 +1,497 @@
+// Fused 3D level kernels (gfx950): the same arithmetic, in the same rounding
+// order, as the generic kernels of transform.hip, with fewer passes over HBM.
+//
+// Decomposition of one level (fine n0 x n1 x n2 -> coarse c0 x c1 x c2):
+//   k3_coeff_r21   tiles of (dim 1, dim 2) marching over the fine planes of
+//                  dim 0: in-plane interpolant (dim 2 sweep, then dim 1),
+//                  plane interpolation along dim 0, coefficients, quantization
+//                  of the owned nodes, coarse copy, then mass + restriction
+//                  along dim 2 and dim 1 in LDS -> g1 (n0 x c1 x c2);
+//   k3_r0_thomas0  mass + restriction along dim 0 fused with the Thomas solve
+//                  along dim 0, one lane per (j1, j2) line -> z;
+//   k_thomas       (generic) Thomas along dim 1;
+//   k3_thomas2_axpy rows of the contiguous dimension staged in LDS, Thomas
+//                  along dim 2, then u_{l-1} = u_l|coarse + z (or - z).
+// Recomposition: k3_scatter_r21 (dequantize + restriction along dims 2, 1),
+// the same solves, then k3_interp_add (dequantize + interpolant + add).
+//
+// Tiles start at even fine indices, so every new node inside a tile has both
+// coarse neighbours inside the tile, and every fine index outside [0, n) is
+// skipped.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace mg {
+
+namespace {
+
+constexpr int NT = 256;             // threads per block
+constexpr int TY = 8, TX = 64;      // coarse outputs per tile in dims 1 and 2
+constexpr int RY = 2 * TY + 3;      // fine rows of a tile (with a halo of 2)
+constexpr int RX = 2 * TX + 3;      // fine columns of a tile
+constexpr int SEG = 16;             // coarse intervals of dim 0 per block
+constexpr int AXPY_LDS = 65536;     // bytes of LDS for the contiguous-dimension solve
+
+__device__ inline bool is_new(int f, int n) { return (f & 1) && f < n - 1; }
+__device__ inline int cidx(int f) { return (f + 1) >> 1; }          // coarse index of a coarse fine index
+__device__ inline int cpos(int j, int nc, int nf) { return j == nc - 1 ? nf - 1 : 2 * j; }
+
+template <typename T>
+struct Lv3 {
+  int n0, n1, n2, c0, c1, c2;
+  DimConsts<T> d0, d1, d2;
+  uint64_t level_off;
+  const uint64_t* sub;  // sub-grid table of the level (slot layout: user dim d in slot d + 1)
+};
+
+// mass stencil of a line at fine index i: ((a*g[i-1] + b*g[i]) + c*g[i+1])
+template <typename T, typename G>
+__device__ inline T mass_at(int i, int n, const DimConsts<T>& w, G g) {
+  T s = w.mb[i] * g(i);
+  if (i > 0) s = w.ma[i] * g(i - 1) + s;
+  if (i < n - 1) s = s + w.mc[i] * g(i + 1);
+  return s;
+}
+
+// restriction to coarse j of the mass-weighted line: ((rl*M[c-1] + M[c]) + rr*M[c+1])
+template <typename T, typename G>
+__device__ inline T restrict_at(int j, int nc, int n, const DimConsts<T>& w, G g) {
+  const int c = cpos(j, nc, n);
+  T f = mass_at<T>(c, n, w, g);
+  if (c >= 2 && !(c & 1)) f = w.rl[j] * mass_at<T>(c - 1, n, w, g) + f;
+  if (!(c & 1) && c < n - 2) f = f + w.rr[j] * mass_at<T>(c + 1, n, w, g);
+  return f;
+}
+
+template <typename T>
+__device__ inline void quant_store(T c, double inv_b, int R, uint64_t pos, uint16_t* __restrict__ sym,
+                                   int64_t* __restrict__ qside) {
+  const double y = (double)c * inv_b;
+  const double a = floor(fabs(y) + 0.5);
+  const int64_t q = (int64_t)(y < 0.0 ? -a : a);
+  if (q > -R && q < R) {
+    sym[pos] = (uint16_t)(q + R);
+  } else {
+    sym[pos] = 0;
+    qside[pos] = q;
+  }
+}
+
+template <typename T>
+__device__ inline T dequant_load(const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside, uint64_t pos,
+                                 double b, int R) {
+  const uint16_t s = sym[pos];
+  const int64_t q = s ? (int64_t)s - R : qside[pos];
+  return static_cast<T>((double)q * b);
+}
+
+// sub-grid offset and strides of the 7 masks, staged in LDS: [m][0] offset, [m][1..3] strides
+__device__ inline void load_sub(uint64_t (*subs)[4], const uint64_t* sub, uint64_t level_off) {
+  for (int k = threadIdx.x; k < 8 * 4; k += blockDim.x) {
+    const int m = k >> 2, e = k & 3;
+    subs[m][e] = m == 0 ? 0 : (e == 0 ? level_off + sub[m] : sub[16 + 4 * m + e]);
+  }
+}
+
+__device__ inline uint64_t pos_of(const uint64_t (*subs)[4], int m, int f0, int f1, int f2) {
+  const int i0 = (m & 1) ? (f0 >> 1) : cidx(f0);
+  const int i1 = (m & 2) ? (f1 >> 1) : cidx(f1);
+  const int i2 = (m & 4) ? (f2 >> 1) : cidx(f2);
+  return subs[m][0] + (uint64_t)i0 * subs[m][1] + (uint64_t)i1 * subs[m][2] + (uint64_t)i2 * subs[m][3];
+}
+
+// ------------------------------------------------------------------ decomposition
+// MODE 1: quantize into sym/qside; MODE 0: write float coefficients to cstream.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* __restrict__ ucoarse,
+                                                   T* __restrict__ g1, uint16_t* __restrict__ sym,
+                                                   int64_t* __restrict__ qside, T* __restrict__ cstream,
+                                                   const double* __restrict__ bins, int level, int R, Lv3<T> p) {
+  __shared__ T U[RY * RX];
+  __shared__ T BA[RY * RX];
+  __shared__ T BB[RY * RX];
+  __shared__ T G2[RY * TX];
+  __shared__ uint64_t subs[8][4];
+  const int t = threadIdx.x;
+  const int J1 = blockIdx.y * TY, J2 = blockIdx.x * TX;
+  const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
+  const int n0 = p.n0, n1 = p.n1, n2 = p.n2;
+  const int cb = blockIdx.z * SEG;
+  const int ce = min(cb + SEG, p.c0 - 1);
+  const uint64_t plane = (uint64_t)n1 * n2;
+  // owned fine ranges of this tile
+  const int o1b = 2 * J1, o1e = min(2 * (J1 + TY), n1);
+  const int o2b = 2 * J2, o2e = min(2 * (J2 + TX), n2);
+  double inv_b = 0.0;
+  if (MODE == 1) inv_b = 1.0 / bins[level];
+  load_sub(subs, p.sub, p.level_off);
+
+  auto load_plane = [&](int f0) {
+    for (int k = t; k < RY * RX; k += NT) {
+      const int r = k / RX, x = k - r * RX;
+      const int f1 = F1 + r, f2 = F2 + x;
+      U[k] = (f1 >= 0 && f1 < n1 && f2 >= 0 && f2 < n2) ? u[(uint64_t)f0 * plane + (uint64_t)f1 * n2 + f2] : T(0);
+    }
+    __syncthreads();
+  };
+  // in-plane interpolant of the coarse-coarse nodes: dim 2 on coarse rows, then dim 1
+  auto build_b = [&](T* B) {
+    for (int k = t; k < RY * RX; k += NT) {
+      const int r = k / RX, x = k - r * RX;
+      const int f1 = F1 + r, f2 = F2 + x;
+      if (f1 < 0 || f1 >= n1 || f2 < 0 || f2 >= n2 || is_new(f1, n1)) continue;
+      B[k] = is_new(f2, n2) ? p.d2.wl[f2] * U[k - 1] + p.d2.wr[f2] * U[k + 1] : U[k];
+    }
+    __syncthreads();
+    for (int k = t; k < RY * RX; k += NT) {
+      const int r = k / RX, x = k - r * RX;
+      const int f1 = F1 + r, f2 = F2 + x;
+      if (f2 < 0 || f2 >= n2 || !is_new(f1, n1)) continue;
+      B[k] = p.d1.wl[f1] * B[k - RX] + p.d1.wr[f1] * B[k + RX];
+    }
+    __syncthreads();
+  };
+  // coefficients of plane f0 into U, outputs of the owned nodes, then R2 and R1 -> g1
+  auto emit = [&](int f0, const T* Bl, const T* Br) {
+    const bool new0 = is_new(f0, n0);
+    const T w0l = new0 ? p.d0.wl[f0] : T(0), w0r = new0 ? p.d0.wr[f0] : T(0);
+    for (int k = t; k < RY * RX; k += NT) {
+      const int r = k / RX, x = k - r * RX;
+      const int f1 = F1 + r, f2 = F2 + x;
+      if (f1 < 0 || f1 >= n1 || f2 < 0 || f2 >= n2) continue;
+      const T v = U[k];
+      const T pi = new0 ? w0l * Bl[k] + w0r * Br[k] : Bl[k];
+      const T c = v - pi;
+      U[k] = c;
+      if (f1 < o1b || f1 >= o1e || f2 < o2b || f2 >= o2e) continue;
+      const int m = (new0 ? 1 : 0) | (is_new(f1, n1) ? 2 : 0) | (is_new(f2, n2) ? 4 : 0);
+      if (m == 0) {
+        ucoarse[((uint64_t)cidx(f0) * p.c1 + cidx(f1)) * p.c2 + cidx(f2)] = v;
+      } else {
+        const uint64_t pos = pos_of(subs, m, f0, f1, f2);
+        if (MODE == 1)
+          quant_store(c, inv_b, R, pos, sym, qside);
+        else
+          cstream[pos] = c;
+      }
+    }
+    __syncthreads();
+    // mass + restriction along dim 2 for every row of the tile
+    for (int k = t; k < RY * TX; k += NT) {
+      const int r = k / TX, jx = k - r * TX;
+      const int f1 = F1 + r, j2 = J2 + jx;
+      if (f1 < 0 || f1 >= n1 || j2 >= p.c2) continue;
+      const T* row = U + r * RX - F2;  // row[f2] for fine f2 inside the tile
+      G2[k] = restrict_at<T>(j2, p.c2, n2, p.d2, [&](int i) { return row[i]; });
+    }
+    __syncthreads();
+    // mass + restriction along dim 1 -> g1
+    for (int k = t; k < TY * TX; k += NT) {
+      const int jy = k / TX, jx = k - jy * TX;
+      const int j1 = J1 + jy, j2 = J2 + jx;
+      if (j1 >= p.c1 || j2 >= p.c2) continue;
+      const T* col = G2 + jx - F1 * TX;  // col[f1 * TX]
+      const T f = restrict_at<T>(j1, p.c1, n1, p.d1, [&](int i) { return col[i * TX]; });
+      g1[((uint64_t)f0 * p.c1 + j1) * p.c2 + j2] = f;
+    }
+    __syncthreads();
+  };
+
+  T* Bp = BA;
+  T* Bn = BB;
+  int fc = cpos(cb, p.c0, n0);
+  load_plane(fc);
+  build_b(Bp);
+  emit(fc, Bp, Bp);
+  for (int j = cb; j < ce; ++j) {
+    const int fn = cpos(j + 1, p.c0, n0);
+    load_plane(fn);
+    build_b(Bn);
+    if (j + 1 < ce || j + 1 == p.c0 - 1) emit(fn, Bn, Bn);
+    if (fn - fc == 2) {
+      load_plane(fc + 1);
+      emit(fc + 1, Bp, Bn);
+    }
+    T* tmp = Bp;
+    Bp = Bn;
+    Bn = tmp;
+    fc = fn;
+  }
+}
+
+// mass + restriction along dim 0 of g1 (n0 x c1 x c2), then Thomas along dim 0 -> z (c0 x c1 x c2)
+template <typename T>
+__global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T* __restrict__ z, int n0, int c0,
+                                                    uint64_t lines, DimConsts<T> w) {
+  const uint64_t t = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= lines) return;
+  const T* g = g1 + t;
+  T* zz = z + t;
+  auto G = [&](int i) { return g[(uint64_t)i * lines]; };
+  T prev = T(0);
+  for (int j = 0; j < c0; ++j) {
+    const T f = restrict_at<T>(j, c0, n0, w, G);
+    prev = j == 0 ? f * w.tr[0] : (f - w.ta[j] * prev) * w.tr[j];
+    zz[(uint64_t)j * lines] = prev;
+  }
+  T x = prev;
+  for (int j = c0 - 2; j >= 0; --j) {
+    x = zz[(uint64_t)j * lines] - w.tcp[j] * x;
+    zz[(uint64_t)j * lines] = x;
+  }
+}
+
+// Thomas along the contiguous dimension on `rows` rows per block, then out = a +/- z
+template <typename T, bool ADD>
+__global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T* out,
+                                                      uint64_t nrows, int n, int rows, DimConsts<T> w) {
+  __shared__ T tile[AXPY_LDS / sizeof(T)];
+  const uint64_t r0 = (uint64_t)blockIdx.x * rows;
+  const int nr = (int)min((uint64_t)rows, nrows - r0);
+  const uint64_t base = r0 * (uint64_t)n;
+  const int cnt = nr * n;
+  for (int k = threadIdx.x; k < cnt; k += NT) tile[k] = z[base + k];
+  __syncthreads();
+  if ((int)threadIdx.x < nr) {
+    T* line = tile + threadIdx.x * n;
+    T prev = line[0] * w.tr[0];
+    line[0] = prev;
+    for (int i = 1; i < n; ++i) {
+      prev = (line[i] - w.ta[i] * prev) * w.tr[i];
+      line[i] = prev;
+    }
+    T x = prev;
+    for (int i = n - 2; i >= 0; --i) {
+      x = line[i] - w.tcp[i] * x;
+      line[i] = x;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < cnt; k += NT) out[base + k] = ADD ? a[base + k] + tile[k] : a[base + k] - tile[k];
+}
+
+// ------------------------------------------------------------------ recomposition
+// coefficients of each fine plane from the stream (zeros at coarse nodes), then R2, R1 -> g1
+template <typename T, int MODE>
+__global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside,
+                                                     const T* __restrict__ cstream, const double* __restrict__ bins,
+                                                     int level, int R, T* __restrict__ g1, Lv3<T> p, int planes_per) {
+  __shared__ T U[RY * RX];
+  __shared__ T G2[RY * TX];
+  __shared__ uint64_t subs[8][4];
+  const int t = threadIdx.x;
+  const int J1 = blockIdx.y * TY, J2 = blockIdx.x * TX;
+  const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
+  const int n0 = p.n0, n1 = p.n1, n2 = p.n2;
+  const double b = MODE == 1 ? bins[level] : 0.0;
+  load_sub(subs, p.sub, p.level_off);
+  __syncthreads();
+  const int fb = blockIdx.z * planes_per, fe = min(fb + planes_per, n0);
+  for (int f0 = fb; f0 < fe; ++f0) {
+    const bool new0 = is_new(f0, n0);
+    for (int k = t; k < RY * RX; k += NT) {
+      const int r = k / RX, x = k - r * RX;
+      const int f1 = F1 + r, f2 = F2 + x;
+      T c = T(0);
+      if (f1 >= 0 && f1 < n1 && f2 >= 0 && f2 < n2) {
+        const int m = (new0 ? 1 : 0) | (is_new(f1, n1) ? 2 : 0) | (is_new(f2, n2) ? 4 : 0);
+        if (m) {
+          const uint64_t pos = pos_of(subs, m, f0, f1, f2);
+          c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
+        }
+      }
+      U[k] = c;
+    }
+    __syncthreads();
+    for (int k = t; k < RY * TX; k += NT) {
+      const int r = k / TX, jx = k - r * TX;
+      const int f1 = F1 + r, j2 = J2 + jx;
+      if (f1 < 0 || f1 >= n1 || j2 >= p.c2) continue;
+      const T* row = U + r * RX - F2;
+      G2[k] = restrict_at<T>(j2, p.c2, n2, p.d2, [&](int i) { return row[i]; });
+    }
+    __syncthreads();
+    for (int k = t; k < TY * TX; k += NT) {
+      const int jy = k / TX, jx = k - jy * TX;
+      const int j1 = J1 + jy, j2 = J2 + jx;
+      if (j1 >= p.c1 || j2 >= p.c2) continue;
+      const T* col = G2 + jx - F1 * TX;
+      g1[((uint64_t)f0 * p.c1 + j1) * p.c2 + j2] =
+          restrict_at<T>(j1, p.c1, n1, p.d1, [&](int i) { return col[i * TX]; });
+    }
+    __syncthreads();
+  }
+}
+
+// u_l = c + Pi(uc) at new nodes, uc at coarse nodes; Pi nested with dim 2 innermost
+template <typename T, int MODE>
+__global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T* __restrict__ uc,
+                                                    const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside,
+                                                    const T* __restrict__ cstream, const double* __restrict__ bins,
+                                                    int level, int R, Lv3<T> p) {
+  __shared__ uint64_t subs[8][4];
+  load_sub(subs, p.sub, p.level_off);
+  __syncthreads();
+  const int f2 = blockIdx.x * NT + threadIdx.x;
+  const int f1 = blockIdx.y;
+  const int f0 = blockIdx.z;
+  if (f2 >= p.n2) return;
+  const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
+  const bool e0 = is_new(f0, n0), e1 = is_new(f1, n1), e2 = is_new(f2, n2);
+  const int m = (e0 ? 1 : 0) | (e1 ? 2 : 0) | (e2 ? 4 : 0);
+  const uint64_t o = ((uint64_t)f0 * n1 + f1) * n2 + f2;
+  auto UC = [&](int q0, int q1, int q2) { return uc[((uint64_t)q0 * c1 + q1) * c2 + q2]; };
+  if (m == 0) {
+    out[o] = UC(cidx(f0), cidx(f1), cidx(f2));
+    return;
+  }
+  auto V = [&](int q0, int q1) -> T {
+    if (e2) return p.d2.wl[f2] * UC(q0, q1, f2 >> 1) + p.d2.wr[f2] * UC(q0, q1, (f2 >> 1) + 1);
+    return UC(q0, q1, cidx(f2));
+  };
+  auto W = [&](int q0) -> T {
+    if (e1) return p.d1.wl[f1] * V(q0, f1 >> 1) + p.d1.wr[f1] * V(q0, (f1 >> 1) + 1);
+    return V(q0, cidx(f1));
+  };
+  const T pi = e0 ? p.d0.wl[f0] * W(f0 >> 1) + p.d0.wr[f0] * W((f0 >> 1) + 1) : W(cidx(f0));
+  const uint64_t pos = pos_of(subs, m, f0, f1, f2);
+  const T c = MODE == 1 ? dequant_load<T>(sym, qside, pos, bins[level], R) : cstream[pos];
+  out[o] = c + pi;
+}
+
+inline unsigned blocks1(uint64_t n) { return (unsigned)std::max<uint64_t>(1, (n + NT - 1) / NT); }
+
+}  // namespace
+
+template <typename T>
+bool fused3d_ok(const Hierarchy& h) {
+  if (h.D != 3) return false;
+  for (int s = 1; s < MAXD; ++s)
+    if (!h.active[s]) return false;
+  if (h.shape[1] > 65535 || h.shape[2] > 65535 || h.shape[3] > (1 << 24)) return false;
+  // the contiguous-dimension solve stages at least one coarse row in LDS
+  return (uint64_t)h.sizes[h.L > 0 ? h.L - 1 : 0][3] * sizeof(T) <= (uint64_t)AXPY_LDS;
+}
+
+template <typename T>
+static Lv3<T> lv3(const Hierarchy& h, int l, const T* table) {
+  Lv3<T> p;
+  p.n0 = (int)h.sizes[l][1];
+  p.n1 = (int)h.sizes[l][2];
+  p.n2 = (int)h.sizes[l][3];
+  p.c0 = (int)h.sizes[l - 1][1];
+  p.c1 = (int)h.sizes[l - 1][2];
+  p.c2 = (int)h.sizes[l - 1][3];
+  p.d0 = dim_consts<T>(h, l, 1, table);
+  p.d1 = dim_consts<T>(h, l, 2, table);
+  p.d2 = dim_consts<T>(h, l, 3, table);
+  p.level_off = h.level_off[l];
+  p.sub = static_cast<const uint64_t*>(h.dev_itab) + 80 * (uint64_t)l;
+  return p;
+}
+
+// g1 buffer: n0 * c1 * c2; z buffer: c0 * c1 * c2
+template <typename T>
+uint64_t fused3d_scratch_elems(const Hierarchy& h) {
+  uint64_t g = 0;
+  for (int l = 1; l <= h.L; ++l)
+    g = std::max<uint64_t>(g, (uint64_t)h.sizes[l][1] * h.sizes[l - 1][2] * h.sizes[l - 1][3]);
+  return g;
+}
+
+// Decomposition of level l: writes the coefficients (sym/qside or cstream), the
+// coarse grid u_{l-1} into `ucoarse`, using g1 and z scratch.
+template <typename T>
+void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T* u, T* ucoarse, T* g1, T* z,
+                             const QuantOut* q, T* cstream, hipStream_t st) {
+  Lv3<T> p = lv3<T>(h, l, table);
+  const bool fine = l == h.L;
+  {
+    KernelTimer kt(fine ? "coeff_r21_fine" : "coeff_r21_coarse", st);
+    dim3 grid((p.c2 + TX - 1) / TX, (p.c1 + TY - 1) / TY, (p.c0 - 1 + SEG - 1) / SEG);
+    if (q)
+      hipLaunchKernelGGL((k3_coeff_r21<T, 1>), grid, dim3(NT), 0, st, u, ucoarse, g1, q->sym, q->qside,
+                         (T*)nullptr, q->bins, l, q->R, p);
+    else
+      hipLaunchKernelGGL((k3_coeff_r21<T, 0>), grid, dim3(NT), 0, st, u, ucoarse, g1, (uint16_t*)nullptr,
+                         (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p);
+  }
+  const uint64_t lines = (uint64_t)p.c1 * p.c2;
+  {
+    KernelTimer kt(fine ? "r0_thomas0_fine" : "r0_thomas0_coarse", st);
+    hipLaunchKernelGGL(k3_r0_thomas0<T>, dim3(blocks1(lines)), dim3(NT), 0, st, g1, z, p.n0, p.c0, lines, p.d0);
+  }
+  {
+    KernelTimer kt(fine ? "thomas1_fine" : "thomas1_coarse", st);
+    launch_thomas_strided<T>(z, (uint64_t)p.c0, p.c1, (uint64_t)p.c2, dim_consts<T>(h, l, 2, table), st);
+  }
+  {
+    KernelTimer kt(fine ? "thomas2_add_fine" : "thomas2_add_coarse", st);
+    const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / sizeof(T) / p.c2)));
+    const uint64_t nrows = (uint64_t)p.c0 * p.c1;
+    hipLaunchKernelGGL((k3_thomas2_axpy<T, true>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT), 0, st, z,
+                       ucoarse, ucoarse, nrows, p.c2, rows, p.d2);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+// Recomposition of level l: from the coefficients and u_{l-1} (cur) to u_l (out).
+template <typename T>
+void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* g1, T* z,
+                             const QuantOut* q, const T* cstream, hipStream_t st) {
+  Lv3<T> p = lv3<T>(h, l, table);
+  const bool fine = l == h.L;
+  const int planes_per = 8;
+  {
+    KernelTimer kt(fine ? "scatter_r21_fine" : "scatter_r21_coarse", st);
+    dim3 grid((p.c2 + TX - 1) / TX, (p.c1 + TY - 1) / TY, (p.n0 + planes_per - 1) / planes_per);
+    if (q)
+      hipLaunchKernelGGL((k3_scatter_r21<T, 1>), grid, dim3(NT), 0, st, q->sym, q->qside, (const T*)nullptr, q->bins,
+                         l, q->R, g1, p, planes_per);
+    else
+      hipLaunchKernelGGL((k3_scatter_r21<T, 0>), grid, dim3(NT), 0, st, (const uint16_t*)nullptr,
+                         (const int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, g1, p, planes_per);
+  }
+  const uint64_t lines = (uint64_t)p.c1 * p.c2;
+  {
+    KernelTimer kt(fine ? "r0_thomas0_fine" : "r0_thomas0_coarse", st);
+    hipLaunchKernelGGL(k3_r0_thomas0<T>, dim3(blocks1(lines)), dim3(NT), 0, st, g1, z, p.n0, p.c0, lines, p.d0);
+  }
+  {
+    KernelTimer kt(fine ? "thomas1_fine" : "thomas1_coarse", st);
+    launch_thomas_strided<T>(z, (uint64_t)p.c0, p.c1, (uint64_t)p.c2, dim_consts<T>(h, l, 2, table), st);
+  }
+  {
+    KernelTimer kt(fine ? "thomas2_sub_fine" : "thomas2_sub_coarse", st);
+    const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / sizeof(T) / p.c2)));
+    const uint64_t nrows = (uint64_t)p.c0 * p.c1;
+    // uc = u_{l-1} - z, written over z
+    hipLaunchKernelGGL((k3_thomas2_axpy<T, false>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT), 0, st, z,
+                       cur, z, nrows, p.c2, rows, p.d2);
+  }
+  {
+    KernelTimer kt(fine ? "interp_add3_fine" : "interp_add3_coarse", st);
+    dim3 grid(blocks1((uint64_t)p.n2), (unsigned)p.n1, (unsigned)p.n0);
+    if (q)
+      hipLaunchKernelGGL((k3_interp_add<T, 1>), grid, dim3(NT), 0, st, out, z, q->sym, q->qside, (const T*)nullptr,
+                         q->bins, l, q->R, p);
+    else
+      hipLaunchKernelGGL((k3_interp_add<T, 0>), grid, dim3(NT), 0, st, out, z, (const uint16_t*)nullptr,
+                         (const int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+#define MG_INST3(T)                                                                                             \
+  template bool fused3d_ok<T>(const Hierarchy&);                                                               \
+  template uint64_t fused3d_scratch_elems<T>(const Hierarchy&);                                                \
+  template void fused3d_decompose_level<T>(const Hierarchy&, int, const T*, const T*, T*, T*, T*, const QuantOut*, \
+                                           T*, hipStream_t);                                                   \
+  template void fused3d_recompose_level<T>(const Hierarchy&, int, const T*, const T*, T*, T*, T*, const QuantOut*, \
+                                           const T*, hipStream_t);
+MG_INST3(float)
+MG_INST3(double)
+#undef MG_INST3
+
+}  // namespace mg

@@ -50,6 +50,8 @@ CASES = {
     "batchdims-2x65x1x33-f32": ((2, 65, 1, 33), np.float32, None),
     "even-64x50-f32": ((64, 50), np.float32, None),
     "3d-65x65x65-f32": ((65, 65, 65), np.float32, None),
+    "3d-129x130x131-f32-nonuniform": ((129, 130, 131), np.float32, "rand"),
+    "3d-64x50x37-f64": ((64, 50, 37), np.float64, None),
 }
 
 
