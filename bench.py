@@ -34,16 +34,16 @@ def algorithmic_bytes(kernel: str, n: int, dtype_bytes: int, levels_sizes):
     N = nf ** 3
     Nc = nc ** 3
     s = dtype_bytes
-    if kernel == "coeff_fine":
-        # read u; write cbar (correction input), symbols of the new nodes, coarse copy
-        return N * s + N * s + 2 * (N - Nc) + Nc * s
-    if kernel == "interp_add_fine":
-        # read cbar and the coarse grid; write u
-        return N * s + Nc * s + N * s
-    if kernel == "scatter_fine":
-        return 2 * (N - Nc) + N * s
-    if kernel == "mass_restrict_fine":
-        return None
+    if kernel == "coeff_r21_fine":
+        # read u once; write the new nodes' 2-byte symbols, the coarse copy and the
+        # plane restricted along dims 2 and 1 (nf x nc x nc)
+        return N * s + 2 * (N - Nc) + Nc * s + nf * nc * nc * s
+    if kernel == "interp_add3_fine":
+        # read the new nodes' symbols and the coarse grid; write u
+        return 2 * (N - Nc) + Nc * s + N * s
+    if kernel == "scatter_r21_fine":
+        # read the new nodes' symbols; write the restricted plane
+        return 2 * (N - Nc) + nf * nc * nc * s
     return None
 
 
@@ -123,13 +123,13 @@ def main():
         s = s // 2 + 1
     sizes.append(3)
     sizes = sizes[::-1]
-    roof_kernel = "coeff_fine"
+    roof_kernel = "coeff_r21_fine"
     launches, total_ms = rep[roof_kernel]
     avg_ms = total_ms / launches
     alg = algorithmic_bytes(roof_kernel, n, 4, sizes)
     achieved = alg / (avg_ms * 1e-3) / 1e9
     decomp_ms = sum(v[1] for k, v in rep.items()
-                    if k.startswith(("coeff", "mass_restrict", "thomas", "add_", "maxabs"))) / kt_steps
+                    if k.startswith(("coeff", "mass_restrict", "thomas", "add_", "maxabs", "r0_thomas0")) and "sub" not in k) / kt_steps
     N = u.numel()
     alg_dq = N * 4 + 2 * N + 2 * 4 * sum(x ** 3 for x in sizes[:-1])  # read u, write symbols, coarse grids
 

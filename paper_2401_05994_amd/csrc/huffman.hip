@@ -54,20 +54,26 @@ __global__ void __launch_bounds__(TPB) k_histogram(const uint16_t* __restrict__ 
 
 // ------------------------------------------------------------------ codebook
 // One workgroup; everything stays in LDS.  keys: (count << 16 | symbol),
-// empty bins sort last.  After the sort the keys array holds the leaf
-// weights, then (in place) the two-queue merge, then the leaf depths.
+// empty bins sort last.  The two-queue merge runs on one lane with the queue
+// heads held in registers; internal-node depths come from pointer jumping,
+// leaf lengths from the number of leaves per depth (deepest for the smallest
+// weights), canonical codes from a second sort by (length, symbol).
 __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ hist, int dict,
                                                    uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
   __shared__ uint64_t keys[MAXDICT];
   __shared__ uint16_t syms[MAXDICT];
+  __shared__ uint16_t par[MAXDICT];
+  __shared__ uint8_t dep[MAXDICT];
   __shared__ uint8_t lens[MAXDICT];
   __shared__ int nleaf;
-  __shared__ uint32_t bl_count[MAXLEN + 1];
-  __shared__ uint64_t next_code[MAXLEN + 1];
+  __shared__ uint32_t icount[MAXLEN + 2];
+  __shared__ uint32_t lstart[MAXLEN + 2];
+  __shared__ uint64_t first[MAXLEN + 1];
+  __shared__ uint32_t lcount[MAXLEN + 1], loff[MAXLEN + 1];
   const int t = threadIdx.x;
   const int nt = blockDim.x;
   if (t == 0) nleaf = 0;
-  for (int i = t; i <= MAXLEN; i += nt) bl_count[i] = 0;
+  for (int i = t; i <= MAXLEN + 1; i += nt) icount[i] = 0;
   __syncthreads();
   for (int s = t; s < dict; s += nt) {
     const uint64_t c = hist[s];
@@ -76,95 +82,152 @@ __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ 
     if (c) atomicAdd(&nleaf, 1);
   }
   __syncthreads();
-  // bitonic sort, ascending
-  for (int k = 2; k <= dict; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = t; i < dict; i += nt) {
-        const int p = i ^ j;
-        if (p > i) {
-          const uint64_t a = keys[i], b = keys[p];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            keys[i] = b;
-            keys[p] = a;
+  auto bitonic = [&]() {
+    for (int k = 2; k <= dict; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = t; i < dict; i += nt) {
+          const int p = i ^ j;
+          if (p > i) {
+            const uint64_t a = keys[i], b = keys[p];
+            if ((a > b) == ((i & k) == 0)) {
+              keys[i] = b;
+              keys[p] = a;
+            }
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
-  }
+  };
+  bitonic();
   const int n = nleaf;
   for (int i = t; i < n; i += nt) {
     syms[i] = (uint16_t)(keys[i] & 0xffff);
     keys[i] >>= 16;
   }
   __syncthreads();
-  if (t == 0 && n > 1) {
-    uint64_t* A = keys;
-    // phase 1: two-queue merge; a consumed internal node's slot takes its parent's index
-    int leaf = 0, root = 0;
-    for (int next = 0; next < n - 1; ++next) {
-      uint64_t w;
-      if (leaf >= n || (root < next && A[root] < A[leaf])) {
-        w = A[root];
-        A[root++] = (uint64_t)next;
-      } else {
-        w = A[leaf++];
-      }
-      if (leaf >= n || (root < next && A[root] < A[leaf])) {
-        w += A[root];
-        A[root++] = (uint64_t)next;
-      } else {
-        w += A[leaf++];
-      }
-      A[next] = w;
-    }
-    // phase 2: internal node depths
-    A[n - 2] = 0;
-    for (int next = n - 3; next >= 0; --next) A[next] = A[A[next]] + 1;
-    // phase 3: leaf depths, deepest for the smallest weights
-    int avbl = 1, used = 0, depth = 0, rt = n - 2, nx = n - 1;
-    while (avbl > 0) {
-      while (rt >= 0 && (int)A[rt] == depth) {
-        ++used;
-        --rt;
-      }
-      while (avbl > used) {
-        A[nx--] = (uint64_t)depth;
-        --avbl;
-      }
-      avbl = 2 * used;
-      ++depth;
-      used = 0;
-    }
-  }
-  __syncthreads();
   if (n == 1) {
     if (t == 0) lens[syms[0]] = 1;
-  } else {
-    for (int i = t; i < n; i += nt) lens[syms[i]] = (uint8_t)keys[i];
+  } else if (n > 1) {
+    // merge (in place: a consumed internal node's slot takes its parent's index)
+    if (t == 0) {
+      uint64_t* A = keys;
+      const uint64_t INF = ~0ull;
+      // register windows over both queues: lq[i] = weight of leaf (leaf + i),
+      // iq[i] = weight of internal node (root + i) (INF until it exists); the
+      // loads that refill a window are issued several picks before they are used
+      uint64_t lq0 = A[0], lq1 = n > 1 ? A[1] : INF, lq2 = n > 2 ? A[2] : INF, lq3 = n > 3 ? A[3] : INF;
+      uint64_t iq0 = INF, iq1 = INF, iq2 = INF, iq3 = INF;
+      int leaf = 0, root = 0;
+      for (int next = 0; next < n - 1; ++next) {
+        uint64_t w = 0;
+#pragma unroll
+        for (int pick = 0; pick < 2; ++pick) {
+          // the internal queue holds the nodes [root, next); the leaf queue wins ties
+          if (leaf < n && (root >= next || lq0 <= iq0)) {
+            w += lq0;
+            ++leaf;
+            lq0 = lq1;
+            lq1 = lq2;
+            lq2 = lq3;
+            lq3 = leaf + 3 < n ? A[leaf + 3] : INF;
+          } else {
+            w += iq0;
+            A[root] = (uint64_t)next;
+            ++root;
+            iq0 = iq1;
+            iq1 = iq2;
+            iq2 = iq3;
+            iq3 = root + 3 < next ? A[root + 3] : INF;
+          }
+        }
+        A[next] = w;
+        // the new node enters the internal window if it is among its first four
+        const int pos = next - root;
+        if (pos == 0)
+          iq0 = w;
+        else if (pos == 1)
+          iq1 = w;
+        else if (pos == 2)
+          iq2 = w;
+        else if (pos == 3)
+          iq3 = w;
+      }
+    }
+    __syncthreads();
+    // internal node k < n-1: parent index in keys[k] (the root n-2 holds its weight)
+    const int ni = n - 1;
+    for (int k = t; k < ni; k += nt) {
+      par[k] = (uint16_t)(k == ni - 1 ? k : (int)keys[k]);
+      dep[k] = k == ni - 1 ? 0 : 1;
+    }
+    __syncthreads();
+    for (int step = 1; step < ni; step <<= 1) {  // pointer jumping: depth = hops to the root
+      int nd[8], np[8];
+      int c = 0;
+      for (int k = t; k < ni; k += nt, ++c) {
+        const int p = par[k];
+        nd[c] = dep[k] + dep[p];
+        np[c] = par[p];
+      }
+      __syncthreads();
+      c = 0;
+      for (int k = t; k < ni; k += nt, ++c) {
+        dep[k] = (uint8_t)nd[c];
+        par[k] = (uint16_t)np[c];
+      }
+      __syncthreads();
+    }
+    for (int k = t; k < ni; k += nt) atomicAdd(&icount[dep[k]], 1u);
+    __syncthreads();
+    if (t == 0) {
+      // leaves at depth d: 2 * (internal nodes at depth d-1) - (internal nodes at depth d);
+      // the smallest weights take the deepest leaves
+      uint32_t start = 0;
+      for (int d = MAXLEN; d >= 1; --d) {
+        const uint32_t leaves = 2 * icount[d - 1] - icount[d];
+        lstart[d] = start;
+        start += leaves;
+      }
+      lstart[0] = start;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += nt) {
+      int d = MAXLEN;
+      while (d > 1 && lstart[d - 1] <= (uint32_t)i) --d;
+      lens[syms[i]] = (uint8_t)d;
+    }
   }
   __syncthreads();
-  for (int s = t; s < dict; s += nt)
-    if (lens[s]) atomicAdd(&bl_count[lens[s]], 1u);
-  __syncthreads();
-  if (t == 0) {
-    // canonical codes: first code per length, then consecutive in symbol order
-    uint64_t code = 0;
-    next_code[0] = 0;
-    for (int b = 1; b <= MAXLEN; ++b) {
-      code = (code + (b > 1 ? bl_count[b - 1] : 0)) << 1;
-      next_code[b] = code;
-    }
-    for (int s = 0; s < dict; ++s) {
-      const int L = lens[s];
-      keys[s] = L ? next_code[L]++ : 0ull;
-    }
-  }
+  // canonical codes: sort by (length, symbol), then consecutive codes per length
+  for (int i = t; i <= MAXLEN; i += nt) lcount[i] = 0;
   __syncthreads();
   for (int s = t; s < dict; s += nt) {
+    keys[s] = lens[s] ? (((uint64_t)lens[s] << 16) | (uint64_t)s) : ~0ull;
+    if (lens[s]) atomicAdd(&lcount[lens[s]], 1u);
+  }
+  __syncthreads();
+  bitonic();
+  if (t == 0) {
+    uint64_t code = 0;
+    uint32_t off = 0;
+    for (int b = 1; b <= MAXLEN; ++b) {
+      code = (code + (b > 1 ? lcount[b - 1] : 0)) << 1;
+      first[b] = code;
+      loff[b] = off;
+      off += lcount[b];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < dict; i += nt) {
+    const uint64_t k = keys[i];
+    if (k == ~0ull) continue;
+    const int L = (int)(k >> 16), s = (int)(k & 0xffff);
+    codes[s] = first[L] + (uint64_t)(i - (int)loff[L]);
+  }
+  for (int s = t; s < dict; s += nt) {
     len_out[s] = lens[s];
-    codes[s] = keys[s];
+    if (!lens[s]) codes[s] = 0;
   }
 }
 
@@ -366,7 +429,7 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
 }
 
 // One thread per chunk.  status[0] is set to 1 on malformed input.
-__global__ void __launch_bounds__(64) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
+__global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
                                                const uint64_t* __restrict__ word_off,
                                                const uint32_t* __restrict__ chunk_bits, uint64_t n, int chunk,
                                                uint64_t nch, const DecTables* __restrict__ tab,
@@ -382,7 +445,10 @@ __global__ void __launch_bounds__(64) k_decode(const uint32_t* __restrict__ payl
     lim1[b] = tab->lim1[b];
     offs[b] = tab->offset[b];
   }
-  for (int s = threadIdx.x; s < dict; s += blockDim.x) sorted[s] = sorted_g[s];
+  {
+    const int used = tab->maxlen ? (int)(tab->offset[tab->maxlen] + tab->count[tab->maxlen]) : 0;
+    for (int s = threadIdx.x; s < used && s < dict; s += blockDim.x) sorted[s] = sorted_g[s];
+  }
   __syncthreads();
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nch) return;
@@ -556,9 +622,9 @@ void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const u
   hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(1024), 0, st, len, dict, tab, sorted);
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch) {
-    const unsigned blocks = (unsigned)((nch + 63) / 64);
+    const unsigned blocks = (unsigned)((nch + 255) / 256);
     KernelTimer kt("decode", st);
-    hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(64), 0, st, payload, payload_words, word_off, chunk_bits, n,
+    hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits, n,
                        chunk, nch, tab, sorted, dict, sym, esc_off, n_out, outliers, qside, d_status);
   }
   MG_HIP(hipGetLastError());

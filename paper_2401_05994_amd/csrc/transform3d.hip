@@ -30,7 +30,7 @@ constexpr int NT = 256;             // threads per block
 constexpr int TY = 8, TX = 64;      // coarse outputs per tile in dims 1 and 2
 constexpr int RY = 2 * TY + 3;      // fine rows of a tile (with a halo of 2)
 constexpr int RX = 2 * TX + 3;      // fine columns of a tile
-constexpr int SEG = 16;             // coarse intervals of dim 0 per block
+constexpr int PER = (RY * RX + NT - 1) / NT;  // tile elements per thread
 constexpr int AXPY_LDS = 65536;     // bytes of LDS for the contiguous-dimension solve
 
 __device__ inline bool is_new(int f, int n) { return (f & 1) && f < n - 1; }
@@ -107,7 +107,8 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* __restrict__ ucoarse,
                                                    T* __restrict__ g1, uint16_t* __restrict__ sym,
                                                    int64_t* __restrict__ qside, T* __restrict__ cstream,
-                                                   const double* __restrict__ bins, int level, int R, Lv3<T> p) {
+                                                   const double* __restrict__ bins, int level, int R, Lv3<T> p,
+                                                   int seg) {
   __shared__ T U[RY * RX];
   __shared__ T BA[RY * RX];
   __shared__ T BB[RY * RX];
@@ -117,8 +118,8 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   const int J1 = blockIdx.y * TY, J2 = blockIdx.x * TX;
   const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
   const int n0 = p.n0, n1 = p.n1, n2 = p.n2;
-  const int cb = blockIdx.z * SEG;
-  const int ce = min(cb + SEG, p.c0 - 1);
+  const int cb = blockIdx.z * seg;
+  const int ce = min(cb + seg, p.c0 - 1);
   const uint64_t plane = (uint64_t)n1 * n2;
   // owned fine ranges of this tile
   const int o1b = 2 * J1, o1e = min(2 * (J1 + TY), n1);
@@ -127,11 +128,24 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   if (MODE == 1) inv_b = 1.0 / bins[level];
   load_sub(subs, p.sub, p.level_off);
 
-  auto load_plane = [&](int f0) {
-    for (int k = t; k < RY * RX; k += NT) {
+  // the next plane is loaded into registers while the current one is processed
+  T pre[PER];
+  auto prefetch = [&](int f0) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int k = t + e * NT;
       const int r = k / RX, x = k - r * RX;
       const int f1 = F1 + r, f2 = F2 + x;
-      U[k] = (f1 >= 0 && f1 < n1 && f2 >= 0 && f2 < n2) ? u[(uint64_t)f0 * plane + (uint64_t)f1 * n2 + f2] : T(0);
+      pre[e] = (k < RY * RX && f1 >= 0 && f1 < n1 && f2 >= 0 && f2 < n2)
+                   ? u[(uint64_t)f0 * plane + (uint64_t)f1 * n2 + f2]
+                   : T(0);
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int k = t + e * NT;
+      if (k < RY * RX) U[k] = pre[e];
     }
     __syncthreads();
   };
@@ -198,25 +212,61 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
     __syncthreads();
   };
 
+  // Planes of the segment in order: the first coarse plane, then per interval
+  // j its closing coarse plane (kind 1) and, when the interval has one, its new
+  // plane (kind 2).  Kind 1 planes build the right interpolant; a new plane
+  // uses the left and right ones; the two swap when an interval is done.
+  auto task_at = [&](int j, int phase, int& plane, int& kind, int& tj) -> bool {
+    while (j < ce) {
+      const int fcj = cpos(j, p.c0, n0), fnj = cpos(j + 1, p.c0, n0);
+      if (phase == 0) {
+        plane = fnj, kind = 1, tj = j;
+        return true;
+      }
+      if (fnj - fcj == 2) {
+        plane = fcj + 1, kind = 2, tj = j;
+        return true;
+      }
+      ++j;
+      phase = 0;
+    }
+    return false;
+  };
   T* Bp = BA;
   T* Bn = BB;
-  int fc = cpos(cb, p.c0, n0);
-  load_plane(fc);
-  build_b(Bp);
-  emit(fc, Bp, Bp);
-  for (int j = cb; j < ce; ++j) {
-    const int fn = cpos(j + 1, p.c0, n0);
-    load_plane(fn);
-    build_b(Bn);
-    if (j + 1 < ce || j + 1 == p.c0 - 1) emit(fn, Bn, Bn);
-    if (fn - fc == 2) {
-      load_plane(fc + 1);
-      emit(fc + 1, Bp, Bn);
+  int cplane = cpos(cb, p.c0, n0), ckind = 0, cj = cb;
+  int nj = cb, nph = 0;
+  prefetch(cplane);
+  commit();
+  while (true) {
+    if (ckind != 2) build_b(ckind == 0 ? Bp : Bn);
+    int xplane = 0, xkind = 0, xj = 0;
+    const bool more = task_at(nj, nph, xplane, xkind, xj);
+    if (more) prefetch(xplane);
+    if (ckind == 0)
+      emit(cplane, Bp, Bp);
+    else if (ckind == 1) {
+      if (cj + 1 < ce || cj + 1 == p.c0 - 1) emit(cplane, Bn, Bn);
+    } else {
+      emit(cplane, Bp, Bn);
     }
-    T* tmp = Bp;
-    Bp = Bn;
-    Bn = tmp;
-    fc = fn;
+    const bool interval_done =
+        ckind == 2 || (ckind == 1 && cpos(cj + 1, p.c0, n0) - cpos(cj, p.c0, n0) == 1);
+    if (interval_done) {
+      T* tmp = Bp;
+      Bp = Bn;
+      Bn = tmp;
+    }
+    if (!more) break;
+    if (xkind == 1) {
+      nj = xj;
+      nph = 1;
+    } else {
+      nj = xj + 1;
+      nph = 0;
+    }
+    commit();
+    cplane = xplane, ckind = xkind, cj = xj;
   }
 }
 
@@ -409,13 +459,16 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
   const bool fine = l == h.L;
   {
     KernelTimer kt(fine ? "coeff_r21_fine" : "coeff_r21_coarse", st);
-    dim3 grid((p.c2 + TX - 1) / TX, (p.c1 + TY - 1) / TY, (p.c0 - 1 + SEG - 1) / SEG);
+    // coarse intervals of dim 0 per block: enough blocks to fill the chip, at most 16
+    const uint64_t tiles = (uint64_t)((p.c2 + TX - 1) / TX) * ((p.c1 + TY - 1) / TY);
+    const int seg = (int)std::max<uint64_t>(1, std::min<uint64_t>(16, ((uint64_t)(p.c0 - 1) * tiles + 4095) / 4096));
+    dim3 grid((p.c2 + TX - 1) / TX, (p.c1 + TY - 1) / TY, (p.c0 - 1 + seg - 1) / seg);
     if (q)
       hipLaunchKernelGGL((k3_coeff_r21<T, 1>), grid, dim3(NT), 0, st, u, ucoarse, g1, q->sym, q->qside,
-                         (T*)nullptr, q->bins, l, q->R, p);
+                         (T*)nullptr, q->bins, l, q->R, p, seg);
     else
       hipLaunchKernelGGL((k3_coeff_r21<T, 0>), grid, dim3(NT), 0, st, u, ucoarse, g1, (uint16_t*)nullptr,
-                         (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p);
+                         (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, seg);
   }
   const uint64_t lines = (uint64_t)p.c1 * p.c2;
   {
@@ -455,15 +508,15 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
   }
   const uint64_t lines = (uint64_t)p.c1 * p.c2;
   {
-    KernelTimer kt(fine ? "r0_thomas0_fine" : "r0_thomas0_coarse", st);
+    KernelTimer kt(fine ? "rec_r0_thomas0_fine" : "rec_r0_thomas0_coarse", st);
     hipLaunchKernelGGL(k3_r0_thomas0<T>, dim3(blocks1(lines)), dim3(NT), 0, st, g1, z, p.n0, p.c0, lines, p.d0);
   }
   {
-    KernelTimer kt(fine ? "thomas1_fine" : "thomas1_coarse", st);
+    KernelTimer kt(fine ? "rec_thomas1_fine" : "rec_thomas1_coarse", st);
     launch_thomas_strided<T>(z, (uint64_t)p.c0, p.c1, (uint64_t)p.c2, dim_consts<T>(h, l, 2, table), st);
   }
   {
-    KernelTimer kt(fine ? "thomas2_sub_fine" : "thomas2_sub_coarse", st);
+    KernelTimer kt(fine ? "rec_thomas2_sub_fine" : "rec_thomas2_sub_coarse", st);
     const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / sizeof(T) / p.c2)));
     const uint64_t nrows = (uint64_t)p.c0 * p.c1;
     // uc = u_{l-1} - z, written over z
