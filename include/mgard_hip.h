@@ -127,6 +127,57 @@ mgard_status mgard_compress(uint32_t ndim, const uint64_t* shape, const double* 
 mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
                               uint64_t out_capacity, const mgard_opts* opts, mgard_header* hdr);
 
+/* ------------------------------------------------------------- batches
+ * A project addition (the paper compresses one variable per call, Sec. 3):
+ * many fields of different shapes compressed by one graph launch.
+ *
+ * mgard_batch_create plans the compression of `nfields` fields (each with its
+ * own shape, coordinates, dtype and device input; opts->alloc must be PLAIN or
+ * COUNT) under one tolerance into d_out: field i is written at byte offset
+ * h_offsets[i] (host array of nfields, filled by the call; slots are
+ * mgard_compress_bound bytes, 256-byte aligned, in field order) and its
+ * compressed size goes to d_sizes[i] (device, uint64) at each launch.  The
+ * call allocates the plan's scratch (one device allocation, owned by the
+ * plan), uploads the headers and constant tables, runs the autotuner for the
+ * fields' level shapes (mgard_autotune), then captures every field's
+ * compression into one HIP graph over a few parallel branches.  Nothing in the
+ * graph allocates, copies from host memory, sets memory or synchronises with
+ * the host.  Inputs and output are bound at creation: each launch compresses
+ * the current contents of the same input buffers.  MGARD_ERR_CAPACITY when
+ * out_capacity < mgard_batch_bound().
+ *
+ * mgard_batch_launch replays the graph on `stream` (a hipStream_t, NULL for
+ * the default stream) with one hipGraphLaunch and returns without waiting.
+ * Launches of one plan must not overlap; distinct plans are independent. */
+typedef struct {
+  uint32_t ndim;
+  uint32_t dtype;             /* mgard_dtype */
+  uint64_t shape[4];
+  const double* coords[4];    /* host; NULL entries: uniform 0..n-1 */
+  const void* d_in;           /* device, C order */
+} mgard_field;
+
+typedef struct mgard_batch mgard_batch;
+
+uint64_t mgard_batch_bound(uint32_t nfields, const mgard_field* fields, const mgard_opts* opts);
+mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, double tol, void* d_out,
+                                uint64_t out_capacity, uint64_t* h_offsets, uint64_t* d_sizes,
+                                const mgard_opts* opts, mgard_batch** plan);
+mgard_status mgard_batch_launch(mgard_batch* plan, void* stream);
+void mgard_batch_free(mgard_batch* plan);
+
+/* Autotuner (project addition).  For each level of the fused 3D path of this
+ * shape and dtype, times the candidate launch shapes of the decomposition's
+ * plane-marching kernel (coarse intervals per block) and of the
+ * recomposition's scatter kernel (fine planes per block) on d_in and keeps
+ * the fastest; later compressions and decompressions of that level shape use
+ * them.  The choices persist in the JSON file named by the environment
+ * variable MGARD_TUNE_FILE when it is set (read at the first call, rewritten
+ * after each tuning).  Shapes without a fused 3D path have nothing to tune
+ * (MGARD_OK).  Tuning runs kernels on opts->stream and synchronises it. */
+mgard_status mgard_autotune(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                            mgard_dtype dtype, const void* d_in, const mgard_opts* opts);
+
 /* Host-only header parser: h_buf holds at least the first `bytes` bytes of a
  * compressed buffer.  Returns MGARD_ERR_FORMAT when they do not form a valid
  * header (MGARD_ERR_CAPACITY when more bytes are needed for the full header;
@@ -172,7 +223,8 @@ mgard_status mgard_dequantize(uint32_t ndim, const uint64_t* shape, mgard_dtype 
 
 /* Histogram of n uint16 symbols into d_hist (uint64, dict_size entries) and
  * the number of escape symbols (0) in each chunk into d_chunk_esc (uint32,
- * ceil(n/chunk) entries). */
+ * ceil(n/chunk) entries).  d_symbols must be 16-byte aligned; MGARD_ERR_ARG
+ * for a symbol outside the dictionary. */
 mgard_status mgard_histogram(const uint16_t* d_symbols, uint64_t n, uint32_t dict_size,
                              uint32_t chunk, uint64_t* d_hist, uint32_t* d_chunk_esc,
                              const mgard_opts* opts);
@@ -187,14 +239,17 @@ mgard_status mgard_huffman_codebook(const uint64_t* d_hist, uint32_t dict_size,
 /* Chunked encoding: each chunk of `chunk` symbols is packed MSB-first into
  * 32-bit words starting word-aligned; d_chunk_bits (uint32) receives its bit
  * count, d_payload the concatenated chunks.  *payload_words (host) receives
- * the payload length; payload_capacity is in words. */
+ * the payload length; payload_capacity is in words.  d_symbols must be
+ * 16-byte aligned. */
 mgard_status mgard_huffman_encode(const uint16_t* d_symbols, uint64_t n, uint32_t dict_size,
                                   uint32_t chunk, const uint8_t* d_code_len,
                                   const uint64_t* d_codes, uint32_t* d_chunk_bits,
                                   uint32_t* d_payload, uint64_t payload_capacity,
                                   uint64_t* payload_words, const mgard_opts* opts);
 
-/* Inverse of mgard_huffman_encode. */
+/* Inverse of mgard_huffman_encode.  d_symbols must be 16-byte aligned
+ * (MGARD_ERR_ARG otherwise); MGARD_ERR_FORMAT when the payload does not
+ * decode to exactly n symbols with the given bit counts. */
 mgard_status mgard_huffman_decode(const uint32_t* d_payload, uint64_t payload_words,
                                   const uint32_t* d_chunk_bits, uint64_t n, uint32_t dict_size,
                                   uint32_t chunk, const uint8_t* d_code_len, uint16_t* d_symbols,

@@ -91,6 +91,11 @@ def load_library():
         "mgard_plain_constant": (C.c_int, [U32, PU64, P, PD, PD, U32]),
         "mgard_timing": (C.c_int, [C.c_int]),
         "mgard_timing_report": (C.c_int, [C.c_char_p, U64, PU64]),
+        "mgard_autotune": (C.c_int, [U32, PU64, P, C.c_int, P, P]),
+        "mgard_batch_bound": (U64, [U32, P, P]),
+        "mgard_batch_create": (C.c_int, [U32, P, D, P, U64, PU64, P, P, C.POINTER(P)]),
+        "mgard_batch_launch": (C.c_int, [P, P]),
+        "mgard_batch_free": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -505,3 +510,87 @@ def mgard_mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, e
     o = make_opts()
     _check(lib.mgard_mlp_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(step), lr, beta1, beta2, eps,
                               C.byref(o)))
+
+
+# ---------------------------------------------------------------- batches
+
+
+class mgard_field(C.Structure):
+    _fields_ = [("ndim", C.c_uint32), ("dtype", C.c_uint32), ("shape", C.c_uint64 * 4),
+                ("coords", C.c_void_p * 4), ("d_in", C.c_void_p)]
+
+
+def mgard_autotune(u, coords=None, dict_size=8192, chunk=1024):
+    """Runs the launch-shape tuner for the levels of u's shape (see mgard_autotune in the header)."""
+    lib = load_library()
+    u = u.contiguous()
+    cc = _Coords(coords, u.dim())
+    o = make_opts(dict_size=dict_size, chunk=chunk)
+    _check(lib.mgard_autotune(u.dim(), _shape(u.shape), cc.ptr, _dtype_code(u), _ptr(u), C.byref(o)))
+
+
+class Batch:
+    """A captured batch plan: many fields compressed by one graph launch.
+
+    fields: CUDA float tensors (kept alive by the plan); coords: None or one
+    entry per field (None or a per-dimension list).  launch() replays the
+    graph on the current stream; results() waits and returns, per field, the
+    compressed bytes as a view of the shared output buffer.
+    """
+
+    def __init__(self, fields, tol, coords=None, eb="rel", alloc="plain", dict_size=8192, chunk=1024):
+        torch = _torch()
+        lib = load_library()
+        self.fields = [f.contiguous() for f in fields]
+        n = len(self.fields)
+        arr = (mgard_field * n)()
+        self._coords = []
+        for i, f in enumerate(self.fields):
+            arr[i].ndim = f.dim()
+            arr[i].dtype = _dtype_code(f)
+            for d in range(f.dim()):
+                arr[i].shape[d] = int(f.shape[d])
+            cf = coords[i] if coords is not None else None
+            if cf is not None:
+                for d, x in enumerate(cf):
+                    if x is not None:
+                        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+                        self._coords.append(a)
+                        arr[i].coords[d] = a.ctypes.data
+            arr[i].d_in = f.data_ptr()
+        self._arr = arr
+        o = make_opts(eb, alloc, dict_size, chunk)
+        bound = lib.mgard_batch_bound(n, C.cast(arr, C.c_void_p), C.byref(o))
+        if bound == 0:
+            _check(-1)
+        dev = self.fields[0].device
+        self.out = torch.empty(int(bound), dtype=torch.uint8, device=dev)
+        self.sizes = torch.zeros(n, dtype=torch.int64, device=dev)
+        offs = (C.c_uint64 * n)()
+        plan = C.c_void_p()
+        _check(lib.mgard_batch_create(n, C.cast(arr, C.c_void_p), float(tol), _ptr(self.out), self.out.numel(),
+                                      offs, _ptr(self.sizes), C.byref(o), C.byref(plan)))
+        self.plan = plan
+        self.offsets = [int(offs[i]) for i in range(n)]
+
+    def launch(self, stream=None):
+        if stream is None:
+            stream = _torch().cuda.current_stream().cuda_stream
+        _check(load_library().mgard_batch_launch(self.plan, C.c_void_p(stream)))
+
+    def results(self):
+        torch = _torch()
+        torch.cuda.synchronize()
+        sizes = self.sizes.cpu().tolist()
+        return [(self.out[o:o + s], s) for o, s in zip(self.offsets, sizes)]
+
+    def close(self):
+        if getattr(self, "plan", None):
+            load_library().mgard_batch_free(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -27,6 +27,15 @@ struct mgard_model {
   int device = -1;
 };
 
+// A captured batch: the graph, its executable form and the one device
+// allocation holding every field's static header and scratch.
+struct mgard_batch {
+  int device = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* mem = nullptr;
+};
+
 namespace mg {
 
 void fail(mgard_status code, const std::string& msg) { throw Failure{code, msg}; }
@@ -150,7 +159,7 @@ __global__ void k_outlier_offset(const uint64_t* word_off, uint64_t nch, uint64_
 
 __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* esc_off, uint64_t nch,
                            const uint64_t* ooff, const double* scalars, const double* bins, int L,
-                           uint64_t bins_off, int learned, Finale* fin) {
+                           uint64_t bins_off, int learned, Finale* fin, uint64_t* size_out) {
   const int fallback = learned && scalars[5] != 0.0 ? 1 : 0;
   if (threadIdx.x != 0) return;
   const uint64_t pw = word_off[nch], no = esc_off[nch];
@@ -164,6 +173,7 @@ __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* 
   double* bo = reinterpret_cast<double*>(out + bins_off);
   for (int l = 0; l <= L; ++l) bo[l] = bins[l];
   fin->total_bytes = *ooff + 8 * no;
+  if (size_out) *size_out = fin->total_bytes;
   fin->n_outliers = no;
   fin->payload_words = pw;
   for (int i = 0; i < 6; ++i) fin->scalars[i] = scalars[i];
@@ -318,21 +328,15 @@ void check_bins(const Parsed& P, const uint8_t* b) {
   }
 }
 
+// Scratch bytes of one compression.
 template <typename T>
-void compress_impl(Hierarchy& h, const double* const* coords, double tol, const T* d_in, char* d_out,
-                   uint64_t* out_bytes, const Opts& o, mgard_info* info) {
-  const bool f64 = sizeof(T) == 8;
-  hipStream_t st = o.st;
-  const T* table = static_cast<const T*>(device_table(h, f64, st));
+uint64_t compress_scratch_bytes(const Hierarchy& h, const Opts& o, uint64_t nch) {
   const uint64_t n = h.count(h.L);
-  Layout y = layout(h, coords, o.dict, o.chunk, n);
-  const uint64_t nch = y.nch;
-  // scratch
   const uint64_t dbytes = decompose_scratch_bytes<T>(h);
   uint64_t need = dbytes + carve_size<uint16_t>(n) + carve_size<int64_t>(n) +
                   carve_size<double>(MAXL + 1) + carve_size<double>(8) + carve_size<uint64_t>(4) +
                   2 * carve_size<uint64_t>((uint64_t)o.dict) + 2 * carve_size<uint64_t>(nch + 1) +
-                  carve_size<Finale>(1) + 4096;
+                  carve_size<Finale>(1) + encode_scratch_bytes(o.dict) + 4096;
   const int nl = h.L + 1;
   const uint64_t lbytes =
       o.alloc == MGARD_ALLOC_LEARNED
@@ -341,10 +345,32 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
                 carve_size<float>(MAXL + 1) + carve_size<float>((uint64_t)2 * MLP_HID * (MAXL + 1)) +
                 carve_size<double>(MAXL + 1) + carve_size<unsigned long long>(1) + 1024
           : 0;
-  need += lbytes;
-  Workspace& ws = workspace();
-  ws.reserve(need);
-  Carver cv(ws.base());
+  return need + lbytes;
+}
+
+// Every device step of one compression, enqueued on o.st with no host
+// synchronisation, host-memory copy or memset, so that it can be captured in
+// a graph.  The static header is copied from `header` (device memory); the
+// results land in *fin_out (device) and, when size_out is given, the total
+// size in *size_out (device).
+template <typename T>
+Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double tol, const T* d_in, char* d_out,
+                         const Opts& o, void* scratch, const uint8_t* header, uint64_t header_bytes,
+                         uint64_t* size_out) {
+  const bool f64 = sizeof(T) == 8;
+  hipStream_t st = o.st;
+  const uint64_t n = h.count(h.L);
+  const uint64_t nch = y.nch;
+  const uint64_t dbytes = decompose_scratch_bytes<T>(h);
+  const int nl = h.L + 1;
+  const uint64_t lbytes =
+      o.alloc == MGARD_ALLOC_LEARNED
+          ? 2 * carve_size<T>(n) + carve_size<uint64_t>(MAXL + 2) + carve_size<double>((uint64_t)2 * nl * STATS_BLOCKS) +
+                carve_size<double>(3 * (MAXL + 1)) + carve_size<float>((uint64_t)MLP_IN * (MAXL + 1)) +
+                carve_size<float>(MAXL + 1) + carve_size<float>((uint64_t)2 * MLP_HID * (MAXL + 1)) +
+                carve_size<double>(MAXL + 1) + carve_size<unsigned long long>(1) + 1024
+          : 0;
+  Carver cv(scratch);
   void* dscratch = cv.take<char>(dbytes);
   void* learned_scratch = lbytes ? cv.take<char>(lbytes) : nullptr;
   uint16_t* sym = cv.take<uint16_t>(n);
@@ -357,9 +383,10 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
   uint64_t* word_off = cv.take<uint64_t>(nch + 1);
   uint64_t* esc_off = cv.take<uint64_t>(nch + 1);
   Finale* fin = cv.take<Finale>(1);
+  void* enc_scratch = cv.take<char>(encode_scratch_bytes(o.dict));
 
-  std::vector<uint8_t> hb = header_bytes(h, coords, f64 ? 1 : 0, o.eb, o.alloc, tol, o.dict, o.chunk, n, nch);
-  MG_HIP(hipMemcpyAsync(d_out, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
+  MG_HIP(hipMemcpyAsync(d_out, header, header_bytes, hipMemcpyDeviceToDevice, st));
+  launch_fill_u64(&misc[2], 1, 0, st);
 
   // tolerance and bin widths
   launch_maxabs<T>(d_in, n, &misc[0], st);
@@ -421,11 +448,31 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
   launch_scan_u32(chunk_esc, nch, esc_off, st);
   hipLaunchKernelGGL(k_outlier_offset, dim3(1), dim3(1), 0, st, word_off, nch, y.payload, &misc[1]);
   launch_encode(sym, n, o.dict, o.chunk, code_len, codes, word_off, reinterpret_cast<uint32_t*>(d_out + y.payload),
-                esc_off, qside, d_out, &misc[1], st);
+                esc_off, qside, d_out, &misc[1], enc_scratch, st);
   hipLaunchKernelGGL(k_zero_pad, dim3(1), dim3(1), 0, st, d_out, word_off, nch, y.payload);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, d_out, word_off, esc_off, nch, &misc[1], scalars, bins,
-                     h.L, y.bins, o.alloc == MGARD_ALLOC_LEARNED ? 1 : 0, fin);
+                     h.L, y.bins, o.alloc == MGARD_ALLOC_LEARNED ? 1 : 0, fin, size_out);
   MG_HIP(hipGetLastError());
+  return fin;
+}
+
+template <typename T>
+void compress_impl(Hierarchy& h, const double* const* coords, double tol, const T* d_in, char* d_out,
+                   uint64_t* out_bytes, const Opts& o, mgard_info* info) {
+  const bool f64 = sizeof(T) == 8;
+  hipStream_t st = o.st;
+  const T* table = static_cast<const T*>(device_table(h, f64, st));
+  const uint64_t n = h.count(h.L);
+  const Layout y = layout(h, coords, o.dict, o.chunk, n);
+  std::vector<uint8_t> hb = header_bytes(h, coords, f64 ? 1 : 0, o.eb, o.alloc, tol, o.dict, o.chunk, n, y.nch);
+  const uint64_t need = compress_scratch_bytes<T>(h, o, y.nch);
+  Workspace& ws = workspace();
+  ws.reserve(need + carve_size<uint8_t>(hb.size()));
+  Carver cv(ws.base());
+  void* scratch = cv.take<char>(need);
+  uint8_t* d_hdr = cv.take<uint8_t>(hb.size());
+  MG_HIP(hipMemcpyAsync(d_hdr, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
+  Finale* fin = compress_enqueue<T>(h, table, y, tol, d_in, d_out, o, scratch, d_hdr, hb.size(), nullptr);
   Finale hf;
   MG_HIP(hipMemcpyAsync(&hf, fin, sizeof(Finale), hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
@@ -455,8 +502,9 @@ void decompress_impl(Hierarchy& h, const Parsed& P, const char* d_in, T* d_out, 
   const uint64_t n = P.hd.n_symbols, nch = P.hd.n_chunks;
   const int dict = (int)P.hd.dict_size, chunk = (int)P.hd.chunk_symbols;
   const uint64_t rbytes = recompose_scratch_bytes<T>(h);
+  const uint64_t n_out = P.hd.n_outliers;
   uint64_t need = rbytes + carve_size<uint16_t>(n) + carve_size<int64_t>(n) + 2 * carve_size<uint64_t>(nch + 1) +
-                  decode_table_bytes(dict) + carve_size<uint32_t>(4) + 4096;
+                  carve_size<uint64_t>(n_out) + decode_table_bytes(dict) + carve_size<uint32_t>(4) + 4096;
   Workspace& ws = workspace();
   ws.reserve(need);
   Carver cv(ws.base());
@@ -465,6 +513,7 @@ void decompress_impl(Hierarchy& h, const Parsed& P, const char* d_in, T* d_out, 
   int64_t* qside = cv.take<int64_t>(n);
   uint64_t* word_off = cv.take<uint64_t>(nch + 1);
   uint64_t* esc_off = cv.take<uint64_t>(nch + 1);
+  uint64_t* epos = cv.take<uint64_t>(n_out);
   void* tabs = cv.take<char>(decode_table_bytes(dict));
   uint32_t* status = cv.take<uint32_t>(4);
   MG_HIP(hipMemsetAsync(status, 0, 16, st));
@@ -474,7 +523,7 @@ void decompress_impl(Hierarchy& h, const Parsed& P, const char* d_in, T* d_out, 
   launch_scan_u32(chunk_esc, nch, esc_off, st);
   launch_decode_full(reinterpret_cast<const uint32_t*>(d_in + P.payload), P.hd.payload_words, word_off,
                      chunk_bits, n, dict, chunk, reinterpret_cast<const uint8_t*>(d_in + P.code_len), sym,
-                     esc_off, P.hd.n_outliers, reinterpret_cast<const int64_t*>(d_in + P.outliers), qside, tabs,
+                     esc_off, n_out, reinterpret_cast<const int64_t*>(d_in + P.outliers), qside, epos, tabs,
                      status, st);
   QuantOut q;
   q.sym = sym;
@@ -486,6 +535,97 @@ void decompress_impl(Hierarchy& h, const Parsed& P, const char* d_in, T* d_out, 
   MG_HIP(hipMemcpyAsync(hs, status, 16, hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
   if (hs[0]) fail(MGARD_ERR_FORMAT, "payload does not decode");
+}
+
+// Plain widths for tol 1e-3 (relative) of d_in and the quantized level
+// buffers, then the timing of every fused 3D level's launch candidates.
+template <typename T>
+void autotune_impl(Hierarchy& h, const T* d_in, const Opts& o) {
+  if (!fused3d_ok<T>(h) || h.L < 1) return;
+  const bool f64 = sizeof(T) == 8;
+  hipStream_t st = o.st;
+  const T* table = static_cast<const T*>(device_table(h, f64, st));
+  const uint64_t n = h.count(h.L);
+  const uint64_t dbytes = decompose_scratch_bytes<T>(h);
+  Workspace& ws = workspace();
+  ws.reserve(dbytes + carve_size<uint16_t>(n) + carve_size<int64_t>(n) + carve_size<double>(MAXL + 1) +
+             carve_size<double>(8) + carve_size<uint64_t>(4) + 1024);
+  Carver cv(ws.base());
+  void* dscratch = cv.take<char>(dbytes);
+  uint16_t* sym = cv.take<uint16_t>(n);
+  int64_t* qside = cv.take<int64_t>(n);
+  double* bins = cv.take<double>(MAXL + 1);
+  double* scalars = cv.take<double>(8);
+  uint64_t* misc = cv.take<uint64_t>(4);
+  launch_maxabs<T>(d_in, n, &misc[0], st);
+  BinArgs ba{};
+  for (int l = 0; l <= h.L; ++l) {
+    ba.K[l] = h.K[l];
+    ba.counts[l] = (double)h.level_count[l];
+  }
+  launch_bins(f64 ? 1 : 0, &misc[0], 1e-3, MGARD_REL, h.S, h.L, MGARD_ALLOC_PLAIN, ba, bins, scalars, st);
+  QuantOut q;
+  q.sym = sym;
+  q.qside = qside;
+  q.bins = bins;
+  q.R = o.dict / 2;
+  fused3d_tune<T>(h, table, d_in, &q, dscratch, st);
+  MG_HIP(hipStreamSynchronize(st));
+}
+
+bool tuned_all_levels(const Hierarchy& h, bool f64) {
+  for (int l = 1; l <= h.L; ++l) {
+    const int n0 = (int)h.sizes[l][1], n1 = (int)h.sizes[l][2], n2 = (int)h.sizes[l][3];
+    if (!tune_known(TUNE_COEFF_SEG, f64, n0, n1, n2) || !tune_known(TUNE_SCATTER_PLANES, f64, n0, n1, n2))
+      return false;
+  }
+  return true;
+}
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+const double* const* field_coords(const mgard_field& f) {
+  for (uint32_t d = 0; d < f.ndim && d < 4; ++d)
+    if (f.coords[d]) return f.coords;
+  return nullptr;
+}
+
+struct BatchJob {
+  std::shared_ptr<Hierarchy> h;
+  Layout y;
+  std::vector<uint8_t> hb;
+  const void* table = nullptr;
+  bool f64 = false;
+  uint64_t scratch = 0, hdr_off = 0, scr_off = 0, out_off = 0, bound = 0;
+};
+
+std::vector<BatchJob> plan_jobs(uint32_t nfields, const mgard_field* fields, double tol, const Opts& o,
+                                bool with_tables, uint64_t* out_total, uint64_t* mem_total) {
+  std::vector<BatchJob> jobs(nfields);
+  uint64_t out_off = 0, mem = 0;
+  for (uint32_t i = 0; i < nfields; ++i) {
+    const mgard_field& f = fields[i];
+    if (f.dtype != MGARD_F32 && f.dtype != MGARD_F64) fail(MGARD_ERR_DTYPE, "field dtype");
+    BatchJob& J = jobs[i];
+    const double* const* cc = field_coords(f);
+    J.h = get_hierarchy(f.ndim, f.shape, cc);
+    J.f64 = f.dtype == MGARD_F64;
+    if (with_tables) J.table = device_table(*J.h, J.f64, o.st);
+    const uint64_t n = J.h->count(J.h->L);
+    J.y = layout(*J.h, cc, o.dict, o.chunk, n);
+    J.hb = header_bytes(*J.h, cc, J.f64 ? 1 : 0, o.eb, o.alloc, tol, o.dict, o.chunk, n, J.y.nch);
+    J.bound = bound_of(*J.h, cc, o.dict, o.chunk);
+    J.out_off = out_off;
+    out_off = align256(out_off + J.bound);
+    J.scratch = J.f64 ? compress_scratch_bytes<double>(*J.h, o, J.y.nch) : compress_scratch_bytes<float>(*J.h, o, J.y.nch);
+    J.hdr_off = mem;
+    mem += align256(J.hb.size());
+    J.scr_off = mem;
+    mem += align256(J.scratch);
+  }
+  *out_total = out_off;
+  *mem_total = mem;
+  return jobs;
 }
 
 struct CoordPtrs {
@@ -556,6 +696,149 @@ mgard_status mgard_compress(uint32_t ndim, const uint64_t* shape, const double* 
       compress_impl<double>(*h, coords, tol, static_cast<const double*>(d_in), static_cast<char*>(d_out),
                             out_bytes, o, info);
   });
+}
+
+mgard_status mgard_autotune(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,
+                            const void* d_in, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_in) fail(MGARD_ERR_ARG, "null buffer");
+    auto h = get_hierarchy(ndim, shape, coords);
+    if (dtype == MGARD_F32)
+      autotune_impl<float>(*h, static_cast<const float*>(d_in), o);
+    else
+      autotune_impl<double>(*h, static_cast<const double*>(d_in), o);
+  });
+}
+
+uint64_t mgard_batch_bound(uint32_t nfields, const mgard_field* fields, const mgard_opts* opts) {
+  uint64_t total = 0;
+  mgard_status s = guard([&] {
+    Opts o = read_opts(opts);
+    if (!fields && nfields) fail(MGARD_ERR_ARG, "null fields");
+    uint64_t mem = 0;
+    (void)plan_jobs(nfields, fields, 1.0, o, false, &total, &mem);
+  });
+  return s == MGARD_OK ? total : 0;
+}
+
+mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, double tol, void* d_out,
+                                uint64_t out_capacity, uint64_t* h_offsets, uint64_t* d_sizes,
+                                const mgard_opts* opts, mgard_batch** plan) {
+  return guard([&] {
+    if (!plan) fail(MGARD_ERR_ARG, "null plan");
+    *plan = nullptr;
+    Opts o = read_opts(opts);
+    if (o.alloc == MGARD_ALLOC_LEARNED) fail(MGARD_ERR_ARG, "batches use the plain or count allocation");
+    if (!nfields || !fields || !d_out || !h_offsets || !d_sizes) fail(MGARD_ERR_ARG, "null buffer or no fields");
+    if (!(tol > 0.0) || !std::isfinite(tol)) fail(MGARD_ERR_TOL, "tolerance must be positive and finite");
+    for (uint32_t i = 0; i < nfields; ++i)
+      if (!fields[i].d_in) fail(MGARD_ERR_ARG, "null field input");
+    std::unique_ptr<mgard_batch, void (*)(mgard_batch*)> B(new mgard_batch, mgard_batch_free);
+    MG_HIP(hipGetDevice(&B->device));
+    uint64_t out_total = 0, mem_total = 0;
+    std::vector<BatchJob> jobs = plan_jobs(nfields, fields, tol, o, true, &out_total, &mem_total);
+    if (out_capacity < out_total) fail(MGARD_ERR_CAPACITY, "output capacity below mgard_batch_bound");
+    if (hipMalloc(&B->mem, std::max<uint64_t>(mem_total, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      B->mem = nullptr;
+      fail(MGARD_ERR_OOM, "batch scratch");
+    }
+    char* mem = static_cast<char*>(B->mem);
+    for (uint32_t i = 0; i < nfields; ++i) {
+      MG_HIP(hipMemcpy(mem + jobs[i].hdr_off, jobs[i].hb.data(), jobs[i].hb.size(), hipMemcpyHostToDevice));
+      h_offsets[i] = jobs[i].out_off;
+    }
+    // launch shapes for every level shape not tuned yet
+    for (uint32_t i = 0; i < nfields; ++i) {
+      Hierarchy& h = *jobs[i].h;
+      if (tuned_all_levels(h, jobs[i].f64)) continue;
+      if (jobs[i].f64)
+        autotune_impl<double>(h, static_cast<const double*>(fields[i].d_in), o);
+      else
+        autotune_impl<float>(h, static_cast<const float*>(fields[i].d_in), o);
+    }
+    MG_HIP(hipDeviceSynchronize());
+
+    // capture: the fields spread over a few forked streams, joined at the end
+    const int K = (int)std::min<uint32_t>(4, nfields);
+    hipStream_t cs = nullptr;
+    std::vector<hipStream_t> ss(K, nullptr);
+    std::vector<hipEvent_t> ev(K + 1, nullptr);
+    auto cleanup = [&] {
+      for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+      for (auto& x : ss)
+        if (x) (void)hipStreamDestroy(x);
+      if (cs) (void)hipStreamDestroy(cs);
+      timing_pause(false);
+    };
+    try {
+      MG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      for (int k = 0; k < K; ++k) MG_HIP(hipStreamCreateWithFlags(&ss[k], hipStreamNonBlocking));
+      for (int k = 0; k <= K; ++k) MG_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+      timing_pause(true);
+      MG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      try {
+        MG_HIP(hipEventRecord(ev[K], cs));
+        for (int k = 0; k < K; ++k) MG_HIP(hipStreamWaitEvent(ss[k], ev[K], 0));
+        for (uint32_t i = 0; i < nfields; ++i) {
+          const BatchJob& J = jobs[i];
+          Opts oi = o;
+          oi.st = ss[i % K];
+          char* out = static_cast<char*>(d_out) + J.out_off;
+          const uint8_t* hdr = reinterpret_cast<const uint8_t*>(mem + J.hdr_off);
+          if (J.f64)
+            compress_enqueue<double>(*J.h, static_cast<const double*>(J.table), J.y, tol,
+                                     static_cast<const double*>(fields[i].d_in), out, oi, mem + J.scr_off, hdr,
+                                     J.hb.size(), d_sizes + i);
+          else
+            compress_enqueue<float>(*J.h, static_cast<const float*>(J.table), J.y, tol,
+                                    static_cast<const float*>(fields[i].d_in), out, oi, mem + J.scr_off, hdr,
+                                    J.hb.size(), d_sizes + i);
+        }
+        for (int k = 0; k < K; ++k) {
+          MG_HIP(hipEventRecord(ev[k], ss[k]));
+          MG_HIP(hipStreamWaitEvent(cs, ev[k], 0));
+        }
+        MG_HIP(hipStreamEndCapture(cs, &B->graph));
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        throw;
+      }
+      MG_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    } catch (...) {
+      cleanup();
+      throw;
+    }
+    cleanup();
+    *plan = B.release();
+  });
+}
+
+mgard_status mgard_batch_launch(mgard_batch* plan, void* stream) {
+  return guard([&] {
+    if (!plan || !plan->exec) fail(MGARD_ERR_ARG, "null plan");
+    int dev = -1;
+    MG_HIP(hipGetDevice(&dev));
+    if (dev != plan->device) fail(MGARD_ERR_ARG, "plan lives on another device");
+    MG_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+  });
+}
+
+void mgard_batch_free(mgard_batch* plan) {
+  if (!plan) return;
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->mem) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(plan->mem);
+  }
+  delete plan;
 }
 
 mgard_status mgard_inspect(const void* h_buf, uint64_t bytes, mgard_header* hdr) {
@@ -732,6 +1015,7 @@ mgard_status mgard_histogram(const uint16_t* d_symbols, uint64_t n, uint32_t dic
     if (!d_symbols || !d_hist || !d_chunk_esc) fail(MGARD_ERR_ARG, "null buffer");
     if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
     if (chunk < 256 || chunk > 8192 || chunk % 256) fail(MGARD_ERR_ARG, "chunk");
+    if (reinterpret_cast<uintptr_t>(d_symbols) % 16) fail(MGARD_ERR_ARG, "d_symbols must be 16-byte aligned");
     Workspace& ws = workspace();
     ws.reserve(1024);
     uint32_t* status = static_cast<uint32_t*>(ws.base());
@@ -765,10 +1049,13 @@ mgard_status mgard_huffman_encode(const uint16_t* d_symbols, uint64_t n, uint32_
       fail(MGARD_ERR_ARG, "null buffer");
     if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
     if (chunk < 256 || chunk > 8192 || chunk % 256) fail(MGARD_ERR_ARG, "chunk");
+    if (reinterpret_cast<uintptr_t>(d_symbols) % 16) fail(MGARD_ERR_ARG, "d_symbols must be 16-byte aligned");
     const uint64_t nch = (n + chunk - 1) / chunk;
     Workspace& ws = workspace();
-    ws.reserve(carve_size<uint64_t>(nch + 1) + 1024);
-    uint64_t* word_off = static_cast<uint64_t*>(ws.base());
+    ws.reserve(carve_size<uint64_t>(nch + 1) + encode_scratch_bytes((int)dict_size) + 1024);
+    Carver cv(ws.base());
+    uint64_t* word_off = cv.take<uint64_t>(nch + 1);
+    void* enc_scratch = cv.take<char>(encode_scratch_bytes((int)dict_size));
     launch_chunk_bits(d_symbols, n, (int)dict_size, (int)chunk, d_code_len, d_chunk_bits, o.st);
     launch_scan_words(d_chunk_bits, nch, word_off, o.st);
     uint64_t total = 0;
@@ -777,7 +1064,7 @@ mgard_status mgard_huffman_encode(const uint16_t* d_symbols, uint64_t n, uint32_
     *payload_words = total;
     if (total > payload_capacity) fail(MGARD_ERR_CAPACITY, "payload capacity");
     launch_encode(d_symbols, n, (int)dict_size, (int)chunk, d_code_len, d_codes, word_off, d_payload, nullptr, nullptr, nullptr,
-                  nullptr, o.st);
+                  nullptr, enc_scratch, o.st);
     MG_HIP(hipStreamSynchronize(o.st));
   });
 }
@@ -790,6 +1077,7 @@ mgard_status mgard_huffman_decode(const uint32_t* d_payload, uint64_t payload_wo
     if (!d_payload || !d_chunk_bits || !d_code_len || !d_symbols) fail(MGARD_ERR_ARG, "null buffer");
     if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
     if (chunk < 256 || chunk > 8192 || chunk % 256) fail(MGARD_ERR_ARG, "chunk");
+    if (reinterpret_cast<uintptr_t>(d_symbols) % 16) fail(MGARD_ERR_ARG, "d_symbols must be 16-byte aligned");
     const uint64_t nch = (n + chunk - 1) / chunk;
     Workspace& ws = workspace();
     ws.reserve(carve_size<uint64_t>(nch + 1) + decode_table_bytes((int)dict_size) + carve_size<uint32_t>(4) +
@@ -801,7 +1089,7 @@ mgard_status mgard_huffman_decode(const uint32_t* d_payload, uint64_t payload_wo
     MG_HIP(hipMemsetAsync(status, 0, 16, o.st));
     launch_scan_words(d_chunk_bits, nch, word_off, o.st);
     launch_decode_full(d_payload, payload_words, word_off, d_chunk_bits, n, (int)dict_size, (int)chunk,
-                       d_code_len, d_symbols, nullptr, 0, nullptr, nullptr, tabs, status, o.st);
+                       d_code_len, d_symbols, nullptr, 0, nullptr, nullptr, nullptr, tabs, status, o.st);
     uint32_t hs[4];
     MG_HIP(hipMemcpyAsync(hs, status, 16, hipMemcpyDeviceToHost, o.st));
     MG_HIP(hipStreamSynchronize(o.st));

@@ -22,84 +22,195 @@ constexpr int MAXLEN = 64;
 constexpr int MAXDICT = 8192;  // largest dictionary; all LDS below is static
 
 // ------------------------------------------------------------------ histogram
-__global__ void __launch_bounds__(TPB) k_histogram(const uint16_t* __restrict__ sym, uint64_t n, int dict,
-                                                   int chunk, uint64_t nch, unsigned long long* __restrict__ hist,
-                                                   uint32_t* __restrict__ chunk_esc, uint32_t* __restrict__ status) {
+// Blocks of 1024 threads with a private LDS histogram; each wave takes whole
+// chunks (chunk is a multiple of 256), four symbols per lane per step with
+// 8-byte loads, and counts the chunk's escapes with a wave reduction.  Each
+// block adds its nonzero bins to the global histogram once.
+constexpr int WAVE_T = 1024;              // threads of the wave-per-chunk kernels
+constexpr int WAVES = WAVE_T / 64;
+
+// Symbols i .. i+3 of a chunk ending at `end` (i is a multiple of 4); lanes
+// past the end get 0xffffffff.
+__device__ inline void load4_symbols(const uint16_t* __restrict__ sym, uint64_t i, uint64_t end, uint32_t* s) {
+  if (i + 4 <= end) {
+    const uint2 v = *reinterpret_cast<const uint2*>(sym + i);
+    s[0] = v.x & 0xffffu;
+    s[1] = v.x >> 16;
+    s[2] = v.y & 0xffffu;
+    s[3] = v.y >> 16;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = i + j < end ? (uint32_t)sym[i + j] : 0xffffffffu;
+  }
+}
+
+__global__ void __launch_bounds__(WAVE_T) k_histogram(const uint16_t* __restrict__ sym, uint64_t n, int dict,
+                                                      int chunk, uint64_t nch, unsigned long long* __restrict__ hist,
+                                                      uint32_t* __restrict__ chunk_esc,
+                                                      uint32_t* __restrict__ status) {
   __shared__ uint32_t sh[MAXDICT];
-  __shared__ uint32_t esc;
-  for (int b = threadIdx.x; b < dict; b += TPB) sh[b] = 0;
+  for (int b = threadIdx.x; b < dict; b += WAVE_T) sh[b] = 0;
   __syncthreads();
-  for (uint64_t k = blockIdx.x; k < nch; k += gridDim.x) {
-    if (threadIdx.x == 0) esc = 0;
-    __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+  bool bad = false;
+  for (uint64_t k = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); k < nch; k += stride) {
     const uint64_t beg = k * (uint64_t)chunk;
     const uint64_t end = min(beg + (uint64_t)chunk, n);
     uint32_t e = 0;
-    for (uint64_t i = beg + threadIdx.x; i < end; i += TPB) {
-      const uint32_t s = sym[i];
-      if (s < (uint32_t)dict)
-        atomicAdd(&sh[s], 1u);
-      else
-        atomicOr(status, 1u);  // symbol outside the dictionary
-      e += (s == 0);
+    for (uint64_t i = beg + 4 * (uint64_t)lane; i < end; i += 256) {
+      uint32_t s4[4];
+      load4_symbols(sym, i, end, s4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t v = s4[j];
+        if (v == 0xffffffffu) continue;
+        if (v < (uint32_t)dict)
+          atomicAdd(&sh[v], 1u);
+        else
+          bad = true;  // symbol outside the dictionary
+        e += v == 0;
+      }
     }
-    if (e) atomicAdd(&esc, e);
-    __syncthreads();
-    if (threadIdx.x == 0) chunk_esc[k] = esc;
+#pragma unroll
+    for (int d = 32; d; d >>= 1) e += __shfl_xor(e, d);
+    if (lane == 0) chunk_esc[k] = e;
   }
+  if (bad) atomicOr(status, 1u);
   __syncthreads();
-  for (int b = threadIdx.x; b < dict; b += TPB)
+  for (int b = threadIdx.x; b < dict; b += WAVE_T)
     if (sh[b]) atomicAdd(&hist[b], (unsigned long long)sh[b]);
 }
 
+// ------------------------------------------------------------------ wave helpers
+__device__ inline uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+
+// Mask of the lanes whose `v` (7 bits) equals this lane's.
+__device__ inline uint64_t match7(uint32_t v) {
+  uint64_t m = __ballot(1);
+#pragma unroll
+  for (int b = 0; b < 7; ++b) {
+    const bool bit = (v >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+// Canonical ranks, for a block of 1024 threads: for every symbol s with
+// lens[s] in 1..MAXLEN, rank[s] = the number of symbols t < s of the same
+// length; cnt[L] = the number of symbols of length L (cnt[0] counts the unused
+// ones).  Wave w owns a contiguous range of 64-symbol groups, so ranks are
+// per-wave counts plus the counts of the waves before it.
+__device__ void canonical_ranks(const uint8_t* lens, int dict, uint16_t* rank,
+                                uint32_t (*wcnt)[MAXLEN + 1], uint32_t* cnt) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int ngroups = (dict + 63) / 64;
+  const int gpw = (ngroups + 15) / 16;
+  const int g0 = min(w * gpw, ngroups), g1 = min(g0 + gpw, ngroups);
+  for (int i = t; i < 16 * (MAXLEN + 1); i += blockDim.x) wcnt[i / (MAXLEN + 1)][i % (MAXLEN + 1)] = 0;
+  __syncthreads();
+  for (int g = g0; g < g1; ++g) {
+    const int s = g * 64 + lane;
+    if (s < dict) atomicAdd(&wcnt[w][lens[s]], 1u);
+  }
+  __syncthreads();
+  if (t <= MAXLEN) {
+    uint32_t run = 0;
+    for (int v = 0; v < 16; ++v) {
+      const uint32_t x = wcnt[v][t];
+      wcnt[v][t] = run;
+      run += x;
+    }
+    cnt[t] = run;
+  }
+  __syncthreads();
+  volatile uint32_t* mine = wcnt[w];
+  const uint64_t below = lanes_below(lane);
+  for (int g = g0; g < g1; ++g) {
+    const int s = g * 64 + lane;
+    const uint32_t L = s < dict ? lens[s] : 0u;
+    const uint64_t m = match7(L);
+    const uint32_t r = (uint32_t)__popcll(m & below);
+    const uint32_t base = mine[L];
+    if (L) rank[s] = (uint16_t)(base + r);
+    __builtin_amdgcn_wave_barrier();
+    if (r == 0) mine[L] = base + (uint32_t)__popcll(m);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ codebook
-// One workgroup; everything stays in LDS.  keys: (count << 16 | symbol),
-// empty bins sort last.  The two-queue merge runs on one lane with the queue
-// heads held in registers; internal-node depths come from pointer jumping,
-// leaf lengths from the number of leaves per depth (deepest for the smallest
-// weights), canonical codes from a second sort by (length, symbol).
+constexpr int MERGE_SEQ_MIN = 8;    // smaller batches are built by one thread ...
+constexpr int MERGE_SEQ_RUN = 64;   // ... this many nodes at a time
+constexpr int MERGE_PER = MAXDICT / 1024;  // batch nodes per thread
+
+// Number of leaves among the first p items of the stable merge (ties to the
+// leaf) of leaves keys[K..n) (sorted) and internal nodes keys[0..K), p >= 2K:
+// every leaf below slot K is among them, and no internal node from K on is.
+__device__ inline int merge_split(const uint64_t* keys, int n, int K, int p) {
+  int lo = max(0, p - K), hi = min(p, n);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] <= keys[p - mid - 1])
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// One workgroup of 1024 threads; everything stays in LDS.  keys: (count << 16
+// | symbol), empty bins sort last.  The merge builds internal nodes in
+// batches (see below); internal-node depths come from pointer jumping, leaf
+// lengths from the number of leaves per depth (deepest for the smallest
+// weights), canonical codes from per-length ranks in symbol order.
 __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ hist, int dict,
                                                    uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
   __shared__ uint64_t keys[MAXDICT];
   __shared__ uint16_t syms[MAXDICT];
-  __shared__ uint16_t par[MAXDICT];
+  __shared__ uint16_t par[MAXDICT];  // parents, then canonical ranks
   __shared__ uint8_t dep[MAXDICT];
   __shared__ uint8_t lens[MAXDICT];
+  __shared__ uint32_t wcnt[16][MAXLEN + 1];
   __shared__ int nleaf;
+  __shared__ int merge_k, merge_b;
   __shared__ uint32_t icount[MAXLEN + 2];
   __shared__ uint32_t lstart[MAXLEN + 2];
   __shared__ uint64_t first[MAXLEN + 1];
-  __shared__ uint32_t lcount[MAXLEN + 1], loff[MAXLEN + 1];
+  __shared__ uint32_t lcount[MAXLEN + 1];
   const int t = threadIdx.x;
   const int nt = blockDim.x;
   if (t == 0) nleaf = 0;
   for (int i = t; i <= MAXLEN + 1; i += nt) icount[i] = 0;
   __syncthreads();
-  for (int s = t; s < dict; s += nt) {
-    const uint64_t c = hist[s];
-    keys[s] = c ? ((c << 16) | (uint64_t)s) : ~0ull;
-    lens[s] = 0;
-    if (c) atomicAdd(&nleaf, 1);
+  {
+    int mine = 0;
+    for (int s = t; s < dict; s += nt) {
+      const uint64_t c = hist[s];
+      keys[s] = c ? ((c << 16) | (uint64_t)s) : ~0ull;
+      lens[s] = 0;
+      mine += c ? 1 : 0;
+    }
+    if (mine) atomicAdd(&nleaf, mine);
   }
   __syncthreads();
-  auto bitonic = [&]() {
-    for (int k = 2; k <= dict; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = t; i < dict; i += nt) {
-          const int p = i ^ j;
-          if (p > i) {
-            const uint64_t a = keys[i], b = keys[p];
-            if ((a > b) == ((i & k) == 0)) {
-              keys[i] = b;
-              keys[p] = a;
-            }
+  for (int k = 2; k <= dict; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < dict; i += nt) {
+        const int p = i ^ j;
+        if (p > i) {
+          const uint64_t a = keys[i], b = keys[p];
+          if ((a > b) == ((i & k) == 0)) {
+            keys[i] = b;
+            keys[p] = a;
           }
         }
-        __syncthreads();
       }
+      __syncthreads();
     }
-  };
-  bitonic();
+  }
   const int n = nleaf;
   for (int i = t; i < n; i += nt) {
     syms[i] = (uint16_t)(keys[i] & 0xffff);
@@ -109,56 +220,105 @@ __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ 
   if (n == 1) {
     if (t == 0) lens[syms[0]] = 1;
   } else if (n > 1) {
-    // merge (in place: a consumed internal node's slot takes its parent's index)
-    if (t == 0) {
-      uint64_t* A = keys;
-      const uint64_t INF = ~0ull;
-      // register windows over both queues: lq[i] = weight of leaf (leaf + i),
-      // iq[i] = weight of internal node (root + i) (INF until it exists); the
-      // loads that refill a window are issued several picks before they are used
-      uint64_t lq0 = A[0], lq1 = n > 1 ? A[1] : INF, lq2 = n > 2 ? A[2] : INF, lq3 = n > 3 ? A[3] : INF;
-      uint64_t iq0 = INF, iq1 = INF, iq2 = INF, iq3 = INF;
-      int leaf = 0, root = 0;
-      for (int next = 0; next < n - 1; ++next) {
+    // The two-queue merge consumes the stable merge (ties to the leaf) of the
+    // sorted leaves and the internal nodes in creation order, and internal
+    // node k joins that merge's items 2k and 2k+1.  So, with K nodes built,
+    // nodes K .. K+B-1 follow from the merge of the leaves with nodes < K, as
+    // long as their items lie before the point where node K itself enters
+    // (after every leaf of weight <= its own): they are built in parallel.
+    // When B is small a single thread builds a sequential stretch instead.
+    // Node k is stored in slot k (its leaf is consumed by then); parents of
+    // internal nodes go to par[].
+    if (t == 0) merge_k = 0;
+    __syncthreads();
+    for (;;) {
+      const int K = merge_k;
+      if (K >= n - 1) break;
+      if (t == 0) {
+        int a = merge_split(keys, n, K, 2 * K), b = 2 * K - a;
         uint64_t w = 0;
-#pragma unroll
         for (int pick = 0; pick < 2; ++pick) {
-          // the internal queue holds the nodes [root, next); the leaf queue wins ties
-          if (leaf < n && (root >= next || lq0 <= iq0)) {
-            w += lq0;
-            ++leaf;
-            lq0 = lq1;
-            lq1 = lq2;
-            lq2 = lq3;
-            lq3 = leaf + 3 < n ? A[leaf + 3] : INF;
-          } else {
-            w += iq0;
-            A[root] = (uint64_t)next;
-            ++root;
-            iq0 = iq1;
-            iq1 = iq2;
-            iq2 = iq3;
-            iq3 = root + 3 < next ? A[root + 3] : INF;
+          if (a < n && (b >= K || keys[a] <= keys[b]))
+            w += keys[a++];
+          else
+            w += keys[b++];
+        }
+        // leaves of weight <= w: those below slot K all are (they come before node K)
+        int lo = K, hi = n;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (keys[mid] <= w)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        const int enter = K + lo;  // merge position of node K
+        const int B = min(max(1, (enter - 2 * K) / 2), n - 1 - K);
+        if (B >= MERGE_SEQ_MIN) {
+          merge_b = B;
+        } else {
+          a = merge_split(keys, n, K, 2 * K);
+          b = 2 * K - a;
+          const int end = min(K + MERGE_SEQ_RUN, n - 1);
+          for (int node = K; node < end; ++node) {
+            uint64_t v = 0;
+            for (int pick = 0; pick < 2; ++pick) {
+              if (a < n && (b >= node || keys[a] <= keys[b])) {
+                v += keys[a++];
+              } else {
+                par[b] = (uint16_t)node;
+                v += keys[b++];
+              }
+            }
+            keys[node] = v;
+          }
+          merge_b = -(end - K);
+        }
+      }
+      __syncthreads();
+      const int B = merge_b;
+      if (B > 0) {
+        uint64_t w[MERGE_PER];
+        int c0[MERGE_PER], c1[MERGE_PER];
+#pragma unroll
+        for (int q = 0; q < MERGE_PER; ++q) {
+          const int j = t + q * nt;
+          w[q] = 0;
+          c0[q] = c1[q] = -1;
+          if (j < B) {
+            const int p = 2 * (K + j);
+            int a = merge_split(keys, n, K, p), b = p - a;
+            for (int pick = 0; pick < 2; ++pick) {
+              if (a < n && (b >= K || keys[a] <= keys[b])) {
+                w[q] += keys[a++];
+              } else {
+                if (pick == 0)
+                  c0[q] = b;
+                else
+                  c1[q] = b;
+                w[q] += keys[b++];
+              }
+            }
           }
         }
-        A[next] = w;
-        // the new node enters the internal window if it is among its first four
-        const int pos = next - root;
-        if (pos == 0)
-          iq0 = w;
-        else if (pos == 1)
-          iq1 = w;
-        else if (pos == 2)
-          iq2 = w;
-        else if (pos == 3)
-          iq3 = w;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MERGE_PER; ++q) {
+          const int j = t + q * nt;
+          if (j < B) {
+            keys[K + j] = w[q];
+            if (c0[q] >= 0) par[c0[q]] = (uint16_t)(K + j);
+            if (c1[q] >= 0) par[c1[q]] = (uint16_t)(K + j);
+          }
+        }
       }
+      if (t == 0) merge_k = K + (B > 0 ? B : -B);
+      __syncthreads();
     }
-    __syncthreads();
-    // internal node k < n-1: parent index in keys[k] (the root n-2 holds its weight)
+    // internal node k < n-1: parent in par[k]; the root n-2 is its own parent
     const int ni = n - 1;
     for (int k = t; k < ni; k += nt) {
-      par[k] = (uint16_t)(k == ni - 1 ? k : (int)keys[k]);
+      if (k == ni - 1) par[k] = (uint16_t)k;
       dep[k] = k == ni - 1 ? 0 : 1;
     }
     __syncthreads();
@@ -193,92 +353,266 @@ __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ 
     }
     __syncthreads();
     for (int i = t; i < n; i += nt) {
-      int d = MAXLEN;
-      while (d > 1 && lstart[d - 1] <= (uint32_t)i) --d;
-      lens[syms[i]] = (uint8_t)d;
+      // leaf i has length d with lstart[d] <= i < lstart[d-1]; lstart does not
+      // rise with d, so d is the smallest depth with lstart[d] <= i
+      int lo = 1, hi = MAXLEN;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (lstart[mid] <= (uint32_t)i)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      lens[syms[i]] = (uint8_t)lo;
     }
   }
   __syncthreads();
-  // canonical codes: sort by (length, symbol), then consecutive codes per length
-  for (int i = t; i <= MAXLEN; i += nt) lcount[i] = 0;
-  __syncthreads();
-  for (int s = t; s < dict; s += nt) {
-    keys[s] = lens[s] ? (((uint64_t)lens[s] << 16) | (uint64_t)s) : ~0ull;
-    if (lens[s]) atomicAdd(&lcount[lens[s]], 1u);
-  }
-  __syncthreads();
-  bitonic();
+  // canonical codes: consecutive codes per length in symbol order
+  canonical_ranks(lens, dict, par, wcnt, lcount);
   if (t == 0) {
     uint64_t code = 0;
-    uint32_t off = 0;
     for (int b = 1; b <= MAXLEN; ++b) {
       code = (code + (b > 1 ? lcount[b - 1] : 0)) << 1;
       first[b] = code;
-      loff[b] = off;
-      off += lcount[b];
     }
   }
   __syncthreads();
-  for (int i = t; i < dict; i += nt) {
-    const uint64_t k = keys[i];
-    if (k == ~0ull) continue;
-    const int L = (int)(k >> 16), s = (int)(k & 0xffff);
-    codes[s] = first[L] + (uint64_t)(i - (int)loff[L]);
-  }
   for (int s = t; s < dict; s += nt) {
-    len_out[s] = lens[s];
-    if (!lens[s]) codes[s] = 0;
+    const int L = lens[s];
+    len_out[s] = (uint8_t)L;
+    codes[s] = L ? first[L] + (uint64_t)par[s] : 0ull;
   }
 }
 
 // ------------------------------------------------------------------ chunk sizes
-__global__ void __launch_bounds__(TPB) k_chunk_bits(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
-                                                    uint64_t nch, uint32_t mask, const uint8_t* __restrict__ len,
-                                                    uint32_t* __restrict__ chunk_bits) {
-  __shared__ uint32_t acc;
-  for (uint64_t k = blockIdx.x; k < nch; k += gridDim.x) {
-    if (threadIdx.x == 0) acc = 0;
-    __syncthreads();
+// Bits of each chunk: one wave per chunk, code lengths in LDS.
+__global__ void __launch_bounds__(WAVE_T) k_chunk_bits(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+                                                       uint64_t nch, uint32_t mask, const uint8_t* __restrict__ len,
+                                                       uint32_t* __restrict__ chunk_bits) {
+  __shared__ uint8_t lens[MAXDICT];
+  for (uint32_t s = threadIdx.x; s <= mask; s += WAVE_T) lens[s] = len[s];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+  for (uint64_t k = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); k < nch; k += stride) {
     const uint64_t beg = k * (uint64_t)chunk;
     const uint64_t end = min(beg + (uint64_t)chunk, n);
     uint32_t b = 0;
-    for (uint64_t i = beg + threadIdx.x; i < end; i += TPB) b += len[sym[i] & mask];
-    atomicAdd(&acc, b);
-    __syncthreads();
-    if (threadIdx.x == 0) chunk_bits[k] = acc;
-    __syncthreads();
+    for (uint64_t i = beg + 4 * (uint64_t)lane; i < end; i += 256) {
+      uint32_t s4[4];
+      load4_symbols(sym, i, end, s4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (s4[j] != 0xffffffffu) b += lens[s4[j] & mask];
+    }
+#pragma unroll
+    for (int d = 32; d; d >>= 1) b += __shfl_xor(b, d);
+    if (lane == 0) chunk_bits[k] = b;
   }
 }
 
 // ------------------------------------------------------------------ scans
-// Exclusive scan over n values (words of chunk bit counts when WORDS), one
-// workgroup; off has n+1 entries, off[n] the total.
+// Exclusive scan of n values (the words of chunk bit counts when WORDS) into
+// off[0..n], off[n] the total, in three launches: tile sums parked in the
+// first output slot of each tile, a one-block scan of those, and a per-tile
+// scan that adds its tile's base.
+constexpr int SCAN_T = 256, SCAN_PER = 16, SCAN_TILE = SCAN_T * SCAN_PER;
+
 template <bool WORDS>
-__global__ void __launch_bounds__(1024) k_scan(const uint32_t* __restrict__ v, uint64_t n,
-                                               uint64_t* __restrict__ off) {
-  __shared__ uint64_t part[1024];
+__device__ inline uint64_t scan_value(uint32_t x) {
+  return WORDS ? (((uint64_t)x + 31u) >> 5) : (uint64_t)x;
+}
+
+__device__ inline uint64_t block_exclusive_scan(uint64_t v, uint64_t* sh, uint64_t* total) {
   const int t = threadIdx.x;
-  const uint64_t per = (n + 1023) / 1024;
-  const uint64_t beg = min((uint64_t)t * per, n), end = min(beg + per, n);
-  uint64_t s = 0;
-  for (uint64_t i = beg; i < end; ++i) s += WORDS ? (uint64_t)((v[i] + 31u) >> 5) : (uint64_t)v[i];
-  part[t] = s;
+  sh[t] = v;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    uint64_t add = t >= d ? part[t - d] : 0;
+  for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+    const uint64_t a = t >= d ? sh[t - d] : 0;
     __syncthreads();
-    part[t] += add;
+    sh[t] += a;
     __syncthreads();
   }
-  uint64_t run = part[t] - s;
-  for (uint64_t i = beg; i < end; ++i) {
-    off[i] = run;
-    run += WORDS ? (uint64_t)((v[i] + 31u) >> 5) : (uint64_t)v[i];
+  const uint64_t incl = sh[t];
+  *total = sh[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+template <bool WORDS>
+__global__ void __launch_bounds__(SCAN_T) k_scan_tiles(const uint32_t* __restrict__ v, uint64_t n,
+                                                       uint64_t* __restrict__ off) {
+  __shared__ uint64_t sh[SCAN_T];
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+  uint64_t s = 0;
+  for (int j = 0; j < SCAN_PER; ++j) {
+    const uint64_t i = base + (uint64_t)j * SCAN_T + threadIdx.x;
+    if (i < n) s += scan_value<WORDS>(v[i]);
   }
-  if (t == 1023) off[n] = part[1023];
+  uint64_t total;
+  block_exclusive_scan(s, sh, &total);
+  if (threadIdx.x == 0) off[base] = total;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(uint64_t* __restrict__ off, uint64_t n) {
+  __shared__ uint64_t sh[1024];
+  const uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+  uint64_t carry = 0;
+  for (uint64_t g = 0; g < nt; g += blockDim.x) {
+    const uint64_t b = g + threadIdx.x;
+    const uint64_t x = b < nt ? off[b * SCAN_TILE] : 0;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan(x, sh, &total);
+    if (b < nt) off[b * SCAN_TILE] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) off[n] = carry;
+}
+
+template <bool WORDS>
+__global__ void __launch_bounds__(SCAN_T) k_scan_apply(const uint32_t* __restrict__ v, uint64_t n,
+                                                       uint64_t* __restrict__ off) {
+  __shared__ uint64_t sh[SCAN_T];
+  __shared__ uint64_t tbase_sh;
+  const uint64_t tile = (uint64_t)blockIdx.x * SCAN_TILE;
+  // only thread 0 reads the parked base: it is also the thread that overwrites it
+  if (threadIdx.x == 0) tbase_sh = off[tile];
+  const uint64_t mine = tile + (uint64_t)threadIdx.x * SCAN_PER;
+  uint64_t x[SCAN_PER];
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    x[j] = mine + j < n ? scan_value<WORDS>(v[mine + j]) : 0;
+    s += x[j];
+  }
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(s, sh, &total);  // its barriers publish tbase_sh
+  run += tbase_sh;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    if (mine + j < n) off[mine + j] = run;
+    run += x[j];
+  }
+}
+
+template <bool WORDS>
+void launch_scan(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st) {
+  const uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (nt) hipLaunchKernelGGL(k_scan_tiles<WORDS>, dim3((unsigned)nt), dim3(SCAN_T), 0, st, v, n, off);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, off, n);
+  if (nt) hipLaunchKernelGGL(k_scan_apply<WORDS>, dim3((unsigned)nt), dim3(SCAN_T), 0, st, v, n, off);
+  MG_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ encode
+// Codes of at most ENC_MAXLEN bits are packed with their length into one word
+// (code << 6 | length); k_pack_codes also records the longest length, which
+// decides on the device which encode kernel does the work.
+constexpr int ENC_MAXLEN = 26;
+constexpr int ENC_CHUNK = 1024;                          // largest chunk of the wave kernel
+constexpr int ENC_WORDS = ENC_CHUNK * ENC_MAXLEN / 32;   // its LDS words per wave
+constexpr int ENC_T = 512;
+
+__global__ void __launch_bounds__(1024) k_pack_codes(const uint8_t* __restrict__ len, const uint64_t* __restrict__ codes,
+                                                     int dict, uint32_t* __restrict__ enc,
+                                                     uint32_t* __restrict__ maxlen_out) {
+  __shared__ uint32_t mx;
+  if (threadIdx.x == 0) mx = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < dict; s += blockDim.x) {
+    const uint32_t L = len[s];
+    if (L) atomicMax(&mx, L);
+    enc[s] = (L && L <= ENC_MAXLEN) ? (uint32_t)((codes[s] << 6) | L) : 0u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *maxlen_out = mx;
+}
+
+// One wave per chunk (chunk <= ENC_CHUNK, codes <= ENC_MAXLEN bits): each lane
+// takes four consecutive symbols per step, a wave scan gives its bit offset,
+// and its codes pass through a 64-bit accumulator into the wave's LDS words
+// (word-granular atomics: only the first and last word of a lane are shared);
+// the finished chunk is copied out coalesced.
+__global__ void __launch_bounds__(ENC_T) k_encode_wave(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+                                                      uint64_t nch, uint32_t mask, const uint32_t* __restrict__ enc_g,
+                                                      const uint32_t* __restrict__ maxlen,
+                                                      const uint64_t* __restrict__ word_off,
+                                                      uint32_t* __restrict__ payload,
+                                                      const uint64_t* __restrict__ esc_off,
+                                                      const int64_t* __restrict__ qside, char* obase,
+                                                      const uint64_t* __restrict__ ooff) {
+  if (*maxlen > (uint32_t)ENC_MAXLEN) return;  // the generic kernel encodes instead
+  __shared__ uint32_t enc[MAXDICT];
+  __shared__ uint32_t words[ENC_T / 64][ENC_WORDS];
+  for (uint32_t s = threadIdx.x; s <= mask; s += ENC_T) enc[s] = enc_g[s];
+  __syncthreads();
+  int64_t* outliers = obase ? reinterpret_cast<int64_t*>(obase + *ooff) : nullptr;
+  const int lane = threadIdx.x & 63;
+  uint32_t* wb = words[threadIdx.x >> 6];
+  const uint64_t stride = (uint64_t)gridDim.x * (ENC_T / 64);
+  for (uint64_t k = (uint64_t)blockIdx.x * (ENC_T / 64) + (threadIdx.x >> 6); k < nch; k += stride) {
+    const uint64_t beg = k * (uint64_t)chunk;
+    const uint64_t end = min(beg + (uint64_t)chunk, n);
+    const uint64_t w0 = word_off[k];
+    const uint32_t nw = (uint32_t)min(word_off[k + 1] - w0, (uint64_t)ENC_WORDS);
+    for (uint32_t i = lane; i < nw; i += 64) wb[i] = 0;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t base = 0;  // chunk bit offset of this step's first symbol
+    uint64_t eo = outliers ? esc_off[k] : 0;
+    for (uint64_t i0 = beg; i0 < end; i0 += 256) {
+      const uint64_t i = i0 + 4 * (uint64_t)lane;
+      uint32_t s4[4], e4[4];
+      load4_symbols(sym, i, end, s4);
+      uint32_t bits = 0, esc = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        e4[j] = s4[j] != 0xffffffffu ? enc[s4[j] & mask] : 0u;
+        bits += e4[j] & 63u;
+        esc += s4[j] == 0;
+      }
+      uint32_t bi = bits, ei = esc;  // inclusive scans over the wave
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t yb = __shfl_up(bi, d), ye = __shfl_up(ei, d);
+        if (lane >= d) {
+          bi += yb;
+          ei += ye;
+        }
+      }
+      const uint32_t off = base + bi - bits;
+      uint32_t wi = off >> 5;
+      int fill = (int)(off & 31u);
+      uint64_t acc = 0;  // left-aligned at word wi
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int L = (int)(e4[j] & 63u);
+        if (L) {
+          acc |= (uint64_t)(e4[j] >> 6) << (64 - fill - L);
+          fill += L;
+          if (fill >= 32) {
+            if (wi < ENC_WORDS) atomicOr(&wb[wi], (uint32_t)(acc >> 32));
+            acc <<= 32;
+            fill -= 32;
+            ++wi;
+          }
+        }
+      }
+      if (fill > 0 && wi < ENC_WORDS) atomicOr(&wb[wi], (uint32_t)(acc >> 32));
+      if (outliers && esc) {
+        uint64_t o = eo + (ei - esc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (s4[j] == 0) outliers[o++] = qside[i + j];
+      }
+      eo += __shfl(ei, 63);
+      base += __shfl(bi, 63);
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i = lane; i < nw; i += 64) payload[w0 + i] = wb[i];
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 __device__ inline void put_code(uint32_t* words, uint64_t b, int L, uint64_t code) {
   // code occupies chunk bits [b, b+L), MSB-first
   const uint64_t e = b + (uint64_t)L;
@@ -294,15 +628,19 @@ __device__ inline void put_code(uint32_t* words, uint64_t b, int L, uint64_t cod
 }
 
 // MAXW: LDS words of one chunk, chunk * MAXLEN / 32 for the largest chunk of the instantiation.
+// Generic encoder (any chunk size and code length); it stands aside when the
+// wave kernel handles the call (chunk <= ENC_CHUNK and codes <= ENC_MAXLEN bits).
 template <int MAXW>
 __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
                                                 uint64_t nch, uint32_t mask, const uint8_t* __restrict__ len,
+                                                const uint32_t* __restrict__ maxlen,
                                                 const uint64_t* __restrict__ codes,
                                                 const uint64_t* __restrict__ word_off,
                                                 uint32_t* __restrict__ payload,
                                                 const uint64_t* __restrict__ esc_off,
                                                 const int64_t* __restrict__ qside, char* obase,
                                                 const uint64_t* __restrict__ ooff) {
+  if (chunk <= ENC_CHUNK && *maxlen <= (uint32_t)ENC_MAXLEN) return;
   __shared__ uint32_t words[MAXW];
   int64_t* outliers = obase ? reinterpret_cast<int64_t*>(obase + *ooff) : nullptr;  // chunk * MAXLEN / 32 words
   __shared__ uint64_t scan[TPB];
@@ -357,51 +695,63 @@ __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym
 // Canonical decoding tables: per length L, the first code, the count and the
 // offset into the symbols sorted by (length, symbol); lim1[L] is the
 // left-aligned (64-bit) end of the codes of length <= L, minus one, so the
-// length of the next code is the smallest L with window <= lim1[L].
+// length of the next code is the smallest L with window <= lim1[L].  The code
+// ranges of successive lengths are contiguous from 0, so only windows above
+// lim1[maxlen] are invalid.
+//
+// Fast path (every length <= 32 and at most FASTN - 1 distinct lengths): for
+// the j-th distinct length flen[j], flim[j] = the top 32 bits of its lim1
+// (whose low 32 bits are all ones, so comparing the top 32 bits of the window
+// decides) and fdelta[j] = offset - first (mod 2^32); entry nfast has length 0
+// (an invalid code) and entries after it never match.
+constexpr int FASTN = 16;
 struct DecTables {
   uint64_t first[MAXLEN + 1];
   uint64_t lim1[MAXLEN + 1];
   uint32_t count[MAXLEN + 1];
   uint32_t offset[MAXLEN + 1];
-  uint32_t minlen, maxlen, bad, pad;
+  uint32_t minlen, maxlen, bad, used;
+  uint32_t nfast, pad;
+  uint32_t flen[FASTN], flim[FASTN], fdelta[FASTN];
 };
 
 __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restrict__ len, int dict, DecTables* tab,
                                                         uint16_t* __restrict__ sorted) {
   __shared__ uint8_t lens[MAXDICT];
+  __shared__ uint16_t rank[MAXDICT];
+  __shared__ uint32_t wcnt[16][MAXLEN + 1];
   __shared__ uint32_t cnt[MAXLEN + 1];
-  __shared__ uint32_t fill[MAXLEN + 1];
+  __shared__ uint32_t offs[MAXLEN + 1];
   __shared__ uint32_t bad;
   const int t = threadIdx.x, nt = blockDim.x;
   if (t == 0) bad = 0;
-  for (int b = t; b <= MAXLEN; b += nt) cnt[b] = 0;
   __syncthreads();
   for (int s = t; s < dict; s += nt) {
     const uint8_t L = len[s];
-    lens[s] = L;
-    if (L > MAXLEN)
-      atomicOr(&bad, 1u);
-    else if (L)
-      atomicAdd(&cnt[L], 1u);
+    if (L > MAXLEN) atomicOr(&bad, 1u);
+    lens[s] = L > MAXLEN ? 0 : L;
   }
   __syncthreads();
+  canonical_ranks(lens, dict, rank, wcnt, cnt);
   if (t == 0) {
     uint64_t code = 0;
-    uint32_t off = 0, minlen = 0, maxlen = 0;
+    uint32_t off = 0, minlen = 0, maxlen = 0, nd = 0;
     for (int b = 1; b <= MAXLEN; ++b) {
       code = (code + (b > 1 ? cnt[b - 1] : 0)) << 1;
       tab->first[b] = code;
       tab->count[b] = cnt[b];
       tab->offset[b] = off;
-      fill[b] = off;
+      offs[b] = off;
       off += cnt[b];
       if (cnt[b]) {
         if (!minlen) minlen = b;
         maxlen = b;
+        ++nd;
       }
     }
+    uint32_t flag = bad;
     // Kraft: the codes of the longest length must fit in that length
-    if (maxlen && maxlen < 64 && tab->first[maxlen] + cnt[maxlen] > (1ull << maxlen)) bad = 1;
+    if (maxlen && maxlen < 64 && tab->first[maxlen] + cnt[maxlen] > (1ull << maxlen)) flag = 1;
     // left-aligned limits, saturating at 2^64 - 1
     for (int b = 1; b <= MAXLEN; ++b) {
       const uint64_t e = tab->first[b] + tab->count[b];
@@ -420,35 +770,80 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
     tab->lim1[0] = 0;
     tab->minlen = minlen;
     tab->maxlen = maxlen;
-    tab->bad = bad;
-    for (int s = 0; s < dict; ++s) {
-      const int L = lens[s];
-      if (L && L <= MAXLEN) sorted[fill[L]++] = (uint16_t)s;
+    tab->bad = flag;
+    tab->used = off;
+    const bool fast = maxlen && maxlen <= 32 && nd <= FASTN - 1;
+    int j = 0;
+    if (fast)
+      for (int b = minlen; b <= (int)maxlen; ++b) {
+        if (!cnt[b]) continue;
+        tab->flen[j] = b;
+        tab->flim[j] = (uint32_t)(tab->lim1[b] >> 32);
+        tab->fdelta[j] = offs[b] - (uint32_t)tab->first[b];
+        ++j;
+      }
+    for (; j < FASTN; ++j) {
+      tab->flen[j] = 0;
+      tab->flim[j] = 0xffffffffu;
+      tab->fdelta[j] = 0;
     }
+    tab->nfast = fast ? nd : 0;
+  }
+  __syncthreads();
+  for (int s = t; s < dict; s += nt) {
+    const int L = lens[s];
+    if (L) sorted[offs[L] + rank[s]] = (uint16_t)s;
   }
 }
 
-// One thread per chunk.  status[0] is set to 1 on malformed input.
+constexpr uint32_t RING = 32;         // words per lane (a power of two)
+constexpr uint32_t RING_STRIDE = 33;  // odd stride: lanes reading the same slot hit different banks
+
+// Four payload words from min(at, words - 4) on (words >= 4): the load is
+// unconditional so it can land in its destination registers while earlier
+// words are decoded; the shift that puts word `at` first is applied when the
+// group is used.
+__device__ inline uint4 load_group(const uint32_t* __restrict__ payload, uint64_t at, uint64_t words,
+                                   uint32_t* shift) {
+  const uint64_t a = min(at, words - 4);
+  *shift = (uint32_t)min(at - a, (uint64_t)4);
+  uint4 v;
+  __builtin_memcpy(&v, payload + a, 16);
+  return v;
+}
+
+// Word i of the result is word i + sh of v; zeros past the payload's end.
+__device__ inline uint4 shift_group(uint4 v, uint32_t sh) {
+  uint4 r;
+  r.x = sh == 0 ? v.x : sh == 1 ? v.y : sh == 2 ? v.z : sh == 3 ? v.w : 0u;
+  r.y = sh == 0 ? v.y : sh == 1 ? v.z : sh == 2 ? v.w : 0u;
+  r.z = sh == 0 ? v.z : sh == 1 ? v.w : 0u;
+  r.w = sh == 0 ? v.w : 0u;
+  return r;
+}
+
+// One thread per chunk.  status[0] is set to 1 on malformed input.  When
+// esc_off is given, the stream position of the j-th escape symbol is written
+// to epos[j] (chunk k owns entries [esc_off[k], esc_off[k+1])); the loop
+// itself issues no loads besides the payload, so it never waits on them early.
 __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
                                                const uint64_t* __restrict__ word_off,
                                                const uint32_t* __restrict__ chunk_bits, uint64_t n, int chunk,
                                                uint64_t nch, const DecTables* __restrict__ tab,
                                                const uint16_t* __restrict__ sorted_g, int dict,
                                                uint16_t* __restrict__ sym, const uint64_t* __restrict__ esc_off,
-                                               uint64_t n_out, const int64_t* __restrict__ outliers,
-                                               int64_t* __restrict__ qside, uint32_t* __restrict__ status) {
+                                               uint64_t* __restrict__ epos, uint32_t* __restrict__ status) {
   __shared__ uint64_t first[MAXLEN + 1], lim1[MAXLEN + 1];
   __shared__ uint32_t offs[MAXLEN + 1];
   __shared__ uint16_t sorted[MAXDICT];
+  __shared__ uint32_t ring[256 * RING_STRIDE];
+  const uint32_t used = min(tab->used, (uint32_t)dict);
   for (int b = threadIdx.x; b <= MAXLEN; b += blockDim.x) {
     first[b] = tab->first[b];
     lim1[b] = tab->lim1[b];
     offs[b] = tab->offset[b];
   }
-  {
-    const int used = tab->maxlen ? (int)(tab->offset[tab->maxlen] + tab->count[tab->maxlen]) : 0;
-    for (int s = threadIdx.x; s < used && s < dict; s += blockDim.x) sorted[s] = sorted_g[s];
-  }
+  for (uint32_t s = threadIdx.x; s < used; s += blockDim.x) sorted[s] = sorted_g[s];
   __syncthreads();
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nch) return;
@@ -464,87 +859,201 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
   }
   const uint64_t beg = k * (uint64_t)chunk;
   const uint64_t cntk = min((uint64_t)chunk, n - beg);
-  const int minlen = (int)tab->minlen, maxlen = (int)tab->maxlen;
-  const uint32_t* src = payload + w0;
-  const uint64_t nw = w1 - w0;
-  uint64_t buf = 0;  // left-aligned bits
-  int have = 0;
-  uint64_t next_word = 0, consumed = 0;
-  uint64_t eo = esc_off ? esc_off[k] : 0;  // escapes are resolved only when outliers are given
-  uint64_t pack = 0;
-  const bool fast = maxlen <= 32;
-  for (uint64_t i = 0; i < cntk; ++i) {
-    // keep at least 33 valid bits at the top of the buffer
-    while (have <= 32) {
-      const uint64_t w = next_word < nw ? (uint64_t)src[next_word] : 0ull;
-      ++next_word;
-      buf |= w << (32 - have);
-      have += 32;
+  const bool escapes = esc_off != nullptr;
+  uint64_t eo = escapes ? esc_off[k] : 0;
+  const uint64_t eo_end = escapes ? esc_off[k + 1] : 0;
+  uint64_t consumed = 0;
+  if (tab->nfast && payload_words >= 4) {
+    // Branch-free length search over the distinct lengths.  The chunk's words
+    // pass through a per-lane ring in LDS: every 8 symbols (wave-uniform) the
+    // 8 words fetched 8 symbols earlier are written to the ring and the next 8
+    // are fetched if the ring has room, so no load is waited for soon after it
+    // is issued.  The ring never holds fewer than 8 unread words at a refill
+    // point, and at most 8 words are read between two refill points.
+    uint32_t flen[FASTN], flim[FASTN], fdelta[FASTN];
+#pragma unroll
+    for (int j = 0; j < FASTN; ++j) {
+      flen[j] = tab->flen[j];
+      flim[j] = tab->flim[j];
+      fdelta[j] = tab->fdelta[j];
     }
-    int s;
-    if (fast) {
-      // code length: the smallest L in [minlen, maxlen] with buf <= lim1[L]
-      int lo = minlen, hi = maxlen;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (buf <= lim1[mid])
-          hi = mid;
-        else
-          lo = mid + 1;
+    uint32_t* myring = ring + threadIdx.x * RING_STRIDE;
+    uint64_t fetch_at = w0;
+    uint32_t wr = 0, rd = 0;
+    for (int g = 0; g < 4; ++g) {
+      uint32_t sh;
+      const uint4 v = shift_group(load_group(payload, fetch_at, payload_words, &sh), sh);
+      myring[wr] = v.x;
+      myring[wr + 1] = v.y;
+      myring[wr + 2] = v.z;
+      myring[wr + 3] = v.w;
+      wr += 4;
+      fetch_at += 4;
+    }
+    uint32_t sha, shb;
+    uint4 pa = load_group(payload, fetch_at, payload_words, &sha);
+    uint4 pb = load_group(payload, fetch_at + 4, payload_words, &shb);
+    fetch_at += 8;
+    bool pend = true;
+    uint32_t nextw = myring[0];
+    uint64_t buf = 0;  // left-aligned bits
+    int have = 0;
+    uint64_t pack = 0, prev = 0;
+    for (uint64_t i = 0; i < cntk; ++i) {
+      if ((i & 7) == 4) {
+        if (pend) {
+          const uint4 va = shift_group(pa, sha), vb = shift_group(pb, shb);
+          myring[wr & (RING - 1)] = va.x;
+          myring[(wr + 1) & (RING - 1)] = va.y;
+          myring[(wr + 2) & (RING - 1)] = va.z;
+          myring[(wr + 3) & (RING - 1)] = va.w;
+          myring[(wr + 4) & (RING - 1)] = vb.x;
+          myring[(wr + 5) & (RING - 1)] = vb.y;
+          myring[(wr + 6) & (RING - 1)] = vb.z;
+          myring[(wr + 7) & (RING - 1)] = vb.w;
+          wr += 8;
+          pend = false;
+        }
+        if (wr - rd <= RING - 8) {
+          pa = load_group(payload, fetch_at, payload_words, &sha);
+          pb = load_group(payload, fetch_at + 4, payload_words, &shb);
+          fetch_at += 8;
+          pend = true;
+        }
       }
-      const int L = lo;
-      const uint64_t v = buf >> (64 - L);
-      if (buf > lim1[L] || v < first[L]) {
-        atomicOr(status, 1u);
-        return;
+      if (have < 32) {
+        buf |= (uint64_t)nextw << (32 - have);
+        have += 32;
+        ++rd;
+        nextw = myring[rd & (RING - 1)];
       }
-      s = sorted[offs[L] + (uint32_t)(v - first[L])];
-      buf <<= L;
-      have -= L;
+      const uint32_t top = (uint32_t)(buf >> 32);
+      uint32_t L = flen[0], d = fdelta[0];
+#pragma unroll
+      for (int j = 0; j + 1 < FASTN; ++j) {
+        const bool past = top > flim[j];
+        L = past ? flen[j + 1] : L;
+        d = past ? fdelta[j + 1] : d;
+      }
+      const uint32_t idx = d + (top >> (32 - L));
       consumed += L;
-    } else {
-      // codes longer than 32 bits exist: decode one bit at a time
-      uint64_t code = 0;
-      s = -1;
-      for (int L = 1; L <= maxlen; ++L) {
-        if (have == 0) {
-          buf = (next_word < nw ? (uint64_t)src[next_word] : 0ull) << 32;
+      if (L == 0 || idx >= used || consumed > nbits) {
+        atomicOr(status, 1u);
+        return;
+      }
+      const uint32_t s = sorted[idx];
+      buf <<= L;
+      have -= (int)L;
+      pack = (pack >> 16) | ((uint64_t)s << 48);
+      if ((i & 7) == 3) prev = pack;
+      if ((i & 7) == 7) {
+        const uint4 v = make_uint4((uint32_t)prev, (uint32_t)(prev >> 32), (uint32_t)pack, (uint32_t)(pack >> 32));
+        *reinterpret_cast<uint4*>(sym + beg + i - 7) = v;
+      }
+      if (s == 0 && escapes) {
+        if (eo >= eo_end) {
+          atomicOr(status, 1u);
+          return;
+        }
+        epos[eo++] = beg + i;
+      }
+    }
+    // the last cntk % 8 symbols: pack holds the newest four (newest in the top
+    // 16 bits), prev the group's first four (first in the low 16 bits)
+    const int tail = (int)(cntk & 7);
+    for (int j = 0; j < tail; ++j) {
+      const int age = tail - 1 - j;  // symbols decoded after this one
+      const uint16_t v = age < 4 ? (uint16_t)(pack >> (48 - 16 * age)) : (uint16_t)(prev >> (16 * j));
+      sym[beg + (cntk & ~7ull) + j] = v;
+    }
+  } else {
+    const int minlen = (int)tab->minlen, maxlen = (int)tab->maxlen;
+    const uint32_t* src = payload + w0;
+    const uint64_t nw = w1 - w0;
+    uint64_t buf = 0;  // left-aligned bits
+    int have = 0;
+    uint64_t next_word = 0;
+    for (uint64_t i = 0; i < cntk; ++i) {
+      int s;
+      if (maxlen <= 32) {
+        while (have <= 32) {
+          const uint64_t w = next_word < nw ? (uint64_t)src[next_word] : 0ull;
           ++next_word;
-          have = 32;
+          buf |= w << (32 - have);
+          have += 32;
         }
-        code = (code << 1) | (buf >> 63);
-        buf <<= 1;
-        --have;
-        ++consumed;
-        if (L >= minlen && code >= first[L] && code - first[L] < tab->count[L]) {
-          s = sorted[offs[L] + (uint32_t)(code - first[L])];
-          break;
+        // code length: the smallest L in [minlen, maxlen] with buf <= lim1[L]
+        int lo = minlen, hi = maxlen;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (buf <= lim1[mid])
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        const int L = lo;
+        const uint64_t v = buf >> (64 - L);
+        if (buf > lim1[L] || v < first[L] || offs[L] + (v - first[L]) >= used) {
+          atomicOr(status, 1u);
+          return;
+        }
+        s = sorted[offs[L] + (uint32_t)(v - first[L])];
+        buf <<= L;
+        have -= L;
+        consumed += L;
+      } else {
+        // codes longer than 32 bits exist: decode one bit at a time
+        uint64_t code = 0;
+        s = -1;
+        for (int L = 1; L <= maxlen; ++L) {
+          if (have == 0) {
+            buf = (next_word < nw ? (uint64_t)src[next_word] : 0ull) << 32;
+            ++next_word;
+            have = 32;
+          }
+          code = (code << 1) | (buf >> 63);
+          buf <<= 1;
+          --have;
+          ++consumed;
+          if (L >= minlen && code >= first[L] && code - first[L] < tab->count[L] &&
+              offs[L] + (code - first[L]) < used) {
+            s = sorted[offs[L] + (uint32_t)(code - first[L])];
+            break;
+          }
+        }
+        if (s < 0) {
+          atomicOr(status, 1u);
+          return;
         }
       }
-      if (s < 0) {
+      if (consumed > nbits) {
         atomicOr(status, 1u);
         return;
       }
-    }
-    if (consumed > nbits) {
-      atomicOr(status, 1u);
-      return;
-    }
-    pack |= (uint64_t)(uint16_t)s << (16 * (i & 3));
-    if ((i & 3) == 3) {
-      *reinterpret_cast<uint64_t*>(sym + beg + i - 3) = pack;
-      pack = 0;
-    }
-    if (s == 0 && qside) {
-      if (eo >= n_out) {
-        atomicOr(status, 1u);
-        return;
+      sym[beg + i] = (uint16_t)s;
+      if (s == 0 && escapes) {
+        if (eo >= eo_end) {
+          atomicOr(status, 1u);
+          return;
+        }
+        epos[eo++] = beg + i;
       }
-      qside[beg + i] = outliers[eo++];
     }
   }
-  for (uint64_t i = cntk & ~3ull; i < cntk; ++i) sym[beg + i] = (uint16_t)(pack >> (16 * (i & 3)));
-  if (consumed != nbits) atomicOr(status, 1u);
+  if (consumed != nbits || eo != eo_end) atomicOr(status, 1u);
+}
+
+// qside[epos[j]] = outliers[j], once every chunk has decoded cleanly (then
+// every epos entry is written and lies below n).
+__global__ void __launch_bounds__(TPB) k_scatter_outliers(const uint64_t* __restrict__ epos,
+                                                         const int64_t* __restrict__ outliers, uint64_t n_out,
+                                                         uint64_t n, int64_t* __restrict__ qside,
+                                                         const uint32_t* __restrict__ status) {
+  if (*status) return;
+  for (uint64_t j = (uint64_t)blockIdx.x * TPB + threadIdx.x; j < n_out; j += (uint64_t)gridDim.x * TPB) {
+    const uint64_t p = epos[j];
+    if (p < n) qside[p] = outliers[j];
+  }
 }
 
 inline unsigned blocks_for(uint64_t nch, unsigned cap) {
@@ -556,10 +1065,10 @@ inline unsigned blocks_for(uint64_t nch, unsigned cap) {
 void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
                       uint32_t* chunk_esc, uint32_t* status, hipStream_t st) {
   const uint64_t nch = (n + chunk - 1) / chunk;
-  MG_HIP(hipMemsetAsync(hist, 0, sizeof(uint64_t) * dict, st));
+  launch_fill_u64(hist, (uint64_t)dict, 0, st);
   if (nch == 0) return;
   KernelTimer kt("histogram", st);
-  hipLaunchKernelGGL(k_histogram, dim3(blocks_for(nch, 2048)), dim3(TPB), 0, st, sym, n,
+  hipLaunchKernelGGL(k_histogram, dim3(blocks_for((nch + WAVES - 1) / WAVES, 256)), dim3(WAVE_T), 0, st, sym, n,
                      dict, chunk, nch, (unsigned long long*)hist, chunk_esc, status);
   MG_HIP(hipGetLastError());
 }
@@ -575,34 +1084,44 @@ void launch_chunk_bits(const uint16_t* sym, uint64_t n, int dict, int chunk, con
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return;
   KernelTimer kt("chunk_bits", st);
-  hipLaunchKernelGGL(k_chunk_bits, dim3(blocks_for(nch, 8192)), dim3(TPB), 0, st, sym, n, chunk, nch,
-                     (uint32_t)(dict - 1), len, chunk_bits);
+  hipLaunchKernelGGL(k_chunk_bits, dim3(blocks_for((nch + WAVES - 1) / WAVES, 256)), dim3(WAVE_T), 0, st, sym, n,
+                     chunk, nch, (uint32_t)(dict - 1), len, chunk_bits);
   MG_HIP(hipGetLastError());
 }
 
 void launch_scan_words(const uint32_t* chunk_bits, uint64_t nch, uint64_t* word_off, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan<true>, dim3(1), dim3(1024), 0, st, chunk_bits, nch, word_off);
-  MG_HIP(hipGetLastError());
+  KernelTimer kt("scan", st);
+  launch_scan<true>(chunk_bits, nch, word_off, st);
 }
 
 void launch_scan_u32(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan<false>, dim3(1), dim3(1024), 0, st, v, n, off);
-  MG_HIP(hipGetLastError());
+  KernelTimer kt("scan", st);
+  launch_scan<false>(v, n, off, st);
 }
+
+uint64_t encode_scratch_bytes(int dict) { return carve_size<uint32_t>((uint64_t)dict) + carve_size<uint32_t>(4); }
 
 void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                    const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
                    const uint64_t* esc_off, const int64_t* qside, char* obase,
-                   const uint64_t* ooff, hipStream_t st) {
+                   const uint64_t* ooff, void* scratch, hipStream_t st) {
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return;
+  Carver cv(scratch);
+  uint32_t* enc = cv.take<uint32_t>((uint64_t)dict);
+  uint32_t* maxlen = cv.take<uint32_t>(4);
   KernelTimer kt("encode", st);
+  hipLaunchKernelGGL(k_pack_codes, dim3(1), dim3(1024), 0, st, len, codes, dict, enc, maxlen);
+  const uint32_t mask = (uint32_t)(dict - 1);
+  if (chunk <= ENC_CHUNK)
+    hipLaunchKernelGGL(k_encode_wave, dim3(blocks_for((nch + ENC_T / 64 - 1) / (ENC_T / 64), 512)), dim3(ENC_T), 0,
+                       st, sym, n, chunk, nch, mask, enc, maxlen, word_off, payload, esc_off, qside, obase, ooff);
   if (chunk <= 4096)
     hipLaunchKernelGGL(k_encode<4096 * MAXLEN / 32>, dim3(blocks_for(nch, 4096)), dim3(TPB), 0, st, sym, n, chunk,
-                       nch, (uint32_t)(dict - 1), len, codes, word_off, payload, esc_off, qside, obase, ooff);
+                       nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, obase, ooff);
   else
     hipLaunchKernelGGL(k_encode<8192 * MAXLEN / 32>, dim3(blocks_for(nch, 4096)), dim3(TPB), 0, st, sym, n, chunk,
-                       nch, (uint32_t)(dict - 1), len, codes, word_off, payload, esc_off, qside, obase, ooff);
+                       nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, obase, ooff);
   MG_HIP(hipGetLastError());
 }
 
@@ -610,22 +1129,29 @@ uint64_t decode_table_bytes(int dict) {
   return carve_size<DecTables>(1) + carve_size<uint16_t>((uint64_t)dict) + carve_size<uint32_t>(4);
 }
 
-// Full decode entry used by the API: builds the tables, then decodes.
+// Full decode entry used by the API: builds the tables, decodes, then places
+// the outliers (when given; epos has room for n_out positions).
 void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const uint64_t* word_off,
                         const uint32_t* chunk_bits, uint64_t n, int dict, int chunk,
                         const uint8_t* len, uint16_t* sym, const uint64_t* esc_off, uint64_t n_out,
-                        const int64_t* outliers, int64_t* qside, void* table_scratch,
+                        const int64_t* outliers, int64_t* qside, uint64_t* epos, void* table_scratch,
                         uint32_t* d_status, hipStream_t st) {
   Carver cv(table_scratch);
   DecTables* tab = cv.take<DecTables>(1);
   uint16_t* sorted = cv.take<uint16_t>((uint64_t)dict);
   hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(1024), 0, st, len, dict, tab, sorted);
   const uint64_t nch = (n + chunk - 1) / chunk;
+  const bool escapes = esc_off && outliers && qside && epos;
   if (nch) {
     const unsigned blocks = (unsigned)((nch + 255) / 256);
     KernelTimer kt("decode", st);
     hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits, n,
-                       chunk, nch, tab, sorted, dict, sym, esc_off, n_out, outliers, qside, d_status);
+                       chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, escapes ? epos : nullptr,
+                       d_status);
+  }
+  if (escapes && n_out) {
+    hipLaunchKernelGGL(k_scatter_outliers, dim3(blocks_for((n_out + TPB - 1) / TPB, 4096)), dim3(TPB), 0, st, epos,
+                       outliers, n_out, n, qside, d_status);
   }
   MG_HIP(hipGetLastError());
 }

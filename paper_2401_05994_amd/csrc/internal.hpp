@@ -44,6 +44,7 @@ class KernelTimer {
 };
 bool timing_enabled();
 void timing_set(int on);
+void timing_pause(bool paused);  // this thread only: no records while set (graph capture)
 std::string timing_report();
 
 // ----------------------------------------------------------------- hierarchy
@@ -181,7 +182,24 @@ template <typename T>
 void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* g1, T* z,
                              const QuantOut* q, const T* cstream, hipStream_t st);
 
+// Autotuned launch shapes (tune.hip): per knob, dtype and fine level shape.
+constexpr int TUNE_COEFF_SEG = 0;       // coarse intervals of dim 0 per block, plane-marching decomposition
+constexpr int TUNE_SCATTER_PLANES = 1;  // fine planes per block, recomposition scatter
+constexpr int TUNE_KNOBS = 2;
+int tune_get(int knob, bool f64, int n0, int n1, int n2, int fallback);
+bool tune_known(int knob, bool f64, int n0, int n1, int n2);
+void tune_set(int knob, bool f64, int n0, int n1, int n2, int value);
+void tune_force(int knob, int value);  // this thread only; 0 clears
+void tune_save();
+// Times the candidates of every level of the fused 3D path on d_in (which
+// also serves as each coarser level's input) and records the fastest; q
+// holds the quantization buffers and bins (transform.hip).
+template <typename T>
+void fused3d_tune(const Hierarchy& h, const T* table, const T* d_in, const QuantOut* q, void* scratch,
+                  hipStream_t st);
+
 // Quantization helpers (quant.hip).
+void launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
 template <typename T>
 void launch_maxabs(const T* d, uint64_t n, uint64_t* d_bits, hipStream_t st);
 struct BinArgs {
@@ -209,15 +227,16 @@ void launch_chunk_bits(const uint16_t* sym, uint64_t n, int dict, int chunk, con
 void launch_scan_words(const uint32_t* chunk_bits, uint64_t nch, uint64_t* word_off,
                        hipStream_t st);
 void launch_scan_u32(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st);
+uint64_t encode_scratch_bytes(int dict);
 void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                    const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
                    const uint64_t* esc_off, const int64_t* qside, char* obase,
-                   const uint64_t* ooff, hipStream_t st);
+                   const uint64_t* ooff, void* scratch, hipStream_t st);
 uint64_t decode_table_bytes(int dict);
 void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const uint64_t* word_off,
                         const uint32_t* chunk_bits, uint64_t n, int dict, int chunk,
                         const uint8_t* len, uint16_t* sym, const uint64_t* esc_off, uint64_t n_out,
-                        const int64_t* outliers, int64_t* qside, void* table_scratch,
+                        const int64_t* outliers, int64_t* qside, uint64_t* epos, void* table_scratch,
                         uint32_t* d_status, hipStream_t st);
 
 // Learned allocation (mlp.hip).  Parameter layout (float32): mean[4], std[4],

@@ -245,7 +245,7 @@ void launch_apply_theta(const double* d_bins, const float* d_theta, int nlev, do
 
 template <typename T>
 void launch_linf(const T* a, const T* b, uint64_t n, unsigned long long* d_err, hipStream_t st) {
-  MG_HIP(hipMemsetAsync(d_err, 0, 8, st));
+  launch_fill_u64(reinterpret_cast<uint64_t*>(d_err), 1, 0, st);
   KernelTimer kt("linf", st);
   hipLaunchKernelGGL(k_linf<T>, dim3(grid_for(n, 8192)), dim3(TPB), 0, st, a, b, n, d_err);
   MG_HIP(hipGetLastError());

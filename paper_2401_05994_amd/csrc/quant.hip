@@ -132,9 +132,22 @@ __global__ void __launch_bounds__(TPB) k_dequantize(const uint16_t* __restrict__
 
 }  // namespace
 
+namespace {
+__global__ void __launch_bounds__(TPB) k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
+  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < n; t += (uint64_t)gridDim.x * TPB) p[t] = v;
+}
+}  // namespace
+
+// A kernel rather than hipMemsetAsync, so that captured graphs hold no memset node.
+void launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024)), dim3(TPB), 0, st, p, n, v);
+  MG_HIP(hipGetLastError());
+}
+
 template <typename T>
 void launch_maxabs(const T* d, uint64_t n, uint64_t* d_bits, hipStream_t st) {
-  MG_HIP(hipMemsetAsync(d_bits, 0, sizeof(uint64_t), st));
+  launch_fill_u64(d_bits, 1, 0, st);
   KernelTimer kt("maxabs", st);
   hipLaunchKernelGGL(k_maxabs<T>, dim3(grid_for(n, 4096)), dim3(TPB), 0, st, d, n, d_bits);
   MG_HIP(hipGetLastError());

@@ -22,12 +22,15 @@ struct Rec {
 std::mutex g_mu;
 bool g_on = false;
 std::vector<Rec> g_recs;
+thread_local bool g_paused = false;  // set while a graph is being captured on this thread
 }  // namespace
 
 bool timing_enabled() { return g_on; }
 
+void timing_pause(bool paused) { g_paused = paused; }
+
 KernelTimer::KernelTimer(const char* name, hipStream_t st) : st_(st), idx_(-1) {
-  if (!g_on) return;
+  if (!g_on || g_paused) return;
   Rec r;
   r.name = name;
   MG_HIP(hipEventCreate(&r.a));

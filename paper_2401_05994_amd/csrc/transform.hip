@@ -227,24 +227,47 @@ __global__ void __launch_bounds__(TPB) k_mass_restrict(const T* __restrict__ in,
 
 // Step 3 along one dimension, in place, one thread per line.
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t outer, int n,
-                                                uint64_t inner, DimConsts<T> w) {
+__global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t outer, int n, uint64_t inner,
+                                                const T* __restrict__ ta, const T* __restrict__ tr,
+                                                const T* __restrict__ tcp) {
+  // Both sweeps load G values of the line before the group's
+  // recurrence; the weights are restrict (scalar loads).  Same arithmetic and
+  // order as the plain loops.
+  constexpr int G = 16;
   const uint64_t lines = outer * inner;
   for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < lines;
        t += (uint64_t)gridDim.x * TPB) {
     const uint64_t k = t % inner;
     const uint64_t o = t / inner;
     T* line = data + o * (uint64_t)n * inner + k;
-    T prev = line[0] * w.tr[0];
+    T prev = line[0] * tr[0];
     line[0] = prev;
-    for (int i = 1; i < n; ++i) {
-      prev = (line[(uint64_t)i * inner] - w.ta[i] * prev) * w.tr[i];
-      line[(uint64_t)i * inner] = prev;
+    for (int i0 = 1; i0 < n; i0 += G) {
+      T v[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) v[q] = i0 + q < n ? line[(uint64_t)(i0 + q) * inner] : T(0);
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int i = i0 + q;
+        if (i < n) {
+          prev = (v[q] - ta[i] * prev) * tr[i];
+          line[(uint64_t)i * inner] = prev;
+        }
+      }
     }
     T x = prev;
-    for (int i = n - 2; i >= 0; --i) {
-      x = line[(uint64_t)i * inner] - w.tcp[i] * x;
-      line[(uint64_t)i * inner] = x;
+    for (int i0 = n - 2; i0 >= 0; i0 -= G) {
+      T v[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) v[q] = i0 - q >= 0 ? line[(uint64_t)(i0 - q) * inner] : T(0);
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int i = i0 - q;
+        if (i >= 0) {
+          x = v[q] - tcp[i] * x;
+          line[(uint64_t)i * inner] = x;
+        }
+      }
     }
   }
 }
@@ -351,8 +374,9 @@ void correction(const Hierarchy& h, int l, const T* table, const T* cbar, T* buf
     for (int q = 0; q < s; ++q) outer *= (uint64_t)shp[q];
     for (int q = s + 1; q < MAXD; ++q) inner *= (uint64_t)shp[q];
     KernelTimer kt(l == h.L ? "thomas_fine" : "thomas_coarse", st);
+    const DimConsts<T> w = dim_consts<T>(h, l, s, table);
     hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, z, outer, (int)shp[s],
-                       inner, dim_consts<T>(h, l, s, table));
+                       inner, w.ta, w.tr, w.tcp);
   }
   *zout = z;
 }
@@ -387,7 +411,8 @@ Scratch scratch_counts(const Hierarchy& h) {
 
 template <typename T>
 void launch_thomas_strided(T* data, uint64_t outer, int n, uint64_t inner, DimConsts<T> w, hipStream_t st) {
-  hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, data, outer, n, inner, w);
+  hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, data, outer, n, inner, w.ta, w.tr,
+                     w.tcp);
 }
 
 template <typename T>
@@ -533,12 +558,92 @@ void recompose(const Hierarchy& h, const T* table, const T* d_stream, const Quan
   MG_HIP(hipGetLastError());
 }
 
+// The tuner runs the real level functions with each candidate forced, on the
+// decomposition's own level grids (the finest is d_in), and keeps the fastest
+// of three timed runs after a warm-up.  The level functions read their input
+// and rewrite their outputs, so repeating them is harmless; the recomposition
+// writes the finest level into the c-bar buffer, never into d_in.
+template <typename T>
+void fused3d_tune(const Hierarchy& h, const T* table, const T* d_in, const QuantOut* q, void* scratch,
+                  hipStream_t st) {
+  if (!fused3d_ok<T>(h) || h.L < 1) return;
+  const bool f64 = sizeof(T) == 8;
+  Scratch sc = scratch_counts(h);
+  Carver cv(scratch);
+  T* cbar = cv.take<T>(sc.cbar);
+  T* pa = cv.take<T>(sc.pa);
+  T* pb = cv.take<T>(sc.pb);
+  T* ga = cv.take<T>(sc.ga);
+  T* gb = cv.take<T>(sc.gb);
+  hipEvent_t e0, e1;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  auto time_it = [&](auto&& run) -> float {
+    run();
+    MG_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r) run();
+    MG_HIP(hipEventRecord(e1, st));
+    MG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+  };
+  struct Reset {
+    ~Reset() {
+      tune_force(TUNE_COEFF_SEG, 0);
+      tune_force(TUNE_SCATTER_PLANES, 0);
+    }
+  } reset;
+  const T* cur = d_in;
+  T* nxt = pa;
+  for (int l = h.L; l >= 1; --l) {
+    const int n0 = (int)h.sizes[l][1], n1 = (int)h.sizes[l][2], n2 = (int)h.sizes[l][3];
+    const int c0 = (int)h.sizes[l - 1][1];
+    int best = 1;
+    float bt = 3.4e38f;
+    for (int seg = 1; seg <= 16 && seg <= std::max(1, c0 - 1); seg *= 2) {
+      tune_force(TUNE_COEFF_SEG, seg);
+      const float t = time_it([&] { fused3d_decompose_level<T>(h, l, table, cur, nxt, ga, gb, q, nullptr, st); });
+      if (t < bt) {
+        bt = t;
+        best = seg;
+      }
+    }
+    tune_force(TUNE_COEFF_SEG, 0);
+    tune_set(TUNE_COEFF_SEG, f64, n0, n1, n2, best);
+    cur = nxt;
+    nxt = (nxt == pa) ? pb : pa;
+  }
+  // cur holds the coarsest grid; recompose upwards
+  for (int l = 1; l <= h.L; ++l) {
+    const int n0 = (int)h.sizes[l][1], n1 = (int)h.sizes[l][2], n2 = (int)h.sizes[l][3];
+    T* out = l == h.L ? cbar : (cur == pa ? pb : pa);
+    int best = 8;
+    float bt = 3.4e38f;
+    for (int planes = 2; planes <= 16 && planes <= std::max(2, n0); planes *= 2) {
+      tune_force(TUNE_SCATTER_PLANES, planes);
+      const float t = time_it([&] { fused3d_recompose_level<T>(h, l, table, cur, out, ga, gb, q, nullptr, st); });
+      if (t < bt) {
+        bt = t;
+        best = planes;
+      }
+    }
+    tune_force(TUNE_SCATTER_PLANES, 0);
+    tune_set(TUNE_SCATTER_PLANES, f64, n0, n1, n2, best);
+    cur = out;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tune_save();
+}
+
 #define MG_INST(T)                                                                                    \
   template LevelGeom<T> level_geom<T>(const Hierarchy&, int, const T*);                             \
   template DimConsts<T> dim_consts<T>(const Hierarchy&, int, int, const T*);                        \
   template void launch_thomas_strided<T>(T*, uint64_t, int, uint64_t, DimConsts<T>, hipStream_t);   \
   template uint64_t decompose_scratch_bytes<T>(const Hierarchy&);                                   \
   template uint64_t recompose_scratch_bytes<T>(const Hierarchy&);                                   \
+  template void fused3d_tune<T>(const Hierarchy&, const T*, const T*, const QuantOut*, void*, hipStream_t); \
   template void decompose<T>(const Hierarchy&, const T*, const T*, T*, const QuantOut*, void*,      \
                              hipStream_t);                                                          \
   template void recompose<T>(const Hierarchy&, const T*, const T*, const QuantOut*, T*, void*,      \

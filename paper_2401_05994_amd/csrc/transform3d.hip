@@ -45,9 +45,53 @@ struct Lv3 {
   const uint64_t* sub;  // sub-grid table of the level (slot layout: user dim d in slot d + 1)
 };
 
+// A block's copy of one dimension's weights in LDS: element i of the full
+// array sits at p[i - off].
+template <typename T>
+struct OffArr {
+  const T* p;
+  int off;
+  __device__ T operator[](int i) const { return p[i - off]; }
+};
+template <typename T>
+struct TileW {
+  OffArr<T> wl, wr, ma, mb, mc, rl, rr;
+};
+
+// Stages, for fine indices [F, F + NF) and coarse indices [J, J + NJ) of a
+// dimension of fine size n and coarse size nc, the weights a tile reads into
+// W (7 arrays: wl, wr, ma, mb, mc over NF, rl, rr over NJ); outside entries are 0.
+template <typename T, int NF, int NJ>
+__device__ inline TileW<T> stage_weights(T* W, const DimConsts<T>& d, int F, int J, int n, int nc) {
+  for (int k = threadIdx.x; k < NF; k += blockDim.x) {
+    const int f = F + k;
+    const bool in = f >= 0 && f < n;
+    W[k] = in ? d.wl[f] : T(0);
+    W[NF + k] = in ? d.wr[f] : T(0);
+    W[2 * NF + k] = in ? d.ma[f] : T(0);
+    W[3 * NF + k] = in ? d.mb[f] : T(0);
+    W[4 * NF + k] = in ? d.mc[f] : T(0);
+  }
+  for (int k = threadIdx.x; k < NJ; k += blockDim.x) {
+    const int j = J + k;
+    const bool in = j < nc;
+    W[5 * NF + k] = in ? d.rl[j] : T(0);
+    W[5 * NF + NJ + k] = in ? d.rr[j] : T(0);
+  }
+  TileW<T> w;
+  w.wl = {W, F};
+  w.wr = {W + NF, F};
+  w.ma = {W + 2 * NF, F};
+  w.mb = {W + 3 * NF, F};
+  w.mc = {W + 4 * NF, F};
+  w.rl = {W + 5 * NF, J};
+  w.rr = {W + 5 * NF + NJ, J};
+  return w;
+}
+
 // mass stencil of a line at fine index i: ((a*g[i-1] + b*g[i]) + c*g[i+1])
-template <typename T, typename G>
-__device__ inline T mass_at(int i, int n, const DimConsts<T>& w, G g) {
+template <typename T, typename W, typename G>
+__device__ inline T mass_at(int i, int n, const W& w, G g) {
   T s = w.mb[i] * g(i);
   if (i > 0) s = w.ma[i] * g(i - 1) + s;
   if (i < n - 1) s = s + w.mc[i] * g(i + 1);
@@ -55,8 +99,8 @@ __device__ inline T mass_at(int i, int n, const DimConsts<T>& w, G g) {
 }
 
 // restriction to coarse j of the mass-weighted line: ((rl*M[c-1] + M[c]) + rr*M[c+1])
-template <typename T, typename G>
-__device__ inline T restrict_at(int j, int nc, int n, const DimConsts<T>& w, G g) {
+template <typename T, typename W, typename G>
+__device__ inline T restrict_at(int j, int nc, int n, const W& w, G g) {
   const int c = cpos(j, nc, n);
   T f = mass_at<T>(c, n, w, g);
   if (c >= 2 && !(c & 1)) f = w.rl[j] * mass_at<T>(c - 1, n, w, g) + f;
@@ -108,11 +152,13 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
                                                    T* __restrict__ g1, uint16_t* __restrict__ sym,
                                                    int64_t* __restrict__ qside, T* __restrict__ cstream,
                                                    const double* __restrict__ bins, int level, int R, Lv3<T> p,
-                                                   int seg) {
+                                                   int seg, const T* __restrict__ d0wl, const T* __restrict__ d0wr) {
   __shared__ T U[RY * RX];
   __shared__ T BA[RY * RX];
   __shared__ T BB[RY * RX];
   __shared__ T G2[RY * TX];
+  __shared__ T W2s[5 * RX + 2 * TX];
+  __shared__ T W1s[5 * RY + 2 * TY];
   __shared__ uint64_t subs[8][4];
   const int t = threadIdx.x;
   const int J1 = blockIdx.y * TY, J2 = blockIdx.x * TX;
@@ -127,25 +173,36 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   double inv_b = 0.0;
   if (MODE == 1) inv_b = 1.0 / bins[level];
   load_sub(subs, p.sub, p.level_off);
+  // weights in LDS, so that the only global loads in the plane loop are the
+  // prefetched planes (a weight load would make the next wait drain them)
+  const TileW<T> w2 = stage_weights<T, RX, TX>(W2s, p.d2, F2, J2, n2, p.c2);
+  const TileW<T> w1 = stage_weights<T, RY, TY>(W1s, p.d1, F1, J1, n1, p.c1);
 
-  // the next plane is loaded into registers while the current one is processed
+  // The next plane is loaded into registers while the current one is
+  // processed.  The loads read clamped (in-range) addresses unconditionally;
+  // elements outside the grid are zeroed when the plane is committed, so no
+  // register is written between a load's issue and its use.
   T pre[PER];
+  auto in_tile = [&](int e) {
+    const int k = t + e * NT;
+    const int r = k / RX, x = k - r * RX;
+    const int f1 = F1 + r, f2 = F2 + x;
+    return k < RY * RX && f1 >= 0 && f1 < n1 && f2 >= 0 && f2 < n2;
+  };
   auto prefetch = [&](int f0) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-      const int k = t + e * NT;
+      const int k = min(t + e * NT, RY * RX - 1);
       const int r = k / RX, x = k - r * RX;
-      const int f1 = F1 + r, f2 = F2 + x;
-      pre[e] = (k < RY * RX && f1 >= 0 && f1 < n1 && f2 >= 0 && f2 < n2)
-                   ? u[(uint64_t)f0 * plane + (uint64_t)f1 * n2 + f2]
-                   : T(0);
+      const int f1 = min(max(F1 + r, 0), n1 - 1), f2 = min(max(F2 + x, 0), n2 - 1);
+      pre[e] = u[(uint64_t)f0 * plane + (uint64_t)f1 * n2 + f2];
     }
   };
   auto commit = [&]() {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int k = t + e * NT;
-      if (k < RY * RX) U[k] = pre[e];
+      if (k < RY * RX) U[k] = in_tile(e) ? pre[e] : T(0);
     }
     __syncthreads();
   };
@@ -155,21 +212,21 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
       const int r = k / RX, x = k - r * RX;
       const int f1 = F1 + r, f2 = F2 + x;
       if (f1 < 0 || f1 >= n1 || f2 < 0 || f2 >= n2 || is_new(f1, n1)) continue;
-      B[k] = is_new(f2, n2) ? p.d2.wl[f2] * U[k - 1] + p.d2.wr[f2] * U[k + 1] : U[k];
+      B[k] = is_new(f2, n2) ? w2.wl[f2] * U[k - 1] + w2.wr[f2] * U[k + 1] : U[k];
     }
     __syncthreads();
     for (int k = t; k < RY * RX; k += NT) {
       const int r = k / RX, x = k - r * RX;
       const int f1 = F1 + r, f2 = F2 + x;
       if (f2 < 0 || f2 >= n2 || !is_new(f1, n1)) continue;
-      B[k] = p.d1.wl[f1] * B[k - RX] + p.d1.wr[f1] * B[k + RX];
+      B[k] = w1.wl[f1] * B[k - RX] + w1.wr[f1] * B[k + RX];
     }
     __syncthreads();
   };
   // coefficients of plane f0 into U, outputs of the owned nodes, then R2 and R1 -> g1
   auto emit = [&](int f0, const T* Bl, const T* Br) {
     const bool new0 = is_new(f0, n0);
-    const T w0l = new0 ? p.d0.wl[f0] : T(0), w0r = new0 ? p.d0.wr[f0] : T(0);
+    const T w0l = new0 ? d0wl[f0] : T(0), w0r = new0 ? d0wr[f0] : T(0);
     for (int k = t; k < RY * RX; k += NT) {
       const int r = k / RX, x = k - r * RX;
       const int f1 = F1 + r, f2 = F2 + x;
@@ -197,7 +254,7 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
       const int f1 = F1 + r, j2 = J2 + jx;
       if (f1 < 0 || f1 >= n1 || j2 >= p.c2) continue;
       const T* row = U + r * RX - F2;  // row[f2] for fine f2 inside the tile
-      G2[k] = restrict_at<T>(j2, p.c2, n2, p.d2, [&](int i) { return row[i]; });
+      G2[k] = restrict_at<T>(j2, p.c2, n2, w2, [&](int i) { return row[i]; });
     }
     __syncthreads();
     // mass + restriction along dim 1 -> g1
@@ -206,7 +263,7 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
       const int j1 = J1 + jy, j2 = J2 + jx;
       if (j1 >= p.c1 || j2 >= p.c2) continue;
       const T* col = G2 + jx - F1 * TX;  // col[f1 * TX]
-      const T f = restrict_at<T>(j1, p.c1, n1, p.d1, [&](int i) { return col[i * TX]; });
+      const T f = restrict_at<T>(j1, p.c1, n1, w1, [&](int i) { return col[i * TX]; });
       g1[((uint64_t)f0 * p.c1 + j1) * p.c2 + j2] = f;
     }
     __syncthreads();
@@ -270,32 +327,99 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   }
 }
 
-// mass + restriction along dim 0 of g1 (n0 x c1 x c2), then Thomas along dim 0 -> z (c0 x c1 x c2)
+// mass + restriction along dim 0 of g1 (n0 x c1 x c2), then Thomas along dim 0 -> z (c0 x c1 x c2).
+// One lane per (j1, j2) line.  Both sweeps run in groups of SWEEP coarse
+// indices whose loads are all issued before the group's recurrence, so a
+// lane waits for memory once per group rather than once per index; the
+// arithmetic and its order are those of the plain loops.
+constexpr int SWEEP = 16;
+
+// The weights come as separate restrict pointers: the compiler then knows the
+// stores to z leave them alone and reads them with scalar loads.
 template <typename T>
 __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T* __restrict__ z, int n0, int c0,
-                                                    uint64_t lines, DimConsts<T> w) {
+                                                    uint64_t lines, const T* __restrict__ w_ma,
+                                                    const T* __restrict__ w_mb, const T* __restrict__ w_mc,
+                                                    const T* __restrict__ w_rl, const T* __restrict__ w_rr,
+                                                    const T* __restrict__ w_ta, const T* __restrict__ w_tr,
+                                                    const T* __restrict__ w_tcp) {
+  struct {
+    const T *ma, *mb, *mc, *rl, *rr, *ta, *tr, *tcp;
+  } w{w_ma, w_mb, w_mc, w_rl, w_rr, w_ta, w_tr, w_tcp};
   const uint64_t t = (uint64_t)blockIdx.x * NT + threadIdx.x;
   if (t >= lines) return;
   const T* g = g1 + t;
   T* zz = z + t;
-  auto G = [&](int i) { return g[(uint64_t)i * lines]; };
   T prev = T(0);
-  for (int j = 0; j < c0; ++j) {
-    const T f = restrict_at<T>(j, c0, n0, w, G);
+  // coarse j < c0 - 1 sits at fine 2j: it reads fine rows 2j-2 .. 2j+2
+  const int jend = c0 - 1;
+  for (int j0 = 0; j0 < jend; j0 += SWEEP) {
+    T rows[2 * SWEEP + 3];
+    const int r0 = 2 * j0 - 2;
+#pragma unroll
+    for (int q = 0; q < 2 * SWEEP + 3; ++q) {
+      const int r = r0 + q;
+      rows[q] = (r >= 0 && r < n0 && q <= 2 * (jend - 1 - j0) + 4) ? g[(uint64_t)r * lines] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < SWEEP; ++u) {
+      const int j = j0 + u;
+      if (j < jend) {
+        // mass_at and restrict_at for c = 2j, rows[q] holding fine row r0 + q
+        auto M = [&](int d) -> T {
+          const int i = 2 * j + d;
+          T s = w.mb[i] * rows[2 * u + 2 + d];
+          if (i > 0) s = w.ma[i] * rows[2 * u + 1 + d] + s;
+          if (i < n0 - 1) s = s + w.mc[i] * rows[2 * u + 3 + d];
+          return s;
+        };
+        T f = M(0);
+        if (j >= 1) f = w.rl[j] * M(-1) + f;
+        if (2 * j < n0 - 2) f = f + w.rr[j] * M(1);
+        prev = j == 0 ? f * w.tr[0] : (f - w.ta[j] * prev) * w.tr[j];
+        zz[(uint64_t)j * lines] = prev;
+      }
+    }
+  }
+  {
+    const int j = jend;
+    auto G = [&](int i) { return g[(uint64_t)i * lines]; };
+    DimConsts<T> dc{};
+    dc.ma = w.ma;
+    dc.mb = w.mb;
+    dc.mc = w.mc;
+    dc.rl = w.rl;
+    dc.rr = w.rr;
+    const T f = restrict_at<T>(j, c0, n0, dc, G);
     prev = j == 0 ? f * w.tr[0] : (f - w.ta[j] * prev) * w.tr[j];
     zz[(uint64_t)j * lines] = prev;
   }
   T x = prev;
-  for (int j = c0 - 2; j >= 0; --j) {
-    x = zz[(uint64_t)j * lines] - w.tcp[j] * x;
-    zz[(uint64_t)j * lines] = x;
+  for (int j1 = c0 - 2; j1 >= 0; j1 -= SWEEP) {
+    T v[SWEEP];
+#pragma unroll
+    for (int u = 0; u < SWEEP; ++u) {
+      const int j = j1 - u;
+      v[u] = j >= 0 ? zz[(uint64_t)j * lines] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < SWEEP; ++u) {
+      const int j = j1 - u;
+      if (j >= 0) {
+        x = v[u] - w.tcp[j] * x;
+        zz[(uint64_t)j * lines] = x;
+      }
+    }
   }
 }
 
-// Thomas along the contiguous dimension on `rows` rows per block, then out = a +/- z
+// Thomas along the contiguous dimension on `rows` rows per block, then out = a +/- z.
+// The weights are restrict pointers (scalar loads); the sweeps are unrolled
+// so that their LDS reads and weight loads are issued ahead of the recurrence.
 template <typename T, bool ADD>
-__global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T* out,
-                                                      uint64_t nrows, int n, int rows, DimConsts<T> w) {
+__global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T* out, uint64_t nrows, int n, int rows,
+                                                      const T* __restrict__ ta, const T* __restrict__ tr,
+                                                      const T* __restrict__ tcp) {
   __shared__ T tile[AXPY_LDS / sizeof(T)];
   const uint64_t r0 = (uint64_t)blockIdx.x * rows;
   const int nr = (int)min((uint64_t)rows, nrows - r0);
@@ -305,15 +429,17 @@ __global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T*
   __syncthreads();
   if ((int)threadIdx.x < nr) {
     T* line = tile + threadIdx.x * n;
-    T prev = line[0] * w.tr[0];
+    T prev = line[0] * tr[0];
     line[0] = prev;
+#pragma unroll 8
     for (int i = 1; i < n; ++i) {
-      prev = (line[i] - w.ta[i] * prev) * w.tr[i];
+      prev = (line[i] - ta[i] * prev) * tr[i];
       line[i] = prev;
     }
     T x = prev;
+#pragma unroll 8
     for (int i = n - 2; i >= 0; --i) {
-      x = line[i] - w.tcp[i] * x;
+      x = line[i] - tcp[i] * x;
       line[i] = x;
     }
   }
@@ -329,6 +455,8 @@ __global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict_
                                                      int level, int R, T* __restrict__ g1, Lv3<T> p, int planes_per) {
   __shared__ T U[RY * RX];
   __shared__ T G2[RY * TX];
+  __shared__ T W2s[5 * RX + 2 * TX];
+  __shared__ T W1s[5 * RY + 2 * TY];
   __shared__ uint64_t subs[8][4];
   const int t = threadIdx.x;
   const int J1 = blockIdx.y * TY, J2 = blockIdx.x * TX;
@@ -336,6 +464,8 @@ __global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict_
   const int n0 = p.n0, n1 = p.n1, n2 = p.n2;
   const double b = MODE == 1 ? bins[level] : 0.0;
   load_sub(subs, p.sub, p.level_off);
+  const TileW<T> w2 = stage_weights<T, RX, TX>(W2s, p.d2, F2, J2, n2, p.c2);
+  const TileW<T> w1 = stage_weights<T, RY, TY>(W1s, p.d1, F1, J1, n1, p.c1);
   __syncthreads();
   const int fb = blockIdx.z * planes_per, fe = min(fb + planes_per, n0);
   for (int f0 = fb; f0 < fe; ++f0) {
@@ -359,7 +489,7 @@ __global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict_
       const int f1 = F1 + r, j2 = J2 + jx;
       if (f1 < 0 || f1 >= n1 || j2 >= p.c2) continue;
       const T* row = U + r * RX - F2;
-      G2[k] = restrict_at<T>(j2, p.c2, n2, p.d2, [&](int i) { return row[i]; });
+      G2[k] = restrict_at<T>(j2, p.c2, n2, w2, [&](int i) { return row[i]; });
     }
     __syncthreads();
     for (int k = t; k < TY * TX; k += NT) {
@@ -368,13 +498,17 @@ __global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict_
       if (j1 >= p.c1 || j2 >= p.c2) continue;
       const T* col = G2 + jx - F1 * TX;
       g1[((uint64_t)f0 * p.c1 + j1) * p.c2 + j2] =
-          restrict_at<T>(j1, p.c1, n1, p.d1, [&](int i) { return col[i * TX]; });
+          restrict_at<T>(j1, p.c1, n1, w1, [&](int i) { return col[i * TX]; });
     }
     __syncthreads();
   }
 }
 
-// u_l = c + Pi(uc) at new nodes, uc at coarse nodes; Pi nested with dim 2 innermost
+// u_l = c + Pi(uc) at new nodes, uc at coarse nodes; Pi nested with dim 2 innermost.
+// A block covers IA_ROWS rows of one plane, its threads walking the rows'
+// elements in order (row, column) so that short rows do not leave lanes idle.
+constexpr int IA_ROWS = 8;
+
 template <typename T, int MODE>
 __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T* __restrict__ uc,
                                                     const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside,
@@ -383,31 +517,42 @@ __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T
   __shared__ uint64_t subs[8][4];
   load_sub(subs, p.sub, p.level_off);
   __syncthreads();
-  const int f2 = blockIdx.x * NT + threadIdx.x;
-  const int f1 = blockIdx.y;
-  const int f0 = blockIdx.z;
-  if (f2 >= p.n2) return;
   const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
-  const bool e0 = is_new(f0, n0), e1 = is_new(f1, n1), e2 = is_new(f2, n2);
-  const int m = (e0 ? 1 : 0) | (e1 ? 2 : 0) | (e2 ? 4 : 0);
-  const uint64_t o = ((uint64_t)f0 * n1 + f1) * n2 + f2;
-  auto UC = [&](int q0, int q1, int q2) { return uc[((uint64_t)q0 * c1 + q1) * c2 + q2]; };
-  if (m == 0) {
-    out[o] = UC(cidx(f0), cidx(f1), cidx(f2));
-    return;
+  const int f0 = blockIdx.y;
+  const int R0 = blockIdx.x * IA_ROWS;
+  const int total = min(IA_ROWS, n1 - R0) * n2;
+  const bool e0 = is_new(f0, n0);
+  const T w0l = e0 ? p.d0.wl[f0] : T(0), w0r = e0 ? p.d0.wr[f0] : T(0);
+  const double b = MODE == 1 ? bins[level] : 0.0;
+  int row = (int)threadIdx.x / n2, col = (int)threadIdx.x - row * n2;
+  for (int e = threadIdx.x; e < total; e += NT) {
+    const int f1 = R0 + row, f2 = col;
+    col += NT;
+    while (col >= n2) {
+      col -= n2;
+      ++row;
+    }
+    const bool e1 = is_new(f1, n1), e2 = is_new(f2, n2);
+    const int m = (e0 ? 1 : 0) | (e1 ? 2 : 0) | (e2 ? 4 : 0);
+    const uint64_t o = ((uint64_t)f0 * n1 + f1) * n2 + f2;
+    auto UC = [&](int q0, int q1, int q2) { return uc[((uint64_t)q0 * c1 + q1) * c2 + q2]; };
+    if (m == 0) {
+      out[o] = UC(cidx(f0), cidx(f1), cidx(f2));
+      continue;
+    }
+    auto V = [&](int q0, int q1) -> T {
+      if (e2) return p.d2.wl[f2] * UC(q0, q1, f2 >> 1) + p.d2.wr[f2] * UC(q0, q1, (f2 >> 1) + 1);
+      return UC(q0, q1, cidx(f2));
+    };
+    auto W = [&](int q0) -> T {
+      if (e1) return p.d1.wl[f1] * V(q0, f1 >> 1) + p.d1.wr[f1] * V(q0, (f1 >> 1) + 1);
+      return V(q0, cidx(f1));
+    };
+    const T pi = e0 ? w0l * W(f0 >> 1) + w0r * W((f0 >> 1) + 1) : W(cidx(f0));
+    const uint64_t pos = pos_of(subs, m, f0, f1, f2);
+    const T c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
+    out[o] = c + pi;
   }
-  auto V = [&](int q0, int q1) -> T {
-    if (e2) return p.d2.wl[f2] * UC(q0, q1, f2 >> 1) + p.d2.wr[f2] * UC(q0, q1, (f2 >> 1) + 1);
-    return UC(q0, q1, cidx(f2));
-  };
-  auto W = [&](int q0) -> T {
-    if (e1) return p.d1.wl[f1] * V(q0, f1 >> 1) + p.d1.wr[f1] * V(q0, (f1 >> 1) + 1);
-    return V(q0, cidx(f1));
-  };
-  const T pi = e0 ? p.d0.wl[f0] * W(f0 >> 1) + p.d0.wr[f0] * W((f0 >> 1) + 1) : W(cidx(f0));
-  const uint64_t pos = pos_of(subs, m, f0, f1, f2);
-  const T c = MODE == 1 ? dequant_load<T>(sym, qside, pos, bins[level], R) : cstream[pos];
-  out[o] = c + pi;
 }
 
 inline unsigned blocks1(uint64_t n) { return (unsigned)std::max<uint64_t>(1, (n + NT - 1) / NT); }
@@ -461,19 +606,21 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
     KernelTimer kt(fine ? "coeff_r21_fine" : "coeff_r21_coarse", st);
     // coarse intervals of dim 0 per block: enough blocks to fill the chip, at most 16
     const uint64_t tiles = (uint64_t)((p.c2 + TX - 1) / TX) * ((p.c1 + TY - 1) / TY);
-    const int seg = (int)std::max<uint64_t>(1, std::min<uint64_t>(16, ((uint64_t)(p.c0 - 1) * tiles + 4095) / 4096));
+    const int guess = (int)std::max<uint64_t>(1, std::min<uint64_t>(16, ((uint64_t)(p.c0 - 1) * tiles + 4095) / 4096));
+    const int seg = std::max(1, tune_get(TUNE_COEFF_SEG, sizeof(T) == 8, p.n0, p.n1, p.n2, guess));
     dim3 grid((p.c2 + TX - 1) / TX, (p.c1 + TY - 1) / TY, (p.c0 - 1 + seg - 1) / seg);
     if (q)
       hipLaunchKernelGGL((k3_coeff_r21<T, 1>), grid, dim3(NT), 0, st, u, ucoarse, g1, q->sym, q->qside,
-                         (T*)nullptr, q->bins, l, q->R, p, seg);
+                         (T*)nullptr, q->bins, l, q->R, p, seg, p.d0.wl, p.d0.wr);
     else
       hipLaunchKernelGGL((k3_coeff_r21<T, 0>), grid, dim3(NT), 0, st, u, ucoarse, g1, (uint16_t*)nullptr,
-                         (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, seg);
+                         (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, seg, p.d0.wl, p.d0.wr);
   }
   const uint64_t lines = (uint64_t)p.c1 * p.c2;
   {
     KernelTimer kt(fine ? "r0_thomas0_fine" : "r0_thomas0_coarse", st);
-    hipLaunchKernelGGL(k3_r0_thomas0<T>, dim3(blocks1(lines)), dim3(NT), 0, st, g1, z, p.n0, p.c0, lines, p.d0);
+    hipLaunchKernelGGL(k3_r0_thomas0<T>, dim3(blocks1(lines)), dim3(NT), 0, st, g1, z, p.n0, p.c0, lines, p.d0.ma,
+                       p.d0.mb, p.d0.mc, p.d0.rl, p.d0.rr, p.d0.ta, p.d0.tr, p.d0.tcp);
   }
   {
     KernelTimer kt(fine ? "thomas1_fine" : "thomas1_coarse", st);
@@ -484,7 +631,7 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
     const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / sizeof(T) / p.c2)));
     const uint64_t nrows = (uint64_t)p.c0 * p.c1;
     hipLaunchKernelGGL((k3_thomas2_axpy<T, true>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT), 0, st, z,
-                       ucoarse, ucoarse, nrows, p.c2, rows, p.d2);
+                       ucoarse, ucoarse, nrows, p.c2, rows, p.d2.ta, p.d2.tr, p.d2.tcp);
   }
   MG_HIP(hipGetLastError());
 }
@@ -495,7 +642,7 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
                              const QuantOut* q, const T* cstream, hipStream_t st) {
   Lv3<T> p = lv3<T>(h, l, table);
   const bool fine = l == h.L;
-  const int planes_per = 8;
+  const int planes_per = std::max(1, tune_get(TUNE_SCATTER_PLANES, sizeof(T) == 8, p.n0, p.n1, p.n2, 8));
   {
     KernelTimer kt(fine ? "scatter_r21_fine" : "scatter_r21_coarse", st);
     dim3 grid((p.c2 + TX - 1) / TX, (p.c1 + TY - 1) / TY, (p.n0 + planes_per - 1) / planes_per);
@@ -509,7 +656,8 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
   const uint64_t lines = (uint64_t)p.c1 * p.c2;
   {
     KernelTimer kt(fine ? "rec_r0_thomas0_fine" : "rec_r0_thomas0_coarse", st);
-    hipLaunchKernelGGL(k3_r0_thomas0<T>, dim3(blocks1(lines)), dim3(NT), 0, st, g1, z, p.n0, p.c0, lines, p.d0);
+    hipLaunchKernelGGL(k3_r0_thomas0<T>, dim3(blocks1(lines)), dim3(NT), 0, st, g1, z, p.n0, p.c0, lines, p.d0.ma,
+                       p.d0.mb, p.d0.mc, p.d0.rl, p.d0.rr, p.d0.ta, p.d0.tr, p.d0.tcp);
   }
   {
     KernelTimer kt(fine ? "rec_thomas1_fine" : "rec_thomas1_coarse", st);
@@ -521,11 +669,11 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
     const uint64_t nrows = (uint64_t)p.c0 * p.c1;
     // uc = u_{l-1} - z, written over z
     hipLaunchKernelGGL((k3_thomas2_axpy<T, false>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT), 0, st, z,
-                       cur, z, nrows, p.c2, rows, p.d2);
+                       cur, z, nrows, p.c2, rows, p.d2.ta, p.d2.tr, p.d2.tcp);
   }
   {
     KernelTimer kt(fine ? "interp_add3_fine" : "interp_add3_coarse", st);
-    dim3 grid(blocks1((uint64_t)p.n2), (unsigned)p.n1, (unsigned)p.n0);
+    dim3 grid((unsigned)((p.n1 + IA_ROWS - 1) / IA_ROWS), (unsigned)p.n0);
     if (q)
       hipLaunchKernelGGL((k3_interp_add<T, 1>), grid, dim3(NT), 0, st, out, z, q->sym, q->qside, (const T*)nullptr,
                          q->bins, l, q->R, p);

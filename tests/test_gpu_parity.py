@@ -217,6 +217,60 @@ def test_huffman_long_codes_bitexact(lib):
     assert np.array_equal(lib.u16(dec).astype(np.int64), sym)
 
 
+def _adversarial_histograms():
+    rng = np.random.default_rng(21)
+    fib = [1, 1]
+    while len(fib) < 40:
+        fib.append(fib[-1] + fib[-2])
+    h = np.zeros(8192, dtype=np.int64)
+    h[rng.choice(8192, 40, replace=False)] = fib
+    yield "fibonacci-40", h  # one leaf per depth: the merge's sequential stretches
+    yield "equal-8192", np.full(8192, 3, dtype=np.int64)
+    h = np.zeros(256, dtype=np.int64)
+    h[[5, 200]] = [7, 1]
+    yield "two-symbols", h
+    h = np.zeros(1024, dtype=np.int64)
+    h[rng.choice(1024, 300, replace=False)] = rng.integers(1, 4, 300)
+    yield "ties-1024", h
+    h = rng.integers(0, 2, 8192) * rng.integers(1, 1 << 34, 8192)
+    yield "large-counts", h.astype(np.int64)  # weights beyond 32 bits
+    x = np.clip(np.round(rng.normal(4096, 900, 2_000_000)), 0, 8191).astype(np.int64)
+    yield "normal-8192", np.bincount(x, minlength=8192)
+
+
+@pytest.mark.parametrize("case", list(range(6)))
+def test_codebook_adversarial(lib, case):
+    """Code lengths and canonical codes from histograms that stress the batched merge."""
+    name, h = list(_adversarial_histograms())[case]
+    say("codebook", name)
+    lens, codes = lib.mgard_huffman_codebook(dev(h), len(h))
+    lref = H.code_lengths(h)
+    cref = H.canonical_codes(lref)
+    assert np.array_equal(host(lens).astype(np.int64), lref)
+    assert np.array_equal(host(codes).view(np.uint64)[lref > 0], cref[lref > 0])
+
+
+def test_huffman_many_lengths_bitexact(lib):
+    """A complete prefix code with 25 distinct lengths, all <= 32 (the decoder's search path)."""
+    say("huffman many lengths")
+    dict_size, chunk = 256, 512
+    lens = np.zeros(dict_size, dtype=np.int64)
+    lens[:26] = list(range(1, 26)) + [25]
+    codes = H.canonical_codes(lens)
+    rng = np.random.default_rng(4)
+    sym = np.minimum(rng.geometric(0.3, size=20_001) - 1, 25)
+    bref, wref = H.encode(sym, lens, codes, chunk)
+    dlens = dev(lens.astype(np.uint8))
+    bits, payload = lib.mgard_huffman_encode(dev(sym.astype(np.int16)), dlens, dev(codes.view(np.int64)),
+                                             dict_size, chunk)
+    assert list(host(bits).astype(np.int64)) == bref
+    assert np.array_equal(host(payload).view(np.uint32).astype(np.int64), np.asarray(wref, dtype=np.int64))
+    dec = lib.mgard_huffman_decode(dev(np.asarray(wref, dtype=np.uint32).view(np.int32)),
+                                   dev(np.asarray(bref, dtype=np.uint32).view(np.int32)), len(sym), dlens,
+                                   dict_size, chunk)
+    assert np.array_equal(lib.u16(dec).astype(np.int64), sym)
+
+
 @pytest.mark.parametrize("name,tol", [("c1-129x129-f64", 1e-3), ("c1-129x129-f64", 1e-5),
                                       ("3d-33x20x17-f32-nonuniform", 1e-2), ("3d-65x65x65-f32", 1e-3),
                                       ("even-64x50-f32", 1e-4), ("4d-9x10x7x6-f64", 1e-3)])
