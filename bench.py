@@ -47,6 +47,50 @@ def algorithmic_bytes(kernel: str, n: int, dtype_bytes: int, levels_sizes):
     return None
 
 
+def bench_batch(m, torch, launches: int = 3, tol: float = 1e-3):
+    """The 256-field uneven-shape batch (2D 65..2049 per side, 3D 33..257, slopes U[-4, -5/3],
+    rel Linf tol 1e-3): plan (tuning + capture) once, then time whole-graph launches."""
+    import fieldgen
+
+    specs = fieldgen.batch_specs()
+    fields = []
+    for i, sp in enumerate(specs):
+        # host synthesis: one FFT size per field, which the host does in seconds
+        fields.append(torch.from_numpy(fieldgen.spectral(sp.shape, sp.beta, sp.seed).astype("float32")).cuda())
+        if (i + 1) % 64 == 0:
+            print(f"[bench] batch: generated {i + 1}/{len(specs)} fields", file=sys.stderr, flush=True)
+    in_bytes = sum(f.numel() * 4 for f in fields)
+    print(f"[bench] batch: {len(fields)} fields, {in_bytes / 1e9:.3f} GB", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    b = m.Batch(fields, tol)
+    plan_s = time.perf_counter() - t0
+    print(f"[bench] batch: planned (tuning + capture) in {plan_s:.1f} s", file=sys.stderr, flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(launches):
+        b.launch()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    res = b.results()
+    out_bytes = sum(sz for _, sz in res)
+    # spot check: the largest field decompresses within its bound
+    big = max(range(len(fields)), key=lambda i: fields[i].numel())
+    rec = m.mgard_decompress(res[big][0], res[big][1])
+    err = float((rec - fields[big]).abs().max())
+    tau = tol * float(fields[big].abs().max())
+    assert err <= tau, f"batch field {big}: L-infinity error {err} exceeds {tau}"
+    b.close()
+    print(f"[bench] batch: {ms:.2f} ms per launch (plan {plan_s:.1f} s)", file=sys.stderr, flush=True)
+    return {"workload": "256 seeded float32 fields of uneven shapes (2D 65..2049 per side, 3D 33..257), "
+                        "slopes U[-4,-5/3], rel Linf 1e-3, one graph launch", "fields": len(fields),
+            "in_bytes": in_bytes, "ms_per_launch": round(ms, 3), "GBps": round(in_bytes / (ms * 1e-3) / 1e9, 3),
+            "ratio": round(in_bytes / out_bytes, 4), "plan_s": round(plan_s, 2), "launches": launches}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +100,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=97)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-field batch measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the path has no multi-GPU mode "
@@ -162,6 +207,9 @@ def main():
                                "frac": round(alg_dq / (decomp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_ms_per_step": {k: round(v[1] / kt_steps, 4) for k, v in sorted(rep.items())},
     }
+
+    if not args.no_batch:
+        result["batched"] = bench_batch(m, torch)
 
     if not args.no_cpu_baseline:
         from oracle import codec

@@ -222,6 +222,10 @@ def main(argv=None):
     t.add_argument("--epochs", type=int, default=200)
     t.add_argument("--out", default=DEFAULT_MODEL)
     t.add_argument("--dataset", default=None, help="optional .npz to save/load the labelled rows")
+    t.add_argument("--seed0", type=int, default=10000, help="seed of the first training field")
+    t.add_argument("--merge", default=None,
+                   help="comma-separated labelled-row files (.npz) to train on instead of labelling")
+    t.add_argument("--label-only", action="store_true", help="write the labelled rows (--dataset) and stop")
     e = sub.add_parser("evaluate")
     e.add_argument("--model", default=DEFAULT_MODEL)
     e.add_argument("--n", type=int, default=1025)
@@ -230,15 +234,27 @@ def main(argv=None):
     args = ap.parse_args(argv)
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
     if args.cmd == "train":
-        if args.dataset and os.path.exists(args.dataset):
+        fields = args.count
+        if args.merge:
+            parts = []
+            for f in args.merge.split(","):
+                with np.load(f, allow_pickle=False) as z:
+                    parts.append((z["X"], z["Y"], int(z["fields"]) if "fields" in z else 0))
+            X = np.concatenate([p[0] for p in parts])
+            Y = np.concatenate([p[1] for p in parts])
+            fields = sum(p[2] for p in parts)
+        elif args.dataset and os.path.exists(args.dataset):
             with np.load(args.dataset, allow_pickle=False) as z:
                 X, Y = z["X"], z["Y"]
         else:
-            X, Y = build_dataset(args.count, args.n, log=log)
+            X, Y = build_dataset(args.count, args.n, seed0=args.seed0, log=log)
             if args.dataset:
-                np.savez(args.dataset, X=X, Y=Y)
+                np.savez(args.dataset, X=X, Y=Y, fields=args.count, seed0=args.seed0, n=args.n)
+            if args.label_only:
+                print(json.dumps({"rows": int(X.shape[0]), "dataset": args.dataset}))
+                return
         params, hist = train(X, Y, epochs=args.epochs, log=log)
-        save(args.out, params, {"fields": args.count, "n": args.n, "rows": int(X.shape[0]),
+        save(args.out, params, {"fields": fields, "n": args.n, "rows": int(X.shape[0]),
                                 "final_loss": hist[-1], "theta_mean": float(Y.mean())})
         print(json.dumps({"rows": int(X.shape[0]), "final_loss": hist[-1], "out": args.out}))
     else:
