@@ -79,17 +79,21 @@ def adam_step(params, grads, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=
     return params, m, v
 
 
-# Features of a level (float64): log(rms/tau), log(max|c|/tau), log(count), l/L.
+# Features of a level (float64): log(rms/tau), log(max|c|/tau), log(count / stream length), l/L.
 def level_features(stats, tau):
     """stats: (L+1, 3) rows of (count, sum of squares, max |c|)."""
     stats = np.asarray(stats, dtype=np.float64)
     nlev = stats.shape[0]
     tau = tau if tau > 0 else 1.0
+    total = float(np.sum(stats[:, 0])) if nlev else 0.0
+    total = total if total > 0 else 1.0
     out = np.zeros((nlev, 4))
     for l in range(nlev):
         cnt, ss, mx = stats[l]
         rms = np.sqrt(ss / (cnt if cnt > 0 else 1.0))
-        out[l] = [np.log(rms / tau + 1e-30), np.log(mx / tau + 1e-30), np.log(cnt if cnt > 0 else 1.0),
+        # the level's share of the stream (not its raw count), so that a network trained on one
+        # field size applies to another
+        out[l] = [np.log(rms / tau + 1e-30), np.log(mx / tau + 1e-30), np.log((cnt if cnt > 0 else 1.0) / total),
                   l / (nlev - 1) if nlev > 1 else 0.0]
     return out
 
@@ -126,7 +130,7 @@ def unpack(flat, sizes=(4, 64, 64, 1)):
     return params, mean, std
 
 
-def learned_bins(plain_bins, theta):
-    """b_l = b_plain * exp(clamp(theta_l, -3, 5))."""
+def learned_bins(plain_bins, theta, scale=1.0):
+    """b_l = b_plain * exp(scale * clamp(theta_l, -3, 5)); the judge tries scale 1, then 1/2."""
     t = np.clip(np.asarray(theta, dtype=np.float64).ravel(), -3.0, 5.0)
-    return [float(b) * float(np.exp(x)) for b, x in zip(plain_bins, t)]
+    return [float(b) * float(np.exp(x * scale)) for b, x in zip(plain_bins, t)]

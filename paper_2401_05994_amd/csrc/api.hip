@@ -348,9 +348,12 @@ uint64_t compress_scratch_bytes(const Hierarchy& h, const Opts& o, uint64_t nch)
   return need + lbytes;
 }
 
+constexpr int kLearnedAttempts = 2;  // learned widths tried before the plain ones
+
 // Every device step of one compression, enqueued on o.st with no host
 // synchronisation, host-memory copy or memset, so that it can be captured in
-// a graph.  The static header is copied from `header` (device memory); the
+// a graph (the learned allocation, which batches do not use, reads back the
+// judge's verdict between its attempts).  The static header is copied from `header` (device memory); the
 // results land in *fin_out (device) and, when size_out is given, the total
 // size in *size_out (device).
 template <typename T>
@@ -424,12 +427,26 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
     launch_level_stats<T>(cstream, d_off, nlev, part, stats, st);
     launch_features(stats, scalars, nlev, o.model_params, x, st);
     mlp_forward(o.model_params, x, nlev, theta, nullptr, tmp, st);
-    launch_apply_theta(bins, theta, nlev, learned, st);
-    launch_quantize<T>(cstream, n, d_off, nlev, learned, q.R, sym, qside, st);
-    QuantOut ql = q;
-    ql.bins = learned;
-    recompose<T>(h, table, nullptr, &ql, recon, dscratch, st);
-    launch_linf<T>(recon, d_in, n, err, st);
+    // the judge: widths b * exp(s * theta) for s = 1, then 1/2; the first
+    // whose recomposition meets tau is kept, else the plain widths
+    for (int attempt = 0; attempt < kLearnedAttempts; ++attempt) {
+      launch_apply_theta(bins, theta, nlev, std::ldexp(1.0, -attempt), learned, st);
+      launch_quantize<T>(cstream, n, d_off, nlev, learned, q.R, sym, qside, st);
+      QuantOut ql = q;
+      ql.bins = learned;
+      recompose<T>(h, table, nullptr, &ql, recon, dscratch, st);
+      launch_linf<T>(recon, d_in, n, err, st);
+      if (attempt + 1 < kLearnedAttempts) {
+        double ht[2];
+        unsigned long long he = 0;
+        MG_HIP(hipMemcpyAsync(&he, err, 8, hipMemcpyDeviceToHost, st));
+        MG_HIP(hipMemcpyAsync(ht, scalars, 16, hipMemcpyDeviceToHost, st));
+        MG_HIP(hipStreamSynchronize(st));
+        double e;
+        std::memcpy(&e, &he, 8);
+        if (e <= ht[0]) break;
+      }
+    }
     launch_select_bins(err, scalars, bins, learned, nlev, st);
     launch_quantize<T>(cstream, n, d_off, nlev, bins, q.R, sym, qside, st);
   } else {

@@ -255,7 +255,7 @@ void launch_level_stats(const T* c, const uint64_t* d_off, int nlev, double* d_p
                         hipStream_t st);
 void launch_features(const double* d_stats, const double* d_scalars, int nlev, const float* d_params,
                      float* d_x, hipStream_t st);
-void launch_apply_theta(const double* d_bins, const float* d_theta, int nlev, double* d_learned,
+void launch_apply_theta(const double* d_bins, const float* d_theta, int nlev, double scale, double* d_learned,
                         hipStream_t st);
 template <typename T>
 void launch_linf(const T* a, const T* b, uint64_t n, unsigned long long* d_err, hipStream_t st);

@@ -83,25 +83,28 @@ __global__ void k_features(const double* __restrict__ stats, const double* __res
   const int l = threadIdx.x;
   if (l >= nlev) return;
   const double tau = scalars[0] > 0.0 ? scalars[0] : 1.0;
+  double total = 0.0;
+  for (int k = 0; k < nlev; ++k) total += stats[3 * k];
+  total = total > 0.0 ? total : 1.0;
   const double cnt = stats[3 * l];
   const double rms = sqrt(stats[3 * l + 1] / (cnt > 0.0 ? cnt : 1.0));
   const double mx = stats[3 * l + 2];
   double f[F];
   f[0] = log(rms / tau + 1e-30);
   f[1] = log(mx / tau + 1e-30);
-  f[2] = log(cnt > 0.0 ? cnt : 1.0);
+  f[2] = log((cnt > 0.0 ? cnt : 1.0) / total);  // the level's share of the stream: independent of the field size
   f[3] = nlev > 1 ? (double)l / (double)(nlev - 1) : 0.0;
   for (int i = 0; i < F; ++i) x[l * F + i] = (float)((f[i] - (double)params[i]) / (double)params[F + i]);
 }
 
 // bins[l] = plain * exp(clamp(theta_l)); written to learned[], plain kept in bins[]
 __global__ void k_apply_theta(const double* __restrict__ bins, const float* __restrict__ theta, int nlev,
-                              double* __restrict__ learned) {
+                              double scale, double* __restrict__ learned) {
   const int l = threadIdx.x;
   if (l >= nlev) return;
   double t = (double)theta[l];
   t = t < -3.0 ? -3.0 : (t > 5.0 ? 5.0 : t);
-  learned[l] = bins[l] * exp(t);
+  learned[l] = bins[l] * exp(t * scale);
 }
 
 // ------------------------------------------------------------ L-infinity error
@@ -238,8 +241,9 @@ void launch_features(const double* d_stats, const double* d_scalars, int nlev, c
   MG_HIP(hipGetLastError());
 }
 
-void launch_apply_theta(const double* d_bins, const float* d_theta, int nlev, double* d_learned, hipStream_t st) {
-  hipLaunchKernelGGL(k_apply_theta, dim3(1), dim3(64), 0, st, d_bins, d_theta, nlev, d_learned);
+void launch_apply_theta(const double* d_bins, const float* d_theta, int nlev, double scale, double* d_learned,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_apply_theta, dim3(1), dim3(64), 0, st, d_bins, d_theta, nlev, scale, d_learned);
   MG_HIP(hipGetLastError());
 }
 

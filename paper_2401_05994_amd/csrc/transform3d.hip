@@ -138,11 +138,17 @@ __device__ inline void load_sub(uint64_t (*subs)[4], const uint64_t* sub, uint64
   }
 }
 
-__device__ inline uint64_t pos_of(const uint64_t (*subs)[4], int m, int f0, int f1, int f2) {
-  const int i0 = (m & 1) ? (f0 >> 1) : cidx(f0);
-  const int i1 = (m & 2) ? (f1 >> 1) : cidx(f1);
-  const int i2 = (m & 4) ? (f2 >> 1) : cidx(f2);
-  return subs[m][0] + (uint64_t)i0 * subs[m][1] + (uint64_t)i1 * subs[m][2] + (uint64_t)i2 * subs[m][3];
+// Stream position of the first element of fine row (f0, f1) in the sub-grid
+// of dim-2 parity e2 (0: coarse along dim 2, 1: new); a coarse-coarse-coarse
+// row has none (0).  Along the row, position = base + (e2 ? f2 >> 1 : cidx(f2)),
+// the last dimension of every sub-grid being contiguous.
+__device__ inline uint64_t row_base(const uint64_t (*subs)[4], int f0, int n0, int f1, int n1, int e2) {
+  const bool e0 = is_new(f0, n0), e1 = is_new(f1, n1);
+  const int m = (e0 ? 1 : 0) | (e1 ? 2 : 0) | (e2 ? 4 : 0);
+  if (!m) return 0;
+  const int i0 = e0 ? (f0 >> 1) : cidx(f0);
+  const int i1 = e1 ? (f1 >> 1) : cidx(f1);
+  return subs[m][0] + (uint64_t)i0 * subs[m][1] + (uint64_t)i1 * subs[m][2];
 }
 
 // ------------------------------------------------------------------ decomposition
@@ -160,6 +166,7 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   __shared__ T W2s[5 * RX + 2 * TX];
   __shared__ T W1s[5 * RY + 2 * TY];
   __shared__ uint64_t subs[8][4];
+  __shared__ uint64_t rb[RY][2];  // row bases of the committed plane
   const int t = threadIdx.x;
   const int J1 = blockIdx.y * TY, J2 = blockIdx.x * TX;
   const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
@@ -198,11 +205,15 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
       pre[e] = u[(uint64_t)f0 * plane + (uint64_t)f1 * n2 + f2];
     }
   };
-  auto commit = [&]() {
+  auto commit = [&](int f0) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int k = t + e * NT;
       if (k < RY * RX) U[k] = in_tile(e) ? pre[e] : T(0);
+    }
+    if (t < 2 * RY) {
+      const int f1 = F1 + (t >> 1);
+      rb[t >> 1][t & 1] = (f1 >= 0 && f1 < n1) ? row_base(subs, f0, n0, f1, n1, t & 1) : 0;
     }
     __syncthreads();
   };
@@ -236,11 +247,12 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
       const T c = v - pi;
       U[k] = c;
       if (f1 < o1b || f1 >= o1e || f2 < o2b || f2 >= o2e) continue;
-      const int m = (new0 ? 1 : 0) | (is_new(f1, n1) ? 2 : 0) | (is_new(f2, n2) ? 4 : 0);
+      const bool e2 = is_new(f2, n2);
+      const int m = (new0 ? 1 : 0) | (is_new(f1, n1) ? 2 : 0) | (e2 ? 4 : 0);
       if (m == 0) {
         ucoarse[((uint64_t)cidx(f0) * p.c1 + cidx(f1)) * p.c2 + cidx(f2)] = v;
       } else {
-        const uint64_t pos = pos_of(subs, m, f0, f1, f2);
+        const uint64_t pos = rb[r][e2 ? 1 : 0] + (uint64_t)(e2 ? (f2 >> 1) : cidx(f2));
         if (MODE == 1)
           quant_store(c, inv_b, R, pos, sym, qside);
         else
@@ -293,8 +305,9 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   T* Bn = BB;
   int cplane = cpos(cb, p.c0, n0), ckind = 0, cj = cb;
   int nj = cb, nph = 0;
+  __syncthreads();  // subs and the staged weights are visible to all threads
   prefetch(cplane);
-  commit();
+  commit(cplane);
   while (true) {
     if (ckind != 2) build_b(ckind == 0 ? Bp : Bn);
     int xplane = 0, xkind = 0, xj = 0;
@@ -322,7 +335,7 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
       nj = xj + 1;
       nph = 0;
     }
-    commit();
+    commit(xplane);
     cplane = xplane, ckind = xkind, cj = xj;
   }
 }
@@ -458,6 +471,7 @@ __global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict_
   __shared__ T W2s[5 * RX + 2 * TX];
   __shared__ T W1s[5 * RY + 2 * TY];
   __shared__ uint64_t subs[8][4];
+  __shared__ uint64_t rb[2][RY][2];  // row bases of the current and the next plane
   const int t = threadIdx.x;
   const int J1 = blockIdx.y * TY, J2 = blockIdx.x * TX;
   const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
@@ -468,16 +482,26 @@ __global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict_
   const TileW<T> w1 = stage_weights<T, RY, TY>(W1s, p.d1, F1, J1, n1, p.c1);
   __syncthreads();
   const int fb = blockIdx.z * planes_per, fe = min(fb + planes_per, n0);
+  auto bases = [&](int f0, int slot) {
+    if (t < 2 * RY && f0 < fe) {
+      const int f1 = F1 + (t >> 1);
+      rb[slot][t >> 1][t & 1] = (f1 >= 0 && f1 < n1) ? row_base(subs, f0, n0, f1, n1, t & 1) : 0;
+    }
+  };
+  bases(fb, 0);
+  __syncthreads();
   for (int f0 = fb; f0 < fe; ++f0) {
     const bool new0 = is_new(f0, n0);
+    const int slot = (f0 - fb) & 1;
     for (int k = t; k < RY * RX; k += NT) {
       const int r = k / RX, x = k - r * RX;
       const int f1 = F1 + r, f2 = F2 + x;
       T c = T(0);
       if (f1 >= 0 && f1 < n1 && f2 >= 0 && f2 < n2) {
-        const int m = (new0 ? 1 : 0) | (is_new(f1, n1) ? 2 : 0) | (is_new(f2, n2) ? 4 : 0);
+        const bool e2 = is_new(f2, n2);
+        const int m = (new0 ? 1 : 0) | (is_new(f1, n1) ? 2 : 0) | (e2 ? 4 : 0);
         if (m) {
-          const uint64_t pos = pos_of(subs, m, f0, f1, f2);
+          const uint64_t pos = rb[slot][r][e2 ? 1 : 0] + (uint64_t)(e2 ? (f2 >> 1) : cidx(f2));
           c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
         }
       }
@@ -500,13 +524,16 @@ __global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict_
       g1[((uint64_t)f0 * p.c1 + j1) * p.c2 + j2] =
           restrict_at<T>(j1, p.c1, n1, w1, [&](int i) { return col[i * TX]; });
     }
+    bases(f0 + 1, slot ^ 1);
     __syncthreads();
   }
 }
 
 // u_l = c + Pi(uc) at new nodes, uc at coarse nodes; Pi nested with dim 2 innermost.
-// A block covers IA_ROWS rows of one plane, its threads walking the rows'
-// elements in order (row, column) so that short rows do not leave lanes idle.
+// A block covers IA_ROWS rows of one plane.  Each lane takes a pair of fine
+// columns (2q, 2q+1): column 2q is coarse along dim 2 and column 2q+1 is new
+// (or, for an even side, the last coarse column), so lanes do not diverge on
+// the dim-2 parity and the pair shares its coarse values q and q+1.
 constexpr int IA_ROWS = 8;
 
 template <typename T, int MODE>
@@ -514,44 +541,84 @@ __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T
                                                     const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside,
                                                     const T* __restrict__ cstream, const double* __restrict__ bins,
                                                     int level, int R, Lv3<T> p) {
+  // per row of the block: stream bases (dim-2 parity 0 / 1), the offsets of
+  // the coarse rows it interpolates from ((dim-0 choice, dim-1 choice), the
+  // second choices used by new planes / rows only), its output offset and
+  // its dim-1 weights
   __shared__ uint64_t subs[8][4];
-  load_sub(subs, p.sub, p.level_off);
-  __syncthreads();
+  __shared__ uint64_t rbs[IA_ROWS][2], cbs[IA_ROWS][4], obs[IA_ROWS];
+  __shared__ T w1s[IA_ROWS][2];
+  __shared__ int e1s[IA_ROWS];
   const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
   const int f0 = blockIdx.y;
   const int R0 = blockIdx.x * IA_ROWS;
-  const int total = min(IA_ROWS, n1 - R0) * n2;
+  const int nrow = min(IA_ROWS, n1 - R0);
   const bool e0 = is_new(f0, n0);
+  load_sub(subs, p.sub, p.level_off);
+  __syncthreads();
+  if ((int)threadIdx.x < nrow) {
+    const int r = threadIdx.x, f1 = R0 + r;
+    const bool e1 = is_new(f1, n1);
+    rbs[r][0] = row_base(subs, f0, n0, f1, n1, 0);
+    rbs[r][1] = row_base(subs, f0, n0, f1, n1, 1);
+    const int q0 = e0 ? (f0 >> 1) : cidx(f0), q1 = e1 ? (f1 >> 1) : cidx(f1);
+    for (int a = 0; a < 2; ++a)
+      for (int bb = 0; bb < 2; ++bb)
+        cbs[r][a * 2 + bb] = ((uint64_t)(q0 + (e0 ? a : 0)) * c1 + (uint64_t)(q1 + (e1 ? bb : 0))) * c2;
+    obs[r] = ((uint64_t)f0 * n1 + f1) * n2;
+    w1s[r][0] = e1 ? p.d1.wl[f1] : T(0);
+    w1s[r][1] = e1 ? p.d1.wr[f1] : T(0);
+    e1s[r] = e1 ? 1 : 0;
+  }
+  __syncthreads();
+  const int pairs = (n2 + 1) >> 1;  // column pairs per row; the last may hold one column
+  const int total = nrow * pairs;
   const T w0l = e0 ? p.d0.wl[f0] : T(0), w0r = e0 ? p.d0.wr[f0] : T(0);
   const double b = MODE == 1 ? bins[level] : 0.0;
-  int row = (int)threadIdx.x / n2, col = (int)threadIdx.x - row * n2;
+  int row = (int)threadIdx.x / pairs, q = (int)threadIdx.x - row * pairs;
   for (int e = threadIdx.x; e < total; e += NT) {
-    const int f1 = R0 + row, f2 = col;
-    col += NT;
-    while (col >= n2) {
-      col -= n2;
+    const int r = row, qq = q;
+    q += NT;
+    while (q >= pairs) {
+      q -= pairs;
       ++row;
     }
-    const bool e1 = is_new(f1, n1), e2 = is_new(f2, n2);
-    const int m = (e0 ? 1 : 0) | (e1 ? 2 : 0) | (e2 ? 4 : 0);
-    const uint64_t o = ((uint64_t)f0 * n1 + f1) * n2 + f2;
-    auto UC = [&](int q0, int q1, int q2) { return uc[((uint64_t)q0 * c1 + q1) * c2 + q2]; };
-    if (m == 0) {
-      out[o] = UC(cidx(f0), cidx(f1), cidx(f2));
-      continue;
+    const bool e1 = e1s[r] != 0;
+    const int fa = 2 * qq, fb = fa + 1;        // fine columns of the pair
+    const bool has_b = fb < n2;
+    const bool nb = is_new(fb, n2);             // column fb new (else the last coarse column, or absent)
+    const T* U0 = uc + cbs[r][0];
+    // coarse values of the pair: column q (and q+1 when fb exists)
+    auto val = [&](int a, int bb, int c) { return uc[cbs[r][a * 2 + bb] + c]; };
+    const T wl2 = nb ? p.d2.wl[fb] : T(0), wr2 = nb ? p.d2.wr[fb] : T(0);
+    // V at column fa (coarse): the coarse value; at column fb: interpolation or the next coarse value
+    auto Va = [&](int a, int bb) -> T { return val(a, bb, qq); };
+    auto Vb = [&](int a, int bb) -> T {
+      if (nb) return wl2 * val(a, bb, qq) + wr2 * val(a, bb, qq + 1);
+      return val(a, bb, qq + 1);
+    };
+    auto Wa = [&](int a) -> T { return e1 ? w1s[r][0] * Va(a, 0) + w1s[r][1] * Va(a, 1) : Va(a, 0); };
+    auto Wb = [&](int a) -> T { return e1 ? w1s[r][0] * Vb(a, 0) + w1s[r][1] * Vb(a, 1) : Vb(a, 0); };
+    const uint64_t o = obs[r] + fa;
+    // column fa: coarse along dim 2 (mask without bit 2)
+    if (!e0 && !e1) {
+      out[o] = U0[qq];
+    } else {
+      const T pi = e0 ? w0l * Wa(0) + w0r * Wa(1) : Wa(0);
+      const uint64_t pos = rbs[r][0] + (uint64_t)qq;
+      const T c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
+      out[o] = c + pi;
     }
-    auto V = [&](int q0, int q1) -> T {
-      if (e2) return p.d2.wl[f2] * UC(q0, q1, f2 >> 1) + p.d2.wr[f2] * UC(q0, q1, (f2 >> 1) + 1);
-      return UC(q0, q1, cidx(f2));
-    };
-    auto W = [&](int q0) -> T {
-      if (e1) return p.d1.wl[f1] * V(q0, f1 >> 1) + p.d1.wr[f1] * V(q0, (f1 >> 1) + 1);
-      return V(q0, cidx(f1));
-    };
-    const T pi = e0 ? w0l * W(f0 >> 1) + w0r * W((f0 >> 1) + 1) : W(cidx(f0));
-    const uint64_t pos = pos_of(subs, m, f0, f1, f2);
-    const T c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
-    out[o] = c + pi;
+    if (has_b) {
+      if (!nb && !e0 && !e1) {
+        out[o + 1] = U0[qq + 1];
+      } else {
+        const T pi = e0 ? w0l * Wb(0) + w0r * Wb(1) : Wb(0);
+        const uint64_t pos = nb ? rbs[r][1] + (uint64_t)qq : rbs[r][0] + (uint64_t)(qq + 1);
+        const T c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
+        out[o + 1] = c + pi;
+      }
+    }
   }
 }
 
@@ -642,7 +709,10 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
                              const QuantOut* q, const T* cstream, hipStream_t st) {
   Lv3<T> p = lv3<T>(h, l, table);
   const bool fine = l == h.L;
-  const int planes_per = std::max(1, tune_get(TUNE_SCATTER_PLANES, sizeof(T) == 8, p.n0, p.n1, p.n2, 8));
+  // fine planes per block: about 2048 blocks, at most 8 planes each, unless tuned
+  const uint64_t tiles = (uint64_t)((p.c2 + TX - 1) / TX) * ((p.c1 + TY - 1) / TY);
+  const int guess = (int)std::max<uint64_t>(1, std::min<uint64_t>(8, (uint64_t)p.n0 * tiles / 2048));
+  const int planes_per = std::max(1, tune_get(TUNE_SCATTER_PLANES, sizeof(T) == 8, p.n0, p.n1, p.n2, guess));
   {
     KernelTimer kt(fine ? "scatter_r21_fine" : "scatter_r21_coarse", st);
     dim3 grid((p.c2 + TX - 1) / TX, (p.c1 + TY - 1) / TY, (p.n0 + planes_per - 1) / planes_per);

@@ -12,7 +12,7 @@ kept at their current values.  Starting from theta = 0 (the plain allocation,
 which meets the bound a priori) every accepted step keeps the bound.
 
 Features (one row per level, as the device computes them): log(rms/tau),
-log(max|c|/tau), log(count), l/L.
+log(max|c|/tau), log(count / stream length), l/L.
 
 Usage:
     python -m paper_2401_05994_amd.learned train --count 2000 --n 257 --out <file.npz>
@@ -57,11 +57,12 @@ def plain_bins(shape, tol, maxabs, dtype="float32", coords=None):
 
 def features(stats, tau):
     nlev = stats.shape[0]
+    total = float(sum(stats[l][0] for l in range(nlev))) or 1.0
     out = np.zeros((nlev, 4))
     for l in range(nlev):
         cnt, ss, mx = stats[l]
         rms = math.sqrt(ss / (cnt if cnt > 0 else 1.0))
-        out[l] = [math.log(rms / tau + 1e-30), math.log(mx / tau + 1e-30), math.log(max(cnt, 1.0)),
+        out[l] = [math.log(rms / tau + 1e-30), math.log(mx / tau + 1e-30), math.log(max(cnt, 1.0) / total),
                   l / (nlev - 1) if nlev > 1 else 0.0]
     return out
 
@@ -195,13 +196,14 @@ def load(path=DEFAULT_MODEL):
         return z["params"].astype(np.float32), json.loads(str(z["meta"]))
 
 
-def evaluate(model_params, u, tols, coords=None):
+def evaluate(model_params, u, tols, coords=None, log=print):
     """Plain versus learned ratio and error at each tolerance (device compression, host-side sizes)."""
     m = _lib()
     model = m.Model(model_params)
     nbytes_in = u.numel() * u.element_size()
     rows = []
     for tol in tols:
+        log(f"[learned] evaluating tol {tol:g}")
         _, nb_p, info_p = m.mgard_compress(u, tol, coords)
         _, nb_c, info_c = m.mgard_compress(u, tol, coords, alloc="count")
         buf, nb_l, info_l = m.mgard_compress_learned(u, tol, model, coords)
@@ -261,9 +263,10 @@ def main(argv=None):
         import torch
 
         params, meta = load(args.model)
+        log(f"[learned] generating the {args.n}^3 evaluation field (seed {args.seed})")
         u = training_field(args.n, args.seed, -5.0 / 3.0)
-        del torch
-        rows = evaluate(params, u, [float(x) for x in args.tols.split(",")])
+        torch.cuda.synchronize()
+        rows = evaluate(params, u, [float(x) for x in args.tols.split(",")], log=log)
         print(json.dumps({"model": meta, "n": args.n, "rows": rows}))
 
 

@@ -177,12 +177,12 @@ def test_learned_bins_follow_oracle_network(lib):
     f32 = [[W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)] for W, b in params]
     xn = (feats.astype(np.float32).astype(np.float64) - flat[:4].astype(np.float64)) / flat[4:8].astype(np.float64)
     theta, _ = M.forward(f32, xn)
-    want = M.learned_bins(p.bins, theta)
     hd = codec.parse(host(buf[:nb]).tobytes())
     if info["fallback_used"]:
         assert hd.bins == p.bins
     else:
-        assert rel(hd.bins, want) <= 1e-5
+        # the judge keeps the first of scale 1, 1/2 that meets the bound
+        assert min(rel(hd.bins, M.learned_bins(p.bins, theta, s)) for s in (1.0, 0.5)) <= 1e-5
     r = codec.decompress(host(buf[:nb]).tobytes())
     assert np.abs(r.astype(np.float64) - u.astype(np.float64)).max() <= info["tau_abs"]
 
