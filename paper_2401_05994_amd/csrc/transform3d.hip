@@ -108,17 +108,20 @@ __device__ inline T restrict_at(int j, int nc, int n, const W& w, G g) {
   return f;
 }
 
+// q = sign(y) * floor(|y| + 1/2), y = c / b in float64.  |q| < R is decided on
+// the rounded magnitude, so the common case converts to 32 bits only; the
+// 64-bit conversion is left to escapes.
 template <typename T>
 __device__ inline void quant_store(T c, double inv_b, int R, uint64_t pos, uint16_t* __restrict__ sym,
                                    int64_t* __restrict__ qside) {
   const double y = (double)c * inv_b;
   const double a = floor(fabs(y) + 0.5);
-  const int64_t q = (int64_t)(y < 0.0 ? -a : a);
-  if (q > -R && q < R) {
-    sym[pos] = (uint16_t)(q + R);
+  if (a < (double)R) {
+    const int qa = (int)a;
+    sym[pos] = (uint16_t)(y < 0.0 ? R - qa : R + qa);
   } else {
     sym[pos] = 0;
-    qside[pos] = q;
+    qside[pos] = (int64_t)(y < 0.0 ? -a : a);
   }
 }
 
@@ -126,8 +129,8 @@ template <typename T>
 __device__ inline T dequant_load(const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside, uint64_t pos,
                                  double b, int R) {
   const uint16_t s = sym[pos];
-  const int64_t q = s ? (int64_t)s - R : qside[pos];
-  return static_cast<T>((double)q * b);
+  const double q = s ? (double)((int)s - R) : (double)qside[pos];
+  return static_cast<T>(q * b);
 }
 
 // sub-grid offset and strides of the 7 masks, staged in LDS: [m][0] offset, [m][1..3] strides
@@ -152,6 +155,61 @@ __device__ inline uint64_t row_base(const uint64_t (*subs)[4], int f0, int n0, i
 }
 
 // ------------------------------------------------------------------ decomposition
+// Tile layout of the plane-marching decomposition kernel: CY x CX coarse
+// outputs in (dim 1, dim 2); FY x FX fine nodes with a halo of 2 before and 1
+// after; rows of the LDS arrays are PX apart.  Thread t owns fine column
+// t % 128 and half of the rows (t / 128), so every column quantity is a
+// per-thread constant and every row quantity is uniform across a wavefront.
+constexpr int CX = 62, CY = 8;
+constexpr int FX = 2 * CX + 3, FY = 2 * CY + 3;  // 127 x 19
+constexpr int PX = 128;                          // LDS row pitch of the fine tile
+constexpr int HR = (FY + 1) / 2;                 // rows per half (10, then 9)
+
+// Restriction weights of one coarse index, held in registers: the mass
+// stencils at fine c-1, c, c+1 and the restriction terms, applied in the
+// order of mass_at / restrict_at.
+template <typename T>
+struct RestrictW {
+  int c = 0;
+  bool l = false, r = false;
+  T rl = 0, rr = 0;
+  T a[3] = {0, 0, 0}, b[3] = {0, 0, 0}, d[3] = {0, 0, 0};
+  bool hl[3] = {false, false, false}, hr[3] = {false, false, false};
+
+  template <typename W>
+  __device__ void load(int j, int nc, int n, const W& w) {
+    c = cpos(j, nc, n);
+    l = c >= 2 && !(c & 1);
+    r = !(c & 1) && c < n - 2;
+    rl = l ? w.rl[j] : T(0);
+    rr = r ? w.rr[j] : T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = c - 1 + k;
+      const bool in = i >= 0 && i < n && (k == 1 || (k == 0 && l) || (k == 2 && r));
+      hl[k] = in && i > 0;
+      hr[k] = in && i < n - 1;
+      b[k] = in ? w.mb[i] : T(0);
+      a[k] = hl[k] ? w.ma[i] : T(0);
+      d[k] = hr[k] ? w.mc[i] : T(0);
+    }
+  }
+  template <typename G>
+  __device__ T apply(G g) const {
+    auto M = [&](int k) {
+      const int i = c - 1 + k;
+      T s = b[k] * g(i);
+      if (hl[k]) s = a[k] * g(i - 1) + s;
+      if (hr[k]) s = s + d[k] * g(i + 1);
+      return s;
+    };
+    T f = M(1);
+    if (l) f = rl * M(0) + f;
+    if (r) f = f + rr * M(2);
+    return f;
+  }
+};
+
 // MODE 1: quantize into sym/qside; MODE 0: write float coefficients to cstream.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* __restrict__ ucoarse,
@@ -159,78 +217,86 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
                                                    int64_t* __restrict__ qside, T* __restrict__ cstream,
                                                    const double* __restrict__ bins, int level, int R, Lv3<T> p,
                                                    int seg, const T* __restrict__ d0wl, const T* __restrict__ d0wr) {
-  __shared__ T U[RY * RX];
-  __shared__ T BA[RY * RX];
-  __shared__ T BB[RY * RX];
-  __shared__ T G2[RY * TX];
-  __shared__ T W2s[5 * RX + 2 * TX];
-  __shared__ T W1s[5 * RY + 2 * TY];
+  __shared__ T U[FY * PX];
+  __shared__ T BA[FY * PX];
+  __shared__ T BB[FY * PX];
+  __shared__ T G2[FY * 64];
+  __shared__ T W1s[5 * FY + 2 * CY];
   __shared__ uint64_t subs[8][4];
-  __shared__ uint64_t rb[RY][2];  // row bases of the committed plane
+  __shared__ uint64_t rb[FY][2];  // stream row bases of the committed plane (dim-2 parity 0 / 1)
+  __shared__ uint64_t ucb[FY];    // coarse-grid row offsets of the committed plane
   const int t = threadIdx.x;
-  const int J1 = blockIdx.y * TY, J2 = blockIdx.x * TX;
+  const int J1 = blockIdx.y * CY, J2 = blockIdx.x * CX;
   const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
   const int n0 = p.n0, n1 = p.n1, n2 = p.n2;
   const int cb = blockIdx.z * seg;
   const int ce = min(cb + seg, p.c0 - 1);
   const uint64_t plane = (uint64_t)n1 * n2;
-  // owned fine ranges of this tile
-  const int o1b = 2 * J1, o1e = min(2 * (J1 + TY), n1);
-  const int o2b = 2 * J2, o2e = min(2 * (J2 + TX), n2);
+  const int o1b = 2 * J1, o1e = min(2 * (J1 + CY), n1);  // owned fine rows
   double inv_b = 0.0;
   if (MODE == 1) inv_b = 1.0 / bins[level];
   load_sub(subs, p.sub, p.level_off);
-  // weights in LDS, so that the only global loads in the plane loop are the
-  // prefetched planes (a weight load would make the next wait drain them)
-  const TileW<T> w2 = stage_weights<T, RX, TX>(W2s, p.d2, F2, J2, n2, p.c2);
-  const TileW<T> w1 = stage_weights<T, RY, TY>(W1s, p.d1, F1, J1, n1, p.c1);
+  const TileW<T> w1 = stage_weights<T, FY, CY>(W1s, p.d1, F1, J1, n1, p.c1);
+
+  // this thread's column and rows
+  const int x = t & (PX - 1), h = t >> 7;
+  const int r0 = h * HR, nr = h ? FY - HR : HR;
+  const int f2 = F2 + x;
+  const bool colok = x < FX && f2 >= 0 && f2 < n2;
+  const bool e2 = colok && is_new(f2, n2);
+  const T wl2 = e2 ? p.d2.wl[f2] : T(0), wr2 = e2 ? p.d2.wr[f2] : T(0);
+  const bool own2 = colok && f2 >= 2 * J2 && f2 < min(2 * (J2 + CX), n2);
+  const uint64_t i2 = e2 ? (uint64_t)(f2 >> 1) : (uint64_t)cidx(f2);
+  const int f2c = min(max(f2, 0), n2 - 1);
+  // this thread's restriction along dim 2: coarse column jx, rows g, g+4, ...
+  const int jx = t & 63, g4 = t >> 6;
+  const int j2 = J2 + jx;
+  const bool ok2 = jx < CX && j2 < p.c2;
+  RestrictW<T> rw2;
+  if (ok2) rw2.load(j2, p.c2, n2, p.d2);
 
   // The next plane is loaded into registers while the current one is
-  // processed.  The loads read clamped (in-range) addresses unconditionally;
-  // elements outside the grid are zeroed when the plane is committed, so no
-  // register is written between a load's issue and its use.
-  T pre[PER];
-  auto in_tile = [&](int e) {
-    const int k = t + e * NT;
-    const int r = k / RX, x = k - r * RX;
-    const int f1 = F1 + r, f2 = F2 + x;
-    return k < RY * RX && f1 >= 0 && f1 < n1 && f2 >= 0 && f2 < n2;
-  };
+  // processed: unconditional loads from clamped addresses, zeroed outside the
+  // grid when committed, so no register is written between a load and its use.
+  T pre[HR];
   auto prefetch = [&](int f0) {
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int k = min(t + e * NT, RY * RX - 1);
-      const int r = k / RX, x = k - r * RX;
-      const int f1 = min(max(F1 + r, 0), n1 - 1), f2 = min(max(F2 + x, 0), n2 - 1);
-      pre[e] = u[(uint64_t)f0 * plane + (uint64_t)f1 * n2 + f2];
+    for (int j = 0; j < HR; ++j) {
+      const int f1 = min(max(F1 + r0 + j, 0), n1 - 1);
+      pre[j] = u[(uint64_t)f0 * plane + (uint64_t)f1 * n2 + f2c];
     }
   };
   auto commit = [&](int f0) {
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int k = t + e * NT;
-      if (k < RY * RX) U[k] = in_tile(e) ? pre[e] : T(0);
+    for (int j = 0; j < HR; ++j) {
+      const int f1 = F1 + r0 + j;
+      if (j < nr) U[(r0 + j) * PX + x] = (colok && f1 >= 0 && f1 < n1) ? pre[j] : T(0);
     }
-    if (t < 2 * RY) {
-      const int f1 = F1 + (t >> 1);
-      rb[t >> 1][t & 1] = (f1 >= 0 && f1 < n1) ? row_base(subs, f0, n0, f1, n1, t & 1) : 0;
+    if (t < FY) {
+      const int f1 = F1 + t;
+      const bool in = f1 >= 0 && f1 < n1;
+      rb[t][0] = in ? row_base(subs, f0, n0, f1, n1, 0) : 0;
+      rb[t][1] = in ? row_base(subs, f0, n0, f1, n1, 1) : 0;
+      ucb[t] = in && !is_new(f0, n0) && !is_new(f1, n1) ? ((uint64_t)cidx(f0) * p.c1 + cidx(f1)) * p.c2 : 0;
     }
     __syncthreads();
   };
   // in-plane interpolant of the coarse-coarse nodes: dim 2 on coarse rows, then dim 1
   auto build_b = [&](T* B) {
-    for (int k = t; k < RY * RX; k += NT) {
-      const int r = k / RX, x = k - r * RX;
-      const int f1 = F1 + r, f2 = F2 + x;
-      if (f1 < 0 || f1 >= n1 || f2 < 0 || f2 >= n2 || is_new(f1, n1)) continue;
-      B[k] = is_new(f2, n2) ? w2.wl[f2] * U[k - 1] + w2.wr[f2] * U[k + 1] : U[k];
+#pragma unroll
+    for (int j = 0; j < HR; ++j) {
+      const int r = r0 + j, f1 = F1 + r;
+      if (j >= nr || f1 < 0 || f1 >= n1 || is_new(f1, n1) || !colok) continue;
+      const int k = r * PX + x;
+      B[k] = e2 ? wl2 * U[k - 1] + wr2 * U[k + 1] : U[k];
     }
     __syncthreads();
-    for (int k = t; k < RY * RX; k += NT) {
-      const int r = k / RX, x = k - r * RX;
-      const int f1 = F1 + r, f2 = F2 + x;
-      if (f2 < 0 || f2 >= n2 || !is_new(f1, n1)) continue;
-      B[k] = w1.wl[f1] * B[k - RX] + w1.wr[f1] * B[k + RX];
+#pragma unroll
+    for (int j = 0; j < HR; ++j) {
+      const int r = r0 + j, f1 = F1 + r;
+      if (j >= nr || !is_new(f1, n1) || !colok) continue;
+      const int k = r * PX + x;
+      B[k] = w1.wl[f1] * B[k - PX] + w1.wr[f1] * B[k + PX];
     }
     __syncthreads();
   };
@@ -238,21 +304,21 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   auto emit = [&](int f0, const T* Bl, const T* Br) {
     const bool new0 = is_new(f0, n0);
     const T w0l = new0 ? d0wl[f0] : T(0), w0r = new0 ? d0wr[f0] : T(0);
-    for (int k = t; k < RY * RX; k += NT) {
-      const int r = k / RX, x = k - r * RX;
-      const int f1 = F1 + r, f2 = F2 + x;
-      if (f1 < 0 || f1 >= n1 || f2 < 0 || f2 >= n2) continue;
+#pragma unroll
+    for (int j = 0; j < HR; ++j) {
+      const int r = r0 + j, f1 = F1 + r;
+      if (j >= nr || f1 < 0 || f1 >= n1 || !colok) continue;
+      const int k = r * PX + x;
       const T v = U[k];
       const T pi = new0 ? w0l * Bl[k] + w0r * Br[k] : Bl[k];
       const T c = v - pi;
       U[k] = c;
-      if (f1 < o1b || f1 >= o1e || f2 < o2b || f2 >= o2e) continue;
-      const bool e2 = is_new(f2, n2);
-      const int m = (new0 ? 1 : 0) | (is_new(f1, n1) ? 2 : 0) | (e2 ? 4 : 0);
-      if (m == 0) {
-        ucoarse[((uint64_t)cidx(f0) * p.c1 + cidx(f1)) * p.c2 + cidx(f2)] = v;
+      if (f1 < o1b || f1 >= o1e || !own2) continue;
+      const bool e1 = is_new(f1, n1);
+      if (!new0 && !e1 && !e2) {
+        ucoarse[ucb[r] + (uint64_t)cidx(f2)] = v;
       } else {
-        const uint64_t pos = rb[r][e2 ? 1 : 0] + (uint64_t)(e2 ? (f2 >> 1) : cidx(f2));
+        const uint64_t pos = rb[r][e2 ? 1 : 0] + i2;
         if (MODE == 1)
           quant_store(c, inv_b, R, pos, sym, qside);
         else
@@ -261,21 +327,19 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
     }
     __syncthreads();
     // mass + restriction along dim 2 for every row of the tile
-    for (int k = t; k < RY * TX; k += NT) {
-      const int r = k / TX, jx = k - r * TX;
-      const int f1 = F1 + r, j2 = J2 + jx;
-      if (f1 < 0 || f1 >= n1 || j2 >= p.c2) continue;
-      const T* row = U + r * RX - F2;  // row[f2] for fine f2 inside the tile
-      G2[k] = restrict_at<T>(j2, p.c2, n2, w2, [&](int i) { return row[i]; });
+    for (int r = g4; r < FY; r += 4) {
+      const int f1 = F1 + r;
+      if (f1 < 0 || f1 >= n1 || !ok2) continue;
+      const T* row = U + r * PX - F2;  // row[f2] for fine f2 inside the tile
+      G2[r * 64 + jx] = rw2.apply([&](int i) { return row[i]; });
     }
     __syncthreads();
     // mass + restriction along dim 1 -> g1
-    for (int k = t; k < TY * TX; k += NT) {
-      const int jy = k / TX, jx = k - jy * TX;
-      const int j1 = J1 + jy, j2 = J2 + jx;
-      if (j1 >= p.c1 || j2 >= p.c2) continue;
-      const T* col = G2 + jx - F1 * TX;  // col[f1 * TX]
-      const T f = restrict_at<T>(j1, p.c1, n1, w1, [&](int i) { return col[i * TX]; });
+    for (int jy = g4; jy < CY; jy += 4) {
+      const int j1 = J1 + jy;
+      if (j1 >= p.c1 || !ok2) continue;
+      const T* col = G2 + jx - F1 * 64;  // col[f1 * 64]
+      const T f = restrict_at<T>(j1, p.c1, n1, w1, [&](int i) { return col[i * 64]; });
       g1[((uint64_t)f0 * p.c1 + j1) * p.c2 + j2] = f;
     }
     __syncthreads();
@@ -672,10 +736,10 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
   {
     KernelTimer kt(fine ? "coeff_r21_fine" : "coeff_r21_coarse", st);
     // coarse intervals of dim 0 per block: enough blocks to fill the chip, at most 16
-    const uint64_t tiles = (uint64_t)((p.c2 + TX - 1) / TX) * ((p.c1 + TY - 1) / TY);
+    const uint64_t tiles = (uint64_t)((p.c2 + CX - 1) / CX) * ((p.c1 + CY - 1) / CY);
     const int guess = (int)std::max<uint64_t>(1, std::min<uint64_t>(16, ((uint64_t)(p.c0 - 1) * tiles + 4095) / 4096));
     const int seg = std::max(1, tune_get(TUNE_COEFF_SEG, sizeof(T) == 8, p.n0, p.n1, p.n2, guess));
-    dim3 grid((p.c2 + TX - 1) / TX, (p.c1 + TY - 1) / TY, (p.c0 - 1 + seg - 1) / seg);
+    dim3 grid((p.c2 + CX - 1) / CX, (p.c1 + CY - 1) / CY, (p.c0 - 1 + seg - 1) / seg);
     if (q)
       hipLaunchKernelGGL((k3_coeff_r21<T, 1>), grid, dim3(NT), 0, st, u, ucoarse, g1, q->sym, q->qside,
                          (T*)nullptr, q->bins, l, q->R, p, seg, p.d0.wl, p.d0.wr);
