@@ -87,6 +87,35 @@ def test_multilinear_input_has_zero_coefficients(shape):
     assert np.abs(ucoarse - X.coarse_part(u, h, l)).max() <= 1e-13 * scale
 
 
+@pytest.mark.parametrize("shape", [(9,), (10, 7), (9, 12, 8), (5, 6, 5, 4)])
+def test_coefficient_at_is_residual_of_multilinear_interpolation(shape):
+    """At every new node of the finest level: u(p) minus the tensor-product
+    linear interpolation of the coarse nodes (scipy's RegularGridInterpolator),
+    and exactly the value the full decomposition places in the stream."""
+    from scipy.interpolate import RegularGridInterpolator
+
+    rng = np.random.default_rng(17)
+    xs = [fieldgen.random_coords(n, rng) for n in shape]
+    h = grid.Hierarchy(shape, xs)
+    u = rng.standard_normal(shape)
+    l = h.L
+    cs = [h.cidx(l, d) for d in range(h.D)]
+    interp = RegularGridInterpolator([xs[d][cs[d]] for d in range(h.D)], u[np.ix_(*cs)], method="linear")
+    cbar, _ = X.decompose_level(u, h, l, np.float64)
+    fine = [set(h.fidx(l, d).tolist()) for d in range(h.D)]
+    seen = 0
+    for p in np.ndindex(*shape):
+        got = X.coefficient_at(u, h, p, np.float64)
+        if not any(p[d] in fine[d] for d in range(h.D)):
+            assert got == 0.0
+            continue
+        seen += 1
+        want = u[p] - interp([xs[d][p[d]] for d in range(h.D)])[0]
+        assert abs(got - want) <= 1e-12 * (1 + abs(u).max())
+        assert got == cbar[p]
+    assert seen == np.prod(shape) - np.prod([len(c) for c in cs])
+
+
 def test_constant_input():
     h = grid.Hierarchy((33, 17))
     u = np.full((33, 17), 2.5)
