@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--n", type=int, default=513)
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=97)
+    ap.add_argument("--cpu-n", type=int, default=145)
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-field batch measurement")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
