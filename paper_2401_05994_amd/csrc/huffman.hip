@@ -843,7 +843,20 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
     lim1[b] = tab->lim1[b];
     offs[b] = tab->offset[b];
   }
-  for (uint32_t s = threadIdx.x; s < used; s += blockDim.x) sorted[s] = sorted_g[s];
+  // symbols in code order: eight loads per lane in flight before the LDS stores
+  for (uint32_t s0 = threadIdx.x; s0 < used; s0 += 8 * blockDim.x) {
+    uint16_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t s = s0 + u * blockDim.x;
+      v[u] = s < used ? sorted_g[s] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t s = s0 + u * blockDim.x;
+      if (s < used) sorted[s] = v[u];
+    }
+  }
   __syncthreads();
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nch) return;
@@ -899,7 +912,40 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
     uint64_t buf = 0;  // left-aligned bits
     int have = 0;
     uint64_t pack = 0, prev = 0;
-    for (uint64_t i = 0; i < cntk; ++i) {
+    uint32_t cons = 0, bad = 0;  // bits consumed; malformed-input flag, acted on every 8 symbols
+    const uint32_t nb32 = (uint32_t)nbits;
+    // Symbol i is packed in iteration i + 1, after the next lookup has been
+    // issued, so no iteration waits for its own LDS read; the bit buffer only
+    // depends on the code length.
+    uint32_t sp = 0;
+    auto put = [&](uint64_t j, uint32_t s) -> bool {
+      pack = (pack >> 16) | ((uint64_t)s << 48);
+      if ((j & 7) == 3) prev = pack;
+      if ((j & 7) == 7) {
+        const uint4 v = make_uint4((uint32_t)prev, (uint32_t)(prev >> 32), (uint32_t)pack, (uint32_t)(pack >> 32));
+        *reinterpret_cast<uint4*>(sym + beg + j - 7) = v;
+        if (bad) {
+          atomicOr(status, 1u);
+          return false;
+        }
+        // escape symbols (value 0) among the eight, in order
+        const uint64_t m = 0x0001000100010001ull, h = 0x8000800080008000ull;
+        if (escapes && (((prev - m) & ~prev & h) | ((pack - m) & ~pack & h))) {
+          for (int k = 0; k < 8; ++k) {
+            const uint16_t x = (uint16_t)((k < 4 ? prev : pack) >> (16 * (k & 3)));
+            if (x) continue;
+            if (eo >= eo_end) {
+              atomicOr(status, 1u);
+              return false;
+            }
+            epos[eo++] = beg + j - 7 + k;
+          }
+        }
+      }
+      return true;
+    };
+    // one symbol: refill, length, bit buffer, lookup into s
+    auto step = [&](uint64_t i, uint32_t& s) {
       if ((i & 7) == 4) {
         if (pend) {
           const uint4 va = shift_group(pa, sha), vb = shift_group(pb, shb);
@@ -921,10 +967,14 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
           pend = true;
         }
       }
-      if (have < 32) {
-        buf |= (uint64_t)nextw << (32 - have);
-        have += 32;
-        ++rd;
+      // top up the buffer to at least 32 bits (branch-free; the ring slot is
+      // re-read when no word was taken)
+      {
+        const bool need = have < 32;
+        const uint32_t sh = need ? (uint32_t)(32 - have) : 0u;
+        buf |= need ? ((uint64_t)nextw << sh) : 0ull;
+        have += need ? 32 : 0;
+        rd += need ? 1u : 0u;
         nextw = myring[rd & (RING - 1)];
       }
       const uint32_t top = (uint32_t)(buf >> 32);
@@ -935,29 +985,38 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
         L = past ? flen[j + 1] : L;
         d = past ? fdelta[j + 1] : d;
       }
-      const uint32_t idx = d + (top >> (32 - L));
-      consumed += L;
-      if (L == 0 || idx >= used || consumed > nbits) {
-        atomicOr(status, 1u);
-        return;
-      }
-      const uint32_t s = sorted[idx];
+      // L = 0: no code of the table starts with these bits
+      const uint32_t idx = L ? d + (top >> (32 - L)) : 0xffffffffu;
       buf <<= L;
       have -= (int)L;
-      pack = (pack >> 16) | ((uint64_t)s << 48);
-      if ((i & 7) == 3) prev = pack;
-      if ((i & 7) == 7) {
-        const uint4 v = make_uint4((uint32_t)prev, (uint32_t)(prev >> 32), (uint32_t)pack, (uint32_t)(pack >> 32));
-        *reinterpret_cast<uint4*>(sym + beg + i - 7) = v;
-      }
-      if (s == 0 && escapes) {
-        if (eo >= eo_end) {
-          atomicOr(status, 1u);
-          return;
-        }
-        epos[eo++] = beg + i;
-      }
+      cons += L;
+      const bool ok = idx < used;
+      bad |= (!ok || cons > nb32) ? 1u : 0u;
+      s = sorted[ok ? idx : 0];
+    };
+    // two symbols per trip, in two registers, so a lookup is consumed one
+    // step after it is issued without a register copy of a pending load
+    uint32_t s0 = 0, s1 = 0;
+    uint64_t i = 0;
+    for (; i + 2 <= cntk; i += 2) {
+      step(i, s0);
+      if (i > 0 && !put(i - 1, s1)) return;
+      step(i + 1, s1);
+      if (!put(i, s0)) return;
     }
+    if (i < cntk) {  // odd count: the last symbol goes to s0
+      step(i, s0);
+      if (i > 0 && !put(i - 1, s1)) return;
+      sp = s0;
+    } else {
+      sp = s1;
+    }
+    if (cntk > 0 && !put(cntk - 1, sp)) return;
+    if (bad) {
+      atomicOr(status, 1u);
+      return;
+    }
+    consumed = cons;
     // the last cntk % 8 symbols: pack holds the newest four (newest in the top
     // 16 bits), prev the group's first four (first in the low 16 bits)
     const int tail = (int)(cntk & 7);
@@ -965,6 +1024,13 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
       const int age = tail - 1 - j;  // symbols decoded after this one
       const uint16_t v = age < 4 ? (uint16_t)(pack >> (48 - 16 * age)) : (uint16_t)(prev >> (16 * j));
       sym[beg + (cntk & ~7ull) + j] = v;
+      if (v == 0 && escapes) {
+        if (eo >= eo_end) {
+          atomicOr(status, 1u);
+          return;
+        }
+        epos[eo++] = beg + (cntk & ~7ull) + j;
+      }
     }
   } else {
     const int minlen = (int)tab->minlen, maxlen = (int)tab->maxlen;

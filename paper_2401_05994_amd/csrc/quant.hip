@@ -30,9 +30,22 @@ __device__ inline uint64_t abs_bits(double x) {
 // max of |x| as ordered bit patterns (NaN patterns sort above infinity)
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_maxabs(const T* __restrict__ d, uint64_t n, uint64_t* out) {
+  // eight independent loads per lane per trip, so a lane waits once per eight elements
   uint64_t m = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (uint64_t)gridDim.x * TPB) {
-    uint64_t b = abs_bits(d[i]);
+  const uint64_t step = (uint64_t)gridDim.x * TPB;
+  uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x;
+  for (; i + 7 * step < n; i += 8 * step) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = d[i + u * step];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint64_t b = abs_bits(v[u]);
+      m = b > m ? b : m;
+    }
+  }
+  for (; i < n; i += step) {
+    const uint64_t b = abs_bits(d[i]);
     m = b > m ? b : m;
   }
   __shared__ uint64_t red[TPB];

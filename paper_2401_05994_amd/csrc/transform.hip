@@ -242,10 +242,20 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
     T* line = data + o * (uint64_t)n * inner + k;
     T prev = line[0] * tr[0];
     line[0] = prev;
-    for (int i0 = 1; i0 < n; i0 += G) {
-      T v[G];
+    // two buffers: the next group's loads are issued before this group's recurrence
+    auto load_f = [&](int i0, T* v) {
 #pragma unroll
       for (int q = 0; q < G; ++q) v[q] = i0 + q < n ? line[(uint64_t)(i0 + q) * inner] : T(0);
+    };
+    auto fwd = [&](int i0, const T* v) {
+      if (i0 + G <= n) {  // whole group: one straight block, weight loads issued together
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+          prev = (v[q] - ta[i0 + q] * prev) * tr[i0 + q];
+          line[(uint64_t)(i0 + q) * inner] = prev;
+        }
+        return;
+      }
 #pragma unroll
       for (int q = 0; q < G; ++q) {
         const int i = i0 + q;
@@ -254,12 +264,31 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
           line[(uint64_t)i * inner] = prev;
         }
       }
+    };
+    {
+      T va[G], vb[G];
+      load_f(1, va);
+      for (int i0 = 1; i0 < n; i0 += 2 * G) {
+        load_f(i0 + G, vb);
+        fwd(i0, va);
+        load_f(i0 + 2 * G, va);
+        fwd(i0 + G, vb);
+      }
     }
     T x = prev;
-    for (int i0 = n - 2; i0 >= 0; i0 -= G) {
-      T v[G];
+    auto load_b = [&](int i0, T* v) {
 #pragma unroll
       for (int q = 0; q < G; ++q) v[q] = i0 - q >= 0 ? line[(uint64_t)(i0 - q) * inner] : T(0);
+    };
+    auto bwd = [&](int i0, const T* v) {
+      if (i0 - (G - 1) >= 0) {
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+          x = v[q] - tcp[i0 - q] * x;
+          line[(uint64_t)(i0 - q) * inner] = x;
+        }
+        return;
+      }
 #pragma unroll
       for (int q = 0; q < G; ++q) {
         const int i = i0 - q;
@@ -267,6 +296,16 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
           x = v[q] - tcp[i] * x;
           line[(uint64_t)i * inner] = x;
         }
+      }
+    };
+    {
+      T va[G], vb[G];
+      load_b(n - 2, va);
+      for (int i0 = n - 2; i0 >= 0; i0 -= 2 * G) {
+        load_b(i0 - G, vb);
+        bwd(i0, va);
+        load_b(i0 - 2 * G, va);
+        bwd(i0 - G, vb);
       }
     }
   }

@@ -430,19 +430,41 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
   T prev = T(0);
   // coarse j < c0 - 1 sits at fine 2j: it reads fine rows 2j-2 .. 2j+2
   const int jend = c0 - 1;
-  for (int j0 = 0; j0 < jend; j0 += SWEEP) {
-    T rows[2 * SWEEP + 3];
+  // fine rows of the group starting at coarse j0 (nothing past the last group)
+  auto load_rows = [&](int j0, T* rows) {
     const int r0 = 2 * j0 - 2;
 #pragma unroll
     for (int q = 0; q < 2 * SWEEP + 3; ++q) {
       const int r = r0 + q;
-      rows[q] = (r >= 0 && r < n0 && q <= 2 * (jend - 1 - j0) + 4) ? g[(uint64_t)r * lines] : T(0);
+      rows[q] = (j0 < jend && r >= 0 && r < n0 && q <= 2 * (jend - 1 - j0) + 4) ? g[(uint64_t)r * lines] : T(0);
+    }
+  };
+  auto forward = [&](int j0, const T* rows) {
+    // interior group: every neighbour exists, so the group is one straight
+    // block whose weight loads can be issued together (same arithmetic)
+    if (j0 >= 1 && j0 + SWEEP - 1 < jend && 2 * (j0 + SWEEP - 1) < n0 - 2) {
+#pragma unroll
+      for (int u = 0; u < SWEEP; ++u) {
+        const int j = j0 + u;
+        auto M = [&](int d) -> T {
+          const int i = 2 * j + d;
+          T s = w.mb[i] * rows[2 * u + 2 + d];
+          s = w.ma[i] * rows[2 * u + 1 + d] + s;
+          return s + w.mc[i] * rows[2 * u + 3 + d];
+        };
+        T f = M(0);
+        f = w.rl[j] * M(-1) + f;
+        f = f + w.rr[j] * M(1);
+        prev = (f - w.ta[j] * prev) * w.tr[j];
+        zz[(uint64_t)j * lines] = prev;
+      }
+      return;
     }
 #pragma unroll
     for (int u = 0; u < SWEEP; ++u) {
       const int j = j0 + u;
       if (j < jend) {
-        // mass_at and restrict_at for c = 2j, rows[q] holding fine row r0 + q
+        // mass_at and restrict_at for c = 2j, rows[q] holding fine row 2*j0 - 2 + q
         auto M = [&](int d) -> T {
           const int i = 2 * j + d;
           T s = w.mb[i] * rows[2 * u + 2 + d];
@@ -456,6 +478,17 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
         prev = j == 0 ? f * w.tr[0] : (f - w.ta[j] * prev) * w.tr[j];
         zz[(uint64_t)j * lines] = prev;
       }
+    }
+  };
+  // two row buffers: the next group's loads are issued before this group's recurrence
+  {
+    T ra[2 * SWEEP + 3], rb[2 * SWEEP + 3];
+    load_rows(0, ra);
+    for (int j0 = 0; j0 < jend; j0 += 2 * SWEEP) {
+      load_rows(j0 + SWEEP, rb);
+      forward(j0, ra);
+      load_rows(j0 + 2 * SWEEP, ra);
+      forward(j0 + SWEEP, rb);
     }
   }
   {
@@ -472,12 +505,22 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
     zz[(uint64_t)j * lines] = prev;
   }
   T x = prev;
-  for (int j1 = c0 - 2; j1 >= 0; j1 -= SWEEP) {
-    T v[SWEEP];
+  auto load_z = [&](int j1, T* v) {
 #pragma unroll
     for (int u = 0; u < SWEEP; ++u) {
       const int j = j1 - u;
       v[u] = j >= 0 ? zz[(uint64_t)j * lines] : T(0);
+    }
+  };
+  auto backward = [&](int j1, const T* v) {
+    if (j1 - (SWEEP - 1) >= 0) {
+#pragma unroll
+      for (int u = 0; u < SWEEP; ++u) {
+        const int j = j1 - u;
+        x = v[u] - w.tcp[j] * x;
+        zz[(uint64_t)j * lines] = x;
+      }
+      return;
     }
 #pragma unroll
     for (int u = 0; u < SWEEP; ++u) {
@@ -486,6 +529,16 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
         x = v[u] - w.tcp[j] * x;
         zz[(uint64_t)j * lines] = x;
       }
+    }
+  };
+  {
+    T va[SWEEP], vb[SWEEP];
+    load_z(c0 - 2, va);
+    for (int j1 = c0 - 2; j1 >= 0; j1 -= 2 * SWEEP) {
+      load_z(j1 - SWEEP, vb);
+      backward(j1, va);
+      load_z(j1 - 2 * SWEEP, va);
+      backward(j1 - SWEEP, vb);
     }
   }
 }
@@ -502,7 +555,21 @@ __global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T*
   const int nr = (int)min((uint64_t)rows, nrows - r0);
   const uint64_t base = r0 * (uint64_t)n;
   const int cnt = nr * n;
-  for (int k = threadIdx.x; k < cnt; k += NT) tile[k] = z[base + k];
+  // copies run CP loads ahead of their stores, so a lane waits once per CP elements
+  constexpr int CP = 8;
+  for (int k0 = threadIdx.x; k0 < cnt; k0 += CP * NT) {
+    T v[CP];
+#pragma unroll
+    for (int u = 0; u < CP; ++u) {
+      const int k = k0 + u * NT;
+      v[u] = k < cnt ? z[base + k] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < CP; ++u) {
+      const int k = k0 + u * NT;
+      if (k < cnt) tile[k] = v[u];
+    }
+  }
   __syncthreads();
   if ((int)threadIdx.x < nr) {
     T* line = tile + threadIdx.x * n;
@@ -521,7 +588,19 @@ __global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T*
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < cnt; k += NT) out[base + k] = ADD ? a[base + k] + tile[k] : a[base + k] - tile[k];
+  for (int k0 = threadIdx.x; k0 < cnt; k0 += CP * NT) {
+    T v[CP];
+#pragma unroll
+    for (int u = 0; u < CP; ++u) {
+      const int k = k0 + u * NT;
+      v[u] = k < cnt ? a[base + k] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < CP; ++u) {
+      const int k = k0 + u * NT;
+      if (k < cnt) out[base + k] = ADD ? v[u] + tile[k] : v[u] - tile[k];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ recomposition
@@ -594,93 +673,151 @@ __global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict_
 }
 
 // u_l = c + Pi(uc) at new nodes, uc at coarse nodes; Pi nested with dim 2 innermost.
-// A block covers IA_ROWS rows of one plane.  Each lane takes a pair of fine
-// columns (2q, 2q+1): column 2q is coarse along dim 2 and column 2q+1 is new
-// (or, for an even side, the last coarse column), so lanes do not diverge on
-// the dim-2 parity and the pair shares its coarse values q and q+1.
+// A block covers IA_ROWS fine rows of one plane and a tile of xt column pairs
+// (2q, 2q+1): column 2q is coarse along dim 2 and column 2q+1 is new (or, for
+// an even side, the last coarse column), so the pair shares its coarse values
+// q and q+1.  The coarse rows the block interpolates from (at most IA_CR per
+// coarse plane, at most two planes) are staged in LDS once; each lane issues
+// the symbol loads of all its (row, pair) items before any arithmetic.
 constexpr int IA_ROWS = 8;
+constexpr int IA_CR = IA_ROWS / 2 + 1;
+constexpr int IA_XP = 320;                                 // column pairs per block at most
+constexpr int IA_IT = (IA_ROWS * IA_XP + NT - 1) / NT;     // items per lane at most
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T* __restrict__ uc,
                                                     const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside,
                                                     const T* __restrict__ cstream, const double* __restrict__ bins,
-                                                    int level, int R, Lv3<T> p) {
-  // per row of the block: stream bases (dim-2 parity 0 / 1), the offsets of
-  // the coarse rows it interpolates from ((dim-0 choice, dim-1 choice), the
-  // second choices used by new planes / rows only), its output offset and
-  // its dim-1 weights
+                                                    int level, int R, Lv3<T> p, int xt) {
+  __shared__ T Cs[2][IA_CR][IA_XP + 1];
+  __shared__ T W2s[2][IA_XP];  // dim-2 weights of the tile's new columns 2q + 1
   __shared__ uint64_t subs[8][4];
-  __shared__ uint64_t rbs[IA_ROWS][2], cbs[IA_ROWS][4], obs[IA_ROWS];
+  __shared__ uint64_t rb0[IA_ROWS], rb1[IA_ROWS], obs[IA_ROWS];
   __shared__ T w1s[IA_ROWS][2];
-  __shared__ int e1s[IA_ROWS];
+  __shared__ int kbs[IA_ROWS], e1s[IA_ROWS];
   const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
-  const int f0 = blockIdx.y;
-  const int R0 = blockIdx.x * IA_ROWS;
+  const int t = threadIdx.x;
+  const int f0 = blockIdx.z;
+  const int R0 = blockIdx.y * IA_ROWS;
   const int nrow = min(IA_ROWS, n1 - R0);
+  const int X0 = blockIdx.x * xt;                // first pair (= first coarse column) of the tile
+  const int pairs = (n2 + 1) >> 1;               // column pairs per row; the last may hold one column
+  const int np = min(xt, pairs - X0);
+  const int items = nrow * np;
   const bool e0 = is_new(f0, n0);
+  const int q0 = e0 ? (f0 >> 1) : cidx(f0);
+  const int lo = cidx(R0);                       // R0 is even: a coarse row
+  const int last = R0 + nrow - 1;
+  const int hi = is_new(last, n1) ? (last >> 1) + 1 : cidx(last);
+  const int ncr = hi - lo + 1;
+  const int ncol = min(np + 1, c2 - X0);         // coarse columns X0 .. X0 + ncol - 1
   load_sub(subs, p.sub, p.level_off);
   __syncthreads();
-  if ((int)threadIdx.x < nrow) {
-    const int r = threadIdx.x, f1 = R0 + r;
+  if (t < nrow) {
+    const int f1 = R0 + t;
     const bool e1 = is_new(f1, n1);
-    rbs[r][0] = row_base(subs, f0, n0, f1, n1, 0);
-    rbs[r][1] = row_base(subs, f0, n0, f1, n1, 1);
-    const int q0 = e0 ? (f0 >> 1) : cidx(f0), q1 = e1 ? (f1 >> 1) : cidx(f1);
-    for (int a = 0; a < 2; ++a)
-      for (int bb = 0; bb < 2; ++bb)
-        cbs[r][a * 2 + bb] = ((uint64_t)(q0 + (e0 ? a : 0)) * c1 + (uint64_t)(q1 + (e1 ? bb : 0))) * c2;
-    obs[r] = ((uint64_t)f0 * n1 + f1) * n2;
-    w1s[r][0] = e1 ? p.d1.wl[f1] : T(0);
-    w1s[r][1] = e1 ? p.d1.wr[f1] : T(0);
-    e1s[r] = e1 ? 1 : 0;
+    rb0[t] = row_base(subs, f0, n0, f1, n1, 0);
+    rb1[t] = row_base(subs, f0, n0, f1, n1, 1);
+    obs[t] = ((uint64_t)f0 * n1 + f1) * n2;
+    w1s[t][0] = e1 ? p.d1.wl[f1] : T(0);
+    w1s[t][1] = e1 ? p.d1.wr[f1] : T(0);
+    kbs[t] = (e1 ? (f1 >> 1) : cidx(f1)) - lo;
+    e1s[t] = e1 ? 1 : 0;
   }
   __syncthreads();
-  const int pairs = (n2 + 1) >> 1;  // column pairs per row; the last may hold one column
-  const int total = nrow * pairs;
-  const T w0l = e0 ? p.d0.wl[f0] : T(0), w0r = e0 ? p.d0.wr[f0] : T(0);
   const double b = MODE == 1 ? bins[level] : 0.0;
-  int row = (int)threadIdx.x / pairs, q = (int)threadIdx.x - row * pairs;
-  for (int e = threadIdx.x; e < total; e += NT) {
-    const int r = row, qq = q;
-    q += NT;
-    while (q >= pairs) {
-      q -= pairs;
-      ++row;
+  const T w0l = e0 ? p.d0.wl[f0] : T(0), w0r = e0 ? p.d0.wr[f0] : T(0);
+
+  // items: e = t + it * NT -> (row e / np, pair e % np), advanced incrementally
+  int ir[IA_IT], iq[IA_IT];
+  {
+    int r = t / np, q = t - (t / np) * np;
+#pragma unroll
+    for (int it = 0; it < IA_IT; ++it) {
+      ir[it] = r;
+      iq[it] = q;
+      q += NT;
+      while (q >= np) {
+        q -= np;
+        ++r;
+      }
     }
+  }
+  // symbols (or float coefficients) of every item: column 2q, then column 2q+1
+  uint16_t sa[IA_IT], sb[IA_IT];
+  T ca[IA_IT], cbv[IA_IT];
+#pragma unroll
+  for (int it = 0; it < IA_IT; ++it) {
+    sa[it] = sb[it] = 0;
+    ca[it] = cbv[it] = T(0);
+    if (t + it * NT >= items) continue;
+    const int r = ir[it], qq = X0 + iq[it];
     const bool e1 = e1s[r] != 0;
-    const int fa = 2 * qq, fb = fa + 1;        // fine columns of the pair
+    const int fb = 2 * qq + 1;
+    const bool nb = is_new(fb, n2);
+    if (e0 || e1) {
+      const uint64_t pos = rb0[r] + (uint64_t)qq;
+      if (MODE == 1) sa[it] = sym[pos]; else ca[it] = cstream[pos];
+    }
+    if (fb < n2 && (nb || e0 || e1)) {
+      const uint64_t pos = nb ? rb1[r] + (uint64_t)qq : rb0[r] + (uint64_t)(qq + 1);
+      if (MODE == 1) sb[it] = sym[pos]; else cbv[it] = cstream[pos];
+    }
+  }
+  // coarse rows lo..hi of planes q0 (and q0 + 1 for a new plane), columns of the tile
+  {
+    const int npl = e0 ? 2 : 1;
+    const int per = ncr * ncol;
+    for (int k = t; k < npl * per; k += NT) {
+      const int a = k / per, rem = k - a * per;
+      const int rr = rem / ncol, j = rem - rr * ncol;
+      Cs[a][rr][j] = uc[((uint64_t)(q0 + a) * c1 + (uint64_t)(lo + rr)) * c2 + (uint64_t)(X0 + j)];
+    }
+    for (int q = t; q < np; q += NT) {
+      const int fb = 2 * (X0 + q) + 1;
+      const bool nb = is_new(fb, n2);
+      W2s[0][q] = nb ? p.d2.wl[fb] : T(0);
+      W2s[1][q] = nb ? p.d2.wr[fb] : T(0);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IA_IT; ++it) {
+    if (t + it * NT >= items) continue;
+    const int r = ir[it], q = iq[it], qq = X0 + q;
+    const bool e1 = e1s[r] != 0;
+    const int kb = kbs[r];
+    const int fa = 2 * qq, fb = fa + 1;
     const bool has_b = fb < n2;
-    const bool nb = is_new(fb, n2);             // column fb new (else the last coarse column, or absent)
-    const T* U0 = uc + cbs[r][0];
-    // coarse values of the pair: column q (and q+1 when fb exists)
-    auto val = [&](int a, int bb, int c) { return uc[cbs[r][a * 2 + bb] + c]; };
-    const T wl2 = nb ? p.d2.wl[fb] : T(0), wr2 = nb ? p.d2.wr[fb] : T(0);
-    // V at column fa (coarse): the coarse value; at column fb: interpolation or the next coarse value
-    auto Va = [&](int a, int bb) -> T { return val(a, bb, qq); };
+    const bool nb = is_new(fb, n2);
+    const T wl2 = W2s[0][q], wr2 = W2s[1][q];
+    const T w1l = w1s[r][0], w1r = w1s[r][1];
+    auto Va = [&](int a, int bb) -> T { return Cs[a][kb + bb][q]; };
     auto Vb = [&](int a, int bb) -> T {
-      if (nb) return wl2 * val(a, bb, qq) + wr2 * val(a, bb, qq + 1);
-      return val(a, bb, qq + 1);
+      if (nb) return wl2 * Cs[a][kb + bb][q] + wr2 * Cs[a][kb + bb][q + 1];
+      return Cs[a][kb + bb][q + 1];
     };
-    auto Wa = [&](int a) -> T { return e1 ? w1s[r][0] * Va(a, 0) + w1s[r][1] * Va(a, 1) : Va(a, 0); };
-    auto Wb = [&](int a) -> T { return e1 ? w1s[r][0] * Vb(a, 0) + w1s[r][1] * Vb(a, 1) : Vb(a, 0); };
+    auto Wa = [&](int a) -> T { return e1 ? w1l * Va(a, 0) + w1r * Va(a, 1) : Va(a, 0); };
+    auto Wb = [&](int a) -> T { return e1 ? w1l * Vb(a, 0) + w1r * Vb(a, 1) : Vb(a, 0); };
+    auto coef = [&](uint16_t s, T cf, uint64_t pos) -> T {
+      if (MODE == 0) return cf;
+      const double qv = s ? (double)((int)s - R) : (double)qside[pos];
+      return static_cast<T>(qv * b);
+    };
     const uint64_t o = obs[r] + fa;
-    // column fa: coarse along dim 2 (mask without bit 2)
     if (!e0 && !e1) {
-      out[o] = U0[qq];
+      out[o] = Cs[0][kb][q];
     } else {
       const T pi = e0 ? w0l * Wa(0) + w0r * Wa(1) : Wa(0);
-      const uint64_t pos = rbs[r][0] + (uint64_t)qq;
-      const T c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
-      out[o] = c + pi;
+      out[o] = coef(sa[it], ca[it], rb0[r] + (uint64_t)qq) + pi;
     }
     if (has_b) {
       if (!nb && !e0 && !e1) {
-        out[o + 1] = U0[qq + 1];
+        out[o + 1] = Cs[0][kb][q + 1];
       } else {
         const T pi = e0 ? w0l * Wb(0) + w0r * Wb(1) : Wb(0);
-        const uint64_t pos = nb ? rbs[r][1] + (uint64_t)qq : rbs[r][0] + (uint64_t)(qq + 1);
-        const T c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
-        out[o + 1] = c + pi;
+        const uint64_t pos = nb ? rb1[r] + (uint64_t)qq : rb0[r] + (uint64_t)(qq + 1);
+        out[o + 1] = coef(sb[it], cbv[it], pos) + pi;
       }
     }
   }
@@ -807,13 +944,17 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
   }
   {
     KernelTimer kt(fine ? "interp_add3_fine" : "interp_add3_coarse", st);
-    dim3 grid((unsigned)((p.n1 + IA_ROWS - 1) / IA_ROWS), (unsigned)p.n0);
+    // column pairs per block: the fewest tiles of at most IA_XP pairs, balanced
+    const int pairs = (p.n2 + 1) / 2;
+    const int ntx = (pairs + IA_XP - 1) / IA_XP;
+    const int xt = (pairs + ntx - 1) / ntx;
+    dim3 grid((unsigned)((pairs + xt - 1) / xt), (unsigned)((p.n1 + IA_ROWS - 1) / IA_ROWS), (unsigned)p.n0);
     if (q)
       hipLaunchKernelGGL((k3_interp_add<T, 1>), grid, dim3(NT), 0, st, out, z, q->sym, q->qside, (const T*)nullptr,
-                         q->bins, l, q->R, p);
+                         q->bins, l, q->R, p, xt);
     else
       hipLaunchKernelGGL((k3_interp_add<T, 0>), grid, dim3(NT), 0, st, out, z, (const uint16_t*)nullptr,
-                         (const int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p);
+                         (const int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, xt);
   }
   MG_HIP(hipGetLastError());
 }
