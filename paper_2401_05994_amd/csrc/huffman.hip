@@ -826,6 +826,11 @@ __device__ inline uint4 shift_group(uint4 v, uint32_t sh) {
 // esc_off is given, the stream position of the j-th escape symbol is written
 // to epos[j] (chunk k owns entries [esc_off[k], esc_off[k+1])); the loop
 // itself issues no loads besides the payload, so it never waits on them early.
+// NF: length-chain size.  Three instances are launched; the one whose range
+// holds the table's number of distinct lengths decodes (NF = 8: 1..7,
+// NF = 12: 8..11, NF = 16: 12..15 and tables without a fast path), the others
+// return at once.
+template <int NF>
 __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
                                                const uint64_t* __restrict__ word_off,
                                                const uint32_t* __restrict__ chunk_bits, uint64_t n, int chunk,
@@ -837,6 +842,11 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
   __shared__ uint32_t offs[MAXLEN + 1];
   __shared__ uint16_t sorted[MAXDICT];
   __shared__ uint32_t ring[256 * RING_STRIDE];
+  {
+    const uint32_t nd = tab->nfast;
+    const bool mine = NF == 8 ? (nd >= 1 && nd <= 7) : NF == 12 ? (nd >= 8 && nd <= 11) : (nd == 0 || nd >= 12);
+    if (!mine) return;
+  }
   const uint32_t used = min(tab->used, (uint32_t)dict);
   for (int b = threadIdx.x; b <= MAXLEN; b += blockDim.x) {
     first[b] = tab->first[b];
@@ -883,9 +893,9 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
     // are fetched if the ring has room, so no load is waited for soon after it
     // is issued.  The ring never holds fewer than 8 unread words at a refill
     // point, and at most 8 words are read between two refill points.
-    uint32_t flen[FASTN], flim[FASTN], fdelta[FASTN];
+    uint32_t flen[NF], flim[NF], fdelta[NF];
 #pragma unroll
-    for (int j = 0; j < FASTN; ++j) {
+    for (int j = 0; j < NF; ++j) {
       flen[j] = tab->flen[j];
       flim[j] = tab->flim[j];
       fdelta[j] = tab->fdelta[j];
@@ -944,10 +954,11 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
       }
       return true;
     };
-    // one symbol: refill, length, bit buffer, lookup into s
-    auto step = [&](uint64_t i, uint32_t& s) {
-      if ((i & 7) == 4) {
-        if (pend) {
+    // the words fetched one refill point earlier go to the ring; the next
+    // eight are fetched when the ring has room (every eighth symbol, before
+    // symbol i with i % 8 == 4)
+    auto refill = [&]() {
+      if (pend) {
           const uint4 va = shift_group(pa, sha), vb = shift_group(pb, shb);
           myring[wr & (RING - 1)] = va.x;
           myring[(wr + 1) & (RING - 1)] = va.y;
@@ -966,7 +977,9 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
           fetch_at += 8;
           pend = true;
         }
-      }
+          };
+    // one symbol: length, bit buffer, lookup into s
+    auto step = [&](uint32_t& s) {
       // top up the buffer to at least 32 bits (branch-free; the ring slot is
       // re-read when no word was taken)
       {
@@ -980,7 +993,7 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
       const uint32_t top = (uint32_t)(buf >> 32);
       uint32_t L = flen[0], d = fdelta[0];
 #pragma unroll
-      for (int j = 0; j + 1 < FASTN; ++j) {
+      for (int j = 0; j + 1 < NF; ++j) {
         const bool past = top > flim[j];
         L = past ? flen[j + 1] : L;
         d = past ? fdelta[j + 1] : d;
@@ -994,24 +1007,43 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
       bad |= (!ok || cons > nb32) ? 1u : 0u;
       s = sorted[ok ? idx : 0];
     };
-    // two symbols per trip, in two registers, so a lookup is consumed one
-    // step after it is issued without a register copy of a pending load
+    auto pack_in = [&](uint32_t s) { pack = (pack >> 16) | ((uint64_t)s << 48); };
+    // Eight symbols per trip, alternating between two registers, so a lookup
+    // is consumed one step after it is issued without copying a pending load.
     uint32_t s0 = 0, s1 = 0;
-    uint64_t i = 0;
-    for (; i + 2 <= cntk; i += 2) {
-      step(i, s0);
-      if (i > 0 && !put(i - 1, s1)) return;
-      step(i + 1, s1);
-      if (!put(i, s0)) return;
+    uint64_t i0 = 0;
+    for (; i0 + 8 <= cntk; i0 += 8) {
+      step(s0);
+      if (i0 > 0 && !put(i0 - 1, s1)) return;
+      step(s1);
+      pack_in(s0);
+      step(s0);
+      pack_in(s1);
+      step(s1);
+      pack_in(s0);
+      refill();
+      step(s0);
+      pack_in(s1);
+      prev = pack;
+      step(s1);
+      pack_in(s0);
+      step(s0);
+      pack_in(s1);
+      step(s1);
+      pack_in(s0);
     }
-    if (i < cntk) {  // odd count: the last symbol goes to s0
-      step(i, s0);
-      if (i > 0 && !put(i - 1, s1)) return;
-      sp = s0;
-    } else {
-      sp = s1;
+    // fewer than eight left (the stream's last chunk): one symbol at a time
+    bool held = i0 > 0;
+    sp = s1;
+    for (uint64_t i = i0; i < cntk; ++i) {
+      if ((i & 7) == 4) refill();
+      uint32_t s;
+      step(s);
+      if (held && !put(i - 1, sp)) return;
+      sp = s;
+      held = true;
     }
-    if (cntk > 0 && !put(cntk - 1, sp)) return;
+    if (held && !put(cntk - 1, sp)) return;
     if (bad) {
       atomicOr(status, 1u);
       return;
@@ -1211,8 +1243,16 @@ void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const u
   if (nch) {
     const unsigned blocks = (unsigned)((nch + 255) / 256);
     KernelTimer kt("decode", st);
-    hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits, n,
+    // one of the three instances decodes (chosen on the device by the table's
+    // number of distinct code lengths); the others return at once
+    hipLaunchKernelGGL(k_decode<8>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits, n,
                        chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, escapes ? epos : nullptr,
+                       d_status);
+    hipLaunchKernelGGL(k_decode<12>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits,
+                       n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, escapes ? epos : nullptr,
+                       d_status);
+    hipLaunchKernelGGL(k_decode<16>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits,
+                       n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, escapes ? epos : nullptr,
                        d_status);
   }
   if (escapes && n_out) {

@@ -212,7 +212,7 @@ struct RestrictW {
 
 // MODE 1: quantize into sym/qside; MODE 0: write float coefficients to cstream.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* __restrict__ ucoarse,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2))) k3_coeff_r21(const T* __restrict__ u, T* __restrict__ ucoarse,
                                                    T* __restrict__ g1, uint16_t* __restrict__ sym,
                                                    int64_t* __restrict__ qside, T* __restrict__ cstream,
                                                    const double* __restrict__ bins, int level, int R, Lv3<T> p,
@@ -220,7 +220,6 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   __shared__ T U[FY * PX];
   __shared__ T BA[FY * PX];
   __shared__ T BB[FY * PX];
-  __shared__ T G2[FY * 64];
   __shared__ T W1s[5 * FY + 2 * CY];
   __shared__ uint64_t subs[8][4];
   __shared__ uint64_t rb[FY][2];  // stream row bases of the committed plane (dim-2 parity 0 / 1)
@@ -239,7 +238,9 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   const TileW<T> w1 = stage_weights<T, FY, CY>(W1s, p.d1, F1, J1, n1, p.c1);
 
   // this thread's column and rows
-  const int x = t & (PX - 1), h = t >> 7;
+  // h and g4 are the same for every lane of a wavefront (128 and 64 lanes per
+  // value): made scalar, every row quantity below is a scalar too
+  const int x = t & (PX - 1), h = __builtin_amdgcn_readfirstlane(t >> 7);
   const int r0 = h * HR, nr = h ? FY - HR : HR;
   const int f2 = F2 + x;
   const bool colok = x < FX && f2 >= 0 && f2 < n2;
@@ -249,7 +250,7 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
   const uint64_t i2 = e2 ? (uint64_t)(f2 >> 1) : (uint64_t)cidx(f2);
   const int f2c = min(max(f2, 0), n2 - 1);
   // this thread's restriction along dim 2: coarse column jx, rows g, g+4, ...
-  const int jx = t & 63, g4 = t >> 6;
+  const int jx = t & 63, g4 = __builtin_amdgcn_readfirstlane(t >> 6);
   const int j2 = J2 + jx;
   const bool ok2 = jx < CX && j2 < p.c2;
   RestrictW<T> rw2;
@@ -326,12 +327,26 @@ __global__ void __launch_bounds__(NT) k3_coeff_r21(const T* __restrict__ u, T* _
       }
     }
     __syncthreads();
-    // mass + restriction along dim 2 for every row of the tile
-    for (int r = g4; r < FY; r += 4) {
-      const int f1 = F1 + r;
-      if (f1 < 0 || f1 >= n1 || !ok2) continue;
-      const T* row = U + r * PX - F2;  // row[f2] for fine f2 inside the tile
-      G2[r * 64 + jx] = rw2.apply([&](int i) { return row[i]; });
+    // mass + restriction along dim 2 for every row of the tile, held in
+    // registers until every lane is done reading U, then stored in U's place
+    // (rows of 64: G2[r * 64 + jx])
+    constexpr int R2N = (FY + 3) / 4;
+    T g2v[R2N];
+#pragma unroll
+    for (int k = 0; k < R2N; ++k) {
+      const int r = g4 + 4 * k, f1 = F1 + r;
+      g2v[k] = T(0);
+      if (r < FY && f1 >= 0 && f1 < n1 && ok2) {
+        const T* row = U + r * PX - F2;  // row[f2] for fine f2 inside the tile
+        g2v[k] = rw2.apply([&](int i) { return row[i]; });
+      }
+    }
+    __syncthreads();
+    T* G2 = U;
+#pragma unroll
+    for (int k = 0; k < R2N; ++k) {
+      const int r = g4 + 4 * k, f1 = F1 + r;
+      if (r < FY && f1 >= 0 && f1 < n1 && ok2) G2[r * 64 + jx] = g2v[k];
     }
     __syncthreads();
     // mass + restriction along dim 1 -> g1
