@@ -27,10 +27,6 @@ namespace mg {
 namespace {
 
 constexpr int NT = 256;             // threads per block
-constexpr int TY = 8, TX = 64;      // coarse outputs per tile in dims 1 and 2
-constexpr int RY = 2 * TY + 3;      // fine rows of a tile (with a halo of 2)
-constexpr int RX = 2 * TX + 3;      // fine columns of a tile
-constexpr int PER = (RY * RX + NT - 1) / NT;  // tile elements per thread
 constexpr int AXPY_LDS = 65536;     // bytes of LDS for the contiguous-dimension solve
 
 __device__ inline bool is_new(int f, int n) { return (f & 1) && f < n - 1; }
@@ -619,70 +615,127 @@ __global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T*
 }
 
 // ------------------------------------------------------------------ recomposition
-// coefficients of each fine plane from the stream (zeros at coarse nodes), then R2, R1 -> g1
+// Coefficients of each fine plane from the stream (zeros at coarse nodes),
+// then mass + restriction along dim 2 and dim 1 -> g1.  Same tile layout as
+// the decomposition kernel: thread t owns fine column t % 128 and half of the
+// rows (scalar per wavefront); the symbols of the next plane are loaded into
+// registers while the current one is restricted.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(NT) k3_scatter_r21(const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside,
-                                                     const T* __restrict__ cstream, const double* __restrict__ bins,
-                                                     int level, int R, T* __restrict__ g1, Lv3<T> p, int planes_per) {
-  __shared__ T U[RY * RX];
-  __shared__ T G2[RY * TX];
-  __shared__ T W2s[5 * RX + 2 * TX];
-  __shared__ T W1s[5 * RY + 2 * TY];
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2)))
+k3_scatter_r21(const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside, const T* __restrict__ cstream,
+               const double* __restrict__ bins, int level, int R, T* __restrict__ g1, Lv3<T> p, int planes_per) {
+  __shared__ T U[FY * PX];
+  __shared__ T W1s[5 * FY + 2 * CY];
   __shared__ uint64_t subs[8][4];
-  __shared__ uint64_t rb[2][RY][2];  // row bases of the current and the next plane
+  __shared__ uint64_t rb[2][FY][2];
   const int t = threadIdx.x;
-  const int J1 = blockIdx.y * TY, J2 = blockIdx.x * TX;
+  const int J1 = blockIdx.y * CY, J2 = blockIdx.x * CX;
   const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
   const int n0 = p.n0, n1 = p.n1, n2 = p.n2;
   const double b = MODE == 1 ? bins[level] : 0.0;
   load_sub(subs, p.sub, p.level_off);
-  const TileW<T> w2 = stage_weights<T, RX, TX>(W2s, p.d2, F2, J2, n2, p.c2);
-  const TileW<T> w1 = stage_weights<T, RY, TY>(W1s, p.d1, F1, J1, n1, p.c1);
-  __syncthreads();
+  const TileW<T> w1 = stage_weights<T, FY, CY>(W1s, p.d1, F1, J1, n1, p.c1);
+  const int x = t & (PX - 1), h = __builtin_amdgcn_readfirstlane(t >> 7);
+  const int r0 = h * HR, nr = h ? FY - HR : HR;
+  const int f2 = F2 + x;
+  const bool colok = x < FX && f2 >= 0 && f2 < n2;
+  const bool e2 = colok && is_new(f2, n2);
+  const uint64_t i2 = e2 ? (uint64_t)(f2 >> 1) : (uint64_t)cidx(f2);
+  const int jx = t & 63, g4 = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int j2 = J2 + jx;
+  const bool ok2 = jx < CX && j2 < p.c2;
+  RestrictW<T> rw2;
+  if (ok2) rw2.load(j2, p.c2, n2, p.d2);
+  __syncthreads();  // subs and the staged weights
+
+  // Stream row bases of a plane (dim-2 parity 0 / 1), two planes in flight:
+  // rb[slot][r][e2] for fine row F1 + r, 0 outside the grid.
   const int fb = blockIdx.z * planes_per, fe = min(fb + planes_per, n0);
   auto bases = [&](int f0, int slot) {
-    if (t < 2 * RY && f0 < fe) {
+    if (t < 2 * FY && f0 < fe) {
       const int f1 = F1 + (t >> 1);
       rb[slot][t >> 1][t & 1] = (f1 >= 0 && f1 < n1) ? row_base(subs, f0, n0, f1, n1, t & 1) : 0;
     }
   };
-  bases(fb, 0);
-  __syncthreads();
-  for (int f0 = fb; f0 < fe; ++f0) {
-    const bool new0 = is_new(f0, n0);
-    const int slot = (f0 - fb) & 1;
-    for (int k = t; k < RY * RX; k += NT) {
-      const int r = k / RX, x = k - r * RX;
-      const int f1 = F1 + r, f2 = F2 + x;
+  // The coefficients of the next plane are loaded into registers while the
+  // current one is restricted: unconditional loads (position 0 stands in for
+  // nodes without a coefficient: outside the grid, or coarse in every
+  // dimension); their positions and presence stay in registers for the commit.
+  uint16_t sv[HR];
+  T cv[HR];
+  uint64_t pv[HR];
+  uint32_t hasm = 0;
+  auto prefetch = [&](int f0, int slot) {
+    hasm = 0;
+    const bool e0 = is_new(f0, n0);
+#pragma unroll
+    for (int j = 0; j < HR; ++j) {
+      const int r = r0 + j, f1 = F1 + r;
+      const bool rowok = j < nr && f1 >= 0 && f1 < n1;
+      const bool has = rowok && colok && (e0 || is_new(f1, n1) || e2);
+      const uint64_t pos = has ? rb[slot][rowok ? r : 0][e2 ? 1 : 0] + i2 : 0;
+      hasm |= has ? 1u << j : 0u;
+      pv[j] = pos;
+      if (MODE == 1)
+        sv[j] = sym[pos];
+      else
+        cv[j] = cstream[pos];
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int j = 0; j < HR; ++j) {
+      if (j >= nr) continue;
       T c = T(0);
-      if (f1 >= 0 && f1 < n1 && f2 >= 0 && f2 < n2) {
-        const bool e2 = is_new(f2, n2);
-        const int m = (new0 ? 1 : 0) | (is_new(f1, n1) ? 2 : 0) | (e2 ? 4 : 0);
-        if (m) {
-          const uint64_t pos = rb[slot][r][e2 ? 1 : 0] + (uint64_t)(e2 ? (f2 >> 1) : cidx(f2));
-          c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
+      if ((hasm >> j) & 1) {
+        if (MODE == 1) {
+          const double q = sv[j] ? (double)((int)sv[j] - R) : (double)qside[pv[j]];
+          c = static_cast<T>(q * b);
+        } else {
+          c = cv[j];
         }
       }
-      U[k] = c;
+      U[(r0 + j) * PX + x] = c;
     }
-    __syncthreads();
-    for (int k = t; k < RY * TX; k += NT) {
-      const int r = k / TX, jx = k - r * TX;
-      const int f1 = F1 + r, j2 = J2 + jx;
-      if (f1 < 0 || f1 >= n1 || j2 >= p.c2) continue;
-      const T* row = U + r * RX - F2;
-      G2[k] = restrict_at<T>(j2, p.c2, n2, w2, [&](int i) { return row[i]; });
-    }
-    __syncthreads();
-    for (int k = t; k < TY * TX; k += NT) {
-      const int jy = k / TX, jx = k - jy * TX;
-      const int j1 = J1 + jy, j2 = J2 + jx;
-      if (j1 >= p.c1 || j2 >= p.c2) continue;
-      const T* col = G2 + jx - F1 * TX;
-      g1[((uint64_t)f0 * p.c1 + j1) * p.c2 + j2] =
-          restrict_at<T>(j1, p.c1, n1, w1, [&](int i) { return col[i * TX]; });
-    }
+  };
+  bases(fb, 0);
+  __syncthreads();
+  if (fb < fe) prefetch(fb, 0);
+  for (int f0 = fb; f0 < fe; ++f0) {
+    const int slot = (f0 - fb) & 1;
+    commit();
     bases(f0 + 1, slot ^ 1);
+    __syncthreads();
+    if (f0 + 1 < fe) prefetch(f0 + 1, slot ^ 1);
+    // mass + restriction along dim 2 for every row of the tile, held in
+    // registers until every lane is done reading U, then stored in U's place
+    constexpr int R2N = (FY + 3) / 4;
+    T g2v[R2N];
+#pragma unroll
+    for (int k = 0; k < R2N; ++k) {
+      const int r = g4 + 4 * k, f1 = F1 + r;
+      g2v[k] = T(0);
+      if (r < FY && f1 >= 0 && f1 < n1 && ok2) {
+        const T* row = U + r * PX - F2;  // row[f2] for fine f2 inside the tile
+        g2v[k] = rw2.apply([&](int i) { return row[i]; });
+      }
+    }
+    __syncthreads();
+    T* G2 = U;
+#pragma unroll
+    for (int k = 0; k < R2N; ++k) {
+      const int r = g4 + 4 * k, f1 = F1 + r;
+      if (r < FY && f1 >= 0 && f1 < n1 && ok2) G2[r * 64 + jx] = g2v[k];
+    }
+    __syncthreads();
+    // mass + restriction along dim 1 -> g1
+    for (int jy = g4; jy < CY; jy += 4) {
+      const int j1 = J1 + jy;
+      if (j1 >= p.c1 || !ok2) continue;
+      const T* col = G2 + jx - F1 * 64;  // col[f1 * 64]
+      const T f = restrict_at<T>(j1, p.c1, n1, w1, [&](int i) { return col[i * 64]; });
+      g1[((uint64_t)f0 * p.c1 + j1) * p.c2 + j2] = f;
+    }
     __syncthreads();
   }
 }
@@ -926,12 +979,12 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
   Lv3<T> p = lv3<T>(h, l, table);
   const bool fine = l == h.L;
   // fine planes per block: about 2048 blocks, at most 8 planes each, unless tuned
-  const uint64_t tiles = (uint64_t)((p.c2 + TX - 1) / TX) * ((p.c1 + TY - 1) / TY);
+  const uint64_t tiles = (uint64_t)((p.c2 + CX - 1) / CX) * ((p.c1 + CY - 1) / CY);
   const int guess = (int)std::max<uint64_t>(1, std::min<uint64_t>(8, (uint64_t)p.n0 * tiles / 2048));
   const int planes_per = std::max(1, tune_get(TUNE_SCATTER_PLANES, sizeof(T) == 8, p.n0, p.n1, p.n2, guess));
   {
     KernelTimer kt(fine ? "scatter_r21_fine" : "scatter_r21_coarse", st);
-    dim3 grid((p.c2 + TX - 1) / TX, (p.c1 + TY - 1) / TY, (p.n0 + planes_per - 1) / planes_per);
+    dim3 grid((p.c2 + CX - 1) / CX, (p.c1 + CY - 1) / CY, (p.n0 + planes_per - 1) / planes_per);
     if (q)
       hipLaunchKernelGGL((k3_scatter_r21<T, 1>), grid, dim3(NT), 0, st, q->sym, q->qside, (const T*)nullptr, q->bins,
                          l, q->R, g1, p, planes_per);
