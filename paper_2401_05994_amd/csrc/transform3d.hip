@@ -741,44 +741,44 @@ k3_scatter_r21(const uint16_t* __restrict__ sym, const int64_t* __restrict__ qsi
 }
 
 // u_l = c + Pi(uc) at new nodes, uc at coarse nodes; Pi nested with dim 2 innermost.
-// A block covers IA_ROWS fine rows of one plane and a tile of xt column pairs
-// (2q, 2q+1): column 2q is coarse along dim 2 and column 2q+1 is new (or, for
-// an even side, the last coarse column), so the pair shares its coarse values
-// q and q+1.  The coarse rows the block interpolates from (at most IA_CR per
-// coarse plane, at most two planes) are staged in LDS once; each lane issues
-// the symbol loads of all its (row, pair) items before any arithmetic.
+// A block covers IA_ROWS fine rows of one plane and IA_XP column pairs
+// (2q, 2q+1) with 2q+1 < n2: column 2q is coarse along dim 2 and column 2q+1
+// is new (or, for an even side, the last coarse column).  Lane t owns pair
+// X0 + t for every row, so its dim-2 weights are registers and every row
+// quantity is the same across a wavefront; for an odd side the lane with the
+// last pair also writes the last column (coarse, unpaired).  The coarse rows
+// the block interpolates from (at most IA_CR per coarse plane, at most two
+// planes) are staged in LDS; each lane loads the symbols of all its rows
+// before any arithmetic.
 constexpr int IA_ROWS = 8;
 constexpr int IA_CR = IA_ROWS / 2 + 1;
-constexpr int IA_XP = 320;                                 // column pairs per block at most
-constexpr int IA_IT = (IA_ROWS * IA_XP + NT - 1) / NT;     // items per lane at most
+constexpr int IA_XP = NT;  // column pairs per block
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T* __restrict__ uc,
                                                     const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside,
                                                     const T* __restrict__ cstream, const double* __restrict__ bins,
-                                                    int level, int R, Lv3<T> p, int xt) {
+                                                    int level, int R, Lv3<T> p) {
   __shared__ T Cs[2][IA_CR][IA_XP + 1];
-  __shared__ T W2s[2][IA_XP];  // dim-2 weights of the tile's new columns 2q + 1
   __shared__ uint64_t subs[8][4];
   __shared__ uint64_t rb0[IA_ROWS], rb1[IA_ROWS], obs[IA_ROWS];
   __shared__ T w1s[IA_ROWS][2];
-  __shared__ int kbs[IA_ROWS], e1s[IA_ROWS];
+  __shared__ int kbs[IA_ROWS];
   const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
   const int t = threadIdx.x;
   const int f0 = blockIdx.z;
   const int R0 = blockIdx.y * IA_ROWS;
   const int nrow = min(IA_ROWS, n1 - R0);
-  const int X0 = blockIdx.x * xt;                // first pair (= first coarse column) of the tile
-  const int pairs = (n2 + 1) >> 1;               // column pairs per row; the last may hold one column
-  const int np = min(xt, pairs - X0);
-  const int items = nrow * np;
+  const int npairs = n2 >> 1;
+  const int X0 = blockIdx.x * IA_XP;           // first pair (= first coarse column) of the tile
+  const int np = min(IA_XP, npairs - X0);
+  const int ncol = min(np + 1, c2 - X0);       // coarse columns X0 .. X0 + ncol - 1
   const bool e0 = is_new(f0, n0);
   const int q0 = e0 ? (f0 >> 1) : cidx(f0);
-  const int lo = cidx(R0);                       // R0 is even: a coarse row
+  const int lo = cidx(R0);                     // R0 is even: a coarse row
   const int last = R0 + nrow - 1;
   const int hi = is_new(last, n1) ? (last >> 1) + 1 : cidx(last);
   const int ncr = hi - lo + 1;
-  const int ncol = min(np + 1, c2 - X0);         // coarse columns X0 .. X0 + ncol - 1
   load_sub(subs, p.sub, p.level_off);
   __syncthreads();
   if (t < nrow) {
@@ -790,46 +790,34 @@ __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T
     w1s[t][0] = e1 ? p.d1.wl[f1] : T(0);
     w1s[t][1] = e1 ? p.d1.wr[f1] : T(0);
     kbs[t] = (e1 ? (f1 >> 1) : cidx(f1)) - lo;
-    e1s[t] = e1 ? 1 : 0;
   }
+  // this lane's pair, its dim-2 weights, and whether it also owns the last column
+  const int q = t, qq = X0 + q;
+  const bool live = q < np;
+  const int fa = 2 * qq, fb = fa + 1;
+  const bool nb = live && is_new(fb, n2);
+  const T wl2 = nb ? p.d2.wl[fb] : T(0), wr2 = nb ? p.d2.wr[fb] : T(0);
+  const bool extra = live && (n2 & 1) && qq == npairs - 1;  // column n2 - 1 = fb + 1
   __syncthreads();
-  const double b = MODE == 1 ? bins[level] : 0.0;
-  const T w0l = e0 ? p.d0.wl[f0] : T(0), w0r = e0 ? p.d0.wr[f0] : T(0);
-
-  // items: e = t + it * NT -> (row e / np, pair e % np), advanced incrementally
-  int ir[IA_IT], iq[IA_IT];
-  {
-    int r = t / np, q = t - (t / np) * np;
+  // symbols (or float coefficients) of every row: column fa, column fb, and the extra column
+  uint16_t sa[IA_ROWS], sb[IA_ROWS], sx[IA_ROWS];
+  T ca[IA_ROWS], cb[IA_ROWS], cx[IA_ROWS];
 #pragma unroll
-    for (int it = 0; it < IA_IT; ++it) {
-      ir[it] = r;
-      iq[it] = q;
-      q += NT;
-      while (q >= np) {
-        q -= np;
-        ++r;
+  for (int r = 0; r < IA_ROWS; ++r) {
+    sa[r] = sb[r] = sx[r] = 0;
+    ca[r] = cb[r] = cx[r] = T(0);
+    if (r >= nrow || !live) continue;
+    const bool e1 = is_new(R0 + r, n1);
+    if (e0 || e1) {
+      const uint64_t pa = rb0[r] + (uint64_t)qq;
+      if (MODE == 1) sa[r] = sym[pa]; else ca[r] = cstream[pa];
+      if (extra) {
+        if (MODE == 1) sx[r] = sym[pa + 1]; else cx[r] = cstream[pa + 1];
       }
     }
-  }
-  // symbols (or float coefficients) of every item: column 2q, then column 2q+1
-  uint16_t sa[IA_IT], sb[IA_IT];
-  T ca[IA_IT], cbv[IA_IT];
-#pragma unroll
-  for (int it = 0; it < IA_IT; ++it) {
-    sa[it] = sb[it] = 0;
-    ca[it] = cbv[it] = T(0);
-    if (t + it * NT >= items) continue;
-    const int r = ir[it], qq = X0 + iq[it];
-    const bool e1 = e1s[r] != 0;
-    const int fb = 2 * qq + 1;
-    const bool nb = is_new(fb, n2);
-    if (e0 || e1) {
-      const uint64_t pos = rb0[r] + (uint64_t)qq;
-      if (MODE == 1) sa[it] = sym[pos]; else ca[it] = cstream[pos];
-    }
-    if (fb < n2 && (nb || e0 || e1)) {
-      const uint64_t pos = nb ? rb1[r] + (uint64_t)qq : rb0[r] + (uint64_t)(qq + 1);
-      if (MODE == 1) sb[it] = sym[pos]; else cbv[it] = cstream[pos];
+    if (nb || e0 || e1) {
+      const uint64_t pb = nb ? rb1[r] + (uint64_t)qq : rb0[r] + (uint64_t)(qq + 1);
+      if (MODE == 1) sb[r] = sym[pb]; else cb[r] = cstream[pb];
     }
   }
   // coarse rows lo..hi of planes q0 (and q0 + 1 for a new plane), columns of the tile
@@ -841,52 +829,49 @@ __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T
       const int rr = rem / ncol, j = rem - rr * ncol;
       Cs[a][rr][j] = uc[((uint64_t)(q0 + a) * c1 + (uint64_t)(lo + rr)) * c2 + (uint64_t)(X0 + j)];
     }
-    for (int q = t; q < np; q += NT) {
-      const int fb = 2 * (X0 + q) + 1;
-      const bool nb = is_new(fb, n2);
-      W2s[0][q] = nb ? p.d2.wl[fb] : T(0);
-      W2s[1][q] = nb ? p.d2.wr[fb] : T(0);
-    }
   }
   __syncthreads();
+  if (!live) return;
+  const double b = MODE == 1 ? bins[level] : 0.0;
+  const T w0l = e0 ? p.d0.wl[f0] : T(0), w0r = e0 ? p.d0.wr[f0] : T(0);
+  auto coef = [&](uint16_t s, T cf, uint64_t pos) -> T {
+    if (MODE == 0) return cf;
+    const double qv = s ? (double)((int)s - R) : (double)qside[pos];
+    return static_cast<T>(qv * b);
+  };
 #pragma unroll
-  for (int it = 0; it < IA_IT; ++it) {
-    if (t + it * NT >= items) continue;
-    const int r = ir[it], q = iq[it], qq = X0 + q;
-    const bool e1 = e1s[r] != 0;
+  for (int r = 0; r < IA_ROWS; ++r) {
+    if (r >= nrow) continue;
+    const bool e1 = is_new(R0 + r, n1);
     const int kb = kbs[r];
-    const int fa = 2 * qq, fb = fa + 1;
-    const bool has_b = fb < n2;
-    const bool nb = is_new(fb, n2);
-    const T wl2 = W2s[0][q], wr2 = W2s[1][q];
     const T w1l = w1s[r][0], w1r = w1s[r][1];
-    auto Va = [&](int a, int bb) -> T { return Cs[a][kb + bb][q]; };
+    // coarse value of plane choice a, row choice bb, coarse column qc (tile-relative)
+    auto V = [&](int a, int bb, int qc) -> T { return Cs[a][kb + bb][qc]; };
+    auto Va = [&](int a, int bb) -> T { return V(a, bb, q); };
     auto Vb = [&](int a, int bb) -> T {
-      if (nb) return wl2 * Cs[a][kb + bb][q] + wr2 * Cs[a][kb + bb][q + 1];
-      return Cs[a][kb + bb][q + 1];
+      if (nb) return wl2 * V(a, bb, q) + wr2 * V(a, bb, q + 1);
+      return V(a, bb, q + 1);
     };
-    auto Wa = [&](int a) -> T { return e1 ? w1l * Va(a, 0) + w1r * Va(a, 1) : Va(a, 0); };
-    auto Wb = [&](int a) -> T { return e1 ? w1l * Vb(a, 0) + w1r * Vb(a, 1) : Vb(a, 0); };
-    auto coef = [&](uint16_t s, T cf, uint64_t pos) -> T {
-      if (MODE == 0) return cf;
-      const double qv = s ? (double)((int)s - R) : (double)qside[pos];
-      return static_cast<T>(qv * b);
-    };
+    auto Vx = [&](int a, int bb) -> T { return V(a, bb, q + 1); };
+    auto W = [&](auto&& Vf, int a) -> T { return e1 ? w1l * Vf(a, 0) + w1r * Vf(a, 1) : Vf(a, 0); };
+    auto PI = [&](auto&& Vf) -> T { return e0 ? w0l * W(Vf, 0) + w0r * W(Vf, 1) : W(Vf, 0); };
     const uint64_t o = obs[r] + fa;
-    if (!e0 && !e1) {
+    // column fa: coarse along dim 2
+    if (!e0 && !e1)
       out[o] = Cs[0][kb][q];
-    } else {
-      const T pi = e0 ? w0l * Wa(0) + w0r * Wa(1) : Wa(0);
-      out[o] = coef(sa[it], ca[it], rb0[r] + (uint64_t)qq) + pi;
-    }
-    if (has_b) {
-      if (!nb && !e0 && !e1) {
-        out[o + 1] = Cs[0][kb][q + 1];
-      } else {
-        const T pi = e0 ? w0l * Wb(0) + w0r * Wb(1) : Wb(0);
-        const uint64_t pos = nb ? rb1[r] + (uint64_t)qq : rb0[r] + (uint64_t)(qq + 1);
-        out[o + 1] = coef(sb[it], cbv[it], pos) + pi;
-      }
+    else
+      out[o] = coef(sa[r], ca[r], rb0[r] + (uint64_t)qq) + PI(Va);
+    // column fb: new along dim 2, or the last (coarse) column of an even side
+    if (!nb && !e0 && !e1)
+      out[o + 1] = Cs[0][kb][q + 1];
+    else
+      out[o + 1] = coef(sb[r], cb[r], nb ? rb1[r] + (uint64_t)qq : rb0[r] + (uint64_t)(qq + 1)) + PI(Vb);
+    // the last column of an odd side (coarse along dim 2)
+    if (extra) {
+      if (!e0 && !e1)
+        out[o + 2] = Cs[0][kb][q + 1];
+      else
+        out[o + 2] = coef(sx[r], cx[r], rb0[r] + (uint64_t)(qq + 1)) + PI(Vx);
     }
   }
 }
@@ -1012,17 +997,14 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
   }
   {
     KernelTimer kt(fine ? "interp_add3_fine" : "interp_add3_coarse", st);
-    // column pairs per block: the fewest tiles of at most IA_XP pairs, balanced
-    const int pairs = (p.n2 + 1) / 2;
-    const int ntx = (pairs + IA_XP - 1) / IA_XP;
-    const int xt = (pairs + ntx - 1) / ntx;
-    dim3 grid((unsigned)((pairs + xt - 1) / xt), (unsigned)((p.n1 + IA_ROWS - 1) / IA_ROWS), (unsigned)p.n0);
+    const int npairs = p.n2 / 2;
+    dim3 grid((unsigned)((npairs + IA_XP - 1) / IA_XP), (unsigned)((p.n1 + IA_ROWS - 1) / IA_ROWS), (unsigned)p.n0);
     if (q)
       hipLaunchKernelGGL((k3_interp_add<T, 1>), grid, dim3(NT), 0, st, out, z, q->sym, q->qside, (const T*)nullptr,
-                         q->bins, l, q->R, p, xt);
+                         q->bins, l, q->R, p);
     else
       hipLaunchKernelGGL((k3_interp_add<T, 0>), grid, dim3(NT), 0, st, out, z, (const uint16_t*)nullptr,
-                         (const int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, xt);
+                         (const int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p);
   }
   MG_HIP(hipGetLastError());
 }
