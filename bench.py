@@ -133,6 +133,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=145)
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-field batch measurement")
+    ap.add_argument("--only-batch", action="store_true", help="run only the 256-field batch measurement")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB three times (counter calibration)")
@@ -150,6 +151,9 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.only_batch:
+        print(json.dumps({"batched": bench_batch(m, torch)}))
+        return
     if args.calib_copy > 0:
         src = torch.ones(args.calib_copy << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

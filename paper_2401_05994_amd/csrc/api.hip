@@ -356,12 +356,26 @@ constexpr int kLearnedAttempts = 2;  // learned widths tried before the plain on
 // judge's verdict between its attempts).  The static header is copied from `header` (device memory); the
 // results land in *fin_out (device) and, when size_out is given, the total
 // size in *size_out (device).
+// The buffers of one compression inside its scratch (the same carving for
+// every phase of compress_enqueue).
+struct CompressBufs {
+  void* dscratch;
+  void* learned_scratch;
+  uint16_t* sym;
+  int64_t* qside;
+  double* bins;
+  double* scalars;
+  uint64_t* misc;  // [0] max bits, [1] outlier byte offset, [2] status
+  uint64_t* hist;
+  uint64_t* codes;
+  uint64_t* word_off;
+  uint64_t* esc_off;
+  Finale* fin;
+  void* enc_scratch;
+};
+
 template <typename T>
-Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double tol, const T* d_in, char* d_out,
-                         const Opts& o, void* scratch, const uint8_t* header, uint64_t header_bytes,
-                         uint64_t* size_out) {
-  const bool f64 = sizeof(T) == 8;
-  hipStream_t st = o.st;
+CompressBufs carve_compress(const Hierarchy& h, const Layout& y, const Opts& o, void* scratch) {
   const uint64_t n = h.count(h.L);
   const uint64_t nch = y.nch;
   const uint64_t dbytes = decompose_scratch_bytes<T>(h);
@@ -374,20 +388,54 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
                 carve_size<double>(MAXL + 1) + carve_size<unsigned long long>(1) + 1024
           : 0;
   Carver cv(scratch);
-  void* dscratch = cv.take<char>(dbytes);
-  void* learned_scratch = lbytes ? cv.take<char>(lbytes) : nullptr;
-  uint16_t* sym = cv.take<uint16_t>(n);
-  int64_t* qside = cv.take<int64_t>(n);
-  double* bins = cv.take<double>(MAXL + 1);
-  double* scalars = cv.take<double>(8);
-  uint64_t* misc = cv.take<uint64_t>(4);  // [0] max bits, [1] outlier byte offset, [2] status
-  uint64_t* hist = cv.take<uint64_t>((uint64_t)o.dict);
-  uint64_t* codes = cv.take<uint64_t>((uint64_t)o.dict);
-  uint64_t* word_off = cv.take<uint64_t>(nch + 1);
-  uint64_t* esc_off = cv.take<uint64_t>(nch + 1);
-  Finale* fin = cv.take<Finale>(1);
-  void* enc_scratch = cv.take<char>(encode_scratch_bytes(o.dict));
+  CompressBufs b;
+  b.dscratch = cv.take<char>(dbytes);
+  b.learned_scratch = lbytes ? cv.take<char>(lbytes) : nullptr;
+  b.sym = cv.take<uint16_t>(n);
+  b.qside = cv.take<int64_t>(n);
+  b.bins = cv.take<double>(MAXL + 1);
+  b.scalars = cv.take<double>(8);
+  b.misc = cv.take<uint64_t>(4);
+  b.hist = cv.take<uint64_t>((uint64_t)o.dict);
+  b.codes = cv.take<uint64_t>((uint64_t)o.dict);
+  b.word_off = cv.take<uint64_t>(nch + 1);
+  b.esc_off = cv.take<uint64_t>(nch + 1);
+  b.fin = cv.take<Finale>(1);
+  b.enc_scratch = cv.take<char>(encode_scratch_bytes(o.dict));
+  return b;
+}
 
+// Phases: CE_ALL runs the whole compression; CE_FRONT stops after the
+// histogram and CE_BACK runs from the chunk bit counts on, so a batch can
+// build the codebooks of all its fields in one launch in between.
+enum { CE_ALL = 0, CE_FRONT = 1, CE_BACK = 2 };
+
+template <typename T>
+Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double tol, const T* d_in, char* d_out,
+                         const Opts& o, void* scratch, const uint8_t* header, uint64_t header_bytes,
+                         uint64_t* size_out, int phase = CE_ALL) {
+  const bool f64 = sizeof(T) == 8;
+  hipStream_t st = o.st;
+  const uint64_t n = h.count(h.L);
+  const uint64_t nch = y.nch;
+  const CompressBufs cb = carve_compress<T>(h, y, o, scratch);
+  void* dscratch = cb.dscratch;
+  void* learned_scratch = cb.learned_scratch;
+  uint16_t* sym = cb.sym;
+  int64_t* qside = cb.qside;
+  double* bins = cb.bins;
+  double* scalars = cb.scalars;
+  uint64_t* misc = cb.misc;
+  uint64_t* hist = cb.hist;
+  uint64_t* codes = cb.codes;
+  uint64_t* word_off = cb.word_off;
+  uint64_t* esc_off = cb.esc_off;
+  Finale* fin = cb.fin;
+  void* enc_scratch = cb.enc_scratch;
+  uint32_t* chunk_esc = reinterpret_cast<uint32_t*>(d_out + y.chunk_esc);
+  uint32_t* chunk_bits = reinterpret_cast<uint32_t*>(d_out + y.chunk_bits);
+  uint8_t* code_len = reinterpret_cast<uint8_t*>(d_out + y.code_len);
+  if (phase != CE_BACK) {
   MG_HIP(hipMemcpyAsync(d_out, header, header_bytes, hipMemcpyDeviceToDevice, st));
   launch_fill_u64(&misc[2], 1, 0, st);
 
@@ -455,11 +503,10 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
   }
 
   // lossless stage, tables written in place
-  uint32_t* chunk_esc = reinterpret_cast<uint32_t*>(d_out + y.chunk_esc);
-  uint32_t* chunk_bits = reinterpret_cast<uint32_t*>(d_out + y.chunk_bits);
-  uint8_t* code_len = reinterpret_cast<uint8_t*>(d_out + y.code_len);
   launch_histogram(sym, n, o.dict, o.chunk, hist, chunk_esc, reinterpret_cast<uint32_t*>(&misc[2]), st);
+  if (phase == CE_FRONT) return fin;
   launch_codebook(hist, o.dict, code_len, codes, st);
+  }
   launch_chunk_bits(sym, n, o.dict, o.chunk, code_len, chunk_bits, st);
   launch_scan_words(chunk_bits, nch, word_off, st);
   launch_scan_u32(chunk_esc, nch, esc_off, st);
@@ -757,16 +804,27 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
     uint64_t out_total = 0, mem_total = 0;
     std::vector<BatchJob> jobs = plan_jobs(nfields, fields, tol, o, true, &out_total, &mem_total);
     if (out_capacity < out_total) fail(MGARD_ERR_CAPACITY, "output capacity below mgard_batch_bound");
+    // the codebook jobs of all fields (one grouped launch) sit after the fields' scratch
+    const uint64_t jobs_off = align256(mem_total);
+    mem_total = jobs_off + (uint64_t)nfields * sizeof(CodebookJob);
     if (hipMalloc(&B->mem, std::max<uint64_t>(mem_total, 256)) != hipSuccess) {
       (void)hipGetLastError();
       B->mem = nullptr;
       fail(MGARD_ERR_OOM, "batch scratch");
     }
     char* mem = static_cast<char*>(B->mem);
+    std::vector<CodebookJob> cjobs(nfields);
     for (uint32_t i = 0; i < nfields; ++i) {
       MG_HIP(hipMemcpy(mem + jobs[i].hdr_off, jobs[i].hb.data(), jobs[i].hb.size(), hipMemcpyHostToDevice));
       h_offsets[i] = jobs[i].out_off;
+      const BatchJob& J = jobs[i];
+      const CompressBufs cb = J.f64 ? carve_compress<double>(*J.h, J.y, o, mem + J.scr_off)
+                                    : carve_compress<float>(*J.h, J.y, o, mem + J.scr_off);
+      cjobs[i] = CodebookJob{cb.hist, reinterpret_cast<uint8_t*>(static_cast<char*>(d_out) + J.out_off + J.y.code_len),
+                             cb.codes};
     }
+    const CodebookJob* d_cjobs = reinterpret_cast<const CodebookJob*>(mem + jobs_off);
+    MG_HIP(hipMemcpy(mem + jobs_off, cjobs.data(), nfields * sizeof(CodebookJob), hipMemcpyHostToDevice));
     // launch shapes for every level shape not tuned yet
     for (uint32_t i = 0; i < nfields; ++i) {
       Hierarchy& h = *jobs[i].h;
@@ -800,25 +858,33 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
       try {
         MG_HIP(hipEventRecord(ev[K], cs));
         for (int k = 0; k < K; ++k) MG_HIP(hipStreamWaitEvent(ss[k], ev[K], 0));
-        for (uint32_t i = 0; i < nfields; ++i) {
-          const BatchJob& J = jobs[i];
-          Opts oi = o;
-          oi.st = ss[i % K];
-          char* out = static_cast<char*>(d_out) + J.out_off;
-          const uint8_t* hdr = reinterpret_cast<const uint8_t*>(mem + J.hdr_off);
-          if (J.f64)
-            compress_enqueue<double>(*J.h, static_cast<const double*>(J.table), J.y, tol,
-                                     static_cast<const double*>(fields[i].d_in), out, oi, mem + J.scr_off, hdr,
-                                     J.hb.size(), d_sizes + i);
-          else
-            compress_enqueue<float>(*J.h, static_cast<const float*>(J.table), J.y, tol,
-                                    static_cast<const float*>(fields[i].d_in), out, oi, mem + J.scr_off, hdr,
-                                    J.hb.size(), d_sizes + i);
-        }
-        for (int k = 0; k < K; ++k) {
-          MG_HIP(hipEventRecord(ev[k], ss[k]));
-          MG_HIP(hipStreamWaitEvent(cs, ev[k], 0));
-        }
+        // every field up to its histogram, all codebooks in one launch, then the rest
+        auto enqueue = [&](int phase) {
+          for (uint32_t i = 0; i < nfields; ++i) {
+            const BatchJob& J = jobs[i];
+            Opts oi = o;
+            oi.st = ss[i % K];
+            char* out = static_cast<char*>(d_out) + J.out_off;
+            const uint8_t* hdr = reinterpret_cast<const uint8_t*>(mem + J.hdr_off);
+            if (J.f64)
+              compress_enqueue<double>(*J.h, static_cast<const double*>(J.table), J.y, tol,
+                                       static_cast<const double*>(fields[i].d_in), out, oi, mem + J.scr_off, hdr,
+                                       J.hb.size(), d_sizes + i, phase);
+            else
+              compress_enqueue<float>(*J.h, static_cast<const float*>(J.table), J.y, tol,
+                                      static_cast<const float*>(fields[i].d_in), out, oi, mem + J.scr_off, hdr,
+                                      J.hb.size(), d_sizes + i, phase);
+          }
+          for (int k = 0; k < K; ++k) {
+            MG_HIP(hipEventRecord(ev[k], ss[k]));
+            MG_HIP(hipStreamWaitEvent(cs, ev[k], 0));
+          }
+        };
+        enqueue(CE_FRONT);
+        launch_codebook_group(d_cjobs, nfields, o.dict, cs);
+        MG_HIP(hipEventRecord(ev[K], cs));
+        for (int k = 0; k < K; ++k) MG_HIP(hipStreamWaitEvent(ss[k], ev[K], 0));
+        enqueue(CE_BACK);
         MG_HIP(hipStreamEndCapture(cs, &B->graph));
       } catch (...) {
         hipGraph_t g = nullptr;

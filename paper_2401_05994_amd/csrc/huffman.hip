@@ -166,8 +166,8 @@ __device__ inline int merge_split(const uint64_t* keys, int n, int K, int p) {
 // batches (see below); internal-node depths come from pointer jumping, leaf
 // lengths from the number of leaves per depth (deepest for the smallest
 // weights), canonical codes from per-length ranks in symbol order.
-__global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ hist, int dict,
-                                                   uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
+__device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist, int dict,
+                                               uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
   __shared__ uint64_t keys[MAXDICT];
   __shared__ uint16_t syms[MAXDICT];
   __shared__ uint16_t par[MAXDICT];  // parents, then canonical ranks
@@ -382,6 +382,17 @@ __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ 
     len_out[s] = (uint8_t)L;
     codes[s] = L ? first[L] + (uint64_t)par[s] : 0ull;
   }
+}
+
+__global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ hist, int dict,
+                                                   uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
+  codebook_block(hist, dict, len_out, codes);
+}
+
+// One codebook per block: the codebooks of a batch's fields in one launch.
+__global__ void __launch_bounds__(1024) k_codebook_group(const CodebookJob* __restrict__ jobs, int dict) {
+  const CodebookJob j = jobs[blockIdx.x];
+  codebook_block(j.hist, dict, j.len, j.codes);
 }
 
 // ------------------------------------------------------------------ chunk sizes
@@ -1174,6 +1185,13 @@ void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint
 void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes, hipStream_t st) {
   KernelTimer kt("codebook", st);
   hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, dict, len, codes);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_codebook_group(const CodebookJob* jobs, uint32_t njobs, int dict, hipStream_t st) {
+  if (!njobs) return;
+  KernelTimer kt("codebook", st);
+  hipLaunchKernelGGL(k_codebook_group, dim3(njobs), dim3(1024), 0, st, jobs, dict);
   MG_HIP(hipGetLastError());
 }
 

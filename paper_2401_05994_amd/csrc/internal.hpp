@@ -221,6 +221,13 @@ void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint
                       uint32_t* chunk_esc, uint32_t* status, hipStream_t st);
 void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes,
                      hipStream_t st);
+// Several codebooks in one launch (one block each): jobs is a device array.
+struct CodebookJob {
+  const uint64_t* hist;
+  uint8_t* len;
+  uint64_t* codes;
+};
+void launch_codebook_group(const CodebookJob* jobs, uint32_t njobs, int dict, hipStream_t st);
 void launch_chunk_bits(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                        uint32_t* chunk_bits, hipStream_t st);
 // exclusive scan of per-chunk words (ceil(bits/32)) -> offsets (n+1 entries, last = total)

@@ -177,17 +177,28 @@ struct RestrictW {
     c = cpos(j, nc, n);
     l = c >= 2 && !(c & 1);
     r = !(c & 1) && c < n - 2;
-    rl = l ? w.rl[j] : T(0);
-    rr = r ? w.rr[j] : T(0);
+    // every load from an index clamped into range, issued before any is
+    // used, then the values that do not apply are zeroed
+    const T vrl = w.rl[j], vrr = w.rr[j];
+    T vb[3], va[3], vd[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = min(max(c - 1 + k, 0), n - 1);
+      vb[k] = w.mb[i];
+      va[k] = w.ma[i];
+      vd[k] = w.mc[i];
+    }
+    rl = l ? vrl : T(0);
+    rr = r ? vrr : T(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int i = c - 1 + k;
       const bool in = i >= 0 && i < n && (k == 1 || (k == 0 && l) || (k == 2 && r));
       hl[k] = in && i > 0;
       hr[k] = in && i < n - 1;
-      b[k] = in ? w.mb[i] : T(0);
-      a[k] = hl[k] ? w.ma[i] : T(0);
-      d[k] = hr[k] ? w.mc[i] : T(0);
+      b[k] = in ? vb[k] : T(0);
+      a[k] = hl[k] ? va[k] : T(0);
+      d[k] = hr[k] ? vd[k] : T(0);
     }
   }
   template <typename G>
@@ -269,6 +280,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
       const int f1 = F1 + r0 + j;
       if (j < nr) U[(r0 + j) * PX + x] = (colok && f1 >= 0 && f1 < n1) ? pre[j] : T(0);
     }
+
     if (t < FY) {
       const int f1 = F1 + t;
       const bool in = f1 >= 0 && f1 < n1;
