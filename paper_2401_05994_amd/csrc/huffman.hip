@@ -185,33 +185,46 @@ __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist
   if (t == 0) nleaf = 0;
   for (int i = t; i <= MAXLEN + 1; i += nt) icount[i] = 0;
   __syncthreads();
+  // Used symbols only, as keys (count << 16 | symbol), packed in any order
+  // (one LDS atomic per wavefront); the keys are distinct, so the sort below
+  // fixes their order.
   {
-    int mine = 0;
-    for (int s = t; s < dict; s += nt) {
-      const uint64_t c = hist[s];
-      keys[s] = c ? ((c << 16) | (uint64_t)s) : ~0ull;
-      lens[s] = 0;
-      mine += c ? 1 : 0;
+    const int lane = t & 63;
+    for (int s0 = 0; s0 < dict; s0 += nt) {
+      const int s = s0 + t;
+      const uint64_t c = s < dict ? hist[s] : 0;
+      if (s < dict) lens[s] = 0;
+      const uint64_t m = __ballot(c != 0);
+      int base = 0;
+      if (lane == 0 && m) base = atomicAdd(&nleaf, __popcll(m));
+      base = __shfl(base, 0);
+      if (c) keys[base + __popcll(m & lanes_below(lane))] = (c << 16) | (uint64_t)s;
     }
-    if (mine) atomicAdd(&nleaf, mine);
   }
   __syncthreads();
-  for (int k = 2; k <= dict; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = t; i < dict; i += nt) {
-        const int p = i ^ j;
-        if (p > i) {
+  const int n = nleaf;
+  // bitonic sort of the next power of two >= n keys (padding sorts last), every
+  // thread on one compare-exchange pair per pass
+  {
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = n + t; i < P; i += nt) keys[i] = ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int q = t; q < P / 2; q += nt) {
+          const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));  // bit j of i clear
+          const int p = i | j;
           const uint64_t a = keys[i], b = keys[p];
           if ((a > b) == ((i & k) == 0)) {
             keys[i] = b;
             keys[p] = a;
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
-  const int n = nleaf;
   for (int i = t; i < n; i += nt) {
     syms[i] = (uint16_t)(keys[i] & 0xffff);
     keys[i] >>= 16;
