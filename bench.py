@@ -262,6 +262,26 @@ def main():
         "kernels_ms_per_step": {k: round(v[1] / kt_steps, 4) for k, v in sorted(rep.items())},
     }
 
+    # the learned allocation on the same field and tolerance (outside the timed region)
+    from paper_2401_05994_amd import learned as lrn
+
+    if os.path.exists(lrn.DEFAULT_MODEL):
+        params, _ = lrn.load()
+        model = m.Model(params)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        lbuf, lnb, linfo = m.mgard_compress_learned(u, args.tol, model, out=out)
+        torch.cuda.synchronize()
+        lms = (time.perf_counter() - a) * 1e3
+        lrec = m.mgard_decompress(lbuf, lnb, out=rec)
+        lerr = float((lrec - u).abs().max())
+        assert lerr <= linfo["tau_abs"], f"learned: L-infinity error {lerr} exceeds {linfo['tau_abs']}"
+        result["learned"] = {"ratio_learned": round(in_bytes / lnb, 4), "ratio_plain": round(in_bytes / nb, 4),
+                             "learned_over_plain": round(nb / lnb, 4), "fallback": int(linfo["fallback_used"]),
+                             "linf_over_tau": round(lerr / linfo["tau_abs"], 4), "compress_ms": round(lms, 2)}
+        print(f"[bench] learned: ratio {in_bytes / lnb:.3f} vs plain {in_bytes / nb:.3f}", file=sys.stderr,
+              flush=True)
+
     if not args.no_batch:
         result["batched"] = bench_batch(m, torch)
 
