@@ -311,6 +311,71 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
   }
 }
 
+// Thomas along the contiguous dimension: `rows` lines per block staged in LDS
+// (coalesced, eight loads per lane in flight), one lane per line, the same
+// arithmetic as k_thomas, then written back.  Lines sit `stride` (odd)
+// elements apart in LDS so the lanes of a wavefront fall in different banks.
+constexpr int ROWS_LDS = 65536;  // bytes
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_thomas_rows(T* __restrict__ data, uint64_t nrows, int n, int rows,
+                                                     int stride, const T* __restrict__ ta,
+                                                     const T* __restrict__ tr, const T* __restrict__ tcp) {
+  __shared__ T tile[ROWS_LDS / sizeof(T)];
+  constexpr int CP = 8;
+  const uint64_t r0 = (uint64_t)blockIdx.x * rows;
+  const int nr = (int)min((uint64_t)rows, nrows - r0);
+  const int cnt = nr * n;
+  T* g = data + r0 * (uint64_t)n;
+  for (int k0 = threadIdx.x; k0 < cnt; k0 += CP * TPB) {
+    T v[CP];
+#pragma unroll
+    for (int u = 0; u < CP; ++u) {
+      const int k = k0 + u * TPB;
+      v[u] = k < cnt ? g[k] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < CP; ++u) {
+      const int k = k0 + u * TPB;
+      if (k < cnt) tile[(k / n) * stride + k % n] = v[u];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nr) {
+    T* line = tile + threadIdx.x * stride;
+    T prev = line[0] * tr[0];
+    line[0] = prev;
+#pragma unroll 8
+    for (int i = 1; i < n; ++i) {
+      prev = (line[i] - ta[i] * prev) * tr[i];
+      line[i] = prev;
+    }
+    T x = prev;
+#pragma unroll 8
+    for (int i = n - 2; i >= 0; --i) {
+      x = line[i] - tcp[i] * x;
+      line[i] = x;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < cnt; k += TPB) g[k] = tile[(k / n) * stride + k % n];
+}
+
+// Thomas along slot s: lines of the contiguous dimension go through LDS when a
+// line fits, other dimensions use the strided kernel.
+template <typename T>
+void launch_thomas_any(T* data, uint64_t outer, int n, uint64_t inner, const DimConsts<T>& w, hipStream_t st) {
+  const int stride = n | 1;
+  if (inner == 1 && (uint64_t)stride * sizeof(T) <= (uint64_t)ROWS_LDS) {
+    const int rows = (int)std::min<uint64_t>(TPB, (uint64_t)ROWS_LDS / ((uint64_t)stride * sizeof(T)));
+    hipLaunchKernelGGL(k_thomas_rows<T>, dim3((unsigned)((outer + rows - 1) / rows)), dim3(TPB), 0, st, data, outer,
+                       n, rows, stride, w.ta, w.tr, w.tcp);
+  } else {
+    hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, data, outer, n, inner, w.ta,
+                       w.tr, w.tcp);
+  }
+}
+
 template <typename T, bool ADD>
 __global__ void __launch_bounds__(TPB) k_axpy(T* __restrict__ dst, const T* __restrict__ a,
                                               const T* __restrict__ b, uint64_t n) {
@@ -413,9 +478,7 @@ void correction(const Hierarchy& h, int l, const T* table, const T* cbar, T* buf
     for (int q = 0; q < s; ++q) outer *= (uint64_t)shp[q];
     for (int q = s + 1; q < MAXD; ++q) inner *= (uint64_t)shp[q];
     KernelTimer kt(l == h.L ? "thomas_fine" : "thomas_coarse", st);
-    const DimConsts<T> w = dim_consts<T>(h, l, s, table);
-    hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, z, outer, (int)shp[s],
-                       inner, w.ta, w.tr, w.tcp);
+    launch_thomas_any<T>(z, outer, (int)shp[s], inner, dim_consts<T>(h, l, s, table), st);
   }
   *zout = z;
 }
