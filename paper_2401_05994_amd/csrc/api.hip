@@ -505,14 +505,14 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
   // lossless stage, tables written in place
   launch_histogram(sym, n, o.dict, o.chunk, hist, chunk_esc, reinterpret_cast<uint32_t*>(&misc[2]), st);
   if (phase == CE_FRONT) return fin;
-  launch_codebook(hist, o.dict, code_len, codes, st);
+  launch_codebook(hist, o.dict, code_len, codes, enc_scratch, st);
   }
   launch_chunk_bits(sym, n, o.dict, o.chunk, code_len, chunk_bits, st);
   launch_scan_words(chunk_bits, nch, word_off, st);
   launch_scan_u32(chunk_esc, nch, esc_off, st);
   hipLaunchKernelGGL(k_outlier_offset, dim3(1), dim3(1), 0, st, word_off, nch, y.payload, &misc[1]);
   launch_encode(sym, n, o.dict, o.chunk, code_len, codes, word_off, reinterpret_cast<uint32_t*>(d_out + y.payload),
-                esc_off, qside, d_out, &misc[1], enc_scratch, st);
+                esc_off, qside, d_out, &misc[1], enc_scratch, true, st);
   hipLaunchKernelGGL(k_zero_pad, dim3(1), dim3(1), 0, st, d_out, word_off, nch, y.payload);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, d_out, word_off, esc_off, nch, &misc[1], scalars, bins,
                      h.L, y.bins, o.alloc == MGARD_ALLOC_LEARNED ? 1 : 0, fin, size_out);
@@ -820,8 +820,10 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
       const BatchJob& J = jobs[i];
       const CompressBufs cb = J.f64 ? carve_compress<double>(*J.h, J.y, o, mem + J.scr_off)
                                     : carve_compress<float>(*J.h, J.y, o, mem + J.scr_off);
+      uint32_t *enc = nullptr, *maxlen = nullptr;
+      encode_tables(cb.enc_scratch, o.dict, &enc, &maxlen);
       cjobs[i] = CodebookJob{cb.hist, reinterpret_cast<uint8_t*>(static_cast<char*>(d_out) + J.out_off + J.y.code_len),
-                             cb.codes};
+                             cb.codes, enc, maxlen};
     }
     const CodebookJob* d_cjobs = reinterpret_cast<const CodebookJob*>(mem + jobs_off);
     MG_HIP(hipMemcpy(mem + jobs_off, cjobs.data(), nfields * sizeof(CodebookJob), hipMemcpyHostToDevice));
@@ -1117,7 +1119,7 @@ mgard_status mgard_huffman_codebook(const uint64_t* d_hist, uint32_t dict_size, 
     Opts o = read_opts(opts);
     if (!d_hist || !d_code_len || !d_codes) fail(MGARD_ERR_ARG, "null buffer");
     if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
-    launch_codebook(d_hist, (int)dict_size, d_code_len, d_codes, o.st);
+    launch_codebook(d_hist, (int)dict_size, d_code_len, d_codes, nullptr, o.st);
     MG_HIP(hipStreamSynchronize(o.st));
   });
 }
@@ -1147,7 +1149,7 @@ mgard_status mgard_huffman_encode(const uint16_t* d_symbols, uint64_t n, uint32_
     *payload_words = total;
     if (total > payload_capacity) fail(MGARD_ERR_CAPACITY, "payload capacity");
     launch_encode(d_symbols, n, (int)dict_size, (int)chunk, d_code_len, d_codes, word_off, d_payload, nullptr, nullptr, nullptr,
-                  nullptr, enc_scratch, o.st);
+                  nullptr, enc_scratch, false, o.st);
     MG_HIP(hipStreamSynchronize(o.st));
   });
 }

@@ -20,6 +20,7 @@ namespace {
 constexpr int TPB = 256;
 constexpr int MAXLEN = 64;
 constexpr int MAXDICT = 8192;  // largest dictionary; all LDS below is static
+constexpr int ENC_MAXLEN = 26;
 
 // ------------------------------------------------------------------ histogram
 // Blocks of 1024 threads with a private LDS histogram; each wave takes whole
@@ -166,8 +167,12 @@ __device__ inline int merge_split(const uint64_t* keys, int n, int K, int p) {
 // batches (see below); internal-node depths come from pointer jumping, leaf
 // lengths from the number of leaves per depth (deepest for the smallest
 // weights), canonical codes from per-length ranks in symbol order.
+// When enc is given, the encoder's packed table (code << 6 | length, 0 for an
+// unused symbol or a code longer than ENC_MAXLEN) and the longest length go to
+// enc and *maxlen_out as well.
 __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist, int dict,
-                                               uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
+                                               uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes,
+                                               uint32_t* __restrict__ enc, uint32_t* __restrict__ maxlen_out) {
   __shared__ uint64_t keys[MAXDICT];
   __shared__ uint16_t syms[MAXDICT];
   __shared__ uint16_t par[MAXDICT];  // parents, then canonical ranks
@@ -390,22 +395,35 @@ __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist
     }
   }
   __syncthreads();
+  uint32_t mine = 0;
   for (int s = t; s < dict; s += nt) {
     const int L = lens[s];
+    const uint64_t c = L ? first[L] + (uint64_t)par[s] : 0ull;
     len_out[s] = (uint8_t)L;
-    codes[s] = L ? first[L] + (uint64_t)par[s] : 0ull;
+    codes[s] = c;
+    if (enc) enc[s] = (L && L <= ENC_MAXLEN) ? (uint32_t)((c << 6) | (uint64_t)L) : 0u;
+    mine = max(mine, (uint32_t)L);
+  }
+  if (enc) {
+    __shared__ uint32_t mx;
+    if (t == 0) mx = 0;
+    __syncthreads();
+    if (mine) atomicMax(&mx, mine);
+    __syncthreads();
+    if (t == 0) *maxlen_out = mx;
   }
 }
 
 __global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ hist, int dict,
-                                                   uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes) {
-  codebook_block(hist, dict, len_out, codes);
+                                                   uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes,
+                                                   uint32_t* __restrict__ enc, uint32_t* __restrict__ maxlen_out) {
+  codebook_block(hist, dict, len_out, codes, enc, maxlen_out);
 }
 
 // One codebook per block: the codebooks of a batch's fields in one launch.
 __global__ void __launch_bounds__(1024) k_codebook_group(const CodebookJob* __restrict__ jobs, int dict) {
   const CodebookJob j = jobs[blockIdx.x];
-  codebook_block(j.hist, dict, j.len, j.codes);
+  codebook_block(j.hist, dict, j.len, j.codes, j.enc, j.maxlen);
 }
 
 // ------------------------------------------------------------------ chunk sizes
@@ -530,9 +548,9 @@ void launch_scan(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st) {
 
 // ------------------------------------------------------------------ encode
 // Codes of at most ENC_MAXLEN bits are packed with their length into one word
-// (code << 6 | length); k_pack_codes also records the longest length, which
-// decides on the device which encode kernel does the work.
-constexpr int ENC_MAXLEN = 26;
+// (code << 6 | length), by the codebook kernel or by k_pack_codes, which also
+// record the longest length: it decides on the device which encode kernel
+// does the work.
 constexpr int ENC_CHUNK = 1024;                          // largest chunk of the wave kernel
 constexpr int ENC_WORDS = ENC_CHUNK * ENC_MAXLEN / 32;   // its LDS words per wave
 constexpr int ENC_T = 512;
@@ -1195,9 +1213,18 @@ void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint
   MG_HIP(hipGetLastError());
 }
 
-void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes, hipStream_t st) {
+void encode_tables(void* scratch, int dict, uint32_t** enc, uint32_t** maxlen) {
+  Carver cv(scratch);
+  *enc = cv.take<uint32_t>((uint64_t)dict);
+  *maxlen = cv.take<uint32_t>(4);
+}
+
+void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes, void* enc_scratch,
+                     hipStream_t st) {
+  uint32_t *enc = nullptr, *maxlen = nullptr;
+  if (enc_scratch) encode_tables(enc_scratch, dict, &enc, &maxlen);
   KernelTimer kt("codebook", st);
-  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, dict, len, codes);
+  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, dict, len, codes, enc, maxlen);
   MG_HIP(hipGetLastError());
 }
 
@@ -1233,14 +1260,14 @@ uint64_t encode_scratch_bytes(int dict) { return carve_size<uint32_t>((uint64_t)
 void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                    const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
                    const uint64_t* esc_off, const int64_t* qside, char* obase,
-                   const uint64_t* ooff, void* scratch, hipStream_t st) {
+                   const uint64_t* ooff, void* scratch, bool packed, hipStream_t st) {
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return;
-  Carver cv(scratch);
-  uint32_t* enc = cv.take<uint32_t>((uint64_t)dict);
-  uint32_t* maxlen = cv.take<uint32_t>(4);
+  uint32_t *enc = nullptr, *maxlen = nullptr;
+  encode_tables(scratch, dict, &enc, &maxlen);
   KernelTimer kt("encode", st);
-  hipLaunchKernelGGL(k_pack_codes, dim3(1), dim3(1024), 0, st, len, codes, dict, enc, maxlen);
+  // the codebook kernel may have written the packed table already
+  if (!packed) hipLaunchKernelGGL(k_pack_codes, dim3(1), dim3(1024), 0, st, len, codes, dict, enc, maxlen);
   const uint32_t mask = (uint32_t)(dict - 1);
   if (chunk <= ENC_CHUNK)
     hipLaunchKernelGGL(k_encode_wave, dim3(blocks_for((nch + ENC_T / 64 - 1) / (ENC_T / 64), 512)), dim3(ENC_T), 0,

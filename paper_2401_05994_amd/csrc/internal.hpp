@@ -219,13 +219,19 @@ void launch_dequantize(const uint16_t* sym, const int64_t* qside, uint64_t n,
 // Huffman (huffman.hip).
 void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
                       uint32_t* chunk_esc, uint32_t* status, hipStream_t st);
-void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes,
+// enc_scratch (nullable): the encoder's scratch, whose packed code table and
+// longest length the codebook kernel then fills (see launch_encode's packed).
+void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes, void* enc_scratch,
                      hipStream_t st);
+// The packed code table and longest-length slot inside an encoder scratch.
+void encode_tables(void* enc_scratch, int dict, uint32_t** enc, uint32_t** maxlen);
 // Several codebooks in one launch (one block each): jobs is a device array.
 struct CodebookJob {
   const uint64_t* hist;
   uint8_t* len;
   uint64_t* codes;
+  uint32_t* enc;     // packed table of the field's encoder scratch
+  uint32_t* maxlen;
 };
 void launch_codebook_group(const CodebookJob* jobs, uint32_t njobs, int dict, hipStream_t st);
 void launch_chunk_bits(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
@@ -238,7 +244,7 @@ uint64_t encode_scratch_bytes(int dict);
 void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                    const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
                    const uint64_t* esc_off, const int64_t* qside, char* obase,
-                   const uint64_t* ooff, void* scratch, hipStream_t st);
+                   const uint64_t* ooff, void* scratch, bool packed, hipStream_t st);
 uint64_t decode_table_bytes(int dict);
 void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const uint64_t* word_off,
                         const uint32_t* chunk_bits, uint64_t n, int dict, int chunk,
