@@ -181,6 +181,18 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
 template <typename T>
 void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* g1, T* z,
                              const QuantOut* q, const T* cstream, hipStream_t st);
+// The small levels (every side <= 17) and the coarsest grid in one workgroup:
+// levels 1..lt, lt = fused3d_tail_levels (0: none).  Decomposition starts from
+// u, the fine grid of level lt, and writes the stream of levels lt..0;
+// recomposition reads levels 0..lt and writes the fine grid of level lt to out.
+template <typename T>
+int fused3d_tail_levels(const Hierarchy& h);
+template <typename T>
+void fused3d_tail_decompose(const Hierarchy& h, int lt, const T* table, const T* u, const QuantOut* q, T* cstream,
+                            hipStream_t st);
+template <typename T>
+void fused3d_tail_recompose(const Hierarchy& h, int lt, const T* table, T* out, const QuantOut* q, const T* cstream,
+                            hipStream_t st);
 
 // Autotuned launch shapes (tune.hip): per knob, dtype and fine level shape.
 constexpr int TUNE_COEFF_SEG = 0;       // coarse intervals of dim 0 per block, plane-marching decomposition

@@ -566,10 +566,16 @@ void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, c
   T* nxt = pa;
   const int mode = q ? 1 : 0;
   const bool f3 = fused3d_ok<T>(h);
-  for (int l = h.L; l >= 1 && f3; --l) {
+  const int lt = f3 ? fused3d_tail_levels<T>(h) : 0;  // levels 1..lt: one small-level kernel
+  for (int l = h.L; l > lt && f3; --l) {
     fused3d_decompose_level<T>(h, l, table, cur, nxt, ga, gb, q, d_stream, st);
     cur = nxt;
     nxt = (nxt == pa) ? pb : pa;
+  }
+  if (lt > 0) {
+    // the small levels and the coarsest grid
+    fused3d_tail_decompose<T>(h, lt, table, cur, q, d_stream, st);
+    return;
   }
   for (int l = f3 ? 0 : h.L; l >= 1; --l) {
     LevelGeom<T> g = level_geom<T>(h, l, table);
@@ -618,15 +624,18 @@ void recompose(const Hierarchy& h, const T* table, const T* d_stream, const Quan
     if (l == h.L) return d_out;
     return ((h.L - l) % 2 == 1) ? pa : pb;
   };
-  T* cur = level_buf(0);
-  if (mode == 0)
+  const bool f3 = fused3d_ok<T>(h);
+  const int lt = f3 ? fused3d_tail_levels<T>(h) : 0;  // levels 1..lt: one small-level kernel
+  T* cur = level_buf(lt);
+  if (lt > 0)
+    fused3d_tail_recompose<T>(h, lt, table, cur, q, d_stream, st);
+  else if (mode == 0)
     hipLaunchKernelGGL((k_coarsest_in<T, 0>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, d_stream, nullptr,
                        nullptr, nullptr, 0, n0);
   else
     hipLaunchKernelGGL((k_coarsest_in<T, 1>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, nullptr, q->sym,
                        q->qside, q->bins, q->R, n0);
-  const bool f3 = fused3d_ok<T>(h);
-  for (int l = 1; l <= h.L && f3; ++l) {
+  for (int l = lt + 1; l <= h.L && f3; ++l) {
     T* out = level_buf(l);
     fused3d_recompose_level<T>(h, l, table, cur, out, ga, gb, q, d_stream, st);
     cur = out;

@@ -888,6 +888,267 @@ __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T
   }
 }
 
+// ------------------------------------------------------------------ small levels
+// The levels whose three sides are all at most TAIL_N, and the coarsest grid,
+// in one workgroup with every intermediate grid in LDS: the same arithmetic as
+// the per-level kernels above (the same interpolation nest, mass_at /
+// restrict_at, Thomas recurrences and quantizer), one barrier between steps
+// instead of one launch per step.
+constexpr int TAIL_N = 17;
+constexpr int TAIL_F = TAIL_N * TAIL_N * TAIL_N;                  // fine grid of a tail level
+constexpr int TAIL_H = TAIL_N / 2 + 1;                            // its coarse side
+constexpr int TAIL_C = TAIL_H * TAIL_H * TAIL_H;                  // coarse grid
+constexpr int TAIL_G2 = TAIL_N * TAIL_N * TAIL_H;                 // after the dim-2 restriction
+constexpr int TAIL_G1 = TAIL_N * TAIL_H * TAIL_H;                 // after the dim-1 restriction
+constexpr int TAIL_T = 1024;
+constexpr int TAIL_LMAX = 6;
+
+template <typename T>
+struct TailLevels {
+  int nl;               // levels in the tail
+  Lv3<T> lv[TAIL_LMAX];  // decomposition: finest first; recomposition: coarsest first
+};
+
+// A level's weights in LDS: ws[d][a][i] holds array a of dimension d (wl, wr,
+// ma, mb, mc over fine indices; rl, rr, ta, tr, tcp over coarse ones); the
+// returned constants point into it.
+template <typename T>
+struct TailW {
+  DimConsts<T> d[3];
+};
+template <typename T>
+__device__ inline const T* tail_arr(const DimConsts<T>& w, int a) {
+  switch (a) {
+    case 0: return w.wl;
+    case 1: return w.wr;
+    case 2: return w.ma;
+    case 3: return w.mb;
+    case 4: return w.mc;
+    case 5: return w.rl;
+    case 6: return w.rr;
+    case 7: return w.ta;
+    case 8: return w.tr;
+    default: return w.tcp;
+  }
+}
+template <typename T>
+__device__ inline TailW<T> tail_stage_weights(T (*ws)[10][TAIL_N], const Lv3<T>& p) {
+  for (int e = threadIdx.x; e < 3 * 10 * TAIL_N; e += TAIL_T) {
+    const int d = e / (10 * TAIL_N), a = (e / TAIL_N) % 10, i = e % TAIL_N;
+    const DimConsts<T>& w = d == 0 ? p.d0 : d == 1 ? p.d1 : p.d2;
+    const int nf = d == 0 ? p.n0 : d == 1 ? p.n1 : p.n2, nc = d == 0 ? p.c0 : d == 1 ? p.c1 : p.c2;
+    if (i < (a < 5 ? nf : nc)) ws[d][a][i] = tail_arr(w, a)[i];
+  }
+  TailW<T> r;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    r.d[d] = DimConsts<T>{ws[d][0], ws[d][1], ws[d][2], ws[d][3], ws[d][4],
+                          ws[d][5], ws[d][6], ws[d][7], ws[d][8], ws[d][9]};
+  return r;
+}
+
+// Thomas along one line (n values `stride` apart), as k_thomas
+template <typename T>
+__device__ inline void tail_thomas(T* base, int n, int stride, const DimConsts<T>& w) {
+  T prev = base[0] * w.tr[0];
+  base[0] = prev;
+  for (int i = 1; i < n; ++i) {
+    prev = (base[i * stride] - w.ta[i] * prev) * w.tr[i];
+    base[i * stride] = prev;
+  }
+  T x = prev;
+  for (int i = n - 2; i >= 0; --i) {
+    x = base[i * stride] - w.tcp[i] * x;
+    base[i * stride] = x;
+  }
+}
+
+// c (n0 x n1 x n2, zeros at coarse nodes) -> z (c0 x c1 x c2): restrictions
+// along dims 2, 1, 0 (g2, g1 scratch; z may alias g2), then the three solves.
+template <typename T>
+__device__ inline void tail_correction(const Lv3<T>& p, const TailW<T>& w, const T* c, T* g2, T* g1, T* z) {
+  const int t = threadIdx.x;
+  const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c0 = p.c0, c1 = p.c1, c2 = p.c2;
+  for (int e = t; e < n0 * n1 * c2; e += TAIL_T) {
+    const int f01 = e / c2, j2 = e - f01 * c2;
+    g2[e] = restrict_at<T>(j2, c2, n2, w.d[2], [&](int i) { return c[f01 * n2 + i]; });
+  }
+  __syncthreads();
+  for (int e = t; e < n0 * c1 * c2; e += TAIL_T) {
+    const int f0 = e / (c1 * c2), j12 = e - f0 * (c1 * c2), j1 = j12 / c2, j2 = j12 - j1 * c2;
+    g1[e] = restrict_at<T>(j1, c1, n1, w.d[1], [&](int i) { return g2[(f0 * n1 + i) * c2 + j2]; });
+  }
+  __syncthreads();
+  for (int e = t; e < c0 * c1 * c2; e += TAIL_T) {
+    const int j0 = e / (c1 * c2), j12 = e - j0 * (c1 * c2);
+    z[e] = restrict_at<T>(j0, c0, n0, w.d[0], [&](int i) { return g1[i * (c1 * c2) + j12]; });
+  }
+  __syncthreads();
+  for (int e = t; e < c1 * c2; e += TAIL_T) tail_thomas(z + e, c0, c1 * c2, w.d[0]);
+  __syncthreads();
+  for (int e = t; e < c0 * c2; e += TAIL_T) {
+    const int j0 = e / c2, j2 = e - j0 * c2;
+    tail_thomas(z + j0 * c1 * c2 + j2, c1, c2, w.d[1]);
+  }
+  __syncthreads();
+  for (int e = t; e < c0 * c1; e += TAIL_T) tail_thomas(z + e * c2, c2, 1, w.d[2]);
+  __syncthreads();
+}
+
+// stream position of fine node (f0, f1, f2) of a level with mask m != 0
+__device__ inline uint64_t tail_pos(const uint64_t (*subs)[4], int f0, int n0, int f1, int n1, int f2, int n2) {
+  const bool e0 = is_new(f0, n0), e1 = is_new(f1, n1), e2 = is_new(f2, n2);
+  const int m = (e0 ? 1 : 0) | (e1 ? 2 : 0) | (e2 ? 4 : 0);
+  const uint64_t i0 = e0 ? (uint64_t)(f0 >> 1) : (uint64_t)cidx(f0);
+  const uint64_t i1 = e1 ? (uint64_t)(f1 >> 1) : (uint64_t)cidx(f1);
+  const uint64_t i2 = e2 ? (uint64_t)(f2 >> 1) : (uint64_t)cidx(f2);
+  return subs[m][0] + i0 * subs[m][1] + i1 * subs[m][2] + i2;
+}
+
+// Decomposition of levels lt .. lt - nl + 1 (a.lv[k] = level lt - k) and the
+// coarsest grid; u is the fine grid of level lt.  MODE 1: symbols; MODE 0:
+// float coefficients in cstream.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TAIL_T) k3_tail_decompose(const T* __restrict__ u, uint16_t* __restrict__ sym,
+                                                           int64_t* __restrict__ qside, T* __restrict__ cstream,
+                                                           const double* __restrict__ bins, int R, int lt,
+                                                           TailLevels<T> a) {
+  __shared__ T A[TAIL_F], B[TAIL_C], C[TAIL_F], G[TAIL_G2];
+  __shared__ T WS[3][10][TAIL_N];
+  __shared__ uint64_t subs[8][4];
+  const int t = threadIdx.x;
+  {
+    const Lv3<T>& p = a.lv[0];
+    for (int e = t; e < p.n0 * p.n1 * p.n2; e += TAIL_T) A[e] = u[e];
+  }
+  T* U = A;   // fine grid of the current level
+  T* UC = B;  // its coarse grid
+  int ncoarse = 0;
+  for (int k = 0; k < a.nl; ++k) {
+    const Lv3<T>& p = a.lv[k];
+    const int level = lt - k;
+    const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
+    load_sub(subs, p.sub, p.level_off);
+    const TailW<T> w = tail_stage_weights<T>(WS, p);
+    __syncthreads();
+    const double inv_b = MODE == 1 ? 1.0 / bins[level] : 0.0;
+    // coefficients (interpolant nested with dim 2 innermost), quantization, coarse copy
+    for (int e = t; e < n0 * n1 * n2; e += TAIL_T) {
+      const int f0 = e / (n1 * n2), f12 = e - f0 * (n1 * n2), f1 = f12 / n2, f2 = f12 - f1 * n2;
+      const bool e0 = is_new(f0, n0), e1 = is_new(f1, n1), e2 = is_new(f2, n2);
+      if (!e0 && !e1 && !e2) {
+        UC[(cidx(f0) * c1 + cidx(f1)) * c2 + cidx(f2)] = U[e];
+        C[e] = T(0);
+        continue;
+      }
+      auto Y = [&](int g0, int g1) -> T {
+        const T* row = U + (g0 * n1 + g1) * n2;
+        return e2 ? w.d[2].wl[f2] * row[f2 - 1] + w.d[2].wr[f2] * row[f2 + 1] : row[f2];
+      };
+      auto X = [&](int g0) -> T {
+        return e1 ? w.d[1].wl[f1] * Y(g0, f1 - 1) + w.d[1].wr[f1] * Y(g0, f1 + 1) : Y(g0, f1);
+      };
+      const T pi = e0 ? w.d[0].wl[f0] * X(f0 - 1) + w.d[0].wr[f0] * X(f0 + 1) : X(f0);
+      const T c = U[e] - pi;
+      C[e] = c;
+      const uint64_t pos = tail_pos(subs, f0, n0, f1, n1, f2, n2);
+      if (MODE == 1)
+        quant_store(c, inv_b, R, pos, sym, qside);
+      else
+        cstream[pos] = c;
+    }
+    __syncthreads();
+    // z = M^-1 P^T M c (g1 over the coefficients, which are done), then u_{l-1} = u_l|coarse + z
+    tail_correction<T>(p, w, C, G, C, G);
+    ncoarse = p.c0 * c1 * c2;
+    for (int e = t; e < ncoarse; e += TAIL_T) UC[e] = UC[e] + G[e];
+    __syncthreads();
+    T* tmp = U;
+    U = UC;
+    UC = tmp;
+  }
+  // the coarsest grid opens the stream
+  const double inv_b0 = MODE == 1 ? 1.0 / bins[0] : 0.0;
+  for (int e = t; e < ncoarse; e += TAIL_T) {
+    if (MODE == 1)
+      quant_store(U[e], inv_b0, R, (uint64_t)e, sym, qside);
+    else
+      cstream[e] = U[e];
+  }
+}
+
+// Recomposition of levels lt - nl + 1 .. lt (a.lv[k] = level lt - nl + 1 + k)
+// from the coarsest grid in the stream; writes the fine grid of level lt to out.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TAIL_T) k3_tail_recompose(T* __restrict__ out, const uint16_t* __restrict__ sym,
+                                                           const int64_t* __restrict__ qside,
+                                                           const T* __restrict__ cstream,
+                                                           const double* __restrict__ bins, int R, int lt,
+                                                           TailLevels<T> a) {
+  __shared__ T P0[TAIL_C], P1[TAIL_C], C[TAIL_F], G[TAIL_G2], G1[TAIL_G1];
+  __shared__ T WS[3][10][TAIL_N];
+  __shared__ uint64_t subs[8][4];
+  const int t = threadIdx.x;
+  T* UC = P0;  // coarse grid of the current level
+  T* UF = P1;  // its fine grid (below the last level)
+  {
+    const Lv3<T>& p = a.lv[0];
+    const double b0 = MODE == 1 ? bins[0] : 0.0;
+    for (int e = t; e < p.c0 * p.c1 * p.c2; e += TAIL_T)
+      UC[e] = MODE == 1 ? dequant_load<T>(sym, qside, (uint64_t)e, b0, R) : cstream[e];
+  }
+  for (int k = 0; k < a.nl; ++k) {
+    const Lv3<T>& p = a.lv[k];
+    const int level = lt - a.nl + 1 + k;
+    const bool last = k == a.nl - 1;
+    const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
+    load_sub(subs, p.sub, p.level_off);
+    const TailW<T> w = tail_stage_weights<T>(WS, p);
+    __syncthreads();
+    const double b = MODE == 1 ? bins[level] : 0.0;
+    // coefficients of the level (zeros at coarse nodes)
+    for (int e = t; e < n0 * n1 * n2; e += TAIL_T) {
+      const int f0 = e / (n1 * n2), f12 = e - f0 * (n1 * n2), f1 = f12 / n2, f2 = f12 - f1 * n2;
+      const bool any = is_new(f0, n0) || is_new(f1, n1) || is_new(f2, n2);
+      T c = T(0);
+      if (any) {
+        const uint64_t pos = tail_pos(subs, f0, n0, f1, n1, f2, n2);
+        c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
+      }
+      C[e] = c;
+    }
+    __syncthreads();
+    tail_correction<T>(p, w, C, G, G1, G);
+    // uc = u_{l-1} - z
+    for (int e = t; e < p.c0 * c1 * c2; e += TAIL_T) UC[e] = UC[e] - G[e];
+    __syncthreads();
+    // u_l = c + Pi(uc) at new nodes, uc at coarse nodes (dim 2 innermost)
+    T* dst = last ? out : UF;
+    for (int e = t; e < n0 * n1 * n2; e += TAIL_T) {
+      const int f0 = e / (n1 * n2), f12 = e - f0 * (n1 * n2), f1 = f12 / n2, f2 = f12 - f1 * n2;
+      const bool e0 = is_new(f0, n0), e1 = is_new(f1, n1), e2 = is_new(f2, n2);
+      const int q0 = e0 ? (f0 >> 1) : cidx(f0), q1 = e1 ? (f1 >> 1) : cidx(f1), q2 = e2 ? (f2 >> 1) : cidx(f2);
+      auto V = [&](int a0, int a1, int a2) -> T { return UC[(a0 * c1 + a1) * c2 + a2]; };
+      if (!e0 && !e1 && !e2) {
+        dst[e] = V(q0, q1, q2);
+        continue;
+      }
+      auto Y = [&](int a0, int a1) -> T {
+        return e2 ? w.d[2].wl[f2] * V(a0, a1, q2) + w.d[2].wr[f2] * V(a0, a1, q2 + 1) : V(a0, a1, q2);
+      };
+      auto X = [&](int a0) -> T {
+        return e1 ? w.d[1].wl[f1] * Y(a0, q1) + w.d[1].wr[f1] * Y(a0, q1 + 1) : Y(a0, q1);
+      };
+      const T pi = e0 ? w.d[0].wl[f0] * X(q0) + w.d[0].wr[f0] * X(q0 + 1) : X(q0);
+      dst[e] = C[e] + pi;
+    }
+    __syncthreads();
+    T* tmp = UC;
+    UC = UF;
+    UF = tmp;
+  }
+}
+
 inline unsigned blocks1(uint64_t n) { return (unsigned)std::max<uint64_t>(1, (n + NT - 1) / NT); }
 
 }  // namespace
@@ -1021,13 +1282,65 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
   MG_HIP(hipGetLastError());
 }
 
+// Levels handled by the small-level kernels: every level l <= lt has all
+// three sides <= TAIL_N (0: none).
+template <typename T>
+int fused3d_tail_levels(const Hierarchy& h) {
+  if (!fused3d_ok<T>(h)) return 0;
+  int lt = 0;
+  for (int l = 1; l <= h.L && l <= TAIL_LMAX; ++l) {
+    bool small = true;
+    for (int s = 1; s < MAXD; ++s) small = small && h.sizes[l][s] <= TAIL_N;
+    if (!small) break;
+    lt = l;
+  }
+  return lt;
+}
+
+template <typename T>
+void fused3d_tail_decompose(const Hierarchy& h, int lt, const T* table, const T* u, const QuantOut* q, T* cstream,
+                            hipStream_t st) {
+  TailLevels<T> a{};
+  a.nl = lt;
+  for (int k = 0; k < lt; ++k) a.lv[k] = lv3<T>(h, lt - k, table);
+  KernelTimer kt("tail_decompose", st);
+  if (q)
+    hipLaunchKernelGGL((k3_tail_decompose<T, 1>), dim3(1), dim3(TAIL_T), 0, st, u, q->sym, q->qside, (T*)nullptr,
+                       q->bins, q->R, lt, a);
+  else
+    hipLaunchKernelGGL((k3_tail_decompose<T, 0>), dim3(1), dim3(TAIL_T), 0, st, u, (uint16_t*)nullptr,
+                       (int64_t*)nullptr, cstream, (const double*)nullptr, 0, lt, a);
+  MG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void fused3d_tail_recompose(const Hierarchy& h, int lt, const T* table, T* out, const QuantOut* q, const T* cstream,
+                            hipStream_t st) {
+  TailLevels<T> a{};
+  a.nl = lt;
+  for (int k = 0; k < lt; ++k) a.lv[k] = lv3<T>(h, k + 1, table);
+  KernelTimer kt("tail_recompose", st);
+  if (q)
+    hipLaunchKernelGGL((k3_tail_recompose<T, 1>), dim3(1), dim3(TAIL_T), 0, st, out, q->sym, q->qside,
+                       (const T*)nullptr, q->bins, q->R, lt, a);
+  else
+    hipLaunchKernelGGL((k3_tail_recompose<T, 0>), dim3(1), dim3(TAIL_T), 0, st, out, (const uint16_t*)nullptr,
+                       (const int64_t*)nullptr, cstream, (const double*)nullptr, 0, lt, a);
+  MG_HIP(hipGetLastError());
+}
+
 #define MG_INST3(T)                                                                                             \
   template bool fused3d_ok<T>(const Hierarchy&);                                                               \
   template uint64_t fused3d_scratch_elems<T>(const Hierarchy&);                                                \
   template void fused3d_decompose_level<T>(const Hierarchy&, int, const T*, const T*, T*, T*, T*, const QuantOut*, \
                                            T*, hipStream_t);                                                   \
   template void fused3d_recompose_level<T>(const Hierarchy&, int, const T*, const T*, T*, T*, T*, const QuantOut*, \
-                                           const T*, hipStream_t);
+                                           const T*, hipStream_t);                                             \
+  template int fused3d_tail_levels<T>(const Hierarchy&);                                                       \
+  template void fused3d_tail_decompose<T>(const Hierarchy&, int, const T*, const T*, const QuantOut*, T*,      \
+                                          hipStream_t);                                                        \
+  template void fused3d_tail_recompose<T>(const Hierarchy&, int, const T*, T*, const QuantOut*, const T*,      \
+                                          hipStream_t);
 MG_INST3(float)
 MG_INST3(double)
 #undef MG_INST3
