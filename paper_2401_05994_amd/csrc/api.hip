@@ -508,8 +508,7 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
   launch_codebook(hist, o.dict, code_len, codes, enc_scratch, st);
   }
   launch_chunk_bits(sym, n, o.dict, o.chunk, code_len, chunk_bits, st);
-  launch_scan_words(chunk_bits, nch, word_off, st);
-  launch_scan_u32(chunk_esc, nch, esc_off, st);
+  launch_scan_pair(chunk_bits, chunk_esc, nch, word_off, esc_off, st);
   hipLaunchKernelGGL(k_outlier_offset, dim3(1), dim3(1), 0, st, word_off, nch, y.payload, &misc[1]);
   launch_encode(sym, n, o.dict, o.chunk, code_len, codes, word_off, reinterpret_cast<uint32_t*>(d_out + y.payload),
                 esc_off, qside, d_out, &misc[1], enc_scratch, true, st);

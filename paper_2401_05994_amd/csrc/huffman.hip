@@ -537,6 +537,71 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(const uint32_t* __restric
   }
 }
 
+// Both scans of the compression path in one sequence of launches: blockIdx.y
+// 0 scans the chunk word counts (ceil(bits / 32)) of a into oa, 1 the values
+// of b into ob.
+struct ScanPair {
+  const uint32_t* v[2];
+  uint64_t* off[2];
+};
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_tiles2(ScanPair p, uint64_t n) {
+  __shared__ uint64_t sh[SCAN_T];
+  const int y = blockIdx.y;
+  const uint32_t* __restrict__ v = p.v[y];
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+  uint64_t s = 0;
+  for (int j = 0; j < SCAN_PER; ++j) {
+    const uint64_t i = base + (uint64_t)j * SCAN_T + threadIdx.x;
+    if (i < n) s += y == 0 ? scan_value<true>(v[i]) : scan_value<false>(v[i]);
+  }
+  uint64_t total;
+  block_exclusive_scan(s, sh, &total);
+  if (threadIdx.x == 0) p.off[y][base] = total;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top2(ScanPair p, uint64_t n) {
+  __shared__ uint64_t sh[1024];
+  uint64_t* __restrict__ off = p.off[blockIdx.y];
+  const uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+  uint64_t carry = 0;
+  for (uint64_t g = 0; g < nt; g += blockDim.x) {
+    const uint64_t b = g + threadIdx.x;
+    const uint64_t x = b < nt ? off[b * SCAN_TILE] : 0;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan(x, sh, &total);
+    if (b < nt) off[b * SCAN_TILE] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) off[n] = carry;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_apply2(ScanPair p, uint64_t n) {
+  __shared__ uint64_t sh[SCAN_T];
+  __shared__ uint64_t tbase_sh;
+  const int y = blockIdx.y;
+  const uint32_t* __restrict__ v = p.v[y];
+  uint64_t* __restrict__ off = p.off[y];
+  const uint64_t tile = (uint64_t)blockIdx.x * SCAN_TILE;
+  if (threadIdx.x == 0) tbase_sh = off[tile];
+  const uint64_t mine = tile + (uint64_t)threadIdx.x * SCAN_PER;
+  uint64_t x[SCAN_PER];
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    x[j] = mine + j < n ? (y == 0 ? scan_value<true>(v[mine + j]) : scan_value<false>(v[mine + j])) : 0;
+    s += x[j];
+  }
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(s, sh, &total);  // its barriers publish tbase_sh
+  run += tbase_sh;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    if (mine + j < n) off[mine + j] = run;
+    run += x[j];
+  }
+}
+
 template <bool WORDS>
 void launch_scan(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st) {
   const uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -1253,6 +1318,17 @@ void launch_scan_words(const uint32_t* chunk_bits, uint64_t nch, uint64_t* word_
 void launch_scan_u32(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st) {
   KernelTimer kt("scan", st);
   launch_scan<false>(v, n, off, st);
+}
+
+void launch_scan_pair(const uint32_t* chunk_bits, const uint32_t* esc, uint64_t nch, uint64_t* word_off,
+                      uint64_t* esc_off, hipStream_t st) {
+  KernelTimer kt("scan", st);
+  ScanPair p{{chunk_bits, esc}, {word_off, esc_off}};
+  const uint64_t nt = (nch + SCAN_TILE - 1) / SCAN_TILE;
+  if (nt) hipLaunchKernelGGL(k_scan_tiles2, dim3((unsigned)nt, 2), dim3(SCAN_T), 0, st, p, nch);
+  hipLaunchKernelGGL(k_scan_top2, dim3(1, 2), dim3(1024), 0, st, p, nch);
+  if (nt) hipLaunchKernelGGL(k_scan_apply2, dim3((unsigned)nt, 2), dim3(SCAN_T), 0, st, p, nch);
+  MG_HIP(hipGetLastError());
 }
 
 uint64_t encode_scratch_bytes(int dict) { return carve_size<uint32_t>((uint64_t)dict) + carve_size<uint32_t>(4); }

@@ -252,6 +252,9 @@ void launch_chunk_bits(const uint16_t* sym, uint64_t n, int dict, int chunk, con
 void launch_scan_words(const uint32_t* chunk_bits, uint64_t nch, uint64_t* word_off,
                        hipStream_t st);
 void launch_scan_u32(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st);
+// both at once: word offsets of the chunk bit counts and offsets of the escape counts
+void launch_scan_pair(const uint32_t* chunk_bits, const uint32_t* esc, uint64_t nch, uint64_t* word_off,
+                      uint64_t* esc_off, hipStream_t st);
 uint64_t encode_scratch_bytes(int dict);
 void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                    const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
