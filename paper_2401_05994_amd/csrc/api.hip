@@ -582,8 +582,7 @@ void decompress_impl(Hierarchy& h, const Parsed& P, const char* d_in, T* d_out, 
   MG_HIP(hipMemsetAsync(status, 0, 16, st));
   const uint32_t* chunk_bits = reinterpret_cast<const uint32_t*>(d_in + P.chunk_bits);
   const uint32_t* chunk_esc = reinterpret_cast<const uint32_t*>(d_in + P.chunk_esc);
-  launch_scan_words(chunk_bits, nch, word_off, st);
-  launch_scan_u32(chunk_esc, nch, esc_off, st);
+  launch_scan_pair(chunk_bits, chunk_esc, nch, word_off, esc_off, st);
   launch_decode_full(reinterpret_cast<const uint32_t*>(d_in + P.payload), P.hd.payload_words, word_off,
                      chunk_bits, n, dict, chunk, reinterpret_cast<const uint8_t*>(d_in + P.code_len), sym,
                      esc_off, n_out, reinterpret_cast<const int64_t*>(d_in + P.outliers), qside, epos, tabs,
