@@ -812,6 +812,13 @@ __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym
 // decides) and fdelta[j] = offset - first (mod 2^32); entry nfast has length 0
 // (an invalid code) and entries after it never match.
 constexpr int FASTN = 16;
+// Prefix table of the fast path: entry v is the index (into flen/fdelta) of
+// the one code length whose left-aligned interval holds every 32-bit window
+// starting with the LUT_BITS bits v, or LUT_NONE when the prefix straddles two
+// lengths (the compare chain decides those windows).
+constexpr int LUT_BITS = 12;
+constexpr uint8_t LUT_NONE = 0xff;
+
 struct DecTables {
   uint64_t first[MAXLEN + 1];
   uint64_t lim1[MAXLEN + 1];
@@ -820,6 +827,7 @@ struct DecTables {
   uint32_t minlen, maxlen, bad, used;
   uint32_t nfast, pad;
   uint32_t flen[FASTN], flim[FASTN], fdelta[FASTN];
+  uint8_t lut[1 << LUT_BITS];
 };
 
 __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restrict__ len, int dict, DecTables* tab,
@@ -830,6 +838,7 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
   __shared__ uint32_t cnt[MAXLEN + 1];
   __shared__ uint32_t offs[MAXLEN + 1];
   __shared__ uint32_t bad;
+  __shared__ uint32_t sflim[FASTN], snfast;
   const int t = threadIdx.x, nt = blockDim.x;
   if (t == 0) bad = 0;
   __syncthreads();
@@ -895,11 +904,29 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
       tab->fdelta[j] = 0;
     }
     tab->nfast = fast ? nd : 0;
+    for (int j = 0; j < FASTN; ++j) sflim[j] = tab->flim[j];
+    snfast = fast ? nd : 0;
   }
   __syncthreads();
   for (int s = t; s < dict; s += nt) {
     const int L = lens[s];
     if (L) sorted[offs[L] + rank[s]] = (uint16_t)s;
+  }
+  // windows starting with prefix v run from v << (32 - LUT_BITS) to that plus
+  // 2^(32 - LUT_BITS) - 1; the chain's answer for a window is the number of
+  // limits below it, so the prefix has one answer when both ends agree
+  for (int v = t; v < (1 << LUT_BITS); v += nt) {
+    uint8_t e = LUT_NONE;
+    if (snfast) {
+      const uint32_t lo = (uint32_t)v << (32 - LUT_BITS), hi = lo | ((1u << (32 - LUT_BITS)) - 1u);
+      int clo = 0, chi = 0;
+      for (int j = 0; j + 1 < FASTN; ++j) {
+        clo += lo > sflim[j] ? 1 : 0;
+        chi += hi > sflim[j] ? 1 : 0;
+      }
+      if (clo == chi) e = (uint8_t)clo;
+    }
+    tab->lut[v] = e;
   }
 }
 
@@ -949,6 +976,8 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
   __shared__ uint32_t offs[MAXLEN + 1];
   __shared__ uint16_t sorted[MAXDICT];
   __shared__ uint32_t ring[256 * RING_STRIDE];
+  __shared__ uint32_t lut_w[(1 << LUT_BITS) / 4];  // the prefix table, four entries per word
+  __shared__ uint32_t fl_s[FASTN], fd_s[FASTN];
   {
     const uint32_t nd = tab->nfast;
     const bool mine = NF == 8 ? (nd >= 1 && nd <= 7) : NF == 12 ? (nd >= 8 && nd <= 11) : (nd == 0 || nd >= 12);
@@ -959,6 +988,14 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
     first[b] = tab->first[b];
     lim1[b] = tab->lim1[b];
     offs[b] = tab->offset[b];
+  }
+  {
+    const uint32_t* lw = reinterpret_cast<const uint32_t*>(tab->lut);
+    for (int i = threadIdx.x; i < (1 << LUT_BITS) / 4; i += blockDim.x) lut_w[i] = lw[i];
+    if (threadIdx.x < FASTN) {
+      fl_s[threadIdx.x] = tab->flen[threadIdx.x];
+      fd_s[threadIdx.x] = tab->fdelta[threadIdx.x];
+    }
   }
   // symbols in code order: eight loads per lane in flight before the LDS stores
   for (uint32_t s0 = threadIdx.x; s0 < used; s0 += 8 * blockDim.x) {
@@ -1098,12 +1135,23 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
         nextw = myring[rd & (RING - 1)];
       }
       const uint32_t top = (uint32_t)(buf >> 32);
-      uint32_t L = flen[0], d = fdelta[0];
+      // the length from the prefix table; the compare chain only for windows
+      // whose prefix straddles two lengths
+      const uint32_t pv = top >> (32 - LUT_BITS);
+      const uint32_t e = (lut_w[pv >> 2] >> (8 * (pv & 3))) & 0xffu;
+      uint32_t L, d;
+      if (e != LUT_NONE) {
+        L = fl_s[e];
+        d = fd_s[e];
+      } else {
+        L = flen[0];
+        d = fdelta[0];
 #pragma unroll
-      for (int j = 0; j + 1 < NF; ++j) {
-        const bool past = top > flim[j];
-        L = past ? flen[j + 1] : L;
-        d = past ? fdelta[j + 1] : d;
+        for (int j = 0; j + 1 < NF; ++j) {
+          const bool past = top > flim[j];
+          L = past ? flen[j + 1] : L;
+          d = past ? fdelta[j + 1] : d;
+        }
       }
       // L = 0: no code of the table starts with these bits
       const uint32_t idx = L ? d + (top >> (32 - L)) : 0xffffffffu;
