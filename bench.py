@@ -29,11 +29,21 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "coeff_r21_fine_513cubed_f32_traff
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2401_05994_amd", "csrc", "transform3d.hip")
 
 
+# The finest decomposition kernel and every device helper it uses come before
+# this line of its source file; what follows (other kernels, host code) does
+# not change it.
+KERNEL_SOURCE_END = b"// mass + restriction along dim 0 of g1"
+
+
 def source_sha256(path: str) -> str:
+    """sha256 of the kernel's source text: the file up to KERNEL_SOURCE_END
+    (the whole file if the marker is missing)."""
     import hashlib
 
     with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+        text = f.read()
+    end = text.find(KERNEL_SOURCE_END)
+    return hashlib.sha256(text if end < 0 else text[:end]).hexdigest()
 
 
 def measured_traffic(n: int, tol: float):
