@@ -181,6 +181,15 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
 template <typename T>
 void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* g1, T* z,
                              const QuantOut* q, const T* cstream, hipStream_t st);
+// The two halves of fused3d_recompose_level: the correction of level l (it
+// reads only level l's coefficients) into z, using g1; then u_l from u_{l-1}
+// (cur), z and the coefficients.
+template <typename T>
+void fused3d_recompose_correction(const Hierarchy& h, int l, const T* table, T* g1, T* z, const QuantOut* q,
+                                  const T* cstream, hipStream_t st);
+template <typename T>
+void fused3d_recompose_finish(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* z,
+                              const QuantOut* q, const T* cstream, hipStream_t st);
 // The small levels (every side <= 17) and the coarsest grid in one workgroup:
 // levels 1..lt, lt = fused3d_tail_levels (0: none).  Decomposition starts from
 // u, the fine grid of level lt, and writes the stream of levels lt..0;

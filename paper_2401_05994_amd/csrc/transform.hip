@@ -17,6 +17,7 @@
 // The order of every rounding is fixed above so that results are
 // reproducible; the library is built with floating-point contraction off.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -487,6 +488,39 @@ struct Scratch {
   uint64_t cbar, pa, pb, ga, gb;  // element counts
 };
 
+// A side stream per device (default priority, created on first use) with its
+// fork and join events.  One host thread at a time enqueues work through a
+// device's side stream: the lock is held from fork until the object goes away,
+// after the join has been enqueued, so no call waits on another's events.
+constexpr int SIDE_MAXDEV = 64;
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ef = nullptr, ej = nullptr;
+  std::unique_lock<std::mutex> lk;
+
+  void fork(hipStream_t st) {
+    static std::mutex mtx[SIDE_MAXDEV];
+    static hipStream_t streams[SIDE_MAXDEV] = {};
+    static hipEvent_t evs[SIDE_MAXDEV][2] = {};
+    int dev = 0;
+    MG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SIDE_MAXDEV) fail(MGARD_ERR_DEVICE, "device index beyond the side-stream table");
+    lk = std::unique_lock<std::mutex>(mtx[dev]);
+    if (!streams[dev]) {
+      MG_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+      MG_HIP(hipEventCreateWithFlags(&evs[dev][0], hipEventDisableTiming));
+      MG_HIP(hipEventCreateWithFlags(&evs[dev][1], hipEventDisableTiming));
+    }
+    s = streams[dev];
+    ef = evs[dev][0];
+    ej = evs[dev][1];
+    MG_HIP(hipEventRecord(ef, st));
+    MG_HIP(hipStreamWaitEvent(s, ef, 0));
+  }
+  void record_join() { MG_HIP(hipEventRecord(ej, s)); }
+  void join(hipStream_t st) { MG_HIP(hipStreamWaitEvent(st, ej, 0)); }
+};
+
 Scratch scratch_counts(const Hierarchy& h) {
   Scratch s{};
   const int L = h.L;
@@ -626,6 +660,31 @@ void recompose(const Hierarchy& h, const T* table, const T* d_stream, const Quan
   };
   const bool f3 = fused3d_ok<T>(h);
   const int lt = f3 ? fused3d_tail_levels<T>(h) : 0;  // levels 1..lt: one small-level kernel
+  // The finest level's correction reads only the finest level's coefficients:
+  // it runs on a side stream, into ga / gb, while the coarser levels recompose
+  // on st with their solve scratch in the c-bar region (unused by the fused
+  // levels) whenever that region holds it.
+  T* cga = ga;
+  T* cgb = gb;
+  bool overlap = false;
+  if (f3 && h.L > lt) {
+    uint64_t g1c = 0;
+    for (int l = lt + 1; l < h.L; ++l)
+      g1c = std::max<uint64_t>(g1c, (uint64_t)h.sizes[l][1] * h.sizes[l - 1][2] * h.sizes[l - 1][3]);
+    const uint64_t zc = h.L - 1 > lt ? h.count(h.L - 2) : 0;
+    overlap = carve_size<T>(g1c) + carve_size<T>(zc) <= carve_size<T>(sc.cbar);
+    if (overlap) {
+      Carver cc(cbar);
+      cga = cc.take<T>(g1c);
+      cgb = cc.take<T>(zc);
+    }
+  }
+  SideStream side;
+  if (overlap) {
+    side.fork(st);
+    fused3d_recompose_correction<T>(h, h.L, table, ga, gb, q, d_stream, side.s);
+    side.record_join();
+  }
   T* cur = level_buf(lt);
   if (lt > 0)
     fused3d_tail_recompose<T>(h, lt, table, cur, q, d_stream, st);
@@ -637,7 +696,12 @@ void recompose(const Hierarchy& h, const T* table, const T* d_stream, const Quan
                        q->qside, q->bins, q->R, n0);
   for (int l = lt + 1; l <= h.L && f3; ++l) {
     T* out = level_buf(l);
-    fused3d_recompose_level<T>(h, l, table, cur, out, ga, gb, q, d_stream, st);
+    if (l == h.L && overlap) {
+      side.join(st);
+      fused3d_recompose_finish<T>(h, l, table, cur, out, gb, q, d_stream, st);
+    } else {
+      fused3d_recompose_level<T>(h, l, table, cur, out, cga, cgb, q, d_stream, st);
+    }
     cur = out;
   }
   for (int l = f3 ? h.L + 1 : 1; l <= h.L; ++l) {

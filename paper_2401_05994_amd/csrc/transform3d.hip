@@ -1232,8 +1232,8 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
 
 // Recomposition of level l: from the coefficients and u_{l-1} (cur) to u_l (out).
 template <typename T>
-void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* g1, T* z,
-                             const QuantOut* q, const T* cstream, hipStream_t st) {
+void fused3d_recompose_correction(const Hierarchy& h, int l, const T* table, T* g1, T* z, const QuantOut* q,
+                                  const T* cstream, hipStream_t st) {
   Lv3<T> p = lv3<T>(h, l, table);
   const bool fine = l == h.L;
   // fine planes per block: about 2048 blocks, at most 8 planes each, unless tuned
@@ -1260,6 +1260,14 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
     KernelTimer kt(fine ? "rec_thomas1_fine" : "rec_thomas1_coarse", st);
     launch_thomas_strided<T>(z, (uint64_t)p.c0, p.c1, (uint64_t)p.c2, dim_consts<T>(h, l, 2, table), st);
   }
+  MG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void fused3d_recompose_finish(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* z,
+                              const QuantOut* q, const T* cstream, hipStream_t st) {
+  Lv3<T> p = lv3<T>(h, l, table);
+  const bool fine = l == h.L;
   {
     KernelTimer kt(fine ? "rec_thomas2_sub_fine" : "rec_thomas2_sub_coarse", st);
     const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / sizeof(T) / p.c2)));
@@ -1280,6 +1288,13 @@ void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T*
                          (const int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p);
   }
   MG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* g1, T* z,
+                             const QuantOut* q, const T* cstream, hipStream_t st) {
+  fused3d_recompose_correction<T>(h, l, table, g1, z, q, cstream, st);
+  fused3d_recompose_finish<T>(h, l, table, cur, out, z, q, cstream, st);
 }
 
 // Levels handled by the small-level kernels: every level l <= lt has all
@@ -1336,6 +1351,10 @@ void fused3d_tail_recompose(const Hierarchy& h, int lt, const T* table, T* out, 
                                            T*, hipStream_t);                                                   \
   template void fused3d_recompose_level<T>(const Hierarchy&, int, const T*, const T*, T*, T*, T*, const QuantOut*, \
                                            const T*, hipStream_t);                                             \
+  template void fused3d_recompose_correction<T>(const Hierarchy&, int, const T*, T*, T*, const QuantOut*,      \
+                                                const T*, hipStream_t);                                        \
+  template void fused3d_recompose_finish<T>(const Hierarchy&, int, const T*, const T*, T*, T*, const QuantOut*, \
+                                            const T*, hipStream_t);                                            \
   template int fused3d_tail_levels<T>(const Hierarchy&);                                                       \
   template void fused3d_tail_decompose<T>(const Hierarchy&, int, const T*, const T*, const QuantOut*, T*,      \
                                           hipStream_t);                                                        \
