@@ -497,13 +497,30 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
     }
     launch_select_bins(err, scalars, bins, learned, nlev, st);
     launch_quantize<T>(cstream, n, d_off, nlev, bins, q.R, sym, qside, st);
+  } else if (phase == CE_ALL) {
+    // decomposition with fused quantization; the chunks that lie wholly in
+    // the finest level are counted on a side stream as soon as that level's
+    // symbols are written, while the coarser levels decompose
+    const uint64_t k1 = std::min<uint64_t>((h.level_off[h.L] + o.chunk - 1) / o.chunk, nch);
+    launch_fill_u64(hist, (uint64_t)o.dict, 0, st);
+    SideStream side;
+    const std::function<void()> fine_written = [&] {
+      side.fork(st);
+      launch_histogram_chunks(sym, n, o.dict, o.chunk, k1, nch, hist, chunk_esc,
+                              reinterpret_cast<uint32_t*>(&misc[2]), side.s);
+      side.record_join();
+    };
+    decompose<T>(h, table, d_in, nullptr, &q, dscratch, st, &fine_written);
+    launch_histogram_chunks(sym, n, o.dict, o.chunk, 0, k1, hist, chunk_esc, reinterpret_cast<uint32_t*>(&misc[2]),
+                            st);
+    side.join(st);
   } else {
-    // decomposition with fused quantization
     decompose<T>(h, table, d_in, nullptr, &q, dscratch, st);
   }
 
   // lossless stage, tables written in place
-  launch_histogram(sym, n, o.dict, o.chunk, hist, chunk_esc, reinterpret_cast<uint32_t*>(&misc[2]), st);
+  if (o.alloc == MGARD_ALLOC_LEARNED || phase != CE_ALL)
+    launch_histogram(sym, n, o.dict, o.chunk, hist, chunk_esc, reinterpret_cast<uint32_t*>(&misc[2]), st);
   if (phase == CE_FRONT) return fin;
   launch_codebook(hist, o.dict, code_len, codes, enc_scratch, st);
   }

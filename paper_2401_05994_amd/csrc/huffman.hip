@@ -46,7 +46,8 @@ __device__ inline void load4_symbols(const uint16_t* __restrict__ sym, uint64_t 
 }
 
 __global__ void __launch_bounds__(WAVE_T) k_histogram(const uint16_t* __restrict__ sym, uint64_t n, int dict,
-                                                      int chunk, uint64_t nch, unsigned long long* __restrict__ hist,
+                                                      int chunk, uint64_t k0, uint64_t nch,
+                                                      unsigned long long* __restrict__ hist,
                                                       uint32_t* __restrict__ chunk_esc,
                                                       uint32_t* __restrict__ status) {
   __shared__ uint32_t sh[MAXDICT];
@@ -55,7 +56,7 @@ __global__ void __launch_bounds__(WAVE_T) k_histogram(const uint16_t* __restrict
   const int lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * WAVES;
   bool bad = false;
-  for (uint64_t k = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); k < nch; k += stride) {
+  for (uint64_t k = k0 + (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); k < nch; k += stride) {
     const uint64_t beg = k * (uint64_t)chunk;
     const uint64_t end = min(beg + (uint64_t)chunk, n);
     uint32_t e = 0;
@@ -1315,15 +1316,21 @@ inline unsigned blocks_for(uint64_t nch, unsigned cap) {
 
 }  // namespace
 
+void launch_histogram_chunks(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t k0, uint64_t k1,
+                             uint64_t* hist, uint32_t* chunk_esc, uint32_t* status, hipStream_t st) {
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  k1 = std::min(k1, nch);
+  if (k0 >= k1) return;
+  KernelTimer kt("histogram", st);
+  hipLaunchKernelGGL(k_histogram, dim3(blocks_for((k1 - k0 + WAVES - 1) / WAVES, 256)), dim3(WAVE_T), 0, st, sym,
+                     n, dict, chunk, k0, k1, (unsigned long long*)hist, chunk_esc, status);
+  MG_HIP(hipGetLastError());
+}
+
 void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
                       uint32_t* chunk_esc, uint32_t* status, hipStream_t st) {
-  const uint64_t nch = (n + chunk - 1) / chunk;
   launch_fill_u64(hist, (uint64_t)dict, 0, st);
-  if (nch == 0) return;
-  KernelTimer kt("histogram", st);
-  hipLaunchKernelGGL(k_histogram, dim3(blocks_for((nch + WAVES - 1) / WAVES, 256)), dim3(WAVE_T), 0, st, sym, n,
-                     dict, chunk, nch, (unsigned long long*)hist, chunk_esc, status);
-  MG_HIP(hipGetLastError());
+  launch_histogram_chunks(sym, n, dict, chunk, 0, (n + chunk - 1) / chunk, hist, chunk_esc, status, st);
 }
 
 void encode_tables(void* scratch, int dict, uint32_t** enc, uint32_t** maxlen) {

@@ -5,7 +5,9 @@
 
 #include <array>
 #include <cstdint>
+#include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -160,9 +162,11 @@ struct QuantOut {
 };
 template <typename T>
 uint64_t decompose_scratch_bytes(const Hierarchy& h);
+// fine_written (nullable) is called once, on the host, right after the work
+// that writes the finest level's part of the stream has been enqueued on st.
 template <typename T>
 void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, const QuantOut* q,
-               void* scratch, hipStream_t st);
+               void* scratch, hipStream_t st, const std::function<void()>* fine_written = nullptr);
 template <typename T>
 uint64_t recompose_scratch_bytes(const Hierarchy& h);
 template <typename T>
@@ -172,12 +176,31 @@ void recompose(const Hierarchy& h, const T* table, const T* d_stream, const Quan
 template <typename T>
 void launch_thomas_strided(T* data, uint64_t outer, int n, uint64_t inner, DimConsts<T> w, hipStream_t st);
 
+// A side stream per device (default priority, created on first use) with its
+// fork and join events.  One host thread at a time enqueues work through a
+// device's side stream: the lock is held from fork until the object goes away,
+// after the join has been enqueued, so no call waits on another's events.
+class SideStream {
+ public:
+  hipStream_t s = nullptr;
+  void fork(hipStream_t st);   // s waits for the work enqueued on st so far
+  void record_join();          // marks the end of the work enqueued on s
+  void join(hipStream_t st);   // st waits for that work (no-op before a fork)
+
+ private:
+  hipEvent_t ef_ = nullptr, ej_ = nullptr;
+  std::unique_lock<std::mutex> lk_;
+};
+
 // Fused 3D level kernels (transform3d.hip), used when all three sides are decomposed.
 template <typename T>
 bool fused3d_ok(const Hierarchy& h);
+// coeff_written (nullable) is called right after the level's coefficient
+// kernel has been enqueued.
 template <typename T>
 void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T* u, T* ucoarse, T* g1, T* z,
-                             const QuantOut* q, T* cstream, hipStream_t st);
+                             const QuantOut* q, T* cstream, hipStream_t st,
+                             const std::function<void()>* coeff_written = nullptr);
 template <typename T>
 void fused3d_recompose_level(const Hierarchy& h, int l, const T* table, const T* cur, T* out, T* g1, T* z,
                              const QuantOut* q, const T* cstream, hipStream_t st);
@@ -240,6 +263,9 @@ void launch_dequantize(const uint16_t* sym, const int64_t* qside, uint64_t n,
 // Huffman (huffman.hip).
 void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
                       uint32_t* chunk_esc, uint32_t* status, hipStream_t st);
+// Chunks [k0, k1) only, adding into hist (which the caller has cleared).
+void launch_histogram_chunks(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t k0, uint64_t k1,
+                             uint64_t* hist, uint32_t* chunk_esc, uint32_t* status, hipStream_t st);
 // enc_scratch (nullable): the encoder's scratch, whose packed code table and
 // longest length the codebook kernel then fills (see launch_encode's packed).
 void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* codes, void* enc_scratch,

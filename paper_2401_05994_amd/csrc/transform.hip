@@ -17,7 +17,6 @@
 // The order of every rounding is fixed above so that results are
 // reproducible; the library is built with floating-point contraction off.
 #include <algorithm>
-#include <mutex>
 
 #include "internal.hpp"
 
@@ -488,39 +487,6 @@ struct Scratch {
   uint64_t cbar, pa, pb, ga, gb;  // element counts
 };
 
-// A side stream per device (default priority, created on first use) with its
-// fork and join events.  One host thread at a time enqueues work through a
-// device's side stream: the lock is held from fork until the object goes away,
-// after the join has been enqueued, so no call waits on another's events.
-constexpr int SIDE_MAXDEV = 64;
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t ef = nullptr, ej = nullptr;
-  std::unique_lock<std::mutex> lk;
-
-  void fork(hipStream_t st) {
-    static std::mutex mtx[SIDE_MAXDEV];
-    static hipStream_t streams[SIDE_MAXDEV] = {};
-    static hipEvent_t evs[SIDE_MAXDEV][2] = {};
-    int dev = 0;
-    MG_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= SIDE_MAXDEV) fail(MGARD_ERR_DEVICE, "device index beyond the side-stream table");
-    lk = std::unique_lock<std::mutex>(mtx[dev]);
-    if (!streams[dev]) {
-      MG_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
-      MG_HIP(hipEventCreateWithFlags(&evs[dev][0], hipEventDisableTiming));
-      MG_HIP(hipEventCreateWithFlags(&evs[dev][1], hipEventDisableTiming));
-    }
-    s = streams[dev];
-    ef = evs[dev][0];
-    ej = evs[dev][1];
-    MG_HIP(hipEventRecord(ef, st));
-    MG_HIP(hipStreamWaitEvent(s, ef, 0));
-  }
-  void record_join() { MG_HIP(hipEventRecord(ej, s)); }
-  void join(hipStream_t st) { MG_HIP(hipStreamWaitEvent(st, ej, 0)); }
-};
-
 Scratch scratch_counts(const Hierarchy& h) {
   Scratch s{};
   const int L = h.L;
@@ -544,6 +510,34 @@ Scratch scratch_counts(const Hierarchy& h) {
 }
 
 }  // namespace
+
+constexpr int SIDE_MAXDEV = 64;
+
+void SideStream::fork(hipStream_t st) {
+  static std::mutex mtx[SIDE_MAXDEV];
+  static hipStream_t streams[SIDE_MAXDEV] = {};
+  static hipEvent_t evs[SIDE_MAXDEV][2] = {};
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SIDE_MAXDEV) fail(MGARD_ERR_DEVICE, "device index beyond the side-stream table");
+  lk_ = std::unique_lock<std::mutex>(mtx[dev]);
+  if (!streams[dev]) {
+    MG_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+    MG_HIP(hipEventCreateWithFlags(&evs[dev][0], hipEventDisableTiming));
+    MG_HIP(hipEventCreateWithFlags(&evs[dev][1], hipEventDisableTiming));
+  }
+  s = streams[dev];
+  ef_ = evs[dev][0];
+  ej_ = evs[dev][1];
+  MG_HIP(hipEventRecord(ef_, st));
+  MG_HIP(hipStreamWaitEvent(s, ef_, 0));
+}
+
+void SideStream::record_join() { MG_HIP(hipEventRecord(ej_, s)); }
+
+void SideStream::join(hipStream_t st) {
+  if (ej_) MG_HIP(hipStreamWaitEvent(st, ej_, 0));
+}
 
 template <typename T>
 void launch_thomas_strided(T* data, uint64_t outer, int n, uint64_t inner, DimConsts<T> w, hipStream_t st) {
@@ -588,7 +582,12 @@ uint64_t recompose_scratch_bytes(const Hierarchy& h) {
 
 template <typename T>
 void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, const QuantOut* q,
-               void* scratch, hipStream_t st) {
+               void* scratch, hipStream_t st, const std::function<void()>* fine_written) {
+  bool fired = false;
+  auto fire = [&] {
+    if (fine_written && !fired) (*fine_written)();
+    fired = true;
+  };
   Scratch sc = scratch_counts(h);
   Carver cv(scratch);
   T* cbar = cv.take<T>(sc.cbar);
@@ -601,14 +600,16 @@ void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, c
   const int mode = q ? 1 : 0;
   const bool f3 = fused3d_ok<T>(h);
   const int lt = f3 ? fused3d_tail_levels<T>(h) : 0;  // levels 1..lt: one small-level kernel
+  const std::function<void()> fire_fn = fire;
   for (int l = h.L; l > lt && f3; --l) {
-    fused3d_decompose_level<T>(h, l, table, cur, nxt, ga, gb, q, d_stream, st);
+    fused3d_decompose_level<T>(h, l, table, cur, nxt, ga, gb, q, d_stream, st, l == h.L ? &fire_fn : nullptr);
     cur = nxt;
     nxt = (nxt == pa) ? pb : pa;
   }
   if (lt > 0) {
     // the small levels and the coarsest grid
     fused3d_tail_decompose<T>(h, lt, table, cur, q, d_stream, st);
+    fire();
     return;
   }
   for (int l = f3 ? 0 : h.L; l >= 1; --l) {
@@ -623,6 +624,7 @@ void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, c
       hipLaunchKernelGGL((k_coeff<T, 1>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cur, cbar, nxt, nullptr,
                          q->sym, q->qside, q->bins, l, q->R, g, nfine);
     }
+    if (l == h.L) fire();
     T* z = nullptr;
     correction<T>(h, l, table, cbar, ga, gb, &z, st);
     const uint64_t nc = h.count(l - 1);
@@ -639,6 +641,7 @@ void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, c
     hipLaunchKernelGGL((k_coarsest_out<T, 1>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, nullptr, q->sym,
                        q->qside, q->bins, q->R, n0);
   MG_HIP(hipGetLastError());
+  fire();
 }
 
 template <typename T>
@@ -820,7 +823,7 @@ void fused3d_tune(const Hierarchy& h, const T* table, const T* d_in, const Quant
   template uint64_t recompose_scratch_bytes<T>(const Hierarchy&);                                   \
   template void fused3d_tune<T>(const Hierarchy&, const T*, const T*, const QuantOut*, void*, hipStream_t); \
   template void decompose<T>(const Hierarchy&, const T*, const T*, T*, const QuantOut*, void*,      \
-                             hipStream_t);                                                          \
+                             hipStream_t, const std::function<void()>*);                            \
   template void recompose<T>(const Hierarchy&, const T*, const T*, const QuantOut*, T*, void*,      \
                              hipStream_t);
 MG_INST(float)

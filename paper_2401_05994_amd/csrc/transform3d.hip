@@ -1193,7 +1193,8 @@ uint64_t fused3d_scratch_elems(const Hierarchy& h) {
 // coarse grid u_{l-1} into `ucoarse`, using g1 and z scratch.
 template <typename T>
 void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T* u, T* ucoarse, T* g1, T* z,
-                             const QuantOut* q, T* cstream, hipStream_t st) {
+                             const QuantOut* q, T* cstream, hipStream_t st,
+                             const std::function<void()>* coeff_written) {
   Lv3<T> p = lv3<T>(h, l, table);
   const bool fine = l == h.L;
   {
@@ -1210,6 +1211,7 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
       hipLaunchKernelGGL((k3_coeff_r21<T, 0>), grid, dim3(NT), 0, st, u, ucoarse, g1, (uint16_t*)nullptr,
                          (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, seg, p.d0.wl, p.d0.wr);
   }
+  if (coeff_written) (*coeff_written)();
   const uint64_t lines = (uint64_t)p.c1 * p.c2;
   {
     KernelTimer kt(fine ? "r0_thomas0_fine" : "r0_thomas0_coarse", st);
@@ -1348,7 +1350,7 @@ void fused3d_tail_recompose(const Hierarchy& h, int lt, const T* table, T* out, 
   template bool fused3d_ok<T>(const Hierarchy&);                                                               \
   template uint64_t fused3d_scratch_elems<T>(const Hierarchy&);                                                \
   template void fused3d_decompose_level<T>(const Hierarchy&, int, const T*, const T*, T*, T*, T*, const QuantOut*, \
-                                           T*, hipStream_t);                                                   \
+                                           T*, hipStream_t, const std::function<void()>*);                     \
   template void fused3d_recompose_level<T>(const Hierarchy&, int, const T*, const T*, T*, T*, T*, const QuantOut*, \
                                            const T*, hipStream_t);                                             \
   template void fused3d_recompose_correction<T>(const Hierarchy&, int, const T*, T*, T*, const QuantOut*,      \
