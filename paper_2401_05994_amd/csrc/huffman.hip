@@ -163,6 +163,29 @@ __device__ inline int merge_split(const uint64_t* keys, int n, int K, int p) {
   return lo;
 }
 
+// First x in [lo, hi) with pred(x) true (hi when there is none), for a pred
+// that is false and then true along the range: the 64 lanes of one wavefront
+// test 64 evenly spaced points per step, so a range of 8192 takes three steps.
+// Every lane returns the same x.
+template <typename P>
+__device__ inline int wave_first(int lo, int hi, P pred) {
+  const int lane = threadIdx.x & 63;
+  while (lo < hi) {
+    const int step = (hi - lo + 63) >> 6;
+    const int x = lo + lane * step;
+    const uint64_t m = __ballot(x >= hi || pred(x));
+    if (m == 0) {  // every point tested is false, the last one below hi
+      lo += 63 * step + 1;
+      continue;
+    }
+    const int f = __ffsll((unsigned long long)m) - 1;
+    if (f == 0) return lo;
+    hi = min(lo + f * step, hi);
+    lo += (f - 1) * step + 1;
+  }
+  return lo;
+}
+
 // One workgroup of 1024 threads; everything stays in LDS.  keys: (count << 16
 // | symbol), empty bins sort last.  The merge builds internal nodes in
 // batches (see below); internal-node depths come from pointer jumping, leaf
@@ -253,8 +276,10 @@ __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist
     for (;;) {
       const int K = merge_k;
       if (K >= n - 1) break;
-      if (t == 0) {
-        int a = merge_split(keys, n, K, 2 * K), b = 2 * K - a;
+      if (t < 64) {
+        // the first wavefront finds where node K enters the merge
+        const int p = 2 * K;
+        int a = wave_first(max(0, p - K), min(p, n), [&](int x) { return keys[x] > keys[p - x - 1]; }), b = p - a;
         uint64_t w = 0;
         for (int pick = 0; pick < 2; ++pick) {
           if (a < n && (b >= K || keys[a] <= keys[b]))
@@ -263,21 +288,14 @@ __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist
             w += keys[b++];
         }
         // leaves of weight <= w: those below slot K all are (they come before node K)
-        int lo = K, hi = n;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (keys[mid] <= w)
-            lo = mid + 1;
-          else
-            hi = mid;
-        }
+        const int lo = wave_first(K, n, [&](int x) { return keys[x] > w; });
         const int enter = K + lo;  // merge position of node K
         const int B = min(max(1, (enter - 2 * K) / 2), n - 1 - K);
         if (B >= MERGE_SEQ_MIN) {
-          merge_b = B;
-        } else {
-          a = merge_split(keys, n, K, 2 * K);
-          b = 2 * K - a;
+          if (t == 0) merge_b = B;
+        } else if (t == 0) {
+          a = merge_split(keys, n, K, p);
+          b = p - a;
           const int end = min(K + MERGE_SEQ_RUN, n - 1);
           for (int node = K; node < end; ++node) {
             uint64_t v = 0;
@@ -297,38 +315,34 @@ __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist
       __syncthreads();
       const int B = merge_b;
       if (B > 0) {
+        // thread t builds nodes K + j0 .. K + j0 + m - 1: one split search for
+        // the first, then the next 2m merge items in order
+        const int m = (B + nt - 1) / nt;
+        const int j0 = t * m;
         uint64_t w[MERGE_PER];
-        int c0[MERGE_PER], c1[MERGE_PER];
+        if (j0 < B) {
+          const int p = 2 * (K + j0);
+          int a = merge_split(keys, n, K, p), b = p - a;
 #pragma unroll
-        for (int q = 0; q < MERGE_PER; ++q) {
-          const int j = t + q * nt;
-          w[q] = 0;
-          c0[q] = c1[q] = -1;
-          if (j < B) {
-            const int p = 2 * (K + j);
-            int a = merge_split(keys, n, K, p), b = p - a;
-            for (int pick = 0; pick < 2; ++pick) {
-              if (a < n && (b >= K || keys[a] <= keys[b])) {
-                w[q] += keys[a++];
-              } else {
-                if (pick == 0)
-                  c0[q] = b;
-                else
-                  c1[q] = b;
-                w[q] += keys[b++];
+          for (int q = 0; q < MERGE_PER; ++q) {
+            w[q] = 0;
+            if (q < m && j0 + q < B) {
+              for (int pick = 0; pick < 2; ++pick) {
+                if (a < n && (b >= K || keys[a] <= keys[b])) {
+                  w[q] += keys[a++];
+                } else {
+                  par[b] = (uint16_t)(K + j0 + q);
+                  w[q] += keys[b++];
+                }
               }
             }
           }
         }
         __syncthreads();
+        if (j0 < B) {
 #pragma unroll
-        for (int q = 0; q < MERGE_PER; ++q) {
-          const int j = t + q * nt;
-          if (j < B) {
-            keys[K + j] = w[q];
-            if (c0[q] >= 0) par[c0[q]] = (uint16_t)(K + j);
-            if (c1[q] >= 0) par[c1[q]] = (uint16_t)(K + j);
-          }
+          for (int q = 0; q < MERGE_PER; ++q)
+            if (q < m && j0 + q < B) keys[K + j0 + q] = w[q];
         }
       }
       if (t == 0) merge_k = K + (B > 0 ? B : -B);
