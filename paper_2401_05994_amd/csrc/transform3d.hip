@@ -262,24 +262,49 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
   const bool ok2 = jx < CX && j2 < p.c2;
   RestrictW<T> rw2;
   if (ok2) rw2.load(j2, p.c2, n2, p.d2);
+  // Row tests as bit masks (the same for every lane of a wavefront): bit j of
+  // m_in: row r0 + j lies in the grid; m_new: it is a new row along dim 1;
+  // m_own: the block owns it; bit k of m_r2: restriction row g4 + 4k lies in
+  // the grid.  The plane loop reads them through an empty asm that claims to
+  // change them, so the tests are made where they are used instead of being
+  // hoisted out of the loop as one scalar register pair each.
+  uint32_t m_in = 0, m_new = 0, m_own = 0, m_r2 = 0;
+#pragma unroll
+  for (int j = 0; j < HR; ++j) {
+    const int f1 = F1 + r0 + j;
+    const bool in = j < nr && f1 >= 0 && f1 < n1;
+    m_in |= in ? 1u << j : 0u;
+    m_new |= in && is_new(f1, n1) ? 1u << j : 0u;
+    m_own |= in && f1 >= o1b && f1 < o1e ? 1u << j : 0u;
+  }
+  constexpr int R2N = (FY + 3) / 4;
+#pragma unroll
+  for (int k = 0; k < R2N; ++k) {
+    const int r = g4 + 4 * k, f1 = F1 + r;
+    m_r2 |= r < FY && f1 >= 0 && f1 < n1 ? 1u << k : 0u;
+  }
+  m_in = __builtin_amdgcn_readfirstlane(m_in);
+  m_new = __builtin_amdgcn_readfirstlane(m_new);
+  m_own = __builtin_amdgcn_readfirstlane(m_own);
+  m_r2 = __builtin_amdgcn_readfirstlane(m_r2);
+  auto bit = [](uint32_t m, int j) { return ((m >> j) & 1u) != 0u; };
 
   // The next plane is loaded into registers while the current one is
   // processed: unconditional loads from clamped addresses, zeroed outside the
   // grid when committed, so no register is written between a load and its use.
   T pre[HR];
+  int row0 = F1 + r0;  // first fine row of this thread (scalar)
   auto prefetch = [&](int f0) {
 #pragma unroll
     for (int j = 0; j < HR; ++j) {
-      const int f1 = min(max(F1 + r0 + j, 0), n1 - 1);
+      const int f1 = min(max(row0 + j, 0), n1 - 1);
       pre[j] = u[(uint64_t)f0 * plane + (uint64_t)f1 * n2 + f2c];
     }
   };
   auto commit = [&](int f0) {
 #pragma unroll
-    for (int j = 0; j < HR; ++j) {
-      const int f1 = F1 + r0 + j;
-      if (j < nr) U[(r0 + j) * PX + x] = (colok && f1 >= 0 && f1 < n1) ? pre[j] : T(0);
-    }
+    for (int j = 0; j < HR; ++j)
+      if (j < nr) U[(r0 + j) * PX + x] = (colok && bit(m_in, j)) ? pre[j] : T(0);
 
     if (t < FY) {
       const int f1 = F1 + t;
@@ -294,8 +319,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
   auto build_b = [&](T* B) {
 #pragma unroll
     for (int j = 0; j < HR; ++j) {
-      const int r = r0 + j, f1 = F1 + r;
-      if (j >= nr || f1 < 0 || f1 >= n1 || is_new(f1, n1) || !colok) continue;
+      const int r = r0 + j;
+      if (!bit(m_in & ~m_new, j) || !colok) continue;
       const int k = r * PX + x;
       B[k] = e2 ? wl2 * U[k - 1] + wr2 * U[k + 1] : U[k];
     }
@@ -303,7 +328,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
 #pragma unroll
     for (int j = 0; j < HR; ++j) {
       const int r = r0 + j, f1 = F1 + r;
-      if (j >= nr || !is_new(f1, n1) || !colok) continue;
+      if (!bit(m_new, j) || !colok) continue;
       const int k = r * PX + x;
       B[k] = w1.wl[f1] * B[k - PX] + w1.wr[f1] * B[k + PX];
     }
@@ -315,15 +340,15 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
     const T w0l = new0 ? d0wl[f0] : T(0), w0r = new0 ? d0wr[f0] : T(0);
 #pragma unroll
     for (int j = 0; j < HR; ++j) {
-      const int r = r0 + j, f1 = F1 + r;
-      if (j >= nr || f1 < 0 || f1 >= n1 || !colok) continue;
+      const int r = r0 + j;
+      if (!bit(m_in, j) || !colok) continue;
       const int k = r * PX + x;
       const T v = U[k];
       const T pi = new0 ? w0l * Bl[k] + w0r * Br[k] : Bl[k];
       const T c = v - pi;
       U[k] = c;
-      if (f1 < o1b || f1 >= o1e || !own2) continue;
-      const bool e1 = is_new(f1, n1);
+      if (!bit(m_own, j) || !own2) continue;
+      const bool e1 = bit(m_new, j);
       if (!new0 && !e1 && !e2) {
         ucoarse[ucb[r] + (uint64_t)cidx(f2)] = v;
       } else {
@@ -338,13 +363,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
     // mass + restriction along dim 2 for every row of the tile, held in
     // registers until every lane is done reading U, then stored in U's place
     // (rows of 64: G2[r * 64 + jx])
-    constexpr int R2N = (FY + 3) / 4;
     T g2v[R2N];
 #pragma unroll
     for (int k = 0; k < R2N; ++k) {
-      const int r = g4 + 4 * k, f1 = F1 + r;
+      const int r = g4 + 4 * k;
       g2v[k] = T(0);
-      if (r < FY && f1 >= 0 && f1 < n1 && ok2) {
+      if (bit(m_r2, k) && ok2) {
         const T* row = U + r * PX - F2;  // row[f2] for fine f2 inside the tile
         g2v[k] = rw2.apply([&](int i) { return row[i]; });
       }
@@ -353,8 +377,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
     T* G2 = U;
 #pragma unroll
     for (int k = 0; k < R2N; ++k) {
-      const int r = g4 + 4 * k, f1 = F1 + r;
-      if (r < FY && f1 >= 0 && f1 < n1 && ok2) G2[r * 64 + jx] = g2v[k];
+      const int r = g4 + 4 * k;
+      if (bit(m_r2, k) && ok2) G2[r * 64 + jx] = g2v[k];
     }
     __syncthreads();
     // mass + restriction along dim 1 -> g1
@@ -396,6 +420,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
   prefetch(cplane);
   commit(cplane);
   while (true) {
+    asm volatile("" : "+s"(m_in), "+s"(m_new), "+s"(m_own), "+s"(m_r2), "+s"(row0));
     if (ckind != 2) build_b(ckind == 0 ? Bp : Bn);
     int xplane = 0, xkind = 0, xj = 0;
     const bool more = task_at(nj, nph, xplane, xkind, xj);
