@@ -143,6 +143,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=145)
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-field batch measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-allocation ratio")
     ap.add_argument("--only-batch", action="store_true", help="run only the 256-field batch measurement")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -275,7 +276,7 @@ def main():
     # the learned allocation on the same field and tolerance (outside the timed region)
     from paper_2401_05994_amd import learned as lrn
 
-    if os.path.exists(lrn.DEFAULT_MODEL):
+    if not args.no_learned and os.path.exists(lrn.DEFAULT_MODEL):
         params, _ = lrn.load()
         model = m.Model(params)
         torch.cuda.synchronize()
