@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
   auto commit = [&](int f0) {
 #pragma unroll
     for (int j = 0; j < HR; ++j)
-      if (j < nr) U[(r0 + j) * PX + x] = (colok && bit(m_in, j)) ? pre[j] : T(0);
+      if (j < nr) U[(r0 + j) * PX + x] = bit(m_in, j) ? pre[j] : T(0);
 
     if (t < FY) {
       const int f1 = F1 + t;
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
 #pragma unroll
     for (int j = 0; j < HR; ++j) {
       const int r = r0 + j;
-      if (!bit(m_in & ~m_new, j) || !colok) continue;
+      if (!bit(m_in & ~m_new, j)) continue;
       const int k = r * PX + x;
       B[k] = e2 ? wl2 * U[k - 1] + wr2 * U[k + 1] : U[k];
     }
@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
 #pragma unroll
     for (int j = 0; j < HR; ++j) {
       const int r = r0 + j, f1 = F1 + r;
-      if (!bit(m_new, j) || !colok) continue;
+      if (!bit(m_new, j)) continue;
       const int k = r * PX + x;
       B[k] = w1.wl[f1] * B[k - PX] + w1.wr[f1] * B[k + PX];
     }
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
 #pragma unroll
     for (int j = 0; j < HR; ++j) {
       const int r = r0 + j;
-      if (!bit(m_in, j) || !colok) continue;
+      if (!bit(m_in, j)) continue;
       const int k = r * PX + x;
       const T v = U[k];
       const T pi = new0 ? w0l * Bl[k] + w0r * Br[k] : Bl[k];
