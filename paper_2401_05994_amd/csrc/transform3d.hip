@@ -260,8 +260,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
   const int jx = t & 63, g4 = __builtin_amdgcn_readfirstlane(t >> 6);
   const int j2 = J2 + jx;
   const bool ok2 = jx < CX && j2 < p.c2;
+  // every lane loads the weights of a column inside the tile (its own, or the
+  // tile's last for lanes past it), so the dim-2 restriction runs unguarded
+  // in LDS; only the g1 store is masked by ok2
   RestrictW<T> rw2;
-  if (ok2) rw2.load(j2, p.c2, n2, p.d2);
+  rw2.load(min(J2 + min(jx, CX - 1), p.c2 - 1), p.c2, n2, p.d2);
   // Row tests as bit masks (the same for every lane of a wavefront): bit j of
   // m_in: row r0 + j lies in the grid; m_new: it is a new row along dim 1;
   // m_own: the block owns it; bit k of m_r2: restriction row g4 + 4k lies in
@@ -368,7 +371,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
     for (int k = 0; k < R2N; ++k) {
       const int r = g4 + 4 * k;
       g2v[k] = T(0);
-      if (bit(m_r2, k) && ok2) {
+      if (bit(m_r2, k)) {
         const T* row = U + r * PX - F2;  // row[f2] for fine f2 inside the tile
         g2v[k] = rw2.apply([&](int i) { return row[i]; });
       }
@@ -378,7 +381,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
 #pragma unroll
     for (int k = 0; k < R2N; ++k) {
       const int r = g4 + 4 * k;
-      if (bit(m_r2, k) && ok2) G2[r * 64 + jx] = g2v[k];
+      if (bit(m_r2, k)) G2[r * 64 + jx] = g2v[k];
     }
     __syncthreads();
     // mass + restriction along dim 1 -> g1
