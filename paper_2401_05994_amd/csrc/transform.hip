@@ -242,10 +242,14 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
     T* line = data + o * (uint64_t)n * inner + k;
     T prev = line[0] * tr[0];
     line[0] = prev;
-    // two buffers: the next group's loads are issued before this group's recurrence
+    // two buffers: the next group's loads are issued before this group's
+    // recurrence.  Indices are clamped into the line and every load is
+    // unconditional, so the wait before a group covers only the older group's
+    // loads (a load under a branch makes the compiler wait for all of them);
+    // the sweeps use only values whose index lies in the line.
     auto load_f = [&](int i0, T* v) {
 #pragma unroll
-      for (int q = 0; q < G; ++q) v[q] = i0 + q < n ? line[(uint64_t)(i0 + q) * inner] : T(0);
+      for (int q = 0; q < G; ++q) v[q] = line[(uint64_t)min(i0 + q, n - 1) * inner];
     };
     auto fwd = [&](int i0, const T* v) {
       if (i0 + G <= n) {  // whole group: one straight block, weight loads issued together
@@ -278,7 +282,7 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
     T x = prev;
     auto load_b = [&](int i0, T* v) {
 #pragma unroll
-      for (int q = 0; q < G; ++q) v[q] = i0 - q >= 0 ? line[(uint64_t)(i0 - q) * inner] : T(0);
+      for (int q = 0; q < G; ++q) v[q] = line[(uint64_t)max(i0 - q, 0) * inner];
     };
     auto bwd = [&](int i0, const T* v) {
       if (i0 - (G - 1) >= 0) {

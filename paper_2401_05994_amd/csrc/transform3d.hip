@@ -481,13 +481,17 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
   T prev = T(0);
   // coarse j < c0 - 1 sits at fine 2j: it reads fine rows 2j-2 .. 2j+2
   const int jend = c0 - 1;
-  // fine rows of the group starting at coarse j0 (nothing past the last group)
+  // fine rows of the group starting at coarse j0, from row indices clamped
+  // into the grid: every load is unconditional, so the wait before a group
+  // covers only the older group's loads (a load under a branch makes the
+  // compiler wait for all of them).  The sweeps read only rows whose fine
+  // index lies in the grid, so the clamped copies are never used.
   auto load_rows = [&](int j0, T* rows) {
     const int r0 = 2 * j0 - 2;
 #pragma unroll
     for (int q = 0; q < 2 * SWEEP + 3; ++q) {
-      const int r = r0 + q;
-      rows[q] = (j0 < jend && r >= 0 && r < n0 && q <= 2 * (jend - 1 - j0) + 4) ? g[(uint64_t)r * lines] : T(0);
+      const int r = min(max(r0 + q, 0), n0 - 1);
+      rows[q] = g[(uint64_t)r * lines];
     }
   };
   auto forward = [&](int j0, const T* rows) {
@@ -556,11 +560,11 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
     zz[(uint64_t)j * lines] = prev;
   }
   T x = prev;
-  auto load_z = [&](int j1, T* v) {
+  auto load_z = [&](int j1, T* v) {  // clamped and unconditional, as above
 #pragma unroll
     for (int u = 0; u < SWEEP; ++u) {
-      const int j = j1 - u;
-      v[u] = j >= 0 ? zz[(uint64_t)j * lines] : T(0);
+      const int j = max(j1 - u, 0);
+      v[u] = zz[(uint64_t)j * lines];
     }
   };
   auto backward = [&](int j1, const T* v) {
