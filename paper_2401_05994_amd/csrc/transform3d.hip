@@ -798,6 +798,17 @@ constexpr int IA_ROWS = 8;
 constexpr int IA_CR = IA_ROWS / 2 + 1;
 constexpr int IA_XP = NT;  // column pairs per block
 
+// Loads that are issued under a branch, or whose result is merged with a
+// default right away, make the compiler wait for every outstanding memory
+// operation (stores included) before going on.  So every load below is
+// unconditional, from an index clamped into its array (position 0 stands in
+// for a node without a coefficient), and conditions are applied where the
+// values are used; the coarse rows are loaded into registers first, while the
+// row tables are set up; escape symbols (whose values live in the side array)
+// are patched after every row has been stored, so no row waits for the
+// stores of the rows before it.
+constexpr int IA_CS = (2 * IA_CR * (IA_XP + 1) + NT - 1) / NT;  // coarse values per thread
+
 template <typename T, int MODE>
 __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T* __restrict__ uc,
                                                     const uint16_t* __restrict__ sym, const int64_t* __restrict__ qside,
@@ -823,69 +834,88 @@ __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T
   const int last = R0 + nrow - 1;
   const int hi = is_new(last, n1) ? (last >> 1) + 1 : cidx(last);
   const int ncr = hi - lo + 1;
+  // coarse rows lo..hi of planes q0 (and q0 + 1 for a new plane), columns of the tile
+  const int npl = e0 ? 2 : 1;
+  const int per = ncr * ncol;
+  T cvals[IA_CS];
+#pragma unroll
+  for (int it = 0; it < IA_CS; ++it) {
+    const int k = min(t + it * NT, npl * per - 1);
+    const int a = k / per, rem = k - a * per;
+    const int rr = rem / ncol, j = rem - rr * ncol;
+    cvals[it] = uc[((uint64_t)(q0 + a) * c1 + (uint64_t)(lo + rr)) * c2 + (uint64_t)(X0 + j)];
+  }
   load_sub(subs, p.sub, p.level_off);
   __syncthreads();
-  if (t < nrow) {
-    const int f1 = R0 + t;
-    const bool e1 = is_new(f1, n1);
-    rb0[t] = row_base(subs, f0, n0, f1, n1, 0);
-    rb1[t] = row_base(subs, f0, n0, f1, n1, 1);
-    obs[t] = ((uint64_t)f0 * n1 + f1) * n2;
-    w1s[t][0] = e1 ? p.d1.wl[f1] : T(0);
-    w1s[t][1] = e1 ? p.d1.wr[f1] : T(0);
-    kbs[t] = (e1 ? (f1 >> 1) : cidx(f1)) - lo;
-  }
-  // this lane's pair, its dim-2 weights, and whether it also owns the last column
+  // this lane's pair, its dim-2 weights (read only where fb is new), and
+  // whether it also owns the last column
   const int q = t, qq = X0 + q;
   const bool live = q < np;
   const int fa = 2 * qq, fb = fa + 1;
   const bool nb = live && is_new(fb, n2);
-  const T wl2 = nb ? p.d2.wl[fb] : T(0), wr2 = nb ? p.d2.wr[fb] : T(0);
+  const int fbc = min(fb, n2 - 1);
+  const T wl2 = p.d2.wl[fbc], wr2 = p.d2.wr[fbc];
   const bool extra = live && (n2 & 1) && qq == npairs - 1;  // column n2 - 1 = fb + 1
+  if (t < nrow) {
+    const int f1 = R0 + t;
+    const bool e1 = is_new(f1, n1);
+    const T a1 = p.d1.wl[f1], b1 = p.d1.wr[f1];
+    rb0[t] = row_base(subs, f0, n0, f1, n1, 0);
+    rb1[t] = row_base(subs, f0, n0, f1, n1, 1);
+    obs[t] = ((uint64_t)f0 * n1 + f1) * n2;
+    w1s[t][0] = e1 ? a1 : T(0);
+    w1s[t][1] = e1 ? b1 : T(0);
+    kbs[t] = (e1 ? (f1 >> 1) : cidx(f1)) - lo;
+  }
   __syncthreads();
-  // symbols (or float coefficients) of every row: column fa, column fb, and the extra column
+  // stream positions of row r's coefficients in columns fa, fb and the extra
+  // column (0 where there is none)
+  auto positions = [&](int r, uint64_t& pa, uint64_t& pb, uint64_t& px) {
+    const bool rowok = r < nrow && live;
+    const bool e1 = is_new(R0 + r, n1);
+    const uint64_t base0 = rb0[min(r, nrow - 1)], base1 = rb1[min(r, nrow - 1)];
+    pa = rowok && (e0 || e1) ? base0 + (uint64_t)qq : 0;
+    px = rowok && (e0 || e1) && extra ? base0 + (uint64_t)(qq + 1) : 0;
+    pb = rowok && (nb || e0 || e1) ? (nb ? base1 + (uint64_t)qq : base0 + (uint64_t)(qq + 1)) : 0;
+  };
+  // the symbols (or float coefficients) of every row
   uint16_t sa[IA_ROWS], sb[IA_ROWS], sx[IA_ROWS];
   T ca[IA_ROWS], cb[IA_ROWS], cx[IA_ROWS];
 #pragma unroll
   for (int r = 0; r < IA_ROWS; ++r) {
-    sa[r] = sb[r] = sx[r] = 0;
-    ca[r] = cb[r] = cx[r] = T(0);
-    if (r >= nrow || !live) continue;
-    const bool e1 = is_new(R0 + r, n1);
-    if (e0 || e1) {
-      const uint64_t pa = rb0[r] + (uint64_t)qq;
-      if (MODE == 1) sa[r] = sym[pa]; else ca[r] = cstream[pa];
-      if (extra) {
-        if (MODE == 1) sx[r] = sym[pa + 1]; else cx[r] = cstream[pa + 1];
-      }
-    }
-    if (nb || e0 || e1) {
-      const uint64_t pb = nb ? rb1[r] + (uint64_t)qq : rb0[r] + (uint64_t)(qq + 1);
-      if (MODE == 1) sb[r] = sym[pb]; else cb[r] = cstream[pb];
+    uint64_t pa, pb, px;
+    positions(r, pa, pb, px);
+    if (MODE == 1) {
+      sa[r] = sym[pa];
+      sb[r] = sym[pb];
+      sx[r] = sym[px];
+    } else {
+      ca[r] = cstream[pa];
+      cb[r] = cstream[pb];
+      cx[r] = cstream[px];
     }
   }
-  // coarse rows lo..hi of planes q0 (and q0 + 1 for a new plane), columns of the tile
-  {
-    const int npl = e0 ? 2 : 1;
-    const int per = ncr * ncol;
-    for (int k = t; k < npl * per; k += NT) {
+#pragma unroll
+  for (int it = 0; it < IA_CS; ++it) {
+    const int k = t + it * NT;
+    if (k < npl * per) {
       const int a = k / per, rem = k - a * per;
       const int rr = rem / ncol, j = rem - rr * ncol;
-      Cs[a][rr][j] = uc[((uint64_t)(q0 + a) * c1 + (uint64_t)(lo + rr)) * c2 + (uint64_t)(X0 + j)];
+      Cs[a][rr][j] = cvals[it];
     }
   }
   __syncthreads();
   if (!live) return;
   const double b = MODE == 1 ? bins[level] : 0.0;
   const T w0l = e0 ? p.d0.wl[f0] : T(0), w0r = e0 ? p.d0.wr[f0] : T(0);
-  auto coef = [&](uint16_t s, T cf, uint64_t pos) -> T {
+  // the coefficient of a symbol; an escape (0) reads the side array only when
+  // `side` is set (the patch pass) and stands in as 0 otherwise
+  auto coef = [&](uint16_t s, T cf, uint64_t pos, bool side) -> T {
     if (MODE == 0) return cf;
-    const double qv = s ? (double)((int)s - R) : (double)qside[pos];
+    const double qv = s ? (double)((int)s - R) : side ? (double)qside[pos] : 0.0;
     return static_cast<T>(qv * b);
   };
-#pragma unroll
-  for (int r = 0; r < IA_ROWS; ++r) {
-    if (r >= nrow) continue;
+  auto row = [&](int r, bool side) {
     const bool e1 = is_new(R0 + r, n1);
     const int kb = kbs[r];
     const T w1l = w1s[r][0], w1r = w1s[r][1];
@@ -900,23 +930,42 @@ __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T
     auto W = [&](auto&& Vf, int a) -> T { return e1 ? w1l * Vf(a, 0) + w1r * Vf(a, 1) : Vf(a, 0); };
     auto PI = [&](auto&& Vf) -> T { return e0 ? w0l * W(Vf, 0) + w0r * W(Vf, 1) : W(Vf, 0); };
     const uint64_t o = obs[r] + fa;
+    uint64_t pa = 0, pb = 0, px = 0;
+    if (side) positions(r, pa, pb, px);
     // column fa: coarse along dim 2
     if (!e0 && !e1)
       out[o] = Cs[0][kb][q];
     else
-      out[o] = coef(sa[r], ca[r], rb0[r] + (uint64_t)qq) + PI(Va);
+      out[o] = coef(sa[r], ca[r], pa, side) + PI(Va);
     // column fb: new along dim 2, or the last (coarse) column of an even side
     if (!nb && !e0 && !e1)
       out[o + 1] = Cs[0][kb][q + 1];
     else
-      out[o + 1] = coef(sb[r], cb[r], nb ? rb1[r] + (uint64_t)qq : rb0[r] + (uint64_t)(qq + 1)) + PI(Vb);
+      out[o + 1] = coef(sb[r], cb[r], pb, side) + PI(Vb);
     // the last column of an odd side (coarse along dim 2)
     if (extra) {
       if (!e0 && !e1)
         out[o + 2] = Cs[0][kb][q + 1];
       else
-        out[o + 2] = coef(sx[r], cx[r], rb0[r] + (uint64_t)(qq + 1)) + PI(Vx);
+        out[o + 2] = coef(sx[r], cx[r], px, side) + PI(Vx);
     }
+  };
+  uint32_t esc = 0;  // rows of this lane with an escape among its coefficients
+#pragma unroll
+  for (int r = 0; r < IA_ROWS; ++r) {
+    if (r >= nrow) continue;
+    row(r, false);
+    if (MODE == 1) {
+      const bool e1 = is_new(R0 + r, n1);
+      const bool has = (e0 || e1) && (sa[r] == 0 || (extra && sx[r] == 0));
+      const bool hasb = (nb || e0 || e1) && sb[r] == 0;
+      esc |= has || hasb ? 1u << r : 0u;
+    }
+  }
+  // rewrite the rows that hold an escape, now with their side values
+  if (MODE == 1 && esc) {
+    for (int r = 0; r < IA_ROWS; ++r)
+      if ((esc >> r) & 1u) row(r, true);
   }
 }
 
