@@ -45,6 +45,41 @@ __device__ inline void load4_symbols(const uint16_t* __restrict__ sym, uint64_t 
   }
 }
 
+// The full chunks kb, kb + stride, ... below kfull of one wavefront (chunk a
+// multiple of 256, at most 1024): each lane holds four 8-byte groups of a
+// chunk (step s: symbols beg + 256 s + 4 lane .. + 3).  The next chunk's
+// loads are issued before the current chunk is processed and its result
+// stored, and no load is under a branch (steps past the chunk's end re-read
+// its last step and are not used; the chunk index past the end is clamped),
+// so a wait covers only loads issued one chunk earlier and never a store.
+// body(k, v) handles chunk k from v and stores its result from every lane.
+template <typename F>
+__device__ inline void walk_full_chunks(const uint16_t* __restrict__ sym, int chunk, uint64_t kb, uint64_t kfull,
+                                        uint64_t stride, int lane, F&& body) {
+  if (kb >= kfull) return;
+  auto load = [&](uint64_t k, uint2 (&v)[4]) {
+    const uint64_t beg = min(k, kfull - 1) * (uint64_t)chunk + 4 * (uint64_t)lane;
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+      v[st] = *reinterpret_cast<const uint2*>(sym + beg + (uint64_t)min(256 * st, chunk - 256));
+  };
+  uint2 va[4], vb[4];
+  load(kb, va);
+  for (uint64_t k = kb; k < kfull; k += 2 * stride) {
+    load(k + stride, vb);
+    body(k, va);
+    if (k + stride >= kfull) break;
+    load(k + 2 * stride, va);
+    body(k + stride, vb);
+  }
+}
+
+// symbol j (0..3) of an 8-byte group
+__device__ inline uint32_t group_sym(uint2 g, int j) {
+  const uint32_t w = j < 2 ? g.x : g.y;
+  return (j & 1) ? (w >> 16) : (w & 0xffffu);
+}
+
 __global__ void __launch_bounds__(WAVE_T) k_histogram(const uint16_t* __restrict__ sym, uint64_t n, int dict,
                                                       int chunk, uint64_t k0, uint64_t nch,
                                                       unsigned long long* __restrict__ hist,
@@ -55,8 +90,37 @@ __global__ void __launch_bounds__(WAVE_T) k_histogram(const uint16_t* __restrict
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+  const uint64_t wave = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
   bool bad = false;
-  for (uint64_t k = k0 + (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); k < nch; k += stride) {
+  // full chunks of at most 1024 symbols: batched, prefetched loads
+  uint64_t kslow = k0 + wave;  // first chunk left to the per-step loop below
+  if (chunk <= 1024) {
+    const uint64_t kfull = min(nch, n / (uint64_t)chunk);
+    const int steps = chunk / 256;
+    walk_full_chunks(sym, chunk, k0 + wave, kfull, stride, lane, [&](uint64_t k, const uint2 (&v)[4]) {
+      uint32_t e = 0;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        if (st >= steps) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t x = group_sym(v[st], j);
+          if (x < (uint32_t)dict)
+            atomicAdd(&sh[x], 1u);
+          else
+            bad = true;  // symbol outside the dictionary
+          e += x == 0;
+        }
+      }
+#pragma unroll
+      for (int d = 32; d; d >>= 1) e += __shfl_xor(e, d);
+      chunk_esc[k] = e;
+    });
+    // the ragged last chunk, if any, goes to the wave whose turn it is
+    kslow = k0 + wave;
+    if (kslow < kfull) kslow += ((kfull - kslow + stride - 1) / stride) * stride;
+  }
+  for (uint64_t k = kslow; k < nch; k += stride) {
     const uint64_t beg = k * (uint64_t)chunk;
     const uint64_t end = min(beg + (uint64_t)chunk, n);
     uint32_t e = 0;
@@ -451,7 +515,27 @@ __global__ void __launch_bounds__(WAVE_T) k_chunk_bits(const uint16_t* __restric
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * WAVES;
-  for (uint64_t k = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); k < nch; k += stride) {
+  const uint64_t wave = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+  // full chunks of at most 1024 symbols: batched, prefetched loads
+  uint64_t kslow = wave;
+  if (chunk <= 1024) {
+    const uint64_t kfull = min(nch, n / (uint64_t)chunk);
+    const int steps = chunk / 256;
+    walk_full_chunks(sym, chunk, wave, kfull, stride, lane, [&](uint64_t k, const uint2 (&v)[4]) {
+      uint32_t b = 0;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        if (st >= steps) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b += lens[group_sym(v[st], j) & mask];
+      }
+#pragma unroll
+      for (int d = 32; d; d >>= 1) b += __shfl_xor(b, d);
+      chunk_bits[k] = b;
+    });
+    if (kslow < kfull) kslow += ((kfull - kslow + stride - 1) / stride) * stride;
+  }
+  for (uint64_t k = kslow; k < nch; k += stride) {
     const uint64_t beg = k * (uint64_t)chunk;
     const uint64_t end = min(beg + (uint64_t)chunk, n);
     uint32_t b = 0;
