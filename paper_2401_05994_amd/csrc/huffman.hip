@@ -74,6 +74,13 @@ __device__ inline void walk_full_chunks(const uint16_t* __restrict__ sym, int ch
   }
 }
 
+// A value the same on every lane of the wavefront, made scalar: loads indexed
+// by it become scalar loads, which do not share the vector-memory counter.
+__device__ inline uint64_t wave_uniform(uint64_t x) {
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+
 // symbol j (0..3) of an 8-byte group
 __device__ inline uint32_t group_sym(uint2 g, int j) {
   const uint32_t w = j < 2 ? g.x : g.y;
@@ -756,66 +763,100 @@ __global__ void __launch_bounds__(ENC_T) k_encode_wave(const uint16_t* __restric
   const int lane = threadIdx.x & 63;
   uint32_t* wb = words[threadIdx.x >> 6];
   const uint64_t stride = (uint64_t)gridDim.x * (ENC_T / 64);
-  for (uint64_t k = (uint64_t)blockIdx.x * (ENC_T / 64) + (threadIdx.x >> 6); k < nch; k += stride) {
-    const uint64_t beg = k * (uint64_t)chunk;
-    const uint64_t end = min(beg + (uint64_t)chunk, n);
-    const uint64_t w0 = word_off[k];
-    const uint32_t nw = (uint32_t)min(word_off[k + 1] - w0, (uint64_t)ENC_WORDS);
+  const uint64_t wave = (uint64_t)blockIdx.x * (ENC_T / 64) + (threadIdx.x >> 6);
+  // chunk k: clear its LDS words; per step of 256 symbols (first symbol i of
+  // this lane, s4 its four symbols, 0xffffffff past the end) pack the codes;
+  // then copy the words out
+  uint64_t w0 = 0, eo = 0;
+  uint32_t nw = 0, base = 0;  // base: chunk bit offset of the step's first symbol
+  auto open_chunk = [&](uint64_t kk) {
+    const uint64_t k = wave_uniform(kk);
+    w0 = word_off[k];
+    nw = (uint32_t)min(word_off[k + 1] - w0, (uint64_t)ENC_WORDS);
     for (uint32_t i = lane; i < nw; i += 64) wb[i] = 0;
     __builtin_amdgcn_wave_barrier();
-    uint32_t base = 0;  // chunk bit offset of this step's first symbol
-    uint64_t eo = outliers ? esc_off[k] : 0;
-    for (uint64_t i0 = beg; i0 < end; i0 += 256) {
-      const uint64_t i = i0 + 4 * (uint64_t)lane;
-      uint32_t s4[4], e4[4];
-      load4_symbols(sym, i, end, s4);
-      uint32_t bits = 0, esc = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        e4[j] = s4[j] != 0xffffffffu ? enc[s4[j] & mask] : 0u;
-        bits += e4[j] & 63u;
-        esc += s4[j] == 0;
-      }
-      uint32_t bi = bits, ei = esc;  // inclusive scans over the wave
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t yb = __shfl_up(bi, d), ye = __shfl_up(ei, d);
-        if (lane >= d) {
-          bi += yb;
-          ei += ye;
-        }
-      }
-      const uint32_t off = base + bi - bits;
-      uint32_t wi = off >> 5;
-      int fill = (int)(off & 31u);
-      uint64_t acc = 0;  // left-aligned at word wi
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int L = (int)(e4[j] & 63u);
-        if (L) {
-          acc |= (uint64_t)(e4[j] >> 6) << (64 - fill - L);
-          fill += L;
-          if (fill >= 32) {
-            if (wi < ENC_WORDS) atomicOr(&wb[wi], (uint32_t)(acc >> 32));
-            acc <<= 32;
-            fill -= 32;
-            ++wi;
-          }
-        }
-      }
-      if (fill > 0 && wi < ENC_WORDS) atomicOr(&wb[wi], (uint32_t)(acc >> 32));
-      if (outliers && esc) {
-        uint64_t o = eo + (ei - esc);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (s4[j] == 0) outliers[o++] = qside[i + j];
-      }
-      eo += __shfl(ei, 63);
-      base += __shfl(bi, 63);
-    }
+    base = 0;
+    eo = outliers ? esc_off[k] : 0;
+  };
+  auto close_chunk = [&]() {
     __builtin_amdgcn_wave_barrier();
     for (uint32_t i = lane; i < nw; i += 64) payload[w0 + i] = wb[i];
     __builtin_amdgcn_wave_barrier();
+  };
+  auto step = [&](uint64_t i, const uint32_t (&s4)[4]) {
+    uint32_t e4[4];
+    uint32_t bits = 0, esc = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      e4[j] = s4[j] != 0xffffffffu ? enc[s4[j] & mask] : 0u;
+      bits += e4[j] & 63u;
+      esc += s4[j] == 0;
+    }
+    uint32_t bi = bits, ei = esc;  // inclusive scans over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t yb = __shfl_up(bi, d), ye = __shfl_up(ei, d);
+      if (lane >= d) {
+        bi += yb;
+        ei += ye;
+      }
+    }
+    const uint32_t off = base + bi - bits;
+    uint32_t wi = off >> 5;
+    int fill = (int)(off & 31u);
+    uint64_t acc = 0;  // left-aligned at word wi
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int L = (int)(e4[j] & 63u);
+      if (L) {
+        acc |= (uint64_t)(e4[j] >> 6) << (64 - fill - L);
+        fill += L;
+        if (fill >= 32) {
+          if (wi < ENC_WORDS) atomicOr(&wb[wi], (uint32_t)(acc >> 32));
+          acc <<= 32;
+          fill -= 32;
+          ++wi;
+        }
+      }
+    }
+    if (fill > 0 && wi < ENC_WORDS) atomicOr(&wb[wi], (uint32_t)(acc >> 32));
+    if (outliers && esc) {
+      uint64_t o = eo + (ei - esc);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (s4[j] == 0) outliers[o++] = qside[i + j];
+    }
+    eo += __shfl(ei, 63);
+    base += __shfl(bi, 63);
+  };
+  // full chunks: batched, prefetched loads (every chunk here is at most 1024)
+  const uint64_t kfull = min(nch, n / (uint64_t)chunk);
+  const int steps = chunk / 256;
+  walk_full_chunks(sym, chunk, wave, kfull, stride, lane, [&](uint64_t k, const uint2 (&v)[4]) {
+    open_chunk(k);
+    const uint64_t beg = k * (uint64_t)chunk + 4 * (uint64_t)lane;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      if (st >= steps) break;
+      const uint32_t s4[4] = {group_sym(v[st], 0), group_sym(v[st], 1), group_sym(v[st], 2), group_sym(v[st], 3)};
+      step(beg + 256 * (uint64_t)st, s4);
+    }
+    close_chunk();
+  });
+  // the ragged last chunk, if any
+  uint64_t kslow = wave;
+  if (kslow < kfull) kslow += ((kfull - kslow + stride - 1) / stride) * stride;
+  for (uint64_t k = kslow; k < nch; k += stride) {
+    const uint64_t beg = k * (uint64_t)chunk;
+    const uint64_t end = min(beg + (uint64_t)chunk, n);
+    open_chunk(k);
+    for (uint64_t i0 = beg; i0 < end; i0 += 256) {
+      const uint64_t i = i0 + 4 * (uint64_t)lane;
+      uint32_t s4[4];
+      load4_symbols(sym, i, end, s4);
+      step(i, s4);
+    }
+    close_chunk();
   }
 }
 
