@@ -592,10 +592,15 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_tiles(const uint32_t* __restric
                                                        uint64_t* __restrict__ off) {
   __shared__ uint64_t sh[SCAN_T];
   const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+  // every load from an index clamped into [0, n), issued before any is used
+  uint32_t raw[SCAN_PER];
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) raw[j] = v[min(base + (uint64_t)j * SCAN_T + threadIdx.x, n - 1)];
   uint64_t s = 0;
+#pragma unroll
   for (int j = 0; j < SCAN_PER; ++j) {
     const uint64_t i = base + (uint64_t)j * SCAN_T + threadIdx.x;
-    if (i < n) s += scan_value<WORDS>(v[i]);
+    if (i < n) s += scan_value<WORDS>(raw[j]);
   }
   uint64_t total;
   block_exclusive_scan(s, sh, &total);
@@ -626,11 +631,14 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(const uint32_t* __restric
   // only thread 0 reads the parked base: it is also the thread that overwrites it
   if (threadIdx.x == 0) tbase_sh = off[tile];
   const uint64_t mine = tile + (uint64_t)threadIdx.x * SCAN_PER;
+  uint32_t raw[SCAN_PER];
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) raw[j] = v[min(mine + j, n - 1)];
   uint64_t x[SCAN_PER];
   uint64_t s = 0;
 #pragma unroll
   for (int j = 0; j < SCAN_PER; ++j) {
-    x[j] = mine + j < n ? scan_value<WORDS>(v[mine + j]) : 0;
+    x[j] = mine + j < n ? scan_value<WORDS>(raw[j]) : 0;
     s += x[j];
   }
   uint64_t total;
@@ -656,10 +664,15 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_tiles2(ScanPair p, uint64_t n) 
   const int y = blockIdx.y;
   const uint32_t* __restrict__ v = p.v[y];
   const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+  // every load from an index clamped into [0, n), issued before any is used
+  uint32_t raw[SCAN_PER];
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) raw[j] = v[min(base + (uint64_t)j * SCAN_T + threadIdx.x, n - 1)];
   uint64_t s = 0;
+#pragma unroll
   for (int j = 0; j < SCAN_PER; ++j) {
     const uint64_t i = base + (uint64_t)j * SCAN_T + threadIdx.x;
-    if (i < n) s += y == 0 ? scan_value<true>(v[i]) : scan_value<false>(v[i]);
+    if (i < n) s += y == 0 ? scan_value<true>(raw[j]) : scan_value<false>(raw[j]);
   }
   uint64_t total;
   block_exclusive_scan(s, sh, &total);
@@ -691,11 +704,14 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply2(ScanPair p, uint64_t n) 
   const uint64_t tile = (uint64_t)blockIdx.x * SCAN_TILE;
   if (threadIdx.x == 0) tbase_sh = off[tile];
   const uint64_t mine = tile + (uint64_t)threadIdx.x * SCAN_PER;
+  uint32_t raw[SCAN_PER];
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) raw[j] = v[min(mine + j, n - 1)];
   uint64_t x[SCAN_PER];
   uint64_t s = 0;
 #pragma unroll
   for (int j = 0; j < SCAN_PER; ++j) {
-    x[j] = mine + j < n ? (y == 0 ? scan_value<true>(v[mine + j]) : scan_value<false>(v[mine + j])) : 0;
+    x[j] = mine + j < n ? (y == 0 ? scan_value<true>(raw[j]) : scan_value<false>(raw[j])) : 0;
     s += x[j];
   }
   uint64_t total;

@@ -1028,6 +1028,65 @@ __device__ inline TailW<T> tail_stage_weights(T (*ws)[10][TAIL_N], const Lv3<T>&
   return r;
 }
 
+// Every level's weights and sub-grid table in LDS at once (ws[k], subs[k] for
+// a.lv[k]): one batch of loads, from indices clamped into their arrays, for
+// the whole kernel, so no level waits on loads issued after the previous
+// level's stores.
+constexpr int TAIL_WPL = 3 * 10 * TAIL_N;                          // weights per level
+constexpr int TAIL_WIT = (TAIL_LMAX * TAIL_WPL + TAIL_T - 1) / TAIL_T;
+template <typename T>
+__device__ inline void tail_stage_all(T (*ws)[3][10][TAIL_N], uint64_t (*subs)[8][4], const TailLevels<T>& a) {
+  const int t = threadIdx.x;
+  const int total = a.nl * TAIL_WPL;
+  auto where = [&](int e, int& k, int& d, int& q, int& i, int& lim) {
+    k = e / TAIL_WPL;
+    const int r = e - k * TAIL_WPL;
+    d = r / (10 * TAIL_N);
+    q = (r / TAIL_N) % 10;
+    i = r % TAIL_N;
+    const Lv3<T>& p = a.lv[k];
+    const int nf = d == 0 ? p.n0 : d == 1 ? p.n1 : p.n2, nc = d == 0 ? p.c0 : d == 1 ? p.c1 : p.c2;
+    lim = q < 5 ? nf : nc;
+  };
+  T v[TAIL_WIT];
+#pragma unroll
+  for (int it = 0; it < TAIL_WIT; ++it) {
+    int k, d, q, i, lim;
+    where(min(t + it * TAIL_T, total - 1), k, d, q, i, lim);
+    const Lv3<T>& p = a.lv[k];
+    const DimConsts<T>& w = d == 0 ? p.d0 : d == 1 ? p.d1 : p.d2;
+    v[it] = tail_arr(w, q)[min(i, lim - 1)];
+  }
+  uint64_t sv = 0;
+  int sk = 0, sm = 0, se = 0;
+  if (t < a.nl * 32) {
+    sk = t >> 5;
+    sm = (t >> 2) & 7;
+    se = t & 3;
+    const Lv3<T>& p = a.lv[sk];
+    sv = sm == 0 ? 0 : (se == 0 ? p.level_off + p.sub[sm] : p.sub[16 + 4 * sm + se]);
+  }
+#pragma unroll
+  for (int it = 0; it < TAIL_WIT; ++it) {
+    const int e = t + it * TAIL_T;
+    if (e >= total) continue;
+    int k, d, q, i, lim;
+    where(e, k, d, q, i, lim);
+    if (i < lim) ws[k][d][q][i] = v[it];
+  }
+  if (t < a.nl * 32) subs[sk][sm][se] = sv;
+}
+template <typename T>
+__device__ inline TailW<T> tail_weights(T (*ws)[10][TAIL_N]) {
+  TailW<T> r;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    r.d[d] = DimConsts<T>{ws[d][0], ws[d][1], ws[d][2], ws[d][3], ws[d][4],
+                          ws[d][5], ws[d][6], ws[d][7], ws[d][8], ws[d][9]};
+  return r;
+}
+constexpr int TAIL_PER = (TAIL_F + TAIL_T - 1) / TAIL_T;  // fine nodes per thread
+
 // Thomas along one line (n values `stride` apart), as k_thomas
 template <typename T>
 __device__ inline void tail_thomas(T* base, int n, int stride, const DimConsts<T>& w) {
@@ -1095,12 +1154,20 @@ __global__ void __launch_bounds__(TAIL_T) k3_tail_decompose(const T* __restrict_
                                                            const double* __restrict__ bins, int R, int lt,
                                                            TailLevels<T> a) {
   __shared__ T A[TAIL_F], B[TAIL_C], C[TAIL_F], G[TAIL_G2];
-  __shared__ T WS[3][10][TAIL_N];
-  __shared__ uint64_t subs[8][4];
+  __shared__ T WS[TAIL_LMAX][3][10][TAIL_N];
+  __shared__ uint64_t SUBS[TAIL_LMAX][8][4];
   const int t = threadIdx.x;
   {
+    // the fine grid: every load issued (clamped index) before any store
     const Lv3<T>& p = a.lv[0];
-    for (int e = t; e < p.n0 * p.n1 * p.n2; e += TAIL_T) A[e] = u[e];
+    const int nf = p.n0 * p.n1 * p.n2;
+    T v[TAIL_PER];
+#pragma unroll
+    for (int it = 0; it < TAIL_PER; ++it) v[it] = u[min(t + it * TAIL_T, nf - 1)];
+    tail_stage_all<T>(WS, SUBS, a);
+#pragma unroll
+    for (int it = 0; it < TAIL_PER; ++it)
+      if (t + it * TAIL_T < nf) A[t + it * TAIL_T] = v[it];
   }
   T* U = A;   // fine grid of the current level
   T* UC = B;  // its coarse grid
@@ -1109,8 +1176,8 @@ __global__ void __launch_bounds__(TAIL_T) k3_tail_decompose(const T* __restrict_
     const Lv3<T>& p = a.lv[k];
     const int level = lt - k;
     const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
-    load_sub(subs, p.sub, p.level_off);
-    const TailW<T> w = tail_stage_weights<T>(WS, p);
+    const uint64_t (*subs)[4] = SUBS[k];
+    const TailW<T> w = tail_weights<T>(WS[k]);
     __syncthreads();
     const double inv_b = MODE == 1 ? 1.0 / bins[level] : 0.0;
     // coefficients (interpolant nested with dim 2 innermost), quantization, coarse copy
@@ -1167,11 +1234,12 @@ __global__ void __launch_bounds__(TAIL_T) k3_tail_recompose(T* __restrict__ out,
                                                            const double* __restrict__ bins, int R, int lt,
                                                            TailLevels<T> a) {
   __shared__ T P0[TAIL_C], P1[TAIL_C], C[TAIL_F], G[TAIL_G2], G1[TAIL_G1];
-  __shared__ T WS[3][10][TAIL_N];
-  __shared__ uint64_t subs[8][4];
+  __shared__ T WS[TAIL_LMAX][3][10][TAIL_N];
+  __shared__ uint64_t SUBS[TAIL_LMAX][8][4];
   const int t = threadIdx.x;
   T* UC = P0;  // coarse grid of the current level
   T* UF = P1;  // its fine grid (below the last level)
+  tail_stage_all<T>(WS, SUBS, a);
   {
     const Lv3<T>& p = a.lv[0];
     const double b0 = MODE == 1 ? bins[0] : 0.0;
@@ -1183,18 +1251,42 @@ __global__ void __launch_bounds__(TAIL_T) k3_tail_recompose(T* __restrict__ out,
     const int level = lt - a.nl + 1 + k;
     const bool last = k == a.nl - 1;
     const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
-    load_sub(subs, p.sub, p.level_off);
-    const TailW<T> w = tail_stage_weights<T>(WS, p);
+    const uint64_t (*subs)[4] = SUBS[k];
+    const TailW<T> w = tail_weights<T>(WS[k]);
     __syncthreads();
     const double b = MODE == 1 ? bins[level] : 0.0;
-    // coefficients of the level (zeros at coarse nodes)
-    for (int e = t; e < n0 * n1 * n2; e += TAIL_T) {
+    // coefficients of the level (zeros at coarse nodes): every load issued
+    // (position 0 for nodes without one) before any is used
+    const int nf = n0 * n1 * n2;
+    uint64_t pos[TAIL_PER];
+    uint16_t sv[TAIL_PER];
+    T cv[TAIL_PER];
+#pragma unroll
+    for (int it = 0; it < TAIL_PER; ++it) {
+      const int e = t + it * TAIL_T;
+      const int ec = min(e, nf - 1);
+      const int f0 = ec / (n1 * n2), f12 = ec - f0 * (n1 * n2), f1 = f12 / n2, f2 = f12 - f1 * n2;
+      const bool any = is_new(f0, n0) || is_new(f1, n1) || is_new(f2, n2);
+      pos[it] = e < nf && any ? tail_pos(subs, f0, n0, f1, n1, f2, n2) : 0;
+      if (MODE == 1)
+        sv[it] = sym[pos[it]];
+      else
+        cv[it] = cstream[pos[it]];
+    }
+#pragma unroll
+    for (int it = 0; it < TAIL_PER; ++it) {
+      const int e = t + it * TAIL_T;
+      if (e >= nf) continue;
       const int f0 = e / (n1 * n2), f12 = e - f0 * (n1 * n2), f1 = f12 / n2, f2 = f12 - f1 * n2;
       const bool any = is_new(f0, n0) || is_new(f1, n1) || is_new(f2, n2);
       T c = T(0);
       if (any) {
-        const uint64_t pos = tail_pos(subs, f0, n0, f1, n1, f2, n2);
-        c = MODE == 1 ? dequant_load<T>(sym, qside, pos, b, R) : cstream[pos];
+        if (MODE == 1) {
+          const double q = sv[it] ? (double)((int)sv[it] - R) : (double)qside[pos[it]];
+          c = static_cast<T>(q * b);
+        } else {
+          c = cv[it];
+        }
       }
       C[e] = c;
     }
