@@ -30,23 +30,32 @@ __device__ inline uint64_t abs_bits(double x) {
 // max of |x| as ordered bit patterns (NaN patterns sort above infinity)
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_maxabs(const T* __restrict__ d, uint64_t n, uint64_t* out) {
-  // eight independent loads per lane per trip, so a lane waits once per eight elements
+  // Groups of eight loads per lane in two buffers: the next group is in
+  // flight while this one is reduced.  Indices past the end read the last
+  // element again (a max is unchanged by repeats), so no load is under a
+  // branch and none waits for the group after it.
   uint64_t m = 0;
+  if (n == 0) return;
   const uint64_t step = (uint64_t)gridDim.x * TPB;
-  uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x;
-  for (; i + 7 * step < n; i += 8 * step) {
-    T v[8];
+  auto load = [&](uint64_t base, T (&v)[8]) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = d[i + u * step];
+    for (int u = 0; u < 8; ++u) v[u] = d[min(base + u * step, n - 1)];
+  };
+  auto reduce = [&](const T (&v)[8]) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const uint64_t b = abs_bits(v[u]);
       m = b > m ? b : m;
     }
-  }
-  for (; i < n; i += step) {
-    const uint64_t b = abs_bits(d[i]);
-    m = b > m ? b : m;
+  };
+  T va[8], vb[8];
+  uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x;
+  load(i, va);
+  for (; i < n; i += 16 * step) {
+    load(i + 8 * step, vb);
+    reduce(va);
+    load(i + 16 * step, va);
+    reduce(vb);
   }
   __shared__ uint64_t red[TPB];
   red[threadIdx.x] = m;
