@@ -324,6 +324,45 @@ mgard_status mgard_mlp_adam(float* d_params, const float* d_grads, float* d_m, f
                             uint32_t step, float lr, float beta1, float beta2, float eps,
                             const mgard_opts* opts);
 
+/* ----------------------------------------------------------- out-of-core
+ * Compression of a host-resident array larger than device memory (Sec. 2.1,
+ * high-level APIs: out-of-core processing; Sec. 2.2, software architecture:
+ * the array is partitioned into chunks that fit on the device).
+ *
+ * Chunks are slabs of slab_planes planes (>= 3) along dimension 0; a last
+ * slab of fewer than 3 planes joins the one before it.  Every slab is
+ * compressed as a field of its own, in the format of mgard_compress, at the
+ * absolute tolerance of the whole array (MGARD_REL: tol * max |u| over the
+ * array, found in a first streaming pass), so the L-infinity bound holds on
+ * every slab and on the array.  A nonuniform dimension 0 gives each slab its
+ * own coordinates.  Slab k + 1 is copied to the device while slab k is
+ * compressed and slab k - 1 is copied back; h_in and h_out should be pinned
+ * host memory (hipHostMalloc) for the copies to overlap (pageable memory
+ * works, with copies that wait).  Device memory: two slabs, two slab bounds,
+ * and the scratch of one slab, allocated and freed by each call.  The
+ * learned allocation is not offered here (MGARD_ERR_ARG).
+ *
+ * Container (little-endian): 'MGCK', u32 version 1, u32 ndim, u32 dtype,
+ * u64 shape[4] (unused 0), u64 slab_planes, u64 n_slabs, f64 tol, u32 eb,
+ * u32 0, f64 tau_abs, u64 offsets[n_slabs + 1] (byte offset of each slab's
+ * stream; the last is the container's length), then the slab streams.
+ */
+uint64_t mgard_chunked_bound(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,
+                             uint64_t slab_planes, const mgard_opts* opts);
+
+/* h_in: the C-ordered host array; h_out: host buffer of out_capacity bytes
+ * (MGARD_ERR_CAPACITY with *out_bytes = mgard_chunked_bound when short);
+ * *out_bytes: the container's length. */
+mgard_status mgard_compress_chunked(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                                    mgard_dtype dtype, double tol, const void* h_in, uint64_t slab_planes,
+                                    void* h_out, uint64_t out_capacity, uint64_t* out_bytes,
+                                    const mgard_opts* opts);
+
+/* Inverse of mgard_compress_chunked into the host array h_out;
+ * MGARD_ERR_FORMAT for a malformed container or slab stream. */
+mgard_status mgard_decompress_chunked(const void* h_in, uint64_t in_bytes, void* h_out, uint64_t out_capacity,
+                                      const mgard_opts* opts);
+
 /* ----------------------------------------------------------- measurement
  * Kernel timing with HIP events recorded on each launch's stream.
  * mgard_timing(1) clears earlier records and starts recording; (0) clears and

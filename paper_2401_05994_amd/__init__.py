@@ -93,6 +93,9 @@ def load_library():
         "mgard_timing_report": (C.c_int, [C.c_char_p, U64, PU64]),
         "mgard_autotune": (C.c_int, [U32, PU64, P, C.c_int, P, P]),
         "mgard_batch_bound": (U64, [U32, P, P]),
+        "mgard_chunked_bound": (U64, [U32, PU64, P, C.c_int, U64, P]),
+        "mgard_compress_chunked": (C.c_int, [U32, PU64, P, C.c_int, D, P, U64, P, U64, PU64, P]),
+        "mgard_decompress_chunked": (C.c_int, [P, U64, P, U64, P]),
         "mgard_batch_create": (C.c_int, [U32, P, D, P, U64, PU64, P, P, C.POINTER(P)]),
         "mgard_batch_launch": (C.c_int, [P, P]),
         "mgard_batch_free": (None, [P]),
@@ -221,6 +224,49 @@ def mgard_decompress(buf, nbytes, out=None):
     h = mgard_header()
     _check(lib.mgard_decompress(_ptr(buf), int(nbytes), _ptr(out), out.numel() * out.element_size(),
                                 C.byref(o), C.byref(h)))
+    return out
+
+
+def mgard_compress_chunked(u_host, tol, slab_planes, coords=None, eb="rel", dict_size=8192, chunk=1024, out=None):
+    """Out-of-core compression of a CPU tensor (pinned for overlapped copies)
+    in slabs of slab_planes planes along dimension 0.  Returns (uint8 CPU
+    tensor, nbytes)."""
+    torch = _torch()
+    lib = load_library()
+    if u_host.is_cuda:
+        raise ValueError("mgard_compress_chunked takes a host (CPU) tensor")
+    u_host = u_host.contiguous()
+    dt = _dtype_code(u_host)
+    shape = tuple(u_host.shape)
+    cc = _Coords(coords, len(shape))
+    o = make_opts(eb, "plain", dict_size, chunk)
+    bound = lib.mgard_chunked_bound(len(shape), _shape(shape), cc.ptr, dt, int(slab_planes), C.byref(o))
+    if bound == 0:
+        _check(-1)
+    if out is None:
+        out = torch.empty(bound, dtype=torch.uint8, pin_memory=True)
+    nbytes = C.c_uint64(0)
+    _check(lib.mgard_compress_chunked(len(shape), _shape(shape), cc.ptr, dt, float(tol), _ptr(u_host),
+                                      int(slab_planes), _ptr(out), out.numel(), C.byref(nbytes), C.byref(o)))
+    return out, int(nbytes.value)
+
+
+def mgard_decompress_chunked(buf_host, nbytes, out=None):
+    """Inverse of mgard_compress_chunked; returns a CPU tensor (pinned)."""
+    import struct
+
+    torch = _torch()
+    lib = load_library()
+    head = buf_host[:88].numpy().tobytes()
+    if head[:4] != b"MGCK":
+        raise MgardError(-7, "not a chunked container")
+    ndim, dtc = struct.unpack("<II", head[8:16])
+    shape = struct.unpack("<4Q", head[16:48])[:ndim]
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32 if dtc == 0 else torch.float64, pin_memory=True)
+    o = make_opts()
+    _check(lib.mgard_decompress_chunked(_ptr(buf_host), int(nbytes), _ptr(out), out.numel() * out.element_size(),
+                                        C.byref(o)))
     return out
 
 

@@ -15,9 +15,12 @@
 //   80 u64 shape[ndim], f64 coordinates of flagged dimensions, f64 bins[L+1],
 //   u8 code_len[dict], u32 chunk_bits[n_chunks], u32 chunk_esc[n_chunks],
 //   u32 payload[payload_words], zero padding to 8 bytes, i64 outliers[].
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -711,6 +714,292 @@ struct CoordPtrs {
   const double* p[MAXD] = {nullptr, nullptr, nullptr, nullptr};
 };
 
+// ------------------------------------------------------------------ out-of-core
+// A host-resident array in slabs along dimension 0, each compressed as a field
+// of its own at the absolute tolerance of the whole array, behind a container
+// header (layout in include/mgard_hip.h).  Slab k + 1 is copied to the device
+// while slab k is compressed and slab k - 1 copied back, on three streams:
+// copies in (cs), compute (the caller's stream), copies out (ds).
+constexpr uint32_t kChunkMagic = 0x4B43474Du;  // "MGCK"
+constexpr uint64_t kChunkFixed = 88;
+
+struct Slabs {
+  std::vector<uint64_t> p0, p1;
+  uint64_t size() const { return p0.size(); }
+};
+
+Slabs slab_plan(uint64_t n0, uint64_t slab) {
+  if (slab < 3) fail(MGARD_ERR_ARG, "slab_planes must be at least 3");
+  Slabs s;
+  for (uint64_t p = 0; p < n0; p += slab) {
+    s.p0.push_back(p);
+    s.p1.push_back(std::min(p + slab, n0));
+  }
+  // a last slab of fewer than 3 planes joins the one before it
+  if (s.size() > 1 && s.p1.back() - s.p0.back() < 3) {
+    s.p1[s.size() - 2] = n0;
+    s.p0.pop_back();
+    s.p1.pop_back();
+  }
+  return s;
+}
+
+// The streams, events and double buffers of one chunked call; everything
+// queued is finished before any of it is released.
+struct Pipeline {
+  hipStream_t cs = nullptr, ds = nullptr, ks = nullptr;
+  hipEvent_t in_done[2] = {nullptr, nullptr}, out_done[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
+  void* a[2] = {nullptr, nullptr};  // device copies of slabs (or of slab streams)
+  void* b[2] = {nullptr, nullptr};  // device results
+  uint64_t* bits = nullptr;
+  explicit Pipeline(hipStream_t st) : ks(st) {
+    MG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    MG_HIP(hipStreamCreateWithFlags(&ds, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i) {
+      MG_HIP(hipEventCreateWithFlags(&in_done[i], hipEventDisableTiming));
+      MG_HIP(hipEventCreateWithFlags(&out_done[i], hipEventDisableTiming));
+      MG_HIP(hipEventCreateWithFlags(&used[i], hipEventDisableTiming));
+    }
+  }
+  void alloc(uint64_t a_bytes, uint64_t b_bytes, uint64_t nbits) {
+    for (int i = 0; i < 2; ++i) {
+      if (hipMalloc(&a[i], std::max<uint64_t>(a_bytes, 256)) != hipSuccess ||
+          hipMalloc(&b[i], std::max<uint64_t>(b_bytes, 256)) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(MGARD_ERR_OOM, "slab buffers");
+      }
+    }
+    if (hipMalloc(&bits, 8 * std::max<uint64_t>(nbits, 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(MGARD_ERR_OOM, "slab maxima");
+    }
+  }
+  ~Pipeline() {
+    if (ks) (void)hipStreamSynchronize(ks);
+    if (cs) (void)hipStreamSynchronize(cs);
+    if (ds) (void)hipStreamSynchronize(ds);
+    for (int i = 0; i < 2; ++i) {
+      if (a[i]) (void)hipFree(a[i]);
+      if (b[i]) (void)hipFree(b[i]);
+      if (in_done[i]) (void)hipEventDestroy(in_done[i]);
+      if (out_done[i]) (void)hipEventDestroy(out_done[i]);
+      if (used[i]) (void)hipEventDestroy(used[i]);
+    }
+    if (bits) (void)hipFree(bits);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (ds) (void)hipStreamDestroy(ds);
+  }
+};
+
+// Per-slab coordinates: dimension 0 starts at the slab's first plane.
+CoordPtrs slab_coords(uint32_t ndim, const double* const* coords, uint64_t p0) {
+  CoordPtrs c;
+  if (coords)
+    for (uint32_t d = 0; d < ndim; ++d) c.p[d] = coords[d] ? coords[d] + (d == 0 ? p0 : 0) : nullptr;
+  return c;
+}
+
+uint64_t chunked_bound(uint32_t ndim, const uint64_t* shape, const double* const* coords, uint64_t slab,
+                       const Opts& o) {
+  const Slabs sp = slab_plan(shape[0], slab);
+  uint64_t total = kChunkFixed + 8 * (sp.size() + 1);
+  std::array<uint64_t, MAXD> cs{};
+  for (uint32_t d = 0; d < ndim; ++d) cs[d] = shape[d];
+  for (uint64_t k = 0; k < sp.size(); ++k) {
+    cs[0] = sp.p1[k] - sp.p0[k];
+    const CoordPtrs cc = slab_coords(ndim, coords, sp.p0[k]);
+    total += bound_of(*get_hierarchy(ndim, cs.data(), coords ? cc.p : nullptr), coords ? cc.p : nullptr, o.dict,
+                      o.chunk);
+  }
+  return total;
+}
+
+template <typename T>
+void compress_chunked_impl(uint32_t ndim, const uint64_t* shape, const double* const* coords, double tol,
+                           const T* h_in, uint64_t slab, char* h_out, uint64_t cap, uint64_t* out_bytes,
+                           const Opts& o0) {
+  const Slabs sp = slab_plan(shape[0], slab);
+  const uint64_t ns = sp.size();
+  uint64_t plane = 1;
+  for (uint32_t d = 1; d < ndim; ++d) plane *= shape[d];
+  const uint64_t head = kChunkFixed + 8 * (ns + 1);
+  if (cap < head) fail(MGARD_ERR_CAPACITY, "output capacity below the container header");
+  std::vector<std::shared_ptr<Hierarchy>> hs(ns);
+  std::vector<CoordPtrs> cps(ns);
+  std::array<uint64_t, MAXD> cshape{};
+  for (uint32_t d = 0; d < ndim; ++d) cshape[d] = shape[d];
+  uint64_t max_in = 0, max_bound = 0;
+  for (uint64_t k = 0; k < ns; ++k) {
+    cshape[0] = sp.p1[k] - sp.p0[k];
+    cps[k] = slab_coords(ndim, coords, sp.p0[k]);
+    hs[k] = get_hierarchy(ndim, cshape.data(), coords ? cps[k].p : nullptr);
+    max_in = std::max(max_in, cshape[0] * plane * sizeof(T));
+    max_bound = std::max(max_bound, bound_of(*hs[k], coords ? cps[k].p : nullptr, o0.dict, o0.chunk));
+  }
+  Pipeline pl(o0.st);
+  pl.alloc(max_in, max_bound, ns);
+  auto copy_in = [&](uint64_t k) {
+    const int s = (int)(k & 1);
+    MG_HIP(hipMemcpyAsync(pl.a[s], h_in + sp.p0[k] * plane, (sp.p1[k] - sp.p0[k]) * plane * sizeof(T),
+                          hipMemcpyHostToDevice, pl.cs));
+    MG_HIP(hipEventRecord(pl.in_done[s], pl.cs));
+  };
+  // pass 1, relative tolerance only: max |u| of every slab
+  double tau = tol;
+  if (o0.eb == MGARD_REL) {
+    for (uint64_t k = 0; k < ns; ++k) {
+      const int s = (int)(k & 1);
+      if (k >= 2) MG_HIP(hipStreamWaitEvent(pl.cs, pl.used[s], 0));  // slab k - 2 is read
+      copy_in(k);
+      MG_HIP(hipStreamWaitEvent(pl.ks, pl.in_done[s], 0));
+      launch_maxabs<T>(static_cast<const T*>(pl.a[s]), (sp.p1[k] - sp.p0[k]) * plane, pl.bits + k, pl.ks);
+      MG_HIP(hipEventRecord(pl.used[s], pl.ks));
+    }
+    std::vector<uint64_t> hb(ns);
+    MG_HIP(hipMemcpyAsync(hb.data(), pl.bits, 8 * ns, hipMemcpyDeviceToHost, pl.ks));
+    MG_HIP(hipStreamSynchronize(pl.ks));
+    MG_HIP(hipStreamSynchronize(pl.cs));
+    uint64_t mb = 0;
+    for (uint64_t v : hb) mb = std::max(mb, v);
+    double maxabs;
+    if (sizeof(T) == 8) {
+      if (mb >= 0x7ff0000000000000ull) fail(MGARD_ERR_NONFINITE, "input holds NaN or infinity");
+      std::memcpy(&maxabs, &mb, 8);
+    } else {
+      if (mb >= 0x7f800000ull) fail(MGARD_ERR_NONFINITE, "input holds NaN or infinity");
+      const uint32_t b32 = (uint32_t)mb;
+      float f;
+      std::memcpy(&f, &b32, 4);
+      maxabs = (double)f;
+    }
+    tau = tol * maxabs;
+    if (!(tau > 0.0)) fail(MGARD_ERR_TOL, "relative tolerance of an all-zero array");
+  }
+  // pass 2: slab k + 1 in while slab k is compressed and slab k - 1 copied out
+  Opts o = o0;
+  o.eb = MGARD_ABS;
+  o.st = pl.ks;
+  std::vector<uint64_t> offs{head};
+  copy_in(0);
+  for (uint64_t k = 0; k < ns; ++k) {
+    const int s = (int)(k & 1);
+    // a[s ^ 1] was last read by slab k - 1, whose compression has returned
+    if (k + 1 < ns) copy_in(k + 1);
+    MG_HIP(hipStreamWaitEvent(pl.ks, pl.in_done[s], 0));
+    if (k >= 2) MG_HIP(hipStreamWaitEvent(pl.ks, pl.out_done[s], 0));  // b[s] copied out
+    uint64_t nb = 0;
+    compress_impl<T>(*hs[k], coords ? cps[k].p : nullptr, tau, static_cast<const T*>(pl.a[s]),
+                     static_cast<char*>(pl.b[s]), &nb, o, nullptr);
+    if (offs.back() + nb > cap) {
+      *out_bytes = chunked_bound(ndim, shape, coords, slab, o0);
+      fail(MGARD_ERR_CAPACITY, "output capacity below mgard_chunked_bound");
+    }
+    MG_HIP(hipMemcpyAsync(h_out + offs.back(), pl.b[s], nb, hipMemcpyDeviceToHost, pl.ds));
+    MG_HIP(hipEventRecord(pl.out_done[s], pl.ds));
+    offs.push_back(offs.back() + nb);
+  }
+  MG_HIP(hipStreamSynchronize(pl.ds));
+  // the container header
+  uint8_t hb[kChunkFixed];
+  std::memset(hb, 0, sizeof(hb));
+  auto put32 = [&](uint64_t at, uint32_t v) { std::memcpy(hb + at, &v, 4); };
+  auto put64 = [&](uint64_t at, uint64_t v) { std::memcpy(hb + at, &v, 8); };
+  put32(0, kChunkMagic);
+  put32(4, 1);
+  put32(8, ndim);
+  put32(12, sizeof(T) == 8 ? 1 : 0);
+  for (uint32_t d = 0; d < ndim; ++d) put64(16 + 8 * d, shape[d]);
+  put64(48, slab);
+  put64(56, ns);
+  std::memcpy(hb + 64, &tol, 8);
+  put32(72, (uint32_t)o0.eb);
+  std::memcpy(hb + 80, &tau, 8);
+  std::memcpy(h_out, hb, kChunkFixed);
+  std::memcpy(h_out + kChunkFixed, offs.data(), 8 * (ns + 1));
+  *out_bytes = offs.back();
+}
+
+struct ChunkHead {
+  uint32_t ndim = 0, dtype = 0;
+  uint64_t shape[MAXD] = {0, 0, 0, 0};
+  uint64_t slab = 0, ns = 0;
+  std::vector<uint64_t> offs;
+};
+
+ChunkHead parse_chunked(const uint8_t* b, uint64_t bytes) {
+  ChunkHead c;
+  if (bytes < kChunkFixed) fail(MGARD_ERR_FORMAT, "buffer shorter than a container header");
+  uint32_t magic, ver;
+  std::memcpy(&magic, b, 4);
+  std::memcpy(&ver, b + 4, 4);
+  if (magic != kChunkMagic || ver != 1) fail(MGARD_ERR_FORMAT, "not a chunked container");
+  std::memcpy(&c.ndim, b + 8, 4);
+  std::memcpy(&c.dtype, b + 12, 4);
+  if (c.ndim < 1 || c.ndim > MAXD || c.dtype > 1) fail(MGARD_ERR_FORMAT, "container shape or dtype");
+  std::memcpy(c.shape, b + 16, 32);
+  std::memcpy(&c.slab, b + 48, 8);
+  std::memcpy(&c.ns, b + 56, 8);
+  const Slabs sp = slab_plan(c.shape[0], c.slab);
+  if (sp.size() != c.ns || bytes < kChunkFixed + 8 * (c.ns + 1)) fail(MGARD_ERR_FORMAT, "container slab table");
+  c.offs.resize(c.ns + 1);
+  std::memcpy(c.offs.data(), b + kChunkFixed, 8 * (c.ns + 1));
+  if (c.offs[0] != kChunkFixed + 8 * (c.ns + 1) || c.offs.back() > bytes) fail(MGARD_ERR_FORMAT, "container offsets");
+  for (uint64_t k = 0; k < c.ns; ++k)
+    if (c.offs[k + 1] < c.offs[k]) fail(MGARD_ERR_FORMAT, "container offsets");
+  return c;
+}
+
+template <typename T>
+void decompress_chunked_impl(const ChunkHead& c, const uint8_t* h_in, T* h_out, const Opts& o0) {
+  const Slabs sp = slab_plan(c.shape[0], c.slab);
+  const uint64_t ns = sp.size();
+  uint64_t plane = 1;
+  for (uint32_t d = 1; d < c.ndim; ++d) plane *= c.shape[d];
+  // every slab's header, read from the host copy
+  std::vector<Parsed> ps(ns);
+  std::vector<std::shared_ptr<Hierarchy>> hs(ns);
+  uint64_t max_in = 0, max_out = 0;
+  for (uint64_t k = 0; k < ns; ++k) {
+    const uint8_t* b = h_in + c.offs[k];
+    const uint64_t len = c.offs[k + 1] - c.offs[k];
+    Parsed& P = ps[k];
+    if (!parse_header(b, len, P)) fail(MGARD_ERR_FORMAT, "truncated slab header");
+    check_bins(P, b);
+    if (P.hd.total_bytes > len || P.hd.ndim != c.ndim || P.hd.dtype != c.dtype ||
+        P.hd.shape[0] != sp.p1[k] - sp.p0[k])
+      fail(MGARD_ERR_FORMAT, "slab header does not match the container");
+    for (uint32_t d = 1; d < c.ndim; ++d)
+      if (P.hd.shape[d] != c.shape[d]) fail(MGARD_ERR_FORMAT, "slab header does not match the container");
+    CoordPtrs cp;
+    for (uint32_t d = 0; d < P.hd.ndim; ++d) cp.p[d] = P.coords[d].empty() ? nullptr : P.coords[d].data();
+    hs[k] = get_hierarchy(P.hd.ndim, P.hd.shape, cp.p);
+    if ((uint32_t)hs[k]->L != P.hd.levels) fail(MGARD_ERR_FORMAT, "level count does not match shape");
+    max_in = std::max(max_in, len);
+    max_out = std::max(max_out, (sp.p1[k] - sp.p0[k]) * plane * sizeof(T));
+  }
+  Pipeline pl(o0.st);
+  pl.alloc(max_in, max_out, 1);
+  Opts o = o0;
+  o.st = pl.ks;
+  auto copy_in = [&](uint64_t k) {
+    const int s = (int)(k & 1);
+    MG_HIP(hipMemcpyAsync(pl.a[s], h_in + c.offs[k], c.offs[k + 1] - c.offs[k], hipMemcpyHostToDevice, pl.cs));
+    MG_HIP(hipEventRecord(pl.in_done[s], pl.cs));
+  };
+  copy_in(0);
+  for (uint64_t k = 0; k < ns; ++k) {
+    const int s = (int)(k & 1);
+    if (k + 1 < ns) copy_in(k + 1);  // a[s ^ 1] was read by slab k - 1, which has returned
+    MG_HIP(hipStreamWaitEvent(pl.ks, pl.in_done[s], 0));
+    if (k >= 2) MG_HIP(hipStreamWaitEvent(pl.ks, pl.out_done[s], 0));
+    decompress_impl<T>(*hs[k], ps[k], static_cast<const char*>(pl.a[s]), static_cast<T*>(pl.b[s]), o);
+    MG_HIP(hipMemcpyAsync(h_out + sp.p0[k] * plane, pl.b[s], (sp.p1[k] - sp.p0[k]) * plane * sizeof(T),
+                          hipMemcpyDeviceToHost, pl.ds));
+    MG_HIP(hipEventRecord(pl.out_done[s], pl.ds));
+  }
+  MG_HIP(hipStreamSynchronize(pl.ds));
+}
+
 }  // namespace
 }  // namespace mg
 
@@ -1388,5 +1677,54 @@ mgard_status mgard_mlp_adam(float* d_params, const float* d_grads, float* d_m, f
     MG_HIP(hipStreamSynchronize(o.st));
   });
 }
+
+uint64_t mgard_chunked_bound(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,
+                             uint64_t slab_planes, const mgard_opts* opts) {
+  uint64_t r = 0;
+  mgard_status st = guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!shape || ndim < 1 || ndim > MAXD) fail(MGARD_ERR_SHAPE, "shape");
+    r = chunked_bound(ndim, shape, coords, slab_planes, o);
+  });
+  return st == MGARD_OK ? r : 0;
+}
+
+mgard_status mgard_compress_chunked(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                                    mgard_dtype dtype, double tol, const void* h_in, uint64_t slab_planes,
+                                    void* h_out, uint64_t out_capacity, uint64_t* out_bytes,
+                                    const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!h_in || !h_out || !out_bytes || !shape) fail(MGARD_ERR_ARG, "null buffer");
+    if (ndim < 1 || ndim > MAXD) fail(MGARD_ERR_SHAPE, "shape");
+    if (!(tol > 0.0) || !std::isfinite(tol)) fail(MGARD_ERR_TOL, "tolerance must be positive and finite");
+    if (o.alloc == MGARD_ALLOC_LEARNED) fail(MGARD_ERR_ARG, "chunked compression takes the plain or count allocation");
+    if (dtype == MGARD_F32)
+      compress_chunked_impl<float>(ndim, shape, coords, tol, static_cast<const float*>(h_in), slab_planes,
+                                   static_cast<char*>(h_out), out_capacity, out_bytes, o);
+    else
+      compress_chunked_impl<double>(ndim, shape, coords, tol, static_cast<const double*>(h_in), slab_planes,
+                                    static_cast<char*>(h_out), out_capacity, out_bytes, o);
+  });
+}
+
+mgard_status mgard_decompress_chunked(const void* h_in, uint64_t in_bytes, void* h_out, uint64_t out_capacity,
+                                      const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!h_in || !h_out) fail(MGARD_ERR_ARG, "null buffer");
+    const ChunkHead c = parse_chunked(static_cast<const uint8_t*>(h_in), in_bytes);
+    uint64_t n = 1;
+    for (uint32_t d = 0; d < c.ndim; ++d) n *= c.shape[d];
+    if (out_capacity < n * (c.dtype ? 8 : 4)) fail(MGARD_ERR_CAPACITY, "output buffer too small");
+    if (c.dtype)
+      decompress_chunked_impl<double>(c, static_cast<const uint8_t*>(h_in), static_cast<double*>(h_out), o);
+    else
+      decompress_chunked_impl<float>(c, static_cast<const uint8_t*>(h_in), static_cast<float*>(h_out), o);
+  });
+}
+
 
 }  // extern "C"

@@ -436,3 +436,49 @@ def test_adam_first_step_is_signed_lr():
     mlp.adam_step(params, grads, m, v, 1, lr=0.1)
     assert np.allclose(params[0][0], [[0.9, -1.9]], atol=1e-7)
     assert np.allclose(params[0][1], [0.4], atol=1e-7)
+
+
+# ----------------------------------------------------------------- out-of-core chunks
+def test_chunked_slab_plan_covers_the_array_in_slabs_of_three_or_more():
+    from oracle import chunked as K
+
+    for n0 in range(3, 70):
+        for slab in (3, 4, 7, 16, 64):
+            b = K.slab_bounds(n0, slab)
+            assert b[0][0] == 0 and b[-1][1] == n0
+            assert all(b[i][1] == b[i + 1][0] for i in range(len(b) - 1))
+            assert all(p1 - p0 >= 3 for p0, p1 in b)
+            assert all(p1 - p0 == slab for p0, p1 in b[:-1])
+            assert b[-1][1] - b[-1][0] < slab + 3  # a remainder below 3 planes joined the last slab
+    with pytest.raises(ValueError):
+        K.slab_bounds(10, 2)
+
+
+def test_chunked_single_slab_is_the_plain_format_at_the_arrays_tolerance():
+    from oracle import chunked as K
+
+    rng = np.random.default_rng(41)
+    u = fieldgen.random_field((12, 9, 10), rng).astype(np.float32)
+    buf = K.compress_chunked(u, 1e-3, 64)
+    c = K.parse_chunked(buf)
+    assert c["n_slabs"] == 1 and c["tau_abs"] == 1e-3 * float(np.abs(u).max())
+    assert buf[c["offsets"][0]:] == codec.compress(u, c["tau_abs"], rel=False)
+
+
+def test_chunked_slabs_share_the_global_tolerance_and_meet_it():
+    from oracle import chunked as K
+
+    rng = np.random.default_rng(42)
+    shape = (23, 11, 9)
+    u = fieldgen.random_field(shape, rng)
+    u[:8] *= 1e-3  # the first slab's own max is far below the array's
+    xs = [fieldgen.random_coords(n, rng) for n in shape]
+    buf = K.compress_chunked(u, 1e-4, 8, coords=xs)
+    c = K.parse_chunked(buf)
+    tau = 1e-4 * float(np.abs(u).max())
+    assert c["tau_abs"] == tau and c["n_slabs"] == 3  # 8 + 8 + 7 planes
+    for k in range(c["n_slabs"]):
+        hd = codec.parse(buf[c["offsets"][k]:c["offsets"][k + 1]])
+        assert hd.tau_abs == tau and not hd.rel
+    r = K.decompress_chunked(buf)
+    assert float(np.abs(r - u).max()) <= tau
