@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -752,6 +753,7 @@ struct Pipeline {
   void* a[2] = {nullptr, nullptr};  // device copies of slabs (or of slab streams)
   void* b[2] = {nullptr, nullptr};  // device results
   uint64_t* bits = nullptr;
+  std::vector<void*> keep;  // slabs kept on the device from the first pass to the second
   explicit Pipeline(hipStream_t st) : ks(st) {
     MG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     MG_HIP(hipStreamCreateWithFlags(&ds, hipStreamNonBlocking));
@@ -786,6 +788,7 @@ struct Pipeline {
       if (used[i]) (void)hipEventDestroy(used[i]);
     }
     if (bits) (void)hipFree(bits);
+    for (void* p : keep) (void)hipFree(p);
     if (cs) (void)hipStreamDestroy(cs);
     if (ds) (void)hipStreamDestroy(ds);
   }
@@ -838,9 +841,33 @@ void compress_chunked_impl(uint32_t ndim, const uint64_t* shape, const double* c
   }
   Pipeline pl(o0.st);
   pl.alloc(max_in, max_bound, ns);
+  // With a relative tolerance every slab is read twice.  The first slabs stay
+  // on the device between the passes, as many as half of the free device
+  // memory holds after this call's other buffers and one slab's scratch, so
+  // only the rest cross the host link a second time.
+  uint64_t nkeep = 0;
+  if (o0.eb == MGARD_REL) {
+    size_t freeb = 0, totalb = 0;
+    MG_HIP(hipMemGetInfo(&freeb, &totalb));
+    const uint64_t other = 4 * max_in + 2 * max_bound;  // one slab's scratch is a few slabs
+    const uint64_t budget = freeb / 2 > other ? freeb / 2 - other : 0;
+    nkeep = std::min<uint64_t>(ns, max_in ? budget / max_in : 0);
+    // MGARD_CHUNKED_KEEP caps the count (a test covers the mixed path with it)
+    if (const char* e = std::getenv("MGARD_CHUNKED_KEEP")) nkeep = std::min<uint64_t>(nkeep, std::strtoull(e, nullptr, 10));
+    for (uint64_t k = 0; k < nkeep; ++k) {
+      void* p = nullptr;
+      if (hipMalloc(&p, std::max<uint64_t>(max_in, 256)) != hipSuccess) {
+        (void)hipGetLastError();
+        nkeep = k;
+        break;
+      }
+      pl.keep.push_back(p);
+    }
+  }
+  auto slab_dev = [&](uint64_t k) -> void* { return k < nkeep ? pl.keep[k] : pl.a[k & 1]; };
   auto copy_in = [&](uint64_t k) {
     const int s = (int)(k & 1);
-    MG_HIP(hipMemcpyAsync(pl.a[s], h_in + sp.p0[k] * plane, (sp.p1[k] - sp.p0[k]) * plane * sizeof(T),
+    MG_HIP(hipMemcpyAsync(slab_dev(k), h_in + sp.p0[k] * plane, (sp.p1[k] - sp.p0[k]) * plane * sizeof(T),
                           hipMemcpyHostToDevice, pl.cs));
     MG_HIP(hipEventRecord(pl.in_done[s], pl.cs));
   };
@@ -852,7 +879,7 @@ void compress_chunked_impl(uint32_t ndim, const uint64_t* shape, const double* c
       if (k >= 2) MG_HIP(hipStreamWaitEvent(pl.cs, pl.used[s], 0));  // slab k - 2 is read
       copy_in(k);
       MG_HIP(hipStreamWaitEvent(pl.ks, pl.in_done[s], 0));
-      launch_maxabs<T>(static_cast<const T*>(pl.a[s]), (sp.p1[k] - sp.p0[k]) * plane, pl.bits + k, pl.ks);
+      launch_maxabs<T>(static_cast<const T*>(slab_dev(k)), (sp.p1[k] - sp.p0[k]) * plane, pl.bits + k, pl.ks);
       MG_HIP(hipEventRecord(pl.used[s], pl.ks));
     }
     std::vector<uint64_t> hb(ns);
@@ -880,15 +907,15 @@ void compress_chunked_impl(uint32_t ndim, const uint64_t* shape, const double* c
   o.eb = MGARD_ABS;
   o.st = pl.ks;
   std::vector<uint64_t> offs{head};
-  copy_in(0);
+  if (nkeep == 0) copy_in(0);
   for (uint64_t k = 0; k < ns; ++k) {
     const int s = (int)(k & 1);
-    // a[s ^ 1] was last read by slab k - 1, whose compression has returned
-    if (k + 1 < ns) copy_in(k + 1);
-    MG_HIP(hipStreamWaitEvent(pl.ks, pl.in_done[s], 0));
+    // a[s ^ 1] was last read by an earlier slab, whose compression has returned
+    if (k + 1 < ns && k + 1 >= nkeep) copy_in(k + 1);
+    if (k >= nkeep) MG_HIP(hipStreamWaitEvent(pl.ks, pl.in_done[s], 0));
     if (k >= 2) MG_HIP(hipStreamWaitEvent(pl.ks, pl.out_done[s], 0));  // b[s] copied out
     uint64_t nb = 0;
-    compress_impl<T>(*hs[k], coords ? cps[k].p : nullptr, tau, static_cast<const T*>(pl.a[s]),
+    compress_impl<T>(*hs[k], coords ? cps[k].p : nullptr, tau, static_cast<const T*>(slab_dev(k)),
                      static_cast<char*>(pl.b[s]), &nb, o, nullptr);
     if (offs.back() + nb > cap) {
       *out_bytes = chunked_bound(ndim, shape, coords, slab, o0);

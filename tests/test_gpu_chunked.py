@@ -87,3 +87,18 @@ def test_chunked_rejects_bad_arguments(lib):
     bad[100:108] = 255  # the slab offset table
     with pytest.raises(lib.MgardError):
         lib.mgard_decompress_chunked(bad, nb)
+
+
+@pytest.mark.parametrize("keep", ["0", "1", "3"])
+def test_chunked_slabs_kept_between_passes_or_not_give_the_same_bytes(lib, monkeypatch, keep):
+    """With a relative tolerance the first slabs stay on the device between the
+    max pass and the compression pass as memory allows; capping that count
+    (none, one, some of the 5 slabs) must not change the bytes."""
+    import torch
+
+    u, coords, slab, tol, rel = _case("3d-60x33x41-f32-slab16")
+    ref = K.compress_chunked(u, tol, 12)
+    monkeypatch.setenv("MGARD_CHUNKED_KEEP", keep)
+    say("keep", keep)
+    buf, nb = lib.mgard_compress_chunked(torch.from_numpy(u).pin_memory(), tol, 12)
+    assert buf[:nb].numpy().tobytes() == ref
