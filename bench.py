@@ -181,6 +181,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=513)
     ap.add_argument("--tol", type=float, default=1e-3)
+    ap.add_argument("--chunk", type=int, default=1024, help="symbols per Huffman chunk (a multiple of 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=145)
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-field batch measurement")
@@ -219,12 +220,12 @@ def main():
     print(f"[bench] generating {n}^3 float32 field", file=sys.stderr, flush=True)
     u = fieldgen.spectral((n, n, n), -5.0 / 3.0, 2, device=dev).to(torch.float32).contiguous()
     in_bytes = u.numel() * 4
-    bound = m.mgard_compress_bound(u.shape, m.F32)
+    bound = m.mgard_compress_bound(u.shape, m.F32, chunk=args.chunk)
     out = torch.empty(bound, dtype=torch.uint8, device=dev)
     rec = torch.empty_like(u)
 
     def step():
-        buf, nb, info = m.mgard_compress(u, args.tol, out=out)
+        buf, nb, info = m.mgard_compress(u, args.tol, chunk=args.chunk, out=out)
         m.mgard_decompress(buf, nb, out=rec)
         return nb, info
 
@@ -243,7 +244,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         a = time.perf_counter()
-        buf, nb, info = m.mgard_compress(u, args.tol, out=out)
+        buf, nb, info = m.mgard_compress(u, args.tol, chunk=args.chunk, out=out)
         b = time.perf_counter()
         m.mgard_decompress(buf, nb, out=rec)
         torch.cuda.synchronize()
