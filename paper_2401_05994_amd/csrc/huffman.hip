@@ -742,6 +742,20 @@ constexpr int ENC_CHUNK = 1024;                          // largest chunk of the
 constexpr int ENC_WORDS = ENC_CHUNK * ENC_MAXLEN / 32;   // its LDS words per wave
 constexpr int ENC_T = 512;
 
+// Inclusive prefix sum over the 64 lanes of a wavefront with DPP moves:
+// shifts by 1, 2, 4 and 8 lanes within each row of 16, then lane 15 of a row
+// added to the row after it (rows 1 and 3) and lane 31 to rows 2 and 3.
+// Lanes without a source read 0.
+__device__ inline uint32_t wave_inclusive_sum(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
 __global__ void __launch_bounds__(1024) k_pack_codes(const uint8_t* __restrict__ len, const uint64_t* __restrict__ codes,
                                                      int dict, uint32_t* __restrict__ enc,
                                                      uint32_t* __restrict__ maxlen_out) {
@@ -808,15 +822,7 @@ __global__ void __launch_bounds__(ENC_T) k_encode_wave(const uint16_t* __restric
       bits += e4[j] & 63u;
       esc += s4[j] == 0;
     }
-    uint32_t bi = bits, ei = esc;  // inclusive scans over the wave
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t yb = __shfl_up(bi, d), ye = __shfl_up(ei, d);
-      if (lane >= d) {
-        bi += yb;
-        ei += ye;
-      }
-    }
+    const uint32_t bi = wave_inclusive_sum(bits), ei = wave_inclusive_sum(esc);
     const uint32_t off = base + bi - bits;
     uint32_t wi = off >> 5;
     int fill = (int)(off & 31u);
@@ -842,8 +848,8 @@ __global__ void __launch_bounds__(ENC_T) k_encode_wave(const uint16_t* __restric
       for (int j = 0; j < 4; ++j)
         if (s4[j] == 0) outliers[o++] = qside[i + j];
     }
-    eo += __shfl(ei, 63);
-    base += __shfl(bi, 63);
+    eo += (uint32_t)__builtin_amdgcn_readlane(ei, 63);
+    base += (uint32_t)__builtin_amdgcn_readlane(bi, 63);
   };
   // full chunks: batched, prefetched loads (every chunk here is at most 1024)
   const uint64_t kfull = min(nch, n / (uint64_t)chunk);
