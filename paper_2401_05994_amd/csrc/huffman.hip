@@ -82,6 +82,25 @@ __device__ inline uint64_t wave_uniform(uint64_t x) {
 }
 
 // symbol j (0..3) of an 8-byte group
+// Inclusive prefix sum over the 64 lanes of a wavefront with DPP moves:
+// shifts by 1, 2, 4 and 8 lanes within each row of 16, then lane 15 of a row
+// added to the row after it (rows 1 and 3) and lane 31 to rows 2 and 3.
+// Lanes without a source read 0.
+__device__ inline uint32_t wave_inclusive_sum(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
+// Sum over the 64 lanes of a wavefront, the same in every lane.
+__device__ inline uint32_t wave_sum(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_inclusive_sum(x), 63);
+}
+
 __device__ inline uint32_t group_sym(uint2 g, int j) {
   const uint32_t w = j < 2 ? g.x : g.y;
   return (j & 1) ? (w >> 16) : (w & 0xffffu);
@@ -119,9 +138,7 @@ __global__ void __launch_bounds__(WAVE_T) k_histogram(const uint16_t* __restrict
           e += x == 0;
         }
       }
-#pragma unroll
-      for (int d = 32; d; d >>= 1) e += __shfl_xor(e, d);
-      chunk_esc[k] = e;
+      chunk_esc[k] = wave_sum(e);
     });
     // the ragged last chunk, if any, goes to the wave whose turn it is
     kslow = k0 + wave;
@@ -536,9 +553,7 @@ __global__ void __launch_bounds__(WAVE_T) k_chunk_bits(const uint16_t* __restric
 #pragma unroll
         for (int j = 0; j < 4; ++j) b += lens[group_sym(v[st], j) & mask];
       }
-#pragma unroll
-      for (int d = 32; d; d >>= 1) b += __shfl_xor(b, d);
-      chunk_bits[k] = b;
+      chunk_bits[k] = wave_sum(b);
     });
     if (kslow < kfull) kslow += ((kfull - kslow + stride - 1) / stride) * stride;
   }
@@ -741,20 +756,6 @@ void launch_scan(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st) {
 constexpr int ENC_CHUNK = 1024;                          // largest chunk of the wave kernel
 constexpr int ENC_WORDS = ENC_CHUNK * ENC_MAXLEN / 32;   // its LDS words per wave
 constexpr int ENC_T = 512;
-
-// Inclusive prefix sum over the 64 lanes of a wavefront with DPP moves:
-// shifts by 1, 2, 4 and 8 lanes within each row of 16, then lane 15 of a row
-// added to the row after it (rows 1 and 3) and lane 31 to rows 2 and 3.
-// Lanes without a source read 0.
-__device__ inline uint32_t wave_inclusive_sum(uint32_t x) {
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);  // row_shr:2
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);  // row_shr:4
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);  // row_shr:8
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  return x;
-}
 
 __global__ void __launch_bounds__(1024) k_pack_codes(const uint8_t* __restrict__ len, const uint64_t* __restrict__ codes,
                                                      int dict, uint32_t* __restrict__ enc,
