@@ -20,6 +20,7 @@ namespace {
 constexpr int TPB = 256;
 constexpr int MAXLEN = 64;
 constexpr int MAXDICT = 8192;  // largest dictionary; all LDS below is static
+constexpr int CB_T = 1024, CB_KPT = MAXDICT / CB_T;  // codebook block; sort keys per thread
 constexpr int ENC_MAXLEN = 26;
 
 // ------------------------------------------------------------------ histogram
@@ -94,6 +95,12 @@ __device__ inline uint32_t wave_inclusive_sum(uint32_t x) {
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return x;
+}
+
+// Lane shuffle of a 64-bit value: lane l reads lane l ^ m (m < 64).
+__device__ inline uint64_t shfl_xor_u64(uint64_t x, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m), hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m);
+  return (uint64_t)hi << 32 | lo;
 }
 
 // Sum over the 64 lanes of a wavefront, the same in every lane.
@@ -320,31 +327,63 @@ __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist
   }
   __syncthreads();
   const int n = nleaf;
-  // bitonic sort of the next power of two >= n keys (padding sorts last), every
-  // thread on one compare-exchange pair per pass
+  // Bitonic sort of the next power of two P >= n keys (padding sorts last).
+  // Thread t holds positions 8t .. 8t+7 in registers: partners closer than 8
+  // are exchanged in registers, partners 8 .. 256 apart sit in the same
+  // wavefront and come through lane shuffles, and only partners 512 or more
+  // apart go through LDS (two barriers a pass).  Positions at or past P never
+  // meet a real key in a stage k <= P, so every thread runs every pass.
   {
     int P = 1;
     while (P < n) P <<= 1;
-    for (int i = n + t; i < P; i += nt) keys[i] = ~0ull;
-    __syncthreads();
+    const int e0 = t * CB_KPT;
+    uint64_t v[CB_KPT];
+#pragma unroll
+    for (int r = 0; r < CB_KPT; ++r) v[r] = e0 + r < n ? keys[e0 + r] : ~0ull;
     for (int k = 2; k <= P; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int q = t; q < P / 2; q += nt) {
-          const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));  // bit j of i clear
-          const int p = i | j;
-          const uint64_t a = keys[i], b = keys[p];
-          if ((a > b) == ((i & k) == 0)) {
-            keys[i] = b;
-            keys[p] = a;
-          }
+      for (int j = k >> 1; j >= CB_KPT; j >>= 1) {
+        uint64_t o[CB_KPT];
+        if (j >= CB_KPT * 64) {
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < CB_KPT; ++r) keys[e0 + r] = v[r];
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < CB_KPT; ++r) o[r] = keys[(e0 + r) ^ j];
+        } else {
+#pragma unroll
+          for (int r = 0; r < CB_KPT; ++r) o[r] = shfl_xor_u64(v[r], j / CB_KPT);
         }
-        __syncthreads();
+        // the partner shares bit k, so the pair's direction is known here
+        const bool up = (e0 & k) == 0, lower = (e0 & j) == 0;
+#pragma unroll
+        for (int r = 0; r < CB_KPT; ++r) v[r] = lower == up ? min(v[r], o[r]) : max(v[r], o[r]);
+      }
+#pragma unroll
+      for (int J = CB_KPT / 2; J; J >>= 1) {
+        if (J >= k) continue;
+#pragma unroll
+        for (int r = 0; r < CB_KPT; ++r) {
+          if (r & J) continue;
+          const bool up = ((e0 + r) & k) == 0;
+          const uint64_t a = v[r], b = v[r | J];
+          const bool sw = (a > b) == up;
+          v[r] = sw ? b : a;
+          v[r | J] = sw ? a : b;
+        }
       }
     }
-  }
-  for (int i = t; i < n; i += nt) {
-    syms[i] = (uint16_t)(keys[i] & 0xffff);
-    keys[i] >>= 16;
+    __syncthreads();  // the last LDS pass's reads are done
+#pragma unroll
+    for (int r = 0; r < CB_KPT; ++r) {
+      const int e = e0 + r;
+      if (e < n) {
+        syms[e] = (uint16_t)(v[r] & 0xffff);
+        keys[e] = v[r] >> 16;
+      } else if (e < P) {
+        keys[e] = ~0ull;
+      }
+    }
   }
   __syncthreads();
   if (n == 1) {
@@ -517,14 +556,14 @@ __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist
   }
 }
 
-__global__ void __launch_bounds__(1024) k_codebook(const uint64_t* __restrict__ hist, int dict,
+__global__ void __launch_bounds__(CB_T) k_codebook(const uint64_t* __restrict__ hist, int dict,
                                                    uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes,
                                                    uint32_t* __restrict__ enc, uint32_t* __restrict__ maxlen_out) {
   codebook_block(hist, dict, len_out, codes, enc, maxlen_out);
 }
 
 // One codebook per block: the codebooks of a batch's fields in one launch.
-__global__ void __launch_bounds__(1024) k_codebook_group(const CodebookJob* __restrict__ jobs, int dict) {
+__global__ void __launch_bounds__(CB_T) k_codebook_group(const CodebookJob* __restrict__ jobs, int dict) {
   const CodebookJob j = jobs[blockIdx.x];
   codebook_block(j.hist, dict, j.len, j.codes, j.enc, j.maxlen);
 }
@@ -1506,14 +1545,14 @@ void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* cod
   uint32_t *enc = nullptr, *maxlen = nullptr;
   if (enc_scratch) encode_tables(enc_scratch, dict, &enc, &maxlen);
   KernelTimer kt("codebook", st);
-  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, st, hist, dict, len, codes, enc, maxlen);
+  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(CB_T), 0, st, hist, dict, len, codes, enc, maxlen);
   MG_HIP(hipGetLastError());
 }
 
 void launch_codebook_group(const CodebookJob* jobs, uint32_t njobs, int dict, hipStream_t st) {
   if (!njobs) return;
   KernelTimer kt("codebook", st);
-  hipLaunchKernelGGL(k_codebook_group, dim3(njobs), dim3(1024), 0, st, jobs, dict);
+  hipLaunchKernelGGL(k_codebook_group, dim3(njobs), dim3(CB_T), 0, st, jobs, dict);
   MG_HIP(hipGetLastError());
 }
 
