@@ -289,6 +289,36 @@ def test_compressed_bytes_equal_oracle(lib, name, tol):
     assert np.abs(r.astype(np.float64) - u.astype(np.float64)).max() <= tol * np.abs(u).max()
 
 
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_maxabs_every_alignment_and_tail(lib, dt):
+    """max|u| equals numpy's whatever the array's start within 16 bytes and
+    whatever its length (ragged ends, several trips of the grid-stride loop),
+    with the largest magnitude first, in the middle or last; a NaN or
+    infinity in the last element is still reported."""
+    rng = np.random.default_rng(71)
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    E = 16 // np.dtype(dt).itemsize
+    big = (1 << 25) + 3  # several trips of the grid-stride loop
+    base = torch.zeros(big + E, dtype=tdt, device=DEV)
+    say("maxabs", np.dtype(dt).name)
+    for n in [1, 2, 3, 5, 7, 4099, 1000003, big]:
+        x = rng.standard_normal(n).astype(dt)
+        for off in range(E) if n < big else (0, 1):
+            for k in (0, n // 2, n - 1):
+                keep = x[k]
+                x[k] = -1e3
+                v = base[off:off + n]
+                v.copy_(torch.from_numpy(x))
+                x[k] = keep
+                assert lib.mgard_maxabs(v) == 1e3, (n, off, k)
+    for bad in (np.nan, np.inf):
+        x = np.ones(4099, dtype=dt)
+        x[-1] = bad
+        with pytest.raises(lib.MgardError) as e:
+            lib.mgard_maxabs(dev(x))
+        assert e.value.code == -5
+
+
 def test_error_paths(lib):
     say("error paths")
     u = np.ones((33, 33), dtype=np.float32)
