@@ -30,7 +30,7 @@ def say(*a):
 
 
 def dev(x):
-    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    return torch.from_numpy(np.array(x, order="C")).to(DEV)  # a writable copy, also of read-only buffers
 
 
 def host(t):
