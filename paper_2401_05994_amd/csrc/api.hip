@@ -1169,8 +1169,11 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
     }
     MG_HIP(hipDeviceSynchronize());
 
-    // capture: the fields spread over a few forked streams, joined at the end
-    const int K = (int)std::min<uint32_t>(4, nfields);
+    // capture: the fields spread over 16 forked streams, joined at the end.  More
+    // branches than the device's four hardware queues still pay: the graph's
+    // many short kernels overlap better (the 256-field batch took 91.6, 41.6,
+    // 35.0 and 33.0 ms per launch with 1, 4, 8 and 16 branches).
+    const int K = (int)std::min<uint32_t>(16, nfields);
     hipStream_t cs = nullptr;
     std::vector<hipStream_t> ss(K, nullptr);
     std::vector<hipEvent_t> ev(K + 1, nullptr);
