@@ -45,7 +45,10 @@ typedef enum {
   MGARD_ERR_ARG = -1,       /* null pointer, bad option value, bad coordinates */
   MGARD_ERR_SHAPE = -2,     /* ndim outside 1..4, a zero side, too many elements */
   MGARD_ERR_DTYPE = -3,     /* dtype is not MGARD_F32 / MGARD_F64 */
-  MGARD_ERR_TOL = -4,       /* tolerance not positive / not finite */
+  MGARD_ERR_TOL = -4,       /* tolerance not positive / not finite, or outside the
+                               supported range: the rounding reserve
+                               4 (L+1) eps max|u| exceeds tau / 2, or max|u| / b_l
+                               reaches 2^49 for some level */
   MGARD_ERR_NONFINITE = -5, /* the input holds a NaN or an infinity */
   MGARD_ERR_CAPACITY = -6,  /* an output buffer is smaller than required */
   MGARD_ERR_FORMAT = -7,    /* compressed buffer is malformed or truncated */
@@ -136,7 +139,9 @@ mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
  * COUNT) under one tolerance into d_out: field i is written at byte offset
  * h_offsets[i] (host array of nfields, filled by the call; slots are
  * mgard_compress_bound bytes, 256-byte aligned, in field order) and its
- * compressed size goes to d_sizes[i] (device, uint64) at each launch.  The
+ * compressed size goes to d_sizes[i] (device, uint64) at each launch, or 0
+ * when field i cannot be compressed (its input holds a NaN or an infinity,
+ * or the tolerance is outside the supported range, see MGARD_ERR_TOL).  The
  * call allocates the plan's scratch (one device allocation, owned by the
  * plan), uploads the headers and constant tables, runs the autotuner for the
  * fields' level shapes (mgard_autotune), then captures every field's

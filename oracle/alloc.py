@@ -22,6 +22,14 @@ here for the L-infinity norm:
 tau_eff leaves room for the rounding of the transform in the working type:
 tau_eff = tau - min(rho, tau/2), rho = 4 (L+1) eps_T ||u||_inf, eps_T the
 machine epsilon of T.  A field that is identically zero gets b = 1.
+
+Supported range (a reading: the bound above is only worth stating when the
+rounding reserve is a small part of tau, and the quantizer's integers must be
+exact): a tolerance is rejected when rho > tau/2, or when ||u||_inf / b_l
+reaches 2^49 for some level.  The multilevel coefficients stay within a small
+multiple of ||u||_inf (convex interpolation, L2 projections stable in the
+maximum norm), so with that cap |c / b| stays far below 2^63 even for learned
+widths down to exp(-3) b.
 """
 from __future__ import annotations
 
@@ -127,3 +135,15 @@ def error_bound(hier: Hierarchy, bins) -> float:
     """The a-priori L-infinity bound of a bin allocation."""
     K = level_K(hier)
     return bins[0] / 2.0 + sum((1.0 + K[l]) * bins[l] / 2.0 for l in range(1, hier.L + 1))
+
+
+MAX_SCALE = 2.0 ** 49
+
+
+def out_of_range(tau: float, maxabs: float, L: int, T, bins) -> bool:
+    """True when the tolerance lies outside the supported range (see above)."""
+    tau_eff = tau_effective(tau, maxabs, L, T)
+    if not tau_eff > 0.0:
+        return False
+    rho = 4.0 * (L + 1) * eps_of(T) * maxabs
+    return rho > 0.5 * tau or any(not maxabs < MAX_SCALE * b for b in bins)

@@ -91,6 +91,8 @@ def compress_parts(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bi
     tau_eff = A.tau_effective(tau, maxabs, hier.L, T)
     if bins is None:
         bins = A.plain_bins(hier, tau_eff) if alloc == "plain" else A.count_weighted_bins(hier, tau_eff)
+        if A.out_of_range(tau, maxabs, hier.L, T, bins):
+            raise ValueError("tolerance outside the supported range")
     coarsest, cbars = X.decompose(u, hier, T)
     stream = Q.to_stream(coarsest, cbars, hier)
     q = Q.quantize_stream(stream, hier, bins)

@@ -165,6 +165,9 @@ __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* 
                            const uint64_t* ooff, const double* scalars, const double* bins, int L,
                            uint64_t bins_off, int learned, Finale* fin, uint64_t* size_out) {
   const int fallback = learned && scalars[5] != 0.0 ? 1 : 0;
+  // a field that cannot be compressed (NaN or infinity in the input, or a
+  // tolerance outside the supported range) reports size 0
+  const bool rejected = scalars[2] != 0.0 || scalars[6] != 0.0;
   if (threadIdx.x != 0) return;
   const uint64_t pw = word_off[nch], no = esc_off[nch];
   double* hd = reinterpret_cast<double*>(out);
@@ -177,10 +180,10 @@ __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* 
   double* bo = reinterpret_cast<double*>(out + bins_off);
   for (int l = 0; l <= L; ++l) bo[l] = bins[l];
   fin->total_bytes = *ooff + 8 * no;
-  if (size_out) *size_out = fin->total_bytes;
+  if (size_out) *size_out = rejected ? 0 : fin->total_bytes;
   fin->n_outliers = no;
   fin->payload_words = pw;
-  for (int i = 0; i < 6; ++i) fin->scalars[i] = scalars[i];
+  for (int i = 0; i < 7; ++i) fin->scalars[i] = scalars[i];
   if (!learned) {
     fin->scalars[4] = -1.0;
     fin->scalars[5] = 0.0;
@@ -561,6 +564,7 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
   MG_HIP(hipMemcpyAsync(&hf, fin, sizeof(Finale), hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
   if (hf.scalars[2] != 0.0) fail(MGARD_ERR_NONFINITE, "input holds NaN or infinity");
+  if (hf.scalars[6] != 0.0) fail(MGARD_ERR_TOL, "tolerance below the rounding reserve or the quantizer's range");
   *out_bytes = hf.total_bytes;
   if (info) {
     std::memset(info, 0, sizeof(*info));

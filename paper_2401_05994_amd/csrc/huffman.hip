@@ -1160,7 +1160,8 @@ __device__ inline uint4 shift_group(uint4 v, uint32_t sh) {
 
 // One thread per chunk.  status[0] is set to 1 on malformed input.  When
 // esc_off is given, the stream position of the j-th escape symbol is written
-// to epos[j] (chunk k owns entries [esc_off[k], esc_off[k+1])); the loop
+// to epos[j] (chunk k owns entries [esc_off[k], esc_off[k+1]), which must lie
+// inside the n_out entries of epos, and esc_off[nch] must equal n_out); the loop
 // itself issues no loads besides the payload, so it never waits on them early.
 // NF: length-chain size.  Three instances are launched; the one whose range
 // holds the table's number of distinct lengths decodes (NF = 8: 1..7,
@@ -1173,7 +1174,8 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
                                                uint64_t nch, const DecTables* __restrict__ tab,
                                                const uint16_t* __restrict__ sorted_g, int dict,
                                                uint16_t* __restrict__ sym, const uint64_t* __restrict__ esc_off,
-                                               uint64_t* __restrict__ epos, uint32_t* __restrict__ status) {
+                                               uint64_t n_out, uint64_t* __restrict__ epos,
+                                               uint32_t* __restrict__ status) {
   __shared__ uint64_t first[MAXLEN + 1], lim1[MAXLEN + 1];
   __shared__ uint32_t offs[MAXLEN + 1];
   __shared__ uint16_t sorted[MAXDICT];
@@ -1231,6 +1233,13 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
   const bool escapes = esc_off != nullptr;
   uint64_t eo = escapes ? esc_off[k] : 0;
   const uint64_t eo_end = escapes ? esc_off[k + 1] : 0;
+  // epos holds n_out entries: a chunk whose escape range (from the buffer's
+  // own per-chunk counts) leaves it, or escape totals that disagree with
+  // n_out, are malformed input and nothing is written
+  if (escapes && (eo > eo_end || eo_end > n_out || (k + 1 == nch && eo_end != n_out))) {
+    atomicOr(status, 1u);
+    return;
+  }
   uint64_t consumed = 0;
   if (tab->nfast && payload_words >= 4) {
     // Branch-free length search over the distinct lengths.  The chunk's words
@@ -1636,14 +1645,14 @@ void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const u
     // one of the three instances decodes (chosen on the device by the table's
     // number of distinct code lengths); the others return at once
     hipLaunchKernelGGL(k_decode<8>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits, n,
-                       chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, escapes ? epos : nullptr,
-                       d_status);
+                       chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, n_out,
+                       escapes ? epos : nullptr, d_status);
     hipLaunchKernelGGL(k_decode<12>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits,
-                       n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, escapes ? epos : nullptr,
-                       d_status);
+                       n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, n_out,
+                       escapes ? epos : nullptr, d_status);
     hipLaunchKernelGGL(k_decode<16>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits,
-                       n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, escapes ? epos : nullptr,
-                       d_status);
+                       n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, n_out,
+                       escapes ? epos : nullptr, d_status);
   }
   if (escapes && n_out) {
     hipLaunchKernelGGL(k_scatter_outliers, dim3(blocks_for((n_out + TPB - 1) / TPB, 4096)), dim3(TPB), 0, st, epos,

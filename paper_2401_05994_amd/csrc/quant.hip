@@ -70,7 +70,15 @@ __global__ void __launch_bounds__(TPB) k_maxabs(const T* __restrict__ d, uint64_
   if (threadIdx.x == 0) atomicMax((unsigned long long*)out, (unsigned long long)red[0]);
 }
 
-// scalars: [0] tau_abs, [1] maxabs, [2] non-finite flag, [3] tau_eff
+// Largest max|u| / b accepted: coefficients stay within a small multiple of
+// max|u| (interpolation is convex and the L2 projections are stable in the
+// maximum norm), so |c / b| stays far below 2^63 and the integer conversion of
+// the quantizer is exact; learned widths, down to exp(-3) b, keep that margin.
+constexpr double kMaxScale = 562949953421312.0;  // 2^49
+
+// scalars: [0] tau_abs, [1] maxabs, [2] non-finite flag, [3] tau_eff,
+// [6] tolerance outside the supported range: the rounding reserve
+// rho = 4 (L+1) eps max|u| exceeds tau / 2, or max|u| / b_l reaches 2^49
 __global__ void k_bins(int f64, const uint64_t* __restrict__ maxbits, double tol, int rel, double S,
                        int L, int alloc, BinArgs args, double* __restrict__ bins,
                        double* __restrict__ scalars) {
@@ -98,6 +106,7 @@ __global__ void k_bins(int f64, const uint64_t* __restrict__ maxbits, double tol
   scalars[1] = maxabs;
   scalars[2] = (double)nonfinite;
   scalars[3] = tau_eff;
+  scalars[6] = 0.0;
   if (!(tau_eff > 0.0)) {
     for (int l = 0; l <= L; ++l) bins[l] = 1.0;
     return;
@@ -110,6 +119,9 @@ __global__ void k_bins(int f64, const uint64_t* __restrict__ maxbits, double tol
     const double b = 2.0 * tau_eff / S;
     for (int l = 0; l <= L; ++l) bins[l] = b;
   }
+  bool out = rho > half;
+  for (int l = 0; l <= L; ++l) out = out || !(maxabs < kMaxScale * bins[l]);
+  scalars[6] = (!nonfinite && out) ? 1.0 : 0.0;
 }
 
 __device__ inline int level_of(uint64_t i, const uint64_t* __restrict__ off, int nlev) {

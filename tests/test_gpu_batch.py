@@ -93,3 +93,24 @@ def test_autotune_records_every_level_and_keeps_bytes(lib, tmp_path, monkeypatch
         assert table["scatter_planes:f32:" + key] >= 1
     rec = lib.mgard_decompress(buf, nb2)
     assert float((rec - u).abs().max()) <= info["tau_abs"]
+
+
+def test_batch_reports_nonfinite_fields(lib):
+    """A field holding a NaN or an infinity gets size 0 in the batch's size
+    array; the other fields still match their single compressions."""
+    import torch
+
+    good = fieldgen.spectral((40, 33), -3.0, 31, device="cuda").to(torch.float32).contiguous()
+    nanf = good.clone()
+    nanf[5, 7] = float("nan")
+    inff = fieldgen.spectral((17, 20, 19), -3.0, 32, device="cuda").to(torch.float64).contiguous()
+    inff[3, 4, 5] = float("inf")
+    say("nonfinite fields")
+    b = lib.Batch([good, nanf, inff], 1e-3)
+    b.launch()
+    res = b.results()
+    assert res[1][1] == 0 and res[2][1] == 0
+    buf, nb, _ = lib.mgard_compress(good, 1e-3)
+    assert res[0][1] == nb and torch.equal(res[0][0], buf[:nb])
+    b.close()
+

@@ -353,3 +353,65 @@ def test_error_paths(lib):
     z = torch.zeros((17, 17), dtype=torch.float64, device=DEV)
     b2, n2, _ = lib.mgard_compress(z, 1e-3)
     assert torch.equal(lib.mgard_decompress(b2, n2), z)
+
+
+def test_tolerance_outside_range_rejected(lib):
+    """Tolerances whose rounding reserve exceeds tau/2 (float32, 1e-7) or whose
+    max|u| / b reaches 2^49 (float64, 1D n = 5, rel 4.5e-15) are refused with
+    MGARD_ERR_TOL, as the oracle refuses them; the neighbours are accepted."""
+    say("tolerance range")
+    u = fieldgen.bumps2d(65).astype(np.float32)
+    with pytest.raises(lib.MgardError) as e:
+        lib.mgard_compress(dev(u), 1e-7)
+    assert e.value.code == -4
+    with pytest.raises(ValueError):
+        codec.compress(u, 1e-7)
+    lib.mgard_compress(dev(u), 1e-4)
+    w = np.array([1.0, -0.5, 0.25, 0.75, -1.0])
+    with pytest.raises(lib.MgardError) as e:
+        lib.mgard_compress(dev(w), 4.5e-15)
+    assert e.value.code == -4
+    with pytest.raises(ValueError):
+        codec.compress(w, 4.5e-15)
+    buf, nb, _ = lib.mgard_compress(dev(w), 1e-13)
+    assert host(buf[:nb]).tobytes() == codec.compress(w, 1e-13)
+
+
+def _escape_buffer(lib):
+    """A valid buffer with many escapes (dictionary of 256 at a tight bound)."""
+    u = fieldgen.bumps2d(129, seed=1)
+    buf, nbytes, info = lib.mgard_compress(dev(u), 1e-6, dict_size=256)
+    assert info["n_outliers"] > 100
+    return u, buf[:nbytes].clone(), nbytes, codec.parse(host(buf[:nbytes]).tobytes())
+
+
+def test_malformed_escape_counts_rejected(lib):
+    """A buffer whose header outlier count or per-chunk escape counts disagree
+    with its symbols is refused with MGARD_ERR_FORMAT before any escape
+    position is stored (the positions buffer holds n_outliers entries)."""
+    say("malformed escape counts")
+    u, buf, nbytes, hd = _escape_buffer(lib)
+    rec = lib.mgard_decompress(buf, nbytes)
+    assert float((rec - dev(u)).abs().max()) <= 1e-6 * float(np.abs(u).max())
+    nout = hd.n_outliers
+    esc = np.frombuffer(host(buf).tobytes(), "<u4", hd.n_chunks, hd.offsets["chunk_esc"])
+    k = int(np.argmax(esc))
+    cases = {}
+    for name, v in [("n_outliers-1", nout - 1), ("n_outliers=0", 0)]:
+        b = buf.clone()
+        b[64:72] = torch.from_numpy(np.frombuffer(np.uint64(v).tobytes(), np.uint8).copy()).to(DEV)
+        cases[name] = b
+    for name, delta in [("chunk_esc+1", 1), ("chunk_esc+2^20", 1 << 20), ("chunk_esc-1", -1)]:
+        b = buf.clone()
+        o = hd.offsets["chunk_esc"] + 4 * k
+        v = np.uint32(int(esc[k]) + delta)
+        b[o:o + 4] = torch.from_numpy(np.frombuffer(v.tobytes(), np.uint8).copy()).to(DEV)
+        cases[name] = b
+    for name, b in cases.items():
+        say("  case", name)
+        with pytest.raises(lib.MgardError) as e:
+            lib.mgard_decompress(b, nbytes)
+        assert e.value.code == -7, name
+    # the library still decodes the intact buffer afterwards
+    assert torch.equal(lib.mgard_decompress(buf, nbytes), rec)
+
