@@ -171,7 +171,8 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
 mgard_status mgard_batch_launch(mgard_batch* plan, void* stream);
 void mgard_batch_free(mgard_batch* plan);
 
-/* Autotuner (project addition).  For each level of the fused 3D path of this
+/* Autotuner: the auto-tuning part of the library's adaptive scheduling layer
+ * (Sec. 2.2, software architecture).  For each level of the fused 3D path of this
  * shape and dtype, times the candidate launch shapes of the decomposition's
  * plane-marching kernel (coarse intervals per block) and of the
  * recomposition's scatter kernel (fine planes per block) on d_in and keeps
@@ -300,6 +301,25 @@ void mgard_model_free(mgard_model* model);
  * count, h_stats[3l+1] = sum of squares (float64), h_stats[3l+2] = max |c|. */
 mgard_status mgard_level_stats(uint32_t ndim, const uint64_t* shape, mgard_dtype dtype,
                                const void* d_coeff, double* h_stats, const mgard_opts* opts);
+
+/* The network's raw input rows for a coefficient stream (stream order as
+ * above): h_x[4l .. 4l+3] = log(rms_l/tau_abs), log(max_l |c|/tau_abs),
+ * log(count_l / stream length), l/L, computed on the device by the same
+ * kernels as the learned compression (before the stored normalisation).
+ * max_rows: capacity of h_x in rows (MGARD_ERR_CAPACITY below levels + 1). */
+mgard_status mgard_level_features(uint32_t ndim, const uint64_t* shape, mgard_dtype dtype,
+                                  const void* d_coeff, double tau_abs, float* h_x,
+                                  uint32_t max_rows, const mgard_opts* opts);
+
+/* The a-priori bin widths (opts->alloc PLAIN or COUNT, opts->eb) of d_in under
+ * tol, computed on the device by the kernels of mgard_compress: max|u|, then
+ * tau, the rounding reserve and the widths (Sec. 2: bin widths from an error
+ * estimator).  h_bins receives levels + 1 widths, coarsest grid first
+ * (max_bins: its capacity); *h_tau_abs (nullable) the absolute bound.  Fails
+ * as mgard_compress does for non-finite input or an unsupported tolerance. */
+mgard_status mgard_bin_widths(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                              mgard_dtype dtype, double tol, const void* d_in, double* h_bins,
+                              uint32_t max_bins, double* h_tau_abs, const mgard_opts* opts);
 
 /* max |a_i - b_i| over n values of dtype, evaluated in float64, into *h_err. */
 mgard_status mgard_linf_error(mgard_dtype dtype, const void* d_a, const void* d_b, uint64_t n,

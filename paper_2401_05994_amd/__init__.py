@@ -445,6 +445,9 @@ def _learned_sigs(lib):
         "mgard_model_create": (C.c_int, [P, U64, C.POINTER(C.c_void_p)]),
         "mgard_model_free": (None, [P]),
         "mgard_level_stats": (C.c_int, [U32, C.POINTER(U64), C.c_int, P, C.POINTER(C.c_double), P]),
+        "mgard_level_features": (C.c_int, [U32, C.POINTER(U64), C.c_int, P, C.c_double, P, U32, P]),
+        "mgard_bin_widths": (C.c_int, [U32, C.POINTER(U64), P, C.c_int, C.c_double, P, C.POINTER(C.c_double),
+                                       U32, C.POINTER(C.c_double), P]),
         "mgard_linf_error": (C.c_int, [C.c_int, P, P, U64, C.POINTER(C.c_double), P]),
         "mgard_mlp_forward": (C.c_int, [P, P, U32, P, P, P]),
         "mgard_mlp_backward": (C.c_int, [P, P, P, U32, P, P]),
@@ -510,6 +513,32 @@ def mgard_level_stats(coeff, shape):
     o = make_opts()
     _check(lib.mgard_level_stats(len(shape), _shape(shape), _dtype_code(coeff), _ptr(coeff), st, C.byref(o)))
     return np.array(list(st)).reshape(L + 1, 3)
+
+
+def mgard_level_features(coeff, shape, tau_abs):
+    """The network's raw input rows (levels + 1, 4) as the device computes them."""
+    lib = _learned_sigs(load_library())
+    L, _ = mgard_stream_layout(shape)
+    x = (C.c_float * (4 * (L + 1)))()
+    o = make_opts()
+    _check(lib.mgard_level_features(len(shape), _shape(shape), _dtype_code(coeff), _ptr(coeff), float(tau_abs), x,
+                                    L + 1, C.byref(o)))
+    return np.array(list(x), dtype=np.float32).reshape(L + 1, 4)
+
+
+def mgard_bin_widths(u, tol, coords=None, eb="rel", alloc="plain"):
+    """The a-priori bin widths (plain or count) of u under tol, and tau_abs, from the device."""
+    lib = _learned_sigs(load_library())
+    u = u.contiguous()
+    shape = tuple(u.shape)
+    L, _ = mgard_stream_layout(shape)
+    cc = _Coords(coords, len(shape))
+    bins = (C.c_double * (L + 1))()
+    tau = C.c_double(0)
+    o = make_opts(eb, alloc)
+    _check(lib.mgard_bin_widths(len(shape), _shape(shape), cc.ptr, _dtype_code(u), float(tol), _ptr(u), bins, L + 1,
+                                C.byref(tau), C.byref(o)))
+    return list(bins), tau.value
 
 
 def mgard_linf_error(a, b):

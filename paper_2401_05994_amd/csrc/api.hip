@@ -1628,6 +1628,77 @@ mgard_status mgard_level_stats(uint32_t ndim, const uint64_t* shape, mgard_dtype
   });
 }
 
+mgard_status mgard_level_features(uint32_t ndim, const uint64_t* shape, mgard_dtype dtype, const void* d_coeff,
+                                  double tau_abs, float* h_x, uint32_t max_rows, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_coeff || !h_x) fail(MGARD_ERR_ARG, "null pointer");
+    if (!(tau_abs > 0.0) || !std::isfinite(tau_abs)) fail(MGARD_ERR_TOL, "tau_abs must be positive and finite");
+    auto h = get_hierarchy(ndim, shape, nullptr);
+    const int nl = h->L + 1;
+    if ((uint32_t)nl > max_rows) fail(MGARD_ERR_CAPACITY, "h_x holds fewer rows than levels + 1");
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<uint64_t>(MAXL + 2) + carve_size<double>((uint64_t)2 * nl * STATS_BLOCKS) +
+               carve_size<double>(3 * (MAXL + 1)) + carve_size<double>(8) +
+               carve_size<float>((uint64_t)MLP_IN * (MAXL + 1)) + 1024);
+    Carver cv(ws.base());
+    uint64_t* d_off = cv.take<uint64_t>(MAXL + 2);
+    double* part = cv.take<double>((uint64_t)2 * nl * STATS_BLOCKS);
+    double* stats = cv.take<double>(3 * (MAXL + 1));
+    double* scalars = cv.take<double>(8);
+    float* x = cv.take<float>((uint64_t)MLP_IN * (MAXL + 1));
+    MG_HIP(hipMemcpyAsync(d_off, h->level_off.data(), 8 * (h->L + 2), hipMemcpyHostToDevice, o.st));
+    MG_HIP(hipMemcpyAsync(scalars, &tau_abs, 8, hipMemcpyHostToDevice, o.st));
+    if (dtype == MGARD_F64)
+      launch_level_stats<double>(static_cast<const double*>(d_coeff), d_off, nl, part, stats, o.st);
+    else
+      launch_level_stats<float>(static_cast<const float*>(d_coeff), d_off, nl, part, stats, o.st);
+    launch_features(stats, scalars, nl, nullptr, x, o.st);
+    MG_HIP(hipMemcpyAsync(h_x, x, 4 * MLP_IN * nl, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_bin_widths(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,
+                              double tol, const void* d_in, double* h_bins, uint32_t max_bins, double* h_tau_abs,
+                              const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    const int es = dtype_size(dtype);
+    (void)es;
+    if (!d_in || !h_bins) fail(MGARD_ERR_ARG, "null pointer");
+    if (!(tol > 0.0) || !std::isfinite(tol)) fail(MGARD_ERR_TOL, "tolerance must be positive and finite");
+    if (o.alloc == MGARD_ALLOC_LEARNED) fail(MGARD_ERR_ARG, "the a-priori widths are PLAIN or COUNT");
+    auto h = get_hierarchy(ndim, shape, coords);
+    if ((uint32_t)h->L + 1 > max_bins) fail(MGARD_ERR_CAPACITY, "h_bins holds fewer entries than levels + 1");
+    const uint64_t n = h->count(h->L);
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<uint64_t>(4) + carve_size<double>(MAXL + 1) + carve_size<double>(8) + 1024);
+    Carver cv(ws.base());
+    uint64_t* misc = cv.take<uint64_t>(4);
+    double* bins = cv.take<double>(MAXL + 1);
+    double* scalars = cv.take<double>(8);
+    if (dtype == MGARD_F64)
+      launch_maxabs<double>(static_cast<const double*>(d_in), n, misc, o.st);
+    else
+      launch_maxabs<float>(static_cast<const float*>(d_in), n, misc, o.st);
+    BinArgs ba{};
+    for (int l = 0; l <= h->L; ++l) {
+      ba.K[l] = h->K[l];
+      ba.counts[l] = (double)h->level_count[l];
+    }
+    launch_bins(dtype == MGARD_F64 ? 1 : 0, misc, tol, o.eb, h->S, h->L, o.alloc, ba, bins, scalars, o.st);
+    double hs[8];
+    MG_HIP(hipMemcpyAsync(h_bins, bins, 8 * (h->L + 1), hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipMemcpyAsync(hs, scalars, sizeof(hs), hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+    if (hs[2] != 0.0) fail(MGARD_ERR_NONFINITE, "input holds NaN or infinity");
+    if (hs[6] != 0.0) fail(MGARD_ERR_TOL, "tolerance below the rounding reserve or the quantizer's range");
+    if (h_tau_abs) *h_tau_abs = hs[0];
+  });
+}
+
 mgard_status mgard_linf_error(mgard_dtype dtype, const void* d_a, const void* d_b, uint64_t n, double* h_err,
                               const mgard_opts* opts) {
   return guard([&] {

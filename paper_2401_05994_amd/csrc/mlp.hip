@@ -4,8 +4,9 @@
 // This part is a project addition (the paper defines no learned component).
 // The network maps four features of a level's coefficients to a log-scale
 // factor theta_l of that level's bin width:
-//   features: log(rms/tau), log(max/tau), log(count), l/L, normalised by a
-//             per-feature mean and standard deviation stored with the weights;
+//   features: log(rms/tau), log(max/tau), log(count / stream length), l/L,
+//             normalised by a per-feature mean and standard deviation stored
+//             with the weights;
 //   layers:   Linear(4,64) - ReLU - Linear(64,64) - ReLU - Linear(64,1).
 // Parameter buffer (float32): mean[4], std[4], W1[64][4], b1[64],
 // W2[64][64], b2[64], W3[64], b3[1]; y = x W^T + b.  All sums run in a fixed
@@ -77,7 +78,8 @@ __global__ void k_stats_final(const double* __restrict__ part, const uint64_t* _
   stats[3 * l + 2] = mx;
 }
 
-// features of every level from the stats and tau (scalars[0]); normalised
+// features of every level from the stats and tau (scalars[0]); normalised by
+// the mean and standard deviation in params, or raw when params is null
 __global__ void k_features(const double* __restrict__ stats, const double* __restrict__ scalars, int nlev,
                            const float* __restrict__ params, float* __restrict__ x) {
   const int l = threadIdx.x;
@@ -94,7 +96,8 @@ __global__ void k_features(const double* __restrict__ stats, const double* __res
   f[1] = log(mx / tau + 1e-30);
   f[2] = log((cnt > 0.0 ? cnt : 1.0) / total);  // the level's share of the stream: independent of the field size
   f[3] = nlev > 1 ? (double)l / (double)(nlev - 1) : 0.0;
-  for (int i = 0; i < F; ++i) x[l * F + i] = (float)((f[i] - (double)params[i]) / (double)params[F + i]);
+  for (int i = 0; i < F; ++i)
+    x[l * F + i] = params ? (float)((f[i] - (double)params[i]) / (double)params[F + i]) : (float)f[i];
 }
 
 // bins[l] = plain * exp(clamp(theta_l)); written to learned[], plain kept in bins[]

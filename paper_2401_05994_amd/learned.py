@@ -39,32 +39,14 @@ def _lib():
     return m
 
 
-def _eps(dtype) -> float:
-    return 2.0 ** -23 if dtype == "float32" else 2.0 ** -52
+def plain_bins(u, tol, coords=None):
+    """The library's plain widths and tau for u under a relative tol (computed on the device)."""
+    return _lib().mgard_bin_widths(u, tol, coords)
 
 
-def plain_bins(shape, tol, maxabs, dtype="float32", coords=None):
-    """The library's plain widths: b = 2 tau_eff / S, tau_eff = tau - min(4 (L+1) eps max|u|, tau/2)."""
-    m = _lib()
-    S, _ = m.mgard_plain_constant(shape, coords)
-    L, _ = m.mgard_stream_layout(shape)
-    tau = tol * maxabs
-    rho = 4.0 * (L + 1) * _eps(dtype) * maxabs
-    tau_eff = tau - min(rho, 0.5 * tau)
-    b = 2.0 * tau_eff / S if tau_eff > 0 else 1.0
-    return [b] * (L + 1), tau
-
-
-def features(stats, tau):
-    nlev = stats.shape[0]
-    total = float(sum(stats[l][0] for l in range(nlev))) or 1.0
-    out = np.zeros((nlev, 4))
-    for l in range(nlev):
-        cnt, ss, mx = stats[l]
-        rms = math.sqrt(ss / (cnt if cnt > 0 else 1.0))
-        out[l] = [math.log(rms / tau + 1e-30), math.log(mx / tau + 1e-30), math.log(max(cnt, 1.0) / total),
-                  l / (nlev - 1) if nlev > 1 else 0.0]
-    return out
+def features(coeff, shape, tau):
+    """The network's raw input rows, from the device kernels the learned compression runs."""
+    return _lib().mgard_level_features(coeff, shape, tau).astype(np.float64)
 
 
 class Judge:
@@ -90,13 +72,9 @@ class Judge:
 
 def label(u, tol, theta_max=5.0, iters=6, target=0.95, coords=None):
     """(features, theta*) rows for one field and tolerance."""
-    m = _lib()
-    maxabs = m.mgard_maxabs(u)
-    dtype = "float32" if str(u.dtype).endswith("float32") else "float64"
-    plain, tau = plain_bins(tuple(u.shape), tol, maxabs, dtype, coords)
+    plain, tau = plain_bins(u, tol, coords)
     judge = Judge(u, coords)
-    stats = m.mgard_level_stats(judge.coeff, tuple(u.shape))
-    feats = features(stats, tau)
+    feats = features(judge.coeff, tuple(u.shape), tau)
     nlev = len(plain)
     theta = np.zeros(nlev)
     limit = target * tau

@@ -121,6 +121,30 @@ def test_level_stats_and_linf(lib):
     assert lib.mgard_linf_error(a, b) == ref_e
 
 
+@pytest.mark.parametrize("alloc", ["plain", "count"])
+def test_label_inputs_come_from_the_compression_kernels(lib, alloc):
+    """The training labels' bin widths and features are the device's: the widths
+    equal the header's of a compression (and the oracle's), the features equal
+    the oracle's features of the oracle's stream."""
+    from paper_2401_05994_amd import learned as Lrn
+
+    say("label inputs", alloc)
+    u = fieldgen.spectral((33, 40, 20), -2.5, 8).astype(np.float32)
+    du = dev(u)
+    bins, tau = lib.mgard_bin_widths(du, 1e-3, alloc=alloc)
+    buf, nb, info = lib.mgard_compress(du, 1e-3, alloc=alloc)
+    assert bins == info["bins"] and tau == info["tau_abs"]
+    p = codec.compress_parts(u, 1e-3, alloc=alloc)
+    assert bins == p.bins and tau == p.tau_abs
+    if alloc == "plain":
+        assert Lrn.plain_bins(du, 1e-3) == (bins, tau)
+    h = grid.Hierarchy(u.shape)
+    stream = Q.to_stream(*X.decompose(u, h, np.float32), h)
+    feats = Lrn.features(dev(stream), u.shape, tau)
+    ref = M.level_features(M.level_stats(stream, Q.level_offsets(h)), tau)
+    assert np.abs(feats - ref.astype(np.float32).astype(np.float64)).max() <= 1e-6 * max(1.0, np.abs(ref).max())
+
+
 def _model_with_theta(theta_const):
     params, mean, std = _random_model(3)
     params[2][0][:] = 0.0
