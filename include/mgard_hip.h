@@ -253,6 +253,24 @@ mgard_status mgard_huffman_encode(const uint16_t* d_symbols, uint64_t n, uint32_
                                   uint32_t* d_payload, uint64_t payload_capacity,
                                   uint64_t* payload_words, const mgard_opts* opts);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments, results and errors as mgard_huffman_encode, but its
+ * scratch (chunk word offsets and the packed code table) lives in a fixed
+ * array of the library that every device holds until the process ends
+ * (about 16 MiB), and the call allocates nothing.  n may need at most
+ * MGARD_NOALLOC_MAX_CHUNKS chunks of `chunk` symbols (MGARD_ERR_CAPACITY
+ * otherwise).  All calls on one device share that array and every call
+ * rewrites the part it reads before reading it, so consecutive calls are
+ * independent; calls that overlap on one device (other host threads, other
+ * streams) race and must not be made. */
+#define MGARD_NOALLOC_MAX_CHUNKS 2097152
+mgard_status mgard_huffman_encode_noalloc(const uint16_t* d_symbols, uint64_t n, uint32_t dict_size,
+                                          uint32_t chunk, const uint8_t* d_code_len,
+                                          const uint64_t* d_codes, uint32_t* d_chunk_bits,
+                                          uint32_t* d_payload, uint64_t payload_capacity,
+                                          uint64_t* payload_words, const mgard_opts* opts);
+
 /* Inverse of mgard_huffman_encode.  d_symbols must be 16-byte aligned
  * (MGARD_ERR_ARG otherwise); MGARD_ERR_FORMAT when the payload does not
  * decode to exactly n symbols with the given bit counts. */

@@ -8,10 +8,10 @@ Sec. 3, first listing); compression ratio is input bytes over output bytes.
 Wire format (little-endian; offsets in bytes):
 
     0  'MGHP'             magic
-    4  u16 version = 1
+    4  u16 version = 2
     6  u8  dtype           0 = float32, 1 = float64
     7  u8  ndim            1..4
-    8  u8  eb              0 = absolute, 1 = relative to max |u|
+    8  u8  eb              0 = absolute, 1 = relative
     9  u8  alloc           0 = plain, 1 = learned, 2 = count-weighted
    10  u8  coord_flags     bit d set: dimension d stores its coordinates
    11  u8  fallback        1 when a learned allocation fell back to plain
@@ -25,15 +25,19 @@ Wire format (little-endian; offsets in bytes):
    56  u64 n_chunks
    64  u64 n_outliers
    72  u64 payload_words
-   80  u64 shape[ndim]
+   80  u8  norm            0 = L-infinity, 1 = s-norm with smoothness s
+   81  u8[7] zero
+   88  f64 s
+   96  u64 shape[ndim]
        f64 coords          for each flagged dimension, its n_d coordinates
        f64 bins[L+1]
+       u64 level_escapes[L+1]      escaped values per level
+       u32 level_escape_bits[L+1]  their width per level
        u8  code_len[dict_size]
        u32 chunk_bits[n_chunks]
-       u32 chunk_esc[n_chunks]   escape symbols per chunk
+       u32 chunk_esc[n_chunks]     escape symbols per chunk
        u32 payload[payload_words]
-       (zero padding to a multiple of 8 bytes)
-       i64 outliers[n_outliers]
+       u32 escapes[]               per level, ceil(count * width / 32) words
 """
 from __future__ import annotations
 
@@ -49,7 +53,9 @@ from . import transform as X
 from .grid import Hierarchy
 
 MAGIC = b"MGHP"
-VERSION = 1
+VERSION = 2
+FIXED = 96
+NORM_LINF, NORM_S = 0, 1
 ALLOC_PLAIN, ALLOC_LEARNED, ALLOC_COUNT = 0, 1, 2
 
 
@@ -73,6 +79,9 @@ class Parts:
     chunk_bits: list
     chunk_esc: list
     words: list
+    esc_counts: list
+    esc_widths: list
+    esc_words: np.ndarray
 
 
 def compress_parts(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bins=None,
@@ -102,11 +111,13 @@ def compress_parts(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bi
     codes = H.canonical_codes(lengths)
     cbits, words = H.encode(sym, lengths, codes, chunk)
     esc = [int(np.count_nonzero(sym[k:k + chunk] == 0)) for k in range(0, len(sym), chunk)]
+    ecount, ewidth, ewords = Q.pack_escapes(q, hier, dict_size)
     return Parts(hier, T, maxabs, tau, tau_eff, list(map(float, bins)), stream, q, sym, outl, hist,
-                 lengths, codes, cbits, esc, words)
+                 lengths, codes, cbits, esc, words, ecount, ewidth, ewords)
 
 
-def serialize(p: Parts, tol, rel, coords, dict_size, chunk, alloc_code=ALLOC_PLAIN, fallback=0) -> bytes:
+def serialize(p: Parts, tol, rel, coords, dict_size, chunk, alloc_code=ALLOC_PLAIN, fallback=0, norm=NORM_LINF,
+              s=0.0) -> bytes:
     hier = p.hier
     D = hier.D
     flags = 0
@@ -118,21 +129,21 @@ def serialize(p: Parts, tol, rel, coords, dict_size, chunk, alloc_code=ALLOC_PLA
                 coord_blob += np.asarray(coords[d], dtype="<f8").tobytes()
     n = len(p.symbols)
     nch = len(p.chunk_bits)
-    head = struct.pack("<4sHBBBBBBIIIdddQQQQ", MAGIC, VERSION, 0 if p.T is np.float32 else 1, D,
+    head = struct.pack("<4sHBBBBBBIIIdddQQQQB7xd", MAGIC, VERSION, 0 if p.T is np.float32 else 1, D,
                        1 if rel else 0, alloc_code, flags, fallback, hier.L, dict_size, chunk,
                        float(tol), float(p.tau_abs), float(p.maxabs), n, nch, len(p.outliers),
-                       len(p.words))
-    assert len(head) == 80
+                       len(p.words), norm, float(s))
+    assert len(head) == FIXED
     out = [head, np.asarray(hier.shape, dtype="<u8").tobytes(), coord_blob,
            np.asarray(p.bins, dtype="<f8").tobytes(),
+           np.asarray(p.esc_counts, dtype="<u8").tobytes(),
+           np.asarray(p.esc_widths, dtype="<u4").tobytes(),
            np.asarray(p.lengths, dtype=np.uint8).tobytes(),
            np.asarray(p.chunk_bits, dtype="<u4").tobytes(),
            np.asarray(p.chunk_esc, dtype="<u4").tobytes(),
-           np.asarray(p.words, dtype="<u4").tobytes()]
-    blob = b"".join(out)
-    blob += b"\0" * ((-len(blob)) % 8)
-    blob += np.asarray(p.outliers, dtype="<i8").tobytes()
-    return blob
+           np.asarray(p.words, dtype="<u4").tobytes(),
+           np.asarray(p.esc_words, dtype="<u4").tobytes()]
+    return b"".join(out)
 
 
 def compress(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bins=None, alloc="plain"):
@@ -158,20 +169,24 @@ class Header:
     n_chunks: int
     n_outliers: int
     payload_words: int
+    norm: int
+    s: float
     shape: tuple
     coords: list
     bins: list
+    esc_counts: list
+    esc_widths: list
     offsets: dict
 
 
 def parse(buf: bytes) -> Header:
-    if len(buf) < 80 or buf[:4] != MAGIC:
+    if len(buf) < FIXED or buf[:4] != MAGIC:
         raise ValueError("not a compressed buffer")
     (_, ver, dt, D, rel, al, flags, fb, L, dsz, ch, tol, tau, mx, n, nch, nout,
-     nw) = struct.unpack_from("<4sHBBBBBBIIIdddQQQQ", buf, 0)
+     nw, norm, s) = struct.unpack_from("<4sHBBBBBBIIIdddQQQQB7xd", buf, 0)
     if ver != VERSION or dt > 1 or not 1 <= D <= 4:
         raise ValueError("unsupported header")
-    pos = 80
+    pos = FIXED
     shape = tuple(int(v) for v in np.frombuffer(buf, "<u8", D, pos))
     pos += 8 * D
     coords = [None] * D
@@ -181,6 +196,12 @@ def parse(buf: bytes) -> Header:
             pos += 8 * shape[d]
     bins = [float(v) for v in np.frombuffer(buf, "<f8", L + 1, pos)]
     pos += 8 * (L + 1)
+    ecount = [int(v) for v in np.frombuffer(buf, "<u8", L + 1, pos)]
+    pos += 8 * (L + 1)
+    ewidth = [int(v) for v in np.frombuffer(buf, "<u4", L + 1, pos)]
+    pos += 4 * (L + 1)
+    if sum(ecount) != nout or any(w > 64 for w in ewidth):
+        raise ValueError("escape table")
     off = {"code_len": pos}
     pos += dsz
     off["chunk_bits"] = pos
@@ -189,14 +210,13 @@ def parse(buf: bytes) -> Header:
     pos += 4 * nch
     off["payload"] = pos
     pos += 4 * nw
-    pos += (-pos) % 8
-    off["outliers"] = pos
-    pos += 8 * nout
+    off["escapes"] = pos
+    pos += 4 * sum(Q.escape_words(ecount, ewidth))
     off["end"] = pos
     if pos > len(buf):
         raise ValueError("truncated buffer")
     return Header(np.float32 if dt == 0 else np.float64, D, bool(rel), al, fb, L, dsz, ch, tol, tau,
-                  mx, n, nch, nout, nw, shape, coords, bins, off)
+                  mx, n, nch, nout, nw, norm, s, shape, coords, bins, ecount, ewidth, off)
 
 
 def decompress(buf: bytes):
@@ -206,7 +226,9 @@ def decompress(buf: bytes):
     codes = H.canonical_codes(lengths)
     cbits = [int(v) for v in np.frombuffer(buf, "<u4", h.n_chunks, h.offsets["chunk_bits"])]
     words = [int(v) for v in np.frombuffer(buf, "<u4", h.payload_words, h.offsets["payload"])]
-    outl = np.frombuffer(buf, "<i8", h.n_outliers, h.offsets["outliers"])
+    nesc = sum(Q.escape_words(h.esc_counts, h.esc_widths))
+    outl = Q.unpack_escapes(np.frombuffer(buf, "<u4", nesc, h.offsets["escapes"]), h.esc_counts, h.esc_widths,
+                            h.dict_size)
     sym = H.decode(words, cbits, lengths, codes, h.n, h.chunk)
     q = Q.from_symbols(sym, outl, h.dict_size)
     stream = Q.dequantize_stream(q, hier, h.bins, h.dtype)

@@ -86,6 +86,7 @@ def load_library():
         "mgard_histogram": (C.c_int, [P, U64, U32, U32, P, P, P]),
         "mgard_huffman_codebook": (C.c_int, [P, U32, P, P, P]),
         "mgard_huffman_encode": (C.c_int, [P, U64, U32, U32, P, P, P, P, U64, PU64, P]),
+        "mgard_huffman_encode_noalloc": (C.c_int, [P, U64, U32, U32, P, P, P, P, U64, PU64, P]),
         "mgard_huffman_decode": (C.c_int, [P, U64, P, U64, U32, U32, P, P, P]),
         "mgard_maxabs": (C.c_int, [C.c_int, P, U64, PD, P]),
         "mgard_plain_constant": (C.c_int, [U32, PU64, P, PD, PD, U32]),
@@ -379,6 +380,19 @@ def mgard_huffman_encode(sym, lens, codes, dict_size=8192, chunk=1024):
     _check(lib.mgard_huffman_encode(_ptr(sym), n, dict_size, chunk, _ptr(lens), _ptr(codes), _ptr(bits),
                                     _ptr(payload), cap, C.byref(words), C.byref(o)))
     return bits[:nch], payload[: words.value]
+
+
+def mgard_huffman_encode_noalloc(sym, lens, codes, chunk_bits, payload, dict_size=8192, chunk=1024, stream=None):
+    """mgard_huffman_encode into caller buffers (chunk_bits: int32, >= ceil(n/chunk);
+    payload: int32 of any capacity) with the library's fixed scratch: nothing is
+    allocated, here or in the library.  Returns the payload length in words."""
+    lib = load_library()
+    words = C.c_uint64(0)
+    o = make_opts(stream=stream)
+    _check(lib.mgard_huffman_encode_noalloc(_ptr(sym), sym.numel(), dict_size, chunk, _ptr(lens), _ptr(codes),
+                                            _ptr(chunk_bits), _ptr(payload), payload.numel(), C.byref(words),
+                                            C.byref(o)))
+    return words.value
 
 
 def mgard_huffman_decode(payload, bits, n, lens, dict_size=8192, chunk=1024):

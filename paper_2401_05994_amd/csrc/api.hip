@@ -7,23 +7,36 @@
 // Decompression reads the self-describing header (Sec. 2.1) back to the host,
 // validates it, then decodes and recomposes on the device.
 //
-// Wire format (little-endian, byte offsets):
+// Wire format (little-endian, byte offsets), version 2:
 //    0 'MGHP'  4 u16 version  6 u8 dtype  7 u8 ndim  8 u8 eb  9 u8 alloc
 //   10 u8 coord_flags  11 u8 fallback  12 u32 L  16 u32 dict  20 u32 chunk
 //   24 f64 tol  32 f64 tau_abs  40 f64 maxabs  48 u64 n_symbols
 //   56 u64 n_chunks  64 u64 n_outliers  72 u64 payload_words
-//   80 u64 shape[ndim], f64 coordinates of flagged dimensions, f64 bins[L+1],
-//   u8 code_len[dict], u32 chunk_bits[n_chunks], u32 chunk_esc[n_chunks],
-//   u32 payload[payload_words], zero padding to 8 bytes, i64 outliers[].
+//   80 u8 norm (0 L-infinity, 1 s-norm)  81 u8[7] zero  88 f64 s
+//   96 u64 shape[ndim], f64 coordinates of flagged dimensions, f64 bins[L+1],
+//   u64 level_escapes[L+1], u32 level_escape_bits[L+1], u8 code_len[dict],
+//   u32 chunk_bits[n_chunks], u32 chunk_esc[n_chunks], u32 payload[payload_words],
+//   u32 escape words (per level, ceil(count * bits / 32), escapes.hip).
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
+
+// Scratch of mgard_huffman_encode_noalloc, for callers that cannot allocate:
+// the chunk word offsets (MGARD_NOALLOC_MAX_CHUNKS + 1 of them) and the
+// encoder's packed code table, in one fixed array that each device holds from
+// the library's load to the end of the process.  In host code this name is
+// not a device address: the address comes from hipGetSymbolAddress, per
+// device (mg::noalloc_scratch).
+constexpr unsigned long long kNoallocBytes =
+    (((unsigned long long)MGARD_NOALLOC_MAX_CHUNKS + 1) * 8 + 255) / 256 * 256 + 8192 * 4 + 256 + 256;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
 
 // Device-resident network parameters (MLP layout of internal.hpp).
 struct mgard_model {
@@ -73,8 +86,8 @@ mgard_status guard(F&& f) {
   }
 }
 
-constexpr uint16_t kVersion = 1;
-constexpr uint64_t kFixed = 80;
+constexpr uint16_t kVersion = 2;
+constexpr uint64_t kFixed = 96;
 
 struct Opts {
   int eb = MGARD_REL;
@@ -118,7 +131,7 @@ int dtype_size(mgard_dtype t) {
 uint64_t align8(uint64_t v) { return (v + 7) & ~uint64_t(7); }
 
 struct Layout {
-  uint64_t bins, code_len, chunk_bits, chunk_esc, payload;  // byte offsets
+  uint64_t bins, lesc, lbits, code_len, chunk_bits, chunk_esc, payload;  // byte offsets
   uint64_t nch;
 };
 
@@ -129,6 +142,10 @@ Layout layout(const Hierarchy& h, const double* const* coords, int dict, int chu
     if (coords && coords[d]) p += 8ull * h.shape[d + (MAXD - h.D)];
   y.bins = p;
   p += 8ull * (h.L + 1);
+  y.lesc = p;
+  p += 8ull * (h.L + 1);
+  y.lbits = p;
+  p += 4ull * (h.L + 1);
   y.code_len = p;
   p += (uint64_t)dict;
   y.nch = (n + chunk - 1) / chunk;
@@ -140,14 +157,15 @@ Layout layout(const Hierarchy& h, const double* const* coords, int dict, int chu
   return y;
 }
 
-// worst case: every symbol escapes (8 B + 1 bit), or log2(dict)+1 bits per symbol
+// worst case: log2(dict)+1 bits per symbol, and every symbol escapes with a
+// 64-bit code (plus one padding word per level)
 uint64_t bound_of(const Hierarchy& h, const double* const* coords, int dict, int chunk) {
   const uint64_t n = h.count(h.L);
   Layout y = layout(h, coords, dict, chunk, n);
   int lg = 0;
   while ((1 << lg) < dict) ++lg;
   const uint64_t words = (n * (uint64_t)(lg + 1) + 31) / 32 + y.nch;
-  return align8(y.payload + 4 * words) + 8 * n + 64;
+  return align8(y.payload + 4 * words) + 8 * n + 4ull * (h.L + 1) + 64;
 }
 
 struct Finale {  // device results read back by the host at the end
@@ -156,14 +174,10 @@ struct Finale {  // device results read back by the host at the end
   double bins[MAXL + 1];
 };
 
-__global__ void k_outlier_offset(const uint64_t* word_off, uint64_t nch, uint64_t payload_off,
-                                 uint64_t* ooff) {
-  if (threadIdx.x == 0) *ooff = (payload_off + 4 * word_off[nch] + 7) & ~7ull;
-}
-
 __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* esc_off, uint64_t nch,
-                           const uint64_t* ooff, const double* scalars, const double* bins, int L,
-                           uint64_t bins_off, int learned, Finale* fin, uint64_t* size_out) {
+                           uint64_t payload_off, const uint64_t* esc_words, const double* scalars,
+                           const double* bins, int L, uint64_t bins_off, int learned, Finale* fin,
+                           uint64_t* size_out) {
   const int fallback = learned && scalars[5] != 0.0 ? 1 : 0;
   // a field that cannot be compressed (NaN or infinity in the input, or a
   // tolerance outside the supported range) reports size 0
@@ -179,7 +193,7 @@ __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* 
   out[11] = (char)fallback;
   double* bo = reinterpret_cast<double*>(out + bins_off);
   for (int l = 0; l <= L; ++l) bo[l] = bins[l];
-  fin->total_bytes = *ooff + 8 * no;
+  fin->total_bytes = payload_off + 4 * pw + 4 * *esc_words;
   if (size_out) *size_out = rejected ? 0 : fin->total_bytes;
   fin->n_outliers = no;
   fin->payload_words = pw;
@@ -189,12 +203,6 @@ __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* 
     fin->scalars[5] = 0.0;
   }
   for (int l = 0; l <= L; ++l) fin->bins[l] = bins[l];
-}
-
-__global__ void k_zero_pad(char* out, const uint64_t* word_off, uint64_t nch, uint64_t payload_off) {
-  if (threadIdx.x != 0) return;
-  const uint64_t e = payload_off + 4 * word_off[nch];
-  for (uint64_t b = e; b % 8; ++b) out[b] = 0;
 }
 
 std::vector<uint8_t> header_bytes(const Hierarchy& h, const double* const* coords, int dtype, int eb,
@@ -244,8 +252,12 @@ std::vector<uint8_t> header_bytes(const Hierarchy& h, const double* const* coord
 struct Parsed {
   mgard_header hd{};
   std::vector<std::vector<double>> coords;
-  uint64_t bins_off = 0, code_len = 0, chunk_bits = 0, chunk_esc = 0, payload = 0, outliers = 0;
-  uint64_t need = 0;  // bytes of header needed up to the end of bins
+  uint64_t bins_off = 0, lesc = 0, lbits = 0, code_len = 0, chunk_bits = 0, chunk_esc = 0, payload = 0,
+           escapes = 0;
+  std::vector<uint64_t> esc_counts;
+  std::vector<uint32_t> esc_bits;
+  uint64_t esc_words = 0;
+  uint64_t need = 0;  // bytes of header needed up to the end of the escape table
 };
 
 // returns false when more bytes are needed (need is set)
@@ -298,12 +310,30 @@ bool parse_header(const uint8_t* b, uint64_t bytes, Parsed& P) {
   if (h.n_chunks != (n + c - 1) / c) fail(MGARD_ERR_FORMAT, "chunk count does not match");
   if (h.n_outliers > n) fail(MGARD_ERR_FORMAT, "outlier count");
   if (h.payload_words > (n * 64 + 31) / 32 + h.n_chunks) fail(MGARD_ERR_FORMAT, "payload size");
+  if (b[80] > 1) fail(MGARD_ERR_FORMAT, "bad norm");
   for (uint32_t i = 0; i < h.ndim; ++i)
     if ((h.coord_flags >> i) & 1) p += 8 * h.shape[i];
   P.bins_off = p;
   p += 8ull * (h.levels + 1);
+  P.lesc = p;
+  p += 8ull * (h.levels + 1);
+  P.lbits = p;
+  p += 4ull * (h.levels + 1);
   P.need = p;
   if (bytes < p) return false;
+  // escapes per level: counts that add up to n_outliers, widths of at most 64 bits
+  P.esc_counts.assign(h.levels + 1, 0);
+  P.esc_bits.assign(h.levels + 1, 0);
+  uint64_t esc_total = 0;
+  P.esc_words = 0;
+  for (uint32_t l = 0; l <= h.levels; ++l) {
+    std::memcpy(&P.esc_counts[l], b + P.lesc + 8 * l, 8);
+    std::memcpy(&P.esc_bits[l], b + P.lbits + 4 * l, 4);
+    if (P.esc_counts[l] > n || P.esc_bits[l] > 64) fail(MGARD_ERR_FORMAT, "escape table");
+    esc_total += P.esc_counts[l];
+    P.esc_words += (P.esc_counts[l] * P.esc_bits[l] + 31) / 32;
+  }
+  if (esc_total != h.n_outliers) fail(MGARD_ERR_FORMAT, "escape counts do not add up to the outlier count");
   P.coords.assign(h.ndim, {});
   uint64_t q = kFixed + 8ull * h.ndim;
   for (uint32_t i = 0; i < h.ndim; ++i)
@@ -320,9 +350,8 @@ bool parse_header(const uint8_t* b, uint64_t bytes, Parsed& P) {
   p += 4 * h.n_chunks;
   P.payload = p;
   p += 4 * h.payload_words;
-  p = align8(p);
-  P.outliers = p;
-  p += 8 * h.n_outliers;
+  P.escapes = p;
+  p += 4 * P.esc_words;
   h.total_bytes = p;
   return true;
 }
@@ -343,7 +372,8 @@ uint64_t compress_scratch_bytes(const Hierarchy& h, const Opts& o, uint64_t nch)
   uint64_t need = dbytes + carve_size<uint16_t>(n) + carve_size<int64_t>(n) +
                   carve_size<double>(MAXL + 1) + carve_size<double>(8) + carve_size<uint64_t>(4) +
                   2 * carve_size<uint64_t>((uint64_t)o.dict) + 2 * carve_size<uint64_t>(nch + 1) +
-                  carve_size<Finale>(1) + encode_scratch_bytes(o.dict) + 4096;
+                  carve_size<Finale>(1) + encode_scratch_bytes(o.dict) + carve_size<uint64_t>(n) +
+                  3 * carve_size<uint64_t>(MAXL + 2) + 4096;
   const int nl = h.L + 1;
   const uint64_t lbytes =
       o.alloc == MGARD_ALLOC_LEARNED
@@ -372,13 +402,17 @@ struct CompressBufs {
   int64_t* qside;
   double* bins;
   double* scalars;
-  uint64_t* misc;  // [0] max bits, [1] outlier byte offset, [2] status
+  uint64_t* misc;  // [0] max bits, [2] status
   uint64_t* hist;
   uint64_t* codes;
   uint64_t* word_off;
   uint64_t* esc_off;
   Finale* fin;
   void* enc_scratch;
+  uint64_t* ecodes;                // escape codes, compact (n entries at most)
+  uint64_t* esc_start;             // per level: first escape index (L + 2)
+  unsigned long long* esc_wmax;    // per level: largest code (L + 1)
+  uint64_t* esc_woff;              // per level: first escape word (L + 2)
 };
 
 template <typename T>
@@ -409,6 +443,10 @@ CompressBufs carve_compress(const Hierarchy& h, const Layout& y, const Opts& o, 
   b.esc_off = cv.take<uint64_t>(nch + 1);
   b.fin = cv.take<Finale>(1);
   b.enc_scratch = cv.take<char>(encode_scratch_bytes(o.dict));
+  b.ecodes = cv.take<uint64_t>(n);
+  b.esc_start = cv.take<uint64_t>(MAXL + 2);
+  b.esc_wmax = cv.take<unsigned long long>(MAXL + 2);
+  b.esc_woff = cv.take<uint64_t>(MAXL + 2);
   return b;
 }
 
@@ -533,12 +571,16 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
   }
   launch_chunk_bits(sym, n, o.dict, o.chunk, code_len, chunk_bits, st);
   launch_scan_pair(chunk_bits, chunk_esc, nch, word_off, esc_off, st);
-  hipLaunchKernelGGL(k_outlier_offset, dim3(1), dim3(1), 0, st, word_off, nch, y.payload, &misc[1]);
   launch_encode(sym, n, o.dict, o.chunk, code_len, codes, word_off, reinterpret_cast<uint32_t*>(d_out + y.payload),
-                esc_off, qside, d_out, &misc[1], enc_scratch, true, st);
-  hipLaunchKernelGGL(k_zero_pad, dim3(1), dim3(1), 0, st, d_out, word_off, nch, y.payload);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, d_out, word_off, esc_off, nch, &misc[1], scalars, bins,
-                     h.L, y.bins, o.alloc == MGARD_ALLOC_LEARNED ? 1 : 0, fin, size_out);
+                esc_off, qside, cb.ecodes, enc_scratch, true, st);
+  LevelTable lt{};
+  for (int l = 0; l <= h.L + 1; ++l) lt.off[l] = h.level_off[l];
+  launch_escape_pack(sym, n, o.chunk, esc_off, word_off, nch, cb.ecodes, h.L + 1, lt, d_out, y.payload,
+                     reinterpret_cast<uint64_t*>(d_out + y.lesc), reinterpret_cast<uint32_t*>(d_out + y.lbits),
+                     cb.esc_start, cb.esc_wmax, cb.esc_woff, st);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, d_out, word_off, esc_off, nch, y.payload,
+                     cb.esc_woff + (h.L + 1), scalars, bins, h.L, y.bins, o.alloc == MGARD_ALLOC_LEARNED ? 1 : 0,
+                     fin, size_out);
   MG_HIP(hipGetLastError());
   return fin;
 }
@@ -591,6 +633,15 @@ void decompress_impl(Hierarchy& h, const Parsed& P, const char* d_in, T* d_out, 
   const int dict = (int)P.hd.dict_size, chunk = (int)P.hd.chunk_symbols;
   const uint64_t rbytes = recompose_scratch_bytes<T>(h);
   const uint64_t n_out = P.hd.n_outliers;
+  if ((int)P.esc_counts.size() != h.L + 1 || h.L + 1 > MAXL + 1) fail(MGARD_ERR_FORMAT, "level count");
+  EscLevels et{};
+  et.nlev = h.L + 1;
+  for (int l = 0; l <= h.L; ++l) {
+    et.ostart[l + 1] = et.ostart[l] + P.esc_counts[l];
+    et.woff[l + 1] = et.woff[l] + (P.esc_counts[l] * P.esc_bits[l] + 31) / 32;
+    et.bits[l] = P.esc_bits[l];
+  }
+  for (int l = 0; l <= h.L + 1; ++l) et.loff[l] = h.level_off[l];
   uint64_t need = rbytes + carve_size<uint16_t>(n) + carve_size<int64_t>(n) + 2 * carve_size<uint64_t>(nch + 1) +
                   carve_size<uint64_t>(n_out) + decode_table_bytes(dict) + carve_size<uint32_t>(4) + 4096;
   Workspace& ws = workspace();
@@ -610,8 +661,9 @@ void decompress_impl(Hierarchy& h, const Parsed& P, const char* d_in, T* d_out, 
   launch_scan_pair(chunk_bits, chunk_esc, nch, word_off, esc_off, st);
   launch_decode_full(reinterpret_cast<const uint32_t*>(d_in + P.payload), P.hd.payload_words, word_off,
                      chunk_bits, n, dict, chunk, reinterpret_cast<const uint8_t*>(d_in + P.code_len), sym,
-                     esc_off, n_out, reinterpret_cast<const int64_t*>(d_in + P.outliers), qside, epos, tabs,
-                     status, st);
+                     esc_off, n_out, epos, tabs, status, st);
+  launch_escape_scatter(epos, reinterpret_cast<const uint32_t*>(d_in + P.escapes), P.esc_words, et, dict / 2, n,
+                        qside, status, st);
   QuantOut q;
   q.sym = sym;
   q.qside = qside;
@@ -1029,6 +1081,54 @@ void decompress_chunked_impl(const ChunkHead& c, const uint8_t* h_in, T* h_out, 
     MG_HIP(hipEventRecord(pl.out_done[s], pl.ds));
   }
   MG_HIP(hipStreamSynchronize(pl.ds));
+}
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[256] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+void* noalloc_scratch() {
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 256) fail(MGARD_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    MG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(MGARD_ERR_DEVICE, "no device address for the fixed scratch array");
+    g_noalloc_ptr[dev] = p;
+  }
+  return g_noalloc_ptr[dev];
+}
+
+void check_encode_args(const uint16_t* d_symbols, uint32_t dict_size, uint32_t chunk, const uint8_t* d_code_len,
+                       const uint64_t* d_codes, const uint32_t* d_chunk_bits, const uint32_t* d_payload,
+                       const uint64_t* payload_words) {
+  if (!d_symbols || !d_code_len || !d_codes || !d_chunk_bits || !d_payload || !payload_words)
+    fail(MGARD_ERR_ARG, "null buffer");
+  if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
+  if (chunk < 256 || chunk > 8192 || chunk % 256) fail(MGARD_ERR_ARG, "chunk");
+  if (reinterpret_cast<uintptr_t>(d_symbols) % 16) fail(MGARD_ERR_ARG, "d_symbols must be 16-byte aligned");
+}
+
+// The encoding stage on caller buffers with its scratch given: word_off
+// (nch + 1 entries) and enc_scratch (encode_scratch_bytes(dict)).  Every
+// scratch entry read is written first by this call.
+void encode_stage(const uint16_t* d_symbols, uint64_t n, uint32_t dict_size, uint32_t chunk,
+                  const uint8_t* d_code_len, const uint64_t* d_codes, uint32_t* d_chunk_bits, uint32_t* d_payload,
+                  uint64_t payload_capacity, uint64_t* payload_words, uint64_t* word_off, void* enc_scratch,
+                  hipStream_t st) {
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  launch_chunk_bits(d_symbols, n, (int)dict_size, (int)chunk, d_code_len, d_chunk_bits, st);
+  launch_scan_words(d_chunk_bits, nch, word_off, st);
+  uint64_t total = 0;
+  MG_HIP(hipMemcpyAsync(&total, word_off + nch, 8, hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  *payload_words = total;
+  if (total > payload_capacity) fail(MGARD_ERR_CAPACITY, "payload capacity");
+  launch_encode(d_symbols, n, (int)dict_size, (int)chunk, d_code_len, d_codes, word_off, d_payload, nullptr, nullptr,
+                nullptr, enc_scratch, false, st);
+  MG_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace
@@ -1468,27 +1568,34 @@ mgard_status mgard_huffman_encode(const uint16_t* d_symbols, uint64_t n, uint32_
                                   const mgard_opts* opts) {
   return guard([&] {
     Opts o = read_opts(opts);
-    if (!d_symbols || !d_code_len || !d_codes || !d_chunk_bits || !d_payload || !payload_words)
-      fail(MGARD_ERR_ARG, "null buffer");
-    if (dict_size < 256 || dict_size > 8192 || (dict_size & (dict_size - 1))) fail(MGARD_ERR_ARG, "dict_size");
-    if (chunk < 256 || chunk > 8192 || chunk % 256) fail(MGARD_ERR_ARG, "chunk");
-    if (reinterpret_cast<uintptr_t>(d_symbols) % 16) fail(MGARD_ERR_ARG, "d_symbols must be 16-byte aligned");
+    check_encode_args(d_symbols, dict_size, chunk, d_code_len, d_codes, d_chunk_bits, d_payload, payload_words);
     const uint64_t nch = (n + chunk - 1) / chunk;
     Workspace& ws = workspace();
     ws.reserve(carve_size<uint64_t>(nch + 1) + encode_scratch_bytes((int)dict_size) + 1024);
     Carver cv(ws.base());
     uint64_t* word_off = cv.take<uint64_t>(nch + 1);
     void* enc_scratch = cv.take<char>(encode_scratch_bytes((int)dict_size));
-    launch_chunk_bits(d_symbols, n, (int)dict_size, (int)chunk, d_code_len, d_chunk_bits, o.st);
-    launch_scan_words(d_chunk_bits, nch, word_off, o.st);
-    uint64_t total = 0;
-    MG_HIP(hipMemcpyAsync(&total, word_off + nch, 8, hipMemcpyDeviceToHost, o.st));
-    MG_HIP(hipStreamSynchronize(o.st));
-    *payload_words = total;
-    if (total > payload_capacity) fail(MGARD_ERR_CAPACITY, "payload capacity");
-    launch_encode(d_symbols, n, (int)dict_size, (int)chunk, d_code_len, d_codes, word_off, d_payload, nullptr, nullptr, nullptr,
-                  nullptr, enc_scratch, false, o.st);
-    MG_HIP(hipStreamSynchronize(o.st));
+    encode_stage(d_symbols, n, dict_size, chunk, d_code_len, d_codes, d_chunk_bits, d_payload, payload_capacity,
+                 payload_words, word_off, enc_scratch, o.st);
+  });
+}
+
+mgard_status mgard_huffman_encode_noalloc(const uint16_t* d_symbols, uint64_t n, uint32_t dict_size, uint32_t chunk,
+                                          const uint8_t* d_code_len, const uint64_t* d_codes, uint32_t* d_chunk_bits,
+                                          uint32_t* d_payload, uint64_t payload_capacity, uint64_t* payload_words,
+                                          const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    check_encode_args(d_symbols, dict_size, chunk, d_code_len, d_codes, d_chunk_bits, d_payload, payload_words);
+    const uint64_t nch = (n + chunk - 1) / chunk;
+    if (nch > (uint64_t)MGARD_NOALLOC_MAX_CHUNKS)
+      fail(MGARD_ERR_CAPACITY, "more chunks than MGARD_NOALLOC_MAX_CHUNKS");
+    Carver cv(noalloc_scratch());
+    uint64_t* word_off = cv.take<uint64_t>(nch + 1);
+    void* enc_scratch = cv.take<char>(encode_scratch_bytes((int)dict_size));
+    if (cv.used > kNoallocBytes) fail(MGARD_ERR_CAPACITY, "fixed scratch too small");
+    encode_stage(d_symbols, n, dict_size, chunk, d_code_len, d_codes, d_chunk_bits, d_payload, payload_capacity,
+                 payload_words, word_off, enc_scratch, o.st);
   });
 }
 
@@ -1512,7 +1619,7 @@ mgard_status mgard_huffman_decode(const uint32_t* d_payload, uint64_t payload_wo
     MG_HIP(hipMemsetAsync(status, 0, 16, o.st));
     launch_scan_words(d_chunk_bits, nch, word_off, o.st);
     launch_decode_full(d_payload, payload_words, word_off, d_chunk_bits, n, (int)dict_size, (int)chunk,
-                       d_code_len, d_symbols, nullptr, 0, nullptr, nullptr, nullptr, tabs, status, o.st);
+                       d_code_len, d_symbols, nullptr, 0, nullptr, tabs, status, o.st);
     uint32_t hs[4];
     MG_HIP(hipMemcpyAsync(hs, status, 16, hipMemcpyDeviceToHost, o.st));
     MG_HIP(hipStreamSynchronize(o.st));

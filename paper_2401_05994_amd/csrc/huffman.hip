@@ -796,6 +796,12 @@ constexpr int ENC_CHUNK = 1024;                          // largest chunk of the
 constexpr int ENC_WORDS = ENC_CHUNK * ENC_MAXLEN / 32;   // its LDS words per wave
 constexpr int ENC_T = 512;
 
+// The stored code of an escaped value (|q| >= R): 2 (|q| - R) + [q < 0].
+__device__ inline uint64_t escape_code(int64_t q, int R) {
+  const uint64_t a = q < 0 ? (uint64_t)0 - (uint64_t)q : (uint64_t)q;
+  return 2 * (a - (uint64_t)R) + (q < 0 ? 1u : 0u);
+}
+
 __global__ void __launch_bounds__(1024) k_pack_codes(const uint8_t* __restrict__ len, const uint64_t* __restrict__ codes,
                                                      int dict, uint32_t* __restrict__ enc,
                                                      uint32_t* __restrict__ maxlen_out) {
@@ -822,14 +828,14 @@ __global__ void __launch_bounds__(ENC_T) k_encode_wave(const uint16_t* __restric
                                                       const uint64_t* __restrict__ word_off,
                                                       uint32_t* __restrict__ payload,
                                                       const uint64_t* __restrict__ esc_off,
-                                                      const int64_t* __restrict__ qside, char* obase,
-                                                      const uint64_t* __restrict__ ooff) {
+                                                      const int64_t* __restrict__ qside,
+                                                      uint64_t* __restrict__ ecodes, int R) {
   if (*maxlen > (uint32_t)ENC_MAXLEN) return;  // the generic kernel encodes instead
   __shared__ uint32_t enc[MAXDICT];
   __shared__ uint32_t words[ENC_T / 64][ENC_WORDS];
   for (uint32_t s = threadIdx.x; s <= mask; s += ENC_T) enc[s] = enc_g[s];
   __syncthreads();
-  int64_t* outliers = obase ? reinterpret_cast<int64_t*>(obase + *ooff) : nullptr;
+  uint64_t* outliers = ecodes;
   const int lane = threadIdx.x & 63;
   uint32_t* wb = words[threadIdx.x >> 6];
   const uint64_t stride = (uint64_t)gridDim.x * (ENC_T / 64);
@@ -886,7 +892,7 @@ __global__ void __launch_bounds__(ENC_T) k_encode_wave(const uint16_t* __restric
       uint64_t o = eo + (ei - esc);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (s4[j] == 0) outliers[o++] = qside[i + j];
+        if (s4[j] == 0) outliers[o++] = escape_code(qside[i + j], R);
     }
     eo += (uint32_t)__builtin_amdgcn_readlane(ei, 63);
     base += (uint32_t)__builtin_amdgcn_readlane(bi, 63);
@@ -947,11 +953,11 @@ __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym
                                                 const uint64_t* __restrict__ word_off,
                                                 uint32_t* __restrict__ payload,
                                                 const uint64_t* __restrict__ esc_off,
-                                                const int64_t* __restrict__ qside, char* obase,
-                                                const uint64_t* __restrict__ ooff) {
+                                                const int64_t* __restrict__ qside,
+                                                uint64_t* __restrict__ ecodes, int R) {
   if (chunk <= ENC_CHUNK && *maxlen <= (uint32_t)ENC_MAXLEN) return;
-  __shared__ uint32_t words[MAXW];
-  int64_t* outliers = obase ? reinterpret_cast<int64_t*>(obase + *ooff) : nullptr;  // chunk * MAXLEN / 32 words
+  __shared__ uint32_t words[MAXW];  // chunk * MAXLEN / 32 words
+  uint64_t* outliers = ecodes;
   __shared__ uint64_t scan[TPB];
   __shared__ uint32_t escan[TPB];
   const int t = threadIdx.x;
@@ -991,7 +997,7 @@ __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym
         const int L = len[s];
         put_code(words, pos, L, codes[s]);
         pos += L;
-        if (s == 0 && outliers) outliers[eo++] = qside[i];
+        if (s == 0 && outliers) outliers[eo++] = escape_code(qside[i], R);
       }
     }
     __syncthreads();
@@ -1507,19 +1513,6 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
   if (consumed != nbits || eo != eo_end) atomicOr(status, 1u);
 }
 
-// qside[epos[j]] = outliers[j], once every chunk has decoded cleanly (then
-// every epos entry is written and lies below n).
-__global__ void __launch_bounds__(TPB) k_scatter_outliers(const uint64_t* __restrict__ epos,
-                                                         const int64_t* __restrict__ outliers, uint64_t n_out,
-                                                         uint64_t n, int64_t* __restrict__ qside,
-                                                         const uint32_t* __restrict__ status) {
-  if (*status) return;
-  for (uint64_t j = (uint64_t)blockIdx.x * TPB + threadIdx.x; j < n_out; j += (uint64_t)gridDim.x * TPB) {
-    const uint64_t p = epos[j];
-    if (p < n) qside[p] = outliers[j];
-  }
-}
-
 inline unsigned blocks_for(uint64_t nch, unsigned cap) {
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nch, cap));
 }
@@ -1600,8 +1593,8 @@ uint64_t encode_scratch_bytes(int dict) { return carve_size<uint32_t>((uint64_t)
 
 void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                    const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
-                   const uint64_t* esc_off, const int64_t* qside, char* obase,
-                   const uint64_t* ooff, void* scratch, bool packed, hipStream_t st) {
+                   const uint64_t* esc_off, const int64_t* qside, uint64_t* ecodes, void* scratch,
+                   bool packed, hipStream_t st) {
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return;
   uint32_t *enc = nullptr, *maxlen = nullptr;
@@ -1612,13 +1605,13 @@ void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const u
   const uint32_t mask = (uint32_t)(dict - 1);
   if (chunk <= ENC_CHUNK)
     hipLaunchKernelGGL(k_encode_wave, dim3(blocks_for((nch + ENC_T / 64 - 1) / (ENC_T / 64), 512)), dim3(ENC_T), 0,
-                       st, sym, n, chunk, nch, mask, enc, maxlen, word_off, payload, esc_off, qside, obase, ooff);
+                       st, sym, n, chunk, nch, mask, enc, maxlen, word_off, payload, esc_off, qside, ecodes, dict / 2);
   if (chunk <= 4096)
     hipLaunchKernelGGL(k_encode<4096 * MAXLEN / 32>, dim3(blocks_for(nch, 4096)), dim3(TPB), 0, st, sym, n, chunk,
-                       nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, obase, ooff);
+                       nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
   else
     hipLaunchKernelGGL(k_encode<8192 * MAXLEN / 32>, dim3(blocks_for(nch, 4096)), dim3(TPB), 0, st, sym, n, chunk,
-                       nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, obase, ooff);
+                       nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
   MG_HIP(hipGetLastError());
 }
 
@@ -1631,14 +1624,13 @@ uint64_t decode_table_bytes(int dict) {
 void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const uint64_t* word_off,
                         const uint32_t* chunk_bits, uint64_t n, int dict, int chunk,
                         const uint8_t* len, uint16_t* sym, const uint64_t* esc_off, uint64_t n_out,
-                        const int64_t* outliers, int64_t* qside, uint64_t* epos, void* table_scratch,
-                        uint32_t* d_status, hipStream_t st) {
+                        uint64_t* epos, void* table_scratch, uint32_t* d_status, hipStream_t st) {
   Carver cv(table_scratch);
   DecTables* tab = cv.take<DecTables>(1);
   uint16_t* sorted = cv.take<uint16_t>((uint64_t)dict);
   hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(1024), 0, st, len, dict, tab, sorted);
   const uint64_t nch = (n + chunk - 1) / chunk;
-  const bool escapes = esc_off && outliers && qside && epos;
+  const bool escapes = esc_off && epos;
   if (nch) {
     const unsigned blocks = (unsigned)((nch + 255) / 256);
     KernelTimer kt("decode", st);
@@ -1653,10 +1645,6 @@ void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const u
     hipLaunchKernelGGL(k_decode<16>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits,
                        n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, n_out,
                        escapes ? epos : nullptr, d_status);
-  }
-  if (escapes && n_out) {
-    hipLaunchKernelGGL(k_scatter_outliers, dim3(blocks_for((n_out + TPB - 1) / TPB, 4096)), dim3(TPB), 0, st, epos,
-                       outliers, n_out, n, qside, d_status);
   }
   MG_HIP(hipGetLastError());
 }

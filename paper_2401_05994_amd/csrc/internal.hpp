@@ -291,16 +291,46 @@ void launch_scan_u32(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t s
 void launch_scan_pair(const uint32_t* chunk_bits, const uint32_t* esc, uint64_t nch, uint64_t* word_off,
                       uint64_t* esc_off, hipStream_t st);
 uint64_t encode_scratch_bytes(int dict);
+// With esc_off, qside and ecodes given, the code of the j-th escaped value
+// (2 (|q| - R) + [q < 0], R = dict / 2) goes to ecodes[j].
 void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                    const uint64_t* codes, const uint64_t* word_off, uint32_t* payload,
-                   const uint64_t* esc_off, const int64_t* qside, char* obase,
-                   const uint64_t* ooff, void* scratch, bool packed, hipStream_t st);
+                   const uint64_t* esc_off, const int64_t* qside, uint64_t* ecodes, void* scratch,
+                   bool packed, hipStream_t st);
+// Escaped values, packed per level (escapes.hip).  Level offsets of a stream
+// by value (so that no host copy is needed inside a captured graph).
+struct LevelTable {
+  uint64_t off[MAXL + 2];
+};
+// After the encoder has written the escape codes (ecodes): per level the first
+// escape index (ostart, nlev + 1), the largest code (wmax, nlev), the counts
+// and widths (hdr_counts, hdr_bits: the header's arrays) and the word offsets
+// (woff, nlev + 1; woff[nlev] = total words), and the packed words after the
+// payload at d_out + payload_off + 4 word_off[nch].
+void launch_escape_pack(const uint16_t* sym, uint64_t n, int chunk, const uint64_t* esc_off, const uint64_t* word_off,
+                        uint64_t nch, const uint64_t* ecodes, int nlev, const LevelTable& lt, char* d_out,
+                        uint64_t payload_off, uint64_t* hdr_counts, uint32_t* hdr_bits, uint64_t* ostart,
+                        unsigned long long* wmax, uint64_t* woff, hipStream_t st);
+// The per-level layout of a stored stream's escapes, from its header.
+struct EscLevels {
+  uint64_t ostart[MAXL + 2];  // first escape index of each level; the total last
+  uint64_t woff[MAXL + 2];    // first word of each level; all words last
+  uint64_t loff[MAXL + 2];    // stream offsets of the levels; n last
+  uint32_t bits[MAXL + 1];
+  int nlev;
+};
+// qside[epos[j]] = q of escape j (skipped when *status is set; sets it for an
+// escape recorded outside its level).  words: the nw packed words.
+void launch_escape_scatter(const uint64_t* epos, const uint32_t* words, uint64_t nw, const EscLevels& t, int R,
+                           uint64_t n, int64_t* qside, uint32_t* status, hipStream_t st);
+
 uint64_t decode_table_bytes(int dict);
+// Decoding tables and the decode itself; with esc_off and epos given, the
+// stream positions of the n_out escapes go to epos.
 void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const uint64_t* word_off,
                         const uint32_t* chunk_bits, uint64_t n, int dict, int chunk,
                         const uint8_t* len, uint16_t* sym, const uint64_t* esc_off, uint64_t n_out,
-                        const int64_t* outliers, int64_t* qside, uint64_t* epos, void* table_scratch,
-                        uint32_t* d_status, hipStream_t st);
+                        uint64_t* epos, void* table_scratch, uint32_t* d_status, hipStream_t st);
 
 // Learned allocation (mlp.hip).  Parameter layout (float32): mean[4], std[4],
 // W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3[1].

@@ -1,22 +1,21 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark times.
 
-The oracle cannot decompose a 513^3 or 500^3 field in seconds, so these tests
-check what it can compute one node at a time, plus properties that hold at any
-size:
+Element by element against the oracle:
 
-* finest-level coefficients (the residual of the multilinear interpolation,
-  Sec. 2.2) at sampled nodes, bit-exact, found through the stream layout the
-  oracle defines (level by level, sub-grids in mask order);
-* whole compressed chunks of the finest level: the oracle quantizes its own
-  coefficients with its own bins (Sec. 2.3, plain allocation), maps them to
-  symbols and decodes the chunk from the library's payload with its own
-  bit-serial decoder: symbols, outliers and chunk bit counts must agree
-  exactly, including the ragged last chunk of the stream;
-* the header's max |u|, tau and bins against the oracle's;
-* the code lengths form a complete prefix code (Kraft sum 1);
+* the whole coefficient stream of mgard_decompose (every level, the coarse
+  grids included) equals the oracle's decomposition in the same working
+  precision (normwise bound 1e-6 max|u| for float32, 1e-13 for float64 first,
+  then bit equality);
+* for every tolerance, the whole symbol stream of mgard_compress (decoded by
+  the library's decoder from the buffer's payload), the chunk bit counts and
+  escape counts, the escaped values (unpacked by the oracle), the histogram's
+  code lengths and the header's max |u|, tau and bins equal the oracle's
+  quantization of its own stream with its own bins;
+* a few whole chunks are also decoded by the oracle's bit-serial decoder from
+  the library's payload (the first of the finest level and the ragged last);
 * decompose then recompose returns the input within the rounding reserve the
-  error budget sets aside, 4 (L + 1) eps max |u|;
-* the decompressed field is within tau of the input.
+  error budget sets aside, 4 (L + 1) eps max |u|, and the decompressed field
+  is within tau of the input.
 
 Workloads: 513^3 float32 spectral k^-5/3 (seed 2) at rel tol 1e-2, 1e-3, 1e-4;
 500^3 float64 with geometric coordinates (ratio 1.01 per dimension), spectral
@@ -94,27 +93,24 @@ WORKLOADS = {"513f32": (_field_513, np.float32, [1e-2, 1e-3, 1e-4]),
              "500f64": (_field_500, np.float64, [1e-4])}
 
 
-@pytest.fixture(scope="module")
-def cache():
-    d = {}
-    yield d
-    d.clear()
-
-
-def _setup(lib, cache, name):
+@pytest.fixture(scope="module", params=list(WORKLOADS))
+def cache(request, lib):
+    """One workload at a time (tests are grouped by it): the field on the device,
+    its host copy, the hierarchy and, once computed, the oracle's stream."""
     import torch
 
-    if cache.get("name") != name:
-        cache.clear()
-        torch.cuda.empty_cache()
-        make, T, tols = WORKLOADS[name]
-        u, coords = make(torch)
-        say("autotune", tuple(u.shape))
-        lib.mgard_autotune(u, coords)
-        uh = u.cpu().numpy()
-        hier = Hierarchy(u.shape, coords)
-        cache.update(name=name, u=u, coords=coords, uh=uh, hier=hier, lay=Layout(hier), T=T, tols=tols)
-    return cache
+    name = request.param
+    torch.cuda.empty_cache()
+    make, T, tols = WORKLOADS[name]
+    u, coords = make(torch)
+    say("autotune", tuple(u.shape))
+    lib.mgard_autotune(u, coords)
+    uh = u.cpu().numpy()
+    hier = Hierarchy(u.shape, coords)
+    d = dict(name=name, u=u, coords=coords, uh=uh, hier=hier, lay=Layout(hier), T=T, tols=tols)
+    yield d
+    d.clear()
+    torch.cuda.empty_cache()
 
 
 def _sample_fine_nodes(hier, rng, k):
@@ -137,49 +133,55 @@ def _sample_fine_nodes(hier, rng, k):
     return pts
 
 
-@pytest.mark.parametrize("name", list(WORKLOADS))
-def test_fullsize_decompose(lib, cache, name):
-    import torch
+def _oracle_stream(c):
+    if "stream" not in c:
+        say("oracle decompose", c["name"])
+        hier, T = c["hier"], c["T"]
+        c["stream"] = Q.to_stream(*X.decompose(c["uh"], hier, T), hier)
+    return c["stream"]
 
-    c = _setup(lib, cache, name)
+
+def test_fullsize_decompose_every_level(lib, cache):
+    c = cache
+    name = c["name"]
     u, uh, hier, lay, T = c["u"], c["uh"], c["hier"], c["lay"], c["T"]
     L, offs = lib.mgard_stream_layout(u.shape)
     assert L == hier.L and offs == [int(v) for v in lay.off]
     say("decompose", name)
     coeff = lib.mgard_decompose(u, c["coords"])
-    pts = _sample_fine_nodes(hier, np.random.default_rng(5), 3000)
-    pos = [lay.pos_of(p) for p in pts]
-    for p, q in zip(pts[:50], pos[:50]):
+    got = coeff.cpu().numpy()
+    want = _oracle_stream(c)
+    maxabs = float(np.abs(uh).max())
+    bound = (1e-6 if T == np.float32 else 1e-13) * maxabs
+    for l in range(hier.L + 1):
+        a, b = got[lay.off[l]:lay.off[l + 1]], want[lay.off[l]:lay.off[l + 1]]
+        d = float(np.abs(a.astype(np.float64) - b.astype(np.float64)).max()) if len(a) else 0.0
+        assert d <= bound, (name, l, d)
+        bad = np.flatnonzero(a != b)
+        assert bad.size == 0, (name, l, bad.size, [(int(i), float(a[i]), float(b[i])) for i in bad[:3]])
+    # the stream layout: sampled positions map to the nodes the oracle's per-node value names
+    pts = _sample_fine_nodes(hier, np.random.default_rng(5), 200)
+    for p in pts:
+        q = lay.pos_of(p)
         assert lay.node_of(q) == p
-    got = coeff[torch.tensor(pos, device=u.device)].cpu().numpy()
-    want = np.array([X.coefficient_at(uh, hier, p, T) for p in pts], dtype=T)
-    bad = np.flatnonzero(got != want)
-    assert bad.size == 0, [(pts[i], float(got[i]), float(want[i])) for i in bad[:5]]
+        assert got[q] == X.coefficient_at(uh, hier, p, T)
+    del got
     say("recompose", name)
     rec = lib.mgard_recompose(coeff, u.shape, c["coords"])
     del coeff
-    maxabs = float(np.abs(uh).max())
     err = float((rec - u).abs().max())
     reserve = 4.0 * (hier.L + 1) * float(np.finfo(T).eps) * maxabs
     say("decompose-recompose L_inf", err, "reserve", reserve)
     assert err <= reserve
 
 
-def _expected_chunk(uh, hier, lay, T, bins, start, count, dict_size, memo):
-    vals = []
-    for j in range(start, start + count):
-        if j not in memo:
-            memo[j] = X.coefficient_at(uh, hier, lay.node_of(j), T)
-        vals.append(memo[j])
-    q = Q.quantize(np.array(vals, dtype=T), bins[hier.L])
-    return Q.to_symbols(q, dict_size)
+def test_fullsize_symbols_escapes_and_roundtrip(lib, cache):
+    import torch
 
-
-@pytest.mark.parametrize("name", list(WORKLOADS))
-def test_fullsize_compressed_chunks_and_roundtrip(lib, cache, name):
-    c = _setup(lib, cache, name)
+    c = cache
+    name = c["name"]
     u, uh, hier, lay, T = c["u"], c["uh"], c["hier"], c["lay"], c["T"]
-    memo = c.setdefault("memo", {})
+    stream = _oracle_stream(c)
     maxabs = float(np.abs(uh).max())
     for tol in c["tols"]:
         say("compress", name, "tol", tol)
@@ -189,33 +191,48 @@ def test_fullsize_compressed_chunks_and_roundtrip(lib, cache, name):
         tau = A.tau_abs(tol, maxabs, True)
         assert hd.maxabs == maxabs and hd.tau_abs == tau and hd.L == hier.L
         assert hd.shape == hier.shape and hd.n == int(lay.off[-1])
-        assert hd.bins == A.plain_bins(hier, A.tau_effective(tau, maxabs, hier.L, T))
+        bins = A.plain_bins(hier, A.tau_effective(tau, maxabs, hier.L, T))
+        assert hd.bins == bins
+        say("  oracle quantize")
+        q = Q.quantize_stream(stream, hier, bins)
+        sym, outl = Q.to_symbols(q, hd.dict_size)
+        counts, widths = Q.escape_table(q, hier, hd.dict_size)
+        del q
+        lengths_ref = H.code_lengths(H.histogram(sym, hd.dict_size))
         lengths = np.frombuffer(blob, np.uint8, hd.dict_size, hd.offsets["code_len"]).astype(np.int64)
+        assert np.array_equal(lengths, lengths_ref)
         used = lengths[lengths > 0]
         assert sum(math.ldexp(1.0, -int(v)) for v in used) == 1.0
-        codes = H.canonical_codes(lengths)
+        ch = hd.chunk
         cbits = np.frombuffer(blob, "<u4", hd.n_chunks, hd.offsets["chunk_bits"]).astype(np.int64)
         cesc = np.frombuffer(blob, "<u4", hd.n_chunks, hd.offsets["chunk_esc"]).astype(np.int64)
-        words = np.frombuffer(blob, "<u4", hd.payload_words, hd.offsets["payload"])
-        outl = np.frombuffer(blob, "<i8", hd.n_outliers, hd.offsets["outliers"])
+        starts = np.arange(0, hd.n, ch)
+        assert np.array_equal(cbits, np.add.reduceat(lengths[sym], starts))
+        assert np.array_equal(cesc, np.add.reduceat((sym == 0).astype(np.int64), starts))
+        say("  whole symbol stream (library decoder)")
+        po, pw = hd.offsets["payload"], hd.payload_words
+        payload = buf[po:po + 4 * pw].view(torch.int32)
+        bits_d = buf[hd.offsets["chunk_bits"]:hd.offsets["chunk_bits"] + 4 * hd.n_chunks].view(torch.int32)
+        lens_d = buf[hd.offsets["code_len"]:hd.offsets["code_len"] + hd.dict_size]
+        dec = lib.mgard_huffman_decode(payload, bits_d, hd.n, lens_d, hd.dict_size, ch)
+        assert np.array_equal(lib.u16(dec), sym.astype(np.uint16))
+        del dec, payload
+        say("  escapes", hd.n_outliers, "widths", hd.esc_widths)
+        assert hd.esc_counts == counts and hd.esc_widths == widths
+        nesc = sum(Q.escape_words(hd.esc_counts, hd.esc_widths))
+        esc_words = np.frombuffer(blob, "<u4", nesc, hd.offsets["escapes"])
+        assert np.array_equal(Q.unpack_escapes(esc_words, hd.esc_counts, hd.esc_widths, hd.dict_size), outl)
+        # a few chunks through the oracle's bit-serial decoder as well
+        codes = H.canonical_codes(lengths)
+        words = np.frombuffer(blob, "<u4", pw, po)
         wstart = np.concatenate([[0], np.cumsum((cbits + 31) // 32)])
-        ostart = np.concatenate([[0], np.cumsum(cesc)])
-        assert wstart[-1] == hd.payload_words and ostart[-1] == hd.n_outliers
-        ch = hd.chunk
         first = -(-int(lay.off[hier.L]) // ch)
-        last = hd.n_chunks - 1  # ragged: the stream's tail lies in the finest level
-        rng = np.random.default_rng(int(tol * 1e6) + 3)
-        picks = sorted({first, last, *[int(k) for k in rng.integers(first, last, 10)]})
-        say("check chunks", picks)
-        for k in picks:
-            start = k * ch
-            count = min(ch, hd.n - start)
-            sym, out = _expected_chunk(uh, hier, lay, T, hd.bins, start, count, hd.dict_size, memo)
-            assert int(cbits[k]) == int(lengths[sym].sum()), k
-            dec = H.decode([int(w) for w in words[wstart[k]:wstart[k + 1]]], [int(cbits[k])], lengths, codes,
+        for k in sorted({0, first, hd.n_chunks - 1}):
+            count = min(ch, hd.n - k * ch)
+            got = H.decode([int(w) for w in words[wstart[k]:wstart[k + 1]]], [int(cbits[k])], lengths, codes,
                            count, ch)
-            assert np.array_equal(np.asarray(dec, dtype=np.int64), sym), k
-            assert np.array_equal(outl[ostart[k]:ostart[k + 1]], out), k
+            assert np.array_equal(np.asarray(got, dtype=np.int64), sym[k * ch:k * ch + count]), k
+        del sym, outl
         say("decompress", name, "ratio", u.numel() * u.element_size() / nb)
         rec = lib.mgard_decompress(buf, nb)
         err = float((rec - u).abs().max())

@@ -407,6 +407,21 @@ def test_malformed_escape_counts_rejected(lib):
         v = np.uint32(int(esc[k]) + delta)
         b[o:o + 4] = torch.from_numpy(np.frombuffer(v.tobytes(), np.uint8).copy()).to(DEV)
         cases[name] = b
+    # the per-level escape table: a width beyond 64 bits, and one escape moved
+    # to another level (the counts still add up to n_outliers)
+    lesc = codec.FIXED + 8 * len(hd.shape) + 8 * (hd.L + 1)
+    lbits = lesc + 8 * (hd.L + 1)
+    b = buf.clone()
+    b[lbits:lbits + 4] = torch.from_numpy(np.frombuffer(np.uint32(65).tobytes(), np.uint8).copy()).to(DEV)
+    cases["width 65"] = b
+    l1 = max(l for l in range(hd.L + 1) if hd.esc_counts[l] > 0)
+    l0 = l1 - 1 if l1 > 0 else l1 + 1
+    cnt = list(hd.esc_counts)
+    cnt[l1] -= 1
+    cnt[l0] += 1
+    b = buf.clone()
+    b[lesc:lesc + 8 * (hd.L + 1)] = torch.from_numpy(np.asarray(cnt, dtype="<u8").view(np.uint8).copy()).to(DEV)
+    cases["escape moved to level %d" % l0] = b
     for name, b in cases.items():
         say("  case", name)
         with pytest.raises(lib.MgardError) as e:

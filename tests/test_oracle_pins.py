@@ -482,3 +482,46 @@ def test_chunked_slabs_share_the_global_tolerance_and_meet_it():
         assert hd.tau_abs == tau and not hd.rel
     r = K.decompress_chunked(buf)
     assert float(np.abs(r - u).max()) <= tau
+
+
+# ------------------------------------------------------- escaped values
+def test_escape_packing_hand_example():
+    g = GOLD["escape_packing_small"]
+    h = grid.Hierarchy(tuple(g["shape"]))
+    q = np.array(g["q"], dtype=np.int64)
+    counts, widths, words = Q.pack_escapes(q, h, g["dict_size"])
+    assert counts == g["counts"] and widths == g["widths"]
+    assert [int(w) for w in words] == g["words"]
+    sym, outl = Q.to_symbols(q, g["dict_size"])
+    assert list(sym) == g["symbols"]
+    back = Q.unpack_escapes(words, counts, widths, g["dict_size"])
+    assert list(back) == list(outl)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_escape_packing_roundtrip_extremes(seed):
+    """Random escapes (both signs, |q| from R to 2^62, a level whose codes are all
+    0, a level without escapes) come back in stream order; widths are the bit
+    lengths of each level's largest code, and each level starts on a word."""
+    rng = np.random.default_rng(seed)
+    h = grid.Hierarchy((9, 17))
+    n = 9 * 17
+    dict_size = 256
+    R = dict_size // 2
+    off = Q.level_offsets(h)
+    q = rng.integers(-R + 1, R, size=n)
+    lv = [l for l in range(h.L + 1)]
+    big = rng.choice(n, size=n // 3, replace=False)
+    q[big] = np.sign(rng.standard_normal(len(big))).astype(np.int64) * (R + rng.integers(0, 2 ** 62, size=len(big)))
+    q[off[1]:off[2]] = R  # every escape of level 1 has code 0
+    counts, widths, words = Q.pack_escapes(q, h, dict_size)
+    for l in lv:
+        ql = q[off[l]:off[l + 1]]
+        e = ql[np.abs(ql) >= R]
+        assert counts[l] == len(e)
+        if len(e):
+            vmax = max(2 * (abs(int(x)) - R) + (1 if x < 0 else 0) for x in e)
+            assert widths[l] == vmax.bit_length()
+    assert len(words) == sum((c * w + 31) // 32 for c, w in zip(counts, widths))
+    _, outl = Q.to_symbols(q, dict_size)
+    assert np.array_equal(Q.unpack_escapes(words, counts, widths, dict_size, block=7), outl)
