@@ -41,6 +41,7 @@ Wire format (little-endian; offsets in bytes):
 """
 from __future__ import annotations
 
+import math
 import struct
 from dataclasses import dataclass
 
@@ -49,6 +50,7 @@ import numpy as np
 from . import alloc as A
 from . import huffman as H
 from . import quant as Q
+from . import snorm as SN
 from . import transform as X
 from .grid import Hierarchy
 
@@ -85,7 +87,11 @@ class Parts:
 
 
 def compress_parts(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bins=None,
-                   alloc="plain"):
+                   alloc="plain", norm="linf", s=0.0, tau=None):
+    """norm "linf" bounds the maximum error (alloc.py); norm "s" bounds the
+    s-norm of the error (snorm.py; relative only for s = 0, plain widths only).
+    tau, when given, replaces the bound computed from tol (a float64 norm that
+    another implementation summed in another order)."""
     u = np.asarray(u)
     T = u.dtype.type
     if T not in (np.float32, np.float64):
@@ -96,12 +102,26 @@ def compress_parts(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bi
         raise ValueError("tolerance must be positive")
     hier = Hierarchy(u.shape, coords)
     maxabs = float(np.max(np.abs(u))) if u.size else 0.0
-    tau = A.tau_abs(tol, maxabs, rel)
-    tau_eff = A.tau_effective(tau, maxabs, hier.L, T)
-    if bins is None:
-        bins = A.plain_bins(hier, tau_eff) if alloc == "plain" else A.count_weighted_bins(hier, tau_eff)
-        if A.out_of_range(tau, maxabs, hier.L, T, bins):
-            raise ValueError("tolerance outside the supported range")
+    if norm == "s":
+        if alloc != "plain":
+            raise ValueError("the s-norm bound takes the plain allocation")
+        if rel and s != 0.0:
+            raise ValueError("a relative s-norm bound needs s = 0")
+        if tau is None:
+            tau = tol * math.sqrt(SN.l2_norm_sq(u, hier)) if rel else tol
+        tau_eff = SN.tau_effective(tau, maxabs, hier, s, T)
+        if bins is None:
+            bins = SN.bins_for(hier, tau_eff, s)
+            if SN.out_of_range(tau, maxabs, hier, s, T, bins):
+                raise ValueError("tolerance outside the supported range")
+    else:
+        if tau is None:
+            tau = A.tau_abs(tol, maxabs, rel)
+        tau_eff = A.tau_effective(tau, maxabs, hier.L, T)
+        if bins is None:
+            bins = A.plain_bins(hier, tau_eff) if alloc == "plain" else A.count_weighted_bins(hier, tau_eff)
+            if A.out_of_range(tau, maxabs, hier.L, T, bins):
+                raise ValueError("tolerance outside the supported range")
     coarsest, cbars = X.decompose(u, hier, T)
     stream = Q.to_stream(coarsest, cbars, hier)
     q = Q.quantize_stream(stream, hier, bins)
@@ -146,10 +166,14 @@ def serialize(p: Parts, tol, rel, coords, dict_size, chunk, alloc_code=ALLOC_PLA
     return b"".join(out)
 
 
-def compress(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bins=None, alloc="plain"):
-    p = compress_parts(u, tol, rel, coords, dict_size, chunk, bins, alloc)
+def compress(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bins=None, alloc="plain", norm="linf",
+             s=0.0, tau=None):
+    p = compress_parts(u, tol, rel, coords, dict_size, chunk, bins, alloc, norm, s, tau)
     code = ALLOC_PLAIN if (alloc == "plain" and bins is None) else (ALLOC_COUNT if alloc == "count" else ALLOC_LEARNED)
-    return serialize(p, tol, rel, coords, dict_size, chunk, code)
+    if norm == "s":
+        code = ALLOC_PLAIN
+    return serialize(p, tol, rel, coords, dict_size, chunk, code, norm=NORM_S if norm == "s" else NORM_LINF,
+                     s=s if norm == "s" else 0.0)
 
 
 @dataclass
