@@ -58,8 +58,22 @@ typedef enum {
 
 typedef enum { MGARD_F32 = 0, MGARD_F64 = 1 } mgard_dtype;
 /* Error bound type (Sec. 3, first listing: absolute or relative bound).
- * MGARD_REL: the bound is tol * max|u|. */
+ * MGARD_REL: the bound is tol * max|u| (L-infinity) or tol * ||u|| (L2). */
 typedef enum { MGARD_ABS = 0, MGARD_REL = 1 } mgard_eb;
+/* Norm of the bound (Sec. 2: error estimators in several norms, chosen by the
+ * smoothness parameter s).
+ *   LINF  max |u - u~| <= tau (the default).
+ *   S     ||u - u~||_s <= tau, where ||v||^2 = v^T M v is the L2 norm of the
+ *         multilinear interpolant (M = kron of the consistent P1 mass matrices
+ *         on the coordinates; sides of 1 or 2 nodes are summed over) and
+ *         ||v||_s^2 = sum_l 4^(s l) ||(Q_l - Q_{l-1}) v||^2 over the levels,
+ *         coarsest l = 0, Q_l the L2 projection onto level l; s = 0 is the L2
+ *         norm.  Widths b_l = 2 tau_eff sqrt(N_l / (N 4^(s l) W_l)), W_l the
+ *         hat-function integrals of level l's new nodes; tau_eff leaves
+ *         max(1, 2^(s L)) sqrt(W_0) 4 (L+1) eps max|u| for rounding.  Plain
+ *         allocation only; MGARD_REL needs s = 0; not offered by batches or
+ *         the out-of-core calls (MGARD_ERR_ARG). */
+typedef enum { MGARD_NORM_LINF = 0, MGARD_NORM_S = 1 } mgard_norm;
 /* Bin-width allocation across levels.
  *   PLAIN   one bin width b = 2 tau_eff / S for all levels, with
  *           S = 1 + sum_l (1 + K_l) and K_l the product over dimensions of the
@@ -86,9 +100,12 @@ typedef struct {
   uint32_t reserved;
   void* stream;              /* hipStream_t */
   const mgard_model* model;  /* required for MGARD_ALLOC_LEARNED */
+  uint32_t norm;             /* mgard_norm, default MGARD_NORM_LINF */
+  uint32_t reserved2;
+  double s;                  /* smoothness of MGARD_NORM_S (finite), default 0 */
 } mgard_opts;
 
-/* Fills *opts with the defaults (REL, PLAIN, 8192, 1024, default stream). */
+/* Fills *opts with the defaults (REL, PLAIN, 8192, 1024, default stream, L-infinity). */
 void mgard_default_opts(mgard_opts* opts);
 
 typedef struct {
@@ -105,6 +122,8 @@ typedef struct {
   uint64_t shape[4];
   double tol, tau_abs, maxabs;
   uint64_t n_symbols, n_chunks, n_outliers, payload_words, total_bytes;
+  uint32_t norm, reserved;  /* mgard_norm */
+  double s;
 } mgard_header;
 
 /* ---------------------------------------------------------------- high level */
@@ -283,6 +302,13 @@ mgard_status mgard_huffman_decode(const uint32_t* d_payload, uint64_t payload_wo
  * NaN or infinity is present. */
 mgard_status mgard_maxabs(mgard_dtype dtype, const void* d_in, uint64_t n, double* h_maxabs,
                           const mgard_opts* opts);
+
+/* ||u|| = sqrt(u^T M u), the L2 norm of the multilinear interpolant of d_in
+ * (dtype, shape, coordinates) as MGARD_NORM_S defines it, summed in float64
+ * on the device in a fixed order, into *h_norm. */
+mgard_status mgard_l2_norm(uint32_t ndim, const uint64_t* shape, const double* const* coords,
+                           mgard_dtype dtype, const void* d_in, double* h_norm,
+                           const mgard_opts* opts);
 
 /* Plain bin width and the a-priori constant S for a shape (host only). */
 mgard_status mgard_plain_constant(uint32_t ndim, const uint64_t* shape,

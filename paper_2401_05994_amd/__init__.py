@@ -25,6 +25,7 @@ STATUS = {
 }
 F32, F64 = 0, 1
 ABS, REL = 0, 1
+NORM_LINF, NORM_S = 0, 1
 ALLOC = {"plain": 0, "learned": 1, "count": 2}
 
 
@@ -37,7 +38,8 @@ class MgardError(RuntimeError):
 class mgard_opts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("eb", C.c_uint32), ("alloc", C.c_uint32),
                 ("dict_size", C.c_uint32), ("chunk_symbols", C.c_uint32), ("reserved", C.c_uint32),
-                ("stream", C.c_void_p), ("model", C.c_void_p)]
+                ("stream", C.c_void_p), ("model", C.c_void_p), ("norm", C.c_uint32), ("reserved2", C.c_uint32),
+                ("s", C.c_double)]
 
 
 class mgard_info(C.Structure):
@@ -53,7 +55,8 @@ class mgard_header(C.Structure):
                 ("levels", C.c_uint32), ("dict_size", C.c_uint32), ("chunk_symbols", C.c_uint32),
                 ("shape", C.c_uint64 * 4), ("tol", C.c_double), ("tau_abs", C.c_double),
                 ("maxabs", C.c_double), ("n_symbols", C.c_uint64), ("n_chunks", C.c_uint64),
-                ("n_outliers", C.c_uint64), ("payload_words", C.c_uint64), ("total_bytes", C.c_uint64)]
+                ("n_outliers", C.c_uint64), ("payload_words", C.c_uint64), ("total_bytes", C.c_uint64),
+                ("norm", C.c_uint32), ("reserved", C.c_uint32), ("s", C.c_double)]
 
 
 _lib = None
@@ -90,6 +93,7 @@ def load_library():
         "mgard_huffman_decode": (C.c_int, [P, U64, P, U64, U32, U32, P, P, P]),
         "mgard_maxabs": (C.c_int, [C.c_int, P, U64, PD, P]),
         "mgard_plain_constant": (C.c_int, [U32, PU64, P, PD, PD, U32]),
+        "mgard_l2_norm": (C.c_int, [U32, PU64, P, C.c_int, P, PD, P]),
         "mgard_timing": (C.c_int, [C.c_int]),
         "mgard_timing_report": (C.c_int, [C.c_char_p, U64, PU64]),
         "mgard_autotune": (C.c_int, [U32, PU64, P, C.c_int, P, P]),
@@ -160,13 +164,16 @@ def _dtype_code(t):
     raise TypeError("float32 or float64 tensor expected")
 
 
-def make_opts(eb="rel", alloc="plain", dict_size=8192, chunk=1024, stream=None):
+def make_opts(eb="rel", alloc="plain", dict_size=8192, chunk=1024, stream=None, norm="linf", s=0.0):
+    """norm: "linf" (maximum error) or "s" (the s-norm of smoothness s; s = 0 is L2)."""
     o = mgard_opts()
     load_library().mgard_default_opts(C.byref(o))
     o.eb = REL if eb == "rel" else ABS
     o.alloc = ALLOC[alloc]
     o.dict_size = dict_size
     o.chunk_symbols = chunk
+    o.norm = NORM_S if norm == "s" else NORM_LINF
+    o.s = float(s)
     if stream is None:
         stream = _torch().cuda.current_stream().cuda_stream
     o.stream = stream
@@ -185,7 +192,8 @@ def mgard_compress_bound(shape, dtype=F32, coords=None, dict_size=8192, chunk=10
     return int(b)
 
 
-def mgard_compress(u, tol, coords=None, eb="rel", alloc="plain", dict_size=8192, chunk=1024, out=None):
+def mgard_compress(u, tol, coords=None, eb="rel", alloc="plain", dict_size=8192, chunk=1024, out=None, norm="linf",
+                   s=0.0):
     """Compresses a CUDA float tensor.  Returns (uint8 CUDA buffer, nbytes, info dict)."""
     torch = _torch()
     lib = load_library()
@@ -193,7 +201,7 @@ def mgard_compress(u, tol, coords=None, eb="rel", alloc="plain", dict_size=8192,
     dt = _dtype_code(u)
     shape = tuple(u.shape)
     cc = _Coords(coords, len(shape))
-    o = make_opts(eb, alloc, dict_size, chunk)
+    o = make_opts(eb, alloc, dict_size, chunk, norm=norm, s=s)
     bound = mgard_compress_bound(shape, dt, coords, dict_size, chunk)
     if out is None:
         out = torch.empty(bound, dtype=torch.uint8, device=u.device)
@@ -286,7 +294,7 @@ def mgard_inspect(host_bytes: bytes):
         "chunk_symbols": h.chunk_symbols, "shape": [h.shape[i] for i in range(h.ndim)], "tol": h.tol,
         "tau_abs": h.tau_abs, "maxabs": h.maxabs, "n_symbols": h.n_symbols, "n_chunks": h.n_chunks,
         "n_outliers": h.n_outliers, "payload_words": h.payload_words, "total_bytes": h.total_bytes,
-        "complete": code == 0,
+        "norm": h.norm, "s": h.s, "complete": code == 0,
     }
 
 
@@ -411,6 +419,18 @@ def mgard_maxabs(u):
     o = make_opts()
     _check(lib.mgard_maxabs(_dtype_code(u), _ptr(u), u.numel(), C.byref(m), C.byref(o)))
     return m.value
+
+
+def mgard_l2_norm(u, coords=None):
+    """||u|| = sqrt(u^T M u) of a CUDA float tensor (the L2 norm of its multilinear interpolant)."""
+    lib = load_library()
+    u = u.contiguous()
+    shape = tuple(u.shape)
+    cc = _Coords(coords, len(shape))
+    v = C.c_double(0)
+    o = make_opts()
+    _check(lib.mgard_l2_norm(len(shape), _shape(shape), cc.ptr, _dtype_code(u), _ptr(u), C.byref(v), C.byref(o)))
+    return v.value
 
 
 def mgard_plain_constant(shape, coords=None):
@@ -540,8 +560,9 @@ def mgard_level_features(coeff, shape, tau_abs):
     return np.array(list(x), dtype=np.float32).reshape(L + 1, 4)
 
 
-def mgard_bin_widths(u, tol, coords=None, eb="rel", alloc="plain"):
-    """The a-priori bin widths (plain or count) of u under tol, and tau_abs, from the device."""
+def mgard_bin_widths(u, tol, coords=None, eb="rel", alloc="plain", norm="linf", s=0.0):
+    """The a-priori bin widths (plain or count; L-infinity or s-norm) of u under tol, and
+    tau_abs, from the device."""
     lib = _learned_sigs(load_library())
     u = u.contiguous()
     shape = tuple(u.shape)
@@ -549,7 +570,7 @@ def mgard_bin_widths(u, tol, coords=None, eb="rel", alloc="plain"):
     cc = _Coords(coords, len(shape))
     bins = (C.c_double * (L + 1))()
     tau = C.c_double(0)
-    o = make_opts(eb, alloc)
+    o = make_opts(eb, alloc, norm=norm, s=s)
     _check(lib.mgard_bin_widths(len(shape), _shape(shape), cc.ptr, _dtype_code(u), float(tol), _ptr(u), bins, L + 1,
                                 C.byref(tau), C.byref(o)))
     return list(bins), tau.value

@@ -21,9 +21,10 @@
 #include <array>
 #include <cmath>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
-#include <string>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.hpp"
@@ -92,6 +93,8 @@ constexpr uint64_t kFixed = 96;
 struct Opts {
   int eb = MGARD_REL;
   int alloc = MGARD_ALLOC_PLAIN;
+  int norm = MGARD_NORM_LINF;
+  double s = 0.0;
   int dict = 8192;
   int chunk = 1024;
   hipStream_t st = nullptr;
@@ -102,11 +105,23 @@ struct Opts {
 Opts read_opts(const mgard_opts* o) {
   Opts r;
   if (!o) return r;
-  if (o->struct_size != sizeof(mgard_opts)) fail(MGARD_ERR_ARG, "opts->struct_size mismatch");
+  // the options before the norm fields were added are accepted as well (L-infinity)
+  const bool with_norm = o->struct_size == sizeof(mgard_opts);
+  if (!with_norm && o->struct_size != offsetof(mgard_opts, norm)) fail(MGARD_ERR_ARG, "opts->struct_size mismatch");
   if (o->eb > 1) fail(MGARD_ERR_ARG, "opts->eb");
   if (o->alloc > 2) fail(MGARD_ERR_ARG, "opts->alloc");
   r.eb = (int)o->eb;
   r.alloc = (int)o->alloc;
+  if (with_norm) {
+    if (o->norm > 1) fail(MGARD_ERR_ARG, "opts->norm");
+    r.norm = (int)o->norm;
+    if (r.norm == MGARD_NORM_S) {
+      if (!std::isfinite(o->s) || std::fabs(o->s) > 64.0) fail(MGARD_ERR_ARG, "opts->s must be finite, |s| <= 64");
+      if (r.alloc != MGARD_ALLOC_PLAIN) fail(MGARD_ERR_ARG, "the s-norm bound takes the plain allocation");
+      if (r.eb == MGARD_REL && o->s != 0.0) fail(MGARD_ERR_ARG, "a relative s-norm bound needs s = 0");
+      r.s = o->s;
+    }
+  }
   if (o->dict_size) {
     const uint32_t d = o->dict_size;
     if (d < 256 || d > 8192 || (d & (d - 1))) fail(MGARD_ERR_ARG, "dict_size must be a power of two in [256, 8192]");
@@ -207,7 +222,7 @@ __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* 
 
 std::vector<uint8_t> header_bytes(const Hierarchy& h, const double* const* coords, int dtype, int eb,
                                   int alloc, double tol, int dict, int chunk, uint64_t n,
-                                  uint64_t nch) {
+                                  uint64_t nch, int norm = MGARD_NORM_LINF, double snorm = 0.0) {
   std::vector<uint8_t> b(kFixed, 0);
   auto w16 = [&](size_t o, uint16_t v) { std::memcpy(&b[o], &v, 2); };
   auto w32 = [&](size_t o, uint32_t v) { std::memcpy(&b[o], &v, 4); };
@@ -234,6 +249,8 @@ std::vector<uint8_t> header_bytes(const Hierarchy& h, const double* const* coord
   w64(56, nch);
   w64(64, 0);
   w64(72, 0);
+  b[80] = (uint8_t)norm;
+  wd(88, norm == MGARD_NORM_S ? snorm : 0.0);
   const int pad = MAXD - h.D;
   for (int d = 0; d < h.D; ++d) {
     uint64_t s = (uint64_t)h.shape[d + pad];
@@ -311,6 +328,9 @@ bool parse_header(const uint8_t* b, uint64_t bytes, Parsed& P) {
   if (h.n_outliers > n) fail(MGARD_ERR_FORMAT, "outlier count");
   if (h.payload_words > (n * 64 + 31) / 32 + h.n_chunks) fail(MGARD_ERR_FORMAT, "payload size");
   if (b[80] > 1) fail(MGARD_ERR_FORMAT, "bad norm");
+  h.norm = b[80];
+  std::memcpy(&h.s, b + 88, 8);
+  if (!std::isfinite(h.s)) fail(MGARD_ERR_FORMAT, "bad smoothness");
   for (uint32_t i = 0; i < h.ndim; ++i)
     if ((h.coord_flags >> i) & 1) p += 8 * h.shape[i];
   P.bins_off = p;
@@ -373,7 +393,8 @@ uint64_t compress_scratch_bytes(const Hierarchy& h, const Opts& o, uint64_t nch)
                   carve_size<double>(MAXL + 1) + carve_size<double>(8) + carve_size<uint64_t>(4) +
                   2 * carve_size<uint64_t>((uint64_t)o.dict) + 2 * carve_size<uint64_t>(nch + 1) +
                   carve_size<Finale>(1) + encode_scratch_bytes(o.dict) + carve_size<uint64_t>(n) +
-                  3 * carve_size<uint64_t>(MAXL + 2) + 4096;
+                  3 * carve_size<uint64_t>(MAXL + 2) + carve_size<char>(mass_norm_scratch_bytes()) +
+                  carve_size<double>(1) + 4096;
   const int nl = h.L + 1;
   const uint64_t lbytes =
       o.alloc == MGARD_ALLOC_LEARNED
@@ -413,6 +434,8 @@ struct CompressBufs {
   uint64_t* esc_start;             // per level: first escape index (L + 2)
   unsigned long long* esc_wmax;    // per level: largest code (L + 1)
   uint64_t* esc_woff;              // per level: first escape word (L + 2)
+  void* norm_scratch;              // the L2 norm's block partials (s-norm, relative)
+  double* nrm2;                    // u^T M u
 };
 
 template <typename T>
@@ -447,6 +470,8 @@ CompressBufs carve_compress(const Hierarchy& h, const Layout& y, const Opts& o, 
   b.esc_start = cv.take<uint64_t>(MAXL + 2);
   b.esc_wmax = cv.take<unsigned long long>(MAXL + 2);
   b.esc_woff = cv.take<uint64_t>(MAXL + 2);
+  b.norm_scratch = cv.take<char>(mass_norm_scratch_bytes());
+  b.nrm2 = cv.take<double>(1);
   return b;
 }
 
@@ -492,7 +517,14 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
     ba.counts[l] = (double)h.level_count[l];
   }
   const int alloc = o.alloc == MGARD_ALLOC_COUNT ? MGARD_ALLOC_COUNT : MGARD_ALLOC_PLAIN;
-  launch_bins(f64 ? 1 : 0, &misc[0], tol, o.eb, h.S, h.L, alloc, ba, bins, scalars, st);
+  if (o.norm == MGARD_NORM_S) {
+    // the s-norm widths: ||u|| (relative bound) on the device, factors from the host
+    if (o.eb == MGARD_REL)
+      launch_mass_norm<T>(h, device_mass_table(h, st), d_in, cb.norm_scratch, cb.nrm2, st);
+    launch_bins_snorm(f64 ? 1 : 0, &misc[0], cb.nrm2, tol, o.eb, h.L, snorm_args(h, o.s), bins, scalars, st);
+  } else {
+    launch_bins(f64 ? 1 : 0, &misc[0], tol, o.eb, h.S, h.L, alloc, ba, bins, scalars, st);
+  }
 
   QuantOut q;
   q.sym = sym;
@@ -593,7 +625,8 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
   const T* table = static_cast<const T*>(device_table(h, f64, st));
   const uint64_t n = h.count(h.L);
   const Layout y = layout(h, coords, o.dict, o.chunk, n);
-  std::vector<uint8_t> hb = header_bytes(h, coords, f64 ? 1 : 0, o.eb, o.alloc, tol, o.dict, o.chunk, n, y.nch);
+  std::vector<uint8_t> hb =
+      header_bytes(h, coords, f64 ? 1 : 0, o.eb, o.alloc, tol, o.dict, o.chunk, n, y.nch, o.norm, o.s);
   const uint64_t need = compress_scratch_bytes<T>(h, o, y.nch);
   Workspace& ws = workspace();
   ws.reserve(need + carve_size<uint8_t>(hb.size()));
@@ -1230,6 +1263,7 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
     *plan = nullptr;
     Opts o = read_opts(opts);
     if (o.alloc == MGARD_ALLOC_LEARNED) fail(MGARD_ERR_ARG, "batches use the plain or count allocation");
+    if (o.norm == MGARD_NORM_S) fail(MGARD_ERR_ARG, "batches bound the L-infinity norm");
     if (!nfields || !fields || !d_out || !h_offsets || !d_sizes) fail(MGARD_ERR_ARG, "null buffer or no fields");
     if (!(tol > 0.0) || !std::isfinite(tol)) fail(MGARD_ERR_TOL, "tolerance must be positive and finite");
     for (uint32_t i = 0; i < nfields; ++i)
@@ -1781,21 +1815,36 @@ mgard_status mgard_bin_widths(uint32_t ndim, const uint64_t* shape, const double
     if ((uint32_t)h->L + 1 > max_bins) fail(MGARD_ERR_CAPACITY, "h_bins holds fewer entries than levels + 1");
     const uint64_t n = h->count(h->L);
     Workspace& ws = workspace();
-    ws.reserve(carve_size<uint64_t>(4) + carve_size<double>(MAXL + 1) + carve_size<double>(8) + 1024);
+    ws.reserve(carve_size<uint64_t>(4) + carve_size<double>(MAXL + 1) + carve_size<double>(8) +
+               carve_size<char>(mass_norm_scratch_bytes()) + carve_size<double>(1) + 1024);
     Carver cv(ws.base());
     uint64_t* misc = cv.take<uint64_t>(4);
     double* bins = cv.take<double>(MAXL + 1);
     double* scalars = cv.take<double>(8);
+    void* nscr = cv.take<char>(mass_norm_scratch_bytes());
+    double* nrm2 = cv.take<double>(1);
     if (dtype == MGARD_F64)
       launch_maxabs<double>(static_cast<const double*>(d_in), n, misc, o.st);
     else
       launch_maxabs<float>(static_cast<const float*>(d_in), n, misc, o.st);
-    BinArgs ba{};
-    for (int l = 0; l <= h->L; ++l) {
-      ba.K[l] = h->K[l];
-      ba.counts[l] = (double)h->level_count[l];
+    if (o.norm == MGARD_NORM_S) {
+      if (o.eb == MGARD_REL) {
+        const double* bands = device_mass_table(*h, o.st);
+        if (dtype == MGARD_F64)
+          launch_mass_norm<double>(*h, bands, static_cast<const double*>(d_in), nscr, nrm2, o.st);
+        else
+          launch_mass_norm<float>(*h, bands, static_cast<const float*>(d_in), nscr, nrm2, o.st);
+      }
+      launch_bins_snorm(dtype == MGARD_F64 ? 1 : 0, misc, nrm2, tol, o.eb, h->L, snorm_args(*h, o.s), bins, scalars,
+                        o.st);
+    } else {
+      BinArgs ba{};
+      for (int l = 0; l <= h->L; ++l) {
+        ba.K[l] = h->K[l];
+        ba.counts[l] = (double)h->level_count[l];
+      }
+      launch_bins(dtype == MGARD_F64 ? 1 : 0, misc, tol, o.eb, h->S, h->L, o.alloc, ba, bins, scalars, o.st);
     }
-    launch_bins(dtype == MGARD_F64 ? 1 : 0, misc, tol, o.eb, h->S, h->L, o.alloc, ba, bins, scalars, o.st);
     double hs[8];
     MG_HIP(hipMemcpyAsync(h_bins, bins, 8 * (h->L + 1), hipMemcpyDeviceToHost, o.st));
     MG_HIP(hipMemcpyAsync(hs, scalars, sizeof(hs), hipMemcpyDeviceToHost, o.st));
@@ -1803,6 +1852,30 @@ mgard_status mgard_bin_widths(uint32_t ndim, const uint64_t* shape, const double
     if (hs[2] != 0.0) fail(MGARD_ERR_NONFINITE, "input holds NaN or infinity");
     if (hs[6] != 0.0) fail(MGARD_ERR_TOL, "tolerance below the rounding reserve or the quantizer's range");
     if (h_tau_abs) *h_tau_abs = hs[0];
+  });
+}
+
+mgard_status mgard_l2_norm(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,
+                           const void* d_in, double* h_norm, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    (void)dtype_size(dtype);
+    if (!d_in || !h_norm) fail(MGARD_ERR_ARG, "null pointer");
+    auto h = get_hierarchy(ndim, shape, coords);
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<char>(mass_norm_scratch_bytes()) + carve_size<double>(1) + 1024);
+    Carver cv(ws.base());
+    void* nscr = cv.take<char>(mass_norm_scratch_bytes());
+    double* nrm2 = cv.take<double>(1);
+    const double* bands = device_mass_table(*h, o.st);
+    if (dtype == MGARD_F64)
+      launch_mass_norm<double>(*h, bands, static_cast<const double*>(d_in), nscr, nrm2, o.st);
+    else
+      launch_mass_norm<float>(*h, bands, static_cast<const float*>(d_in), nscr, nrm2, o.st);
+    double v = 0.0;
+    MG_HIP(hipMemcpyAsync(&v, nrm2, 8, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+    *h_norm = std::sqrt(v);
   });
 }
 
@@ -1913,6 +1986,7 @@ mgard_status mgard_compress_chunked(uint32_t ndim, const uint64_t* shape, const 
     if (ndim < 1 || ndim > MAXD) fail(MGARD_ERR_SHAPE, "shape");
     if (!(tol > 0.0) || !std::isfinite(tol)) fail(MGARD_ERR_TOL, "tolerance must be positive and finite");
     if (o.alloc == MGARD_ALLOC_LEARNED) fail(MGARD_ERR_ARG, "chunked compression takes the plain or count allocation");
+    if (o.norm == MGARD_NORM_S) fail(MGARD_ERR_ARG, "chunked compression bounds the L-infinity norm");
     if (dtype == MGARD_F32)
       compress_chunked_impl<float>(ndim, shape, coords, tol, static_cast<const float*>(h_in), slab_planes,
                                    static_cast<char*>(h_out), out_capacity, out_bytes, o);

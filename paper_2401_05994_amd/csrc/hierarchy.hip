@@ -116,6 +116,38 @@ DimOps make_ops(const std::vector<double>& x) {
   return o;
 }
 
+// W of one level with coordinates x per slot: the product over slots of the
+// summed hat integrals (h_left + h_right) / 2 (node counts for slots that are
+// not decomposed), minus, for l >= 1 (new_only), the same product over the
+// coarse nodes; sums in index order, products in slot order.
+void level_weight(const std::array<std::vector<double>, MAXD>& x, const std::array<bool, MAXD>& active,
+                  const std::array<int64_t, MAXD>& sizes, bool new_only, double* W) {
+  double all_p = 1.0, coarse_p = 1.0;
+  for (int s = 0; s < MAXD; ++s) {
+    double a = 0.0, c = 0.0;
+    if (active[s]) {
+      const std::vector<double>& v = x[s];
+      const size_t n = v.size();
+      for (size_t i = 0; i < n; ++i) {
+        const double hl = i > 0 ? v[i] - v[i - 1] : 0.0;
+        const double hr = i + 1 < n ? v[i + 1] - v[i] : 0.0;
+        a += (hl + hr) / 2.0;
+      }
+      for (size_t i = 0; i < n; ++i) {
+        if (!(i % 2 == 0 || i == n - 1)) continue;
+        const double hl = i > 0 ? v[i] - v[i - 1] : 0.0;
+        const double hr = i + 1 < n ? v[i + 1] - v[i] : 0.0;
+        c += (hl + hr) / 2.0;
+      }
+    } else {
+      a = c = (double)sizes[s];
+    }
+    all_p *= a;
+    coarse_p *= c;
+  }
+  *W = new_only ? all_p - coarse_p : all_p;
+}
+
 std::mutex g_mu;
 std::map<std::string, std::shared_ptr<Hierarchy>> g_cache;
 
@@ -125,6 +157,7 @@ Hierarchy::~Hierarchy() {
   for (int k = 0; k < 2; ++k)
     if (dev_table[k]) (void)hipFree(dev_table[k]);
   if (dev_itab) (void)hipFree(dev_itab);
+  if (dev_mass) (void)hipFree(dev_mass);
 }
 
 std::shared_ptr<Hierarchy> get_hierarchy(uint32_t ndim, const uint64_t* shape,
@@ -175,12 +208,25 @@ std::shared_ptr<Hierarchy> get_hierarchy(uint32_t ndim, const uint64_t* shape,
   if (L < 0) L = 0;
   if (L > MAXL - 1) fail(MGARD_ERR_SHAPE, "too many levels");
   h->L = L;
+  // the finest grid's mass bands, for the L2 norm of the input
+  for (int s = 0; s < MAXD; ++s) {
+    if (!h->active[s]) continue;
+    std::vector<double> a, b, c;
+    mass_bands(x[s], a, b, c);
+    h->mass_off[s] = h->mass_table.size();
+    h->mass_table.insert(h->mass_table.end(), a.begin(), a.end());
+    h->mass_table.insert(h->mass_table.end(), b.begin(), b.end());
+    h->mass_table.insert(h->mass_table.end(), c.begin(), c.end());
+  }
+  if (h->mass_table.empty()) h->mass_table.assign(1, 0.0);
+  h->W.assign(L + 1, 0.0);
   h->sizes.assign(L + 1, {});
   h->ops.assign(L + 1, {});
   h->devoff.assign(L + 1, {});
   h->K.assign(L + 1, 0.0);
   for (int s = 0; s < MAXD; ++s) h->sizes[L][s] = h->shape[s];
   for (int l = L; l >= 1; --l) {
+    level_weight(x, h->active, h->sizes[l], true, &h->W[l]);
     double k = 1.0;
     for (int s = 0; s < MAXD; ++s) {
       if (!h->active[s]) {
@@ -197,6 +243,7 @@ std::shared_ptr<Hierarchy> get_hierarchy(uint32_t ndim, const uint64_t* shape,
     }
     h->K[l] = k;
   }
+  level_weight(x, h->active, h->sizes[0], false, &h->W[0]);
   double acc = 0.0;
   for (int l = 1; l <= L; ++l) acc += 1.0 + h->K[l];
   h->S = 1.0 + acc;
@@ -292,6 +339,22 @@ const void* device_table(Hierarchy& h, bool f64, hipStream_t stream) {
   h.dev_table[k] = p;
   h.dev_id[k] = dev;
   return p;
+}
+
+const double* device_mass_table(Hierarchy& h, hipStream_t stream) {
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (h.dev_mass && h.dev_mass_id == dev) return static_cast<const double*>(h.dev_mass);
+  if (h.dev_mass) (void)hipFree(h.dev_mass);
+  h.dev_mass = nullptr;
+  void* p = nullptr;
+  if (hipMalloc(&p, h.mass_table.size() * 8) != hipSuccess) fail(MGARD_ERR_OOM, "mass table");
+  MG_HIP(hipMemcpyAsync(p, h.mass_table.data(), h.mass_table.size() * 8, hipMemcpyHostToDevice, stream));
+  MG_HIP(hipStreamSynchronize(stream));
+  h.dev_mass = p;
+  h.dev_mass_id = dev;
+  return static_cast<const double*>(p);
 }
 
 // ----------------------------------------------------------------- workspace

@@ -85,6 +85,14 @@ struct Hierarchy {
   std::vector<uint64_t> itab;
   void* dev_itab = nullptr;
   int dev_itab_id = -1;
+  // s-norm bound: W[l], the hat-function integrals of level l's new nodes (all
+  // nodes at l = 0); the finest grid's mass bands per decomposed slot (a, b, c,
+  // shape[s] each, at mass_off[s] of mass_table), uploaded in float64
+  std::vector<double> W;
+  std::vector<double> mass_table;
+  std::array<uint64_t, MAXD> mass_off{};
+  void* dev_mass = nullptr;
+  int dev_mass_id = -1;
   uint64_t count(int l) const {
     uint64_t n = 1;
     for (int s = 0; s < MAXD; ++s) n *= (uint64_t)sizes[l][s];
@@ -98,6 +106,8 @@ std::shared_ptr<Hierarchy> get_hierarchy(uint32_t ndim, const uint64_t* shape,
                                          const double* const* coords);
 // Device copy of the constants in precision T (uploaded on first use).
 const void* device_table(Hierarchy& h, bool f64, hipStream_t stream);
+// Device copy (float64) of the finest grid's mass bands (uploaded on first use).
+const double* device_mass_table(Hierarchy& h, hipStream_t stream);
 
 // ----------------------------------------------------------------- workspace
 // One growable device allocation per device, carved into aligned pieces.
@@ -259,6 +269,22 @@ template <typename T>
 void launch_dequantize(const uint16_t* sym, const int64_t* qside, uint64_t n,
                        const uint64_t* d_level_off, int nlev, const double* d_bins, int R, T* c,
                        hipStream_t st);
+
+// The s-norm bound (norms.hip): per-level width factors g_l and the rounding
+// reserve factor, computed on the host in float64.
+struct SnormArgs {
+  double g[MAXL + 1];
+  double reserve;
+};
+SnormArgs snorm_args(const Hierarchy& h, double s);
+uint64_t mass_norm_scratch_bytes();
+// *d_out = u^T M u (float64) of the input grid; d_bands from device_mass_table.
+template <typename T>
+void launch_mass_norm(const Hierarchy& h, const double* d_bands, const T* u, void* scratch, double* d_out,
+                      hipStream_t st);
+// Widths b_l = 2 tau_eff g_l; tau = tol sqrt(*d_nrm2) (rel) or tol; scalars as launch_bins.
+void launch_bins_snorm(int f64, const uint64_t* d_maxbits, const double* d_nrm2, double tol, int rel, int L,
+                       const SnormArgs& a, double* d_bins, double* d_scalars, hipStream_t st);
 
 // Huffman (huffman.hip).
 void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,

@@ -239,3 +239,54 @@ def test_fullsize_symbols_escapes_and_roundtrip(lib, cache):
         say("L_inf / tau", err / tau)
         assert err <= tau
         del rec, buf
+
+
+def test_fullsize_l2_bound(lib, cache):
+    """The relative L2 bound at 1e-3 (the paper's cosmology setting, Sec. 4) on the
+    full-size workload: tau from ||u|| within 1e-10 of the oracle's; the header's
+    widths equal the oracle's s-norm widths for that tau; the whole symbol
+    stream equals the oracle's quantization of its own stream with them; the
+    decompressed field's L2 error, measured by the oracle in float64 and by the
+    library, stays within tau."""
+    import torch
+
+    from oracle import snorm as SN
+
+    c = cache
+    u, uh, hier, lay, T = c["u"], c["uh"], c["hier"], c["lay"], c["T"]
+    stream = _oracle_stream(c)
+    tol = 1e-3
+    say("l2 compress", c["name"])
+    buf, nb, info = lib.mgard_compress(u, tol, c["coords"], norm="s", s=0.0)
+    blob = buf[:nb].cpu().numpy().tobytes()
+    hd = codec.parse(blob)
+    nrm = math.sqrt(SN.l2_norm_sq(uh, hier))
+    assert abs(hd.tau_abs - tol * nrm) <= 1e-10 * tol * nrm
+    assert abs(lib.mgard_l2_norm(u, c["coords"]) - nrm) <= 1e-10 * nrm
+    maxabs = float(np.abs(uh).max())
+    bins = SN.bins_for(hier, SN.tau_effective(hd.tau_abs, maxabs, hier, 0.0, T), 0.0)
+    assert hd.bins == bins
+    q = Q.quantize_stream(stream, hier, bins)
+    sym, outl = Q.to_symbols(q, hd.dict_size)
+    counts, widths = Q.escape_table(q, hier, hd.dict_size)
+    del q
+    assert hd.esc_counts == counts and hd.esc_widths == widths
+    po, pw = hd.offsets["payload"], hd.payload_words
+    dec = lib.mgard_huffman_decode(buf[po:po + 4 * pw].view(torch.int32),
+                                   buf[hd.offsets["chunk_bits"]:hd.offsets["chunk_bits"] + 4 * hd.n_chunks].view(
+                                       torch.int32), hd.n,
+                                   buf[hd.offsets["code_len"]:hd.offsets["code_len"] + hd.dict_size], hd.dict_size,
+                                   hd.chunk)
+    assert np.array_equal(lib.u16(dec), sym.astype(np.uint16))
+    del dec, sym
+    nesc = sum(Q.escape_words(hd.esc_counts, hd.esc_widths))
+    esc_words = np.frombuffer(blob, "<u4", nesc, hd.offsets["escapes"])
+    assert np.array_equal(Q.unpack_escapes(esc_words, hd.esc_counts, hd.esc_widths, hd.dict_size), outl)
+    rec = lib.mgard_decompress(buf, nb)
+    e_dev = (rec.double() - u.double()).contiguous()
+    err_lib = lib.mgard_l2_norm(e_dev, c["coords"])
+    e = rec.cpu().numpy().astype(np.float64) - uh.astype(np.float64)
+    err = math.sqrt(SN.l2_norm_sq(e, hier))
+    say("L2 error / tau", err / hd.tau_abs, "ratio", u.numel() * u.element_size() / nb)
+    assert abs(err_lib - err) <= 1e-9 * err
+    assert err <= hd.tau_abs
