@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
 }
 
 // Thomas along the contiguous dimension: `rows` lines per block staged in LDS
-// (coalesced, eight loads per lane in flight), one lane per line, the same
+// (coalesced, every load of a lane in flight at once), one lane per line, the same
 // arithmetic as k_thomas, then written back.  Lines sit `stride` (odd)
 // elements apart in LDS so the lanes of a wavefront fall in different banks.
 constexpr int ROWS_LDS = 65536;  // bytes
@@ -325,22 +325,22 @@ template <typename T>
 __global__ void __launch_bounds__(TPB) k_thomas_rows(T* __restrict__ data, uint64_t nrows, int n, int rows,
                                                      int stride, const T* __restrict__ ta,
                                                      const T* __restrict__ tr, const T* __restrict__ tcp) {
-  __shared__ T tile[ROWS_LDS / sizeof(T)];
-  constexpr int CP = 8;
+  constexpr int CAP = ROWS_LDS / (int)sizeof(T);
+  __shared__ T tile[CAP];
+  // every element a lane copies is loaded before any is stored (clamped
+  // indices, unconditional loads): one wait for memory per block
+  constexpr int EPT = CAP / TPB;
   const uint64_t r0 = (uint64_t)blockIdx.x * rows;
   const int nr = (int)min((uint64_t)rows, nrows - r0);
   const int cnt = nr * n;
   T* g = data + r0 * (uint64_t)n;
-  for (int k0 = threadIdx.x; k0 < cnt; k0 += CP * TPB) {
-    T v[CP];
+  {
+    T v[EPT];
 #pragma unroll
-    for (int u = 0; u < CP; ++u) {
-      const int k = k0 + u * TPB;
-      v[u] = k < cnt ? g[k] : T(0);
-    }
+    for (int u = 0; u < EPT; ++u) v[u] = g[min(threadIdx.x + (unsigned)(u * TPB), (unsigned)cnt - 1)];
 #pragma unroll
-    for (int u = 0; u < CP; ++u) {
-      const int k = k0 + u * TPB;
+    for (int u = 0; u < EPT; ++u) {
+      const int k = threadIdx.x + u * TPB;
       if (k < cnt) tile[(k / n) * stride + k % n] = v[u];
     }
   }

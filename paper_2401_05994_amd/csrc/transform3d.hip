@@ -601,28 +601,34 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
 // Thomas along the contiguous dimension on `rows` rows per block, then out = a +/- z.
 // The weights are restrict pointers (scalar loads); the sweeps are unrolled
 // so that their LDS reads and weight loads are issued ahead of the recurrence.
-template <typename T, bool ADD>
+// Each lane loads all of its EPT elements of the block's rows (clamped
+// indices, unconditional) before it stores any, so a block waits for memory
+// once per phase; LDSB bytes of LDS per block (32 KB lets five blocks share a
+// CU, whose memory phases then overlap the serial solves of the others).
+template <typename T, bool ADD, int LDSB>
 __global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T* out, uint64_t nrows, int n, int rows,
                                                       const T* __restrict__ ta, const T* __restrict__ tr,
                                                       const T* __restrict__ tcp) {
-  __shared__ T tile[AXPY_LDS / sizeof(T)];
+  constexpr int CAP = LDSB / (int)sizeof(T);
+  constexpr int EPT = CAP / NT;
+  __shared__ T tile[CAP];
   const uint64_t r0 = (uint64_t)blockIdx.x * rows;
   const int nr = (int)min((uint64_t)rows, nrows - r0);
   const uint64_t base = r0 * (uint64_t)n;
   const int cnt = nr * n;
-  // copies run CP loads ahead of their stores, so a lane waits once per CP elements
-  constexpr int CP = 8;
-  for (int k0 = threadIdx.x; k0 < cnt; k0 += CP * NT) {
-    T v[CP];
+  const unsigned last = (unsigned)cnt - 1;
+  // uniform row-block bases and 32-bit lane offsets
+  const T* zb = z + base;
+  const T* ab = a + base;
+  T* ob = out + base;
+  {
+    T v[EPT];
 #pragma unroll
-    for (int u = 0; u < CP; ++u) {
-      const int k = k0 + u * NT;
-      v[u] = k < cnt ? z[base + k] : T(0);
-    }
+    for (int u = 0; u < EPT; ++u) v[u] = zb[min(threadIdx.x + (unsigned)(u * NT), last)];
 #pragma unroll
-    for (int u = 0; u < CP; ++u) {
-      const int k = k0 + u * NT;
-      if (k < cnt) tile[k] = v[u];
+    for (int u = 0; u < EPT; ++u) {
+      const unsigned k = threadIdx.x + (unsigned)(u * NT);
+      if (k < (unsigned)cnt) tile[k] = v[u];
     }
   }
   __syncthreads();
@@ -643,18 +649,31 @@ __global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T*
     }
   }
   __syncthreads();
-  for (int k0 = threadIdx.x; k0 < cnt; k0 += CP * NT) {
-    T v[CP];
+  {
+    T v[EPT];
 #pragma unroll
-    for (int u = 0; u < CP; ++u) {
-      const int k = k0 + u * NT;
-      v[u] = k < cnt ? a[base + k] : T(0);
-    }
+    for (int u = 0; u < EPT; ++u) v[u] = ab[min(threadIdx.x + (unsigned)(u * NT), last)];
 #pragma unroll
-    for (int u = 0; u < CP; ++u) {
-      const int k = k0 + u * NT;
-      if (k < cnt) out[base + k] = ADD ? v[u] + tile[k] : v[u] - tile[k];
+    for (int u = 0; u < EPT; ++u) {
+      const unsigned k = threadIdx.x + (unsigned)(u * NT);
+      if (k < (unsigned)cnt) ob[k] = ADD ? v[u] + tile[k] : v[u] - tile[k];
     }
+  }
+}
+
+// Launch of k3_thomas2_axpy over the c0 * c1 rows of length c2: 32 KB of LDS
+// per block when a row fits, else 64 KB.
+template <typename T, bool ADD>
+void launch_thomas2_axpy(const T* z, const T* a, T* out, uint64_t nrows, int n, const T* ta, const T* tr,
+                         const T* tcp, hipStream_t st) {
+  if ((uint64_t)n * sizeof(T) <= (uint64_t)AXPY_LDS / 2) {
+    const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / 2 / sizeof(T) / n)));
+    hipLaunchKernelGGL((k3_thomas2_axpy<T, ADD, AXPY_LDS / 2>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT),
+                       0, st, z, a, out, nrows, n, rows, ta, tr, tcp);
+  } else {
+    const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / sizeof(T) / n)));
+    hipLaunchKernelGGL((k3_thomas2_axpy<T, ADD, AXPY_LDS>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT), 0,
+                       st, z, a, out, nrows, n, rows, ta, tr, tcp);
   }
 }
 
@@ -1397,10 +1416,7 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
   }
   {
     KernelTimer kt(fine ? "thomas2_add_fine" : "thomas2_add_coarse", st);
-    const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / sizeof(T) / p.c2)));
-    const uint64_t nrows = (uint64_t)p.c0 * p.c1;
-    hipLaunchKernelGGL((k3_thomas2_axpy<T, true>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT), 0, st, z,
-                       ucoarse, ucoarse, nrows, p.c2, rows, p.d2.ta, p.d2.tr, p.d2.tcp);
+    launch_thomas2_axpy<T, true>(z, ucoarse, ucoarse, (uint64_t)p.c0 * p.c1, p.c2, p.d2.ta, p.d2.tr, p.d2.tcp, st);
   }
   MG_HIP(hipGetLastError());
 }
@@ -1445,11 +1461,8 @@ void fused3d_recompose_finish(const Hierarchy& h, int l, const T* table, const T
   const bool fine = l == h.L;
   {
     KernelTimer kt(fine ? "rec_thomas2_sub_fine" : "rec_thomas2_sub_coarse", st);
-    const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / sizeof(T) / p.c2)));
-    const uint64_t nrows = (uint64_t)p.c0 * p.c1;
     // uc = u_{l-1} - z, written over z
-    hipLaunchKernelGGL((k3_thomas2_axpy<T, false>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT), 0, st, z,
-                       cur, z, nrows, p.c2, rows, p.d2.ta, p.d2.tr, p.d2.tcp);
+    launch_thomas2_axpy<T, false>(z, cur, z, (uint64_t)p.c0 * p.c1, p.c2, p.d2.ta, p.d2.tr, p.d2.tcp, st);
   }
   {
     KernelTimer kt(fine ? "interp_add3_fine" : "interp_add3_coarse", st);
