@@ -28,5 +28,8 @@ huffman    histogram, codebook, canonical codes, chunked bit packing
 codec      end-to-end compress / decompress to the wire format
 dense      brute-force dense projections used only to pin the above
 mlp        reference MLP (forward, backward, Adam) for the learned allocation
+snorm      L2 / s-norm error control
+refactor   bitplane precision segments, greedy retrieval, reconstruction
+chunked    out-of-core slab container
 """
 from . import grid, transform, alloc, quant, huffman, codec, dense, mlp  # noqa: F401
