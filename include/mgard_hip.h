@@ -432,6 +432,85 @@ mgard_status mgard_compress_chunked(uint32_t ndim, const uint64_t* shape, const 
 mgard_status mgard_decompress_chunked(const void* h_in, uint64_t in_bytes, void* h_out, uint64_t out_capacity,
                                       const mgard_opts* opts);
 
+/* ----------------------------------------------------------- refactoring
+ * The refactoring module (Sec. 2, software design: multilevel coefficients
+ * encoded into precision segments of different significance per level by
+ * bitplane encoding, the error of each segment accumulated, retrieval that
+ * fetches segments greedily by the error estimators; Sec. 3, second listing:
+ * refactor, request a tolerance, fetch the needed components, reconstruct,
+ * tolerance after tolerance).
+ *
+ * Per level l of the coefficient stream (stream order as for the stage
+ * calls), with e_l the integer for which max|c| = f 2^e_l, 1/2 <= f < 1, and
+ * B planes: m = floor(|c| 2^(B - e_l)) < 2^B and the sign bit c < 0.  The
+ * level's segments are its sign plane, then planes k = 0..B-1 holding bit
+ * B-1-k of every m, each packing the level's coefficients most significant
+ * bit first into 32-bit words (coefficient i at bit 31 - i%32 of word i/32).
+ * R_l[k] = max(m mod 2^(B-k)), k = 0..B, is the residual table; with the
+ * first k planes, c^ = dtype(+-(m with its low B-k bits cleared) 2^(e_l-B))
+ * and |c - c^| <= E_l[k] = (R_l[k]+1) 2^(e_l-B) + [k > 0] eps 2^e_l.
+ *
+ * Buffer (little-endian): 'MGRF', u16 version 1, u8 dtype, u8 ndim, u8 B,
+ * u8 coordinate flags, u16 0, u32 L, f64 max|u|, f64 ||u|| (the L2 norm of
+ * MGARD_NORM_S), u64 shape[ndim], f64 coordinates of each flagged dimension,
+ * i32 e_l[L+1] (-2^31 for an all-zero level), u32 R[(L+1)(B+1)] level-major,
+ * u64 level offsets[L+2] (bytes, in the segment area), zero padding to a
+ * multiple of 8 bytes (the metadata ends there), then the segment area: per
+ * level the sign plane and planes 0..B-1, ceil(N_l/32) words each. */
+
+/* Exact size of the refactored buffer (0 for invalid arguments). */
+uint64_t mgard_refactor_bound(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,
+                              uint32_t planes);
+
+/* Decomposes d_in (device) and writes the metadata and every segment of
+ * `planes` (1..32) bitplanes per level into d_out (device, out_capacity >=
+ * mgard_refactor_bound).  *out_bytes receives the size.  MGARD_ERR_NONFINITE
+ * for a NaN or an infinity in the input.  Synchronises opts->stream. */
+mgard_status mgard_refactor(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,
+                            uint32_t planes, const void* d_in, void* d_out, uint64_t out_capacity,
+                            uint64_t* out_bytes, const mgard_opts* opts);
+
+/* Host only.  h_meta holds the first `bytes` bytes of a refactored buffer;
+ * *meta_bytes receives the metadata's size (also, with MGARD_ERR_CAPACITY,
+ * the bytes needed when they are too few); levels, planes and total_bytes
+ * (nullable) receive L, B and the buffer's size.  MGARD_ERR_FORMAT for
+ * malformed metadata. */
+mgard_status mgard_refactor_inspect(const void* h_meta, uint64_t bytes, uint64_t* meta_bytes, uint32_t* levels,
+                                    uint32_t* planes, uint64_t* total_bytes);
+
+/* Host only: the retrieval plan.  From the planes already held per level
+ * (h_have, L+1 entries; NULL = none), adds one plane at a time to the level
+ * whose estimator term falls the most per byte fetched (a level's sign plane
+ * counts with its first plane; ties to the lowest level) until the estimate
+ * meets tau, and writes the planes to hold into h_want (max_levels >= L+1).
+ * Estimators: MGARD_NORM_LINF (opts->norm): 4 (L+1) eps max|u| + E_0[k_0] +
+ * sum_{l>=1} (1 + K_l) E_l[k_l] (K_l as for MGARD_ALLOC_PLAIN);
+ * MGARD_NORM_S: max(1, 2^(sL)) sqrt(W_0) 4 (L+1) eps max|u| +
+ * sqrt(sum_l 4^(s l) W_l E_l[k_l]^2).  tau = tol for MGARD_ABS, tol max|u|
+ * (L-infinity) or tol ||u|| (s = 0) for MGARD_REL.  *h_estimate (nullable)
+ * receives the estimate of h_want; when every plane is held and the estimate
+ * still exceeds tau, h_want holds all planes and the call succeeds. */
+mgard_status mgard_refactor_request(const void* h_meta, uint64_t bytes, double tol, const uint32_t* h_have,
+                                    uint32_t* h_want, uint32_t max_levels, double* h_estimate,
+                                    const mgard_opts* opts);
+
+/* Host only: the byte ranges of a refactored buffer to fetch to go from
+ * h_have to h_want planes per level (n_levels = L+1 entries each; NULL
+ * h_have = none): at most one contiguous range per level, level by level,
+ * offsets from the start of the buffer, into h_offsets / h_lengths (n_levels
+ * entries each); *count receives the number of ranges. */
+mgard_status mgard_refactor_ranges(const void* h_meta, uint64_t bytes, const uint32_t* h_have,
+                                   const uint32_t* h_want, uint32_t n_levels, uint64_t* h_offsets,
+                                   uint64_t* h_lengths, uint32_t* count);
+
+/* Reconstruction from the first h_planes[l] planes of every level (n_levels
+ * = L+1 entries, each <= B): d_in (device) holds a buffer of the full size
+ * whose metadata and those segments are filled in (the rest is not read);
+ * d_out (device) receives prod(shape) values of the stored dtype.  The
+ * metadata is read back to the host and checked first. */
+mgard_status mgard_reconstruct(const void* d_in, uint64_t in_bytes, const uint32_t* h_planes, uint32_t n_levels,
+                               void* d_out, uint64_t out_capacity, const mgard_opts* opts);
+
 /* ----------------------------------------------------------- measurement
  * Kernel timing with HIP events recorded on each launch's stream.
  * mgard_timing(1) clears earlier records and starts recording; (0) clears and

@@ -143,7 +143,9 @@ def words_per_plane(n: int) -> int:
     return (n + 31) // 32
 
 
-def refactor(u, B=32, coords=None) -> Refactored:
+def refactor(u, B=32, coords=None, l2norm=None) -> Refactored:
+    """l2norm, when given, replaces ||u|| computed here (a float64 sum that
+    another implementation took in another order)."""
     u = np.asarray(u)
     T = u.dtype.type
     if T not in (np.float32, np.float64):
@@ -154,7 +156,7 @@ def refactor(u, B=32, coords=None) -> Refactored:
         raise ValueError("non-finite input")
     hier = Hierarchy(u.shape, coords)
     maxabs = float(np.max(np.abs(u))) if u.size else 0.0
-    l2 = math.sqrt(SN.l2_norm_sq(u, hier))
+    l2 = math.sqrt(SN.l2_norm_sq(u, hier)) if l2norm is None else float(l2norm)
     coarsest, cbars = X.decompose(u, hier, T)
     stream = Q.to_stream(coarsest, cbars, hier)
     off = Q.level_offsets(hier)

@@ -104,6 +104,12 @@ def load_library():
         "mgard_batch_create": (C.c_int, [U32, P, D, P, U64, PU64, P, P, C.POINTER(P)]),
         "mgard_batch_launch": (C.c_int, [P, P]),
         "mgard_batch_free": (None, [P]),
+        "mgard_refactor_bound": (U64, [U32, PU64, P, C.c_int, U32]),
+        "mgard_refactor": (C.c_int, [U32, PU64, P, C.c_int, U32, P, P, U64, PU64, P]),
+        "mgard_refactor_inspect": (C.c_int, [P, U64, PU64, C.POINTER(U32), C.POINTER(U32), PU64]),
+        "mgard_refactor_request": (C.c_int, [P, U64, D, P, P, U32, PD, P]),
+        "mgard_refactor_ranges": (C.c_int, [P, U64, P, P, U32, P, P, C.POINTER(U32)]),
+        "mgard_reconstruct": (C.c_int, [P, U64, P, U32, P, U64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -704,3 +710,88 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ refactoring
+def mgard_refactor_bound(shape, dtype=F32, planes=32, coords=None):
+    lib = load_library()
+    cc = _Coords(coords, len(shape))
+    b = lib.mgard_refactor_bound(len(shape), _shape(shape), cc.ptr, dtype, planes)
+    if b == 0:
+        _check(-1)
+    return int(b)
+
+
+def mgard_refactor(u, planes=32, coords=None, out=None):
+    """Refactors a CUDA float tensor into bitplane segments.  Returns (uint8 CUDA buffer, nbytes)."""
+    torch = _torch()
+    lib = load_library()
+    u = u.contiguous()
+    dt = _dtype_code(u)
+    shape = tuple(u.shape)
+    cc = _Coords(coords, len(shape))
+    if out is None:
+        out = torch.empty(mgard_refactor_bound(shape, dt, planes, coords), dtype=torch.uint8, device=u.device)
+    nb = C.c_uint64(0)
+    o = make_opts()
+    _check(lib.mgard_refactor(len(shape), _shape(shape), cc.ptr, dt, planes, _ptr(u), _ptr(out), out.numel(),
+                              C.byref(nb), C.byref(o)))
+    return out, int(nb.value)
+
+
+def mgard_refactor_inspect(meta: bytes):
+    """(metadata bytes, levels, planes, total bytes) of a refactored buffer's first bytes."""
+    lib = load_library()
+    mb, L, B, tot = C.c_uint64(0), C.c_uint32(0), C.c_uint32(0), C.c_uint64(0)
+    b = C.create_string_buffer(bytes(meta), len(meta))
+    _check(lib.mgard_refactor_inspect(b, len(meta), C.byref(mb), C.byref(L), C.byref(B), C.byref(tot)))
+    return int(mb.value), int(L.value), int(B.value), int(tot.value)
+
+
+def _u32s(v):
+    return None if v is None else (C.c_uint32 * len(v))(*[int(x) for x in v])
+
+
+def mgard_refactor_request(meta: bytes, tol, have=None, eb="rel", norm="linf", s=0.0):
+    """Planes per level to hold for tol (greedy, from `have`), and the estimate."""
+    lib = load_library()
+    _, L, _, _ = mgard_refactor_inspect(meta)
+    want = (C.c_uint32 * (L + 1))()
+    est = C.c_double(0.0)
+    o = mgard_opts()
+    lib.mgard_default_opts(C.byref(o))
+    o.eb = REL if eb == "rel" else ABS
+    o.norm = NORM_S if norm == "s" else NORM_LINF
+    o.s = float(s)
+    b = C.create_string_buffer(bytes(meta), len(meta))
+    _check(lib.mgard_refactor_request(b, len(meta), float(tol), _u32s(have), want, L + 1, C.byref(est), C.byref(o)))
+    return [int(x) for x in want], float(est.value)
+
+
+def mgard_refactor_ranges(meta: bytes, have, want):
+    """Byte ranges (offset, length) of the buffer to fetch to go from `have` to `want` planes."""
+    lib = load_library()
+    n = len(want)
+    offs, lens, cnt = (C.c_uint64 * n)(), (C.c_uint64 * n)(), C.c_uint32(0)
+    b = C.create_string_buffer(bytes(meta), len(meta))
+    _check(lib.mgard_refactor_ranges(b, len(meta), _u32s(have), _u32s(want), n, offs, lens, C.byref(cnt)))
+    return [(int(offs[i]), int(lens[i])) for i in range(cnt.value)]
+
+
+def mgard_reconstruct(buf, nbytes, planes, out=None):
+    """Reconstruction from the first planes[l] planes of every level of a refactored CUDA buffer."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        import struct
+
+        head = buf[: min(nbytes, 64)].cpu().numpy().tobytes()
+        if len(head) < 40 or head[:4] != b"MGRF" or not 1 <= head[7] <= 4:
+            raise MgardError(-7, "not a refactored buffer")
+        dt, nd = head[6], head[7]
+        shape = struct.unpack_from("<%dQ" % nd, head, 32)
+        out = torch.empty(shape, dtype=torch.float64 if dt else torch.float32, device=buf.device)
+    o = make_opts()
+    _check(lib.mgard_reconstruct(_ptr(buf), nbytes, _u32s(planes), len(planes), _ptr(out),
+                                 out.numel() * out.element_size(), C.byref(o)))
+    return out

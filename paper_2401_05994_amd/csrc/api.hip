@@ -2013,4 +2013,197 @@ mgard_status mgard_decompress_chunked(const void* h_in, uint64_t in_bytes, void*
 }
 
 
+// ------------------------------------------------------------------ refactoring
+uint64_t mgard_refactor_bound(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,
+                              uint32_t planes) {
+  try {
+    if (planes < 1 || planes > 32) return 0;
+    (void)dtype_size(dtype);
+    auto h = get_hierarchy(ndim, shape, coords);
+    bool hc[MAXD] = {false, false, false, false};
+    for (uint32_t d = 0; d < ndim; ++d) hc[d] = coords && coords[d];
+    const RfLevels lv = rf_levels(*h, planes);
+    return rf_meta_layout(*h, hc, planes, lv).total;
+  } catch (...) {
+    return 0;
+  }
+}
+
+mgard_status mgard_refactor(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,
+                            uint32_t planes, const void* d_in, void* d_out, uint64_t out_capacity, uint64_t* out_bytes,
+                            const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    const int s = dtype_size(dtype);
+    if (!d_in || !d_out || !out_bytes) fail(MGARD_ERR_ARG, "null buffer");
+    if (planes < 1 || planes > 32) fail(MGARD_ERR_ARG, "planes must be 1..32");
+    auto h = get_hierarchy(ndim, shape, coords);
+    bool hc[MAXD] = {false, false, false, false};
+    for (uint32_t d = 0; d < ndim; ++d) hc[d] = coords && coords[d];
+    const RfLevels lv = rf_levels(*h, planes);
+    const RfMetaLayout ml = rf_meta_layout(*h, hc, planes, lv);
+    *out_bytes = ml.total;
+    if (out_capacity < ml.total) fail(MGARD_ERR_CAPACITY, "output capacity below mgard_refactor_bound");
+    const bool f64 = dtype == MGARD_F64;
+    const uint64_t n = h->count(h->L);
+    const void* table = device_table(*h, f64, o.st);
+    const double* bands = device_mass_table(*h, o.st);
+    const uint64_t dbytes = f64 ? decompose_scratch_bytes<double>(*h) : decompose_scratch_bytes<float>(*h);
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<char>(n * s) + carve_size<char>(dbytes) + carve_size<uint64_t>(MAXL + 2) +
+               carve_size<uint64_t>(1) + carve_size<double>(1) + carve_size<char>(mass_norm_scratch_bytes()) +
+               carve_size<int>(MAXL + 2) + 4096);
+    Carver cv(ws.base());
+    char* cstream = cv.take<char>(n * s);
+    void* dscratch = cv.take<char>(dbytes);
+    uint64_t* lbits = cv.take<uint64_t>(MAXL + 2);
+    uint64_t* ubits = cv.take<uint64_t>(1);
+    double* nrm2 = cv.take<double>(1);
+    void* nscr = cv.take<char>(mass_norm_scratch_bytes());
+    int* exps = cv.take<int>(MAXL + 2);
+    const std::vector<uint8_t> hb = rf_header(*h, coords, f64 ? 1 : 0, planes, lv, ml);
+    char* out = static_cast<char*>(d_out);
+    MG_HIP(hipMemcpyAsync(out, hb.data(), hb.size(), hipMemcpyHostToDevice, o.st));
+    uint64_t hbits = 0;
+    if (f64)
+      launch_maxabs<double>(static_cast<const double*>(d_in), n, ubits, o.st);
+    else
+      launch_maxabs<float>(static_cast<const float*>(d_in), n, ubits, o.st);
+    MG_HIP(hipMemcpyAsync(&hbits, ubits, 8, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+    if (hbits >= (f64 ? 0x7ff0000000000000ull : 0x7f800000ull)) fail(MGARD_ERR_NONFINITE, "NaN or infinity");
+    uint32_t* seg = reinterpret_cast<uint32_t*>(out + ml.meta_bytes);
+    uint32_t* R = reinterpret_cast<uint32_t*>(out + ml.R_off);
+    if (f64) {
+      launch_mass_norm<double>(*h, bands, static_cast<const double*>(d_in), nscr, nrm2, o.st);
+      decompose<double>(*h, static_cast<const double*>(table), static_cast<const double*>(d_in),
+                        reinterpret_cast<double*>(cstream), nullptr, dscratch, o.st);
+      for (int l = 0; l <= h->L; ++l)
+        launch_maxabs<double>(reinterpret_cast<const double*>(cstream) + h->level_off[l], h->level_count[l],
+                              lbits + l, o.st);
+    } else {
+      launch_mass_norm<float>(*h, bands, static_cast<const float*>(d_in), nscr, nrm2, o.st);
+      decompose<float>(*h, static_cast<const float*>(table), static_cast<const float*>(d_in),
+                       reinterpret_cast<float*>(cstream), nullptr, dscratch, o.st);
+      for (int l = 0; l <= h->L; ++l)
+        launch_maxabs<float>(reinterpret_cast<const float*>(cstream) + h->level_off[l], h->level_count[l],
+                             lbits + l, o.st);
+    }
+    launch_rf_meta(lbits, ubits, nrm2, f64 ? 1 : 0, h->L + 1, exps, out, ml.exp_off, o.st);
+    if (f64)
+      launch_rf_planes<double>(reinterpret_cast<const double*>(cstream), lv, (int)planes, exps, seg, R, o.st);
+    else
+      launch_rf_planes<float>(reinterpret_cast<const float*>(cstream), lv, (int)planes, exps, seg, R, o.st);
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
+mgard_status mgard_refactor_inspect(const void* h_meta, uint64_t bytes, uint64_t* meta_bytes, uint32_t* levels,
+                                    uint32_t* planes, uint64_t* total_bytes) {
+  return guard([&] {
+    if (!h_meta || !meta_bytes) fail(MGARD_ERR_ARG, "null pointer");
+    RfParsed P;
+    if (!rf_parse(static_cast<const uint8_t*>(h_meta), bytes, P)) {
+      *meta_bytes = P.need;
+      fail(MGARD_ERR_CAPACITY, "more metadata bytes needed");
+    }
+    *meta_bytes = P.meta_bytes;
+    if (levels) *levels = (uint32_t)P.L;
+    if (planes) *planes = (uint32_t)P.B;
+    if (total_bytes) *total_bytes = P.meta_bytes + P.loff[P.L + 1];
+  });
+}
+
+mgard_status mgard_refactor_request(const void* h_meta, uint64_t bytes, double tol, const uint32_t* h_have,
+                                    uint32_t* h_want, uint32_t max_levels, double* h_estimate,
+                                    const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!h_meta || !h_want) fail(MGARD_ERR_ARG, "null pointer");
+    if (!(tol > 0.0) || !std::isfinite(tol)) fail(MGARD_ERR_TOL, "tolerance must be positive and finite");
+    RfParsed P;
+    if (!rf_parse(static_cast<const uint8_t*>(h_meta), bytes, P)) fail(MGARD_ERR_CAPACITY, "truncated metadata");
+    if (max_levels < (uint32_t)P.L + 1) fail(MGARD_ERR_CAPACITY, "h_want shorter than levels + 1");
+    const double* cp[MAXD];
+    auto h = get_hierarchy((uint32_t)P.ndim, P.shape, P.coord_ptrs(cp));
+    rf_check_layout(P, *h, nullptr);
+    const std::vector<uint32_t> k = rf_request(P, *h, tol, o.eb, o.norm, o.s, h_have, h_estimate);
+    for (int l = 0; l <= P.L; ++l) h_want[l] = k[l];
+  });
+}
+
+mgard_status mgard_refactor_ranges(const void* h_meta, uint64_t bytes, const uint32_t* h_have,
+                                   const uint32_t* h_want, uint32_t n_levels, uint64_t* h_offsets,
+                                   uint64_t* h_lengths, uint32_t* count) {
+  return guard([&] {
+    if (!h_meta || !h_want || !h_offsets || !h_lengths || !count) fail(MGARD_ERR_ARG, "null pointer");
+    RfParsed P;
+    if (!rf_parse(static_cast<const uint8_t*>(h_meta), bytes, P)) fail(MGARD_ERR_CAPACITY, "truncated metadata");
+    if (n_levels != (uint32_t)P.L + 1) fail(MGARD_ERR_ARG, "plane arrays must hold levels + 1 entries");
+    uint32_t c = 0;
+    for (int l = 0; l <= P.L; ++l) {
+      const uint32_t hv = h_have ? h_have[l] : 0u, wt = h_want[l];
+      if (hv > (uint32_t)P.B || wt > (uint32_t)P.B) fail(MGARD_ERR_ARG, "more planes than stored");
+      if (wt <= hv) continue;
+      const uint64_t pb = (P.loff[l + 1] - P.loff[l]) / (uint64_t)(P.B + 1);
+      const uint64_t first = hv == 0 ? 0 : hv + 1, last = (uint64_t)wt + 1;  // slot 0: the sign plane
+      h_offsets[c] = P.meta_bytes + P.loff[l] + first * pb;
+      h_lengths[c] = (last - first) * pb;
+      ++c;
+    }
+    *count = c;
+  });
+}
+
+mgard_status mgard_reconstruct(const void* d_in, uint64_t in_bytes, const uint32_t* h_planes, uint32_t n_levels,
+                               void* d_out, uint64_t out_capacity, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_in || !h_planes || !d_out) fail(MGARD_ERR_ARG, "null buffer");
+    std::vector<uint8_t> hb(256);
+    RfParsed P;
+    for (;;) {
+      const uint64_t got = std::min<uint64_t>(hb.size(), in_bytes);
+      MG_HIP(hipMemcpyAsync(hb.data(), d_in, got, hipMemcpyDeviceToHost, o.st));
+      MG_HIP(hipStreamSynchronize(o.st));
+      if (rf_parse(hb.data(), got, P)) break;
+      if (P.need > in_bytes) fail(MGARD_ERR_FORMAT, "truncated refactored buffer");
+      hb.resize(P.need);
+    }
+    if (n_levels != (uint32_t)P.L + 1) fail(MGARD_ERR_ARG, "h_planes must hold levels + 1 entries");
+    const double* cp[MAXD];
+    auto h = get_hierarchy((uint32_t)P.ndim, P.shape, P.coord_ptrs(cp));
+    RfLevels lv;
+    rf_check_layout(P, *h, &lv);
+    if (in_bytes < P.meta_bytes + P.loff[P.L + 1]) fail(MGARD_ERR_FORMAT, "truncated refactored buffer");
+    const uint64_t n = h->count(h->L);
+    const int s = P.dtype ? 8 : 4;
+    if (out_capacity < n * s) fail(MGARD_ERR_CAPACITY, "output buffer too small");
+    for (int l = 0; l <= P.L; ++l) {
+      if (h_planes[l] > (uint32_t)P.B) fail(MGARD_ERR_ARG, "more planes requested than stored");
+      lv.planes[l] = (int)h_planes[l];
+      lv.exp[l] = P.exps[l];
+    }
+    const bool f64 = P.dtype == 1;
+    const void* table = device_table(*h, f64, o.st);
+    const uint64_t rbytes = f64 ? recompose_scratch_bytes<double>(*h) : recompose_scratch_bytes<float>(*h);
+    Workspace& ws = workspace();
+    ws.reserve(carve_size<char>(n * s) + carve_size<char>(rbytes) + 1024);
+    Carver cv(ws.base());
+    char* cstream = cv.take<char>(n * s);
+    void* rscratch = cv.take<char>(rbytes);
+    const uint32_t* seg = reinterpret_cast<const uint32_t*>(static_cast<const char*>(d_in) + P.meta_bytes);
+    if (f64) {
+      launch_rf_decode<double>(seg, lv, P.B, reinterpret_cast<double*>(cstream), o.st);
+      recompose<double>(*h, static_cast<const double*>(table), reinterpret_cast<const double*>(cstream), nullptr,
+                        static_cast<double*>(d_out), rscratch, o.st);
+    } else {
+      launch_rf_decode<float>(seg, lv, P.B, reinterpret_cast<float*>(cstream), o.st);
+      recompose<float>(*h, static_cast<const float*>(table), reinterpret_cast<const float*>(cstream), nullptr,
+                       static_cast<float*>(d_out), rscratch, o.st);
+    }
+    MG_HIP(hipStreamSynchronize(o.st));
+  });
+}
+
 }  // extern "C"

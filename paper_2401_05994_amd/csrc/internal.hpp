@@ -286,6 +286,48 @@ void launch_mass_norm(const Hierarchy& h, const double* d_bands, const T* u, voi
 void launch_bins_snorm(int f64, const uint64_t* d_maxbits, const double* d_nrm2, double tol, int rel, int L,
                        const SnormArgs& a, double* d_bins, double* d_scalars, hipStream_t st);
 
+// Refactoring into bitplane precision segments (refactor.hip).  Per level:
+// stream offset and count, words per plane, the level's first word in the
+// segment area (sign plane, then B planes), its first wavefront (2048
+// coefficients each); for reconstruction also the exponent and planes used.
+struct RfLevels {
+  int nlev;
+  uint64_t off[MAXL + 2], n[MAXL + 2], words[MAXL + 2], word_off[MAXL + 2], wave0[MAXL + 2];
+  int exp[MAXL + 2], planes[MAXL + 2];
+};
+RfLevels rf_levels(const Hierarchy& h, uint32_t B);
+struct RfMetaLayout {
+  uint64_t exp_off, R_off, loff_off, meta_bytes, total;
+};
+RfMetaLayout rf_meta_layout(const Hierarchy& h, const bool* has_coords, uint32_t B, const RfLevels& lv);
+std::vector<uint8_t> rf_header(const Hierarchy& h, const double* const* coords, int dtype, uint32_t B,
+                               const RfLevels& lv, const RfMetaLayout& m);
+struct RfParsed {
+  int dtype = 0, ndim = 0, B = 0, L = 0;
+  double maxabs = 0.0, l2norm = 0.0;
+  uint64_t shape[MAXD] = {0, 0, 0, 0};
+  bool has_coords[MAXD] = {false, false, false, false};
+  std::vector<std::vector<double>> coords;
+  std::vector<int> exps;
+  std::vector<uint32_t> R;
+  std::vector<uint64_t> loff;
+  uint64_t meta_bytes = 0, need = 0;
+  // coordinate pointers for get_hierarchy (NULL when every dimension is uniform)
+  const double* const* coord_ptrs(const double** buf) const;
+};
+// false (and P.need set) when more bytes are needed; throws on malformed input
+bool rf_parse(const uint8_t* b, uint64_t bytes, RfParsed& P);
+void rf_check_layout(const RfParsed& P, const Hierarchy& h, RfLevels* lv);
+std::vector<uint32_t> rf_request(const RfParsed& P, const Hierarchy& h, double tol, int eb, int norm, double s,
+                                 const uint32_t* have, double* estimate);
+template <typename T>
+void launch_rf_planes(const T* cs, const RfLevels& lv, int B, const int* exps, uint32_t* seg, uint32_t* R,
+                      hipStream_t st);
+void launch_rf_meta(const uint64_t* lbits, const uint64_t* ubits, const double* nrm2, int f64, int nlev, int* exps,
+                    void* hdr, uint64_t hdr_exp, hipStream_t st);
+template <typename T>
+void launch_rf_decode(const uint32_t* seg, const RfLevels& lv, int B, T* cs, hipStream_t st);
+
 // Huffman (huffman.hip).
 void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
                       uint32_t* chunk_esc, uint32_t* status, hipStream_t st);
