@@ -30,6 +30,7 @@ dense      brute-force dense projections used only to pin the above
 mlp        reference MLP (forward, backward, Adam) for the learned allocation
 snorm      L2 / s-norm error control
 refactor   bitplane precision segments, greedy retrieval, reconstruction
+lossless   second-stage zero-suppression coder (two-level bitmaps)
 chunked    out-of-core slab container
 """
 from . import grid, transform, alloc, quant, huffman, codec, dense, mlp  # noqa: F401
