@@ -88,6 +88,11 @@ typedef enum { MGARD_NORM_LINF = 0, MGARD_NORM_S = 1 } mgard_norm;
  *           (ablation; also meets the bound a priori). */
 typedef enum { MGARD_ALLOC_PLAIN = 0, MGARD_ALLOC_LEARNED = 1, MGARD_ALLOC_COUNT = 2 } mgard_alloc;
 
+/* Second lossless stage after the entropy coder (Sec. 2: the final lossless
+ * encoding).  ZS: zero suppression, see mgard_lossless_encode; mgard_compress
+ * then writes the 'MGZS' container of its stream when that is smaller. */
+typedef enum { MGARD_LOSSLESS_NONE = 0, MGARD_LOSSLESS_ZS = 1 } mgard_lossless;
+
 typedef struct mgard_model mgard_model; /* device-resident network weights */
 
 typedef struct {
@@ -97,7 +102,8 @@ typedef struct {
   uint32_t dict_size;     /* Huffman dictionary: power of two in [256, 8192]; 0 = 8192 */
   uint32_t chunk_symbols; /* symbols per independently decodable chunk, multiple of 256
                              in [256, 8192]; 0 = 1024 */
-  uint32_t reserved;
+  uint32_t lossless;      /* mgard_lossless: second lossless stage of mgard_compress,
+                             default MGARD_LOSSLESS_NONE */
   void* stream;              /* hipStream_t */
   const mgard_model* model;  /* required for MGARD_ALLOC_LEARNED */
   uint32_t norm;             /* mgard_norm, default MGARD_NORM_LINF */
@@ -145,6 +151,7 @@ mgard_status mgard_compress(uint32_t ndim, const uint64_t* shape, const double* 
 /* Decompresses in_bytes of d_in (device) into d_out (device, out_capacity
  * bytes, at least prod(shape)*sizeof(dtype) as stored in the header).  The
  * header is read back to the host first and validated before any decoding.
+ * A buffer in the 'MGZS' container of the lossless stage is decoded first.
  * hdr (nullable) receives the parsed header. */
 mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
                               uint64_t out_capacity, const mgard_opts* opts, mgard_header* hdr);
@@ -431,6 +438,40 @@ mgard_status mgard_compress_chunked(uint32_t ndim, const uint64_t* shape, const 
  * MGARD_ERR_FORMAT for a malformed container or slab stream. */
 mgard_status mgard_decompress_chunked(const void* h_in, uint64_t in_bytes, void* h_out, uint64_t out_capacity,
                                       const mgard_opts* opts);
+
+/* ------------------------------------------------------- lossless stage
+ * The final lossless stage (Sec. 2: quantized integers and precision
+ * segments "are compressed through lossless encoding"), as zero
+ * suppression, the redundancy this pipeline leaves after its entropy coder
+ * (the all-zero shortest code of a dominant symbol, the mostly-zero high
+ * bitplanes of the refactoring), in chunks coded independently:
+ *   the input bytes, zero-padded to whole little-endian 32-bit words, in
+ *   chunks of 4096 words (the last may be shorter, m words); level-1 bitmap:
+ *   bit 31 - i%32 of word i/32 set when word i is nonzero; level-2 bitmap:
+ *   the same over the level-1 words; a coded chunk is the level-2 bitmap,
+ *   the nonzero level-1 words, the nonzero words, each in order, and the
+ *   chunk is stored raw when that is not shorter than m words (a stored
+ *   length of m means raw).
+ * Container (little-endian): 'MGZS', u16 version 1, u16 0, u64 raw bytes,
+ * u64 chunks, u64 word offsets[chunks + 1] of the stored chunks, then the
+ * stored chunks.  mgard_decompress reads it as well as a plain stream. */
+
+/* Largest container for raw_bytes of input. */
+uint64_t mgard_lossless_bound(uint64_t raw_bytes);
+
+/* Encodes raw_bytes of d_in (device, 4-byte aligned) into d_out (device,
+ * out_capacity >= mgard_lossless_bound); *out_bytes receives the container's
+ * size.  Synchronises opts->stream. */
+mgard_status mgard_lossless_encode(const void* d_in, uint64_t raw_bytes, void* d_out, uint64_t out_capacity,
+                                   uint64_t* out_bytes, const mgard_opts* opts);
+
+/* Decodes a container (in_bytes at d_in, device) into d_out (device;
+ * out_capacity >= the raw size rounded up to a multiple of 4: whole words
+ * are written); *raw_bytes receives the raw size.  MGARD_ERR_FORMAT when the
+ * offsets or a chunk's bitmaps do not match its stored length (checked
+ * before any data word is read).  Synchronises opts->stream. */
+mgard_status mgard_lossless_decode(const void* d_in, uint64_t in_bytes, void* d_out, uint64_t out_capacity,
+                                   uint64_t* raw_bytes, const mgard_opts* opts);
 
 /* ----------------------------------------------------------- refactoring
  * The refactoring module (Sec. 2, software design: multilevel coefficients

@@ -37,7 +37,7 @@ class MgardError(RuntimeError):
 
 class mgard_opts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("eb", C.c_uint32), ("alloc", C.c_uint32),
-                ("dict_size", C.c_uint32), ("chunk_symbols", C.c_uint32), ("reserved", C.c_uint32),
+                ("dict_size", C.c_uint32), ("chunk_symbols", C.c_uint32), ("lossless", C.c_uint32),
                 ("stream", C.c_void_p), ("model", C.c_void_p), ("norm", C.c_uint32), ("reserved2", C.c_uint32),
                 ("s", C.c_double)]
 
@@ -110,6 +110,9 @@ def load_library():
         "mgard_refactor_request": (C.c_int, [P, U64, D, P, P, U32, PD, P]),
         "mgard_refactor_ranges": (C.c_int, [P, U64, P, P, U32, P, P, C.POINTER(U32)]),
         "mgard_reconstruct": (C.c_int, [P, U64, P, U32, P, U64, P]),
+        "mgard_lossless_bound": (U64, [U64]),
+        "mgard_lossless_encode": (C.c_int, [P, U64, P, U64, PU64, P]),
+        "mgard_lossless_decode": (C.c_int, [P, U64, P, U64, PU64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -170,10 +173,12 @@ def _dtype_code(t):
     raise TypeError("float32 or float64 tensor expected")
 
 
-def make_opts(eb="rel", alloc="plain", dict_size=8192, chunk=1024, stream=None, norm="linf", s=0.0):
-    """norm: "linf" (maximum error) or "s" (the s-norm of smoothness s; s = 0 is L2)."""
+def make_opts(eb="rel", alloc="plain", dict_size=8192, chunk=1024, stream=None, norm="linf", s=0.0, lossless=False):
+    """norm: "linf" (maximum error) or "s" (the s-norm of smoothness s; s = 0 is L2);
+    lossless: the zero-suppression stage after the entropy coder."""
     o = mgard_opts()
     load_library().mgard_default_opts(C.byref(o))
+    o.lossless = 1 if lossless else 0
     o.eb = REL if eb == "rel" else ABS
     o.alloc = ALLOC[alloc]
     o.dict_size = dict_size
@@ -199,15 +204,16 @@ def mgard_compress_bound(shape, dtype=F32, coords=None, dict_size=8192, chunk=10
 
 
 def mgard_compress(u, tol, coords=None, eb="rel", alloc="plain", dict_size=8192, chunk=1024, out=None, norm="linf",
-                   s=0.0):
-    """Compresses a CUDA float tensor.  Returns (uint8 CUDA buffer, nbytes, info dict)."""
+                   s=0.0, lossless=False):
+    """Compresses a CUDA float tensor.  Returns (uint8 CUDA buffer, nbytes, info dict).
+    lossless: add the zero-suppression stage (its container when that is smaller)."""
     torch = _torch()
     lib = load_library()
     u = u.contiguous()
     dt = _dtype_code(u)
     shape = tuple(u.shape)
     cc = _Coords(coords, len(shape))
-    o = make_opts(eb, alloc, dict_size, chunk, norm=norm, s=s)
+    o = make_opts(eb, alloc, dict_size, chunk, norm=norm, s=s, lossless=lossless)
     bound = mgard_compress_bound(shape, dt, coords, dict_size, chunk)
     if out is None:
         out = torch.empty(bound, dtype=torch.uint8, device=u.device)
@@ -229,11 +235,15 @@ def mgard_decompress(buf, nbytes, out=None):
     """Decompresses a uint8 CUDA buffer; returns the field as a CUDA tensor."""
     torch = _torch()
     lib = load_library()
-    head = buf[: min(int(nbytes), 1 << 16)].cpu().numpy().tobytes()
-    hd = mgard_inspect(head)
-    shape = tuple(hd["shape"])
-    dtype = torch.float32 if hd["dtype"] == 0 else torch.float64
     if out is None:
+        head = buf[: min(int(nbytes), 1 << 16)].cpu().numpy().tobytes()
+        if head[:4] == b"MGZS":
+            # the lossless stage's container: its stream is needed for the shape
+            buf, nbytes = mgard_lossless_decode(buf, nbytes)
+            head = buf[: min(int(nbytes), 1 << 16)].cpu().numpy().tobytes()
+        hd = mgard_inspect(head)
+        shape = tuple(hd["shape"])
+        dtype = torch.float32 if hd["dtype"] == 0 else torch.float64
         out = torch.empty(shape, dtype=dtype, device=buf.device)
     o = make_opts()
     h = mgard_header()
@@ -795,3 +805,36 @@ def mgard_reconstruct(buf, nbytes, planes, out=None):
     _check(lib.mgard_reconstruct(_ptr(buf), nbytes, _u32s(planes), len(planes), _ptr(out),
                                  out.numel() * out.element_size(), C.byref(o)))
     return out
+
+
+# ------------------------------------------------------------------ lossless stage
+def mgard_lossless_bound(raw_bytes):
+    return int(load_library().mgard_lossless_bound(int(raw_bytes)))
+
+
+def mgard_lossless_encode(buf, nbytes, out=None):
+    """Zero-suppression container of the first nbytes of a uint8 CUDA buffer: (buffer, nbytes)."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(mgard_lossless_bound(nbytes), dtype=torch.uint8, device=buf.device)
+    nb = C.c_uint64(0)
+    o = make_opts()
+    _check(lib.mgard_lossless_encode(_ptr(buf), int(nbytes), _ptr(out), out.numel(), C.byref(nb), C.byref(o)))
+    return out, int(nb.value)
+
+
+def mgard_lossless_decode(buf, nbytes, out=None, raw_bytes=None):
+    """Inverse of mgard_lossless_encode: (uint8 CUDA buffer, raw bytes)."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        if raw_bytes is None:
+            import struct
+
+            raw_bytes = struct.unpack_from("<Q", buf[:24].cpu().numpy().tobytes(), 8)[0]
+        out = torch.empty(4 * ((raw_bytes + 3) // 4), dtype=torch.uint8, device=buf.device)
+    rb = C.c_uint64(0)
+    o = make_opts()
+    _check(lib.mgard_lossless_decode(_ptr(buf), int(nbytes), _ptr(out), out.numel(), C.byref(rb), C.byref(o)))
+    return out, int(rb.value)

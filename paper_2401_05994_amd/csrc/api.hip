@@ -97,6 +97,7 @@ struct Opts {
   double s = 0.0;
   int dict = 8192;
   int chunk = 1024;
+  int lossless = MGARD_LOSSLESS_NONE;
   hipStream_t st = nullptr;
   const mgard_model* model = nullptr;
   const float* model_params = nullptr;  // device parameters of the model
@@ -132,6 +133,8 @@ Opts read_opts(const mgard_opts* o) {
     if (c < 256 || c > 8192 || (c % 256)) fail(MGARD_ERR_ARG, "chunk_symbols must be a multiple of 256 in [256, 8192]");
     r.chunk = (int)c;
   }
+  if (o->lossless > MGARD_LOSSLESS_ZS) fail(MGARD_ERR_ARG, "opts->lossless");
+  r.lossless = (int)o->lossless;
   r.st = static_cast<hipStream_t>(o->stream);
   r.model = o->model;
   return r;
@@ -1186,7 +1189,10 @@ const char* mgard_last_error(void) { return g_err.c_str(); }
 const char* mgard_version(void) { return "mgard-hip 1 (gfx950)"; }
 
 mgard_status mgard_release_workspace(void) {
-  return guard([&] { workspace().release(); });
+  return guard([&] {
+    workspace().release();
+    aux_workspace().release();
+  });
 }
 
 uint64_t mgard_compress_bound(uint32_t ndim, const uint64_t* shape, const double* const* coords,
@@ -1227,6 +1233,23 @@ mgard_status mgard_compress(uint32_t ndim, const uint64_t* shape, const double* 
     else
       compress_impl<double>(*h, coords, tol, static_cast<const double*>(d_in), static_cast<char*>(d_out),
                             out_bytes, o, info);
+    if (o.lossless == MGARD_LOSSLESS_ZS) {
+      // the stream's container, staged aside; kept when it is the smaller
+      const uint64_t nb = *out_bytes;
+      const uint64_t nch = (nb + 16383) / 16384;
+      Workspace& aux = aux_workspace();
+      aux.reserve(carve_size<char>(zs_bound(nb)) + carve_size<uint32_t>(nch + 1) + 1024);
+      Carver cv(aux.base());
+      char* stage = cv.take<char>(zs_bound(nb));
+      uint32_t* sizes = cv.take<uint32_t>(nch + 1);
+      const uint64_t cb = zs_encode(d_out, nb, stage, zs_bound(nb), sizes, o.st);
+      if (cb < nb) {
+        MG_HIP(hipMemcpyAsync(d_out, stage, cb, hipMemcpyDeviceToDevice, o.st));
+        MG_HIP(hipStreamSynchronize(o.st));
+        *out_bytes = cb;
+        if (info) info->out_bytes = cb;
+      }
+    }
   });
 }
 
@@ -1417,6 +1440,25 @@ mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
   return guard([&] {
     Opts o = read_opts(opts);
     if (!d_in || !d_out) fail(MGARD_ERR_ARG, "null buffer");
+    {
+      // a stream in the lossless stage's container: decoded aside first
+      uint8_t zh[24] = {0};
+      const uint64_t got = std::min<uint64_t>(in_bytes, 24);
+      MG_HIP(hipMemcpyAsync(zh, d_in, got, hipMemcpyDeviceToHost, o.st));
+      MG_HIP(hipStreamSynchronize(o.st));
+      uint64_t raw = 0, nch = 0;
+      if (got >= 4 && std::memcmp(zh, "MGZS", 4) == 0) {
+        if (!zs_parse(zh, in_bytes, &raw, &nch)) fail(MGARD_ERR_FORMAT, "malformed lossless container");
+        Workspace& aux = aux_workspace();
+        aux.reserve(carve_size<uint32_t>((raw + 3) / 4) + carve_size<uint64_t>(1) + 1024);
+        Carver cv(aux.base());
+        uint32_t* plain = cv.take<uint32_t>((raw + 3) / 4);
+        uint32_t* status = reinterpret_cast<uint32_t*>(cv.take<uint64_t>(1));
+        zs_decode(d_in, in_bytes, raw, nch, plain, status, o.st);
+        d_in = plain;
+        in_bytes = raw;
+      }
+    }
     std::vector<uint8_t> hb(std::min<uint64_t>(in_bytes, kFixed));
     if (in_bytes < kFixed) fail(MGARD_ERR_FORMAT, "buffer shorter than a header");
     MG_HIP(hipMemcpyAsync(hb.data(), d_in, kFixed, hipMemcpyDeviceToHost, o.st));
@@ -2012,6 +2054,47 @@ mgard_status mgard_decompress_chunked(const void* h_in, uint64_t in_bytes, void*
   });
 }
 
+
+// ------------------------------------------------------------------ lossless stage
+uint64_t mgard_lossless_bound(uint64_t raw_bytes) { return zs_bound(raw_bytes); }
+
+mgard_status mgard_lossless_encode(const void* d_in, uint64_t raw_bytes, void* d_out, uint64_t out_capacity,
+                                   uint64_t* out_bytes, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if ((!d_in && raw_bytes) || !d_out || !out_bytes) fail(MGARD_ERR_ARG, "null buffer");
+    if (reinterpret_cast<uintptr_t>(d_in) % 4) fail(MGARD_ERR_ARG, "d_in must be 4-byte aligned");
+    if (reinterpret_cast<uintptr_t>(d_out) % 8) fail(MGARD_ERR_ARG, "d_out must be 8-byte aligned");
+    const uint64_t nch = (raw_bytes + 16383) / 16384;
+    Workspace& aux = aux_workspace();
+    aux.reserve(carve_size<uint32_t>(nch + 1) + 1024);
+    Carver cv(aux.base());
+    uint32_t* sizes = cv.take<uint32_t>(nch + 1);
+    *out_bytes = zs_encode(d_in, raw_bytes, d_out, out_capacity, sizes, o.st);
+  });
+}
+
+mgard_status mgard_lossless_decode(const void* d_in, uint64_t in_bytes, void* d_out, uint64_t out_capacity,
+                                   uint64_t* raw_bytes, const mgard_opts* opts) {
+  return guard([&] {
+    Opts o = read_opts(opts);
+    if (!d_in || !d_out || !raw_bytes) fail(MGARD_ERR_ARG, "null buffer");
+    if (reinterpret_cast<uintptr_t>(d_in) % 8 || reinterpret_cast<uintptr_t>(d_out) % 4)
+      fail(MGARD_ERR_ARG, "d_in must be 8-byte and d_out 4-byte aligned");
+    uint8_t zh[24] = {0};
+    const uint64_t got = std::min<uint64_t>(in_bytes, 24);
+    MG_HIP(hipMemcpyAsync(zh, d_in, got, hipMemcpyDeviceToHost, o.st));
+    MG_HIP(hipStreamSynchronize(o.st));
+    uint64_t raw = 0, nch = 0;
+    if (!zs_parse(zh, in_bytes, &raw, &nch)) fail(MGARD_ERR_FORMAT, "not a lossless container");
+    *raw_bytes = raw;
+    if (out_capacity < 4 * ((raw + 3) / 4)) fail(MGARD_ERR_CAPACITY, "output buffer too small");
+    Workspace& aux = aux_workspace();
+    aux.reserve(1024);
+    uint32_t* status = static_cast<uint32_t*>(aux.base());
+    zs_decode(d_in, in_bytes, raw, nch, d_out, status, o.st);
+  });
+}
 
 // ------------------------------------------------------------------ refactoring
 uint64_t mgard_refactor_bound(uint32_t ndim, const uint64_t* shape, const double* const* coords, mgard_dtype dtype,

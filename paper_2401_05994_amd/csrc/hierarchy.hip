@@ -392,4 +392,12 @@ Workspace& workspace() {
   return ws[dev];
 }
 
+Workspace& aux_workspace() {
+  static Workspace ws[64];
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) fail(MGARD_ERR_DEVICE, "device index");
+  return ws[dev];
+}
+
 }  // namespace mg

@@ -123,6 +123,9 @@ class Workspace {
   uint64_t size_ = 0;
 };
 Workspace& workspace();
+// A second one, for staging that outlives calls which use the first (the
+// lossless stage's input or output around compression and decompression).
+Workspace& aux_workspace();
 
 struct Carver {
   char* p;
@@ -327,6 +330,20 @@ void launch_rf_meta(const uint64_t* lbits, const uint64_t* ubits, const double* 
                     void* hdr, uint64_t hdr_exp, hipStream_t st);
 template <typename T>
 void launch_rf_decode(const uint32_t* seg, const RfLevels& lv, int B, T* cs, hipStream_t st);
+
+// Second-stage lossless coder (lossless.hip).
+uint64_t zs_bound(uint64_t raw_bytes);
+// Encodes raw_bytes of d_in (4-byte aligned) into the container at d_out and
+// returns its size; d_sizes: scratch of ceil(raw_bytes / 16384) + 1 words.
+// Synchronises st.
+uint64_t zs_encode(const void* d_in, uint64_t raw_bytes, void* d_out, uint64_t capacity, uint32_t* d_sizes,
+                   hipStream_t st);
+// Fixed part of a container held on the host; false when it is not one.
+bool zs_parse(const uint8_t* h, uint64_t bytes, uint64_t* raw_bytes, uint64_t* nch);
+// Decodes into d_out (4 ceil(raw_bytes / 4) bytes); throws MGARD_ERR_FORMAT
+// for malformed input; status: one device word of scratch.  Synchronises st.
+void zs_decode(const void* d_in, uint64_t in_bytes, uint64_t raw_bytes, uint64_t nch, void* d_out, uint32_t* status,
+               hipStream_t st);
 
 // Huffman (huffman.hip).
 void launch_histogram(const uint16_t* sym, uint64_t n, int dict, int chunk, uint64_t* hist,
