@@ -125,12 +125,15 @@ def bench_batch(m, torch, launches: int = 3, tol: float = 1e-3):
     err = float((rec - fields[big]).abs().max())
     tau = tol * float(fields[big].abs().max())
     assert err <= tau, f"batch field {big}: L-infinity error {err} exceeds {tau}"
+    nk = b.launches
     b.close()
-    print(f"[bench] batch: {ms:.2f} ms per launch (plan {plan_s:.1f} s)", file=sys.stderr, flush=True)
+    print(f"[bench] batch: {ms:.2f} ms per launch, {nk} kernel launches per graph (plan {plan_s:.1f} s)",
+          file=sys.stderr, flush=True)
     return {"workload": "256 seeded float32 fields of uneven shapes (2D 65..2049 per side, 3D 33..257), "
                         "slopes U[-4,-5/3], rel Linf 1e-3, one graph launch", "fields": len(fields),
             "in_bytes": in_bytes, "ms_per_launch": round(ms, 3), "GBps": round(in_bytes / (ms * 1e-3) / 1e9, 3),
-            "ratio": round(in_bytes / out_bytes, 4), "plan_s": round(plan_s, 2), "launches": launches}
+            "ratio": round(in_bytes / out_bytes, 4), "plan_s": round(plan_s, 2), "launches": launches,
+            "kernel_launches_per_graph": nk}
 
 
 def bench_chunked(m, torch, n: int = 1025, slab: int = 129, tol: float = 1e-3, reps: int = 2):

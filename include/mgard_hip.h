@@ -171,9 +171,12 @@ mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
  * call allocates the plan's scratch (one device allocation, owned by the
  * plan), uploads the headers and constant tables, runs the autotuner for the
  * fields' level shapes (mgard_autotune), then captures every field's
- * compression into one HIP graph over a few parallel branches.  Nothing in the
- * graph allocates, copies from host memory, sets memory or synchronises with
- * the host.  Inputs and output are bound at creation: each launch compresses
+ * compression into one HIP graph of grouped launches: every field's kernel
+ * launches are recorded in order, and launches of the same kernel by many
+ * fields run as one launch whose blocks find their field's arguments, grid
+ * and block index in a device table (the auto-tuning and adaptive
+ * scheduling layer of Sec. 2.2).  Nothing in the graph allocates, copies
+ * from host memory, sets memory or synchronises with the host.  Inputs and output are bound at creation: each launch compresses
  * the current contents of the same input buffers.  MGARD_ERR_CAPACITY when
  * out_capacity < mgard_batch_bound().
  *
@@ -196,6 +199,8 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
                                 const mgard_opts* opts, mgard_batch** plan);
 mgard_status mgard_batch_launch(mgard_batch* plan, void* stream);
 void mgard_batch_free(mgard_batch* plan);
+/* Kernel launches in one graph launch of the plan (0 for NULL). */
+uint32_t mgard_batch_launches(const mgard_batch* plan);
 
 /* Autotuner: the auto-tuning part of the library's adaptive scheduling layer
  * (Sec. 2.2, software architecture).  For each level of the fused 3D path of this

@@ -104,6 +104,7 @@ def load_library():
         "mgard_batch_create": (C.c_int, [U32, P, D, P, U64, PU64, P, P, C.POINTER(P)]),
         "mgard_batch_launch": (C.c_int, [P, P]),
         "mgard_batch_free": (None, [P]),
+        "mgard_batch_launches": (U32, [P]),
         "mgard_refactor_bound": (U64, [U32, PU64, P, C.c_int, U32]),
         "mgard_refactor": (C.c_int, [U32, PU64, P, C.c_int, U32, P, P, U64, PU64, P]),
         "mgard_refactor_inspect": (C.c_int, [P, U64, PU64, C.POINTER(U32), C.POINTER(U32), PU64]),
@@ -698,6 +699,7 @@ class Batch:
                                       offs, _ptr(self.sizes), C.byref(o), C.byref(plan)))
         self.plan = plan
         self.offsets = [int(offs[i]) for i in range(n)]
+        self.launches = int(lib.mgard_batch_launches(plan))
 
     def launch(self, stream=None):
         if stream is None:

@@ -51,12 +51,44 @@ struct mgard_batch {
   int device = -1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  void* mem = nullptr;
+  void* mem = nullptr;     // every field's static header and scratch
+  void* tables = nullptr;  // the grouped launches' job tables
+  uint32_t launches = 0;   // grouped launches per graph launch
 };
 
 namespace mg {
 
 void fail(mgard_status code, const std::string& msg) { throw Failure{code, msg}; }
+
+Recorder*& recorder() {
+  thread_local Recorder* r = nullptr;
+  return r;
+}
+
+namespace {
+// device-to-device copy of whole 8-byte words, as a kernel a batch can regroup
+__device__ __forceinline__ void k_copy_u64(G3 mg_bid, G3 mg_gdim, uint64_t* __restrict__ dst,
+                                           const uint64_t* __restrict__ src, uint64_t n) {
+  for (uint64_t i = (uint64_t)mg_bid.x * 256 + threadIdx.x; i < n; i += (uint64_t)mg_gdim.x * 256) dst[i] = src[i];
+}
+__global__ void __launch_bounds__(256) k_copy_u64_k(uint64_t* __restrict__ dst, const uint64_t* __restrict__ src,
+                                                    uint64_t n) {
+  k_copy_u64(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, dst, src, n);
+}
+}  // namespace
+
+// A static header copied into a stream's output: a copy on the stream, or a
+// recorded copy kernel while a batch records (its bytes are whole words).
+void copy_d2d(void* dst, const void* src, uint64_t bytes, hipStream_t st) {
+  if (!recorder()) {
+    MG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+    return;
+  }
+  if (bytes % 8 || reinterpret_cast<uintptr_t>(dst) % 8 || reinterpret_cast<uintptr_t>(src) % 8)
+    fail(MGARD_ERR_ARG, "recorded copies move whole aligned words");
+  const uint64_t n = bytes / 8;
+  MG_LAUNCH((&k_copy_u64), (k_copy_u64_k), (256), (0), (dim3((unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 1024)))), st, static_cast<uint64_t*>(dst), static_cast<const uint64_t*>(src), n);
+}
 
 static const float* model_params(const mgard_model* m) {
   int dev = 0;
@@ -192,7 +224,7 @@ struct Finale {  // device results read back by the host at the end
   double bins[MAXL + 1];
 };
 
-__global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* esc_off, uint64_t nch,
+__device__ __forceinline__ void k_finalize(G3 mg_bid, G3 mg_gdim, char* out, const uint64_t* word_off, const uint64_t* esc_off, uint64_t nch,
                            uint64_t payload_off, const uint64_t* esc_words, const double* scalars,
                            const double* bins, int L, uint64_t bins_off, int learned, Finale* fin,
                            uint64_t* size_out) {
@@ -222,6 +254,14 @@ __global__ void k_finalize(char* out, const uint64_t* word_off, const uint64_t* 
   }
   for (int l = 0; l <= L; ++l) fin->bins[l] = bins[l];
 }
+
+__global__ void k_finalize_k(char* out, const uint64_t* word_off, const uint64_t* esc_off, uint64_t nch,
+                           uint64_t payload_off, const uint64_t* esc_words, const double* scalars,
+                           const double* bins, int L, uint64_t bins_off, int learned, Finale* fin,
+                           uint64_t* size_out) {
+  k_finalize(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, out, word_off, esc_off, nch, payload_off, esc_words, scalars, bins, L, bins_off, learned, fin, size_out);
+}
+
 
 std::vector<uint8_t> header_bytes(const Hierarchy& h, const double* const* coords, int dtype, int eb,
                                   int alloc, double tol, int dict, int chunk, uint64_t n,
@@ -509,7 +549,7 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
   uint32_t* chunk_bits = reinterpret_cast<uint32_t*>(d_out + y.chunk_bits);
   uint8_t* code_len = reinterpret_cast<uint8_t*>(d_out + y.code_len);
   if (phase != CE_BACK) {
-  MG_HIP(hipMemcpyAsync(d_out, header, header_bytes, hipMemcpyDeviceToDevice, st));
+  copy_d2d(d_out, header, header_bytes, st);
   launch_fill_u64(&misc[2], 1, 0, st);
 
   // tolerance and bin widths
@@ -595,7 +635,11 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
                             st);
     side.join(st);
   } else {
+    // a recording batch aligns the fields' decompositions (of different
+    // lengths) separately from the stages before and after them
+    if (Recorder* r = recorder()) r->phase = 1;
     decompose<T>(h, table, d_in, nullptr, &q, dscratch, st);
+    if (Recorder* r = recorder()) r->phase = 2;
   }
 
   // lossless stage, tables written in place
@@ -613,9 +657,7 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
   launch_escape_pack(sym, n, o.chunk, esc_off, word_off, nch, cb.ecodes, h.L + 1, lt, d_out, y.payload,
                      reinterpret_cast<uint64_t*>(d_out + y.lesc), reinterpret_cast<uint32_t*>(d_out + y.lbits),
                      cb.esc_start, cb.esc_wmax, cb.esc_woff, st);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, st, d_out, word_off, esc_off, nch, y.payload,
-                     cb.esc_woff + (h.L + 1), scalars, bins, h.L, y.bins, o.alloc == MGARD_ALLOC_LEARNED ? 1 : 0,
-                     fin, size_out);
+  MG_LAUNCH((&k_finalize), (k_finalize_k), (1), (0), (dim3(1)), st, d_out, word_off, esc_off, nch, y.payload, cb.esc_woff + (h.L + 1), scalars, bins, h.L, y.bins, o.alloc == MGARD_ALLOC_LEARNED ? 1 : 0, fin, size_out);
   MG_HIP(hipGetLastError());
   return fin;
 }
@@ -1296,29 +1338,16 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
     uint64_t out_total = 0, mem_total = 0;
     std::vector<BatchJob> jobs = plan_jobs(nfields, fields, tol, o, true, &out_total, &mem_total);
     if (out_capacity < out_total) fail(MGARD_ERR_CAPACITY, "output capacity below mgard_batch_bound");
-    // the codebook jobs of all fields (one grouped launch) sit after the fields' scratch
-    const uint64_t jobs_off = align256(mem_total);
-    mem_total = jobs_off + (uint64_t)nfields * sizeof(CodebookJob);
     if (hipMalloc(&B->mem, std::max<uint64_t>(mem_total, 256)) != hipSuccess) {
       (void)hipGetLastError();
       B->mem = nullptr;
       fail(MGARD_ERR_OOM, "batch scratch");
     }
     char* mem = static_cast<char*>(B->mem);
-    std::vector<CodebookJob> cjobs(nfields);
     for (uint32_t i = 0; i < nfields; ++i) {
       MG_HIP(hipMemcpy(mem + jobs[i].hdr_off, jobs[i].hb.data(), jobs[i].hb.size(), hipMemcpyHostToDevice));
       h_offsets[i] = jobs[i].out_off;
-      const BatchJob& J = jobs[i];
-      const CompressBufs cb = J.f64 ? carve_compress<double>(*J.h, J.y, o, mem + J.scr_off)
-                                    : carve_compress<float>(*J.h, J.y, o, mem + J.scr_off);
-      uint32_t *enc = nullptr, *maxlen = nullptr;
-      encode_tables(cb.enc_scratch, o.dict, &enc, &maxlen);
-      cjobs[i] = CodebookJob{cb.hist, reinterpret_cast<uint8_t*>(static_cast<char*>(d_out) + J.out_off + J.y.code_len),
-                             cb.codes, enc, maxlen};
     }
-    const CodebookJob* d_cjobs = reinterpret_cast<const CodebookJob*>(mem + jobs_off);
-    MG_HIP(hipMemcpy(mem + jobs_off, cjobs.data(), nfields * sizeof(CodebookJob), hipMemcpyHostToDevice));
     // launch shapes for every level shape not tuned yet
     for (uint32_t i = 0; i < nfields; ++i) {
       Hierarchy& h = *jobs[i].h;
@@ -1330,59 +1359,138 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
     }
     MG_HIP(hipDeviceSynchronize());
 
-    // capture: the fields spread over 16 forked streams, joined at the end.  More
-    // branches than the device's four hardware queues still pay: the graph's
-    // many short kernels overlap better (the 256-field batch took 91.6, 41.6,
-    // 35.0 and 33.0 ms per launch with 1, 4, 8 and 16 branches).
-    const int K = (int)std::min<uint32_t>(16, nfields);
-    hipStream_t cs = nullptr;
-    std::vector<hipStream_t> ss(K, nullptr);
-    std::vector<hipEvent_t> ev(K + 1, nullptr);
-    auto cleanup = [&] {
-      for (auto& e : ev)
-        if (e) (void)hipEventDestroy(e);
-      for (auto& x : ss)
-        if (x) (void)hipStreamDestroy(x);
-      if (cs) (void)hipStreamDestroy(cs);
-      timing_pause(false);
-    };
-    try {
-      MG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-      for (int k = 0; k < K; ++k) MG_HIP(hipStreamCreateWithFlags(&ss[k], hipStreamNonBlocking));
-      for (int k = 0; k <= K; ++k) MG_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+    // Every field's launches, recorded in order: up to the histogram, the
+    // codebook, then the rest (the order of a single compression, with no
+    // side stream).
+    std::vector<Recorder> recs(nfields);
+    {
+      struct Restore {
+        ~Restore() {
+          recorder() = nullptr;
+          timing_pause(false);
+        }
+      } restore;
       timing_pause(true);
+      for (uint32_t i = 0; i < nfields; ++i) {
+        const BatchJob& J = jobs[i];
+        char* out = static_cast<char*>(d_out) + J.out_off;
+        const uint8_t* hdr = reinterpret_cast<const uint8_t*>(mem + J.hdr_off);
+        recorder() = &recs[i];
+        auto record = [&](auto tag) {
+          using T = decltype(tag);
+          const T* in = static_cast<const T*>(fields[i].d_in);
+          const T* table = static_cast<const T*>(J.table);
+          compress_enqueue<T>(*J.h, table, J.y, tol, in, out, o, mem + J.scr_off, hdr, J.hb.size(), d_sizes + i,
+                              CE_FRONT);
+          const CompressBufs cb = carve_compress<T>(*J.h, J.y, o, mem + J.scr_off);
+          launch_codebook(cb.hist, o.dict, reinterpret_cast<uint8_t*>(out + J.y.code_len), cb.codes, cb.enc_scratch,
+                          o.st);
+          compress_enqueue<T>(*J.h, table, J.y, tol, in, out, o, mem + J.scr_off, hdr, J.hb.size(), d_sizes + i,
+                              CE_BACK);
+        };
+        if (J.f64)
+          record(double{});
+        else
+          record(float{});
+        recorder() = nullptr;
+      }
+    }
+
+    // Grouping.  Each field's records fall in three phases: the stages before
+    // the decomposition, the decomposition (whose length depends on the
+    // shape), the stages after it.  Every record gets a slot: its index in
+    // the first and third phases (those after the longest first phase), and
+    // in the decomposition its index counted back from the phase's end, so
+    // that every field finishes its decomposition in the same slot.  The
+    // records of one slot and body form one grouped launch; slots run in
+    // order, so each field's records keep their order, and fields share no
+    // memory.
+    struct Group {
+      const GroupOps* ops;
+      std::vector<const LaunchRecord*> members;
+    };
+    std::vector<size_t> len[3];
+    size_t maxlen[3] = {0, 0, 0};
+    for (uint32_t i = 0; i < nfields; ++i) {
+      size_t c[3] = {0, 0, 0};
+      int last = 0;
+      for (const LaunchRecord& r : recs[i].recs) {
+        if (r.phase < last || r.phase > 2) fail(MGARD_ERR_ARG, "recorded phases out of order");
+        last = r.phase;
+        ++c[r.phase];
+      }
+      for (int ph = 0; ph < 3; ++ph) {
+        len[ph].push_back(c[ph]);
+        maxlen[ph] = std::max(maxlen[ph], c[ph]);
+      }
+    }
+    const size_t nslots = maxlen[0] + maxlen[1] + maxlen[2];
+    std::vector<std::vector<Group>> slots(nslots);
+    for (uint32_t i = 0; i < nfields; ++i) {
+      size_t k[3] = {0, 0, 0};
+      for (const LaunchRecord& r : recs[i].recs) {
+        const int ph = r.phase;
+        size_t slot = k[ph]++;
+        if (ph == 1) slot += maxlen[0] + (maxlen[1] - len[1][i]);
+        if (ph == 2) slot += maxlen[0] + maxlen[1];
+        std::vector<Group>& gs = slots[slot];
+        Group* g = nullptr;
+        for (Group& x : gs)
+          if (x.ops == r.ops) g = &x;
+        if (!g) {
+          gs.push_back(Group{r.ops, {}});
+          g = &gs.back();
+        }
+        g->members.push_back(&r);
+      }
+    }
+    std::vector<Group> groups;
+    for (auto& gs : slots)
+      for (auto& g : gs) groups.push_back(std::move(g));
+
+    // job tables: per group, (first block, grid, arguments) of every member
+    std::vector<uint64_t> toff(groups.size());
+    std::vector<uint32_t> tblocks(groups.size());
+    uint64_t tbytes = 0;
+    for (size_t k = 0; k < groups.size(); ++k) {
+      toff[k] = tbytes;
+      tbytes = align256(tbytes + groups[k].members.size() * groups[k].ops->job_bytes);
+    }
+    std::vector<uint8_t> htab(std::max<uint64_t>(tbytes, 256), 0);
+    for (size_t k = 0; k < groups.size(); ++k) {
+      uint64_t begin = 0;
+      for (size_t m = 0; m < groups[k].members.size(); ++m) {
+        const LaunchRecord* r = groups[k].members[m];
+        groups[k].ops->write_job(htab.data() + toff[k] + m * groups[k].ops->job_bytes, (uint32_t)begin, r->grid,
+                                 r->pack.data());
+        begin += (uint64_t)r->grid.x * r->grid.y * r->grid.z;
+      }
+      if (begin > 0x7fffffffull) fail(MGARD_ERR_SHAPE, "a grouped launch needs more than 2^31 blocks");
+      tblocks[k] = (uint32_t)begin;
+    }
+    if (hipMalloc(&B->tables, htab.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      B->tables = nullptr;
+      fail(MGARD_ERR_OOM, "batch job tables");
+    }
+    MG_HIP(hipMemcpy(B->tables, htab.data(), htab.size(), hipMemcpyHostToDevice));
+
+    // one graph of the grouped launches, in order, on one stream
+    hipStream_t cs = nullptr;
+    MG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    try {
       MG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       try {
-        MG_HIP(hipEventRecord(ev[K], cs));
-        for (int k = 0; k < K; ++k) MG_HIP(hipStreamWaitEvent(ss[k], ev[K], 0));
-        // every field up to its histogram, all codebooks in one launch, then the rest
-        auto enqueue = [&](int phase) {
-          for (uint32_t i = 0; i < nfields; ++i) {
-            const BatchJob& J = jobs[i];
-            Opts oi = o;
-            oi.st = ss[i % K];
-            char* out = static_cast<char*>(d_out) + J.out_off;
-            const uint8_t* hdr = reinterpret_cast<const uint8_t*>(mem + J.hdr_off);
-            if (J.f64)
-              compress_enqueue<double>(*J.h, static_cast<const double*>(J.table), J.y, tol,
-                                       static_cast<const double*>(fields[i].d_in), out, oi, mem + J.scr_off, hdr,
-                                       J.hb.size(), d_sizes + i, phase);
-            else
-              compress_enqueue<float>(*J.h, static_cast<const float*>(J.table), J.y, tol,
-                                      static_cast<const float*>(fields[i].d_in), out, oi, mem + J.scr_off, hdr,
-                                      J.hb.size(), d_sizes + i, phase);
-          }
-          for (int k = 0; k < K; ++k) {
-            MG_HIP(hipEventRecord(ev[k], ss[k]));
-            MG_HIP(hipStreamWaitEvent(cs, ev[k], 0));
-          }
-        };
-        enqueue(CE_FRONT);
-        launch_codebook_group(d_cjobs, nfields, o.dict, cs);
-        MG_HIP(hipEventRecord(ev[K], cs));
-        for (int k = 0; k < K; ++k) MG_HIP(hipStreamWaitEvent(ss[k], ev[K], 0));
-        enqueue(CE_BACK);
+        uint32_t n = 0;
+        for (size_t k = 0; k < groups.size(); ++k) {
+          if (!tblocks[k]) continue;
+          groups[k].ops->launch(static_cast<char*>(B->tables) + toff[k], (uint32_t)groups[k].members.size(),
+                                tblocks[k], cs);
+          ++n;
+        }
+        MG_HIP(hipGetLastError());
         MG_HIP(hipStreamEndCapture(cs, &B->graph));
+        B->launches = n;
       } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(cs, &g);
@@ -1392,13 +1500,15 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
       }
       MG_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     } catch (...) {
-      cleanup();
+      (void)hipStreamDestroy(cs);
       throw;
     }
-    cleanup();
+    (void)hipStreamDestroy(cs);
     *plan = B.release();
   });
 }
+
+uint32_t mgard_batch_launches(const mgard_batch* plan) { return plan ? plan->launches : 0; }
 
 mgard_status mgard_batch_launch(mgard_batch* plan, void* stream) {
   return guard([&] {
@@ -1414,10 +1524,9 @@ void mgard_batch_free(mgard_batch* plan) {
   if (!plan) return;
   if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
-  if (plan->mem) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(plan->mem);
-  }
+  if (plan->mem || plan->tables) (void)hipDeviceSynchronize();
+  if (plan->mem) (void)hipFree(plan->mem);
+  if (plan->tables) (void)hipFree(plan->tables);
   delete plan;
 }
 

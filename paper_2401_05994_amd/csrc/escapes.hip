@@ -48,10 +48,10 @@ __device__ inline int level_of_index(const uint64_t* start, int nlev, uint64_t j
 // One wavefront per l <= nlev: ostart[l] = escapes before stream position
 // lt.off[l] (lt.off[nlev] = n): the chunk escape offset of the chunk holding
 // that position plus the escape symbols of the chunk before it.
-__global__ void __launch_bounds__(64) k_esc_starts(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
-                                                   const uint64_t* __restrict__ esc_off, LevelTable lt, int nlev,
+__device__ __forceinline__ void k_esc_starts(G3 mg_bid, G3 mg_gdim, const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+                                                   const uint64_t* __restrict__ esc_off, const LevelTable& lt, int nlev,
                                                    uint64_t* __restrict__ ostart) {
-  const int l = blockIdx.x;
+  const int l = mg_bid.x;
   const uint64_t p = l == nlev ? n : lt.off[l];
   const uint64_t c = p / (uint64_t)chunk;
   uint32_t cnt = 0;
@@ -60,8 +60,15 @@ __global__ void __launch_bounds__(64) k_esc_starts(const uint16_t* __restrict__ 
   if (threadIdx.x == 0) ostart[l] = esc_off[c] + cnt;
 }
 
+__global__ void __launch_bounds__(64) k_esc_starts_k(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+                                                   const uint64_t* __restrict__ esc_off, LevelTable lt, int nlev,
+                                                   uint64_t* __restrict__ ostart) {
+  k_esc_starts(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, sym, n, chunk, esc_off, lt, nlev, ostart);
+}
+
+
 // wmax[l] = max code of level l (wmax cleared by the caller)
-__global__ void __launch_bounds__(TPB) k_esc_widths(const uint64_t* __restrict__ ecodes,
+__device__ __forceinline__ void k_esc_widths(G3 mg_bid, G3 mg_gdim, const uint64_t* __restrict__ ecodes,
                                                     const uint64_t* __restrict__ ostart, int nlev,
                                                     unsigned long long* __restrict__ wmax) {
   __shared__ uint64_t st[MAXL + 2];
@@ -72,7 +79,7 @@ __global__ void __launch_bounds__(TPB) k_esc_widths(const uint64_t* __restrict__
   const uint64_t total = st[nlev];
   int l = -1;
   unsigned long long m = 0;
-  for (uint64_t j = (uint64_t)blockIdx.x * TPB + threadIdx.x; j < total; j += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t j = (uint64_t)mg_bid.x * TPB + threadIdx.x; j < total; j += (uint64_t)mg_gdim.x * TPB) {
     if (l < 0 || j >= st[l + 1]) {
       if (l >= 0 && m) atomicMax(&mx[l], m);
       l = level_of_index(st, nlev, j);
@@ -87,9 +94,16 @@ __global__ void __launch_bounds__(TPB) k_esc_widths(const uint64_t* __restrict__
     if (mx[k]) atomicMax(&wmax[k], mx[k]);
 }
 
+__global__ void __launch_bounds__(TPB) k_esc_widths_k(const uint64_t* __restrict__ ecodes,
+                                                    const uint64_t* __restrict__ ostart, int nlev,
+                                                    unsigned long long* __restrict__ wmax) {
+  k_esc_widths(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, ecodes, ostart, nlev, wmax);
+}
+
+
 // Per level: count and width into the header arrays, word offsets into woff
 // (nlev + 1 entries, woff[nlev] = all words).
-__global__ void k_esc_layout(const uint64_t* __restrict__ ostart, const unsigned long long* __restrict__ wmax,
+__device__ __forceinline__ void k_esc_layout(G3 mg_bid, G3 mg_gdim, const uint64_t* __restrict__ ostart, const unsigned long long* __restrict__ wmax,
                              int nlev, uint64_t* __restrict__ hdr_counts, uint32_t* __restrict__ hdr_bits,
                              uint64_t* __restrict__ woff) {
   if (threadIdx.x != 0) return;
@@ -104,6 +118,13 @@ __global__ void k_esc_layout(const uint64_t* __restrict__ ostart, const unsigned
   }
   woff[nlev] = w;
 }
+
+__global__ void k_esc_layout_k(const uint64_t* __restrict__ ostart, const unsigned long long* __restrict__ wmax,
+                             int nlev, uint64_t* __restrict__ hdr_counts, uint32_t* __restrict__ hdr_bits,
+                             uint64_t* __restrict__ woff) {
+  k_esc_layout(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, ostart, wmax, nlev, hdr_counts, hdr_bits, woff);
+}
+
 
 // Bits [b, b + w) (w <= 64) of a word array of nw words, most-significant bit
 // first; words past the end read as 0.
@@ -125,7 +146,7 @@ __device__ inline uint64_t read_bits(const uint32_t* __restrict__ words, uint64_
 // One thread per output word (grid-stride): word j of level l holds bits
 // [32 (j - woff[l]), +32) of the level's concatenated codes.  The words go
 // after the payload (d_out + payload_off + 4 word_off[nch]).
-__global__ void __launch_bounds__(TPB) k_esc_pack(const uint64_t* __restrict__ ecodes,
+__device__ __forceinline__ void k_esc_pack(G3 mg_bid, G3 mg_gdim, const uint64_t* __restrict__ ecodes,
                                                   const uint64_t* __restrict__ ostart,
                                                   const uint64_t* __restrict__ woff_g,
                                                   const uint32_t* __restrict__ bits_g, int nlev, char* d_out,
@@ -141,7 +162,7 @@ __global__ void __launch_bounds__(TPB) k_esc_pack(const uint64_t* __restrict__ e
   __syncthreads();
   uint32_t* out = reinterpret_cast<uint32_t*>(d_out + payload_off + 4 * word_off[nch]);
   const uint64_t total = wo[nlev];
-  for (uint64_t j = (uint64_t)blockIdx.x * TPB + threadIdx.x; j < total; j += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t j = (uint64_t)mg_bid.x * TPB + threadIdx.x; j < total; j += (uint64_t)mg_gdim.x * TPB) {
     const int l = level_of_index(wo, nlev, j);
     const uint32_t w = wb[l];  // > 0: a level without bits has no words
     const uint64_t cnt = st[l + 1] - st[l];
@@ -159,6 +180,16 @@ __global__ void __launch_bounds__(TPB) k_esc_pack(const uint64_t* __restrict__ e
     out[j] = word;
   }
 }
+
+__global__ void __launch_bounds__(TPB) k_esc_pack_k(const uint64_t* __restrict__ ecodes,
+                                                  const uint64_t* __restrict__ ostart,
+                                                  const uint64_t* __restrict__ woff_g,
+                                                  const uint32_t* __restrict__ bits_g, int nlev, char* d_out,
+                                                  uint64_t payload_off, const uint64_t* __restrict__ word_off,
+                                                  uint64_t nch) {
+  k_esc_pack(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, ecodes, ostart, woff_g, bits_g, nlev, d_out, payload_off, word_off, nch);
+}
+
 
 // qside[epos[j]] = q of escape j, once every chunk has decoded cleanly; an
 // escape whose recorded position lies outside the level its index belongs to
@@ -191,12 +222,11 @@ void launch_escape_pack(const uint16_t* sym, uint64_t n, int chunk, const uint64
                         unsigned long long* wmax, uint64_t* woff, hipStream_t st) {
   KernelTimer kt("escapes", st);
   launch_fill_u64(reinterpret_cast<uint64_t*>(wmax), (uint64_t)nlev, 0, st);
-  hipLaunchKernelGGL(k_esc_starts, dim3(nlev + 1), dim3(64), 0, st, sym, n, chunk, esc_off, lt, nlev, ostart);
+  MG_LAUNCH((&k_esc_starts), (k_esc_starts_k), (64), (0), (dim3(nlev + 1)), st, sym, n, chunk, esc_off, lt, nlev, ostart);
   // few escapes unless the tolerance is tight: blocks past the escapes return at once
-  hipLaunchKernelGGL(k_esc_widths, dim3(grid_for(n / 4, 1024)), dim3(TPB), 0, st, ecodes, ostart, nlev, wmax);
-  hipLaunchKernelGGL(k_esc_layout, dim3(1), dim3(64), 0, st, ostart, wmax, nlev, hdr_counts, hdr_bits, woff);
-  hipLaunchKernelGGL(k_esc_pack, dim3(grid_for(n / 8, 2048)), dim3(TPB), 0, st, ecodes, ostart, woff,
-                     static_cast<const uint32_t*>(hdr_bits), nlev, d_out, payload_off, word_off, nch);
+  MG_LAUNCH((&k_esc_widths), (k_esc_widths_k), (TPB), (0), (dim3(grid_for(n / 4, 1024))), st, ecodes, ostart, nlev, wmax);
+  MG_LAUNCH((&k_esc_layout), (k_esc_layout_k), (64), (0), (dim3(1)), st, ostart, wmax, nlev, hdr_counts, hdr_bits, woff);
+  MG_LAUNCH((&k_esc_pack), (k_esc_pack_k), (TPB), (0), (dim3(grid_for(n / 8, 2048))), st, ecodes, ostart, woff, static_cast<const uint32_t*>(hdr_bits), nlev, d_out, payload_off, word_off, nch);
   MG_HIP(hipGetLastError());
 }
 

@@ -113,7 +113,7 @@ __device__ inline uint32_t group_sym(uint2 g, int j) {
   return (j & 1) ? (w >> 16) : (w & 0xffffu);
 }
 
-__global__ void __launch_bounds__(WAVE_T) k_histogram(const uint16_t* __restrict__ sym, uint64_t n, int dict,
+__device__ __forceinline__ void k_histogram(G3 mg_bid, G3 mg_gdim, const uint16_t* __restrict__ sym, uint64_t n, int dict,
                                                       int chunk, uint64_t k0, uint64_t nch,
                                                       unsigned long long* __restrict__ hist,
                                                       uint32_t* __restrict__ chunk_esc,
@@ -122,8 +122,8 @@ __global__ void __launch_bounds__(WAVE_T) k_histogram(const uint16_t* __restrict
   for (int b = threadIdx.x; b < dict; b += WAVE_T) sh[b] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const uint64_t stride = (uint64_t)gridDim.x * WAVES;
-  const uint64_t wave = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+  const uint64_t stride = (uint64_t)mg_gdim.x * WAVES;
+  const uint64_t wave = (uint64_t)mg_bid.x * WAVES + (threadIdx.x >> 6);
   bool bad = false;
   // full chunks of at most 1024 symbols: batched, prefetched loads
   uint64_t kslow = k0 + wave;  // first chunk left to the per-step loop below
@@ -178,6 +178,15 @@ __global__ void __launch_bounds__(WAVE_T) k_histogram(const uint16_t* __restrict
   for (int b = threadIdx.x; b < dict; b += WAVE_T)
     if (sh[b]) atomicAdd(&hist[b], (unsigned long long)sh[b]);
 }
+
+__global__ void __launch_bounds__(WAVE_T) k_histogram_k(const uint16_t* __restrict__ sym, uint64_t n, int dict,
+                                                      int chunk, uint64_t k0, uint64_t nch,
+                                                      unsigned long long* __restrict__ hist,
+                                                      uint32_t* __restrict__ chunk_esc,
+                                                      uint32_t* __restrict__ status) {
+  k_histogram(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, sym, n, dict, chunk, k0, nch, hist, chunk_esc, status);
+}
+
 
 // ------------------------------------------------------------------ wave helpers
 __device__ inline uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
@@ -556,29 +565,32 @@ __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist
   }
 }
 
-__global__ void __launch_bounds__(CB_T) k_codebook(const uint64_t* __restrict__ hist, int dict,
+__device__ __forceinline__ void k_codebook(G3 mg_bid, G3 mg_gdim, const uint64_t* __restrict__ hist, int dict,
                                                    uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes,
                                                    uint32_t* __restrict__ enc, uint32_t* __restrict__ maxlen_out) {
   codebook_block(hist, dict, len_out, codes, enc, maxlen_out);
 }
 
-// One codebook per block: the codebooks of a batch's fields in one launch.
-__global__ void __launch_bounds__(CB_T) k_codebook_group(const CodebookJob* __restrict__ jobs, int dict) {
-  const CodebookJob j = jobs[blockIdx.x];
-  codebook_block(j.hist, dict, j.len, j.codes, j.enc, j.maxlen);
+__global__ void __launch_bounds__(CB_T) k_codebook_k(const uint64_t* __restrict__ hist, int dict,
+                                                   uint8_t* __restrict__ len_out, uint64_t* __restrict__ codes,
+                                                   uint32_t* __restrict__ enc, uint32_t* __restrict__ maxlen_out) {
+  k_codebook(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, hist, dict, len_out, codes, enc, maxlen_out);
 }
+
+
+// One codebook per block: the codebooks of a batch's fields in one launch.
 
 // ------------------------------------------------------------------ chunk sizes
 // Bits of each chunk: one wave per chunk, code lengths in LDS.
-__global__ void __launch_bounds__(WAVE_T) k_chunk_bits(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+__device__ __forceinline__ void k_chunk_bits(G3 mg_bid, G3 mg_gdim, const uint16_t* __restrict__ sym, uint64_t n, int chunk,
                                                        uint64_t nch, uint32_t mask, const uint8_t* __restrict__ len,
                                                        uint32_t* __restrict__ chunk_bits) {
   __shared__ uint8_t lens[MAXDICT];
   for (uint32_t s = threadIdx.x; s <= mask; s += WAVE_T) lens[s] = len[s];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const uint64_t stride = (uint64_t)gridDim.x * WAVES;
-  const uint64_t wave = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+  const uint64_t stride = (uint64_t)mg_gdim.x * WAVES;
+  const uint64_t wave = (uint64_t)mg_bid.x * WAVES + (threadIdx.x >> 6);
   // full chunks of at most 1024 symbols: batched, prefetched loads
   uint64_t kslow = wave;
   if (chunk <= 1024) {
@@ -612,6 +624,13 @@ __global__ void __launch_bounds__(WAVE_T) k_chunk_bits(const uint16_t* __restric
     if (lane == 0) chunk_bits[k] = b;
   }
 }
+
+__global__ void __launch_bounds__(WAVE_T) k_chunk_bits_k(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+                                                       uint64_t nch, uint32_t mask, const uint8_t* __restrict__ len,
+                                                       uint32_t* __restrict__ chunk_bits) {
+  k_chunk_bits(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, sym, n, chunk, nch, mask, len, chunk_bits);
+}
+
 
 // ------------------------------------------------------------------ scans
 // Exclusive scan of n values (the words of chunk bit counts when WORDS) into
@@ -713,11 +732,11 @@ struct ScanPair {
   uint64_t* off[2];
 };
 
-__global__ void __launch_bounds__(SCAN_T) k_scan_tiles2(ScanPair p, uint64_t n) {
+__device__ __forceinline__ void k_scan_tiles2(G3 mg_bid, G3 mg_gdim, const ScanPair& p, uint64_t n) {
   __shared__ uint64_t sh[SCAN_T];
-  const int y = blockIdx.y;
+  const int y = mg_bid.y;
   const uint32_t* __restrict__ v = p.v[y];
-  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+  const uint64_t base = (uint64_t)mg_bid.x * SCAN_TILE;
   // every load from an index clamped into [0, n), issued before any is used
   uint32_t raw[SCAN_PER];
 #pragma unroll
@@ -733,9 +752,14 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_tiles2(ScanPair p, uint64_t n) 
   if (threadIdx.x == 0) p.off[y][base] = total;
 }
 
-__global__ void __launch_bounds__(1024) k_scan_top2(ScanPair p, uint64_t n) {
+__global__ void __launch_bounds__(SCAN_T) k_scan_tiles2_k(ScanPair p, uint64_t n) {
+  k_scan_tiles2(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, p, n);
+}
+
+
+__device__ __forceinline__ void k_scan_top2(G3 mg_bid, G3 mg_gdim, const ScanPair& p, uint64_t n) {
   __shared__ uint64_t sh[1024];
-  uint64_t* __restrict__ off = p.off[blockIdx.y];
+  uint64_t* __restrict__ off = p.off[mg_bid.y];
   const uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
   uint64_t carry = 0;
   for (uint64_t g = 0; g < nt; g += blockDim.x) {
@@ -749,13 +773,18 @@ __global__ void __launch_bounds__(1024) k_scan_top2(ScanPair p, uint64_t n) {
   if (threadIdx.x == 0) off[n] = carry;
 }
 
-__global__ void __launch_bounds__(SCAN_T) k_scan_apply2(ScanPair p, uint64_t n) {
+__global__ void __launch_bounds__(1024) k_scan_top2_k(ScanPair p, uint64_t n) {
+  k_scan_top2(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, p, n);
+}
+
+
+__device__ __forceinline__ void k_scan_apply2(G3 mg_bid, G3 mg_gdim, const ScanPair& p, uint64_t n) {
   __shared__ uint64_t sh[SCAN_T];
   __shared__ uint64_t tbase_sh;
-  const int y = blockIdx.y;
+  const int y = mg_bid.y;
   const uint32_t* __restrict__ v = p.v[y];
   uint64_t* __restrict__ off = p.off[y];
-  const uint64_t tile = (uint64_t)blockIdx.x * SCAN_TILE;
+  const uint64_t tile = (uint64_t)mg_bid.x * SCAN_TILE;
   if (threadIdx.x == 0) tbase_sh = off[tile];
   const uint64_t mine = tile + (uint64_t)threadIdx.x * SCAN_PER;
   uint32_t raw[SCAN_PER];
@@ -777,6 +806,11 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply2(ScanPair p, uint64_t n) 
     run += x[j];
   }
 }
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_apply2_k(ScanPair p, uint64_t n) {
+  k_scan_apply2(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, p, n);
+}
+
 
 template <bool WORDS>
 void launch_scan(const uint32_t* v, uint64_t n, uint64_t* off, hipStream_t st) {
@@ -822,7 +856,7 @@ __global__ void __launch_bounds__(1024) k_pack_codes(const uint8_t* __restrict__
 // and its codes pass through a 64-bit accumulator into the wave's LDS words
 // (word-granular atomics: only the first and last word of a lane are shared);
 // the finished chunk is copied out coalesced.
-__global__ void __launch_bounds__(ENC_T) k_encode_wave(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+__device__ __forceinline__ void k_encode_wave(G3 mg_bid, G3 mg_gdim, const uint16_t* __restrict__ sym, uint64_t n, int chunk,
                                                       uint64_t nch, uint32_t mask, const uint32_t* __restrict__ enc_g,
                                                       const uint32_t* __restrict__ maxlen,
                                                       const uint64_t* __restrict__ word_off,
@@ -838,8 +872,8 @@ __global__ void __launch_bounds__(ENC_T) k_encode_wave(const uint16_t* __restric
   uint64_t* outliers = ecodes;
   const int lane = threadIdx.x & 63;
   uint32_t* wb = words[threadIdx.x >> 6];
-  const uint64_t stride = (uint64_t)gridDim.x * (ENC_T / 64);
-  const uint64_t wave = (uint64_t)blockIdx.x * (ENC_T / 64) + (threadIdx.x >> 6);
+  const uint64_t stride = (uint64_t)mg_gdim.x * (ENC_T / 64);
+  const uint64_t wave = (uint64_t)mg_bid.x * (ENC_T / 64) + (threadIdx.x >> 6);
   // chunk k: clear its LDS words; per step of 256 symbols (first symbol i of
   // this lane, s4 its four symbols, 0xffffffff past the end) pack the codes;
   // then copy the words out
@@ -928,6 +962,18 @@ __global__ void __launch_bounds__(ENC_T) k_encode_wave(const uint16_t* __restric
   }
 }
 
+__global__ void __launch_bounds__(ENC_T) k_encode_wave_k(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+                                                      uint64_t nch, uint32_t mask, const uint32_t* __restrict__ enc_g,
+                                                      const uint32_t* __restrict__ maxlen,
+                                                      const uint64_t* __restrict__ word_off,
+                                                      uint32_t* __restrict__ payload,
+                                                      const uint64_t* __restrict__ esc_off,
+                                                      const int64_t* __restrict__ qside,
+                                                      uint64_t* __restrict__ ecodes, int R) {
+  k_encode_wave(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, sym, n, chunk, nch, mask, enc_g, maxlen, word_off, payload, esc_off, qside, ecodes, R);
+}
+
+
 __device__ inline void put_code(uint32_t* words, uint64_t b, int L, uint64_t code) {
   // code occupies chunk bits [b, b+L), MSB-first
   const uint64_t e = b + (uint64_t)L;
@@ -946,7 +992,7 @@ __device__ inline void put_code(uint32_t* words, uint64_t b, int L, uint64_t cod
 // Generic encoder (any chunk size and code length); it stands aside when the
 // wave kernel handles the call (chunk <= ENC_CHUNK and codes <= ENC_MAXLEN bits).
 template <int MAXW>
-__global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+__device__ __forceinline__ void k_encode(G3 mg_bid, G3 mg_gdim, const uint16_t* __restrict__ sym, uint64_t n, int chunk,
                                                 uint64_t nch, uint32_t mask, const uint8_t* __restrict__ len,
                                                 const uint32_t* __restrict__ maxlen,
                                                 const uint64_t* __restrict__ codes,
@@ -962,7 +1008,7 @@ __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym
   __shared__ uint32_t escan[TPB];
   const int t = threadIdx.x;
   const int per = chunk / TPB;
-  for (uint64_t k = blockIdx.x; k < nch; k += gridDim.x) {
+  for (uint64_t k = mg_bid.x; k < nch; k += mg_gdim.x) {
     const uint64_t beg = k * (uint64_t)chunk;
     const uint64_t w0 = word_off[k], nw = word_off[k + 1] - w0;
     for (uint64_t i = t; i < nw; i += TPB) words[i] = 0;
@@ -1005,6 +1051,20 @@ __global__ void __launch_bounds__(TPB) k_encode(const uint16_t* __restrict__ sym
     __syncthreads();
   }
 }
+
+template <int MAXW>
+__global__ void __launch_bounds__(TPB) k_encode_k(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
+                                                uint64_t nch, uint32_t mask, const uint8_t* __restrict__ len,
+                                                const uint32_t* __restrict__ maxlen,
+                                                const uint64_t* __restrict__ codes,
+                                                const uint64_t* __restrict__ word_off,
+                                                uint32_t* __restrict__ payload,
+                                                const uint64_t* __restrict__ esc_off,
+                                                const int64_t* __restrict__ qside,
+                                                uint64_t* __restrict__ ecodes, int R) {
+  k_encode<MAXW>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, sym, n, chunk, nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, R);
+}
+
 
 // ------------------------------------------------------------------ decode
 // Canonical decoding tables: per length L, the first code, the count and the
@@ -1525,8 +1585,7 @@ void launch_histogram_chunks(const uint16_t* sym, uint64_t n, int dict, int chun
   k1 = std::min(k1, nch);
   if (k0 >= k1) return;
   KernelTimer kt("histogram", st);
-  hipLaunchKernelGGL(k_histogram, dim3(blocks_for((k1 - k0 + WAVES - 1) / WAVES, 256)), dim3(WAVE_T), 0, st, sym,
-                     n, dict, chunk, k0, k1, (unsigned long long*)hist, chunk_esc, status);
+  MG_LAUNCH((&k_histogram), (k_histogram_k), (WAVE_T), (0), (dim3(blocks_for((k1 - k0 + WAVES - 1) / WAVES, 256))), st, sym, n, dict, chunk, k0, k1, (unsigned long long*)hist, chunk_esc, status);
   MG_HIP(hipGetLastError());
 }
 
@@ -1547,24 +1606,17 @@ void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* cod
   uint32_t *enc = nullptr, *maxlen = nullptr;
   if (enc_scratch) encode_tables(enc_scratch, dict, &enc, &maxlen);
   KernelTimer kt("codebook", st);
-  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(CB_T), 0, st, hist, dict, len, codes, enc, maxlen);
+  MG_LAUNCH((&k_codebook), (k_codebook_k), (CB_T), (0), (dim3(1)), st, hist, dict, len, codes, enc, maxlen);
   MG_HIP(hipGetLastError());
 }
 
-void launch_codebook_group(const CodebookJob* jobs, uint32_t njobs, int dict, hipStream_t st) {
-  if (!njobs) return;
-  KernelTimer kt("codebook", st);
-  hipLaunchKernelGGL(k_codebook_group, dim3(njobs), dim3(CB_T), 0, st, jobs, dict);
-  MG_HIP(hipGetLastError());
-}
 
 void launch_chunk_bits(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                        uint32_t* chunk_bits, hipStream_t st) {
   const uint64_t nch = (n + chunk - 1) / chunk;
   if (nch == 0) return;
   KernelTimer kt("chunk_bits", st);
-  hipLaunchKernelGGL(k_chunk_bits, dim3(blocks_for((nch + WAVES - 1) / WAVES, 256)), dim3(WAVE_T), 0, st, sym, n,
-                     chunk, nch, (uint32_t)(dict - 1), len, chunk_bits);
+  MG_LAUNCH((&k_chunk_bits), (k_chunk_bits_k), (WAVE_T), (0), (dim3(blocks_for((nch + WAVES - 1) / WAVES, 256))), st, sym, n, chunk, nch, (uint32_t)(dict - 1), len, chunk_bits);
   MG_HIP(hipGetLastError());
 }
 
@@ -1583,9 +1635,9 @@ void launch_scan_pair(const uint32_t* chunk_bits, const uint32_t* esc, uint64_t 
   KernelTimer kt("scan", st);
   ScanPair p{{chunk_bits, esc}, {word_off, esc_off}};
   const uint64_t nt = (nch + SCAN_TILE - 1) / SCAN_TILE;
-  if (nt) hipLaunchKernelGGL(k_scan_tiles2, dim3((unsigned)nt, 2), dim3(SCAN_T), 0, st, p, nch);
-  hipLaunchKernelGGL(k_scan_top2, dim3(1, 2), dim3(1024), 0, st, p, nch);
-  if (nt) hipLaunchKernelGGL(k_scan_apply2, dim3((unsigned)nt, 2), dim3(SCAN_T), 0, st, p, nch);
+  if (nt) MG_LAUNCH((&k_scan_tiles2), (k_scan_tiles2_k), (SCAN_T), (0), (dim3((unsigned)nt, 2)), st, p, nch);
+  MG_LAUNCH((&k_scan_top2), (k_scan_top2_k), (1024), (0), (dim3(1, 2)), st, p, nch);
+  if (nt) MG_LAUNCH((&k_scan_apply2), (k_scan_apply2_k), (SCAN_T), (0), (dim3((unsigned)nt, 2)), st, p, nch);
   MG_HIP(hipGetLastError());
 }
 
@@ -1604,14 +1656,11 @@ void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const u
   if (!packed) hipLaunchKernelGGL(k_pack_codes, dim3(1), dim3(1024), 0, st, len, codes, dict, enc, maxlen);
   const uint32_t mask = (uint32_t)(dict - 1);
   if (chunk <= ENC_CHUNK)
-    hipLaunchKernelGGL(k_encode_wave, dim3(blocks_for((nch + ENC_T / 64 - 1) / (ENC_T / 64), 512)), dim3(ENC_T), 0,
-                       st, sym, n, chunk, nch, mask, enc, maxlen, word_off, payload, esc_off, qside, ecodes, dict / 2);
+    MG_LAUNCH((&k_encode_wave), (k_encode_wave_k), (ENC_T), (0), (dim3(blocks_for((nch + ENC_T / 64 - 1) / (ENC_T / 64), 512))), st, sym, n, chunk, nch, mask, enc, maxlen, word_off, payload, esc_off, qside, ecodes, dict / 2);
   if (chunk <= 4096)
-    hipLaunchKernelGGL(k_encode<4096 * MAXLEN / 32>, dim3(blocks_for(nch, 4096)), dim3(TPB), 0, st, sym, n, chunk,
-                       nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
+    MG_LAUNCH((&k_encode<4096 * MAXLEN / 32>), (k_encode_k<4096 * MAXLEN / 32>), (TPB), (0), (dim3(blocks_for(nch, 4096))), st, sym, n, chunk, nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
   else
-    hipLaunchKernelGGL(k_encode<8192 * MAXLEN / 32>, dim3(blocks_for(nch, 4096)), dim3(TPB), 0, st, sym, n, chunk,
-                       nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
+    MG_LAUNCH((&k_encode<8192 * MAXLEN / 32>), (k_encode_k<8192 * MAXLEN / 32>), (TPB), (0), (dim3(blocks_for(nch, 4096))), st, sym, n, chunk, nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
   MG_HIP(hipGetLastError());
 }
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/mgard_hip.h"
+#include "launch.hpp"
 
 namespace mg {
 
@@ -357,15 +358,6 @@ void launch_codebook(const uint64_t* hist, int dict, uint8_t* len, uint64_t* cod
                      hipStream_t st);
 // The packed code table and longest-length slot inside an encoder scratch.
 void encode_tables(void* enc_scratch, int dict, uint32_t** enc, uint32_t** maxlen);
-// Several codebooks in one launch (one block each): jobs is a device array.
-struct CodebookJob {
-  const uint64_t* hist;
-  uint8_t* len;
-  uint64_t* codes;
-  uint32_t* enc;     // packed table of the field's encoder scratch
-  uint32_t* maxlen;
-};
-void launch_codebook_group(const CodebookJob* jobs, uint32_t njobs, int dict, hipStream_t st);
 void launch_chunk_bits(const uint16_t* sym, uint64_t n, int dict, int chunk, const uint8_t* len,
                        uint32_t* chunk_bits, hipStream_t st);
 // exclusive scan of per-chunk words (ceil(bits/32)) -> offsets (n+1 entries, last = total)

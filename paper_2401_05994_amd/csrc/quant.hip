@@ -29,14 +29,14 @@ __device__ inline uint64_t abs_bits(double x) {
 
 // max of |x| as ordered bit patterns (NaN patterns sort above infinity)
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_maxabs(const T* __restrict__ d, uint64_t n, uint64_t* out) {
+__device__ __forceinline__ void k_maxabs(G3 mg_bid, G3 mg_gdim, const T* __restrict__ d, uint64_t n, uint64_t* out) {
   // Groups of eight loads per lane in two buffers: the next group is in
   // flight while this one is reduced.  Indices past the end read the last
   // element again (a max is unchanged by repeats), so no load is under a
   // branch and none waits for the group after it.
   uint64_t m = 0;
   if (n == 0) return;
-  const uint64_t step = (uint64_t)gridDim.x * TPB;
+  const uint64_t step = (uint64_t)mg_gdim.x * TPB;
   auto load = [&](uint64_t base, T (&v)[8]) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) v[u] = d[min(base + u * step, n - 1)];
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(TPB) k_maxabs(const T* __restrict__ d, uint64_
     }
   };
   T va[8], vb[8];
-  uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x;
+  uint64_t i = (uint64_t)mg_bid.x * TPB + threadIdx.x;
   load(i, va);
   for (; i < n; i += 16 * step) {
     load(i + 8 * step, vb);
@@ -70,6 +70,12 @@ __global__ void __launch_bounds__(TPB) k_maxabs(const T* __restrict__ d, uint64_
   if (threadIdx.x == 0) atomicMax((unsigned long long*)out, (unsigned long long)red[0]);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_maxabs_k(const T* __restrict__ d, uint64_t n, uint64_t* out) {
+  k_maxabs<T>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, d, n, out);
+}
+
+
 // Largest max|u| / b accepted: coefficients stay within a small multiple of
 // max|u| (interpolation is convex and the L2 projections are stable in the
 // maximum norm), so |c / b| stays far below 2^63 and the integer conversion of
@@ -79,12 +85,12 @@ constexpr double kMaxScale = 562949953421312.0;  // 2^49
 // scalars: [0] tau_abs, [1] maxabs, [2] non-finite flag, [3] tau_eff,
 // [6] tolerance outside the supported range: the rounding reserve
 // rho = 4 (L+1) eps max|u| exceeds tau / 2, or max|u| / b_l reaches 2^49
-__global__ void k_bins(int f64, const uint64_t* __restrict__ maxbits, double tol, int rel, double S,
-                       int L, int alloc, BinArgs args, double* __restrict__ bins,
+__device__ __forceinline__ void k_bins(G3 mg_bid, G3 mg_gdim, int f64, const uint64_t* __restrict__ maxbits, double tol, int rel, double S,
+                       int L, int alloc, const BinArgs& args, double* __restrict__ bins,
                        double* __restrict__ scalars) {
   const double* K = args.K;
   const double* counts = args.counts;
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (threadIdx.x != 0 || mg_bid.x != 0) return;
   const uint64_t mb = *maxbits;
   double maxabs;
   int nonfinite;
@@ -123,6 +129,13 @@ __global__ void k_bins(int f64, const uint64_t* __restrict__ maxbits, double tol
   for (int l = 0; l <= L; ++l) out = out || !(maxabs < kMaxScale * bins[l]);
   scalars[6] = (!nonfinite && out) ? 1.0 : 0.0;
 }
+
+__global__ void k_bins_k(int f64, const uint64_t* __restrict__ maxbits, double tol, int rel, double S,
+                       int L, int alloc, BinArgs args, double* __restrict__ bins,
+                       double* __restrict__ scalars) {
+  k_bins(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, f64, maxbits, tol, rel, S, L, alloc, args, bins, scalars);
+}
+
 
 __device__ inline int level_of(uint64_t i, const uint64_t* __restrict__ off, int nlev) {
   int l = 0;
@@ -167,15 +180,20 @@ __global__ void __launch_bounds__(TPB) k_dequantize(const uint16_t* __restrict__
 }  // namespace
 
 namespace {
-__global__ void __launch_bounds__(TPB) k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
-  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < n; t += (uint64_t)gridDim.x * TPB) p[t] = v;
+__device__ __forceinline__ void k_fill_u64(G3 mg_bid, G3 mg_gdim, uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
+  for (uint64_t t = (uint64_t)mg_bid.x * TPB + threadIdx.x; t < n; t += (uint64_t)mg_gdim.x * TPB) p[t] = v;
 }
+
+__global__ void __launch_bounds__(TPB) k_fill_u64_k(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
+  k_fill_u64(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, p, n, v);
+}
+
 }  // namespace
 
 // A kernel rather than hipMemsetAsync, so that captured graphs hold no memset node.
 void launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st) {
   if (!n) return;
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 1024)), dim3(TPB), 0, st, p, n, v);
+  MG_LAUNCH((&k_fill_u64), (k_fill_u64_k), (TPB), (0), (dim3(grid_for(n, 1024))), st, p, n, v);
   MG_HIP(hipGetLastError());
 }
 
@@ -184,14 +202,13 @@ void launch_maxabs(const T* d, uint64_t n, uint64_t* d_bits, hipStream_t st) {
   launch_fill_u64(d_bits, 1, 0, st);
   KernelTimer kt("maxabs", st);
   // 1024 blocks (16 wavefronts per CU) read faster than 2048 or more in a sweep of the cap
-  hipLaunchKernelGGL(k_maxabs<T>, dim3(grid_for(n, 1024)), dim3(TPB), 0, st, d, n, d_bits);
+  MG_LAUNCH((&k_maxabs<T>), (k_maxabs_k<T>), (TPB), (0), (dim3(grid_for(n, 1024))), st, d, n, d_bits);
   MG_HIP(hipGetLastError());
 }
 
 void launch_bins(int f64, const uint64_t* d_maxbits, double tol, int rel, double S, int L,
                  int alloc, const BinArgs& a, double* d_bins, double* d_scalars, hipStream_t st) {
-  hipLaunchKernelGGL(k_bins, dim3(1), dim3(64), 0, st, f64, d_maxbits, tol, rel, S, L, alloc, a, d_bins,
-                     d_scalars);
+  MG_LAUNCH((&k_bins), (k_bins_k), (64), (0), (dim3(1)), st, f64, d_maxbits, tol, rel, S, L, alloc, a, d_bins, d_scalars);
   MG_HIP(hipGetLastError());
 }
 

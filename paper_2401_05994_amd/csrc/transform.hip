@@ -167,15 +167,15 @@ __device__ inline T dequantize_one(const uint16_t* __restrict__ sym, const int64
 
 // Step 1 (+ fused quantization when MODE == 1).
 template <typename T, int MODE>
-__global__ void __launch_bounds__(TPB) k_coeff(const T* __restrict__ u, T* __restrict__ cbar,
+__device__ __forceinline__ void k_coeff(G3 mg_bid, G3 mg_gdim, const T* __restrict__ u, T* __restrict__ cbar,
                                                T* __restrict__ ucoarse, T* __restrict__ cstream,
                                                uint16_t* __restrict__ sym, int64_t* __restrict__ qside,
                                                const double* __restrict__ bins, int level, int R,
-                                               LevelGeom<T> g, uint64_t nfine) {
+                                               const LevelGeom<T>& g, uint64_t nfine) {
   double inv_b = 0.0;
   if (MODE == 1) inv_b = 1.0 / bins[level];
-  for (uint64_t p = (uint64_t)blockIdx.x * TPB + threadIdx.x; p < nfine;
-       p += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t p = (uint64_t)mg_bid.x * TPB + threadIdx.x; p < nfine;
+       p += (uint64_t)mg_gdim.x * TPB) {
     Coord c = unflatten(p, g);
     const int m = new_mask(c, g);
     const T up = u[p];
@@ -197,14 +197,24 @@ __global__ void __launch_bounds__(TPB) k_coeff(const T* __restrict__ u, T* __res
   }
 }
 
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPB) k_coeff_k(const T* __restrict__ u, T* __restrict__ cbar,
+                                               T* __restrict__ ucoarse, T* __restrict__ cstream,
+                                               uint16_t* __restrict__ sym, int64_t* __restrict__ qside,
+                                               const double* __restrict__ bins, int level, int R,
+                                               LevelGeom<T> g, uint64_t nfine) {
+  k_coeff<T, MODE>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, u, cbar, ucoarse, cstream, sym, qside, bins, level, R, g, nfine);
+}
+
+
 // Step 2 along one dimension: (outer, nf, inner) -> (outer, nc, inner).
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_mass_restrict(const T* __restrict__ in, T* __restrict__ out,
+__device__ __forceinline__ void k_mass_restrict(G3 mg_bid, G3 mg_gdim, const T* __restrict__ in, T* __restrict__ out,
                                                        uint64_t outer, int nf, int nc, uint64_t inner,
-                                                       DimConsts<T> w) {
+                                                       const DimConsts<T>& w) {
   const uint64_t total = outer * (uint64_t)nc * inner;
-  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < total;
-       t += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t t = (uint64_t)mg_bid.x * TPB + threadIdx.x; t < total;
+       t += (uint64_t)mg_gdim.x * TPB) {
     const uint64_t k = t % inner;
     const uint64_t r = t / inner;
     const int j = (int)(r % (uint64_t)nc);
@@ -225,9 +235,17 @@ __global__ void __launch_bounds__(TPB) k_mass_restrict(const T* __restrict__ in,
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_mass_restrict_k(const T* __restrict__ in, T* __restrict__ out,
+                                                       uint64_t outer, int nf, int nc, uint64_t inner,
+                                                       DimConsts<T> w) {
+  k_mass_restrict<T>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, in, out, outer, nf, nc, inner, w);
+}
+
+
 // Step 3 along one dimension, in place, one thread per line.
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t outer, int n, uint64_t inner,
+__device__ __forceinline__ void k_thomas(G3 mg_bid, G3 mg_gdim, T* __restrict__ data, uint64_t outer, int n, uint64_t inner,
                                                 const T* __restrict__ ta, const T* __restrict__ tr,
                                                 const T* __restrict__ tcp) {
   // Both sweeps load G values of the line before the group's
@@ -235,8 +253,8 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
   // order as the plain loops.
   constexpr int G = 16;
   const uint64_t lines = outer * inner;
-  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < lines;
-       t += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t t = (uint64_t)mg_bid.x * TPB + threadIdx.x; t < lines;
+       t += (uint64_t)mg_gdim.x * TPB) {
     const uint64_t k = t % inner;
     const uint64_t o = t / inner;
     T* line = data + o * (uint64_t)n * inner + k;
@@ -315,6 +333,14 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_thomas_k(T* __restrict__ data, uint64_t outer, int n, uint64_t inner,
+                                                const T* __restrict__ ta, const T* __restrict__ tr,
+                                                const T* __restrict__ tcp) {
+  k_thomas<T>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, data, outer, n, inner, ta, tr, tcp);
+}
+
+
 // Thomas along the contiguous dimension: `rows` lines per block staged in LDS
 // (coalesced, every load of a lane in flight at once), one lane per line, the same
 // arithmetic as k_thomas, then written back.  Lines sit `stride` (odd)
@@ -322,7 +348,7 @@ __global__ void __launch_bounds__(TPB) k_thomas(T* __restrict__ data, uint64_t o
 constexpr int ROWS_LDS = 65536;  // bytes
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_thomas_rows(T* __restrict__ data, uint64_t nrows, int n, int rows,
+__device__ __forceinline__ void k_thomas_rows(G3 mg_bid, G3 mg_gdim, T* __restrict__ data, uint64_t nrows, int n, int rows,
                                                      int stride, const T* __restrict__ ta,
                                                      const T* __restrict__ tr, const T* __restrict__ tcp) {
   constexpr int CAP = ROWS_LDS / (int)sizeof(T);
@@ -330,7 +356,7 @@ __global__ void __launch_bounds__(TPB) k_thomas_rows(T* __restrict__ data, uint6
   // every element a lane copies is loaded before any is stored (clamped
   // indices, unconditional loads): one wait for memory per block
   constexpr int EPT = CAP / TPB;
-  const uint64_t r0 = (uint64_t)blockIdx.x * rows;
+  const uint64_t r0 = (uint64_t)mg_bid.x * rows;
   const int nr = (int)min((uint64_t)rows, nrows - r0);
   const int cnt = nr * n;
   T* g = data + r0 * (uint64_t)n;
@@ -365,6 +391,14 @@ __global__ void __launch_bounds__(TPB) k_thomas_rows(T* __restrict__ data, uint6
   for (int k = threadIdx.x; k < cnt; k += TPB) g[k] = tile[(k / n) * stride + k % n];
 }
 
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_thomas_rows_k(T* __restrict__ data, uint64_t nrows, int n, int rows,
+                                                     int stride, const T* __restrict__ ta,
+                                                     const T* __restrict__ tr, const T* __restrict__ tcp) {
+  k_thomas_rows<T>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, data, nrows, n, rows, stride, ta, tr, tcp);
+}
+
+
 // Thomas along slot s: lines of the contiguous dimension go through LDS when a
 // line fits, other dimensions use the strided kernel.
 template <typename T>
@@ -372,36 +406,50 @@ void launch_thomas_any(T* data, uint64_t outer, int n, uint64_t inner, const Dim
   const int stride = n | 1;
   if (inner == 1 && (uint64_t)stride * sizeof(T) <= (uint64_t)ROWS_LDS) {
     const int rows = (int)std::min<uint64_t>(TPB, (uint64_t)ROWS_LDS / ((uint64_t)stride * sizeof(T)));
-    hipLaunchKernelGGL(k_thomas_rows<T>, dim3((unsigned)((outer + rows - 1) / rows)), dim3(TPB), 0, st, data, outer,
-                       n, rows, stride, w.ta, w.tr, w.tcp);
+    MG_LAUNCH((&k_thomas_rows<T>), (k_thomas_rows_k<T>), (TPB), (0), (dim3((unsigned)((outer + rows - 1) / rows))), st, data, outer, n, rows, stride, w.ta, w.tr, w.tcp);
   } else {
-    hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, data, outer, n, inner, w.ta,
-                       w.tr, w.tcp);
+    MG_LAUNCH((&k_thomas<T>), (k_thomas_k<T>), (TPB), (0), (dim3(grid_for(outer * inner))), st, data, outer, n, inner, w.ta, w.tr, w.tcp);
   }
 }
 
 template <typename T, bool ADD>
-__global__ void __launch_bounds__(TPB) k_axpy(T* __restrict__ dst, const T* __restrict__ a,
+__device__ __forceinline__ void k_axpy(G3 mg_bid, G3 mg_gdim, T* __restrict__ dst, const T* __restrict__ a,
                                               const T* __restrict__ b, uint64_t n) {
-  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < n; t += (uint64_t)gridDim.x * TPB)
+  for (uint64_t t = (uint64_t)mg_bid.x * TPB + threadIdx.x; t < n; t += (uint64_t)mg_gdim.x * TPB)
     dst[t] = ADD ? a[t] + b[t] : a[t] - b[t];
 }
 
+template <typename T, bool ADD>
+__global__ void __launch_bounds__(TPB) k_axpy_k(T* __restrict__ dst, const T* __restrict__ a,
+                                              const T* __restrict__ b, uint64_t n) {
+  k_axpy<T, ADD>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, dst, a, b, n);
+}
+
+
 // coarsest grid <-> stream[0, n0)
 template <typename T, int MODE>
-__global__ void __launch_bounds__(TPB) k_coarsest_out(const T* __restrict__ src, T* __restrict__ cstream,
+__device__ __forceinline__ void k_coarsest_out(G3 mg_bid, G3 mg_gdim, const T* __restrict__ src, T* __restrict__ cstream,
                                                       uint16_t* __restrict__ sym,
                                                       int64_t* __restrict__ qside,
                                                       const double* __restrict__ bins, int R, uint64_t n) {
   double inv_b = 0.0;
   if (MODE == 1) inv_b = 1.0 / bins[0];
-  for (uint64_t t = (uint64_t)blockIdx.x * TPB + threadIdx.x; t < n; t += (uint64_t)gridDim.x * TPB) {
+  for (uint64_t t = (uint64_t)mg_bid.x * TPB + threadIdx.x; t < n; t += (uint64_t)mg_gdim.x * TPB) {
     if (MODE == 0)
       cstream[t] = src[t];
     else
       quantize_one(src[t], inv_b, R, t, sym, qside);
   }
 }
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPB) k_coarsest_out_k(const T* __restrict__ src, T* __restrict__ cstream,
+                                                      uint16_t* __restrict__ sym,
+                                                      int64_t* __restrict__ qside,
+                                                      const double* __restrict__ bins, int R, uint64_t n) {
+  k_coarsest_out<T, MODE>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, src, cstream, sym, qside, bins, R, n);
+}
+
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(TPB) k_coarsest_in(T* __restrict__ dst, const T* __restrict__ cstream,
@@ -469,8 +517,7 @@ void correction(const Hierarchy& h, int l, const T* table, const T* cbar, T* buf
     const int nf = (int)shp[s], nc = (int)h.sizes[l - 1][s];
     const uint64_t total = outer * (uint64_t)nc * inner;
     KernelTimer kt(l == h.L ? "mass_restrict_fine" : "mass_restrict_coarse", st);
-    hipLaunchKernelGGL(k_mass_restrict<T>, dim3(grid_for(total)), dim3(TPB), 0, st, src, dst, outer, nf,
-                       nc, inner, dim_consts<T>(h, l, s, table));
+    MG_LAUNCH((&k_mass_restrict<T>), (k_mass_restrict_k<T>), (TPB), (0), (dim3(grid_for(total))), st, src, dst, outer, nf, nc, inner, dim_consts<T>(h, l, s, table));
     shp[s] = nc;
     src = dst;
     dst = (dst == bufA) ? bufB : bufA;
@@ -545,8 +592,7 @@ void SideStream::join(hipStream_t st) {
 
 template <typename T>
 void launch_thomas_strided(T* data, uint64_t outer, int n, uint64_t inner, DimConsts<T> w, hipStream_t st) {
-  hipLaunchKernelGGL(k_thomas<T>, dim3(grid_for(outer * inner)), dim3(TPB), 0, st, data, outer, n, inner, w.ta, w.tr,
-                     w.tcp);
+  MG_LAUNCH((&k_thomas<T>), (k_thomas_k<T>), (TPB), (0), (dim3(grid_for(outer * inner))), st, data, outer, n, inner, w.ta, w.tr, w.tcp);
 }
 
 template <typename T>
@@ -622,27 +668,24 @@ void decompose(const Hierarchy& h, const T* table, const T* d_in, T* d_stream, c
     {
     KernelTimer kt(l == h.L ? "coeff_fine" : "coeff_coarse", st);
     if (mode == 0)
-      hipLaunchKernelGGL((k_coeff<T, 0>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cur, cbar, nxt, d_stream,
-                         nullptr, nullptr, nullptr, l, 0, g, nfine);
+      MG_LAUNCH((&k_coeff<T, 0>), (k_coeff_k<T, 0>), (TPB), (0), (dim3(grid_for(nfine))), st, cur, cbar, nxt, d_stream, nullptr, nullptr, nullptr, l, 0, g, nfine);
     else
-      hipLaunchKernelGGL((k_coeff<T, 1>), dim3(grid_for(nfine)), dim3(TPB), 0, st, cur, cbar, nxt, nullptr,
-                         q->sym, q->qside, q->bins, l, q->R, g, nfine);
+      MG_LAUNCH((&k_coeff<T, 1>), (k_coeff_k<T, 1>), (TPB), (0), (dim3(grid_for(nfine))), st, cur, cbar, nxt, nullptr, q->sym, q->qside, q->bins, l, q->R, g, nfine);
     }
     if (l == h.L) fire();
     T* z = nullptr;
     correction<T>(h, l, table, cbar, ga, gb, &z, st);
     const uint64_t nc = h.count(l - 1);
     KernelTimer kt(l == h.L ? "add_fine" : "add_coarse", st);
-    hipLaunchKernelGGL((k_axpy<T, true>), dim3(grid_for(nc)), dim3(TPB), 0, st, nxt, nxt, z, nc);
+    MG_LAUNCH((&k_axpy<T, true>), (k_axpy_k<T, true>), (TPB), (0), (dim3(grid_for(nc))), st, nxt, nxt, z, nc);
     cur = nxt;
     nxt = (nxt == pa) ? pb : pa;
   }
   const uint64_t n0 = h.count(0);
   if (mode == 0)
-    hipLaunchKernelGGL((k_coarsest_out<T, 0>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, d_stream, nullptr,
-                       nullptr, nullptr, 0, n0);
+    MG_LAUNCH((&k_coarsest_out<T, 0>), (k_coarsest_out_k<T, 0>), (TPB), (0), (dim3(grid_for(n0))), st, cur, d_stream, nullptr, nullptr, nullptr, 0, n0);
   else
-    hipLaunchKernelGGL((k_coarsest_out<T, 1>), dim3(grid_for(n0)), dim3(TPB), 0, st, cur, nullptr, q->sym,
+    MG_LAUNCH((&k_coarsest_out<T, 1>), (k_coarsest_out_k<T, 1>), (TPB), (0), (dim3(grid_for(n0))), st, cur, nullptr, q->sym,
                        q->qside, q->bins, q->R, n0);
   MG_HIP(hipGetLastError());
   fire();
@@ -729,7 +772,7 @@ void recompose(const Hierarchy& h, const T* table, const T* d_stream, const Quan
     // uc = u_{l-1} - z, in place in z
     {
       KernelTimer kt(l == h.L ? "sub_fine" : "sub_coarse", st);
-      hipLaunchKernelGGL((k_axpy<T, false>), dim3(grid_for(nc)), dim3(TPB), 0, st, z, cur, z, nc);
+      MG_LAUNCH((&k_axpy<T, false>), (k_axpy_k<T, false>), (TPB), (0), (dim3(grid_for(nc))), st, z, cur, z, nc);
     }
     T* out = level_buf(l);
     KernelTimer kt(l == h.L ? "interp_add_fine" : "interp_add_coarse", st);

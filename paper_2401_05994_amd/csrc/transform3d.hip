@@ -219,10 +219,10 @@ struct RestrictW {
 
 // MODE 1: quantize into sym/qside; MODE 0: write float coefficients to cstream.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2))) k3_coeff_r21(const T* __restrict__ u, T* __restrict__ ucoarse,
+__device__ __forceinline__ void k3_coeff_r21(G3 mg_bid, G3 mg_gdim, const T* __restrict__ u, T* __restrict__ ucoarse,
                                                    T* __restrict__ g1, uint16_t* __restrict__ sym,
                                                    int64_t* __restrict__ qside, T* __restrict__ cstream,
-                                                   const double* __restrict__ bins, int level, int R, Lv3<T> p,
+                                                   const double* __restrict__ bins, int level, int R, const Lv3<T>& p,
                                                    int seg, const T* __restrict__ d0wl, const T* __restrict__ d0wr) {
   __shared__ T U[FY * PX];
   __shared__ T BA[FY * PX];
@@ -232,10 +232,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
   __shared__ uint64_t rb[FY][2];  // stream row bases of the committed plane (dim-2 parity 0 / 1)
   __shared__ uint64_t ucb[FY];    // coarse-grid row offsets of the committed plane
   const int t = threadIdx.x;
-  const int J1 = blockIdx.y * CY, J2 = blockIdx.x * CX;
+  const int J1 = mg_bid.y * CY, J2 = mg_bid.x * CX;
   const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
   const int n0 = p.n0, n1 = p.n1, n2 = p.n2;
-  const int cb = blockIdx.z * seg;
+  const int cb = mg_bid.z * seg;
   const int ce = min(cb + seg, p.c0 - 1);
   const uint64_t plane = (uint64_t)n1 * n2;
   const int o1b = 2 * J1, o1e = min(2 * (J1 + CY), n1);  // owned fine rows
@@ -455,6 +455,16 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
   }
 }
 
+template <typename T, int MODE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2))) k3_coeff_r21_k(const T* __restrict__ u, T* __restrict__ ucoarse,
+                                                   T* __restrict__ g1, uint16_t* __restrict__ sym,
+                                                   int64_t* __restrict__ qside, T* __restrict__ cstream,
+                                                   const double* __restrict__ bins, int level, int R, Lv3<T> p,
+                                                   int seg, const T* __restrict__ d0wl, const T* __restrict__ d0wr) {
+  k3_coeff_r21<T, MODE>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, u, ucoarse, g1, sym, qside, cstream, bins, level, R, p, seg, d0wl, d0wr);
+}
+
+
 // mass + restriction along dim 0 of g1 (n0 x c1 x c2), then Thomas along dim 0 -> z (c0 x c1 x c2).
 // One lane per (j1, j2) line.  Both sweeps run in groups of SWEEP coarse
 // indices whose loads are all issued before the group's recurrence, so a
@@ -465,7 +475,7 @@ constexpr int SWEEP = 16;
 // The weights come as separate restrict pointers: the compiler then knows the
 // stores to z leave them alone and reads them with scalar loads.
 template <typename T>
-__global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T* __restrict__ z, int n0, int c0,
+__device__ __forceinline__ void k3_r0_thomas0(G3 mg_bid, G3 mg_gdim, const T* __restrict__ g1, T* __restrict__ z, int n0, int c0,
                                                     uint64_t lines, const T* __restrict__ w_ma,
                                                     const T* __restrict__ w_mb, const T* __restrict__ w_mc,
                                                     const T* __restrict__ w_rl, const T* __restrict__ w_rr,
@@ -474,7 +484,7 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
   struct {
     const T *ma, *mb, *mc, *rl, *rr, *ta, *tr, *tcp;
   } w{w_ma, w_mb, w_mc, w_rl, w_rr, w_ta, w_tr, w_tcp};
-  const uint64_t t = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  const uint64_t t = (uint64_t)mg_bid.x * NT + threadIdx.x;
   if (t >= lines) return;
   const T* g = g1 + t;
   T* zz = z + t;
@@ -598,6 +608,17 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(NT) k3_r0_thomas0_k(const T* __restrict__ g1, T* __restrict__ z, int n0, int c0,
+                                                    uint64_t lines, const T* __restrict__ w_ma,
+                                                    const T* __restrict__ w_mb, const T* __restrict__ w_mc,
+                                                    const T* __restrict__ w_rl, const T* __restrict__ w_rr,
+                                                    const T* __restrict__ w_ta, const T* __restrict__ w_tr,
+                                                    const T* __restrict__ w_tcp) {
+  k3_r0_thomas0<T>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, g1, z, n0, c0, lines, w_ma, w_mb, w_mc, w_rl, w_rr, w_ta, w_tr, w_tcp);
+}
+
+
 // Thomas along the contiguous dimension on `rows` rows per block, then out = a +/- z.
 // The weights are restrict pointers (scalar loads); the sweeps are unrolled
 // so that their LDS reads and weight loads are issued ahead of the recurrence.
@@ -606,13 +627,13 @@ __global__ void __launch_bounds__(NT) k3_r0_thomas0(const T* __restrict__ g1, T*
 // once per phase; LDSB bytes of LDS per block (32 KB lets five blocks share a
 // CU, whose memory phases then overlap the serial solves of the others).
 template <typename T, bool ADD, int LDSB>
-__global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T* out, uint64_t nrows, int n, int rows,
+__device__ __forceinline__ void k3_thomas2_axpy(G3 mg_bid, G3 mg_gdim, const T* z, const T* a, T* out, uint64_t nrows, int n, int rows,
                                                       const T* __restrict__ ta, const T* __restrict__ tr,
                                                       const T* __restrict__ tcp) {
   constexpr int CAP = LDSB / (int)sizeof(T);
   constexpr int EPT = CAP / NT;
   __shared__ T tile[CAP];
-  const uint64_t r0 = (uint64_t)blockIdx.x * rows;
+  const uint64_t r0 = (uint64_t)mg_bid.x * rows;
   const int nr = (int)min((uint64_t)rows, nrows - r0);
   const uint64_t base = r0 * (uint64_t)n;
   const int cnt = nr * n;
@@ -661,6 +682,14 @@ __global__ void __launch_bounds__(NT) k3_thomas2_axpy(const T* z, const T* a, T*
   }
 }
 
+template <typename T, bool ADD, int LDSB>
+__global__ void __launch_bounds__(NT) k3_thomas2_axpy_k(const T* z, const T* a, T* out, uint64_t nrows, int n, int rows,
+                                                      const T* __restrict__ ta, const T* __restrict__ tr,
+                                                      const T* __restrict__ tcp) {
+  k3_thomas2_axpy<T, ADD, LDSB>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, z, a, out, nrows, n, rows, ta, tr, tcp);
+}
+
+
 // Launch of k3_thomas2_axpy over the c0 * c1 rows of length c2: 32 KB of LDS
 // per block when a row fits, else 64 KB.
 template <typename T, bool ADD>
@@ -668,12 +697,10 @@ void launch_thomas2_axpy(const T* z, const T* a, T* out, uint64_t nrows, int n, 
                          const T* tcp, hipStream_t st) {
   if ((uint64_t)n * sizeof(T) <= (uint64_t)AXPY_LDS / 2) {
     const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / 2 / sizeof(T) / n)));
-    hipLaunchKernelGGL((k3_thomas2_axpy<T, ADD, AXPY_LDS / 2>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT),
-                       0, st, z, a, out, nrows, n, rows, ta, tr, tcp);
+    MG_LAUNCH((&k3_thomas2_axpy<T, ADD, AXPY_LDS / 2>), (k3_thomas2_axpy_k<T, ADD, AXPY_LDS / 2>), (NT), (0), (dim3((unsigned)((nrows + rows - 1) / rows))), st, z, a, out, nrows, n, rows, ta, tr, tcp);
   } else {
     const int rows = std::max(1, std::min(64, (int)(AXPY_LDS / sizeof(T) / n)));
-    hipLaunchKernelGGL((k3_thomas2_axpy<T, ADD, AXPY_LDS>), dim3((unsigned)((nrows + rows - 1) / rows)), dim3(NT), 0,
-                       st, z, a, out, nrows, n, rows, ta, tr, tcp);
+    MG_LAUNCH((&k3_thomas2_axpy<T, ADD, AXPY_LDS>), (k3_thomas2_axpy_k<T, ADD, AXPY_LDS>), (NT), (0), (dim3((unsigned)((nrows + rows - 1) / rows))), st, z, a, out, nrows, n, rows, ta, tr, tcp);
   }
 }
 
@@ -1168,10 +1195,10 @@ __device__ inline uint64_t tail_pos(const uint64_t (*subs)[4], int f0, int n0, i
 // coarsest grid; u is the fine grid of level lt.  MODE 1: symbols; MODE 0:
 // float coefficients in cstream.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(TAIL_T) k3_tail_decompose(const T* __restrict__ u, uint16_t* __restrict__ sym,
+__device__ __forceinline__ void k3_tail_decompose(G3 mg_bid, G3 mg_gdim, const T* __restrict__ u, uint16_t* __restrict__ sym,
                                                            int64_t* __restrict__ qside, T* __restrict__ cstream,
                                                            const double* __restrict__ bins, int R, int lt,
-                                                           TailLevels<T> a) {
+                                                           const TailLevels<T>& a) {
   __shared__ T A[TAIL_F], B[TAIL_C], C[TAIL_F], G[TAIL_G2];
   __shared__ T WS[TAIL_LMAX][3][10][TAIL_N];
   __shared__ uint64_t SUBS[TAIL_LMAX][8][4];
@@ -1243,6 +1270,15 @@ __global__ void __launch_bounds__(TAIL_T) k3_tail_decompose(const T* __restrict_
       cstream[e] = U[e];
   }
 }
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TAIL_T) k3_tail_decompose_k(const T* __restrict__ u, uint16_t* __restrict__ sym,
+                                                           int64_t* __restrict__ qside, T* __restrict__ cstream,
+                                                           const double* __restrict__ bins, int R, int lt,
+                                                           TailLevels<T> a) {
+  k3_tail_decompose<T, MODE>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, u, sym, qside, cstream, bins, R, lt, a);
+}
+
 
 // Recomposition of levels lt - nl + 1 .. lt (a.lv[k] = level lt - nl + 1 + k)
 // from the coarsest grid in the stream; writes the fine grid of level lt to out.
@@ -1397,18 +1433,16 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
     const int seg = std::max(1, tune_get(TUNE_COEFF_SEG, sizeof(T) == 8, p.n0, p.n1, p.n2, guess));
     dim3 grid((p.c2 + CX - 1) / CX, (p.c1 + CY - 1) / CY, (p.c0 - 1 + seg - 1) / seg);
     if (q)
-      hipLaunchKernelGGL((k3_coeff_r21<T, 1>), grid, dim3(NT), 0, st, u, ucoarse, g1, q->sym, q->qside,
+      MG_LAUNCH((&k3_coeff_r21<T, 1>), (k3_coeff_r21_k<T, 1>), (NT), (sizeof(T) == 4 ? 5 : 2), (grid), st, u, ucoarse, g1, q->sym, q->qside,
                          (T*)nullptr, q->bins, l, q->R, p, seg, p.d0.wl, p.d0.wr);
     else
-      hipLaunchKernelGGL((k3_coeff_r21<T, 0>), grid, dim3(NT), 0, st, u, ucoarse, g1, (uint16_t*)nullptr,
-                         (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, seg, p.d0.wl, p.d0.wr);
+      MG_LAUNCH((&k3_coeff_r21<T, 0>), (k3_coeff_r21_k<T, 0>), (NT), (sizeof(T) == 4 ? 5 : 2), (grid), st, u, ucoarse, g1, (uint16_t*)nullptr, (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, seg, p.d0.wl, p.d0.wr);
   }
   if (coeff_written) (*coeff_written)();
   const uint64_t lines = (uint64_t)p.c1 * p.c2;
   {
     KernelTimer kt(fine ? "r0_thomas0_fine" : "r0_thomas0_coarse", st);
-    hipLaunchKernelGGL(k3_r0_thomas0<T>, dim3(blocks1(lines)), dim3(NT), 0, st, g1, z, p.n0, p.c0, lines, p.d0.ma,
-                       p.d0.mb, p.d0.mc, p.d0.rl, p.d0.rr, p.d0.ta, p.d0.tr, p.d0.tcp);
+    MG_LAUNCH((&k3_r0_thomas0<T>), (k3_r0_thomas0_k<T>), (NT), (0), (dim3(blocks1(lines))), st, g1, z, p.n0, p.c0, lines, p.d0.ma, p.d0.mb, p.d0.mc, p.d0.rl, p.d0.rr, p.d0.ta, p.d0.tr, p.d0.tcp);
   }
   {
     KernelTimer kt(fine ? "thomas1_fine" : "thomas1_coarse", st);
@@ -1444,8 +1478,7 @@ void fused3d_recompose_correction(const Hierarchy& h, int l, const T* table, T* 
   const uint64_t lines = (uint64_t)p.c1 * p.c2;
   {
     KernelTimer kt(fine ? "rec_r0_thomas0_fine" : "rec_r0_thomas0_coarse", st);
-    hipLaunchKernelGGL(k3_r0_thomas0<T>, dim3(blocks1(lines)), dim3(NT), 0, st, g1, z, p.n0, p.c0, lines, p.d0.ma,
-                       p.d0.mb, p.d0.mc, p.d0.rl, p.d0.rr, p.d0.ta, p.d0.tr, p.d0.tcp);
+    MG_LAUNCH((&k3_r0_thomas0<T>), (k3_r0_thomas0_k<T>), (NT), (0), (dim3(blocks1(lines))), st, g1, z, p.n0, p.c0, lines, p.d0.ma, p.d0.mb, p.d0.mc, p.d0.rl, p.d0.rr, p.d0.ta, p.d0.tr, p.d0.tcp);
   }
   {
     KernelTimer kt(fine ? "rec_thomas1_fine" : "rec_thomas1_coarse", st);
@@ -1508,11 +1541,10 @@ void fused3d_tail_decompose(const Hierarchy& h, int lt, const T* table, const T*
   for (int k = 0; k < lt; ++k) a.lv[k] = lv3<T>(h, lt - k, table);
   KernelTimer kt("tail_decompose", st);
   if (q)
-    hipLaunchKernelGGL((k3_tail_decompose<T, 1>), dim3(1), dim3(TAIL_T), 0, st, u, q->sym, q->qside, (T*)nullptr,
+    MG_LAUNCH((&k3_tail_decompose<T, 1>), (k3_tail_decompose_k<T, 1>), (TAIL_T), (0), (dim3(1)), st, u, q->sym, q->qside, (T*)nullptr,
                        q->bins, q->R, lt, a);
   else
-    hipLaunchKernelGGL((k3_tail_decompose<T, 0>), dim3(1), dim3(TAIL_T), 0, st, u, (uint16_t*)nullptr,
-                       (int64_t*)nullptr, cstream, (const double*)nullptr, 0, lt, a);
+    MG_LAUNCH((&k3_tail_decompose<T, 0>), (k3_tail_decompose_k<T, 0>), (TAIL_T), (0), (dim3(1)), st, u, (uint16_t*)nullptr, (int64_t*)nullptr, cstream, (const double*)nullptr, 0, lt, a);
   MG_HIP(hipGetLastError());
 }
 
