@@ -77,9 +77,10 @@ def algorithmic_bytes(kernel: str, n: int, dtype_bytes: int, levels_sizes):
     Nc = nc ** 3
     s = dtype_bytes
     if kernel == "coeff_r21_fine":
-        # read u once; write the new nodes' 2-byte symbols, the coarse copy and the
-        # plane restricted along dims 2 and 1 (nf x nc x nc)
-        return N * s + 2 * (N - Nc) + Nc * s + nf * nc * nc * s
+        # the level's own work: read u once; write the new nodes' 2-byte symbols and
+        # the coarse copy (the intermediate it also writes is this design's, and is
+        # reported separately)
+        return N * s + 2 * (N - Nc) + Nc * s
     if kernel == "interp_add3_fine":
         # read the new nodes' symbols and the coarse grid; write u
         return 2 * (N - Nc) + Nc * s + N * s
@@ -177,6 +178,116 @@ def bench_chunked(m, torch, n: int = 1025, slab: int = 129, tol: float = 1e-3, r
             "ratio": round(in_bytes / nb, 4), "linf_over_tau": round(err / tau, 4), "includes_pcie": True}
 
 
+def timed_round_trip(m, torch, u, tol, steps, coords=None, lossless=False, kernels=False):
+    """Compress + decompress of a device-resident field: rates, ratio, L-inf / tau and, with
+    kernels=True, the decomposition + quantization kernel time per compress (HIP events)."""
+    dt = m.F32 if u.dtype == torch.float32 else m.F64
+    out = torch.empty(m.mgard_compress_bound(tuple(u.shape), dt, coords), dtype=torch.uint8, device=u.device)
+    rec = torch.empty_like(u)
+    kw = {} if coords is None else {"coords": coords}
+    for _ in range(2):
+        buf, nb, info = m.mgard_compress(u, tol, out=out, lossless=lossless, **kw)
+        m.mgard_decompress(buf, nb, out=rec)
+    torch.cuda.synchronize()
+    tc = td = 0.0
+    for _ in range(steps):
+        a = time.perf_counter()
+        buf, nb, info = m.mgard_compress(u, tol, out=out, lossless=lossless, **kw)
+        b = time.perf_counter()
+        m.mgard_decompress(buf, nb, out=rec)
+        torch.cuda.synchronize()
+        tc += b - a
+        td += time.perf_counter() - b
+    in_bytes = u.numel() * u.element_size()
+    err = float((rec.double() - u.double()).abs().max())
+    tau = info["tau_abs"]
+    assert err <= tau, f"L-infinity error {err} exceeds {tau}"
+    r = {"ms_round_trip": round((tc + td) / steps * 1e3, 3), "GBps": round(in_bytes * steps / (tc + td) / 1e9, 3),
+         "compress_GBps": round(in_bytes * steps / tc / 1e9, 3),
+         "decompress_GBps": round(in_bytes * steps / td / 1e9, 3), "ratio": round(in_bytes / nb, 4),
+         "linf_over_tau": round(err / tau, 4)}
+    if kernels:
+        m.mgard_timing(True)
+        for _ in range(2):
+            m.mgard_compress(u, tol, out=out, **kw)
+        torch.cuda.synchronize()
+        rep = m.mgard_timing_report()
+        m.mgard_timing(False)
+        r["decompose_quantize_ms"] = round(sum(v[1] for k, v in rep.items() if k.startswith(
+            ("coeff", "mass_restrict", "thomas", "add_", "maxabs", "r0_thomas0", "tail_decompose"))) / 2, 4)
+    return r
+
+
+def bench_workloads(m, torch, u513, steps=5):
+    """The other workloads of the benchmark configuration: the 513^3 field at rel tol 1e-2 and
+    1e-4, and the 500^3 float64 field on the geometric grid (ratio 1.01 per dimension, spectral
+    k^-3 plus a tanh front, seed 3) at rel tol 1e-4, each timed as a round trip."""
+    import fieldgen
+
+    out = {}
+    for tol in (1e-2, 1e-4):
+        out[f"513^3 float32 k^-5/3, rel Linf {tol:g}"] = timed_round_trip(m, torch, u513, tol, steps)
+        print(f"[bench] 513^3 tol {tol:g} done", file=sys.stderr, flush=True)
+    print("[bench] generating 500^3 float64 geometric-grid field", file=sys.stderr, flush=True)
+    u, coords = fieldgen.front3d(500, 3, 1.01, device="cuda")
+    u = u.to(torch.float64).contiguous()
+    m.mgard_autotune(u, coords)
+    r = timed_round_trip(m, torch, u, 1e-4, steps, coords=coords, kernels=True)
+    N = u.numel()
+    sizes = [500]
+    while sizes[-1] > 3:
+        sizes.append(sizes[-1] // 2 + 1)
+    # read u once, write 2-byte symbols, the coarse grids' round trips
+    alg = N * 8 + 2 * N + 2 * 8 * sum(x ** 3 for x in sizes[1:])
+    r["decompose_quantize_alg_GBps"] = round(alg / (r["decompose_quantize_ms"] * 1e-3) / 1e9, 1)
+    r["decompose_quantize_frac"] = round(r["decompose_quantize_alg_GBps"] / HBM_PEAK_GBS, 4)
+    out["500^3 float64 geometric grid, k^-3 + tanh front, rel Linf 1e-4"] = r
+    print("[bench] 500^3 float64 done", file=sys.stderr, flush=True)
+    del u
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_refactor(m, torch, u, tol=1e-3, reps=3):
+    """Refactoring of the 513^3 field into 32 bitplanes per level, the retrieval plan for rel
+    L-inf tol, reconstruction from the planned segments; fetched bytes raw and after the
+    second lossless stage."""
+    buf, nb = m.mgard_refactor(u, 32)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        m.mgard_refactor(u, 32, out=buf)
+    torch.cuda.synchronize()
+    t_ref = (time.perf_counter() - a) / reps
+    head = buf[:1 << 16].cpu().numpy().tobytes()
+    mb, L, B, tot = m.mgard_refactor_inspect(head)
+    head = head[:mb]
+    want, est = m.mgard_refactor_request(head, tol)
+    rec = m.mgard_reconstruct(buf, nb, want)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        m.mgard_reconstruct(buf, nb, want, out=rec)
+    torch.cuda.synchronize()
+    t_rec = (time.perf_counter() - a) / reps
+    err = float((rec.double() - u.double()).abs().max())
+    tau = tol * float(u.abs().max())
+    assert err <= tau, f"refactoring: L-infinity error {err} exceeds {tau}"
+    ranges = m.mgard_refactor_ranges(head, None, want)
+    fetched = sum(n for _, n in ranges)
+    coded = 0
+    for off, n in ranges:
+        _, cb = m.mgard_lossless_encode(buf[off:off + n], n)
+        coded += cb
+    in_bytes = u.numel() * 4
+    print(f"[bench] refactor: {t_ref * 1e3:.1f} ms, reconstruct {t_rec * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"workload": f"513^3 float32 k^-5/3 (seed 2), 32 bitplanes per level, request rel Linf {tol:g}",
+            "refactored_bytes": nb, "refactor_ms": round(t_ref * 1e3, 3), "refactor_GBps": round(in_bytes / t_ref / 1e9, 3),
+            "planes": want, "fetched_bytes": fetched, "fetched_bytes_lossless": coded,
+            "reconstruct_ms": round(t_rec * 1e3, 3), "reconstruct_GBps": round(in_bytes / t_rec / 1e9, 3),
+            "linf_over_tau": round(err / tau, 4), "estimate_over_tau": round(est / tau, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +303,8 @@ def main():
     ap.add_argument("--no-chunked", action="store_true", help="skip the out-of-core (host-resident) measurement")
     ap.add_argument("--only-batch", action="store_true", help="run only the 256-field batch measurement")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the other tolerances and the float64 field")
+    ap.add_argument("--no-refactor", action="store_true", help="skip the refactoring measurement")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB three times (counter calibration)")
     args = ap.parse_args()
@@ -283,6 +396,7 @@ def main():
     launches, total_ms = rep[roof_kernel]
     avg_ms = total_ms / launches
     alg = algorithmic_bytes(roof_kernel, n, 4, sizes)
+    inter = sizes[-1] * sizes[-2] * sizes[-2] * 4  # the plane restricted along dims 2 and 1
     achieved = alg / (avg_ms * 1e-3) / 1e9
     decomp_ms = sum(v[1] for k, v in rep.items()
                     if k.startswith(("coeff", "mass_restrict", "thomas", "add_", "maxabs", "r0_thomas0")) and "sub" not in k) / kt_steps
@@ -311,7 +425,9 @@ def main():
         "linf_over_tau": round(err / tau, 4),
         "roofline": {"bound": "hbm", "kernel": roof_kernel, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(n, args.tol), "avg_ms": round(avg_ms, 4), "alg_bytes": alg},
+                     "traffic": measured_traffic(n, args.tol), "avg_ms": round(avg_ms, 4), "alg_bytes": alg,
+                     "intermediate_bytes": inter,
+                     "frac_with_intermediate": round((alg + inter) / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "dominant_kernel": {"name": dom, "ms_per_step": round(rep[dom][1] / kt_steps, 4)},
         "decompose_quantize": {"ms": round(decomp_ms, 4),
                                "alg_GBps": round(alg_dq / (decomp_ms * 1e-3) / 1e9, 1),
@@ -339,6 +455,17 @@ def main():
         print(f"[bench] learned: ratio {in_bytes / lnb:.3f} vs plain {in_bytes / nb:.3f}", file=sys.stderr,
               flush=True)
 
+    # the lossless stage on the same stream (outside the timed region)
+    lbuf, lnb, _ = m.mgard_compress(u, args.tol, chunk=args.chunk, lossless=True)
+    result["lossless_stage"] = {"ratio_without": round(in_bytes / nb, 4), "ratio_with": round(in_bytes / lnb, 4)}
+    del lbuf
+
+    if not args.no_workloads:
+        result["workloads"] = bench_workloads(m, torch, u)
+
+    if not args.no_refactor:
+        result["refactor"] = bench_refactor(m, torch, u)
+
     if not args.no_batch:
         result["batched"] = bench_batch(m, torch)
 
@@ -358,10 +485,29 @@ def main():
             cb = codec.compress(cu, args.tol)
             codec.decompress(cb)
             dt = time.perf_counter() - a
+        # the same sample with the host's BLAS / FFT thread pools unrestricted: the oracle's
+        # numpy steps may then use several threads, its pure-Python Huffman one
+        a = time.perf_counter()
+        cb = codec.compress(cu, args.tol)
+        codec.decompress(cb)
+        dt_all = time.perf_counter() - a
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         result["cpu_baseline"] = {
             "value": round(cu.nbytes / dt / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{cn}^3 float32 field of the same generator and tolerance, compress+decompress "
                       f"round trip ({dt:.1f} s, numpy + pure-Python Huffman, one thread)",
+            "cpu_model": model, "host_cpus": ncpu,
+            "all_threads": {"value": round(cu.nbytes / dt_all / 1e9, 6), "threads_available": ncpu,
+                            "seconds": round(dt_all, 2)},
         }
     print(json.dumps(result))
 
