@@ -175,7 +175,9 @@ mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out,
  * launches are recorded in order, and launches of the same kernel by many
  * fields run as one launch whose blocks find their field's arguments, grid
  * and block index in a device table (the auto-tuning and adaptive
- * scheduling layer of Sec. 2.2).  Nothing in the graph allocates, copies
+ * scheduling layer of Sec. 2.2).  Fields whose decompositions take different
+ * kernels (3D fused, generic, one-block small levels; per precision) form
+ * separate chains on parallel branches of the graph.  Nothing in the graph allocates, copies
  * from host memory, sets memory or synchronises with the host.  Inputs and output are bound at creation: each launch compresses
  * the current contents of the same input buffers.  MGARD_ERR_CAPACITY when
  * out_capacity < mgard_batch_bound().

@@ -1396,57 +1396,91 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
       }
     }
 
-    // Grouping.  Each field's records fall in three phases: the stages before
-    // the decomposition, the decomposition (whose length depends on the
-    // shape), the stages after it.  Every record gets a slot: its index in
-    // the first and third phases (those after the longest first phase), and
-    // in the decomposition its index counted back from the phase's end, so
-    // that every field finishes its decomposition in the same slot.  The
-    // records of one slot and body form one grouped launch; slots run in
-    // order, so each field's records keep their order, and fields share no
-    // memory.
+    // Grouping.  Fields are split into classes by their first decomposition
+    // body (the fused 3D path, the generic path, the one-block small levels,
+    // per precision); each class becomes its own chain of grouped launches,
+    // and the chains run on parallel branches of the graph, so the
+    // latency-bound line solves of one class overlap the bandwidth-bound
+    // kernels of another.  Within a class, each field's records fall in three
+    // phases: the stages before the decomposition, the decomposition (whose
+    // length depends on the shape), the stages after it.  Every record gets a
+    // slot: its index in the first and third phases (those after the longest
+    // first phase), and in the decomposition its index counted back from the
+    // phase's end, so that every field finishes its decomposition in the same
+    // slot.  The records of one slot and body form one grouped launch; slots
+    // run in order, so each field's records keep their order, and fields share
+    // no memory.
     struct Group {
       const GroupOps* ops;
       std::vector<const LaunchRecord*> members;
     };
-    std::vector<size_t> len[3];
-    size_t maxlen[3] = {0, 0, 0};
     for (uint32_t i = 0; i < nfields; ++i) {
-      size_t c[3] = {0, 0, 0};
       int last = 0;
       for (const LaunchRecord& r : recs[i].recs) {
         if (r.phase < last || r.phase > 2) fail(MGARD_ERR_ARG, "recorded phases out of order");
         last = r.phase;
-        ++c[r.phase];
-      }
-      for (int ph = 0; ph < 3; ++ph) {
-        len[ph].push_back(c[ph]);
-        maxlen[ph] = std::max(maxlen[ph], c[ph]);
       }
     }
-    const size_t nslots = maxlen[0] + maxlen[1] + maxlen[2];
-    std::vector<std::vector<Group>> slots(nslots);
+    std::vector<const GroupOps*> class_key;
+    std::vector<std::vector<uint32_t>> class_fields;
     for (uint32_t i = 0; i < nfields; ++i) {
-      size_t k[3] = {0, 0, 0};
-      for (const LaunchRecord& r : recs[i].recs) {
-        const int ph = r.phase;
-        size_t slot = k[ph]++;
-        if (ph == 1) slot += maxlen[0] + (maxlen[1] - len[1][i]);
-        if (ph == 2) slot += maxlen[0] + maxlen[1];
-        std::vector<Group>& gs = slots[slot];
-        Group* g = nullptr;
-        for (Group& x : gs)
-          if (x.ops == r.ops) g = &x;
-        if (!g) {
-          gs.push_back(Group{r.ops, {}});
-          g = &gs.back();
+      const GroupOps* key = nullptr;
+      for (const LaunchRecord& r : recs[i].recs)
+        if (r.phase == 1) {
+          key = r.ops;
+          break;
         }
-        g->members.push_back(&r);
+      size_t c = 0;
+      while (c < class_key.size() && class_key[c] != key) ++c;
+      if (c == class_key.size()) {
+        class_key.push_back(key);
+        class_fields.emplace_back();
       }
+      class_fields[c].push_back(i);
     }
+    auto group_class = [&](const std::vector<uint32_t>& members) {
+      std::vector<size_t> len[3];
+      size_t maxlen[3] = {0, 0, 0};
+      for (uint32_t i : members) {
+        size_t c[3] = {0, 0, 0};
+        for (const LaunchRecord& r : recs[i].recs) ++c[r.phase];
+        for (int ph = 0; ph < 3; ++ph) {
+          len[ph].push_back(c[ph]);
+          maxlen[ph] = std::max(maxlen[ph], c[ph]);
+        }
+      }
+      const size_t nslots = maxlen[0] + maxlen[1] + maxlen[2];
+      std::vector<std::vector<Group>> slots(nslots);
+      for (size_t m = 0; m < members.size(); ++m) {
+        size_t k[3] = {0, 0, 0};
+        for (const LaunchRecord& r : recs[members[m]].recs) {
+          const int ph = r.phase;
+          size_t slot = k[ph]++;
+          if (ph == 1) slot += maxlen[0] + (maxlen[1] - len[1][m]);
+          if (ph == 2) slot += maxlen[0] + maxlen[1];
+          std::vector<Group>& gs = slots[slot];
+          Group* g = nullptr;
+          for (Group& x : gs)
+            if (x.ops == r.ops) g = &x;
+          if (!g) {
+            gs.push_back(Group{r.ops, {}});
+            g = &gs.back();
+          }
+          g->members.push_back(&r);
+        }
+      }
+      std::vector<Group> out;
+      for (auto& gs : slots)
+        for (auto& g : gs) out.push_back(std::move(g));
+      return out;
+    };
     std::vector<Group> groups;
-    for (auto& gs : slots)
-      for (auto& g : gs) groups.push_back(std::move(g));
+    std::vector<size_t> class_begin;  // groups of class c: [class_begin[c], class_begin[c + 1])
+    for (const auto& members : class_fields) {
+      class_begin.push_back(groups.size());
+      for (Group& g : group_class(members)) groups.push_back(std::move(g));
+    }
+    class_begin.push_back(groups.size());
 
     // job tables: per group, (first block, grid, arguments) of every member
     std::vector<uint64_t> toff(groups.size());
@@ -1475,35 +1509,52 @@ mgard_status mgard_batch_create(uint32_t nfields, const mgard_field* fields, dou
     }
     MG_HIP(hipMemcpy(B->tables, htab.data(), htab.size(), hipMemcpyHostToDevice));
 
-    // one graph of the grouped launches, in order, on one stream
-    hipStream_t cs = nullptr;
-    MG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    // one graph: class 0's chain on the capturing stream, every other class's
+    // chain on a stream of its own forked from it and joined back at the end
+    const size_t ncls = class_fields.size();
+    std::vector<hipStream_t> cs(ncls, nullptr);
+    std::vector<hipEvent_t> ev(ncls, nullptr);
+    struct Release {
+      std::vector<hipStream_t>& s;
+      std::vector<hipEvent_t>& e;
+      ~Release() {
+        for (hipStream_t x : s)
+          if (x) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : e)
+          if (x) (void)hipEventDestroy(x);
+      }
+    } release{cs, ev};
+    for (size_t c = 0; c < ncls; ++c) {
+      MG_HIP(hipStreamCreateWithFlags(&cs[c], hipStreamNonBlocking));
+      MG_HIP(hipEventCreateWithFlags(&ev[c], hipEventDisableTiming));
+    }
+    MG_HIP(hipStreamBeginCapture(cs[0], hipStreamCaptureModeThreadLocal));
     try {
-      MG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      try {
-        uint32_t n = 0;
-        for (size_t k = 0; k < groups.size(); ++k) {
+      MG_HIP(hipEventRecord(ev[0], cs[0]));
+      for (size_t c = 1; c < ncls; ++c) MG_HIP(hipStreamWaitEvent(cs[c], ev[0], 0));
+      uint32_t n = 0;
+      for (size_t c = 0; c < ncls; ++c)
+        for (size_t k = class_begin[c]; k < class_begin[c + 1]; ++k) {
           if (!tblocks[k]) continue;
           groups[k].ops->launch(static_cast<char*>(B->tables) + toff[k], (uint32_t)groups[k].members.size(),
-                                tblocks[k], cs);
+                                tblocks[k], cs[c]);
           ++n;
         }
-        MG_HIP(hipGetLastError());
-        MG_HIP(hipStreamEndCapture(cs, &B->graph));
-        B->launches = n;
-      } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(cs, &g);
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipGetLastError();
-        throw;
+      for (size_t c = 1; c < ncls; ++c) {
+        MG_HIP(hipEventRecord(ev[c], cs[c]));
+        MG_HIP(hipStreamWaitEvent(cs[0], ev[c], 0));
       }
-      MG_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+      MG_HIP(hipGetLastError());
+      MG_HIP(hipStreamEndCapture(cs[0], &B->graph));
+      B->launches = n;
     } catch (...) {
-      (void)hipStreamDestroy(cs);
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(cs[0], &g);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
       throw;
     }
-    (void)hipStreamDestroy(cs);
+    MG_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     *plan = B.release();
   });
 }

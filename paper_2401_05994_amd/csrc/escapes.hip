@@ -223,10 +223,11 @@ void launch_escape_pack(const uint16_t* sym, uint64_t n, int chunk, const uint64
   KernelTimer kt("escapes", st);
   launch_fill_u64(reinterpret_cast<uint64_t*>(wmax), (uint64_t)nlev, 0, st);
   MG_LAUNCH((&k_esc_starts), (k_esc_starts_k), (64), (0), (dim3(nlev + 1)), st, sym, n, chunk, esc_off, lt, nlev, ostart);
-  // few escapes unless the tolerance is tight: blocks past the escapes return at once
-  MG_LAUNCH((&k_esc_widths), (k_esc_widths_k), (TPB), (0), (dim3(grid_for(n / 4, 1024))), st, ecodes, ostart, nlev, wmax);
+  // few escapes unless the tolerance is tight: blocks past the escapes return
+  // at once, so the grids assume at least 32 (64) stream positions per thread
+  MG_LAUNCH((&k_esc_widths), (k_esc_widths_k), (TPB), (0), (dim3(grid_for(n / 32, 1024))), st, ecodes, ostart, nlev, wmax);
   MG_LAUNCH((&k_esc_layout), (k_esc_layout_k), (64), (0), (dim3(1)), st, ostart, wmax, nlev, hdr_counts, hdr_bits, woff);
-  MG_LAUNCH((&k_esc_pack), (k_esc_pack_k), (TPB), (0), (dim3(grid_for(n / 8, 2048))), st, ecodes, ostart, woff, static_cast<const uint32_t*>(hdr_bits), nlev, d_out, payload_off, word_off, nch);
+  MG_LAUNCH((&k_esc_pack), (k_esc_pack_k), (TPB), (0), (dim3(grid_for(n / 64, 2048))), st, ecodes, ostart, woff, static_cast<const uint32_t*>(hdr_bits), nlev, d_out, payload_off, word_off, nch);
   MG_HIP(hipGetLastError());
 }
 

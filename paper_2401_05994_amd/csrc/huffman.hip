@@ -21,7 +21,13 @@ constexpr int TPB = 256;
 constexpr int MAXLEN = 64;
 constexpr int MAXDICT = 8192;  // largest dictionary; all LDS below is static
 constexpr int CB_T = 1024, CB_KPT = MAXDICT / CB_T;  // codebook block; sort keys per thread
-constexpr int ENC_MAXLEN = 26;
+// Encoder tables: codes of at most ENC_PACKLEN bits are packed with their
+// length into one word (code << 6 | length); longer codes up to ENC_MAXLEN
+// bits (the wave encoder's limit) are entered as ENC_LONG, and the encoder
+// reads them from the full code and length tables.
+constexpr int ENC_PACKLEN = 26;
+constexpr int ENC_MAXLEN = 32;
+constexpr uint32_t ENC_LONG = 63;
 
 // ------------------------------------------------------------------ histogram
 // Blocks of 1024 threads with a private LDS histogram; each wave takes whole
@@ -189,6 +195,13 @@ __global__ void __launch_bounds__(WAVE_T) k_histogram_k(const uint16_t* __restri
 
 
 // ------------------------------------------------------------------ wave helpers
+// The encoder's table entry of a code of length L (0: unused symbol or a code
+// longer than ENC_MAXLEN, which the generic encoder handles).
+__device__ inline uint32_t pack_code(uint32_t L, uint64_t c) {
+  if (!L || L > (uint32_t)ENC_MAXLEN) return 0u;
+  return L <= (uint32_t)ENC_PACKLEN ? (uint32_t)((c << 6) | L) : ENC_LONG;
+}
+
 __device__ inline uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
 
 // Mask of the lanes whose `v` (7 bits) equals this lane's.
@@ -552,7 +565,7 @@ __device__ __forceinline__ void codebook_block(const uint64_t* __restrict__ hist
     const uint64_t c = L ? first[L] + (uint64_t)par[s] : 0ull;
     len_out[s] = (uint8_t)L;
     codes[s] = c;
-    if (enc) enc[s] = (L && L <= ENC_MAXLEN) ? (uint32_t)((c << 6) | (uint64_t)L) : 0u;
+    if (enc) enc[s] = pack_code(L, c);
     mine = max(mine, (uint32_t)L);
   }
   if (enc) {
@@ -845,7 +858,7 @@ __global__ void __launch_bounds__(1024) k_pack_codes(const uint8_t* __restrict__
   for (int s = threadIdx.x; s < dict; s += blockDim.x) {
     const uint32_t L = len[s];
     if (L) atomicMax(&mx, L);
-    enc[s] = (L && L <= ENC_MAXLEN) ? (uint32_t)((codes[s] << 6) | L) : 0u;
+    enc[s] = pack_code(L, codes[s]);
   }
   __syncthreads();
   if (threadIdx.x == 0) *maxlen_out = mx;
@@ -859,6 +872,8 @@ __global__ void __launch_bounds__(1024) k_pack_codes(const uint8_t* __restrict__
 __device__ __forceinline__ void k_encode_wave(G3 mg_bid, G3 mg_gdim, const uint16_t* __restrict__ sym, uint64_t n, int chunk,
                                                       uint64_t nch, uint32_t mask, const uint32_t* __restrict__ enc_g,
                                                       const uint32_t* __restrict__ maxlen,
+                                                      const uint8_t* __restrict__ len_g,
+                                                      const uint64_t* __restrict__ codes_g,
                                                       const uint64_t* __restrict__ word_off,
                                                       uint32_t* __restrict__ payload,
                                                       const uint64_t* __restrict__ esc_off,
@@ -894,14 +909,27 @@ __device__ __forceinline__ void k_encode_wave(G3 mg_bid, G3 mg_gdim, const uint1
     __builtin_amdgcn_wave_barrier();
   };
   auto step = [&](uint64_t i, const uint32_t (&s4)[4]) {
-    uint32_t e4[4];
-    uint32_t bits = 0, esc = 0;
+    uint32_t L4[4], c4[4];
+    uint32_t bits = 0, esc = 0, longc = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      e4[j] = s4[j] != 0xffffffffu ? enc[s4[j] & mask] : 0u;
-      bits += e4[j] & 63u;
+      const uint32_t e = s4[j] != 0xffffffffu ? enc[s4[j] & mask] : 0u;
+      L4[j] = e & 63u;
+      c4[j] = e >> 6;
+      longc |= L4[j] == ENC_LONG ? 1u : 0u;
       esc += s4[j] == 0;
     }
+    if (longc) {  // codes longer than ENC_PACKLEN bits (rare): the full tables
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (L4[j] == ENC_LONG) {
+          const uint32_t s = s4[j] & mask;
+          L4[j] = len_g[s];
+          c4[j] = (uint32_t)codes_g[s];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bits += L4[j];
     const uint32_t bi = wave_inclusive_sum(bits), ei = wave_inclusive_sum(esc);
     const uint32_t off = base + bi - bits;
     uint32_t wi = off >> 5;
@@ -909,9 +937,9 @@ __device__ __forceinline__ void k_encode_wave(G3 mg_bid, G3 mg_gdim, const uint1
     uint64_t acc = 0;  // left-aligned at word wi
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int L = (int)(e4[j] & 63u);
+      const int L = (int)L4[j];
       if (L) {
-        acc |= (uint64_t)(e4[j] >> 6) << (64 - fill - L);
+        acc |= (uint64_t)c4[j] << (64 - fill - L);
         fill += L;
         if (fill >= 32) {
           if (wi < ENC_WORDS) atomicOr(&wb[wi], (uint32_t)(acc >> 32));
@@ -965,12 +993,14 @@ __device__ __forceinline__ void k_encode_wave(G3 mg_bid, G3 mg_gdim, const uint1
 __global__ void __launch_bounds__(ENC_T) k_encode_wave_k(const uint16_t* __restrict__ sym, uint64_t n, int chunk,
                                                       uint64_t nch, uint32_t mask, const uint32_t* __restrict__ enc_g,
                                                       const uint32_t* __restrict__ maxlen,
+                                                      const uint8_t* __restrict__ len_g,
+                                                      const uint64_t* __restrict__ codes_g,
                                                       const uint64_t* __restrict__ word_off,
                                                       uint32_t* __restrict__ payload,
                                                       const uint64_t* __restrict__ esc_off,
                                                       const int64_t* __restrict__ qside,
                                                       uint64_t* __restrict__ ecodes, int R) {
-  k_encode_wave(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, sym, n, chunk, nch, mask, enc_g, maxlen, word_off, payload, esc_off, qside, ecodes, R);
+  k_encode_wave(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, sym, n, chunk, nch, mask, enc_g, maxlen, len_g, codes_g, word_off, payload, esc_off, qside, ecodes, R);
 }
 
 
@@ -1074,18 +1104,21 @@ __global__ void __launch_bounds__(TPB) k_encode_k(const uint16_t* __restrict__ s
 // ranges of successive lengths are contiguous from 0, so only windows above
 // lim1[maxlen] are invalid.
 //
-// Fast path (every length <= 32 and at most FASTN - 1 distinct lengths): for
-// the j-th distinct length flen[j], flim[j] = the top 32 bits of its lim1
-// (whose low 32 bits are all ones, so comparing the top 32 bits of the window
-// decides) and fdelta[j] = offset - first (mod 2^32); entry nfast has length 0
-// (an invalid code) and entries after it never match.
-constexpr int FASTN = 16;
-// Prefix table of the fast path: entry v is the index (into flen/fdelta) of
-// the one code length whose left-aligned interval holds every 32-bit window
-// starting with the LUT_BITS bits v, or LUT_NONE when the prefix straddles two
-// lengths (the compare chain decides those windows).
+// Fast path (every length <= 32): for the j-th distinct length flen[j],
+// flim[j] = the top 32 bits of its lim1 (whose low 32 bits are all ones, so
+// comparing the top 32 bits of the window decides) and fdelta[j] = offset -
+// first (mod 2^32); entry nfast (the number of distinct lengths) has length 0
+// (an invalid code), limit 2^32 - 1, so no window passes it, and delta
+// 2^32 - 1, so the symbol index it gives is out of range.
+constexpr int FASTN = 33;
+// Prefix table of the fast path: entry v describes the 32-bit windows that
+// start with the LUT_BITS bits v.  Its low 6 bits are j, the index of the
+// shortest length whose interval meets them; bit 6 set: the windows meet the
+// intervals of lengths j and j + 1 (the window's comparison with flim[j]
+// decides); bit 7 set: they meet three or more (comparisons from j on decide);
+// neither: every such window has length j.
 constexpr int LUT_BITS = 12;
-constexpr uint8_t LUT_NONE = 0xff;
+constexpr uint32_t LUT_TWO = 0x40, LUT_MANY = 0x80;
 
 struct DecTables {
   uint64_t first[MAXLEN + 1];
@@ -1156,7 +1189,7 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
     tab->maxlen = maxlen;
     tab->bad = flag;
     tab->used = off;
-    const bool fast = maxlen && maxlen <= 32 && nd <= FASTN - 1;
+    const bool fast = maxlen && maxlen <= 32;  // then nd <= 32 < FASTN
     int j = 0;
     if (fast)
       for (int b = minlen; b <= (int)maxlen; ++b) {
@@ -1166,10 +1199,10 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
         tab->fdelta[j] = offs[b] - (uint32_t)tab->first[b];
         ++j;
       }
-    for (; j < FASTN; ++j) {
+    for (; j < FASTN; ++j) {  // the end entry (an invalid code) and unused ones
       tab->flen[j] = 0;
       tab->flim[j] = 0xffffffffu;
-      tab->fdelta[j] = 0;
+      tab->fdelta[j] = 0xffffffffu;
     }
     tab->nfast = fast ? nd : 0;
     for (int j = 0; j < FASTN; ++j) sflim[j] = tab->flim[j];
@@ -1181,20 +1214,20 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
     if (L) sorted[offs[L] + rank[s]] = (uint16_t)s;
   }
   // windows starting with prefix v run from v << (32 - LUT_BITS) to that plus
-  // 2^(32 - LUT_BITS) - 1; the chain's answer for a window is the number of
-  // limits below it, so the prefix has one answer when both ends agree
+  // 2^(32 - LUT_BITS) - 1; the index of a window's length is the number of
+  // limits below it, between its value at the two ends
   for (int v = t; v < (1 << LUT_BITS); v += nt) {
-    uint8_t e = LUT_NONE;
+    uint32_t e = 0;
     if (snfast) {
       const uint32_t lo = (uint32_t)v << (32 - LUT_BITS), hi = lo | ((1u << (32 - LUT_BITS)) - 1u);
-      int clo = 0, chi = 0;
-      for (int j = 0; j + 1 < FASTN; ++j) {
-        clo += lo > sflim[j] ? 1 : 0;
-        chi += hi > sflim[j] ? 1 : 0;
+      uint32_t clo = 0, chi = 0;
+      for (uint32_t j = 0; j < snfast; ++j) {
+        clo += lo > sflim[j] ? 1u : 0u;
+        chi += hi > sflim[j] ? 1u : 0u;
       }
-      if (clo == chi) e = (uint8_t)clo;
+      e = clo | (chi == clo ? 0u : chi == clo + 1 ? LUT_TWO : LUT_MANY);
     }
-    tab->lut[v] = e;
+    tab->lut[v] = (uint8_t)e;
   }
 }
 
@@ -1229,11 +1262,6 @@ __device__ inline uint4 shift_group(uint4 v, uint32_t sh) {
 // to epos[j] (chunk k owns entries [esc_off[k], esc_off[k+1]), which must lie
 // inside the n_out entries of epos, and esc_off[nch] must equal n_out); the loop
 // itself issues no loads besides the payload, so it never waits on them early.
-// NF: length-chain size.  Three instances are launched; the one whose range
-// holds the table's number of distinct lengths decodes (NF = 8: 1..7,
-// NF = 12: 8..11, NF = 16: 12..15 and tables without a fast path), the others
-// return at once.
-template <int NF>
 __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
                                                const uint64_t* __restrict__ word_off,
                                                const uint32_t* __restrict__ chunk_bits, uint64_t n, int chunk,
@@ -1247,12 +1275,8 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
   __shared__ uint16_t sorted[MAXDICT];
   __shared__ uint32_t ring[256 * RING_STRIDE];
   __shared__ uint32_t lut_w[(1 << LUT_BITS) / 4];  // the prefix table, four entries per word
-  __shared__ uint32_t fl_s[FASTN], fd_s[FASTN];
-  {
-    const uint32_t nd = tab->nfast;
-    const bool mine = NF == 8 ? (nd >= 1 && nd <= 7) : NF == 12 ? (nd >= 8 && nd <= 11) : (nd == 0 || nd >= 12);
-    if (!mine) return;
-  }
+  __shared__ uint2 fld_s[FASTN];                   // (fdelta, flen) of each distinct length
+  __shared__ uint32_t flim_s[FASTN];
   const uint32_t used = min(tab->used, (uint32_t)dict);
   for (int b = threadIdx.x; b <= MAXLEN; b += blockDim.x) {
     first[b] = tab->first[b];
@@ -1263,8 +1287,8 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
     const uint32_t* lw = reinterpret_cast<const uint32_t*>(tab->lut);
     for (int i = threadIdx.x; i < (1 << LUT_BITS) / 4; i += blockDim.x) lut_w[i] = lw[i];
     if (threadIdx.x < FASTN) {
-      fl_s[threadIdx.x] = tab->flen[threadIdx.x];
-      fd_s[threadIdx.x] = tab->fdelta[threadIdx.x];
+      fld_s[threadIdx.x] = make_uint2(tab->fdelta[threadIdx.x], tab->flen[threadIdx.x]);
+      flim_s[threadIdx.x] = tab->flim[threadIdx.x];
     }
   }
   // symbols in code order: eight loads per lane in flight before the LDS stores
@@ -1308,19 +1332,12 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
   }
   uint64_t consumed = 0;
   if (tab->nfast && payload_words >= 4) {
-    // Branch-free length search over the distinct lengths.  The chunk's words
+    // The length of each code comes from the prefix table.  The chunk's words
     // pass through a per-lane ring in LDS: every 8 symbols (wave-uniform) the
     // 8 words fetched 8 symbols earlier are written to the ring and the next 8
     // are fetched if the ring has room, so no load is waited for soon after it
     // is issued.  The ring never holds fewer than 8 unread words at a refill
     // point, and at most 8 words are read between two refill points.
-    uint32_t flen[NF], flim[NF], fdelta[NF];
-#pragma unroll
-    for (int j = 0; j < NF; ++j) {
-      flen[j] = tab->flen[j];
-      flim[j] = tab->flim[j];
-      fdelta[j] = tab->fdelta[j];
-    }
     uint32_t* myring = ring + threadIdx.x * RING_STRIDE;
     uint64_t fetch_at = w0;
     uint32_t wr = 0, rd = 0;
@@ -1412,26 +1429,23 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
         nextw = myring[rd & (RING - 1)];
       }
       const uint32_t top = (uint32_t)(buf >> 32);
-      // the length from the prefix table; the compare chain only for windows
-      // whose prefix straddles two lengths
+      // the length from the prefix table; comparisons with the limits only
+      // for windows whose prefix meets two or more lengths (rare)
       const uint32_t pv = top >> (32 - LUT_BITS);
       const uint32_t e = (lut_w[pv >> 2] >> (8 * (pv & 3))) & 0xffu;
-      uint32_t L, d;
-      if (e != LUT_NONE) {
-        L = fl_s[e];
-        d = fd_s[e];
-      } else {
-        L = flen[0];
-        d = fdelta[0];
-#pragma unroll
-        for (int j = 0; j + 1 < NF; ++j) {
-          const bool past = top > flim[j];
-          L = past ? flen[j + 1] : L;
-          d = past ? fdelta[j + 1] : d;
-        }
+      uint32_t j = e & 63u;
+      uint2 ld = fld_s[j];  // issued before the rare case is resolved
+      if (e & (LUT_TWO | LUT_MANY)) {
+        if (e & LUT_TWO)
+          j += top > flim_s[j] ? 1u : 0u;
+        else
+          while (top > flim_s[j]) ++j;  // flim_s[nfast] = 2^32 - 1 ends it
+        ld = fld_s[j];
       }
-      // L = 0: no code of the table starts with these bits
-      const uint32_t idx = L ? d + (top >> (32 - L)) : 0xffffffffu;
+      const uint32_t L = ld.y, d = ld.x;
+      // L = 0 (no code of the table starts with these bits) leaves idx =
+      // fdelta of the end entry, 2^32 - 1: no branch, no wait on L
+      const uint32_t idx = d + (uint32_t)((uint64_t)top >> (32 - L));
       buf <<= L;
       have -= (int)L;
       cons += L;
@@ -1656,11 +1670,15 @@ void launch_encode(const uint16_t* sym, uint64_t n, int dict, int chunk, const u
   if (!packed) hipLaunchKernelGGL(k_pack_codes, dim3(1), dim3(1024), 0, st, len, codes, dict, enc, maxlen);
   const uint32_t mask = (uint32_t)(dict - 1);
   if (chunk <= ENC_CHUNK)
-    MG_LAUNCH((&k_encode_wave), (k_encode_wave_k), (ENC_T), (0), (dim3(blocks_for((nch + ENC_T / 64 - 1) / (ENC_T / 64), 512))), st, sym, n, chunk, nch, mask, enc, maxlen, word_off, payload, esc_off, qside, ecodes, dict / 2);
+    MG_LAUNCH((&k_encode_wave), (k_encode_wave_k), (ENC_T), (0), (dim3(blocks_for((nch + ENC_T / 64 - 1) / (ENC_T / 64), 512))), st, sym, n, chunk, nch, mask, enc, maxlen, len, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
+  // The generic kernel does the work for chunks above ENC_CHUNK; for smaller
+  // chunks only when some code is longer than ENC_MAXLEN (rare), and its
+  // blocks return at once otherwise, so that grid is kept small.
+  const unsigned gen_blocks = blocks_for(nch, chunk <= ENC_CHUNK ? 256 : 4096);
   if (chunk <= 4096)
-    MG_LAUNCH((&k_encode<4096 * MAXLEN / 32>), (k_encode_k<4096 * MAXLEN / 32>), (TPB), (0), (dim3(blocks_for(nch, 4096))), st, sym, n, chunk, nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
+    MG_LAUNCH((&k_encode<4096 * MAXLEN / 32>), (k_encode_k<4096 * MAXLEN / 32>), (TPB), (0), (dim3(gen_blocks)), st, sym, n, chunk, nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
   else
-    MG_LAUNCH((&k_encode<8192 * MAXLEN / 32>), (k_encode_k<8192 * MAXLEN / 32>), (TPB), (0), (dim3(blocks_for(nch, 4096))), st, sym, n, chunk, nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
+    MG_LAUNCH((&k_encode<8192 * MAXLEN / 32>), (k_encode_k<8192 * MAXLEN / 32>), (TPB), (0), (dim3(gen_blocks)), st, sym, n, chunk, nch, mask, len, maxlen, codes, word_off, payload, esc_off, qside, ecodes, dict / 2);
   MG_HIP(hipGetLastError());
 }
 
@@ -1683,16 +1701,8 @@ void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const u
   if (nch) {
     const unsigned blocks = (unsigned)((nch + 255) / 256);
     KernelTimer kt("decode", st);
-    // one of the three instances decodes (chosen on the device by the table's
-    // number of distinct code lengths); the others return at once
-    hipLaunchKernelGGL(k_decode<8>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits, n,
+    hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits, n,
                        chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, n_out,
-                       escapes ? epos : nullptr, d_status);
-    hipLaunchKernelGGL(k_decode<12>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits,
-                       n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, n_out,
-                       escapes ? epos : nullptr, d_status);
-    hipLaunchKernelGGL(k_decode<16>, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits,
-                       n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, n_out,
                        escapes ? epos : nullptr, d_status);
   }
   MG_HIP(hipGetLastError());

@@ -201,8 +201,11 @@ template <typename T>
 void launch_maxabs(const T* d, uint64_t n, uint64_t* d_bits, hipStream_t st) {
   launch_fill_u64(d_bits, 1, 0, st);
   KernelTimer kt("maxabs", st);
-  // 1024 blocks (16 wavefronts per CU) read faster than 2048 or more in a sweep of the cap
-  MG_LAUNCH((&k_maxabs<T>), (k_maxabs_k<T>), (TPB), (0), (dim3(grid_for(n, 1024))), st, d, n, d_bits);
+  // 1024 blocks (16 wavefronts per CU) read faster than 2048 or more in a sweep
+  // of the cap; below that, at least 32 elements per thread (two trips), so a
+  // small array (a field of a batch) is not spread over blocks that each
+  // reduce a few values
+  MG_LAUNCH((&k_maxabs<T>), (k_maxabs_k<T>), (TPB), (0), (dim3(grid_for(n / 32, 1024))), st, d, n, d_bits);
   MG_HIP(hipGetLastError());
 }
 

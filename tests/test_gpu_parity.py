@@ -250,15 +250,21 @@ def test_codebook_adversarial(lib, case):
     assert np.array_equal(host(codes).view(np.uint64)[lref > 0], cref[lref > 0])
 
 
-def test_huffman_many_lengths_bitexact(lib):
-    """A complete prefix code with 25 distinct lengths, all <= 32 (the decoder's search path)."""
-    say("huffman many lengths")
-    dict_size, chunk = 256, 512
+@pytest.mark.parametrize("top,draw,chunk", [(25, "geometric", 512), (32, "uniform", 1024), (32, "geometric", 256)])
+def test_huffman_many_lengths_bitexact(lib, top, draw, chunk):
+    """A complete prefix code with `top` distinct lengths 1..top, all <= 32 (the
+    decoder's prefix table with windows that meet two and more lengths; with
+    top = 32, codes longer than the encoder's packed 26 bits)."""
+    say("huffman many lengths", top, draw, chunk)
+    dict_size = 256
     lens = np.zeros(dict_size, dtype=np.int64)
-    lens[:26] = list(range(1, 26)) + [25]
+    lens[:top + 1] = list(range(1, top + 1)) + [top]
     codes = H.canonical_codes(lens)
-    rng = np.random.default_rng(4)
-    sym = np.minimum(rng.geometric(0.3, size=20_001) - 1, 25)
+    rng = np.random.default_rng(4 + top)
+    if draw == "geometric":
+        sym = np.minimum(rng.geometric(0.3, size=20_001) - 1, top)
+    else:  # every length equally often: most windows lie among the long codes
+        sym = rng.integers(0, top + 1, size=20_001)
     bref, wref = H.encode(sym, lens, codes, chunk)
     dlens = dev(lens.astype(np.uint8))
     bits, payload = lib.mgard_huffman_encode(dev(sym.astype(np.int16)), dlens, dev(codes.view(np.int64)),
