@@ -10,6 +10,7 @@
 //   * the symbol stream is cut into chunks; each chunk is packed MSB-first into
 //     32-bit words starting word-aligned, so chunks decode independently.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -1262,7 +1263,9 @@ __device__ inline uint4 shift_group(uint4 v, uint32_t sh) {
 // to epos[j] (chunk k owns entries [esc_off[k], esc_off[k+1]), which must lie
 // inside the n_out entries of epos, and esc_off[nch] must equal n_out); the loop
 // itself issues no loads besides the payload, so it never waits on them early.
-__global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
+// BT: lanes per block (the launch picks it so that every block is resident at once).
+template <int BT>
+__global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payload, uint64_t payload_words,
                                                const uint64_t* __restrict__ word_off,
                                                const uint32_t* __restrict__ chunk_bits, uint64_t n, int chunk,
                                                uint64_t nch, const DecTables* __restrict__ tab,
@@ -1273,7 +1276,7 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
   __shared__ uint64_t first[MAXLEN + 1], lim1[MAXLEN + 1];
   __shared__ uint32_t offs[MAXLEN + 1];
   __shared__ uint16_t sorted[MAXDICT];
-  __shared__ uint32_t ring[256 * RING_STRIDE];
+  __shared__ uint32_t ring[BT * RING_STRIDE];
   __shared__ uint32_t lut_w[(1 << LUT_BITS) / 4];  // the prefix table, four entries per word
   __shared__ uint2 fld_s[FASTN];                   // (fdelta, flen) of each distinct length
   __shared__ uint32_t flim_s[FASTN];
@@ -1587,6 +1590,45 @@ __global__ void __launch_bounds__(256) k_decode(const uint32_t* __restrict__ pay
   if (consumed != nbits || eo != eo_end) atomicOr(status, 1u);
 }
 
+// Lanes per decoding block.  A lane decodes a whole chunk, so every chunk of
+// a stream takes about as long; the kernel ends when the CU with the most
+// wavefronts is done.  Of 192, 256 and 320 lanes (three, two and two blocks
+// per CU by their LDS), the one whose blocks are all resident at once with
+// the fewest wavefronts on the busiest CU is used.
+struct DecodeShape {
+  int bt;
+};
+DecodeShape decode_shape(uint64_t nch) {
+  static int ncu = 0, per[3] = {0, 0, 0};
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess)
+      ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_decode<192>, 192, 0) != hipSuccess) per[0] = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_decode<256>, 256, 0) != hipSuccess) per[1] = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[2], k_decode<320>, 320, 0) != hipSuccess) per[2] = 0;
+    (void)hipGetLastError();
+  });
+  const int bts[3] = {192, 256, 320};
+  int best = 1;
+  uint64_t best_cost = ~0ull;
+  for (int c = 0; c < 3; ++c) {
+    if (ncu <= 0 || per[c] <= 0) continue;
+    const uint64_t blocks = (nch + bts[c] - 1) / bts[c];
+    const uint64_t slots = (uint64_t)per[c] * (uint64_t)ncu;
+    const uint64_t rounds = (blocks + slots - 1) / slots;
+    const uint64_t on_busiest = rounds == 1 ? (blocks + ncu - 1) / ncu : rounds * (uint64_t)per[c];
+    const uint64_t cost = on_busiest * (uint64_t)(bts[c] / 64);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = c;
+    }
+  }
+  return DecodeShape{bts[best]};
+}
+
 inline unsigned blocks_for(uint64_t nch, unsigned cap) {
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nch, cap));
 }
@@ -1699,11 +1741,19 @@ void launch_decode_full(const uint32_t* payload, uint64_t payload_words, const u
   const uint64_t nch = (n + chunk - 1) / chunk;
   const bool escapes = esc_off && epos;
   if (nch) {
-    const unsigned blocks = (unsigned)((nch + 255) / 256);
     KernelTimer kt("decode", st);
-    hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(256), 0, st, payload, payload_words, word_off, chunk_bits, n,
-                       chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr, n_out,
-                       escapes ? epos : nullptr, d_status);
+    const DecodeShape sh = decode_shape(nch);
+    auto go = [&](auto kernel, int bt) {
+      hipLaunchKernelGGL(kernel, dim3((unsigned)((nch + bt - 1) / bt)), dim3(bt), 0, st, payload, payload_words,
+                         word_off, chunk_bits, n, chunk, nch, tab, sorted, dict, sym, escapes ? esc_off : nullptr,
+                         n_out, escapes ? epos : nullptr, d_status);
+    };
+    if (sh.bt == 192)
+      go(k_decode<192>, 192);
+    else if (sh.bt == 256)
+      go(k_decode<256>, 256);
+    else
+      go(k_decode<320>, 320);
   }
   MG_HIP(hipGetLastError());
 }
