@@ -465,6 +465,365 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
 }
 
 
+// ------------------------------------------------------------------ decomposition, register tiles (float)
+// The float form of the plane-marching decomposition: one wavefront per tile
+// and no barriers.  Lane i holds fine columns e = F2 + 2i and e + 1 (F2 =
+// 2 J2 - 2) of the tile's RX fine rows in registers: the current plane, the
+// next plane (in flight), and the in-plane interpolants of the two coarse
+// planes around the current interval.  Neighbouring columns come from the
+// adjacent lanes by DPP wavefront shifts, neighbouring rows are registers of
+// the same lane.  The planes of one dim-0 segment are visited as in
+// k3_coeff_r21, and the arithmetic and its order are those of k3_coeff_r21.
+constexpr int RX = 11;    // fine rows per tile: 8 owned, 2 before, 1 after
+constexpr int RCY = 4;    // coarse rows (dim-1 outputs) per tile
+constexpr int RCX = 62;   // coarse columns (dim-2 outputs) per tile: lanes 1..62
+constexpr int RWAVE = 64;
+
+// x of lane i + 1 (0 for lane 63) and of lane i - 1 (0 for lane 0): DPP
+// wavefront shifts, every lane active
+__device__ inline float lane_next(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, true));  // wave_shl:1
+}
+__device__ inline float lane_prev(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, true));  // wave_shr:1
+}
+
+// Tiles in XCD order: consecutive workgroups go to the eight XCDs in turn, so
+// block b takes tile (b mod 8) q + b / 8 (q = ceil(tiles / 8)): each XCD gets
+// a run of tiles adjacent along dim 1, whose shared halo rows its L2 then
+// holds.  Tiles are numbered dim 1 fastest, then dim 2, then the segment.
+__device__ inline bool reg_tile(uint32_t b, int nt1, int nt2, int nseg, int& t1, int& t2, int& sg) {
+  const uint32_t nb = (uint32_t)nt1 * (uint32_t)nt2 * (uint32_t)nseg;
+  const uint32_t q8 = (nb + 7) / 8;
+  const uint32_t t = (b % 8) * q8 + b / 8;
+  if (t >= nb) return false;
+  t1 = (int)(t % (uint32_t)nt1);
+  t2 = (int)((t / (uint32_t)nt1) % (uint32_t)nt2);
+  sg = (int)(t / ((uint32_t)nt1 * (uint32_t)nt2));
+  return true;
+}
+
+template <int MODE>
+__device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float* __restrict__ u,
+                                             float* __restrict__ ucoarse, float* __restrict__ g1,
+                                             uint16_t* __restrict__ sym, int64_t* __restrict__ qside,
+                                             float* __restrict__ cstream, const double* __restrict__ bins, int level,
+                                             int R, const Lv3<float>& p, int seg, int nt1, int nt2, int nseg,
+                                             const float* __restrict__ d0wl, const float* __restrict__ d0wr) {
+  // in-plane interpolants of the interval's two coarse planes, lane-private
+  // slots [plane][row][column][lane]; row weights of the tile
+  __shared__ float Bs[2][RX][2][RWAVE];
+  __shared__ float Wr[5][RX];   // dim 1: interpolation left/right (new rows), mass a/b/c (rows in the grid)
+  __shared__ float Wk[2][RCY];  // dim 1: restriction left/right of coarse row J1 + k
+  // stream positions: sub-grid m (bit 0: new along dim 0, bit 1: dim 1, bit 2:
+  // dim 2) starts at row part + i0 * S0[m] for owned row r: Rb[r - 2][m]
+  // holds its offset + i1 * (stride of i1); S0[m] the stride of i0
+  __shared__ uint64_t Rb[2 * RCY][8];
+  __shared__ uint64_t S0[8];
+  int tile1, tile2, sgi;
+  if (!reg_tile(mg_bid.x, nt1, nt2, nseg, tile1, tile2, sgi)) return;
+  const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
+  const int J1 = tile1 * RCY, J2 = tile2 * RCX;
+  const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
+  const int cb = sgi * seg;
+  const int ce = min(cb + seg, p.c0 - 1);
+  const uint64_t plane = (uint64_t)n1 * n2;
+  double inv_b = 0.0;
+  if (MODE == 1) inv_b = 1.0 / bins[level];
+
+  // ---- columns of this lane
+  const int lane = threadIdx.x;
+  const int e = F2 + 2 * lane, o = e + 1;
+  const bool ein = e >= 0 && e < n2;
+  const bool oin = e >= 0 && o < n2;
+  const bool inner = lane >= 1 && lane <= RCX;  // owned fine columns [2 J2, 2 J2 + 124)
+  const bool own_e = inner && ein, own_o = inner && oin;
+  const bool onew = oin && o < n2 - 1;  // o is new along dim 2 (else the last column, coarse)
+  const bool eshift = e == n2 - 1;      // e is the last column: the loaded pair starts one before
+  const int pc = min(max(e, 0), n2 - 2);
+  const int oc = min(max(o, 0), n2 - 1);
+  const float wl2v = p.d2.wl[oc], wr2v = p.d2.wr[oc];
+  const float wl2 = onew ? wl2v : 0.f, wr2 = onew ? wr2v : 0.f;
+  const uint64_t colidx = e >= 0 ? (uint64_t)(e >> 1) : 0;  // cidx(e) = e / 2 = o >> 1
+  // restriction along dim 2: this lane's coarse column j2 = J2 - 1 + lane
+  const int j2 = J2 - 1 + lane;
+  const bool out2 = inner && j2 < c2;
+  RestrictW<float> rw;
+  rw.load(min(max(j2, 0), c2 - 1), c2, n2, p.d2);
+  const bool rshift = out2 && rw.c == e - 1;  // the last coarse column of an even side sits at e - 1
+
+  // ---- rows of the tile (the same for every lane)
+  uint32_t m_in = 0, m_new = 0;
+#pragma unroll
+  for (int r = 0; r < RX; ++r) {
+    const int f1 = F1 + r;
+    const bool in = f1 >= 0 && f1 < n1;
+    m_in |= in ? 1u << r : 0u;
+    m_new |= in && is_new(f1, n1) ? 1u << r : 0u;
+  }
+  m_in = __builtin_amdgcn_readfirstlane(m_in);
+  m_new = __builtin_amdgcn_readfirstlane(m_new);
+  auto bit = [](uint32_t m, int j) { return ((m >> j) & 1u) != 0u; };
+  if (lane < RX) {
+    const int r = lane, f1c = min(max(F1 + r, 0), n1 - 1);
+    const float vl = p.d1.wl[f1c], vr = p.d1.wr[f1c], va = p.d1.ma[f1c], vb = p.d1.mb[f1c], vc = p.d1.mc[f1c];
+    const bool nw = ((m_new >> r) & 1u) != 0u, in = ((m_in >> r) & 1u) != 0u;
+    Wr[0][r] = nw ? vl : 0.f;
+    Wr[1][r] = nw ? vr : 0.f;
+    Wr[2][r] = in ? va : 0.f;
+    Wr[3][r] = in ? vb : 0.f;
+    Wr[4][r] = in ? vc : 0.f;
+  }
+  uint32_t k_ok = 0, k_odd = 0, k_l = 0, k_r = 0;
+#pragma unroll
+  for (int k = 0; k < RCY; ++k) {
+    const int j1 = J1 + k;
+    const int c = cpos(min(j1, c1 - 1), c1, n1);
+    const bool ok = j1 < c1;
+    k_ok |= ok ? 1u << k : 0u;
+    k_odd |= ok && c != 2 * j1 ? 1u << k : 0u;  // centre at tile row 2k + 1 instead of 2k + 2
+    k_l |= ok && c >= 2 && !(c & 1) ? 1u << k : 0u;
+    k_r |= ok && !(c & 1) && c < n1 - 2 ? 1u << k : 0u;
+  }
+  k_ok = __builtin_amdgcn_readfirstlane(k_ok);
+  k_odd = __builtin_amdgcn_readfirstlane(k_odd);
+  k_l = __builtin_amdgcn_readfirstlane(k_l);
+  k_r = __builtin_amdgcn_readfirstlane(k_r);
+  if (lane < RCY) {
+    const int jc = min(J1 + lane, c1 - 1);
+    Wk[0][lane] = p.d1.rl[jc];
+    Wk[1][lane] = p.d1.rr[jc];
+  }
+  {
+    // lane = 8 (r - 2) + m: the row part of owned row r in sub-grid m
+    const int r = 2 + (lane >> 3), m = lane & 7;
+    const int f1 = F1 + r;
+    const bool e1 = is_new(min(max(f1, 0), n1 - 1), n1);
+    const int i1 = e1 ? (f1 >> 1) : cidx(f1);
+    const uint64_t off = m == 0 ? 0 : p.level_off + p.sub[m];
+    const uint64_t s1 = p.sub[16 + 4 * m + 2];
+    Rb[r - 2][m] = m == 0 ? 0 : off + (uint64_t)max(i1, 0) * s1;
+    if (lane < 8) S0[lane] = lane == 0 ? 0 : p.sub[16 + 4 * lane + 1];
+  }
+  __syncthreads();
+  // mass stencil of tile row r (fine row F1 + r inside the grid), on g
+  auto mass1 = [&](int r, const float* g) -> float {
+    const int f1 = F1 + r;
+    float s = Wr[3][r] * g[r];
+    if (r > 0) s = f1 > 0 ? Wr[2][r] * g[r - 1] + s : s;
+    if (r + 1 < RX) s = f1 < n1 - 1 ? s + Wr[4][r] * g[r + 1] : s;
+    return s;
+  };
+
+  // ---- plane registers
+  float pre[RX][2];  // next plane, in flight
+  float cur[RX][2];  // current plane (u), then its coefficients
+  int rowc[RX];
+#pragma unroll
+  for (int r = 0; r < RX; ++r) rowc[r] = min(max(F1 + r, 0), n1 - 1);
+  auto prefetch = [&](int f0) {
+    const float* base = u + (uint64_t)f0 * plane + pc;
+#pragma unroll
+    for (int r = 0; r < RX; ++r) {
+      float2 v;
+      __builtin_memcpy(&v, base + (uint64_t)rowc[r] * n2, 8);
+      pre[r][0] = v.x;
+      pre[r][1] = v.y;
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int r = 0; r < RX; ++r) {
+      const bool in = bit(m_in, r);
+      cur[r][0] = in && ein ? (eshift ? pre[r][1] : pre[r][0]) : 0.f;
+      cur[r][1] = in && oin ? pre[r][1] : 0.f;
+    }
+  };
+  auto qstore = [&](float c, uint64_t pos) {
+    if (MODE == 1) {
+      const double y = (double)c * inv_b;
+      const double a = floor(fabs(y) + 0.5);
+      const bool esc = !(a < (double)R);
+      const int qa = (int)(esc ? 0.0 : a);
+      sym[pos] = esc ? (uint16_t)0 : (uint16_t)(y < 0.0 ? R - qa : R + qa);
+      if (esc) qside[pos] = (int64_t)(y < 0.0 ? -a : a);
+    } else {
+      cstream[pos] = c;
+    }
+  };
+  int bp = 0, bn = 1;  // slots of the left and right coarse planes' interpolants
+  // Coarse plane: in-plane interpolant (dim 2 on the coarse rows, then dim 1)
+  // into slot bn, and the coefficients u - interpolant in place of u.
+  auto coarse_coeffs = [&]() {
+    float B[RX][2];
+#pragma unroll
+    for (int r = 0; r < RX; ++r) {
+      if (r % 2 == 1 && bit(m_new, r)) continue;
+      const float nx = lane_next(cur[r][0]);
+      B[r][0] = cur[r][0];
+      B[r][1] = onew ? wl2 * cur[r][0] + wr2 * nx : cur[r][1];
+    }
+#pragma unroll
+    for (int r = 1; r < RX; r += 2) {
+      if (!bit(m_new, r)) continue;
+      B[r][0] = Wr[0][r] * B[r - 1][0] + Wr[1][r] * B[r + 1][0];
+      B[r][1] = Wr[0][r] * B[r - 1][1] + Wr[1][r] * B[r + 1][1];
+    }
+#pragma unroll
+    for (int r = 0; r < RX; ++r) {
+      Bs[bn][r][0][lane] = B[r][0];
+      Bs[bn][r][1][lane] = B[r][1];
+    }
+  };
+  // Outputs of the owned nodes of plane f0 (cur: u; cv: coefficients), then
+  // mass + restriction along dims 2 and 1 of the coefficients -> g1.
+  auto emit = [&](int f0, const float (&cv)[RX][2]) {
+    const bool e0 = is_new(f0, n0);
+    const int i0 = e0 ? (f0 >> 1) : cidx(f0);
+    const uint64_t ucplane = (uint64_t)cidx(f0) * c1 * c2;
+    // i0 * stride for the four sub-grids of this plane's dim-0 parity
+    const int m0 = e0 ? 1 : 0;
+    const uint64_t P00 = (uint64_t)i0 * S0[m0], P10 = (uint64_t)i0 * S0[m0 | 2];
+    const uint64_t P01 = (uint64_t)i0 * S0[m0 | 4], P11 = (uint64_t)i0 * S0[m0 | 6];
+#pragma unroll
+    for (int r = 2; r < 2 + 2 * RCY; ++r) {
+      if (!bit(m_in, r)) continue;
+      const int f1 = F1 + r;
+      const bool e1 = bit(m_new, r);
+      const int m01 = m0 | (e1 ? 2 : 0);
+      const uint64_t rb1 = Rb[r - 2][m01 | 4] + (e1 ? P11 : P01);
+      if (!e0 && !e1) {  // coarse row of a coarse plane: e is a coarse node
+        const uint64_t ucb = ucplane + (uint64_t)cidx(f1) * c2 + colidx;
+        if (own_e) ucoarse[ucb] = cur[r][0];
+        if (own_o) {
+          if (onew)
+            qstore(cv[r][1], rb1 + colidx);
+          else
+            ucoarse[ucb + 1] = cur[r][1];
+        }
+      } else {
+        const uint64_t rb0 = Rb[r - 2][m01] + (e1 ? P10 : P00);
+        if (own_e) qstore(cv[r][0], rb0 + colidx);
+        if (own_o) qstore(cv[r][1], onew ? rb1 + colidx : rb0 + colidx + 1);
+      }
+    }
+    // mass + restriction along dim 2, every row of the tile: the window of
+    // fine columns e - 2 .. e + 2 from this lane and its two neighbours
+    float g2[RX];
+#pragma unroll
+    for (int r = 0; r < RX; ++r) {
+      const float w0 = lane_prev(cv[r][0]), w1 = lane_prev(cv[r][1]), w4 = lane_next(cv[r][0]);
+      const float w2 = cv[r][0], w3 = cv[r][1];
+      const float gm = rshift ? w0 : w1, g0 = rshift ? w1 : w2, gp = rshift ? w2 : w3;
+      auto M = [&](int k, float a, float b, float c) {
+        float s = rw.b[k] * b;
+        s = rw.hl[k] ? rw.a[k] * a + s : s;
+        s = rw.hr[k] ? s + rw.d[k] * c : s;
+        return s;
+      };
+      float f = M(1, gm, g0, gp);
+      f = rw.l ? rw.rl * M(0, w0, w1, w2) + f : f;
+      f = rw.r ? f + rw.rr * M(2, w2, w3, w4) : f;
+      g2[r] = f;
+    }
+    // mass + restriction along dim 1 -> g1
+    const uint64_t gplane = (uint64_t)f0 * c1;
+#pragma unroll
+    for (int k = 0; k < RCY; ++k) {
+      if (!bit(k_ok, k)) continue;
+      float f;
+      if (!bit(k_odd, k)) {
+        const int c = 2 * k + 2;
+        f = mass1(c, g2);
+        if (bit(k_l, k)) f = Wk[0][k] * mass1(c - 1, g2) + f;
+        if (bit(k_r, k)) f = f + Wk[1][k] * mass1(c + 1, g2);
+      } else {
+        f = mass1(2 * k + 1, g2);  // an odd centre has neither side term
+      }
+      if (out2) g1[(gplane + (uint64_t)(J1 + k)) * c2 + j2] = f;
+    }
+  };
+
+  // Planes of the segment, as in k3_coeff_r21: the first coarse plane, then
+  // per interval j its closing coarse plane (kind 1) and, when the interval
+  // has one, its new plane (kind 2).
+  auto task_at = [&](int j, int phase, int& pl, int& kind, int& tj) -> bool {
+    while (j < ce) {
+      const int fcj = cpos(j, p.c0, n0), fnj = cpos(j + 1, p.c0, n0);
+      if (phase == 0) {
+        pl = fnj, kind = 1, tj = j;
+        return true;
+      }
+      if (fnj - fcj == 2) {
+        pl = fcj + 1, kind = 2, tj = j;
+        return true;
+      }
+      ++j;
+      phase = 0;
+    }
+    return false;
+  };
+  int cplane = cpos(cb, p.c0, n0), ckind = 0, cj = cb;
+  int nj = cb, nph = 0;
+  prefetch(cplane);
+  commit();
+  while (true) {
+    asm volatile("" : "+s"(m_in), "+s"(m_new));
+    int xplane = 0, xkind = 0, xj = 0;
+    const bool more = task_at(nj, nph, xplane, xkind, xj);
+    if (more) prefetch(xplane);
+    float cv[RX][2];
+    if (ckind != 2) {
+      coarse_coeffs();
+#pragma unroll
+      for (int r = 0; r < RX; ++r) {
+        cv[r][0] = cur[r][0] - Bs[bn][r][0][lane];
+        cv[r][1] = cur[r][1] - Bs[bn][r][1][lane];
+      }
+    } else {
+      const float w0l = d0wl[cplane], w0r = d0wr[cplane];
+#pragma unroll
+      for (int r = 0; r < RX; ++r)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) cv[r][k] = cur[r][k] - (w0l * Bs[bp][r][k][lane] + w0r * Bs[bn][r][k][lane]);
+    }
+    // a closing coarse plane that opens the next segment is that segment's
+    // (except the grid's last plane); the interval is done after its new
+    // plane, or after its closing plane when it has none, and the segment's
+    // first plane is the left plane of its first interval
+    const bool mine = ckind != 1 || cj + 1 < ce || cj + 1 == p.c0 - 1;
+    const bool done = ckind != 1 || cpos(cj + 1, p.c0, n0) - cpos(cj, p.c0, n0) == 1;
+    if (mine) emit(cplane, cv);
+    if (done) {
+      const int t = bp;
+      bp = bn;
+      bn = t;
+    }
+    if (!more) break;
+    if (xkind == 1) {
+      nj = xj;
+      nph = 1;
+    } else {
+      nj = xj + 1;
+      nph = 0;
+    }
+    commit();
+    cplane = xplane, ckind = xkind, cj = xj;
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(RWAVE) k3_coeff_reg_k(const float* __restrict__ u, float* __restrict__ ucoarse,
+                                                        float* __restrict__ g1, uint16_t* __restrict__ sym,
+                                                        int64_t* __restrict__ qside, float* __restrict__ cstream,
+                                                        const double* __restrict__ bins, int level, int R, Lv3<float> p,
+                                                        int seg, int nt1, int nt2, int nseg,
+                                                        const float* __restrict__ d0wl,
+                                                        const float* __restrict__ d0wr) {
+  k3_coeff_reg<MODE>(G3{blockIdx.x, blockIdx.y, blockIdx.z}, G3{gridDim.x, gridDim.y, gridDim.z}, u, ucoarse, g1, sym,
+                     qside, cstream, bins, level, R, p, seg, nt1, nt2, nseg, d0wl, d0wr);
+}
+
 // mass + restriction along dim 0 of g1 (n0 x c1 x c2), then Thomas along dim 0 -> z (c0 x c1 x c2).
 // One lane per (j1, j2) line.  Both sweeps run in groups of SWEEP coarse
 // indices whose loads are all issued before the group's recurrence, so a
@@ -1427,6 +1786,24 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
   const bool fine = l == h.L;
   {
     KernelTimer kt(fine ? "coeff_r21_fine" : "coeff_r21_coarse", st);
+    if constexpr (sizeof(T) == 4) {
+      // register tiles, one wavefront each: coarse intervals of dim 0 per
+      // wavefront so that about 8192 wavefronts run, at most 16, unless tuned
+      const int nt1 = (p.c1 + RCY - 1) / RCY, nt2 = (p.c2 + RCX - 1) / RCX;
+      const uint64_t tiles = (uint64_t)nt1 * nt2;
+      const int guess = (int)std::max<uint64_t>(1, std::min<uint64_t>(16, ((uint64_t)(p.c0 - 1) * tiles + 8191) / 8192));
+      const int seg = std::max(1, tune_get(TUNE_COEFF_SEG, false, p.n0, p.n1, p.n2, guess));
+      const int nseg = (p.c0 - 1 + seg - 1) / seg;
+      const uint64_t nb = tiles * (uint64_t)nseg;
+      if (nb > 0x7fffffffull) fail(MGARD_ERR_SHAPE, "level too large for one launch");
+      const dim3 grid((unsigned)(8 * ((nb + 7) / 8)));
+      if (q)
+        MG_LAUNCH((&k3_coeff_reg<1>), (k3_coeff_reg_k<1>), (RWAVE), (0), (grid), st, u, ucoarse, g1, q->sym, q->qside,
+                  (float*)nullptr, q->bins, l, q->R, p, seg, nt1, nt2, nseg, p.d0.wl, p.d0.wr);
+      else
+        MG_LAUNCH((&k3_coeff_reg<0>), (k3_coeff_reg_k<0>), (RWAVE), (0), (grid), st, u, ucoarse, g1, (uint16_t*)nullptr,
+                  (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, seg, nt1, nt2, nseg, p.d0.wl, p.d0.wr);
+    } else {
     // coarse intervals of dim 0 per block: enough blocks to fill the chip, at most 16
     const uint64_t tiles = (uint64_t)((p.c2 + CX - 1) / CX) * ((p.c1 + CY - 1) / CY);
     const int guess = (int)std::max<uint64_t>(1, std::min<uint64_t>(16, ((uint64_t)(p.c0 - 1) * tiles + 4095) / 4096));
@@ -1437,6 +1814,7 @@ void fused3d_decompose_level(const Hierarchy& h, int l, const T* table, const T*
                          (T*)nullptr, q->bins, l, q->R, p, seg, p.d0.wl, p.d0.wr);
     else
       MG_LAUNCH((&k3_coeff_r21<T, 0>), (k3_coeff_r21_k<T, 0>), (NT), (sizeof(T) == 4 ? 5 : 2), (grid), st, u, ucoarse, g1, (uint16_t*)nullptr, (int64_t*)nullptr, cstream, (const double*)nullptr, l, 0, p, seg, p.d0.wl, p.d0.wr);
+    }
   }
   if (coeff_written) (*coeff_written)();
   const uint64_t lines = (uint64_t)p.c1 * p.c2;
