@@ -551,6 +551,10 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
   RestrictW<float> rw;
   rw.load(min(max(j2, 0), c2 - 1), c2, n2, p.d2);
   const bool rshift = out2 && rw.c == e - 1;  // the last coarse column of an even side sits at e - 1
+  // the whole wavefront on the interior path: no output lane at a grid side
+  const bool interior2 = (!out2 && lane != 0) || (!rshift && rw.l && rw.r && rw.hl[0] && rw.hl[1] && rw.hl[2] &&
+                                                  rw.hr[0] && rw.hr[1] && rw.hr[2]);
+  const bool full2 = __builtin_amdgcn_ballot_w64(interior2) == __builtin_amdgcn_read_exec();
 
   // ---- rows of the tile (the same for every lane)
   uint32_t m_in = 0, m_new = 0;
@@ -639,13 +643,18 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
       cur[r][1] = in && oin ? pre[r][1] : 0.f;
     }
   };
+  // quantization as in quant_store: the symbol is computed and stored by
+  // every lane without a branch; only an escape takes one
   auto qstore = [&](float c, uint64_t pos) {
     if (MODE == 1) {
       const double y = (double)c * inv_b;
       const double a = floor(fabs(y) + 0.5);
       const bool esc = !(a < (double)R);
-      const int qa = (int)(esc ? 0.0 : a);
-      sym[pos] = esc ? (uint16_t)0 : (uint16_t)(y < 0.0 ? R - qa : R + qa);
+      const int qa = (int)fmin(a, (double)R);
+      int sv = y < 0.0 ? R - qa : R + qa;
+      sv = esc ? 0 : sv;
+      asm volatile("" : "+v"(sv));
+      sym[pos] = (uint16_t)sv;
       if (esc) qside[pos] = (int64_t)(y < 0.0 ? -a : a);
     } else {
       cstream[pos] = c;
@@ -654,7 +663,7 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
   int bp = 0, bn = 1;  // slots of the left and right coarse planes' interpolants
   // Coarse plane: in-plane interpolant (dim 2 on the coarse rows, then dim 1)
   // into slot bn, and the coefficients u - interpolant in place of u.
-  auto coarse_coeffs = [&]() {
+  auto coarse_coeffs = [&](float (&cv)[RX][2]) {
     float B[RX][2];
 #pragma unroll
     for (int r = 0; r < RX; ++r) {
@@ -673,6 +682,8 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
     for (int r = 0; r < RX; ++r) {
       Bs[bn][r][0][lane] = B[r][0];
       Bs[bn][r][1][lane] = B[r][1];
+      cv[r][0] = cur[r][0] - B[r][0];
+      cv[r][1] = cur[r][1] - B[r][1];
     }
   };
   // Outputs of the owned nodes of plane f0 (cur: u; cv: coefficients), then
@@ -710,21 +721,41 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
     // mass + restriction along dim 2, every row of the tile: the window of
     // fine columns e - 2 .. e + 2 from this lane and its two neighbours
     float g2[RX];
+    if (full2) {  // every output lane (and lane 0) has both side terms and full stencils
 #pragma unroll
-    for (int r = 0; r < RX; ++r) {
-      const float w0 = lane_prev(cv[r][0]), w1 = lane_prev(cv[r][1]), w4 = lane_next(cv[r][0]);
-      const float w2 = cv[r][0], w3 = cv[r][1];
-      const float gm = rshift ? w0 : w1, g0 = rshift ? w1 : w2, gp = rshift ? w2 : w3;
-      auto M = [&](int k, float a, float b, float c) {
-        float s = rw.b[k] * b;
-        s = rw.hl[k] ? rw.a[k] * a + s : s;
-        s = rw.hr[k] ? s + rw.d[k] * c : s;
-        return s;
-      };
-      float f = M(1, gm, g0, gp);
-      f = rw.l ? rw.rl * M(0, w0, w1, w2) + f : f;
-      f = rw.r ? f + rw.rr * M(2, w2, w3, w4) : f;
-      g2[r] = f;
+      for (int r = 0; r < RX; ++r) {
+        const float w1 = lane_prev(cv[r][1]), w4 = lane_next(cv[r][0]);
+        const float w2 = cv[r][0], w3 = cv[r][1];
+        auto M = [&](int k, float a, float b, float c) {
+          float s = rw.b[k] * b;
+          s = rw.a[k] * a + s;
+          return s + rw.d[k] * c;
+        };
+        // the mass stencil at this lane's e - 1 is the one lane i - 1 takes at
+        // its e + 1: same fine column, weights and values
+        const float m1 = M(1, w1, w2, w3), m2 = M(2, w2, w3, w4);
+        const float m0 = lane_prev(m2);
+        float f = m1;
+        f = rw.rl * m0 + f;
+        g2[r] = f + rw.rr * m2;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RX; ++r) {
+        const float w0 = lane_prev(cv[r][0]), w1 = lane_prev(cv[r][1]), w4 = lane_next(cv[r][0]);
+        const float w2 = cv[r][0], w3 = cv[r][1];
+        const float gm = rshift ? w0 : w1, g0 = rshift ? w1 : w2, gp = rshift ? w2 : w3;
+        auto M = [&](int k, float a, float b, float c) {
+          float s = rw.b[k] * b;
+          s = rw.hl[k] ? rw.a[k] * a + s : s;
+          s = rw.hr[k] ? s + rw.d[k] * c : s;
+          return s;
+        };
+        float f = M(1, gm, g0, gp);
+        f = rw.l ? rw.rl * M(0, w0, w1, w2) + f : f;
+        f = rw.r ? f + rw.rr * M(2, w2, w3, w4) : f;
+        g2[r] = f;
+      }
     }
     // mass + restriction along dim 1 -> g1
     const uint64_t gplane = (uint64_t)f0 * c1;
@@ -774,12 +805,7 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
     if (more) prefetch(xplane);
     float cv[RX][2];
     if (ckind != 2) {
-      coarse_coeffs();
-#pragma unroll
-      for (int r = 0; r < RX; ++r) {
-        cv[r][0] = cur[r][0] - Bs[bn][r][0][lane];
-        cv[r][1] = cur[r][1] - Bs[bn][r][1][lane];
-      }
+      coarse_coeffs(cv);
     } else {
       const float w0l = d0wl[cplane], w0r = d0wr[cplane];
 #pragma unroll
