@@ -503,6 +503,154 @@ __device__ inline bool reg_tile(uint32_t b, int nt1, int nt2, int nseg, int& t1,
   return true;
 }
 
+// Column and row quantities of a register tile, and the mass + restriction
+// of a plane's coefficients along dims 2 and 1 with the arithmetic of
+// RestrictW::apply and restrict_at.  Wr and Wk are the tile's dim-1 weights,
+// staged in LDS by init.
+struct RTile {
+  int n1, n2, c1, c2, J1, J2, F1, F2, lane, e, o, pc, j2;
+  bool ein, oin, inner, own_e, own_o, onew, eshift, out2, rshift, full2;
+  uint64_t colidx;
+  float wl2, wr2;  // interpolation weights of column o (0 unless o is new)
+  RestrictW<float> rw;
+  uint32_t m_in, m_new, k_ok, k_odd, k_l, k_r;
+
+  __device__ void init(const Lv3<float>& p, int tile1, int tile2, float (&Wr)[5][RX], float (&Wk)[2][RCY]) {
+    n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
+    J1 = tile1 * RCY, J2 = tile2 * RCX;
+    F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
+    // columns of this lane
+    lane = threadIdx.x;
+    e = F2 + 2 * lane, o = e + 1;
+    ein = e >= 0 && e < n2;
+    oin = e >= 0 && o < n2;
+    inner = lane >= 1 && lane <= RCX;  // owned fine columns [2 J2, 2 J2 + 124)
+    own_e = inner && ein, own_o = inner && oin;
+    onew = oin && o < n2 - 1;  // o is new along dim 2 (else the last column, coarse)
+    eshift = e == n2 - 1;      // e is the last column: the loaded pair starts one before
+    pc = min(max(e, 0), n2 - 2);
+    const int oc = min(max(o, 0), n2 - 1);
+    const float wl2v = p.d2.wl[oc], wr2v = p.d2.wr[oc];
+    wl2 = onew ? wl2v : 0.f, wr2 = onew ? wr2v : 0.f;
+    colidx = e >= 0 ? (uint64_t)(e >> 1) : 0;  // cidx(e) = e / 2 = o >> 1
+    // restriction along dim 2: this lane's coarse column j2 = J2 - 1 + lane
+    j2 = J2 - 1 + lane;
+    out2 = inner && j2 < c2;
+    rw.load(min(max(j2, 0), c2 - 1), c2, n2, p.d2);
+    rshift = out2 && rw.c == e - 1;  // the last coarse column of an even side sits at e - 1
+    // the whole wavefront on the interior path: every output lane, and lane
+    // 0, away from the grid's sides
+    const bool interior2 = (!out2 && lane != 0) || (!rshift && rw.l && rw.r && rw.hl[0] && rw.hl[1] &&
+                                                    rw.hl[2] && rw.hr[0] && rw.hr[1] && rw.hr[2]);
+    full2 = __builtin_amdgcn_ballot_w64(interior2) == __builtin_amdgcn_read_exec();
+    // rows of the tile (the same for every lane)
+    m_in = 0, m_new = 0;
+#pragma unroll
+    for (int r = 0; r < RX; ++r) {
+      const int f1 = F1 + r;
+      const bool in = f1 >= 0 && f1 < n1;
+      m_in |= in ? 1u << r : 0u;
+      m_new |= in && is_new(f1, n1) ? 1u << r : 0u;
+    }
+    m_in = __builtin_amdgcn_readfirstlane(m_in);
+    m_new = __builtin_amdgcn_readfirstlane(m_new);
+    if (lane < RX) {
+      const int r = lane, f1c = min(max(F1 + r, 0), n1 - 1);
+      const float vl = p.d1.wl[f1c], vr = p.d1.wr[f1c], va = p.d1.ma[f1c], vb = p.d1.mb[f1c], vc = p.d1.mc[f1c];
+      const bool nw = ((m_new >> r) & 1u) != 0u, in = ((m_in >> r) & 1u) != 0u;
+      Wr[0][r] = nw ? vl : 0.f;
+      Wr[1][r] = nw ? vr : 0.f;
+      Wr[2][r] = in ? va : 0.f;
+      Wr[3][r] = in ? vb : 0.f;
+      Wr[4][r] = in ? vc : 0.f;
+    }
+    k_ok = 0, k_odd = 0, k_l = 0, k_r = 0;
+#pragma unroll
+    for (int k = 0; k < RCY; ++k) {
+      const int j1 = J1 + k;
+      const int c = cpos(min(j1, c1 - 1), c1, n1);
+      const bool ok = j1 < c1;
+      k_ok |= ok ? 1u << k : 0u;
+      k_odd |= ok && c != 2 * j1 ? 1u << k : 0u;  // centre at tile row 2k + 1 instead of 2k + 2
+      k_l |= ok && c >= 2 && !(c & 1) ? 1u << k : 0u;
+      k_r |= ok && !(c & 1) && c < n1 - 2 ? 1u << k : 0u;
+    }
+    k_ok = __builtin_amdgcn_readfirstlane(k_ok);
+    k_odd = __builtin_amdgcn_readfirstlane(k_odd);
+    k_l = __builtin_amdgcn_readfirstlane(k_l);
+    k_r = __builtin_amdgcn_readfirstlane(k_r);
+    if (lane < RCY) {
+      const int jc = min(J1 + lane, c1 - 1);
+      Wk[0][lane] = p.d1.rl[jc];
+      Wk[1][lane] = p.d1.rr[jc];
+    }
+  }
+  __device__ static bool bit(uint32_t m, int j) { return ((m >> j) & 1u) != 0u; }
+
+  // mass + restriction along dim 2 of every row of the tile: the window of
+  // fine columns e - 2 .. e + 2 from this lane and its two neighbours
+  __device__ void restrict2(const float (&cv)[RX][2], float (&g2)[RX]) const {
+    if (full2) {  // every output lane (and lane 0) has both side terms and full stencils
+#pragma unroll
+      for (int r = 0; r < RX; ++r) {
+        const float w1 = lane_prev(cv[r][1]), w4 = lane_next(cv[r][0]);
+        const float w2 = cv[r][0], w3 = cv[r][1];
+        auto M = [&](int k, float a, float b, float c) {
+          float s = rw.b[k] * b;
+          s = rw.a[k] * a + s;
+          return s + rw.d[k] * c;
+        };
+        // the mass stencil at this lane's e - 1 is the one lane i - 1 takes at
+        // its e + 1: same fine column, weights and values
+        const float m1 = M(1, w1, w2, w3), m2 = M(2, w2, w3, w4);
+        const float m0 = lane_prev(m2);
+        float f = m1;
+        f = rw.rl * m0 + f;
+        g2[r] = f + rw.rr * m2;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RX; ++r) {
+        const float w0 = lane_prev(cv[r][0]), w1 = lane_prev(cv[r][1]), w4 = lane_next(cv[r][0]);
+        const float w2 = cv[r][0], w3 = cv[r][1];
+        const float gm = rshift ? w0 : w1, g0 = rshift ? w1 : w2, gp = rshift ? w2 : w3;
+        auto M = [&](int k, float a, float b, float c) {
+          float s = rw.b[k] * b;
+          s = rw.hl[k] ? rw.a[k] * a + s : s;
+          s = rw.hr[k] ? s + rw.d[k] * c : s;
+          return s;
+        };
+        float f = M(1, gm, g0, gp);
+        f = rw.l ? rw.rl * M(0, w0, w1, w2) + f : f;
+        f = rw.r ? f + rw.rr * M(2, w2, w3, w4) : f;
+        g2[r] = f;
+      }
+    }
+  }
+  // mass stencil of tile row r (fine row F1 + r inside the grid), on g
+  __device__ float mass1(const float (&Wr)[5][RX], int r, const float (&g)[RX]) const {
+    const int f1 = F1 + r;
+    float s = Wr[3][r] * g[r];
+    if (r > 0) s = f1 > 0 ? Wr[2][r] * g[r - 1] + s : s;
+    if (r + 1 < RX) s = f1 < n1 - 1 ? s + Wr[4][r] * g[r + 1] : s;
+    return s;
+  }
+  // mass + restriction along dim 1: coarse row J1 + k (k_ok bit set)
+  __device__ float restrict1(const float (&Wr)[5][RX], const float (&Wk)[2][RCY], const float (&g2)[RX],
+                             int k) const {
+    float f;
+    if (!bit(k_odd, k)) {
+      const int c = 2 * k + 2;
+      f = mass1(Wr, c, g2);
+      if (bit(k_l, k)) f = Wk[0][k] * mass1(Wr, c - 1, g2) + f;
+      if (bit(k_r, k)) f = f + Wk[1][k] * mass1(Wr, c + 1, g2);
+    } else {
+      f = mass1(Wr, 2 * k + 1, g2);  // an odd centre has neither side term
+    }
+    return f;
+  }
+};
+
 template <int MODE>
 __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float* __restrict__ u,
                                              float* __restrict__ ucoarse, float* __restrict__ g1,
@@ -522,82 +670,22 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
   __shared__ uint64_t S0[8];
   int tile1, tile2, sgi;
   if (!reg_tile(mg_bid.x, nt1, nt2, nseg, tile1, tile2, sgi)) return;
-  const int n0 = p.n0, n1 = p.n1, n2 = p.n2, c1 = p.c1, c2 = p.c2;
-  const int J1 = tile1 * RCY, J2 = tile2 * RCX;
-  const int F1 = 2 * J1 - 2, F2 = 2 * J2 - 2;
+  RTile T;
+  T.init(p, tile1, tile2, Wr, Wk);
+  const int n0 = p.n0, n1 = T.n1, n2 = T.n2, c1 = T.c1, c2 = T.c2;
+  const int J1 = T.J1, F1 = T.F1;
   const int cb = sgi * seg;
   const int ce = min(cb + seg, p.c0 - 1);
   const uint64_t plane = (uint64_t)n1 * n2;
   double inv_b = 0.0;
   if (MODE == 1) inv_b = 1.0 / bins[level];
-
-  // ---- columns of this lane
-  const int lane = threadIdx.x;
-  const int e = F2 + 2 * lane, o = e + 1;
-  const bool ein = e >= 0 && e < n2;
-  const bool oin = e >= 0 && o < n2;
-  const bool inner = lane >= 1 && lane <= RCX;  // owned fine columns [2 J2, 2 J2 + 124)
-  const bool own_e = inner && ein, own_o = inner && oin;
-  const bool onew = oin && o < n2 - 1;  // o is new along dim 2 (else the last column, coarse)
-  const bool eshift = e == n2 - 1;      // e is the last column: the loaded pair starts one before
-  const int pc = min(max(e, 0), n2 - 2);
-  const int oc = min(max(o, 0), n2 - 1);
-  const float wl2v = p.d2.wl[oc], wr2v = p.d2.wr[oc];
-  const float wl2 = onew ? wl2v : 0.f, wr2 = onew ? wr2v : 0.f;
-  const uint64_t colidx = e >= 0 ? (uint64_t)(e >> 1) : 0;  // cidx(e) = e / 2 = o >> 1
-  // restriction along dim 2: this lane's coarse column j2 = J2 - 1 + lane
-  const int j2 = J2 - 1 + lane;
-  const bool out2 = inner && j2 < c2;
-  RestrictW<float> rw;
-  rw.load(min(max(j2, 0), c2 - 1), c2, n2, p.d2);
-  const bool rshift = out2 && rw.c == e - 1;  // the last coarse column of an even side sits at e - 1
-  // the whole wavefront on the interior path: no output lane at a grid side
-  const bool interior2 = (!out2 && lane != 0) || (!rshift && rw.l && rw.r && rw.hl[0] && rw.hl[1] && rw.hl[2] &&
-                                                  rw.hr[0] && rw.hr[1] && rw.hr[2]);
-  const bool full2 = __builtin_amdgcn_ballot_w64(interior2) == __builtin_amdgcn_read_exec();
-
-  // ---- rows of the tile (the same for every lane)
-  uint32_t m_in = 0, m_new = 0;
-#pragma unroll
-  for (int r = 0; r < RX; ++r) {
-    const int f1 = F1 + r;
-    const bool in = f1 >= 0 && f1 < n1;
-    m_in |= in ? 1u << r : 0u;
-    m_new |= in && is_new(f1, n1) ? 1u << r : 0u;
-  }
-  m_in = __builtin_amdgcn_readfirstlane(m_in);
-  m_new = __builtin_amdgcn_readfirstlane(m_new);
+  const int lane = T.lane;
+  const bool ein = T.ein, oin = T.oin, own_e = T.own_e, own_o = T.own_o, onew = T.onew, eshift = T.eshift;
+  const int pc = T.pc;
+  const float wl2 = T.wl2, wr2 = T.wr2;
+  const uint64_t colidx = T.colidx;
+  uint32_t m_in = T.m_in, m_new = T.m_new;
   auto bit = [](uint32_t m, int j) { return ((m >> j) & 1u) != 0u; };
-  if (lane < RX) {
-    const int r = lane, f1c = min(max(F1 + r, 0), n1 - 1);
-    const float vl = p.d1.wl[f1c], vr = p.d1.wr[f1c], va = p.d1.ma[f1c], vb = p.d1.mb[f1c], vc = p.d1.mc[f1c];
-    const bool nw = ((m_new >> r) & 1u) != 0u, in = ((m_in >> r) & 1u) != 0u;
-    Wr[0][r] = nw ? vl : 0.f;
-    Wr[1][r] = nw ? vr : 0.f;
-    Wr[2][r] = in ? va : 0.f;
-    Wr[3][r] = in ? vb : 0.f;
-    Wr[4][r] = in ? vc : 0.f;
-  }
-  uint32_t k_ok = 0, k_odd = 0, k_l = 0, k_r = 0;
-#pragma unroll
-  for (int k = 0; k < RCY; ++k) {
-    const int j1 = J1 + k;
-    const int c = cpos(min(j1, c1 - 1), c1, n1);
-    const bool ok = j1 < c1;
-    k_ok |= ok ? 1u << k : 0u;
-    k_odd |= ok && c != 2 * j1 ? 1u << k : 0u;  // centre at tile row 2k + 1 instead of 2k + 2
-    k_l |= ok && c >= 2 && !(c & 1) ? 1u << k : 0u;
-    k_r |= ok && !(c & 1) && c < n1 - 2 ? 1u << k : 0u;
-  }
-  k_ok = __builtin_amdgcn_readfirstlane(k_ok);
-  k_odd = __builtin_amdgcn_readfirstlane(k_odd);
-  k_l = __builtin_amdgcn_readfirstlane(k_l);
-  k_r = __builtin_amdgcn_readfirstlane(k_r);
-  if (lane < RCY) {
-    const int jc = min(J1 + lane, c1 - 1);
-    Wk[0][lane] = p.d1.rl[jc];
-    Wk[1][lane] = p.d1.rr[jc];
-  }
   {
     // lane = 8 (r - 2) + m: the row part of owned row r in sub-grid m
     const int r = 2 + (lane >> 3), m = lane & 7;
@@ -610,14 +698,6 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
     if (lane < 8) S0[lane] = lane == 0 ? 0 : p.sub[16 + 4 * lane + 1];
   }
   __syncthreads();
-  // mass stencil of tile row r (fine row F1 + r inside the grid), on g
-  auto mass1 = [&](int r, const float* g) -> float {
-    const int f1 = F1 + r;
-    float s = Wr[3][r] * g[r];
-    if (r > 0) s = f1 > 0 ? Wr[2][r] * g[r - 1] + s : s;
-    if (r + 1 < RX) s = f1 < n1 - 1 ? s + Wr[4][r] * g[r + 1] : s;
-    return s;
-  };
 
   // ---- plane registers
   float pre[RX][2];  // next plane, in flight
@@ -718,60 +798,15 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
         if (own_o) qstore(cv[r][1], onew ? rb1 + colidx : rb0 + colidx + 1);
       }
     }
-    // mass + restriction along dim 2, every row of the tile: the window of
-    // fine columns e - 2 .. e + 2 from this lane and its two neighbours
+    // mass + restriction along dims 2 and 1 -> g1
     float g2[RX];
-    if (full2) {  // every output lane (and lane 0) has both side terms and full stencils
-#pragma unroll
-      for (int r = 0; r < RX; ++r) {
-        const float w1 = lane_prev(cv[r][1]), w4 = lane_next(cv[r][0]);
-        const float w2 = cv[r][0], w3 = cv[r][1];
-        auto M = [&](int k, float a, float b, float c) {
-          float s = rw.b[k] * b;
-          s = rw.a[k] * a + s;
-          return s + rw.d[k] * c;
-        };
-        // the mass stencil at this lane's e - 1 is the one lane i - 1 takes at
-        // its e + 1: same fine column, weights and values
-        const float m1 = M(1, w1, w2, w3), m2 = M(2, w2, w3, w4);
-        const float m0 = lane_prev(m2);
-        float f = m1;
-        f = rw.rl * m0 + f;
-        g2[r] = f + rw.rr * m2;
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < RX; ++r) {
-        const float w0 = lane_prev(cv[r][0]), w1 = lane_prev(cv[r][1]), w4 = lane_next(cv[r][0]);
-        const float w2 = cv[r][0], w3 = cv[r][1];
-        const float gm = rshift ? w0 : w1, g0 = rshift ? w1 : w2, gp = rshift ? w2 : w3;
-        auto M = [&](int k, float a, float b, float c) {
-          float s = rw.b[k] * b;
-          s = rw.hl[k] ? rw.a[k] * a + s : s;
-          s = rw.hr[k] ? s + rw.d[k] * c : s;
-          return s;
-        };
-        float f = M(1, gm, g0, gp);
-        f = rw.l ? rw.rl * M(0, w0, w1, w2) + f : f;
-        f = rw.r ? f + rw.rr * M(2, w2, w3, w4) : f;
-        g2[r] = f;
-      }
-    }
-    // mass + restriction along dim 1 -> g1
+    T.restrict2(cv, g2);
     const uint64_t gplane = (uint64_t)f0 * c1;
 #pragma unroll
     for (int k = 0; k < RCY; ++k) {
-      if (!bit(k_ok, k)) continue;
-      float f;
-      if (!bit(k_odd, k)) {
-        const int c = 2 * k + 2;
-        f = mass1(c, g2);
-        if (bit(k_l, k)) f = Wk[0][k] * mass1(c - 1, g2) + f;
-        if (bit(k_r, k)) f = f + Wk[1][k] * mass1(c + 1, g2);
-      } else {
-        f = mass1(2 * k + 1, g2);  // an odd centre has neither side term
-      }
-      if (out2) g1[(gplane + (uint64_t)(J1 + k)) * c2 + j2] = f;
+      if (!bit(T.k_ok, k)) continue;
+      const float f = T.restrict1(Wr, Wk, g2, k);
+      if (T.out2) g1[(gplane + (uint64_t)(J1 + k)) * c2 + T.j2] = f;
     }
   };
 
