@@ -678,11 +678,17 @@ void compress_impl(Hierarchy& h, const double* const* coords, double tol, const 
   Carver cv(ws.base());
   void* scratch = cv.take<char>(need);
   uint8_t* d_hdr = cv.take<uint8_t>(hb.size());
-  MG_HIP(hipMemcpyAsync(d_hdr, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
+  // pinned staging: the header goes up and the sizes come back without a
+  // pageable bounce copy
+  const size_t fin_at = (hb.size() + 255) & ~size_t(255);
+  uint8_t* stage = pinned_staging(fin_at + sizeof(Finale));
+  std::memcpy(stage, hb.data(), hb.size());
+  MG_HIP(hipMemcpyAsync(d_hdr, stage, hb.size(), hipMemcpyHostToDevice, st));
   Finale* fin = compress_enqueue<T>(h, table, y, tol, d_in, d_out, o, scratch, d_hdr, hb.size(), nullptr);
   Finale hf;
-  MG_HIP(hipMemcpyAsync(&hf, fin, sizeof(Finale), hipMemcpyDeviceToHost, st));
+  MG_HIP(hipMemcpyAsync(stage + fin_at, fin, sizeof(Finale), hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
+  std::memcpy(&hf, stage + fin_at, sizeof(Finale));
   if (hf.scalars[2] != 0.0) fail(MGARD_ERR_NONFINITE, "input holds NaN or infinity");
   if (hf.scalars[6] != 0.0) fail(MGARD_ERR_TOL, "tolerance below the rounding reserve or the quantizer's range");
   *out_bytes = hf.total_bytes;
@@ -748,9 +754,11 @@ void decompress_impl(Hierarchy& h, const Parsed& P, const char* d_in, T* d_out, 
   q.bins = reinterpret_cast<const double*>(d_in + P.bins_off);
   q.R = dict / 2;
   recompose<T>(h, table, nullptr, &q, d_out, rscratch, st);
-  uint32_t hs[4];
-  MG_HIP(hipMemcpyAsync(hs, status, 16, hipMemcpyDeviceToHost, st));
+  uint8_t* stage = pinned_staging(16);
+  MG_HIP(hipMemcpyAsync(stage, status, 16, hipMemcpyDeviceToHost, st));
   MG_HIP(hipStreamSynchronize(st));
+  uint32_t hs[4];
+  std::memcpy(hs, stage, 16);
   if (hs[0]) fail(MGARD_ERR_FORMAT, "payload does not decode");
 }
 
@@ -1600,12 +1608,22 @@ mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
   return guard([&] {
     Opts o = read_opts(opts);
     if (!d_in || !d_out) fail(MGARD_ERR_ARG, "null buffer");
+    // One read of the buffer's first kPrefix bytes serves the container
+    // check and, almost always, the whole header.
+    constexpr uint64_t kPrefix = 4096;
+    std::vector<uint8_t> hb;
+    {
+      const uint64_t got = std::min<uint64_t>(in_bytes, kPrefix);
+      uint8_t* stage = pinned_staging(kPrefix);
+      MG_HIP(hipMemcpyAsync(stage, d_in, got, hipMemcpyDeviceToHost, o.st));
+      MG_HIP(hipStreamSynchronize(o.st));
+      hb.assign(stage, stage + got);
+    }
     {
       // a stream in the lossless stage's container: decoded aside first
       uint8_t zh[24] = {0};
       const uint64_t got = std::min<uint64_t>(in_bytes, 24);
-      MG_HIP(hipMemcpyAsync(zh, d_in, got, hipMemcpyDeviceToHost, o.st));
-      MG_HIP(hipStreamSynchronize(o.st));
+      std::memcpy(zh, hb.data(), got);
       uint64_t raw = 0, nch = 0;
       if (got >= 4 && std::memcmp(zh, "MGZS", 4) == 0) {
         if (!zs_parse(zh, in_bytes, &raw, &nch)) fail(MGARD_ERR_FORMAT, "malformed lossless container");
@@ -1617,12 +1635,14 @@ mgard_status mgard_decompress(const void* d_in, uint64_t in_bytes, void* d_out, 
         zs_decode(d_in, in_bytes, raw, nch, plain, status, o.st);
         d_in = plain;
         in_bytes = raw;
+        const uint64_t got2 = std::min<uint64_t>(in_bytes, kPrefix);
+        uint8_t* stage = pinned_staging(kPrefix);
+        MG_HIP(hipMemcpyAsync(stage, d_in, got2, hipMemcpyDeviceToHost, o.st));
+        MG_HIP(hipStreamSynchronize(o.st));
+        hb.assign(stage, stage + got2);
       }
     }
-    std::vector<uint8_t> hb(std::min<uint64_t>(in_bytes, kFixed));
     if (in_bytes < kFixed) fail(MGARD_ERR_FORMAT, "buffer shorter than a header");
-    MG_HIP(hipMemcpyAsync(hb.data(), d_in, kFixed, hipMemcpyDeviceToHost, o.st));
-    MG_HIP(hipStreamSynchronize(o.st));
     Parsed P;
     // the header grows in three parts (fixed, shape, coordinates + bins): read each as it is known
     for (int part = 0; !parse_header(hb.data(), hb.size(), P); ++part) {

@@ -392,6 +392,26 @@ Workspace& workspace() {
   return ws[dev];
 }
 
+uint8_t* pinned_staging(size_t bytes) {
+  thread_local uint8_t* p = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    // only between calls (every call that stages waits for its copies)
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    void* q = nullptr;
+    const size_t n = std::max<size_t>(bytes, 65536);
+    if (hipHostMalloc(&q, n, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(MGARD_ERR_OOM, "pinned staging");
+    }
+    p = static_cast<uint8_t*>(q);
+    cap = n;
+  }
+  return p;
+}
+
 Workspace& aux_workspace() {
   static Workspace ws[64];
   int dev = 0;

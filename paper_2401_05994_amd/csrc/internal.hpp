@@ -127,6 +127,10 @@ Workspace& workspace();
 // A second one, for staging that outlives calls which use the first (the
 // lossless stage's input or output around compression and decompression).
 Workspace& aux_workspace();
+// Pinned host memory of at least `bytes` for the small synchronous copies of
+// a call (headers, sizes, status words), per host thread, kept for the
+// process's life; its contents do not survive the next call on the thread.
+uint8_t* pinned_staging(size_t bytes);
 
 struct Carver {
   char* p;
