@@ -1398,16 +1398,12 @@ __global__ void __launch_bounds__(NT) k3_interp_add(T* __restrict__ out, const T
     const uint64_t o = obs[r] + fa;
     uint64_t pa = 0, pb = 0, px = 0;
     if (side) positions(r, pa, pb, px);
-    // column fa: coarse along dim 2
-    if (!e0 && !e1)
-      out[o] = Cs[0][kb][q];
-    else
-      out[o] = coef(sa[r], ca[r], pa, side) + PI(Va);
-    // column fb: new along dim 2, or the last (coarse) column of an even side
-    if (!nb && !e0 && !e1)
-      out[o + 1] = Cs[0][kb][q + 1];
-    else
-      out[o + 1] = coef(sb[r], cb[r], pb, side) + PI(Vb);
+    // column fa: coarse along dim 2; column fb: new along dim 2, or the last
+    // (coarse) column of an even side; the pair is one 2-element store
+    T pair[2];
+    pair[0] = (!e0 && !e1) ? Cs[0][kb][q] : coef(sa[r], ca[r], pa, side) + PI(Va);
+    pair[1] = (!nb && !e0 && !e1) ? Cs[0][kb][q + 1] : coef(sb[r], cb[r], pb, side) + PI(Vb);
+    __builtin_memcpy(out + o, pair, sizeof(pair));
     // the last column of an odd side (coarse along dim 2)
     if (extra) {
       if (!e0 && !e1)
