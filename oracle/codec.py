@@ -8,7 +8,7 @@ Sec. 3, first listing); compression ratio is input bytes over output bytes.
 Wire format (little-endian; offsets in bytes):
 
     0  'MGHP'             magic
-    4  u16 version = 3
+    4  u16 version = 2
     6  u8  dtype           0 = float32, 1 = float64
     7  u8  ndim            1..4
     8  u8  eb              0 = absolute, 1 = relative
@@ -26,9 +26,7 @@ Wire format (little-endian; offsets in bytes):
    64  u64 n_outliers
    72  u64 payload_words
    80  u8  norm            0 = L-infinity, 1 = s-norm with smoothness s
-   81  u8  zero
-   82  u16 sub_symbols     symbols per sub-chunk run (256)
-   84  u8[4] zero
+   81  u8[7] zero
    88  f64 s
    96  u64 shape[ndim]
        f64 coords          for each flagged dimension, its n_d coordinates
@@ -38,9 +36,6 @@ Wire format (little-endian; offsets in bytes):
        u8  code_len[dict_size]
        u32 chunk_bits[n_chunks]
        u32 chunk_esc[n_chunks]     escape symbols per chunk
-       u16 sub_bits[n_chunks * (ceil(chunk/sub) - 1)]  bits of each run but a
-                                   chunk's last (huffman.sub_chunk_bits),
-                                   one zero u16 after an odd count
        u32 payload[payload_words]
        u32 escapes[]               per level, ceil(count * width / 32) words
 """
@@ -60,9 +55,8 @@ from . import transform as X
 from .grid import Hierarchy
 
 MAGIC = b"MGHP"
-VERSION = 3
+VERSION = 2
 FIXED = 96
-SUB = 256  # symbols per sub-chunk run
 NORM_LINF, NORM_S = 0, 1
 ALLOC_PLAIN, ALLOC_LEARNED, ALLOC_COUNT = 0, 1, 2
 
@@ -86,7 +80,6 @@ class Parts:
     codes: np.ndarray
     chunk_bits: list
     chunk_esc: list
-    sub_bits: list
     words: list
     esc_counts: list
     esc_widths: list
@@ -137,11 +130,10 @@ def compress_parts(u, tol, rel=True, coords=None, dict_size=8192, chunk=1024, bi
     lengths = H.code_lengths(hist)
     codes = H.canonical_codes(lengths)
     cbits, words = H.encode(sym, lengths, codes, chunk)
-    sbits = H.sub_chunk_bits(sym, lengths, len(sym), chunk, SUB)
     esc = [int(np.count_nonzero(sym[k:k + chunk] == 0)) for k in range(0, len(sym), chunk)]
     ecount, ewidth, ewords = Q.pack_escapes(q, hier, dict_size)
     return Parts(hier, T, maxabs, tau, tau_eff, list(map(float, bins)), stream, q, sym, outl, hist,
-                 lengths, codes, cbits, esc, sbits, words, ecount, ewidth, ewords)
+                 lengths, codes, cbits, esc, words, ecount, ewidth, ewords)
 
 
 def serialize(p: Parts, tol, rel, coords, dict_size, chunk, alloc_code=ALLOC_PLAIN, fallback=0, norm=NORM_LINF,
@@ -157,11 +149,10 @@ def serialize(p: Parts, tol, rel, coords, dict_size, chunk, alloc_code=ALLOC_PLA
                 coord_blob += np.asarray(coords[d], dtype="<f8").tobytes()
     n = len(p.symbols)
     nch = len(p.chunk_bits)
-    head = struct.pack("<4sHBBBBBBIIIdddQQQQBxH4xd", MAGIC, VERSION, 0 if p.T is np.float32 else 1, D,
+    head = struct.pack("<4sHBBBBBBIIIdddQQQQB7xd", MAGIC, VERSION, 0 if p.T is np.float32 else 1, D,
                        1 if rel else 0, alloc_code, flags, fallback, hier.L, dict_size, chunk,
                        float(tol), float(p.tau_abs), float(p.maxabs), n, nch, len(p.outliers),
-                       len(p.words), norm, SUB, float(s))
-    sub_tab = list(p.sub_bits) + [0] * (len(p.sub_bits) & 1)
+                       len(p.words), norm, float(s))
     assert len(head) == FIXED
     out = [head, np.asarray(hier.shape, dtype="<u8").tobytes(), coord_blob,
            np.asarray(p.bins, dtype="<f8").tobytes(),
@@ -170,7 +161,6 @@ def serialize(p: Parts, tol, rel, coords, dict_size, chunk, alloc_code=ALLOC_PLA
            np.asarray(p.lengths, dtype=np.uint8).tobytes(),
            np.asarray(p.chunk_bits, dtype="<u4").tobytes(),
            np.asarray(p.chunk_esc, dtype="<u4").tobytes(),
-           np.asarray(sub_tab, dtype="<u2").tobytes(),
            np.asarray(p.words, dtype="<u4").tobytes(),
            np.asarray(p.esc_words, dtype="<u4").tobytes()]
     return b"".join(out)
@@ -217,8 +207,8 @@ def parse(buf: bytes) -> Header:
     if len(buf) < FIXED or buf[:4] != MAGIC:
         raise ValueError("not a compressed buffer")
     (_, ver, dt, D, rel, al, flags, fb, L, dsz, ch, tol, tau, mx, n, nch, nout,
-     nw, norm, sub, s) = struct.unpack_from("<4sHBBBBBBIIIdddQQQQBxH4xd", buf, 0)
-    if ver != VERSION or dt > 1 or not 1 <= D <= 4 or sub != SUB:
+     nw, norm, s) = struct.unpack_from("<4sHBBBBBBIIIdddQQQQB7xd", buf, 0)
+    if ver != VERSION or dt > 1 or not 1 <= D <= 4:
         raise ValueError("unsupported header")
     pos = FIXED
     shape = tuple(int(v) for v in np.frombuffer(buf, "<u8", D, pos))
@@ -242,9 +232,6 @@ def parse(buf: bytes) -> Header:
     pos += 4 * nch
     off["chunk_esc"] = pos
     pos += 4 * nch
-    off["sub_bits"] = pos
-    nsub = nch * (-(-ch // SUB) - 1)
-    pos += 2 * (nsub + (nsub & 1))
     off["payload"] = pos
     pos += 4 * nw
     off["escapes"] = pos
@@ -262,12 +249,11 @@ def decompress(buf: bytes):
     lengths = np.frombuffer(buf, np.uint8, h.dict_size, h.offsets["code_len"]).astype(np.int64)
     codes = H.canonical_codes(lengths)
     cbits = [int(v) for v in np.frombuffer(buf, "<u4", h.n_chunks, h.offsets["chunk_bits"])]
-    sbits = [int(v) for v in np.frombuffer(buf, "<u2", h.n_chunks * (-(-h.chunk // SUB) - 1), h.offsets["sub_bits"])]
     words = [int(v) for v in np.frombuffer(buf, "<u4", h.payload_words, h.offsets["payload"])]
     nesc = sum(Q.escape_words(h.esc_counts, h.esc_widths))
     outl = Q.unpack_escapes(np.frombuffer(buf, "<u4", nesc, h.offsets["escapes"]), h.esc_counts, h.esc_widths,
                             h.dict_size)
-    sym = H.decode(words, cbits, lengths, codes, h.n, h.chunk, sbits, SUB)
+    sym = H.decode(words, cbits, lengths, codes, h.n, h.chunk)
     q = Q.from_symbols(sym, outl, h.dict_size)
     stream = Q.dequantize_stream(q, hier, h.bins, h.dtype)
     coarsest, cbars = Q.from_stream(stream, hier, h.dtype)

@@ -15,12 +15,7 @@ following rules are chosen to make the output reproducible bit for bit:
 * packing: the stream is cut into chunks of ``chunk`` symbols; each chunk's
   codes are concatenated most-significant-bit first into 32-bit words (first
   bit at bit 31), the chunk starts word-aligned and ends zero-padded, and its
-  bit count is recorded.  The payload is the chunks in order;
-* sub-chunks: each chunk is also cut into runs of ``sub`` symbols (the last
-  run of a short chunk may hold fewer, or none); for every run but a chunk's
-  last, the number of bits of its codes is recorded, so that a decoder can
-  start every run at its own bit offset (the sum of the recorded lengths of
-  the runs before it) instead of walking the chunk from its start.
+  bit count is recorded.  The payload is the chunks in order.
 
 Written with plain Python loops: meant for the small inputs of the tests.
 """
@@ -114,31 +109,9 @@ def encode(symbols, lengths, codes, chunk: int):
     return chunk_bits, words
 
 
-def sub_chunk_bits(symbols, lengths, n: int, chunk: int, sub: int):
-    """The sub-chunk table: for chunk k and run j in 0 .. chunk/sub - 2, the
-    summed code lengths of the chunk's symbols j*sub .. (j+1)*sub - 1 (those
-    that exist), in that order."""
-    lengths = [int(v) for v in lengths]
-    symbols = [int(v) for v in symbols]
-    runs = -(-chunk // sub)
-    table = []
-    for start in range(0, n, chunk):
-        count = min(chunk, n - start)
-        for j in range(runs - 1):
-            lo, hi = min(j * sub, count), min((j + 1) * sub, count)
-            table.append(sum(lengths[s] for s in symbols[start + lo:start + hi]))
-    return table
-
-
-def decode(words, chunk_bits, lengths, codes, n: int, chunk: int, sub_bits=None, sub: int = 0):
-    """Without sub_bits each chunk is walked from its first bit.  With the
-    sub-chunk table, every run of `sub` symbols starts at its own offset and
-    must end exactly where the next one starts (the last where the chunk's
-    bit count ends)."""
+def decode(words, chunk_bits, lengths, codes, n: int, chunk: int):
     lengths = [int(v) for v in lengths]
     table = {(int(lengths[s]), int(codes[s])): s for s in range(len(lengths)) if lengths[s] > 0}
-    runs = -(-chunk // sub) if sub_bits is not None else 1
-    run_len = sub if sub_bits is not None else chunk
     out = []
     w0 = 0
     for k, nbits in enumerate(chunk_bits):
@@ -148,34 +121,22 @@ def decode(words, chunk_bits, lengths, codes, n: int, chunk: int, sub_bits=None,
         for w in words[w0:w0 + nwords]:
             bits = (bits << 32) | int(w)
         total = 32 * nwords
-        # run boundaries within the chunk, in bits
-        ends = []
-        acc = 0
-        for j in range(runs - 1):
-            acc += int(sub_bits[k * (runs - 1) + j])
-            ends.append(acc)
-        ends.append(int(nbits))
-        start = 0
-        for j in range(runs):
-            if not start <= ends[j] <= int(nbits):
-                raise ValueError("run bit counts exceed the chunk's")
-            pos = start
-            for _ in range(max(0, min(run_len, count - j * run_len))):
-                code = 0
-                L = 0
-                while True:
-                    if pos >= ends[j]:
-                        raise ValueError("run payload ends inside a code")
-                    bit = (bits >> (total - 1 - pos)) & 1
-                    pos += 1
-                    code = (code << 1) | bit
-                    L += 1
-                    s = table.get((L, code))
-                    if s is not None:
-                        out.append(s)
-                        break
-            if pos != ends[j]:
-                raise ValueError("run bit count does not match its codes")
-            start = ends[j]
+        pos = 0
+        for _ in range(count):
+            code = 0
+            L = 0
+            while True:
+                if pos >= nbits:
+                    raise ValueError("chunk payload ends inside a code")
+                bit = (bits >> (total - 1 - pos)) & 1
+                pos += 1
+                code = (code << 1) | bit
+                L += 1
+                s = table.get((L, code))
+                if s is not None:
+                    out.append(s)
+                    break
+        if pos != nbits:
+            raise ValueError("chunk bit count does not match its codes")
         w0 += nwords
     return np.asarray(out, dtype=np.int64)

@@ -345,65 +345,6 @@ def test_huffman_optimal_kraft_roundtrip(seed):
     assert np.array_equal(out, sym)
 
 
-
-def test_sub_chunk_table_hand_example():
-    # lengths 1, 2, 2 for symbols 1, 2, 3: canonical codes 0, 10, 11.  Chunk
-    # 0 holds 256 x symbol 1 (256 bits), 256 x symbol 2 (512 bits) and 256 x
-    # symbol 3 (512 bits); chunk 1 holds 300 x symbol 2: runs of 256 and 44
-    # symbols (512 and 88 bits), its third run is empty.
-    L = np.array([0, 1, 2, 2])
-    codes = H.canonical_codes(L)
-    assert [int(c) for c in codes[1:]] == [0, 2, 3]
-    sym = [1] * 256 + [2] * 256 + [3] * 256 + [2] * 300
-    bits, words = H.encode(sym, L, codes, 768)
-    assert bits == [1280, 600]
-    tab = H.sub_chunk_bits(sym, L, len(sym), 768, 256)
-    assert tab == [256, 512, 512, 88]
-    out = H.decode(words, bits, L, codes, len(sym), 768, tab, 256)
-    assert list(out) == sym
-
-
-@pytest.mark.parametrize("chunk,n", [(768, 5000), (1024, 4097), (512, 1500), (256, 999), (1024, 100)])
-def test_sub_chunk_runs_decode_from_their_own_offsets(chunk, n):
-    rng = np.random.default_rng(chunk + n)
-    sym = np.minimum(rng.geometric(0.05, size=n), 1023).astype(np.int64)
-    L = H.code_lengths(H.histogram(sym, 1024))
-    codes = H.canonical_codes(L)
-    bits, words = H.encode(sym, L, codes, chunk)
-    tab = H.sub_chunk_bits(sym, L, n, chunk, 256)
-    runs = -(-chunk // 256)
-    assert len(tab) == len(bits) * (runs - 1)
-    # each chunk's runs (recorded ones plus the implied last) add up to its bits
-    for k, b in enumerate(bits):
-        assert sum(tab[k * (runs - 1):(k + 1) * (runs - 1)]) <= b
-    assert np.array_equal(H.decode(words, bits, L, codes, n, chunk, tab, 256), sym)
-    assert np.array_equal(H.decode(words, bits, L, codes, n, chunk), sym)
-    # an entry one bit off makes a run end inside a code or away from the next run
-    if tab:
-        for k in (0, len(tab) - 1):
-            for d in (-1, 1):
-                bad = list(tab)
-                bad[k] += d
-                with pytest.raises(ValueError):
-                    H.decode(words, bits, L, codes, n, chunk, bad, 256)
-
-
-def test_format_sub_table_padding_and_alignment():
-    rng = np.random.default_rng(4)
-    u = rng.standard_normal((7, 9, 11))
-    # chunk 512: one entry per chunk; 693 symbols make 2 chunks (even), 1 chunk below
-    for shape, nch in [((7, 9, 11), 2), ((5, 7, 11), 1)]:
-        v = u[:shape[0], :shape[1], :shape[2]]
-        buf = codec.compress(v, 1e-3, dict_size=1024, chunk=512)
-        hd = codec.parse(buf)
-        assert hd.n_chunks == nch
-        assert hd.offsets["payload"] - hd.offsets["sub_bits"] == 4 * ((nch + 1) // 2)
-        assert hd.offsets["payload"] % 4 == 0
-        assert np.array_equal(codec.decompress(buf), codec.decompress(buf))
-        got = np.frombuffer(buf, "<u2", nch, hd.offsets["sub_bits"])
-        p = codec.compress_parts(v, 1e-3, dict_size=1024, chunk=512)
-        assert list(got) == p.sub_bits
-
 # -------------------------------------------------------------- end to end
 @pytest.mark.parametrize("tol", [1e-2, 1e-3, 1e-4])
 def test_c1_bound_and_roundtrip(tol):
