@@ -1119,7 +1119,7 @@ constexpr int FASTN = 33;
 // decides); bit 7 set: they meet three or more (comparisons from j on decide);
 // neither: every such window has length j.
 constexpr int LUT_BITS = 12;
-constexpr uint32_t LUT_TWO = 0x40, LUT_MANY = 0x80;
+constexpr uint32_t LUT_SPLIT = 1u << 22;
 
 struct DecTables {
   uint64_t first[MAXLEN + 1];
@@ -1129,7 +1129,11 @@ struct DecTables {
   uint32_t minlen, maxlen, bad, used;
   uint32_t nfast, pad;
   uint32_t flen[FASTN], flim[FASTN], fdelta[FASTN];
-  uint8_t lut[1 << LUT_BITS];
+  // entry v: bits 0-15 the symbol-table index of the first code in the
+  // windows starting with v, bits 16-21 their length (0: no code starts with
+  // these bits), when the windows meet one length; else bit 22 set and bits
+  // 24-29 the first length index j whose limit decides (flim, fld).
+  uint32_t lut[1 << LUT_BITS];
 };
 
 __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restrict__ len, int dict, DecTables* tab,
@@ -1141,6 +1145,8 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
   __shared__ uint32_t offs[MAXLEN + 1];
   __shared__ uint32_t bad;
   __shared__ uint32_t sflim[FASTN], snfast;
+  __shared__ uint32_t sflen[FASTN];
+  __shared__ uint64_t sfirst[MAXLEN + 1];
   const int t = threadIdx.x, nt = blockDim.x;
   if (t == 0) bad = 0;
   __syncthreads();
@@ -1206,7 +1212,11 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
       tab->fdelta[j] = 0xffffffffu;
     }
     tab->nfast = fast ? nd : 0;
-    for (int j = 0; j < FASTN; ++j) sflim[j] = tab->flim[j];
+    for (int j = 0; j < FASTN; ++j) {
+      sflim[j] = tab->flim[j];
+      sflen[j] = tab->flen[j];
+    }
+    for (int b = 0; b <= MAXLEN; ++b) sfirst[b] = tab->first[b];
     snfast = fast ? nd : 0;
   }
   __syncthreads();
@@ -1216,9 +1226,12 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
   }
   // windows starting with prefix v run from v << (32 - LUT_BITS) to that plus
   // 2^(32 - LUT_BITS) - 1; the index of a window's length is the number of
-  // limits below it, between its value at the two ends
+  // limits below it, between its value at the two ends.  When both ends give
+  // the same length L, every window's code is its top L bits, the first of
+  // them v's bits (L <= LUT_BITS: v's top L bits; else v followed by zeros),
+  // so the symbol-table index of the first is offset[L] + that - first[L].
   for (int v = t; v < (1 << LUT_BITS); v += nt) {
-    uint32_t e = 0;
+    uint32_t e = 0xffffu;  // no code: length 0, an index past every table
     if (snfast) {
       const uint32_t lo = (uint32_t)v << (32 - LUT_BITS), hi = lo | ((1u << (32 - LUT_BITS)) - 1u);
       uint32_t clo = 0, chi = 0;
@@ -1226,9 +1239,17 @@ __global__ void __launch_bounds__(1024) k_decode_tables(const uint8_t* __restric
         clo += lo > sflim[j] ? 1u : 0u;
         chi += hi > sflim[j] ? 1u : 0u;
       }
-      e = clo | (chi == clo ? 0u : chi == clo + 1 ? LUT_TWO : LUT_MANY);
+      if (chi == clo) {
+        const uint32_t L = sflen[clo];
+        if (L) {
+          const uint64_t c0 = L <= (uint32_t)LUT_BITS ? ((uint64_t)v >> (LUT_BITS - L)) : ((uint64_t)v << (L - LUT_BITS));
+          e = (offs[L] + (uint32_t)(c0 - sfirst[L])) | (L << 16);
+        }
+      } else {
+        e = LUT_SPLIT | (clo << 24) | 0xffffu;
+      }
     }
-    tab->lut[v] = (uint8_t)e;
+    tab->lut[v] = e;
   }
 }
 
@@ -1277,7 +1298,7 @@ __global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payl
   __shared__ uint32_t offs[MAXLEN + 1];
   __shared__ uint16_t sorted[MAXDICT];
   __shared__ uint32_t ring[BT * RING_STRIDE];
-  __shared__ uint32_t lut_w[(1 << LUT_BITS) / 4];  // the prefix table, four entries per word
+  __shared__ uint32_t lut_s[1 << LUT_BITS];  // the prefix table
   __shared__ uint2 fld_s[FASTN];                   // (fdelta, flen) of each distinct length
   __shared__ uint32_t flim_s[FASTN];
   const uint32_t used = min(tab->used, (uint32_t)dict);
@@ -1287,8 +1308,7 @@ __global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payl
     offs[b] = tab->offset[b];
   }
   {
-    const uint32_t* lw = reinterpret_cast<const uint32_t*>(tab->lut);
-    for (int i = threadIdx.x; i < (1 << LUT_BITS) / 4; i += blockDim.x) lut_w[i] = lw[i];
+    for (int i = threadIdx.x; i < (1 << LUT_BITS); i += blockDim.x) lut_s[i] = tab->lut[i];
     if (threadIdx.x < FASTN) {
       fld_s[threadIdx.x] = make_uint2(tab->fdelta[threadIdx.x], tab->flen[threadIdx.x]);
       flim_s[threadIdx.x] = tab->flim[threadIdx.x];
@@ -1432,23 +1452,22 @@ __global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payl
         nextw = myring[rd & (RING - 1)];
       }
       const uint32_t top = (uint32_t)(buf >> 32);
-      // the length from the prefix table; comparisons with the limits only
-      // for windows whose prefix meets two or more lengths (rare)
-      const uint32_t pv = top >> (32 - LUT_BITS);
-      const uint32_t e = (lut_w[pv >> 2] >> (8 * (pv & 3))) & 0xffu;
-      uint32_t j = e & 63u;
-      uint2 ld = fld_s[j];  // issued before the rare case is resolved
-      if (e & (LUT_TWO | LUT_MANY)) {
-        if (e & LUT_TWO)
-          j += top > flim_s[j] ? 1u : 0u;
-        else
-          while (top > flim_s[j]) ++j;  // flim_s[nfast] = 2^32 - 1 ends it
-        ld = fld_s[j];
+      // length and symbol index from the prefix table: the window's first
+      // index plus the code's bits past the prefix (none when L <= LUT_BITS:
+      // the shift is then 32 or more); comparisons with the limits only for
+      // windows that meet two or more lengths (rare)
+      const uint32_t e = lut_s[top >> (32 - LUT_BITS)];
+      uint32_t L = (e >> 16) & 63u;
+      uint32_t idx = (e & 0xffffu) + (uint32_t)((uint64_t)(top << LUT_BITS) >> (32 + LUT_BITS - L));
+      if (e & LUT_SPLIT) {
+        uint32_t jj = e >> 24;
+        while (top > flim_s[jj]) ++jj;  // flim_s[nfast] = 2^32 - 1 ends it
+        const uint2 ld = fld_s[jj];
+        L = ld.y;
+        // L = 0 (no code of the table starts with these bits) leaves idx =
+        // fdelta of the end entry, 2^32 - 1
+        idx = ld.x + (uint32_t)((uint64_t)top >> (32 - L));
       }
-      const uint32_t L = ld.y, d = ld.x;
-      // L = 0 (no code of the table starts with these bits) leaves idx =
-      // fdelta of the end entry, 2^32 - 1: no branch, no wait on L
-      const uint32_t idx = d + (uint32_t)((uint64_t)top >> (32 - L));
       buf <<= L;
       have -= (int)L;
       cons += L;
