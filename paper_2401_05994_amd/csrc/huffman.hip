@@ -1383,7 +1383,9 @@ __global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payl
     uint64_t buf = 0;  // left-aligned bits
     int have = 0;
     uint64_t pack = 0, prev = 0;
-    uint32_t cons = 0, bad = 0;  // bits consumed; malformed-input flag, acted on every 8 symbols
+    // bits consumed and the largest symbol-table index met: malformed input
+    // when either exceeds its bound, acted on every 8 symbols (both only grow)
+    uint32_t cons = 0, imax = 0;
     const uint32_t nb32 = (uint32_t)nbits;
     // Symbol i is packed in iteration i + 1, after the next lookup has been
     // issued, so no iteration waits for its own LDS read; the bit buffer only
@@ -1395,7 +1397,7 @@ __global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payl
       if ((j & 7) == 7) {
         const uint4 v = make_uint4((uint32_t)prev, (uint32_t)(prev >> 32), (uint32_t)pack, (uint32_t)(pack >> 32));
         *reinterpret_cast<uint4*>(sym + beg + j - 7) = v;
-        if (bad) {
+        if (imax >= used || cons > nb32) {
           atomicOr(status, 1u);
           return false;
         }
@@ -1471,9 +1473,8 @@ __global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payl
       buf <<= L;
       have -= (int)L;
       cons += L;
-      const bool ok = idx < used;
-      bad |= (!ok || cons > nb32) ? 1u : 0u;
-      s = sorted[ok ? idx : 0];
+      imax = max(imax, idx);  // checked with the bit count every 8 symbols
+      s = sorted[min(idx, used - 1u)];
     };
     auto pack_in = [&](uint32_t s) { pack = (pack >> 16) | ((uint64_t)s << 48); };
     // Eight symbols per trip, alternating between two registers, so a lookup
@@ -1512,7 +1513,7 @@ __global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payl
       held = true;
     }
     if (held && !put(cntk - 1, sp)) return;
-    if (bad) {
+    if (imax >= used || cons > nb32) {
       atomicOr(status, 1u);
       return;
     }
