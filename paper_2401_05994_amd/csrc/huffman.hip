@@ -1382,37 +1382,33 @@ __global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payl
     uint32_t nextw = myring[0];
     uint64_t buf = 0;  // left-aligned bits
     int have = 0;
-    uint64_t pack = 0, prev = 0;
     // bits consumed and the largest symbol-table index met: malformed input
     // when either exceeds its bound, acted on every 8 symbols (both only grow)
     uint32_t cons = 0, imax = 0;
     const uint32_t nb32 = (uint32_t)nbits;
-    // Symbol i is packed in iteration i + 1, after the next lookup has been
-    // issued, so no iteration waits for its own LDS read; the bit buffer only
-    // depends on the code length.
-    uint32_t sp = 0;
-    auto put = [&](uint64_t j, uint32_t s) -> bool {
-      pack = (pack >> 16) | ((uint64_t)s << 48);
-      if ((j & 7) == 3) prev = pack;
-      if ((j & 7) == 7) {
-        const uint4 v = make_uint4((uint32_t)prev, (uint32_t)(prev >> 32), (uint32_t)pack, (uint32_t)(pack >> 32));
-        *reinterpret_cast<uint4*>(sym + beg + j - 7) = v;
-        if (imax >= used || cons > nb32) {
-          atomicOr(status, 1u);
-          return false;
-        }
-        // escape symbols (value 0) among the eight, in order
-        const uint64_t m = 0x0001000100010001ull, h = 0x8000800080008000ull;
-        if (escapes && (((prev - m) & ~prev & h) | ((pack - m) & ~pack & h))) {
-          for (int k = 0; k < 8; ++k) {
-            const uint16_t x = (uint16_t)((k < 4 ? prev : pack) >> (16 * (k & 3)));
-            if (x) continue;
-            if (eo >= eo_end) {
-              atomicOr(status, 1u);
-              return false;
-            }
-            epos[eo++] = beg + j - 7 + k;
+    // A trip's eight symbols go to eight registers; two symbols make a word
+    // two steps after the second one's lookup was issued, and the trip's four
+    // words are stored at the start of the next trip, so no step waits for
+    // its own lookup.  Escapes and malformed input are checked at the stores.
+    auto store8 = [&](uint64_t j0, uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3) -> bool {
+      *reinterpret_cast<uint4*>(sym + beg + j0) = make_uint4(x0, x1, x2, x3);
+      if (imax >= used || cons > nb32) {
+        atomicOr(status, 1u);
+        return false;
+      }
+      // escape symbols (value 0) among the eight, in order; the test flags
+      // every zero (and at times a neighbour of one)
+      const uint32_t m = 0x00010001u, h = 0x80008000u;
+      if (escapes && (((x0 - m) & ~x0 & h) | ((x1 - m) & ~x1 & h) | ((x2 - m) & ~x2 & h) | ((x3 - m) & ~x3 & h))) {
+        const uint32_t xs[4] = {x0, x1, x2, x3};
+        for (int k = 0; k < 8; ++k) {
+          const uint16_t x = (uint16_t)(xs[k >> 1] >> (16 * (k & 1)));
+          if (x) continue;
+          if (eo >= eo_end) {
+            atomicOr(status, 1u);
+            return false;
           }
+          epos[eo++] = beg + j0 + k;
         }
       }
       return true;
@@ -1476,63 +1472,44 @@ __global__ void __launch_bounds__(BT) k_decode(const uint32_t* __restrict__ payl
       imax = max(imax, idx);  // checked with the bit count every 8 symbols
       s = sorted[min(idx, used - 1u)];
     };
-    auto pack_in = [&](uint32_t s) { pack = (pack >> 16) | ((uint64_t)s << 48); };
-    // Eight symbols per trip, alternating between two registers, so a lookup
-    // is consumed one step after it is issued without copying a pending load.
-    uint32_t s0 = 0, s1 = 0;
+    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0;
+    uint32_t w0 = 0, w1 = 0, w2 = 0;  // the trip's first three words
     uint64_t i0 = 0;
     for (; i0 + 8 <= cntk; i0 += 8) {
-      step(s0);
-      if (i0 > 0 && !put(i0 - 1, s1)) return;
-      step(s1);
-      pack_in(s0);
-      step(s0);
-      pack_in(s1);
-      step(s1);
-      pack_in(s0);
+      step(a0);
+      if (i0 > 0 && !store8(i0 - 8, w0, w1, w2, a6 | (a7 << 16))) return;
+      step(a1);
+      step(a2);
+      w0 = a0 | (a1 << 16);
+      step(a3);
       refill();
-      step(s0);
-      pack_in(s1);
-      prev = pack;
-      step(s1);
-      pack_in(s0);
-      step(s0);
-      pack_in(s1);
-      step(s1);
-      pack_in(s0);
+      step(a4);
+      w1 = a2 | (a3 << 16);
+      step(a5);
+      step(a6);
+      w2 = a4 | (a5 << 16);
+      step(a7);
     }
+    if (i0 > 0 && !store8(i0 - 8, w0, w1, w2, a6 | (a7 << 16))) return;
     // fewer than eight left (the stream's last chunk): one symbol at a time
-    bool held = i0 > 0;
-    sp = s1;
     for (uint64_t i = i0; i < cntk; ++i) {
       if ((i & 7) == 4) refill();
-      uint32_t s;
-      step(s);
-      if (held && !put(i - 1, sp)) return;
-      sp = s;
-      held = true;
+      uint32_t t;
+      step(t);
+      sym[beg + i] = (uint16_t)t;
+      if (t == 0 && escapes) {
+        if (eo >= eo_end) {
+          atomicOr(status, 1u);
+          return;
+        }
+        epos[eo++] = beg + i;
+      }
     }
-    if (held && !put(cntk - 1, sp)) return;
     if (imax >= used || cons > nb32) {
       atomicOr(status, 1u);
       return;
     }
     consumed = cons;
-    // the last cntk % 8 symbols: pack holds the newest four (newest in the top
-    // 16 bits), prev the group's first four (first in the low 16 bits)
-    const int tail = (int)(cntk & 7);
-    for (int j = 0; j < tail; ++j) {
-      const int age = tail - 1 - j;  // symbols decoded after this one
-      const uint16_t v = age < 4 ? (uint16_t)(pack >> (48 - 16 * age)) : (uint16_t)(prev >> (16 * j));
-      sym[beg + (cntk & ~7ull) + j] = v;
-      if (v == 0 && escapes) {
-        if (eo >= eo_end) {
-          atomicOr(status, 1u);
-          return;
-        }
-        epos[eo++] = beg + (cntk & ~7ull) + j;
-      }
-    }
   } else {
     const int minlen = (int)tab->minlen, maxlen = (int)tab->maxlen;
     const uint32_t* src = payload + w0;
