@@ -277,6 +277,54 @@ def test_huffman_many_lengths_bitexact(lib, top, draw, chunk):
     assert np.array_equal(lib.u16(dec).astype(np.int64), sym)
 
 
+def _prefix_case(name):
+    """Complete prefix codes at the edges of the decoder's 12-bit prefix table."""
+    if name == "one-symbol":  # a single code, one bit long
+        lens = np.zeros(256, dtype=np.int64)
+        lens[7] = 1
+        return 256, lens, np.full(9_001, 7)
+    if name == "lengths-1-to-13":  # 1..12 once, 13 twice: the two 13-bit codes share a prefix
+        lens = np.zeros(256, dtype=np.int64)
+        lens[:14] = list(range(1, 13)) + [13, 13]
+        return 256, lens, None
+    if name == "all-12":  # every prefix is one whole code
+        return 4096, np.full(4096, 12, dtype=np.int64), None
+    if name == "all-13":  # every prefix holds two codes
+        return 8192, np.full(8192, 13, dtype=np.int64), None
+    if name == "short-and-14":  # lengths 1, 3 and 14: prefixes of one code, or of four
+        lens = np.zeros(8192, dtype=np.int64)
+        lens[0] = 1
+        lens[1:3] = 3
+        lens[3:3 + 4096] = 14  # 2^-1 + 2 * 2^-3 + 4096 * 2^-14 = 1
+        return 8192, lens, None
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name,chunk", [("one-symbol", 256), ("lengths-1-to-13", 1024), ("all-12", 768),
+                                        ("all-13", 8192), ("short-and-14", 512)])
+def test_huffman_prefix_table_edges_bitexact(lib, name, chunk):
+    """Decoding of codes whose lengths sit at the prefix table's width (12 bits): a code per
+    prefix, two or four codes per prefix, a one-bit single code; oracle encode, GPU encode
+    equal to it and GPU decode back to the symbols."""
+    dict_size, lens, sym = _prefix_case(name)
+    say("huffman prefix edges", name, chunk)
+    codes = H.canonical_codes(lens)
+    used = np.flatnonzero(lens)
+    rng = np.random.default_rng(len(used) + chunk)
+    if sym is None:
+        sym = used[rng.integers(0, len(used), size=30_001)]
+    bref, wref = H.encode(sym, lens, codes, chunk)
+    dlens = dev(lens.astype(np.uint8))
+    bits, payload = lib.mgard_huffman_encode(dev(sym.astype(np.int16)), dlens, dev(codes.view(np.int64)),
+                                             dict_size, chunk)
+    assert list(host(bits).astype(np.int64)) == bref
+    assert np.array_equal(host(payload).view(np.uint32).astype(np.int64), np.asarray(wref, dtype=np.int64))
+    dec = lib.mgard_huffman_decode(dev(np.asarray(wref, dtype=np.uint32).view(np.int32)),
+                                   dev(np.asarray(bref, dtype=np.uint32).view(np.int32)), len(sym), dlens,
+                                   dict_size, chunk)
+    assert np.array_equal(lib.u16(dec).astype(np.int64), sym)
+
+
 @pytest.mark.parametrize("name,tol", [("c1-129x129-f64", 1e-3), ("c1-129x129-f64", 1e-5),
                                       ("3d-33x20x17-f32-nonuniform", 1e-2), ("3d-65x65x65-f32", 1e-3),
                                       ("even-64x50-f32", 1e-4), ("4d-9x10x7x6-f64", 1e-3)])
