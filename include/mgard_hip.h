@@ -337,10 +337,10 @@ mgard_status mgard_plain_constant(uint32_t ndim, const uint64_t* shape,
  * theta_l; the level's bin width is b_plain * exp(s * clamp(theta_l, -3, 5)).
  * With opts->alloc = MGARD_ALLOC_LEARNED and opts->model set, mgard_compress
  * decomposes, evaluates the network, quantizes, recomposes on the device and
- * measures max|u - u~| (the judge), first with s = 1 and, if that exceeds
+ * measures max|u - u~| (the bound check), first with s = 1 and, if that exceeds
  * tau, again with s = 1/2; when both exceed tau the plain widths are used
- * (mgard_info.fallback_used = 1, header fallback byte set).  The judge's
- * verdict is read back once between the two attempts.
+ * (mgard_info.fallback_used = 1, header fallback byte set).  The check's
+ * result is read back once between the two attempts.
  *
  * Parameters: MGARD_MLP_NPARAM float32 values, layout mean[4], std[4],
  * W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3[1] (y = x W^T + b,

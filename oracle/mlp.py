@@ -131,6 +131,6 @@ def unpack(flat, sizes=(4, 64, 64, 1)):
 
 
 def learned_bins(plain_bins, theta, scale=1.0):
-    """b_l = b_plain * exp(scale * clamp(theta_l, -3, 5)); the judge tries scale 1, then 1/2."""
+    """b_l = b_plain * exp(scale * clamp(theta_l, -3, 5)); the bound check tries scale 1, then 1/2."""
     t = np.clip(np.asarray(theta, dtype=np.float64).ravel(), -3.0, 5.0)
     return [float(b) * float(np.exp(x * scale)) for b, x in zip(plain_bins, t)]

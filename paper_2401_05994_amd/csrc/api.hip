@@ -454,7 +454,7 @@ constexpr int kLearnedAttempts = 2;  // learned widths tried before the plain on
 // Every device step of one compression, enqueued on o.st with no host
 // synchronisation, host-memory copy or memset, so that it can be captured in
 // a graph (the learned allocation, which batches do not use, reads back the
-// judge's verdict between its attempts).  The static header is copied from `header` (device memory); the
+// bound check's result between its attempts).  The static header is copied from `header` (device memory); the
 // results land in *fin_out (device) and, when size_out is given, the total
 // size in *size_out (device).
 // The buffers of one compression inside its scratch (the same carving for
@@ -595,7 +595,7 @@ Finale* compress_enqueue(Hierarchy& h, const T* table, const Layout& y, double t
     launch_level_stats<T>(cstream, d_off, nlev, part, stats, st);
     launch_features(stats, scalars, nlev, o.model_params, x, st);
     mlp_forward(o.model_params, x, nlev, theta, nullptr, tmp, st);
-    // the judge: widths b * exp(s * theta) for s = 1, then 1/2; the first
+    // the bound check: widths b * exp(s * theta) for s = 1, then 1/2; the first
     // whose recomposition meets tau is kept, else the plain widths
     for (int attempt = 0; attempt < kLearnedAttempts; ++attempt) {
       launch_apply_theta(bins, theta, nlev, std::ldexp(1.0, -attempt), learned, st);

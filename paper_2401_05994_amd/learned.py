@@ -49,7 +49,7 @@ def features(coeff, shape, tau):
     return _lib().mgard_level_features(coeff, shape, tau).astype(np.float64)
 
 
-class Judge:
+class BoundCheck:
     """Recomposed L-infinity error of a bin allocation for one decomposed field."""
 
     def __init__(self, u, coords=None, dict_size=8192):
@@ -73,8 +73,8 @@ class Judge:
 def label(u, tol, theta_max=5.0, iters=6, target=0.95, coords=None):
     """(features, theta*) rows for one field and tolerance."""
     plain, tau = plain_bins(u, tol, coords)
-    judge = Judge(u, coords)
-    feats = features(judge.coeff, tuple(u.shape), tau)
+    check = BoundCheck(u, coords)
+    feats = features(check.coeff, tuple(u.shape), tau)
     nlev = len(plain)
     theta = np.zeros(nlev)
     limit = target * tau
@@ -84,13 +84,13 @@ def label(u, tol, theta_max=5.0, iters=6, target=0.95, coords=None):
             mid = 0.5 * (lo + hi)
             trial = theta.copy()
             trial[l] = mid
-            err = judge.error([b * math.exp(t) for b, t in zip(plain, trial)])
+            err = check.error([b * math.exp(t) for b, t in zip(plain, trial)])
             if err <= limit:
                 lo = mid
             else:
                 hi = mid
         theta[l] = lo
-    return feats, theta, {"tau": tau, "judge_calls": judge.calls}
+    return feats, theta, {"tau": tau, "check_calls": check.calls}
 
 
 def training_field(n, seed, beta):

@@ -205,7 +205,7 @@ def test_learned_bins_follow_oracle_network(lib):
     if info["fallback_used"]:
         assert hd.bins == p.bins
     else:
-        # the judge keeps the first of scale 1, 1/2 that meets the bound
+        # the bound check keeps the first of scale 1, 1/2 that meets the bound
         assert min(rel(hd.bins, M.learned_bins(p.bins, theta, s)) for s in (1.0, 0.5)) <= 1e-5
     r = codec.decompress(host(buf[:nb]).tobytes())
     assert np.abs(r.astype(np.float64) - u.astype(np.float64)).max() <= info["tau_abs"]
