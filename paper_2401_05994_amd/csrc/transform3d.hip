@@ -702,15 +702,17 @@ __device__ __forceinline__ void k3_coeff_reg(G3 mg_bid, G3 mg_gdim, const float*
   // ---- plane registers
   float pre[RX][2];  // next plane, in flight
   float cur[RX][2];  // current plane (u), then its coefficients
-  int rowc[RX];
-#pragma unroll
-  for (int r = 0; r < RX; ++r) rowc[r] = min(max(F1 + r, 0), n1 - 1);
   auto prefetch = [&](int f0) {
     const float* base = u + (uint64_t)f0 * plane + pc;
+    // the clamped rows are recomputed here (scalar work), not held across
+    // the plane loop in scalar registers
+    int f1a = F1;
+    asm volatile("" : "+s"(f1a));
 #pragma unroll
     for (int r = 0; r < RX; ++r) {
       float2 v;
-      __builtin_memcpy(&v, base + (uint64_t)rowc[r] * n2, 8);
+      const int rc = min(max(f1a + r, 0), n1 - 1);
+      __builtin_memcpy(&v, base + (uint64_t)rc * n2, 8);
       pre[r][0] = v.x;
       pre[r][1] = v.y;
     }
