@@ -28,34 +28,62 @@ __device__ inline uint64_t abs_bits(double x) {
 }
 
 // max of |x| as ordered bit patterns (NaN patterns sort above infinity)
+__device__ inline uint64_t abs_bits4(uint4 w, float) {
+  const uint32_t m0 = max(w.x & 0x7fffffffu, w.y & 0x7fffffffu);
+  const uint32_t m1 = max(w.z & 0x7fffffffu, w.w & 0x7fffffffu);
+  return (uint64_t)max(m0, m1);
+}
+__device__ inline uint64_t abs_bits4(uint4 w, double) {
+  const uint64_t b0 = (((uint64_t)w.y << 32) | w.x) & 0x7fffffffffffffffull;
+  const uint64_t b1 = (((uint64_t)w.w << 32) | w.z) & 0x7fffffffffffffffull;
+  return b0 > b1 ? b0 : b1;
+}
+
 template <typename T>
 __device__ __forceinline__ void k_maxabs(G3 mg_bid, G3 mg_gdim, const T* __restrict__ d, uint64_t n, uint64_t* out) {
-  // Groups of eight loads per lane in two buffers: the next group is in
-  // flight while this one is reduced.  Indices past the end read the last
-  // element again (a max is unchanged by repeats), so no load is under a
-  // branch and none waits for the group after it.
+  // The 16-byte-aligned interior is read as 16-byte words, in groups of two
+  // loads per lane in two buffers: the next group is in flight while this one
+  // is reduced (64 bytes in flight per lane: four loads per group, or more
+  // blocks, read slower).  Indices past the end read the last word again (a max is
+  // unchanged by repeats), so no load is under a branch and none waits for
+  // the group after it.  The unaligned head and the tail (fewer than 16 bytes
+  // each) are read element by element by the first lanes of the grid.
+  constexpr uint64_t V = 16 / sizeof(T);
   uint64_t m = 0;
   if (n == 0) return;
+  uint64_t h = ((16u - ((uintptr_t)d & 15u)) & 15u) / sizeof(T);
+  if (h > n) h = n;
+  const uint64_t nv = (n - h) / V;
+  const uint4* __restrict__ dv = (const uint4*)(d + h);
   const uint64_t step = (uint64_t)mg_gdim.x * TPB;
-  auto load = [&](uint64_t base, T (&v)[8]) {
+  const uint64_t gid = (uint64_t)mg_bid.x * TPB + threadIdx.x;
+  const uint64_t tail0 = h + nv * V;
+  const uint64_t edge = h + (n - tail0);
+  if (gid < edge) {
+    const uint64_t e = gid < h ? gid : tail0 + (gid - h);
+    m = abs_bits(d[e]);
+  }
+  if (nv > 0) {
+    auto load = [&](uint64_t base, uint4 (&v)[2]) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = d[min(base + u * step, n - 1)];
-  };
-  auto reduce = [&](const T (&v)[8]) {
+      for (int u = 0; u < 2; ++u) v[u] = dv[min(base + u * step, nv - 1)];
+    };
+    auto reduce = [&](const uint4 (&v)[2]) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const uint64_t b = abs_bits(v[u]);
-      m = b > m ? b : m;
+      for (int u = 0; u < 2; ++u) {
+        const uint64_t b = abs_bits4(v[u], T());
+        m = b > m ? b : m;
+      }
+    };
+    uint4 va[2], vb[2];
+    uint64_t i = gid;
+    load(i, va);
+    for (; i < nv; i += 4 * step) {
+      load(i + 2 * step, vb);
+      reduce(va);
+      load(i + 4 * step, va);
+      reduce(vb);
     }
-  };
-  T va[8], vb[8];
-  uint64_t i = (uint64_t)mg_bid.x * TPB + threadIdx.x;
-  load(i, va);
-  for (; i < n; i += 16 * step) {
-    load(i + 8 * step, vb);
-    reduce(va);
-    load(i + 16 * step, va);
-    reduce(vb);
   }
   __shared__ uint64_t red[TPB];
   red[threadIdx.x] = m;
