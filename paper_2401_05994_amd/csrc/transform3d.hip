@@ -891,8 +891,11 @@ __global__ void __launch_bounds__(RWAVE) k3_coeff_reg_k(const float* __restrict_
 // One lane per (j1, j2) line.  Both sweeps run in groups of SWEEP coarse
 // indices whose loads are all issued before the group's recurrence, so a
 // lane waits for memory once per group rather than once per index; the
-// arithmetic and its order are those of the plain loops.
-constexpr int SWEEP = 16;
+// arithmetic and its order are those of the plain loops.  Eight indices per
+// group measured fastest: longer groups hold more rows in registers and, on
+// the short lines of the coarse levels, load more clamped rows that no index
+// uses; shorter ones wait for memory more often.
+constexpr int SWEEP = 8;
 
 // The weights come as separate restrict pointers: the compiler then knows the
 // stores to z leave them alone and reads them with scalar loads.
